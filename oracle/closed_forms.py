@@ -1,0 +1,154 @@
+"""Analytic results of the paper used to pin the oracle.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
+
+Everything is in lattice units (dx = dt = c = 1, so v_g = sqrt(5/3) by Eq. 48)
+unless a function says it takes the paper's non-dimensional groups.
+"""
+from __future__ import annotations
+
+import math
+from typing import Tuple
+
+import numpy as np
+
+VG = math.sqrt(5.0 / 3.0)          # Eq. 48: c = sqrt(3/5) v_g with c = 1
+
+
+# --------------------------------------------------------------------------
+# parameter mapping (Eqs. 48-49, Sec. 3.4 closing discussion)
+# --------------------------------------------------------------------------
+
+def overall_knudsen(kn_n: float, kn_r: float) -> float:
+    """1/Kn_C = 1/Kn_R + 1/Kn_N (Sec. 3 introduction)."""
+    return 1.0 / (1.0 / kn_n + 1.0 / kn_r)
+
+
+def tau_from_knudsen(n_cells: int, kn_c: float) -> float:
+    """tau = 0.5 + sqrt(3/5) N_x Kn_C (from Eqs. 48-49; Sec. 3.4 discussion).
+
+    n_cells is the number of lattice spacings across the length d."""
+    return 0.5 + math.sqrt(3.0 / 5.0) * n_cells * kn_c
+
+
+def lattice_relaxation_times(n_cells: int, kn_n: float, kn_r: float) -> Tuple[float, float]:
+    """(tau_N/dt, tau_R/dt) for Knudsen numbers Kn = v_g tau / d on a length of
+    n_cells spacings: tau/dt = Kn * n_cells * sqrt(3/5) (Eq. 48, dx = c dt)."""
+    f = n_cells * math.sqrt(3.0 / 5.0)
+    return kn_n * f, kn_r * f
+
+
+def knudsen(tau_lattice: float, d_cells: float) -> float:
+    """Kn = v_g tau / d in lattice units."""
+    return VG * tau_lattice / d_cells
+
+
+def scheme_constants(tau_n: float, tau_r: float) -> dict:
+    """tau (Eq. 49), the Eq. 54 factor beta, and the per-step heat-flux decay
+    rho = (2 tau_r - 1)/(2 tau_r + 1) that follows from Eqs. 13, 15, 16, 54
+    (total heat flux on a periodic grid is multiplied by rho each step)."""
+    inv_tc = 1.0 / tau_n + (0.0 if math.isinf(tau_r) else 1.0 / tau_r)
+    tau_c = 1.0 / inv_tc
+    if math.isinf(tau_r):
+        beta, rho = 1.0, 1.0
+    else:
+        beta = 2.0 * tau_r / (2.0 * tau_r + 1.0)
+        rho = (2.0 * tau_r - 1.0) / (2.0 * tau_r + 1.0)
+    return dict(tau_c=tau_c, tau=tau_c + 0.5, beta=beta, rho=rho)
+
+
+# --------------------------------------------------------------------------
+# Sec. 3.1.1: 1D transient conduction between isothermal walls
+# --------------------------------------------------------------------------
+
+def fourier_1d_theta_eq61(X, t_star, kn_r, n_terms: int = 2000):
+    """Eq. 61 as printed: film initially at T_c, left wall at T_h from t = 0."""
+    X = np.asarray(X, dtype=np.float64)
+    n = np.arange(1, n_terms + 1)[:, None]
+    s = np.sum(np.sin(n * np.pi * X[None, :]) / n
+               * np.exp(-kn_r ** 2 * n ** 2 * np.pi ** 2 * t_star / 3.0), axis=0)
+    return 1.0 - X - 2.0 / np.pi * s
+
+
+def fourier_1d_q_eq62(X, t_star, kn_r, n_terms: int = 2000):
+    """Eq. 62 as printed (Q = q_x d / (lambda (T_h - T_c)))."""
+    X = np.asarray(X, dtype=np.float64)
+    n = np.arange(1, n_terms + 1)[:, None]
+    s = np.sum(np.cos(n * np.pi * X[None, :])
+               * np.exp(-kn_r ** 2 * n ** 2 * np.pi ** 2 * t_star / 3.0), axis=0)
+    return 1.0 + 2.0 * s
+
+
+def fourier_1d_theta(X, t, d, alpha, theta0: float, n_terms: int = 2000):
+    """Same separation-of-variables solution as Eq. 61 for a film at uniform
+    initial Theta = theta0: Theta = 1 - X + sum_n b_n sin(n pi X) exp(-n^2 pi^2
+    alpha t / d^2), b_n = 2 int_0^1 (theta0 - 1 + X) sin(n pi X) dX.  With
+    theta0 = 0 this is Eq. 61 (alpha t / d^2 = Kn_R^2 t* / 3)."""
+    X = np.asarray(X, dtype=np.float64)
+    n = np.arange(1, n_terms + 1)[:, None].astype(np.float64)
+    sgn = (-1.0) ** n
+    b = 2.0 * ((theta0 - 1.0) * (1.0 - sgn) / (n * np.pi) - sgn / (n * np.pi))
+    return 1.0 - X + np.sum(b * np.sin(n * np.pi * X[None, :])
+                            * np.exp(-n ** 2 * np.pi ** 2 * alpha * t / d ** 2), axis=0)
+
+
+def diffusivity(tau_r: float) -> float:
+    """Thermal diffusivity lambda / C_V = v_g^2 tau_R / 3 (Eq. 9 Fourier limit)."""
+    return VG ** 2 * tau_r / 3.0
+
+
+# --------------------------------------------------------------------------
+# Sec. 3.2: in-plane transport, phonon Poiseuille flow
+# --------------------------------------------------------------------------
+
+def poiseuille_q_eq68(Y, kn_c: float, kn_r: float):
+    """Eq. 68: Q_x(Y) with Kn_eff = sqrt(Kn_C Kn_R / 5)."""
+    Y = np.asarray(Y, dtype=np.float64)
+    k = math.sqrt(kn_c * kn_r / 5.0)
+    e1 = math.exp(-1.0 / k)
+    den = 1.0 + e1 + (8.0 / 15.0) * (kn_c / k) * (1.0 - e1)
+    return 1.0 - (np.exp((Y - 1.0) / k) + np.exp(-Y / k)) / den
+
+
+def poiseuille_conductivity_eq69(kn_c: float, kn_r: float) -> float:
+    """Eq. 69: lambda_eff / lambda."""
+    k = math.sqrt(kn_c * kn_r / 5.0)
+    e1 = math.exp(-1.0 / k)
+    den = 1.0 + e1 + (8.0 / 15.0) * (kn_c / k) * (1.0 - e1)
+    return 1.0 - 2.0 * k * (1.0 - e1) / den
+
+
+def poiseuille_q_scale(tau_r: float, grad: float, cv: float = 1.0) -> float:
+    """Denominator of Q_x: -(1/3) C_V v_g^2 tau_R dT/dx with dT/dx = -grad."""
+    return cv * VG ** 2 * tau_r * grad / 3.0
+
+
+# --------------------------------------------------------------------------
+# Sec. 3.3: cross-plane transport with temperature jump
+# --------------------------------------------------------------------------
+
+def cross_plane_theta_eq70(X, kn_r: float):
+    X = np.asarray(X, dtype=np.float64)
+    return -X / (1.0 + 4.0 / 3.0 * kn_r) + (1.0 + 2.0 / 3.0 * kn_r) / (1.0 + 4.0 / 3.0 * kn_r)
+
+
+def cross_plane_q_eq71(kn_r: float) -> float:
+    """Q = q_x / (C_V v_g (T_h - T_c))."""
+    return kn_r / (3.0 * (1.0 + 4.0 / 3.0 * kn_r))
+
+
+# --------------------------------------------------------------------------
+# Eq. 52: temperature equation -> dispersion of plane waves
+# --------------------------------------------------------------------------
+
+def telegraph_rates(k: float, tau_r: float, tau_c: float) -> np.ndarray:
+    """Growth rates s (per time step) of T ~ exp(s t + i k x) under Eq. 52:
+    s^2 + s (1/tau_R + (4/15) tau_C v_g^2 k^2) + (1/3) v_g^2 k^2 = 0."""
+    b = (0.0 if math.isinf(tau_r) else 1.0 / tau_r) + 4.0 / 15.0 * tau_c * VG ** 2 * k * k
+    c0 = VG ** 2 * k * k / 3.0
+    return np.roots([1.0, b, c0])
+
+
+def second_sound_speed() -> float:
+    """v_g / sqrt(3) (Sec. 3.4), = sqrt(5)/3 lattice nodes per step."""
+    return VG / math.sqrt(3.0)
