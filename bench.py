@@ -1,0 +1,142 @@
+"""Throughput of the fused D2Q8 phonon stream-collide step on one MI355X.
+
+Default workload: the second-sound configuration -- 8192 x 8192 periodic
+lattice, Gaussian pulse dT = 0.01 exp(-r^2 / (2 * 20^2)) on T0 = 1 at the
+centre, tau_N = 0.55, tau_R = 50 -- with FP32 storage of the scaled
+deviations, FP32 arithmetic, and FP64 check-step reductions every 100 steps.
+A step is one pass of the whole hot path over the lattice: pull-advection,
+boundary handling, moments in registers, relaxation with the resistive
+source, store, and (on check steps) the FP64 snapshot/residual/total
+reductions.
+
+Prints one JSON line.  `value` is MLUPS (million lattice-node updates per
+second) of the timed steps, with the populations resident in HBM before the
+timed region starts.  Extra storage types (FP16 scaled, BF16) of the same
+workload are reported under "rows".  The oracle (plain FP64 C stepper) is
+timed on a bounded window of the same workload on the host cores
+("cpu_baseline").
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+BYTES_PER_NODE = {"f32": 64, "f16": 32, "bf16": 32}   # 8 reads + 8 writes per node
+
+
+def _parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=400)
+    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--n", type=int, default=8192, help="lattice side")
+    p.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    p.add_argument("--rows", default="f16,bf16", help="extra storage rows ('' for none)")
+    p.add_argument("--check-interval", type=int, default=100)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=10.0)
+    p.add_argument("--autotune", action="store_true")
+    return p.parse_args()
+
+
+def _run_gpu(args, storage, torch, P, W):
+    case = W.second_sound_case(n=args.n)
+    scale = {"f32": 0.0, "bf16": 0.0, "f16": 2.0 ** -20}[storage]
+    lat = P.Lattice([P.instance_from_case(case, scale)], storage=storage,
+                    check_interval=args.check_interval)
+    tune = lat.autotune(10) if args.autotune else None
+    T0 = torch.from_numpy(W.initial_field(case)).to("cuda")
+    lat.init(0, T0)
+    del T0
+    stream = lat.stream
+    lat.step(args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    t0 = time.perf_counter()
+    lat.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    nodes = case.nx * case.ny
+    step_s = ms / 1e3 / args.steps
+    mlups = nodes / step_s / 1e6
+    gbs = BYTES_PER_NODE[storage] * nodes / step_s / 1e9
+    info = lat.last_check(0) if args.check_interval > 0 else None
+    shape = lat.launch_shape()
+    lat.close()
+    return dict(storage=storage, mlups=mlups, ms_per_step=ms / args.steps, gbs=gbs,
+                wall_s=wall, check=info, shape=shape, tune=tune)
+
+
+def _cpu_baseline(args, W):
+    from oracle import ref
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    ref.set_threads(threads)
+    # bounded window of the same workload: 2048 x 2048 centred sub-lattice of
+    # the 8192^2 pulse (same pulse, same tau's), stepped on the host
+    n = 2048
+    case = W.second_sound_case(n=n)
+    o = ref.Oracle(case, W.initial_field(case))
+    t1 = o.run(2)
+    per_step = max(t1 / 2, 1e-6)
+    steps = max(2, int(args.cpu_seconds / per_step))
+    t = o.run(steps)
+    mlups = n * n * steps / t / 1e6
+    return dict(value=mlups, unit="MLUPS", cores=threads, kind="oracle",
+                sample=f"{n}x{n} window of the 8192^2 second-sound lattice, {steps} steps, "
+                       f"{t:.1f} s, FP64 C stepper with OpenMP over rows")
+
+
+def main():
+    args = _parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    import workloads as W
+    import paper_2010_01847_amd as P
+    torch.cuda.set_device(0)
+    main_row = _run_gpu(args, args.storage, torch, P, W)
+    rows = [main_row]
+    for st in [s for s in args.rows.split(",") if s and s != args.storage]:
+        rows.append(_run_gpu(args, st, torch, P, W))
+    cpu = None if args.no_cpu_baseline else _cpu_baseline(args, W)
+    gbs = main_row["gbs"]
+    out = {
+        "metric": "MLUPS and % of HBM roofline, FP32 vs 16-bit storage vs FP64 oracle error",
+        "value": round(main_row["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_row["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {"workload": f"second_sound_{args.n}x{args.n}_periodic", "nx": args.n, "ny": args.n,
+                   "tau_n": 0.55, "tau_r": 50.0, "storage": args.storage,
+                   "check_interval": args.check_interval, "launch_shape": main_row["shape"]},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None},
+        "cpu_baseline": cpu,
+        "rows": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items() if k != "tune"}
+                 for r in rows],
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

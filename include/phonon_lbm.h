@@ -1,0 +1,239 @@
+/*
+ * phonon_lbm.h -- C ABI of the MI355X (gfx950) phonon lattice Boltzmann library.
+ *
+ * The library advances the D2Q8 lattice Boltzmann equation for phonon
+ * transport under Callaway's dual relaxation model (Guo & Wang, "Lattice
+ * Boltzmann scheme for hydrodynamic equation of phonon transport", Sec. 2):
+ *
+ *   e_i(x + c_i, t + 1) - e_i(x, t) = (e_i^eq - e_i) / tau + S_i      (Eq. 13)
+ *
+ * with the eight velocities of Eq. 14 (no rest population), the drifting
+ * equilibrium of Eq. 15, the resistive source of Eq. 16 with the weights of
+ * Eqs. 17-18, tau = tau_C + 1/2 (Eq. 49), the moments of Eqs. 53-54, and the
+ * boundary treatments of Sec. 2.5 (Eqs. 55, 58, 59-60).  Units are lattice
+ * units: dx = dt = c = 1 (so the group speed is sqrt(5/3), Eq. 48).
+ *
+ * Directions are numbered as in the paper: 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1)
+ * 5:(1,1) 6:(-1,1) 7:(-1,-1) 8:(1,-1); the +x movers {1,5,8} and -x movers
+ * {3,6,7} are the sets of Eqs. 59-60.
+ *
+ * Conventions for every entry point:
+ *   - returns an lbm_status (0 on success); no C++ exception crosses the ABI;
+ *   - a failing call leaves a message readable with lbm_last_error(handle);
+ *   - fields passed in or out are row-major (ny rows of nx values, x fastest);
+ *   - host pointers are caller-owned and only read or written during the call;
+ *   - device pointers (on_device != 0) must be device memory of the handle's
+ *     device; the call enqueues work on the handle's stream and synchronises it
+ *     before returning;
+ *   - a handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef PHONON_LBM_H
+#define PHONON_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx* lbm_handle;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,          /* bad argument: NULL, size, relaxation time, index */
+    LBM_ENOMEM = -2,          /* device or host allocation failed */
+    LBM_EHIP = -3,            /* a HIP runtime call failed (message says which) */
+    LBM_ESTATE = -4,          /* call not valid in the handle's current state */
+    LBM_EUNSUPPORTED = -5,    /* boundary combination the paper does not define */
+    LBM_ENONFINITE = -6       /* a reduction found Inf/NaN (e.g. FP16 overflow) */
+} lbm_status;
+
+/* Storage type of the populations.  Arithmetic is FP32 in every case; what is
+ * stored is the scaled deviation g_i = (e_i - omega_i C_V T_ref(x)) / s. */
+typedef enum { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2 } lbm_storage;
+
+/* Boundary kinds (Sec. 2.5), per axis.  Walls are the nodes 0 and n-1.
+ *   PERIODIC   : wrap-around advection.
+ *   ISOTHERMAL : wall nodes hold omega_i C_V T_s in all eight directions (Eq. 55).
+ *   DIFFUSE    : adiabatic diffuse reflection; after advection the populations
+ *                leaving the wall share the incident energy in proportion to
+ *                omega_i (Eq. 58); the wall node then relaxes like any node.
+ *   GRADIENT   : periodic temperature-gradient seam along x (Eqs. 59-60) with
+ *                period nx and T_h - T_c = grad_x * nx; handled exactly as a
+ *                periodic deviation around the ramp T_ref(x) = t0 - grad_x * x.
+ * Supported pairs: (any x, PERIODIC y), (PERIODIC x, ISOTHERMAL or DIFFUSE y),
+ * (GRADIENT x, DIFFUSE y).  Walls on both axes need corners, which the paper
+ * leaves undefined: LBM_EUNSUPPORTED. */
+typedef enum {
+    LBM_BC_PERIODIC = 0,
+    LBM_BC_ISOTHERMAL = 1,
+    LBM_BC_DIFFUSE = 2,
+    LBM_BC_GRADIENT = 3
+} lbm_bc;
+
+/* How lbm_step issues the per-step work of a multi-instance handle. */
+typedef enum {
+    LBM_SCHED_BATCHED = 0,       /* one launch per step covering every instance (default) */
+    LBM_SCHED_PER_INSTANCE = 1,  /* one launch per instance per step (comparison baseline) */
+    LBM_SCHED_GRAPH = 2          /* batched launches replayed from a captured hipGraph */
+} lbm_schedule;
+
+/* One independent lattice. */
+typedef struct {
+    int32_t nx, ny;        /* nodes, >= 2 each; wall nodes are 0 and n-1 */
+    int32_t bc_x, bc_y;    /* lbm_bc */
+    double tau_n;          /* tau_N / dt > 0 (normal scattering) */
+    double tau_r;          /* tau_R / dt > 0, +inf allowed (resistive scattering) */
+    double cv;             /* C_V > 0; 0 selects 1 */
+    double t0;             /* reference temperature (at x = 0 for GRADIENT) */
+    double grad_x;         /* GRADIENT only: temperature drop per node along +x */
+    double t_wall[4];      /* ISOTHERMAL wall temperatures: x=0, x=nx-1, y=0, y=ny-1 */
+    double scale;          /* storage scale s (a power of two), 0 = chosen at init */
+} lbm_instance;
+
+typedef struct {
+    int32_t n_instances;         /* >= 1 */
+    int32_t storage;             /* lbm_storage */
+    int32_t check_interval;      /* K: FP64 residual/total reductions at steps K, 2K, ...;
+                                    0 = 100; -1 = never; otherwise >= 2 */
+    int32_t flags;               /* LBM_FLAG_* */
+    const lbm_instance* inst;    /* n_instances entries, copied at create */
+    void* stream;                /* hipStream_t to enqueue on; NULL = null stream */
+} lbm_config;
+
+/* Do not allocate device memory at create: the caller provides it with lbm_bind
+ * (for example a torch tensor), sized by lbm_required_bytes. */
+#define LBM_FLAG_EXTERNAL_MEMORY 0x1
+
+/* Version string of the library. */
+const char* lbm_version(void);
+
+/* Message of the last failing call on this handle ("" if none).  With a NULL
+ * handle: the last failure of lbm_create / lbm_required_bytes in this thread.
+ * Valid until the next call on the handle. */
+const char* lbm_last_error(lbm_handle h);
+
+/* Device bytes a handle of this configuration needs (population buffers, the
+ * residual snapshot, reduction partials, tables). */
+int lbm_required_bytes(const lbm_config* cfg, size_t* bytes);
+
+/* Validate cfg, compute per-instance coefficients (Eqs. 49, 54, 16) and the
+ * tile schedule, and (unless LBM_FLAG_EXTERNAL_MEMORY) allocate device memory.
+ * *out is set only on success.  Errors: EINVAL (sizes, tau <= 0, bad enum,
+ * check_interval), EUNSUPPORTED (boundary pair), ENOMEM, EHIP. */
+int lbm_create(const lbm_config* cfg, lbm_handle* out);
+
+/* Attach caller-owned device memory of at least lbm_required_bytes bytes,
+ * 256-byte aligned.  Borrowed for the handle's lifetime, never freed by the
+ * library.  Only for handles created with LBM_FLAG_EXTERNAL_MEMORY, before
+ * lbm_init.  Errors: EINVAL, ESTATE. */
+int lbm_bind(lbm_handle h, void* device_buf, size_t bytes);
+
+/* Initialise instance `inst` at time n = 0 to the equilibrium of Eq. 15 for
+ * temperature T and heat flux (qx, qy): e_i = omega_i C_V T + (5 a_i / 3)
+ * c_i . (q / beta), beta = 2 tau_r / (2 tau_r + 1), so that Eq. 54 read back
+ * at n = 0 returns q.  Isothermal wall nodes take their wall equilibrium
+ * (Eq. 55).  T, qx, qy: host FP64 arrays of ny*nx; T NULL = T_ref (t0, or the
+ * GRADIENT ramp); qx/qy NULL = 0.  With scale = 0 the storage scale becomes
+ * s = 2^(ceil(log2 A) - 13) for FP16 (A = largest |T - T_ref|, |wall - T_ref|,
+ * |q|; s = 1 if A = 0) and s = 1 for FP32/BF16.  All instances must be
+ * initialised before lbm_step; re-initialising any instance resets the step
+ * count of the handle to 0.  Errors: EINVAL, ESTATE (no memory bound), EHIP. */
+int lbm_init(lbm_handle h, int32_t inst, const double* T, const double* qx, const double* qy);
+
+/* As lbm_init with device FP64 arrays (same layout).  FP16 storage needs an
+ * explicit scale (lbm_instance.scale != 0) here: EINVAL otherwise. */
+int lbm_init_device(lbm_handle h, int32_t inst, const double* T, const double* qx,
+                    const double* qy);
+
+/* Enqueue nsteps time steps of every instance on the handle's stream (no host
+ * synchronisation).  Each step, per node: pull the eight populations along
+ * c_i (periodic wrap, the GRADIENT ramp term omega_i C_V grad_x c_ix / s),
+ * apply the boundary treatment to the unknown ones, form E = sum g_i and
+ * j = sum c_i g_i, and relax (Eq. 13 with Eqs. 15-16).  At steps K-1 and K
+ * (mod K) the FP64 snapshot and reductions of lbm_residual are taken.
+ * Errors: EINVAL (nsteps < 0), ESTATE (not initialised), EHIP. */
+int lbm_step(lbm_handle h, int64_t nsteps);
+
+/* Steps taken since the last initialisation. */
+int64_t lbm_steps_done(lbm_handle h);
+
+/* Macroscopic fields of instance `inst` at the current time n (Eqs. 53-54):
+ * T = T_ref + s E / C_V and q = s beta j of the post-advection, post-boundary
+ * (pre-relaxation) populations, computed in FP64 and written as FP32.
+ * on_device != 0: T, qx, qy are device pointers.  Any of them may be NULL. */
+int lbm_moments(lbm_handle h, int32_t inst, float* T, float* qx, float* qy, int32_t on_device);
+
+/* As lbm_moments in FP64, returning the deviation dT = T - T_ref(x) instead of
+ * T (T_ref = t0, or the GRADIENT ramp), so that small deviations keep their
+ * digits. */
+int lbm_moments_f64(lbm_handle h, int32_t inst, double* dT, double* qx, double* qy,
+                    int32_t on_device);
+
+/* FP64 totals of instance `inst` at the current time, computed now:
+ * out[0] = sum (e - C_V T_ref) = C_V sum dT, out[1] = sum q_x, out[2] = sum q_y.
+ * Errors: ENONFINITE if any total is not finite. */
+int lbm_totals(lbm_handle h, int32_t inst, double out[3]);
+
+/* Relative one-step residual of the last check step n (a multiple of K):
+ * r = ||m^n - m^(n-1)||_2 / ||m^n||_2 over all nodes, m = (T - T_ref, q_x, q_y),
+ * moments formed in FP64 from the stored populations.  r = 0 exactly means
+ * the rounded map has reached a fixed point.  Synchronises the stream.
+ * Errors: ESTATE (no check step yet), ENONFINITE (Inf/NaN in the reduction,
+ * e.g. FP16 overflow). */
+int lbm_residual(lbm_handle h, int32_t inst, double* r);
+
+/* The whole last check record: step n, residual, and the FP64 totals of
+ * lbm_totals taken at that step.  Same errors as lbm_residual. */
+typedef struct {
+    int64_t step;
+    double residual;
+    double totals[3];
+} lbm_check_info;
+int lbm_last_check(lbm_handle h, int32_t inst, lbm_check_info* out);
+
+/* Coefficients the kernels use for instance `inst`, as doubles:
+ * out[0] = 1/tau (FP32-rounded), out[1] = beta (FP32-rounded),
+ * out[2] = kappa * beta with kappa = 1/tau - (1 - 1/(2 tau)) / tau_r (FP32-rounded),
+ * out[3] = s, out[4] = tau (exact), out[5] = rho = (2 tau_r - 1)/(2 tau_r + 1) (exact). */
+int lbm_coefficients(lbm_handle h, int32_t inst, double out[6]);
+
+/* Select how multi-instance steps are issued (lbm_schedule).  GRAPH captures
+ * K batched steps (the check interval, or 64 when checks are off) once per
+ * buffer parity and replays them; steps not filling a chunk run eagerly. */
+int lbm_set_schedule(lbm_handle h, int32_t schedule);
+
+/* Kernel launch shape: nodes per thread along x (1, 2 or 4), threads per
+ * block along x (a multiple of 64, <= 512) and rows per block, with
+ * block_x * block_y <= 512; xcd_remap != 0 maps consecutive tiles to the same
+ * XCD.  Applies to later steps; invalidates captured graphs.  Errors: EINVAL. */
+typedef struct {
+    int32_t vec;
+    int32_t block_x;
+    int32_t block_y;
+    int32_t xcd_remap;
+    int32_t nontemporal;   /* != 0: streaming (non-temporal) population stores */
+} lbm_launch_shape;
+int lbm_set_launch_shape(lbm_handle h, const lbm_launch_shape* shape);
+int lbm_get_launch_shape(lbm_handle h, lbm_launch_shape* shape);
+
+/* Time every candidate launch shape on this handle's own instances and keep
+ * the fastest.  Must be called after lbm_create and before lbm_init (it runs
+ * steps on scratch contents); each candidate is timed over `steps` steps
+ * (0 = 20) with HIP events.  If the environment variable LBM_AUTOTUNE_CACHE
+ * names a file, a result for the same device, storage and instance shapes is
+ * read from it instead of timing, and new results are appended to it.
+ * report (may be NULL) receives a JSON summary of the timings.
+ * Errors: ESTATE (already initialised), EHIP. */
+int lbm_autotune(lbm_handle h, int32_t steps, char* report, size_t report_len);
+
+/* Release device memory the library allocated and the handle itself.
+ * Bound memory is not freed.  NULL is ignored. */
+void lbm_destroy(lbm_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PHONON_LBM_H */

@@ -1,0 +1,559 @@
+// Device code of the phonon lattice Boltzmann library for gfx950 (CDNA4, wave64).
+//
+// One fused kernel performs a whole time step of Eq. 13 per node: it pulls the
+// eight populations along the velocities of Eq. 14 from the previous step's
+// post-relaxation buffer, applies the boundary treatment of Sec. 2.5 to the
+// unknown ones, forms the moments of Eqs. 53-54 in registers, relaxes toward
+// the equilibrium of Eq. 15 with the source of Eq. 16, and stores the result
+// into the other buffer.  The path is a bandwidth-bound stencil (about 40
+// flop per 64 bytes in FP32), so there is no matrix-core work: the design
+// goals are coalesced, wide HBM accesses and enough bytes in flight.
+//
+// Stored quantity: g_i = (e_i - omega_i C_V T_ref(x)) / s.  The scheme is
+// affine in e, and a uniform (or, with the gradient seam, ramp) equilibrium
+// with zero flux is a fixed point of the relaxation, so the g-form update is
+// the same relaxation applied to g; the ramp only adds omega_i C_V G c_ix / s
+// to each pulled population, which turns the seam of Eqs. 59-60 into plain
+// periodic wrap.
+//
+// Layout: per instance, eight planes (one per direction) of ny rows of
+// `pitch` elements, x contiguous; two such buffers (ping-pong).
+#include "lbm_internal.h"
+
+#include <stdint.h>
+
+namespace plbm {
+
+// ------------------------------------------------------------------ storage
+
+struct bf16_bits { uint16_t b; };
+
+template <class S> struct Cvt;
+template <> struct Cvt<float> {
+    static __device__ __forceinline__ float ld(float v) { return v; }
+    static __device__ __forceinline__ float st(float f) { return f; }
+};
+template <> struct Cvt<_Float16> {
+    static __device__ __forceinline__ float ld(_Float16 v) { return (float)v; }
+    // v_cvt_f16_f32 rounds to nearest even in the default mode; overflow -> Inf
+    static __device__ __forceinline__ _Float16 st(float f) { return (_Float16)f; }
+};
+template <> struct Cvt<bf16_bits> {
+    static __device__ __forceinline__ float ld(bf16_bits v) {
+        return __uint_as_float((uint32_t)v.b << 16);
+    }
+    // round to nearest, ties to even; NaN stays a quiet NaN, overflow -> Inf
+    static __device__ __forceinline__ bf16_bits st(float f) {
+        uint32_t u = __float_as_uint(f);
+        bf16_bits r;
+        if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) {
+            r.b = (uint16_t)((u >> 16) | 0x0040u);
+        } else {
+            u += 0x7fffu + ((u >> 16) & 1u);
+            r.b = (uint16_t)(u >> 16);
+        }
+        return r;
+    }
+};
+
+template <int BYTES> struct RawT;
+template <> struct RawT<2> { typedef uint16_t T; };
+template <> struct RawT<4> { typedef uint32_t T; };
+template <> struct RawT<8> { typedef uint32_t T __attribute__((ext_vector_type(2))); };
+template <> struct RawT<16> { typedef uint32_t T __attribute__((ext_vector_type(4))); };
+
+// V consecutive elements from an element-aligned address (one wide load; the
+// gfx9 memory path accepts dword-unaligned vector accesses).
+template <class S, int V>
+__device__ __forceinline__ void load_run(const S* __restrict__ p, float* out) {
+    S tmp[V];
+    __builtin_memcpy(tmp, p, sizeof(S) * V);
+#pragma unroll
+    for (int k = 0; k < V; ++k) out[k] = Cvt<S>::ld(tmp[k]);
+}
+
+// V consecutive elements to a V-element-aligned address.
+template <class S, int V>
+__device__ __forceinline__ void store_run(S* __restrict__ p, const float* v, int nontemporal) {
+    S tmp[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) tmp[k] = Cvt<S>::st(v[k]);
+    typedef typename RawT<sizeof(S) * V>::T R;
+    R raw;
+    __builtin_memcpy(&raw, tmp, sizeof(R));
+    R* q = reinterpret_cast<R*>(p);
+    if (nontemporal)
+        __builtin_nontemporal_store(raw, q);
+    else
+        *q = raw;
+}
+
+// ------------------------------------------------------------------ physics
+
+// Weights of Eq. 17 in FP32.
+#define W_AXIS 0.222222222222222222f   // 2/9
+#define W_DIAG 0.027777777777777778f   // 1/36
+
+// Relaxation of one node (Eq. 13 right-hand side with Eqs. 15-16, dt = c = 1)
+// in g-form.  E = sum g, j = sum c_i g (Eq. 53 and the sum of Eq. 54); the
+// equilibrium energy share is split so that 4 ea + 4 ed == E holds exactly
+// (E - 4 ea is exact by Sterbenz' lemma), and the flux share of Eq. 15 minus
+// the source of Eq. 16 is kappa * beta * (5 a_i / 3) c_i . j.
+__device__ __forceinline__ void relax(float g[8], float inv_tau, float kb_a, float kb_d) {
+    const float E = ((g[0] + g[2]) + (g[1] + g[3])) + ((g[4] + g[6]) + (g[5] + g[7]));
+    const float jx = (g[0] - g[2]) + (g[4] - g[6]) + (g[7] - g[5]);
+    const float jy = (g[1] - g[3]) + (g[4] - g[6]) + (g[5] - g[7]);
+    const float ea = W_AXIS * E;
+    const float ed = (E - 4.0f * ea) * 0.25f;
+    const float fx = kb_a * jx, fy = kb_a * jy;
+    const float fp = kb_d * (jx + jy), fm = kb_d * (jx - jy);
+    g[0] = g[0] + inv_tau * (ea - g[0]) + fx;
+    g[1] = g[1] + inv_tau * (ea - g[1]) + fy;
+    g[2] = g[2] + inv_tau * (ea - g[2]) - fx;
+    g[3] = g[3] + inv_tau * (ea - g[3]) - fy;
+    g[4] = g[4] + inv_tau * (ed - g[4]) + fp;
+    g[5] = g[5] + inv_tau * (ed - g[5]) - fm;
+    g[6] = g[6] + inv_tau * (ed - g[6]) - fp;
+    g[7] = g[7] + inv_tau * (ed - g[7]) + fm;
+}
+
+// Boundary treatment after advection (Sec. 2.5) on one node, given its
+// position.  Directions 0..7 are the paper's 1..8.  Written with selects only:
+// every write has a fixed index, so the eight values stay in registers.
+//   diffuse (Eq. 58): the three populations leaving a wall get 4/5, 1/10, 1/10
+//     (omega_i over the sum of the leaving omegas) of the incident sum S; the
+//     axis share is formed as S - 2 (S/10) so the three add up to S;
+//   isothermal (Eq. 55): all eight take omega_i C_V (T_s - T_ref) / s.
+__device__ __forceinline__ void boundary(float g[8], const InstDesc& d, int x, int y) {
+    if (d.bc_y == 2) {
+        const bool lo = (y == 0), hi = (y == d.ny - 1);
+        const float Sl = g[3] + g[6] + g[7];      // incident at y = 0: 4, 7, 8
+        const float Sh = g[1] + g[4] + g[5];      // incident at y = ny-1: 2, 5, 6
+        const float dl = 0.1f * Sl, dh = 0.1f * Sh;
+        const float al = Sl - dl - dl, ah = Sh - dh - dh;
+        g[1] = lo ? al : g[1];  g[4] = lo ? dl : g[4];  g[5] = lo ? dl : g[5];
+        g[3] = hi ? ah : g[3];  g[6] = hi ? dh : g[6];  g[7] = hi ? dh : g[7];
+    } else if (d.bc_y == 1) {
+        const bool w = (y == 0) || (y == d.ny - 1);
+        const float t = (y == 0) ? d.wall_g[2] : d.wall_g[3];
+        const float a = W_AXIS * t, b = W_DIAG * t;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) g[i] = w ? (i < 4 ? a : b) : g[i];
+    }
+    if (d.bc_x == 2) {
+        const bool lo = (x == 0), hi = (x == d.nx - 1);
+        const float Sl = g[2] + g[5] + g[6];      // incident at x = 0: 3, 6, 7
+        const float Sh = g[0] + g[4] + g[7];      // incident at x = nx-1: 1, 5, 8
+        const float dl = 0.1f * Sl, dh = 0.1f * Sh;
+        const float al = Sl - dl - dl, ah = Sh - dh - dh;
+        g[0] = lo ? al : g[0];  g[4] = lo ? dl : g[4];  g[7] = lo ? dl : g[7];
+        g[2] = hi ? ah : g[2];  g[5] = hi ? dh : g[5];  g[6] = hi ? dh : g[6];
+    } else if (d.bc_x == 1) {
+        const bool w = (x == 0) || (x == d.nx - 1);
+        const float t = (x == 0) ? d.wall_g[0] : d.wall_g[1];
+        const float a = W_AXIS * t, b = W_DIAG * t;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) g[i] = w ? (i < 4 ? a : b) : g[i];
+    }
+}
+
+// Seam of Eqs. 59-60 in g-form: every pulled population gains
+// omega_i C_V G c_ix / s.
+__device__ __forceinline__ void ramp_term(float g[8], float gt) {
+    const float a = W_AXIS * gt, b = W_DIAG * gt;
+    g[0] += a; g[4] += b; g[7] += b;
+    g[2] -= a; g[5] -= b; g[6] -= b;
+}
+
+// x shift of the source of direction i (pull from x - c_ix), and the row of the
+// source: 0 = y, 1 = y - 1 (c_iy = +1), 2 = y + 1 (c_iy = -1).  Compile-time
+// functions, so unrolled loops fold them into immediates.
+__device__ __forceinline__ constexpr int src_dx(int i) {
+    return (i == 0 || i == 4 || i == 7) ? -1 : ((i == 2 || i == 5 || i == 6) ? 1 : 0);
+}
+__device__ __forceinline__ constexpr int src_row(int i) {
+    return (i == 1 || i == 4 || i == 5) ? 1 : ((i == 3 || i == 6 || i == 7) ? 2 : 0);
+}
+
+// V elements starting at x0 + dx (V-aligned x0, so the dx == 0 run is
+// V-element aligned).  FP32: one wide load, dword aligned.  16-bit storage:
+// the aligned run at x0 plus one aligned pair on the side the shift reaches
+// into, so no access is below dword alignment.  Caller guarantees
+// x0 + dx >= 0 and, for 16-bit dx = +1, that x0 + V + 1 < nx.
+template <class S, int V>
+__device__ __forceinline__ void load_shifted(const S* __restrict__ row, int x0, int dx, float* out) {
+    if (dx == 0 || sizeof(S) == 4 || V == 1) {
+        load_run<S, V>(row + x0 + dx, out);
+        return;
+    }
+    float a[V], b[2];
+    load_run<S, V>(row + x0, a);
+    if (dx < 0) {
+        load_run<S, 2>(row + x0 - 2, b);
+        out[0] = b[1];
+#pragma unroll
+        for (int k = 1; k < V; ++k) out[k] = a[k - 1];
+    } else {
+        load_run<S, 2>(row + x0 + V, b);
+#pragma unroll
+        for (int k = 0; k < V - 1; ++k) out[k] = a[k + 1];
+        out[V - 1] = b[0];
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum kPartials values over the block in a fixed order; thread 0 writes them.
+__device__ __forceinline__ void block_partials(double v[kPartials], double* out) {
+    __shared__ double red[kMaxBlock / 64][kPartials];
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
+    const int nw = (blockDim.x * blockDim.y + 63) >> 6;
+#pragma unroll
+    for (int c = 0; c < kPartials; ++c) {
+        const double s = wave_sum(v[c]);
+        if (lane == 0) red[wid][c] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int c = 0; c < kPartials; ++c) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += red[w][c];
+            out[c] = s;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ step
+
+template <class S, int V, int MODE>
+__global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t snap_stride,
+                                                          int xcd, int nontemporal) {
+    // tile of this block; with xcd != 0, consecutive tiles go to the same XCD
+    // (workgroups are dealt to the 8 XCDs round robin)
+    const int b = blockIdx.x;
+    int t = b;
+    if (xcd) {
+        const int nb = a.ntiles, q = nb >> 3, r = nb & 7, k = b & 7, j = b >> 3;
+        t = k * q + (k < r ? k : r) + j;
+    }
+    t += a.tile_base;
+    const InstDesc& d = a.desc[a.tile_inst[t]];
+    const int local = t - d.tile_begin;
+    const int ty = local / d.tiles_x;
+    const int tx = local - ty * d.tiles_x;
+    const int x0 = tx * (V * blockDim.x) + threadIdx.x * V;
+    const int y = ty * blockDim.y + threadIdx.y;
+    const int nx = d.nx, ny = d.ny;
+    const bool live = (y < ny) && (x0 < nx);
+
+    double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (live) {
+        const S* __restrict__ src = reinterpret_cast<const S*>(a.src) + d.off;
+        S* __restrict__ dst = reinterpret_cast<S*>(a.dst) + d.off;
+        const int ym = (y == 0) ? ny - 1 : y - 1;
+        const int yp = (y == ny - 1) ? 0 : y + 1;
+        const int64_t rows[3] = {(int64_t)y * d.pitch, (int64_t)ym * d.pitch, (int64_t)yp * d.pitch};
+        const bool full = (x0 + V <= nx);
+        float g[V][8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int dx = src_dx(i);
+            const S* row = src + (int64_t)i * d.plane + rows[src_row(i)];
+            float v[V];
+            const int hi = (sizeof(S) == 2 && V > 1 && dx > 0) ? x0 + V + 1 : x0 + V - 1 + dx;
+            if (full && x0 + dx >= 0 && hi < nx) {
+                load_shifted<S, V>(row, x0, dx, v);
+            } else {
+#pragma unroll
+                for (int k = 0; k < V; ++k) {
+                    int xs = x0 + k + dx;
+                    xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+                    v[k] = (x0 + k < nx) ? Cvt<S>::ld(row[xs]) : 0.0f;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < V; ++k) g[k][i] = v[k];
+        }
+        const bool ramp = (d.bc_x == 3);
+        const bool edge_y = (d.bc_y != 0) && (y == 0 || y == ny - 1);
+        const bool edge_x = (d.bc_x == 1 || d.bc_x == 2) && (x0 == 0 || x0 + V > nx - 1);
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            if (ramp) ramp_term(g[k], d.grad_term);
+            if (edge_y || edge_x) boundary(g[k], d, x0 + k, y);
+        }
+        if (MODE != kPlain) {
+            const int64_t nbase = d.node_off + (int64_t)y * nx;
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                if (x0 + k >= nx) continue;
+                double E = 0.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) E += (double)g[k][i];
+                jx = ((double)g[k][0] - (double)g[k][2]) + ((double)g[k][4] - (double)g[k][6])
+                   + ((double)g[k][7] - (double)g[k][5]);
+                jy = ((double)g[k][1] - (double)g[k][3]) + ((double)g[k][4] - (double)g[k][6])
+                   + ((double)g[k][5] - (double)g[k][7]);
+                const double dT = d.s_cv * E, qx = d.s_beta * jx, qy = d.s_beta * jy;
+                const int64_t n = nbase + x0 + k;
+                if (MODE == kSnap) {
+                    a.snap[n] = dT;
+                    a.snap[n + snap_stride] = qx;
+                    a.snap[n + 2 * snap_stride] = qy;
+                } else {
+                    const double p0 = a.snap[n], p1 = a.snap[n + snap_stride],
+                                 p2 = a.snap[n + 2 * snap_stride];
+                    acc[0] += d.s * E;
+                    acc[1] += qx;
+                    acc[2] += qy;
+                    acc[3] += (dT - p0) * (dT - p0) + (qx - p1) * (qx - p1) + (qy - p2) * (qy - p2);
+                    acc[4] += dT * dT + qx * qx + qy * qy;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < V; ++k) relax(g[k], d.inv_tau, d.kb_axis, d.kb_diag);
+        S* out = dst + rows[0] + x0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            float v[V];
+#pragma unroll
+            for (int k = 0; k < V; ++k) v[k] = g[k][i];
+            S* p = out + (int64_t)i * d.plane;
+            if (full) {
+                store_run<S, V>(p, v, nontemporal);
+            } else {
+#pragma unroll
+                for (int k = 0; k < V; ++k)
+                    if (x0 + k < nx) p[k] = Cvt<S>::st(v[k]);
+            }
+        }
+    }
+    if (MODE == kCheck) block_partials(acc, a.partials + (int64_t)t * kPartials);
+}
+
+template <class S, int V>
+static hipError_t launch_step_v(const Shape& sh, int mode, const StepArgs& a, int64_t snap_stride,
+                                hipStream_t st) {
+    dim3 grid(a.ntiles), block(sh.bx, sh.by);
+    if (mode == kPlain)
+        hipLaunchKernelGGL((step_kernel<S, V, kPlain>), grid, block, 0, st, a, snap_stride, sh.xcd, sh.nt);
+    else if (mode == kSnap)
+        hipLaunchKernelGGL((step_kernel<S, V, kSnap>), grid, block, 0, st, a, snap_stride, sh.xcd, sh.nt);
+    else
+        hipLaunchKernelGGL((step_kernel<S, V, kCheck>), grid, block, 0, st, a, snap_stride, sh.xcd, sh.nt);
+    return hipGetLastError();
+}
+
+template <class S>
+static hipError_t launch_step_s(const Shape& sh, int mode, const StepArgs& a, int64_t ss, hipStream_t st) {
+    switch (sh.vec) {
+        case 1: return launch_step_v<S, 1>(sh, mode, a, ss, st);
+        case 2: return launch_step_v<S, 2>(sh, mode, a, ss, st);
+        case 4: return launch_step_v<S, 4>(sh, mode, a, ss, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step(int storage, const Shape& sh, int mode, const StepArgs& a, int64_t snap_stride,
+                       hipStream_t st) {
+    if (a.ntiles <= 0) return hipSuccess;
+    switch (storage) {
+        case 0: return launch_step_s<float>(sh, mode, a, snap_stride, st);
+        case 1: return launch_step_s<_Float16>(sh, mode, a, snap_stride, st);
+        case 2: return launch_step_s<bf16_bits>(sh, mode, a, snap_stride, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------------------------ moments
+
+// One node per thread, 256 threads along x, one row per block row.
+template <class S>
+__global__ __launch_bounds__(256) void moments_kernel(const InstDesc* __restrict__ descs, int inst,
+                                                      const void* buf, int pull, int out_kind,
+                                                      void* T, void* qx, void* qy, double t0,
+                                                      double grad, double* partials) {
+    const InstDesc& d = descs[inst];
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    const int y = blockIdx.y;
+    const int nx = d.nx, ny = d.ny;
+    double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (x < nx) {
+        const S* src = reinterpret_cast<const S*>(buf) + d.off;
+        float g[8];
+        if (pull) {
+            const int ym = (y == 0) ? ny - 1 : y - 1;
+            const int yp = (y == ny - 1) ? 0 : y + 1;
+            const int rows[3] = {y, ym, yp};
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                int xs = x + src_dx(i);
+                xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+                g[i] = Cvt<S>::ld(src[(int64_t)i * d.plane + (int64_t)rows[src_row(i)] * d.pitch + xs]);
+            }
+            if (d.bc_x == 3) ramp_term(g, d.grad_term);
+            boundary(g, d, x, y);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                g[i] = Cvt<S>::ld(src[(int64_t)i * d.plane + (int64_t)y * d.pitch + x]);
+        }
+        double E = 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) E += (double)g[i];
+        const double jx = ((double)g[0] - (double)g[2]) + ((double)g[4] - (double)g[6])
+                        + ((double)g[7] - (double)g[5]);
+        const double jy = ((double)g[1] - (double)g[3]) + ((double)g[4] - (double)g[6])
+                        + ((double)g[5] - (double)g[7]);
+        const double dT = d.s_cv * E, vx = d.s_beta * jx, vy = d.s_beta * jy;
+        const int64_t n = (int64_t)y * nx + x;
+        if (out_kind == 0) {
+            const double tref = t0 - grad * (double)x;
+            if (T) reinterpret_cast<float*>(T)[n] = (float)(tref + dT);
+            if (qx) reinterpret_cast<float*>(qx)[n] = (float)vx;
+            if (qy) reinterpret_cast<float*>(qy)[n] = (float)vy;
+        } else {
+            if (T) reinterpret_cast<double*>(T)[n] = dT;
+            if (qx) reinterpret_cast<double*>(qx)[n] = vx;
+            if (qy) reinterpret_cast<double*>(qy)[n] = vy;
+        }
+        acc[0] = d.s * E;
+        acc[1] = vx;
+        acc[2] = vy;
+    }
+    if (partials) block_partials(acc, partials + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kPartials);
+}
+
+hipError_t launch_moments(int storage, const InstDesc* d_desc, int inst, const InstDesc& h,
+                          const void* buf, int pull, int out_kind, void* T, void* qx, void* qy,
+                          double t0, double grad, double* partials, hipStream_t st) {
+    dim3 grid((h.nx + 255) / 256, h.ny), block(256);
+    switch (storage) {
+        case 0: hipLaunchKernelGGL(moments_kernel<float>, grid, block, 0, st, d_desc, inst, buf, pull,
+                                   out_kind, T, qx, qy, t0, grad, partials); break;
+        case 1: hipLaunchKernelGGL(moments_kernel<_Float16>, grid, block, 0, st, d_desc, inst, buf, pull,
+                                   out_kind, T, qx, qy, t0, grad, partials); break;
+        case 2: hipLaunchKernelGGL(moments_kernel<bf16_bits>, grid, block, 0, st, d_desc, inst, buf, pull,
+                                   out_kind, T, qx, qy, t0, grad, partials); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ init
+
+// Pre-relaxation state at n = 0 (equilibrium of Eq. 15 with j = q / beta, wall
+// nodes at their Eq. 55 equilibrium), stored rounded to `pre`; its relaxation,
+// computed from the rounded values exactly as a step would, goes to `post`.
+template <class S>
+__global__ __launch_bounds__(256) void init_kernel(const InstDesc* __restrict__ descs, int inst,
+                                                   void* pre, void* post, const double* __restrict__ T,
+                                                   const double* __restrict__ qx,
+                                                   const double* __restrict__ qy, double t0,
+                                                   double grad, double beta) {
+    const InstDesc& d = descs[inst];
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= d.nx) return;
+    const int64_t n = (int64_t)y * d.nx + x;
+    const double dT = T[n] - (t0 - grad * (double)x);
+    const double jx = qx ? qx[n] / beta : 0.0, jy = qy ? qy[n] / beta : 0.0;
+    const double inv_s = 1.0 / d.s;
+    const double ea = (2.0 / 9.0) * d.cv * dT, ed = (1.0 / 36.0) * d.cv * dT;
+    float g[8];
+    g[0] = (float)((ea + jx / 3.0) * inv_s);
+    g[1] = (float)((ea + jy / 3.0) * inv_s);
+    g[2] = (float)((ea - jx / 3.0) * inv_s);
+    g[3] = (float)((ea - jy / 3.0) * inv_s);
+    g[4] = (float)((ed + (jx + jy) / 12.0) * inv_s);
+    g[5] = (float)((ed + (-jx + jy) / 12.0) * inv_s);
+    g[6] = (float)((ed - (jx + jy) / 12.0) * inv_s);
+    g[7] = (float)((ed + (jx - jy) / 12.0) * inv_s);
+    const bool wall = (d.bc_x == 1 && (x == 0 || x == d.nx - 1)) ||
+                      (d.bc_y == 1 && (y == 0 || y == d.ny - 1));
+    if (wall) boundary(g, d, x, y);
+    S* p = reinterpret_cast<S*>(pre) + d.off + (int64_t)y * d.pitch + x;
+    S* q = reinterpret_cast<S*>(post) + d.off + (int64_t)y * d.pitch + x;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const S v = Cvt<S>::st(g[i]);
+        p[(int64_t)i * d.plane] = v;
+        g[i] = Cvt<S>::ld(v);
+    }
+    relax(g, d.inv_tau, d.kb_axis, d.kb_diag);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) q[(int64_t)i * d.plane] = Cvt<S>::st(g[i]);
+}
+
+hipError_t launch_init(int storage, const InstDesc* d_desc, int inst, const InstDesc& h, void* pre,
+                       void* post, const double* T, const double* qx, const double* qy, double t0,
+                       double grad, double beta, hipStream_t st) {
+    dim3 grid((h.nx + 255) / 256, h.ny), block(256);
+    switch (storage) {
+        case 0: hipLaunchKernelGGL(init_kernel<float>, grid, block, 0, st, d_desc, inst, pre, post, T, qx,
+                                   qy, t0, grad, beta); break;
+        case 1: hipLaunchKernelGGL(init_kernel<_Float16>, grid, block, 0, st, d_desc, inst, pre, post, T,
+                                   qx, qy, t0, grad, beta); break;
+        case 2: hipLaunchKernelGGL(init_kernel<bf16_bits>, grid, block, 0, st, d_desc, inst, pre, post, T,
+                                   qx, qy, t0, grad, beta); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ reductions
+
+// Fixed-order sum of `count` partial records starting at `first`: thread t
+// adds records t, t + 256, ... in order, then a fixed tree over the block.
+__device__ void reduce_records(const double* __restrict__ partials, int64_t first, int count,
+                               double* __restrict__ out) {
+    __shared__ double red[256][kPartials];
+    const int t = threadIdx.x;
+    double s[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int j = t; j < count; j += 256)
+#pragma unroll
+        for (int c = 0; c < kPartials; ++c) s[c] += partials[(first + j) * kPartials + c];
+#pragma unroll
+    for (int c = 0; c < kPartials; ++c) red[t][c] = s[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+#pragma unroll
+            for (int c = 0; c < kPartials; ++c) red[t][c] += red[t + w][c];
+        __syncthreads();
+    }
+    if (t == 0)
+#pragma unroll
+        for (int c = 0; c < kPartials; ++c) out[c] = red[0][c];
+}
+
+__global__ __launch_bounds__(256) void finalize_kernel(const InstDesc* __restrict__ descs,
+                                                       const double* __restrict__ partials,
+                                                       double* __restrict__ results) {
+    const InstDesc& d = descs[blockIdx.x];
+    reduce_records(partials, d.tile_begin, d.ntiles, results + (int64_t)blockIdx.x * kPartials);
+}
+
+__global__ __launch_bounds__(256) void finalize_range_kernel(const double* __restrict__ partials,
+                                                             int count, double* __restrict__ out) {
+    reduce_records(partials, 0, count, out);
+}
+
+hipError_t launch_finalize(const InstDesc* d_desc, int ninst, const double* partials, double* results,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(ninst), dim3(256), 0, st, d_desc, partials, results);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_range(const double* partials, int nparts, double* result, hipStream_t st) {
+    hipLaunchKernelGGL(finalize_range_kernel, dim3(1), dim3(256), 0, st, partials, nparts, result);
+    return hipGetLastError();
+}
+
+}  // namespace plbm

@@ -1,0 +1,940 @@
+// Host runtime of the phonon lattice Boltzmann library: the C ABI of
+// phonon_lbm.h.  It validates configurations, derives the per-instance
+// coefficients (Eqs. 49, 54 and the relaxation-plus-source factor from
+// Eqs. 13, 15, 16), lays the populations out in device memory, builds the tile
+// schedule, and issues the kernels of lbm_device.hip on the caller's stream,
+// eagerly or from captured HIP graphs.
+#include "../../include/phonon_lbm.h"
+#include "lbm_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace plbm;
+
+namespace {
+
+constexpr uint32_t kMagic = 0x4c424d31u;   // "LBM1"
+constexpr size_t kAlign = 256;
+thread_local std::string g_create_error;
+
+struct Status {
+    int code;
+    std::string msg;
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int esize_of(int storage) { return storage == LBM_F32 ? 4 : 2; }
+
+// Row pitch in elements: row bytes a multiple of 256.
+int32_t pitch_of(int32_t nx, int es) {
+    const int per = (int)(kAlign / es);
+    return (int32_t)(((int64_t)nx + per - 1) / per * per);
+}
+
+// Elements per direction plane (whole rows; the multiple of 64 elements keeps
+// every plane start 256-byte aligned for both element sizes).
+int64_t plane_of(const lbm_instance& in, int es) {
+    return (int64_t)in.ny * pitch_of(in.nx, es);
+}
+
+struct Coeffs {
+    double tau, tau_c, beta, kappa, rho;
+};
+
+// tau = tau_C + 1/2 (Eq. 49), 1/tau_C = 1/tau_N + 1/tau_R; beta of Eq. 54;
+// kappa = 1/tau - (1 - 1/(2 tau)) / tau_R combines the flux share of the
+// equilibrium (Eq. 15) with the source (Eq. 16); rho = 1 - beta / tau_R is the
+// resulting per-step factor on the heat flux.
+Coeffs coeffs_of(const lbm_instance& in) {
+    Coeffs c;
+    const bool inf_r = std::isinf(in.tau_r);
+    const double inv_tc = 1.0 / in.tau_n + (inf_r ? 0.0 : 1.0 / in.tau_r);
+    c.tau_c = 1.0 / inv_tc;
+    c.tau = c.tau_c + 0.5;
+    c.beta = inf_r ? 1.0 : 2.0 * in.tau_r / (2.0 * in.tau_r + 1.0);
+    c.kappa = 1.0 / c.tau - (inf_r ? 0.0 : (1.0 - 1.0 / (2.0 * c.tau)) / in.tau_r);
+    c.rho = inf_r ? 1.0 : (2.0 * in.tau_r - 1.0) / (2.0 * in.tau_r + 1.0);
+    return c;
+}
+
+Status validate_instance(const lbm_instance& in, int k) {
+    char b[256];
+    if (in.nx < 2 || in.ny < 2) {
+        snprintf(b, sizeof b, "instance %d: nx, ny must be >= 2 (got %d x %d)", k, in.nx, in.ny);
+        return {LBM_EINVAL, b};
+    }
+    if ((int64_t)in.nx * in.ny > ((int64_t)1 << 31)) {
+        snprintf(b, sizeof b, "instance %d: more than 2^31 nodes", k);
+        return {LBM_EINVAL, b};
+    }
+    if (!(in.tau_n > 0.0) || std::isinf(in.tau_n) || !(in.tau_r > 0.0)) {
+        snprintf(b, sizeof b, "instance %d: need 0 < tau_n < inf and tau_r > 0 (got %g, %g)", k,
+                 in.tau_n, in.tau_r);
+        return {LBM_EINVAL, b};
+    }
+    if (in.cv < 0.0 || !std::isfinite(in.cv)) {
+        snprintf(b, sizeof b, "instance %d: cv must be finite and >= 0", k);
+        return {LBM_EINVAL, b};
+    }
+    if (in.bc_x < 0 || in.bc_x > 3 || in.bc_y < 0 || in.bc_y > 2) {
+        snprintf(b, sizeof b, "instance %d: bad boundary kind (bc_x %d, bc_y %d; GRADIENT is x only)",
+                 k, in.bc_x, in.bc_y);
+        return {LBM_EINVAL, b};
+    }
+    const bool wx = in.bc_x == LBM_BC_ISOTHERMAL || in.bc_x == LBM_BC_DIFFUSE;
+    const bool wy = in.bc_y == LBM_BC_ISOTHERMAL || in.bc_y == LBM_BC_DIFFUSE;
+    if (wx && wy) {
+        snprintf(b, sizeof b, "instance %d: walls on both axes need corner treatment (undefined)", k);
+        return {LBM_EUNSUPPORTED, b};
+    }
+    if (in.bc_x == LBM_BC_GRADIENT && in.bc_y == LBM_BC_ISOTHERMAL) {
+        snprintf(b, sizeof b, "instance %d: isothermal walls across a gradient seam are undefined", k);
+        return {LBM_EUNSUPPORTED, b};
+    }
+    int ex = 0;
+    if (in.scale < 0.0 || !std::isfinite(in.scale) ||
+        (in.scale > 0.0 && std::frexp(in.scale, &ex) != 0.5)) {
+        snprintf(b, sizeof b, "instance: scale must be 0 or a power of two (got %g)", in.scale);
+        return {LBM_EINVAL, b};
+    }
+    if (!std::isfinite(in.t0) || !std::isfinite(in.grad_x)) return {LBM_EINVAL, "t0 and grad_x must be finite"};
+    return {LBM_OK, ""};
+}
+
+// Worst-case tile count over launch shapes (smallest tile: 64 x 1 nodes).
+int64_t max_tiles(const std::vector<lbm_instance>& v) {
+    int64_t n = 0;
+    for (auto& in : v) n += (int64_t)((in.nx + 63) / 64) * in.ny;
+    return n;
+}
+
+struct Layout {
+    size_t buf_bytes = 0;      // one population buffer
+    size_t off_buf[2] = {0, 0};
+    size_t off_snap = 0, off_part = 0, off_res = 0, off_mpart = 0, off_mres = 0, off_desc = 0,
+           off_tiles = 0, total = 0;
+    int64_t nodes = 0, tiles_max = 0, mparts_max = 0;
+};
+
+Layout layout_of(const std::vector<lbm_instance>& v, int storage, int check) {
+    Layout L;
+    const int es = esize_of(storage);
+    size_t elems = 0;
+    for (auto& in : v) {
+        elems += 8 * (size_t)plane_of(in, es);
+        L.nodes += (int64_t)in.nx * in.ny;
+        L.mparts_max = std::max<int64_t>(L.mparts_max, (int64_t)((in.nx + 255) / 256) * in.ny);
+    }
+    L.buf_bytes = align_up(elems * es, kAlign);
+    L.tiles_max = max_tiles(v);
+    size_t o = 0;
+    L.off_buf[0] = o; o += L.buf_bytes;
+    L.off_buf[1] = o; o += L.buf_bytes;
+    L.off_snap = o; o += check ? align_up(3 * (size_t)L.nodes * sizeof(double), kAlign) : 0;
+    L.off_part = o; o += align_up((size_t)L.tiles_max * kPartials * sizeof(double), kAlign);
+    L.off_res = o; o += align_up(v.size() * kPartials * sizeof(double), kAlign);
+    L.off_mpart = o; o += align_up((size_t)L.mparts_max * kPartials * sizeof(double), kAlign);
+    L.off_mres = o; o += align_up(kPartials * sizeof(double), kAlign);
+    L.off_desc = o; o += align_up(v.size() * sizeof(InstDesc), kAlign);
+    L.off_tiles = o; o += align_up((size_t)L.tiles_max * sizeof(int32_t), kAlign);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    uint32_t magic = kMagic;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    int storage = 0;
+    int K = 100;                     // check interval, 0 = off
+    std::vector<lbm_instance> inst;
+    std::vector<InstDesc> desc;
+    std::vector<Coeffs> co;
+    std::vector<char> inited;
+    Shape shape;
+    Layout L;
+    int64_t ntiles = 0;
+    std::vector<int32_t> tile_inst;
+    bool external = false;
+    char* base = nullptr;            // device memory (owned unless external)
+    bool owned = false;
+    int cur = 0;                     // buffer holding the post-relaxation state of the last step
+    int64_t steps = 0;
+    int64_t last_check = -1;
+    int sched = LBM_SCHED_BATCHED;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int graph_chunk = 0;
+    double* staging = nullptr;       // device FP64 staging for host I/O (lazy)
+    size_t staging_bytes = 0;
+    std::string err;
+
+    char* ptr(size_t off) const { return base + off; }
+    void* buf(int k) const { return base + L.off_buf[k]; }
+    InstDesc* d_desc() const { return reinterpret_cast<InstDesc*>(base + L.off_desc); }
+    int32_t* d_tiles() const { return reinterpret_cast<int32_t*>(base + L.off_tiles); }
+    double* d_snap() const { return K ? reinterpret_cast<double*>(base + L.off_snap) : nullptr; }
+    double* d_part() const { return reinterpret_cast<double*>(base + L.off_part); }
+    double* d_res() const { return reinterpret_cast<double*>(base + L.off_res); }
+    double* d_mpart() const { return reinterpret_cast<double*>(base + L.off_mpart); }
+    double* d_mres() const { return reinterpret_cast<double*>(base + L.off_mres); }
+
+    int fail(int code, const std::string& m) {
+        err = m;
+        return code;
+    }
+    int hip_fail(hipError_t e, const char* what) {
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return LBM_EHIP;
+    }
+    void drop_graphs() {
+        for (int k = 0; k < 2; ++k) {
+            if (gexec[k]) (void)hipGraphExecDestroy(gexec[k]);
+            if (graph[k]) (void)hipGraphDestroy(graph[k]);
+            gexec[k] = nullptr;
+            graph[k] = nullptr;
+        }
+        graph_chunk = 0;
+    }
+};
+
+#define HIPCALL(h, expr)                                         \
+    do {                                                         \
+        hipError_t e_ = (expr);                                  \
+        if (e_ != hipSuccess) return (h)->hip_fail(e_, #expr);   \
+    } while (0)
+
+static bool valid(lbm_handle h) { return h && h->magic == kMagic; }
+
+// ------------------------------------------------------------------ schedule
+
+static void build_tiles(lbm_ctx* h) {
+    const Shape& s = h->shape;
+    h->ntiles = 0;
+    h->tile_inst.clear();
+    for (size_t k = 0; k < h->inst.size(); ++k) {
+        InstDesc& d = h->desc[k];
+        const int tw = s.tile_w();
+        d.tiles_x = (d.nx + tw - 1) / tw;
+        const int tys = (d.ny + s.by - 1) / s.by;
+        d.tile_begin = (int32_t)h->ntiles;
+        d.ntiles = d.tiles_x * tys;
+        h->ntiles += d.ntiles;
+        h->tile_inst.insert(h->tile_inst.end(), (size_t)d.ntiles, (int32_t)k);
+    }
+}
+
+static int upload_tables(lbm_ctx* h) {
+    HIPCALL(h, hipMemcpyAsync(h->d_desc(), h->desc.data(), h->desc.size() * sizeof(InstDesc),
+                              hipMemcpyHostToDevice, h->stream));
+    HIPCALL(h, hipMemcpyAsync(h->d_tiles(), h->tile_inst.data(), h->tile_inst.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, h->stream));
+    HIPCALL(h, hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+// Kernel coefficients of instance k for the effective storage scale s.
+static void fill_desc(lbm_ctx* h, size_t k, double s) {
+    const lbm_instance& in = h->inst[k];
+    const Coeffs& c = h->co[k];
+    InstDesc& d = h->desc[k];
+    d.inv_tau = (float)(1.0 / c.tau);
+    d.kb_axis = (float)(c.kappa * c.beta / 3.0);
+    d.kb_diag = (float)(c.kappa * c.beta / 12.0);
+    d.grad_term = in.bc_x == LBM_BC_GRADIENT ? (float)(in.cv * in.grad_x / s) : 0.0f;
+    for (int w = 0; w < 4; ++w) d.wall_g[w] = (float)(in.cv * (in.t_wall[w] - in.t0) / s);
+    d.s = s;
+    d.cv = in.cv;
+    d.s_cv = s / in.cv;
+    d.s_beta = s * c.beta;
+}
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+const char* lbm_version(void) { return "phonon-lbm 0.1 (gfx950, D2Q8 Callaway dual relaxation)"; }
+
+const char* lbm_last_error(lbm_handle h) {
+    if (!h) return g_create_error.c_str();
+    if (!valid(h)) return "invalid handle";
+    return h->err.c_str();
+}
+
+static Status check_config(const lbm_config* cfg, std::vector<lbm_instance>* out) {
+    if (!cfg) return {LBM_EINVAL, "config is NULL"};
+    if (cfg->n_instances < 1 || !cfg->inst) return {LBM_EINVAL, "need n_instances >= 1 and inst != NULL"};
+    if (cfg->storage < 0 || cfg->storage > 2) return {LBM_EINVAL, "storage must be LBM_F32, LBM_F16 or LBM_BF16"};
+    if (cfg->check_interval != 0 && cfg->check_interval != -1 && cfg->check_interval < 2)
+        return {LBM_EINVAL, "check_interval must be 0 (default 100), -1 (off) or >= 2"};
+    if (cfg->flags & ~LBM_FLAG_EXTERNAL_MEMORY) return {LBM_EINVAL, "unknown flags"};
+    out->assign(cfg->inst, cfg->inst + cfg->n_instances);
+    for (int k = 0; k < cfg->n_instances; ++k) {
+        lbm_instance& in = (*out)[k];
+        if (in.cv == 0.0) in.cv = 1.0;
+        Status s = validate_instance(in, k);
+        if (s.code) return s;
+    }
+    return {LBM_OK, ""};
+}
+
+static int check_of(const lbm_config* cfg) {
+    return cfg->check_interval == 0 ? 100 : (cfg->check_interval < 0 ? 0 : cfg->check_interval);
+}
+
+int lbm_required_bytes(const lbm_config* cfg, size_t* bytes) {
+    std::vector<lbm_instance> v;
+    Status s = check_config(cfg, &v);
+    if (s.code) {
+        g_create_error = s.msg;
+        return s.code;
+    }
+    if (!bytes) {
+        g_create_error = "bytes is NULL";
+        return LBM_EINVAL;
+    }
+    *bytes = layout_of(v, cfg->storage, check_of(cfg)).total;
+    return LBM_OK;
+}
+
+int lbm_create(const lbm_config* cfg, lbm_handle* out) {
+    g_create_error.clear();
+    if (!out) {
+        g_create_error = "out is NULL";
+        return LBM_EINVAL;
+    }
+    std::vector<lbm_instance> v;
+    Status s = check_config(cfg, &v);
+    if (s.code) {
+        g_create_error = s.msg;
+        return s.code;
+    }
+    lbm_ctx* h = new (std::nothrow) lbm_ctx();
+    if (!h) {
+        g_create_error = "host allocation failed";
+        return LBM_ENOMEM;
+    }
+    h->inst = v;
+    h->storage = cfg->storage;
+    h->K = check_of(cfg);
+    h->stream = reinterpret_cast<hipStream_t>(cfg->stream);
+    h->external = (cfg->flags & LBM_FLAG_EXTERNAL_MEMORY) != 0;
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        g_create_error = std::string("hipGetDevice: ") + hipGetErrorString(e);
+        delete h;
+        return LBM_EHIP;
+    }
+    const int es = esize_of(h->storage);
+    h->L = layout_of(v, h->storage, h->K);
+    h->desc.resize(v.size());
+    h->co.resize(v.size());
+    h->inited.assign(v.size(), 0);
+    size_t eoff = 0;
+    int64_t noff = 0;
+    for (size_t k = 0; k < v.size(); ++k) {
+        InstDesc& d = h->desc[k];
+        std::memset(&d, 0, sizeof d);
+        d.nx = v[k].nx;
+        d.ny = v[k].ny;
+        d.pitch = pitch_of(v[k].nx, es);
+        d.bc_x = v[k].bc_x;
+        d.bc_y = v[k].bc_y;
+        d.plane = plane_of(v[k], es);
+        d.off = (int64_t)eoff;
+        d.node_off = noff;
+        eoff += 8 * (size_t)d.plane;
+        noff += (int64_t)d.nx * d.ny;
+        h->co[k] = coeffs_of(v[k]);
+        fill_desc(h, k, v[k].scale > 0.0 ? v[k].scale : 1.0);
+    }
+    // default launch shape: 4 nodes per thread for FP32, 8 bytes per access
+    // for 16-bit storage, 256 threads per block, XCD-aware tile order
+    h->shape.vec = 4;
+    h->shape.bx = 256;
+    h->shape.by = 1;
+    h->shape.xcd = 1;
+    h->shape.nt = 0;
+    build_tiles(h);
+    e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        g_create_error = std::string("hipStreamCreate: ") + hipGetErrorString(e);
+        delete h;
+        return LBM_EHIP;
+    }
+    if (!h->external) {
+        e = hipMalloc(&h->base, h->L.total);
+        if (e != hipSuccess) {
+            g_create_error = std::string("hipMalloc of ") + std::to_string(h->L.total) +
+                             " bytes: " + hipGetErrorString(e);
+            (void)hipStreamDestroy(h->capture_stream);
+            delete h;
+            return e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EHIP;
+        }
+        h->owned = true;
+        int rc = upload_tables(h);
+        if (rc) {
+            g_create_error = h->err;
+            (void)hipFree(h->base);
+            (void)hipStreamDestroy(h->capture_stream);
+            delete h;
+            return rc;
+        }
+    }
+    *out = h;
+    return LBM_OK;
+}
+
+int lbm_bind(lbm_handle h, void* device_buf, size_t bytes) {
+    if (!valid(h)) return LBM_EINVAL;
+    if (!h->external) return h->fail(LBM_ESTATE, "handle owns its memory (created without LBM_FLAG_EXTERNAL_MEMORY)");
+    if (h->base) return h->fail(LBM_ESTATE, "memory already bound");
+    if (!device_buf || bytes < h->L.total)
+        return h->fail(LBM_EINVAL, "buffer NULL or smaller than lbm_required_bytes (" +
+                                       std::to_string(h->L.total) + ")");
+    if (reinterpret_cast<uintptr_t>(device_buf) % kAlign)
+        return h->fail(LBM_EINVAL, "buffer must be 256-byte aligned");
+    h->base = static_cast<char*>(device_buf);
+    return upload_tables(h);
+}
+
+void lbm_destroy(lbm_handle h) {
+    if (!valid(h)) return;
+    if (h->stream) hipStreamSynchronize(h->stream);
+    else (void)hipDeviceSynchronize();
+    h->drop_graphs();
+    if (h->owned && h->base) (void)hipFree(h->base);
+    if (h->staging) (void)hipFree(h->staging);
+    if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
+    h->magic = 0;
+    delete h;
+}
+
+static int ensure_staging(lbm_ctx* h, size_t bytes) {
+    if (h->staging_bytes >= bytes) return LBM_OK;
+    if (h->staging) {
+        HIPCALL(h, hipStreamSynchronize(h->stream));
+        (void)hipFree(h->staging);
+        h->staging = nullptr;
+        h->staging_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&h->staging, bytes);
+    if (e != hipSuccess) return h->fail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EHIP,
+                                        std::string("staging hipMalloc: ") + hipGetErrorString(e));
+    h->staging_bytes = bytes;
+    return LBM_OK;
+}
+
+static int check_inst(lbm_ctx* h, int32_t k) {
+    if (k < 0 || k >= (int32_t)h->inst.size())
+        return h->fail(LBM_EINVAL, "instance index out of range");
+    if (!h->base) return h->fail(LBM_ESTATE, "no device memory bound");
+    return LBM_OK;
+}
+
+// Automatic storage scale: FP16 keeps the largest expected |g| near 2^12 or
+// below, far under its 65504 limit and well above its normal range floor.
+static double auto_scale(const lbm_ctx* h, const lbm_instance& in, double amp) {
+    if (h->storage != LBM_F16) return 1.0;
+    if (in.bc_x == LBM_BC_ISOTHERMAL) amp = std::max({amp, std::fabs(in.t_wall[0] - in.t0), std::fabs(in.t_wall[1] - in.t0)});
+    if (in.bc_y == LBM_BC_ISOTHERMAL) amp = std::max({amp, std::fabs(in.t_wall[2] - in.t0), std::fabs(in.t_wall[3] - in.t0)});
+    if (in.bc_x == LBM_BC_GRADIENT) {
+        const double tr = std::isinf(in.tau_r) ? 1e6 : in.tau_r;
+        amp = std::max(amp, 5.0 / 9.0 * in.cv * std::fabs(in.grad_x) * std::max(tr, 1.0));
+    }
+    if (!(amp > 0.0) || !std::isfinite(amp)) return 1.0;
+    return std::ldexp(1.0, (int)std::ceil(std::log2(amp)) - 13);
+}
+
+static int do_init(lbm_ctx* h, int32_t k, const double* dT, const double* dqx, const double* dqy) {
+    const lbm_instance& in = h->inst[k];
+    const InstDesc& d = h->desc[k];
+    HIPCALL(h, hipMemcpyAsync(h->d_desc(), h->desc.data(), h->desc.size() * sizeof(InstDesc),
+                              hipMemcpyHostToDevice, h->stream));
+    const double grad = in.bc_x == LBM_BC_GRADIENT ? in.grad_x : 0.0;
+    HIPCALL(h, launch_init(h->storage, h->d_desc(), k, d, h->buf(1 - h->cur), h->buf(h->cur), dT, dqx,
+                           dqy, in.t0, grad, h->co[k].beta, h->stream));
+    HIPCALL(h, hipStreamSynchronize(h->stream));
+    if (h->steps != 0) {
+        // the handle restarts at n = 0: every other instance must be re-initialised
+        std::fill(h->inited.begin(), h->inited.end(), 0);
+        h->steps = 0;
+    }
+    h->last_check = -1;
+    h->inited[k] = 1;
+    h->drop_graphs();
+    return LBM_OK;
+}
+
+int lbm_init(lbm_handle h, int32_t k, const double* T, const double* qx, const double* qy) {
+    if (!valid(h)) return LBM_EINVAL;
+    int rc = check_inst(h, k);
+    if (rc) return rc;
+    const lbm_instance& in = h->inst[k];
+    const size_t n = (size_t)in.nx * in.ny;
+    const double grad = in.bc_x == LBM_BC_GRADIENT ? in.grad_x : 0.0;
+    std::vector<double> tmp;
+    if (!T) {
+        tmp.resize(n);
+        for (int y = 0; y < in.ny; ++y)
+            for (int x = 0; x < in.nx; ++x) tmp[(size_t)y * in.nx + x] = in.t0 - grad * x;
+        T = tmp.data();
+    }
+    double amp = 0.0;
+    for (int y = 0; y < in.ny; ++y)
+        for (int x = 0; x < in.nx; ++x) {
+            const size_t i = (size_t)y * in.nx + x;
+            const double v = T[i] - (in.t0 - grad * x);
+            const double a = std::max({std::fabs(v), qx ? std::fabs(qx[i]) : 0.0, qy ? std::fabs(qy[i]) : 0.0});
+            if (!std::isfinite(a)) return h->fail(LBM_EINVAL, "non-finite initial field");
+            amp = std::max(amp, a);
+        }
+    fill_desc(h, k, in.scale > 0.0 ? in.scale : auto_scale(h, in, amp));
+    rc = ensure_staging(h, 3 * n * sizeof(double));
+    if (rc) return rc;
+    HIPCALL(h, hipMemcpyAsync(h->staging, T, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    const double* dqx = nullptr;
+    const double* dqy = nullptr;
+    if (qx) {
+        HIPCALL(h, hipMemcpyAsync(h->staging + n, qx, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        dqx = h->staging + n;
+    }
+    if (qy) {
+        HIPCALL(h, hipMemcpyAsync(h->staging + 2 * n, qy, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        dqy = h->staging + 2 * n;
+    }
+    return do_init(h, k, h->staging, dqx, dqy);
+}
+
+int lbm_init_device(lbm_handle h, int32_t k, const double* T, const double* qx, const double* qy) {
+    if (!valid(h)) return LBM_EINVAL;
+    int rc = check_inst(h, k);
+    if (rc) return rc;
+    if (!T) return h->fail(LBM_EINVAL, "T is NULL (device init needs a temperature field)");
+    const lbm_instance& in = h->inst[k];
+    if (h->storage == LBM_F16 && in.scale == 0.0)
+        return h->fail(LBM_EINVAL, "FP16 storage with device init needs an explicit scale");
+    fill_desc(h, k, in.scale > 0.0 ? in.scale : 1.0);
+    return do_init(h, k, T, qx, qy);
+}
+
+int64_t lbm_steps_done(lbm_handle h) { return valid(h) ? h->steps : -1; }
+
+static int mode_of(const lbm_ctx* h, int64_t m) {
+    if (!h->K) return kPlain;
+    if (m % h->K == 0) return kCheck;
+    if ((m + 1) % h->K == 0) return kSnap;
+    return kPlain;
+}
+
+// Issue step number m (1-based) on stream st reading buffer `src_k`.
+static int issue_step(lbm_ctx* h, int64_t m, int src_k, hipStream_t st, int sched) {
+    const int mode = mode_of(h, m);
+    StepArgs a;
+    a.desc = h->d_desc();
+    a.tile_inst = h->d_tiles();
+    a.src = h->buf(src_k);
+    a.dst = h->buf(1 - src_k);
+    a.snap = h->d_snap();
+    a.partials = h->d_part();
+    if (sched == LBM_SCHED_PER_INSTANCE) {
+        for (size_t k = 0; k < h->inst.size(); ++k) {
+            a.tile_base = h->desc[k].tile_begin;
+            a.ntiles = h->desc[k].ntiles;
+            HIPCALL(h, launch_step(h->storage, h->shape, mode, a, h->L.nodes, st));
+        }
+    } else {
+        a.tile_base = 0;
+        a.ntiles = (int32_t)h->ntiles;
+        HIPCALL(h, launch_step(h->storage, h->shape, mode, a, h->L.nodes, st));
+    }
+    if (mode == kCheck)
+        HIPCALL(h, launch_finalize(h->d_desc(), (int)h->inst.size(), h->d_part(), h->d_res(), st));
+    return LBM_OK;
+}
+
+static int chunk_of(const lbm_ctx* h) { return h->K ? h->K : 64; }
+
+// Capture one chunk of steps starting at a multiple of the chunk with
+// buffer parity `par` (the index of the buffer holding the current state).
+static int capture(lbm_ctx* h, int par) {
+    const int C = chunk_of(h);
+    HIPCALL(h, hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
+    int src = par;
+    int rc = LBM_OK;
+    for (int s = 1; s <= C && rc == LBM_OK; ++s) {
+        rc = issue_step(h, (int64_t)s, src, h->capture_stream, LBM_SCHED_BATCHED);
+        src = 1 - src;
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->capture_stream, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return h->hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return h->hip_fail(e, "hipGraphInstantiate");
+    }
+    h->graph[par] = g;
+    h->gexec[par] = x;
+    h->graph_chunk = C;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_handle h, int64_t nsteps) {
+    if (!valid(h)) return LBM_EINVAL;
+    if (nsteps < 0) return h->fail(LBM_EINVAL, "nsteps < 0");
+    if (!h->base) return h->fail(LBM_ESTATE, "no device memory bound");
+    for (char c : h->inited)
+        if (!c) return h->fail(LBM_ESTATE, "every instance must be initialised before lbm_step");
+    int64_t left = nsteps;
+    while (left > 0) {
+        const int C = chunk_of(h);
+        if (h->sched == LBM_SCHED_GRAPH && h->steps % C == 0 && left >= C) {
+            if (!h->gexec[h->cur]) {
+                int rc = capture(h, h->cur);
+                if (rc) return rc;
+            }
+            HIPCALL(h, hipGraphLaunch(h->gexec[h->cur], h->stream));
+            h->steps += C;
+            if (C & 1) h->cur = 1 - h->cur;
+            if (h->K) h->last_check = h->steps;
+            left -= C;
+            continue;
+        }
+        const int64_t m = h->steps + 1;
+        int rc = issue_step(h, m, h->cur, h->stream,
+                            h->sched == LBM_SCHED_PER_INSTANCE ? LBM_SCHED_PER_INSTANCE : LBM_SCHED_BATCHED);
+        if (rc) return rc;
+        if (mode_of(h, m) == kCheck) h->last_check = m;
+        h->cur = 1 - h->cur;
+        h->steps = m;
+        --left;
+    }
+    return LBM_OK;
+}
+
+static int run_moments(lbm_ctx* h, int32_t k, int out_kind, void* T, void* qx, void* qy, double* partials) {
+    const lbm_instance& in = h->inst[k];
+    const double grad = in.bc_x == LBM_BC_GRADIENT ? in.grad_x : 0.0;
+    HIPCALL(h, launch_moments(h->storage, h->d_desc(), k, h->desc[k], h->buf(1 - h->cur), h->steps > 0 ? 1 : 0,
+                              out_kind, T, qx, qy, in.t0, grad, partials, h->stream));
+    return LBM_OK;
+}
+
+static int moments_common(lbm_handle h, int32_t k, int out_kind, void* T, void* qx, void* qy, int on_device) {
+    if (!valid(h)) return LBM_EINVAL;
+    int rc = check_inst(h, k);
+    if (rc) return rc;
+    if (!h->inited[k]) return h->fail(LBM_ESTATE, "instance not initialised");
+    const lbm_instance& in = h->inst[k];
+    const size_t n = (size_t)in.nx * in.ny;
+    const size_t es = out_kind == 0 ? sizeof(float) : sizeof(double);
+    if (on_device) {
+        rc = run_moments(h, k, out_kind, T, qx, qy, nullptr);
+        if (rc) return rc;
+        HIPCALL(h, hipStreamSynchronize(h->stream));
+        return LBM_OK;
+    }
+    rc = ensure_staging(h, 3 * n * sizeof(double));
+    if (rc) return rc;
+    char* st = reinterpret_cast<char*>(h->staging);
+    void* dv[3] = {T ? st : nullptr, qx ? st + n * es : nullptr, qy ? st + 2 * n * es : nullptr};
+    rc = run_moments(h, k, out_kind, dv[0], dv[1], dv[2], nullptr);
+    if (rc) return rc;
+    void* hv[3] = {T, qx, qy};
+    for (int c = 0; c < 3; ++c)
+        if (hv[c]) HIPCALL(h, hipMemcpyAsync(hv[c], dv[c], n * es, hipMemcpyDeviceToHost, h->stream));
+    HIPCALL(h, hipStreamSynchronize(h->stream));
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_handle h, int32_t k, float* T, float* qx, float* qy, int32_t on_device) {
+    return moments_common(h, k, 0, T, qx, qy, on_device);
+}
+
+int lbm_moments_f64(lbm_handle h, int32_t k, double* dT, double* qx, double* qy, int32_t on_device) {
+    return moments_common(h, k, 1, dT, qx, qy, on_device);
+}
+
+int lbm_totals(lbm_handle h, int32_t k, double out[3]) {
+    if (!valid(h)) return LBM_EINVAL;
+    int rc = check_inst(h, k);
+    if (rc) return rc;
+    if (!out) return h->fail(LBM_EINVAL, "out is NULL");
+    if (!h->inited[k]) return h->fail(LBM_ESTATE, "instance not initialised");
+    rc = run_moments(h, k, 1, nullptr, nullptr, nullptr, h->d_mpart());
+    if (rc) return rc;
+    const InstDesc& d = h->desc[k];
+    const int nparts = ((d.nx + 255) / 256) * d.ny;
+    HIPCALL(h, launch_finalize_range(h->d_mpart(), nparts, h->d_mres(), h->stream));
+    double r[kPartials];
+    HIPCALL(h, hipMemcpyAsync(r, h->d_mres(), sizeof r, hipMemcpyDeviceToHost, h->stream));
+    HIPCALL(h, hipStreamSynchronize(h->stream));
+    for (int c = 0; c < 3; ++c) out[c] = r[c];
+    for (int c = 0; c < 3; ++c)
+        if (!std::isfinite(out[c])) return h->fail(LBM_ENONFINITE, "non-finite total");
+    return LBM_OK;
+}
+
+int lbm_last_check(lbm_handle h, int32_t k, lbm_check_info* out) {
+    if (!valid(h)) return LBM_EINVAL;
+    int rc = check_inst(h, k);
+    if (rc) return rc;
+    if (!out) return h->fail(LBM_EINVAL, "out is NULL");
+    if (h->last_check < 0) return h->fail(LBM_ESTATE, "no check step yet");
+    double r[kPartials];
+    HIPCALL(h, hipMemcpyAsync(r, h->d_res() + (size_t)k * kPartials, sizeof r, hipMemcpyDeviceToHost, h->stream));
+    HIPCALL(h, hipStreamSynchronize(h->stream));
+    out->step = h->last_check;
+    out->totals[0] = r[0];
+    out->totals[1] = r[1];
+    out->totals[2] = r[2];
+    out->residual = r[4] > 0.0 ? std::sqrt(r[3] / r[4]) : (r[3] == 0.0 ? 0.0 : INFINITY);
+    for (double v : r)
+        if (!std::isfinite(v)) return h->fail(LBM_ENONFINITE, "non-finite value in the check reduction");
+    return LBM_OK;
+}
+
+int lbm_residual(lbm_handle h, int32_t k, double* r) {
+    if (!valid(h)) return LBM_EINVAL;
+    if (!r) return h->fail(LBM_EINVAL, "r is NULL");
+    lbm_check_info ci;
+    int rc = lbm_last_check(h, k, &ci);
+    if (rc && rc != LBM_ENONFINITE) return rc;
+    *r = ci.residual;
+    return rc;
+}
+
+int lbm_coefficients(lbm_handle h, int32_t k, double out[6]) {
+    if (!valid(h)) return LBM_EINVAL;
+    if (k < 0 || k >= (int32_t)h->inst.size()) return h->fail(LBM_EINVAL, "instance index out of range");
+    if (!out) return h->fail(LBM_EINVAL, "out is NULL");
+    const InstDesc& d = h->desc[k];
+    const Coeffs& c = h->co[k];
+    out[0] = d.inv_tau;
+    out[1] = (float)c.beta;
+    out[2] = (float)(c.kappa * c.beta);
+    out[3] = d.s;
+    out[4] = c.tau;
+    out[5] = c.rho;
+    return LBM_OK;
+}
+
+int lbm_set_schedule(lbm_handle h, int32_t schedule) {
+    if (!valid(h)) return LBM_EINVAL;
+    if (schedule < 0 || schedule > 2) return h->fail(LBM_EINVAL, "unknown schedule");
+    h->sched = schedule;
+    return LBM_OK;
+}
+
+static Status shape_ok(const lbm_launch_shape* s) {
+    if (!s) return {LBM_EINVAL, "shape is NULL"};
+    if (s->vec != 1 && s->vec != 2 && s->vec != 4) return {LBM_EINVAL, "vec must be 1, 2 or 4"};
+    if (s->block_x < 64 || s->block_x % 64 || s->block_x > kMaxBlock)
+        return {LBM_EINVAL, "block_x must be a multiple of 64 in [64, 512]"};
+    if (s->block_y < 1 || s->block_x * s->block_y > kMaxBlock)
+        return {LBM_EINVAL, "block_y >= 1 with block_x * block_y <= 512"};
+    return {LBM_OK, ""};
+}
+
+int lbm_set_launch_shape(lbm_handle h, const lbm_launch_shape* s) {
+    if (!valid(h)) return LBM_EINVAL;
+    Status st = shape_ok(s);
+    if (st.code) return h->fail(st.code, st.msg);
+    h->shape.vec = s->vec;
+    h->shape.bx = s->block_x;
+    h->shape.by = s->block_y;
+    h->shape.xcd = s->xcd_remap ? 1 : 0;
+    h->shape.nt = s->nontemporal ? 1 : 0;
+    build_tiles(h);
+    h->drop_graphs();
+    if (h->base) return upload_tables(h);
+    return LBM_OK;
+}
+
+int lbm_get_launch_shape(lbm_handle h, lbm_launch_shape* s) {
+    if (!valid(h)) return LBM_EINVAL;
+    if (!s) return h->fail(LBM_EINVAL, "shape is NULL");
+    s->vec = h->shape.vec;
+    s->block_x = h->shape.bx;
+    s->block_y = h->shape.by;
+    s->xcd_remap = h->shape.xcd;
+    s->nontemporal = h->shape.nt;
+    return LBM_OK;
+}
+
+
+// ------------------------------------------------------------------ autotuner
+
+static std::string tune_key(lbm_ctx* h) {
+    hipDeviceProp_t p;
+    std::string dev = "unknown";
+    if (hipGetDeviceProperties(&p, h->device) == hipSuccess) dev = std::string(p.gcnArchName);
+    uint64_t f = 1469598103934665603ull;   // FNV-1a over the instance shapes
+    auto mix = [&f](int64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            f ^= (uint64_t)((v >> (8 * b)) & 0xff);
+            f *= 1099511628211ull;
+        }
+    };
+    for (auto& in : h->inst) {
+        mix(in.nx);
+        mix(in.ny);
+        mix(in.bc_x * 4 + in.bc_y);
+    }
+    char b[160];
+    snprintf(b, sizeof b, "%s|s%d|n%zu|%016llx", dev.c_str(), h->storage, h->inst.size(),
+             (unsigned long long)f);
+    for (char* c = b; *c; ++c)
+        if (*c == ' ' || *c == '"') *c = '_';
+    return b;
+}
+
+static bool cache_lookup(const char* path, const std::string& key, Shape* out) {
+    FILE* fp = fopen(path, "r");
+    if (!fp) return false;
+    char line[512];
+    bool found = false;
+    while (fgets(line, sizeof line, fp)) {
+        char k[200];
+        Shape s;
+        if (sscanf(line, "{\"key\": \"%199[^\"]\", \"vec\": %d, \"block_x\": %d, \"block_y\": %d, "
+                         "\"xcd\": %d, \"nt\": %d",
+                   k, &s.vec, &s.bx, &s.by, &s.xcd, &s.nt) == 6 &&
+            key == k) {
+            *out = s;
+            found = true;   // the last matching line wins
+        }
+    }
+    fclose(fp);
+    return found;
+}
+
+static int time_shape(lbm_ctx* h, const Shape& s, int steps, hipEvent_t e0, hipEvent_t e1, float* us) {
+    h->shape = s;
+    build_tiles(h);
+    int rc = upload_tables(h);
+    if (rc) return rc;
+    StepArgs a;
+    a.desc = h->d_desc();
+    a.tile_inst = h->d_tiles();
+    a.snap = nullptr;
+    a.partials = nullptr;
+    a.tile_base = 0;
+    a.ntiles = (int32_t)h->ntiles;
+    int src = 0;
+    for (int w = 0; w < 3 + steps; ++w) {
+        if (w == 3) HIPCALL(h, hipEventRecord(e0, h->stream));
+        a.src = h->buf(src);
+        a.dst = h->buf(1 - src);
+        HIPCALL(h, launch_step(h->storage, s, kPlain, a, h->L.nodes, h->stream));
+        src = 1 - src;
+    }
+    HIPCALL(h, hipEventRecord(e1, h->stream));
+    HIPCALL(h, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCALL(h, hipEventElapsedTime(&ms, e0, e1));
+    *us = 1000.0f * ms / steps;
+    return LBM_OK;
+}
+
+int lbm_autotune(lbm_handle h, int32_t steps, char* report, size_t report_len) {
+    if (!valid(h)) return LBM_EINVAL;
+    if (!h->base) return h->fail(LBM_ESTATE, "no device memory bound");
+    for (char c : h->inited)
+        if (c) return h->fail(LBM_ESTATE, "lbm_autotune must run before lbm_init");
+    if (steps <= 0) steps = 20;
+    const std::string key = tune_key(h);
+    const char* path = getenv("LBM_AUTOTUNE_CACHE");
+    Shape cached;
+    if (path && *path && cache_lookup(path, key, &cached)) {
+        lbm_launch_shape ls = {cached.vec, cached.bx, cached.by, cached.xcd, cached.nt};
+        if (report && report_len) snprintf(report, report_len, "{\"key\": \"%s\", \"cached\": true}", key.c_str());
+        return lbm_set_launch_shape(h, &ls);
+    }
+    // scratch contents: zeros, so no timing depends on garbage bit patterns
+    HIPCALL(h, hipMemsetAsync(h->buf(0), 0, h->L.buf_bytes, h->stream));
+    HIPCALL(h, hipMemsetAsync(h->buf(1), 0, h->L.buf_bytes, h->stream));
+    hipEvent_t e0, e1;
+    HIPCALL(h, hipEventCreate(&e0));
+    HIPCALL(h, hipEventCreate(&e1));
+    const int vecs[3] = {1, 2, 4};
+    const int blocks[9][2] = {{64, 1}, {128, 1}, {256, 1}, {512, 1}, {64, 2}, {64, 4}, {128, 2}, {128, 4}, {256, 2}};
+    std::string rep = "{\"key\": \"" + key + "\", \"cached\": false, \"timings_us\": [";
+    Shape best;
+    float best_us = 1e30f;
+    int rc = LBM_OK;
+    bool first = true;
+    auto try_shape = [&](const Shape& s) {
+        if (rc) return;
+        float us = 0.0f;
+        rc = time_shape(h, s, steps, e0, e1, &us);
+        if (rc) return;
+        char b[160];
+        snprintf(b, sizeof b, "%s[%d, %d, %d, %d, %d, %.2f]", first ? "" : ", ", s.vec, s.bx, s.by, s.xcd,
+                 s.nt, us);
+        first = false;
+        rep += b;
+        if (us < best_us) {
+            best_us = us;
+            best = s;
+        }
+    };
+    for (int v : vecs)
+        for (auto& b : blocks) {
+            Shape s;
+            s.vec = v;
+            s.bx = b[0];
+            s.by = b[1];
+            s.xcd = 1;
+            s.nt = 0;
+            try_shape(s);
+        }
+    const Shape base_best = best;
+    for (int xcd = 0; xcd < 2; ++xcd)
+        for (int nt = 0; nt < 2; ++nt) {
+            if (xcd == 1 && nt == 0) continue;
+            Shape s = base_best;
+            s.xcd = xcd;
+            s.nt = nt;
+            try_shape(s);
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    char b[256];
+    snprintf(b, sizeof b, "], \"best\": [%d, %d, %d, %d, %d, %.2f]}", best.vec, best.bx, best.by, best.xcd,
+             best.nt, best_us);
+    rep += b;
+    if (report && report_len) snprintf(report, report_len, "%s", rep.c_str());
+    if (path && *path) {
+        FILE* fp = fopen(path, "a");
+        if (fp) {
+            fprintf(fp, "{\"key\": \"%s\", \"vec\": %d, \"block_x\": %d, \"block_y\": %d, \"xcd\": %d, \"nt\": %d, "
+                        "\"us\": %.2f}\n",
+                    key.c_str(), best.vec, best.bx, best.by, best.xcd, best.nt, best_us);
+            fclose(fp);
+        }
+    }
+    lbm_launch_shape ls = {best.vec, best.bx, best.by, best.xcd, best.nt};
+    return lbm_set_launch_shape(h, &ls);
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+"""The C ABI library loads on a machine without a GPU and exports every entry
+point the header declares; host-side validation answers without a device."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import paper_2010_01847_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "phonon_lbm.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    names = _declared()
+    assert "lbm_create" in names and "lbm_step" in names and "lbm_residual" in names
+    L = P.library()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    bound = {s[0] for s in P.lbm.SIGNATURES}
+    assert set(names) == bound, set(names) ^ bound
+
+
+def test_struct_sizes_match_header():
+    # lbm_instance: 4 int32 + 9 doubles + 4-double array = 16 + 72 + 32 -> 120
+    assert ctypes.sizeof(P.lbm_instance) == 4 * 4 + 5 * 8 + 4 * 8 + 8
+    assert ctypes.sizeof(P.lbm_config) == 4 * 4 + 8 + 8
+    assert ctypes.sizeof(P.lbm_check_info) == 8 + 8 + 24
+    assert ctypes.sizeof(P.lbm_launch_shape) == 20
+
+
+def _cfg(insts, storage=P.LBM_F32, check=0, flags=P.LBM_FLAG_EXTERNAL_MEMORY):
+    arr = (P.lbm_instance * len(insts))(*insts)
+    cfg = P.lbm_config()
+    cfg.n_instances = len(insts)
+    cfg.storage = storage
+    cfg.check_interval = check
+    cfg.flags = flags
+    cfg.inst = ctypes.cast(arr, ctypes.POINTER(P.lbm_instance))
+    cfg._keep = arr
+    return cfg
+
+
+def test_required_bytes_and_layout():
+    it = P.make_instance(100, 30, 0.6, 0.8)
+    b32 = P.lbm_required_bytes(_cfg([it], check=-1))
+    b16 = P.lbm_required_bytes(_cfg([it], storage=P.LBM_F16, check=-1))
+    # two buffers of 8 planes, rows padded to 256 bytes
+    assert b32 >= 2 * 8 * 30 * 128 * 4
+    assert b16 >= 2 * 8 * 30 * 128 * 2
+    assert b32 > b16
+    # check-step snapshot adds 3 doubles per node
+    assert P.lbm_required_bytes(_cfg([it], check=10)) - b32 >= 3 * 8 * 100 * 30
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(nx=1, ny=8, tau_n=0.6, tau_r=0.8), P.LBM_EINVAL),
+    (dict(nx=8, ny=8, tau_n=0.0, tau_r=0.8), P.LBM_EINVAL),
+    (dict(nx=8, ny=8, tau_n=0.6, tau_r=-1.0), P.LBM_EINVAL),
+    (dict(nx=8, ny=8, tau_n=math.inf, tau_r=1.0), P.LBM_EINVAL),
+    (dict(nx=8, ny=8, tau_n=0.6, tau_r=0.8, bc_x="isothermal", bc_y="diffuse"), P.LBM_EUNSUPPORTED),
+    (dict(nx=8, ny=8, tau_n=0.6, tau_r=0.8, bc_x="gradient", bc_y="isothermal"), P.LBM_EUNSUPPORTED),
+    (dict(nx=8, ny=8, tau_n=0.6, tau_r=0.8, bc_y=P.LBM_BC_GRADIENT), P.LBM_EINVAL),
+    (dict(nx=8, ny=8, tau_n=0.6, tau_r=0.8, scale=3.0), P.LBM_EINVAL),
+])
+def test_config_validation(kw, code):
+    with pytest.raises(P.LBMError) as e:
+        P.lbm_required_bytes(_cfg([P.make_instance(**kw)]))
+    assert e.value.code == code
+
+
+def test_bad_config_fields():
+    it = P.make_instance(8, 8, 0.6, 0.8)
+    for field, val in (("storage", 7), ("check_interval", 1), ("flags", 0x100)):
+        cfg = _cfg([it])
+        setattr(cfg, field, val)
+        with pytest.raises(P.LBMError) as e:
+            P.lbm_required_bytes(cfg)
+        assert e.value.code == P.LBM_EINVAL
+    cfg = _cfg([it])
+    cfg.n_instances = 0
+    with pytest.raises(P.LBMError):
+        P.lbm_required_bytes(cfg)
+
+
+def test_tau_r_infinite_and_small_accepted():
+    for tr in (math.inf, 0.2, 1e6):
+        assert P.lbm_required_bytes(_cfg([P.make_instance(16, 8, 0.6, tr)])) > 0
+
+
+def test_null_handle_calls_are_rejected():
+    assert P.library().lbm_step(None, 1) == P.LBM_EINVAL
+    assert P.library().lbm_steps_done(None) == -1
+    P.library().lbm_destroy(None)   # ignored

@@ -1,0 +1,198 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Tolerances: FP32 storage eps <= 1e-5 and 16-bit storage eps <= 5e-3 (relative
+L2 of temperature deviation and heat flux, see parity_util).  Results that
+cannot depend on the launch shape or schedule (same per-node arithmetic) are
+compared bit for bit.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import bloch, closed_forms as cf, ref
+from parity_util import eps, gpu_fields, log, oracle_fields
+from paper_2010_01847_amd import Lattice, LBMError, instance_from_case, LBM_ESTATE, LBM_EINVAL
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [
+    dict(vec=1, block_x=64, block_y=1, xcd_remap=0, nontemporal=0),
+    dict(vec=1, block_x=256, block_y=2, xcd_remap=1, nontemporal=0),
+    dict(vec=2, block_x=128, block_y=4, xcd_remap=1, nontemporal=1),
+    dict(vec=4, block_x=64, block_y=2, xcd_remap=0, nontemporal=0),
+    dict(vec=4, block_x=256, block_y=1, xcd_remap=1, nontemporal=0),
+    dict(vec=4, block_x=512, block_y=1, xcd_remap=1, nontemporal=1),
+]
+
+
+def _random_case(nx, ny, tau_n, tau_r, seed, **kw):
+    case = W.Case(f"rand_{nx}x{ny}", nx, ny, tau_n, tau_r, **kw)
+    T0 = W.random_field(nx, ny, 0.01, case.t0, seed) + (np.tile(case.t_ref(), (ny, 1)) - case.t0)
+    qx, qy = W.random_flux(nx, ny, 1e-3, seed + 1)
+    return case, T0, qx, qy
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_periodic_random_state(storage):
+    """Rough random start (T and q), periodic 97 x 80 (ragged against every tile
+    width), 57 steps."""
+    case, T0, qx, qy = _random_case(97, 80, 0.7, 3.0, 5)
+    ora = oracle_fields(case, 57, T0, qx, qy)
+    g = gpu_fields(case, 57, T0, qx, qy, storage=storage)
+    e_t, e_q = eps(case, g, ora)
+    log(f"periodic 97x80 {storage}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
+    tol = 1e-5 if storage == "f32" else (5e-3 if storage == "f16" else 5e-2)
+    assert e_t < tol and e_q < tol
+
+
+def test_launch_shapes_bitwise():
+    """Every launch shape runs the same per-node arithmetic: identical bits."""
+    case, T0, qx, qy = _random_case(131, 37, 0.55, 50.0, 9)
+    ref_out = None
+    for sh in SHAPES:
+        out = gpu_fields(case, 23, T0, qx, qy, shape=sh, check=5)
+        if ref_out is None:
+            ref_out = out
+            e = eps(case, out, oracle_fields(case, 23, T0, qx, qy))
+            log(f"shapes 131x37: eps={e}")
+            assert max(e) < 1e-5
+        else:
+            for a, b in zip(out, ref_out):
+                assert np.array_equal(a, b), sh
+
+
+@pytest.mark.parametrize("nx,ny", [(2, 2), (2, 5), (3, 2), (5, 3), (64, 2), (65, 3), (257, 4)])
+def test_minimal_and_ragged_grids(nx, ny):
+    case, T0, qx, qy = _random_case(nx, ny, 0.8, 2.0, nx * 100 + ny)
+    for sh in (SHAPES[0], SHAPES[4]):
+        e = eps(case, gpu_fields(case, 17, T0, qx, qy, shape=sh), oracle_fields(case, 17, T0, qx, qy))
+        assert max(e) < 1e-5, (nx, ny, sh, e)
+
+
+def test_isothermal_walls_128x64_5000_steps():
+    """Isothermal walls at T0 +/- 0.5 along x, periodic y, 5000 steps."""
+    case = W.wall_case()
+    ora = oracle_fields(case, case.steps)
+    for storage, tol in (("f32", 1e-5), ("f16", 5e-3)):
+        g = gpu_fields(case, case.steps, storage=storage)
+        e_t, e_q = eps(case, g, ora)
+        log(f"walls 128x64 {storage}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
+        assert e_t < tol and e_q < tol
+
+
+@pytest.mark.parametrize("bc_x,bc_y", [("periodic", "isothermal"), ("diffuse", "periodic"),
+                                       ("periodic", "diffuse"), ("gradient", "diffuse"),
+                                       ("gradient", "periodic"), ("isothermal", "periodic")])
+def test_boundaries_random_state(bc_x, bc_y):
+    """Every supported boundary pair from a rough random state, 200 steps."""
+    kw = dict(bc_x=bc_x, bc_y=bc_y, grad_x=2e-3 if bc_x == "gradient" else 0.0,
+              t_wall=(1.004, 0.997, 1.003, 0.995))
+    case, T0, qx, qy = _random_case(75, 46, 0.6, 7.0, 31, **kw)
+    ora = oracle_fields(case, 200, T0, qx, qy)
+    for sh in (SHAPES[0], SHAPES[3], SHAPES[5]):
+        e_t, e_q = eps(case, gpu_fields(case, 200, T0, qx, qy, shape=sh), ora)
+        log(f"{bc_x}/{bc_y} {sh['vec']}x{sh['block_x']}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
+        assert e_t < 1e-5 and e_q < 1e-5
+
+
+def test_channel_gradient_diffuse_3000_steps():
+    """Poiseuille channel (gradient seam, diffuse walls) from the ramp."""
+    case = W.poiseuille_case(0.6, 100.0, nx=130, ny=64)
+    ora = oracle_fields(case, 3000)
+    g = gpu_fields(case, 3000)
+    e_t, e_q = eps(case, g, ora)
+    log(f"channel 130x64: eps_T={e_t:.3e} eps_q={e_q:.3e}")
+    assert e_q < 1e-5 and e_t < 1e-5
+    # the solution stays uniform along x on the GPU too
+    assert np.array_equal(g[1], np.tile(g[1][:, :1], (1, case.nx)))
+
+
+def test_totals_and_invariants():
+    """FP64 totals: energy constant up to FP32 storage rounding; total heat flux
+    multiplied by rho per step (periodic)."""
+    case, T0, qx, qy = _random_case(160, 90, 0.7, 3.0, 41)
+    lat = Lattice([instance_from_case(case)], check_interval=-1)
+    lat.init(0, T0, qx, qy)
+    a = lat.totals(0)
+    o = ref.Oracle(case, T0, qx, qy)
+    assert np.allclose(a, o.totals(), rtol=1e-6, atol=1e-7)
+    lat.step(10)
+    b = lat.totals(0)
+    rho = cf.scheme_constants(case.tau_n, case.tau_r)["rho"]
+    log(f"totals {a} -> {b}, rho^10 = {rho ** 10:.6e}")
+    assert b[1] == pytest.approx(a[1] * rho ** 10, rel=1e-4)
+    assert b[2] == pytest.approx(a[2] * rho ** 10, rel=1e-4)
+    lat.step(500)
+    c = lat.totals(0)
+    assert abs(c[0] - a[0]) < 1e-6 * np.abs(T0 - 1).sum()
+    lat.close()
+
+
+def test_residual_and_check_totals():
+    """Check-step FP64 residual r = ||m^n - m^(n-1)|| / ||m^n|| equals the one
+    formed from oracle moments at n-1 and n."""
+    case = W.poiseuille_case(0.6, 100.0, nx=40, ny=50)
+    lat = Lattice([instance_from_case(case)], check_interval=25)
+    lat.init(0)
+    with pytest.raises(LBMError) as e:
+        lat.residual(0)
+    assert e.value.code == LBM_ESTATE
+    lat.step(100)
+    info = lat.last_check(0)
+    assert info["step"] == 100
+    o = ref.Oracle(case)
+    o.run(99)
+    m0 = o.moments()
+    o.run(1)
+    m1 = o.moments()
+    ramp = np.tile(case.t_ref(), (case.ny, 1))
+    v0 = [m0[0] - ramp, m0[1], m0[2]]
+    v1 = [m1[0] - ramp, m1[1], m1[2]]
+    r = math.sqrt(sum(np.sum((a - b) ** 2) for a, b in zip(v1, v0)) / sum(np.sum(a ** 2) for a in v1))
+    log(f"residual gpu {info['residual']:.6e} oracle {r:.6e}")
+    assert info["residual"] == pytest.approx(r, rel=1e-3)
+    tot = o.totals()
+    assert info["totals"][1] == pytest.approx(tot[1], rel=1e-5)
+    lat.close()
+
+
+def test_batched_schedules_bitwise_and_parity():
+    """Uneven instances in one handle: batched launch, one launch per instance
+    and the captured graph give identical bits, and each instance matches the
+    oracle."""
+    cases = W.knudsen_sweep(n_inst=6, seed=7, side_lo=20, side_hi=140, steps=0)
+    insts = [instance_from_case(c) for c in cases]
+    outs = {}
+    for sched in ("batched", "per_instance", "graph"):
+        lat = Lattice(insts, check_interval=10)
+        lat.set_schedule(sched)
+        for k in range(len(cases)):
+            lat.init(k)
+        lat.step(45)
+        outs[sched] = [lat.moments(k) for k in range(len(cases))]
+        lat.close()
+    for k, case in enumerate(cases):
+        for sched in ("per_instance", "graph"):
+            for a, b in zip(outs[sched][k], outs["batched"][k]):
+                assert np.array_equal(a, b), (sched, k)
+        e_t, e_q = eps(case, outs["batched"][k], oracle_fields(case, 45))
+        log(f"batched inst {k} {case.nx}x{case.ny} tr={case.tau_r:.3g}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
+        assert e_q < 1e-5 and e_t < 1e-5
+
+
+def test_abi_state_errors():
+    case = W.Case("e", 16, 8, 0.6, 0.8)
+    lat = Lattice([instance_from_case(case), instance_from_case(case)])
+    lat.init(0)
+    with pytest.raises(LBMError) as e:
+        lat.step(1)                 # instance 1 not initialised
+    assert e.value.code == LBM_ESTATE
+    with pytest.raises(LBMError) as e:
+        lat.moments(2)
+    assert e.value.code == LBM_EINVAL
+    lat.init(1)
+    lat.step(3)
+    assert lat.steps == 3
+    lat.close()
