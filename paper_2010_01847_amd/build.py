@@ -1,9 +1,10 @@
 """Build the HIP library ``libphonon_lbm.so`` for gfx950, in-tree.
 
 hipcc cross-compiles for gfx950 without a GPU present.  Every HIP source is
-compiled with packed-FP32 instructions disabled (``-packed-fp32-ops``); the
+compiled with packed-FP32 instructions disabled (``-packed-fp32-ops``; the
 host pass of hipcc warns that it does not know that feature, which is
-harmless.
+harmless) and with floating-point contraction off: the kernels spell out
+their fused multiply-adds, so all template instances compute identical bits.
 """
 from __future__ import annotations
 
@@ -22,6 +23,7 @@ ARCH = "gfx950"
 
 SOURCES = ["lbm_device.hip", "lbm_runtime.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
+          "-ffp-contract=off",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 

@@ -98,23 +98,26 @@ __device__ __forceinline__ void store_run(S* __restrict__ p, const float* v, int
 // in g-form.  E = sum g, j = sum c_i g (Eq. 53 and the sum of Eq. 54); the
 // equilibrium energy share is split so that 4 ea + 4 ed == E holds exactly
 // (E - 4 ea is exact by Sterbenz' lemma), and the flux share of Eq. 15 minus
-// the source of Eq. 16 is kappa * beta * (5 a_i / 3) c_i . j.
+// the source of Eq. 16 is kappa * beta * (5 a_i / 3) c_i . j.  The library is
+// built with contraction off and the fused multiply-adds are written out, so
+// every kernel instance (any nodes-per-thread, any launch shape) performs the
+// same operations and produces the same bits:
+//   g* = fma(kb_i, c_i . j, fma(1/tau, eq_i - g, g)).
 __device__ __forceinline__ void relax(float g[8], float inv_tau, float kb_a, float kb_d) {
     const float E = ((g[0] + g[2]) + (g[1] + g[3])) + ((g[4] + g[6]) + (g[5] + g[7]));
-    const float jx = (g[0] - g[2]) + (g[4] - g[6]) + (g[7] - g[5]);
-    const float jy = (g[1] - g[3]) + (g[4] - g[6]) + (g[5] - g[7]);
+    const float jx = ((g[0] - g[2]) + (g[4] - g[6])) + (g[7] - g[5]);
+    const float jy = ((g[1] - g[3]) + (g[4] - g[6])) + (g[5] - g[7]);
     const float ea = W_AXIS * E;
     const float ed = (E - 4.0f * ea) * 0.25f;
-    const float fx = kb_a * jx, fy = kb_a * jy;
-    const float fp = kb_d * (jx + jy), fm = kb_d * (jx - jy);
-    g[0] = g[0] + inv_tau * (ea - g[0]) + fx;
-    g[1] = g[1] + inv_tau * (ea - g[1]) + fy;
-    g[2] = g[2] + inv_tau * (ea - g[2]) - fx;
-    g[3] = g[3] + inv_tau * (ea - g[3]) - fy;
-    g[4] = g[4] + inv_tau * (ed - g[4]) + fp;
-    g[5] = g[5] + inv_tau * (ed - g[5]) - fm;
-    g[6] = g[6] + inv_tau * (ed - g[6]) - fp;
-    g[7] = g[7] + inv_tau * (ed - g[7]) + fm;
+    const float jp = jx + jy, jm = jx - jy;
+    g[0] = __builtin_fmaf(kb_a, jx, __builtin_fmaf(inv_tau, ea - g[0], g[0]));
+    g[1] = __builtin_fmaf(kb_a, jy, __builtin_fmaf(inv_tau, ea - g[1], g[1]));
+    g[2] = __builtin_fmaf(-kb_a, jx, __builtin_fmaf(inv_tau, ea - g[2], g[2]));
+    g[3] = __builtin_fmaf(-kb_a, jy, __builtin_fmaf(inv_tau, ea - g[3], g[3]));
+    g[4] = __builtin_fmaf(kb_d, jp, __builtin_fmaf(inv_tau, ed - g[4], g[4]));
+    g[5] = __builtin_fmaf(-kb_d, jm, __builtin_fmaf(inv_tau, ed - g[5], g[5]));
+    g[6] = __builtin_fmaf(-kb_d, jp, __builtin_fmaf(inv_tau, ed - g[6], g[6]));
+    g[7] = __builtin_fmaf(kb_d, jm, __builtin_fmaf(inv_tau, ed - g[7], g[7]));
 }
 
 // Boundary treatment after advection (Sec. 2.5) on one node, given its
