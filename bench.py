@@ -43,7 +43,21 @@ def _parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0)
     p.add_argument("--autotune", action="store_true")
+    p.add_argument("--copy-probe", action="store_true",
+                   help="also run a 1 GiB torch device copy 5 times (counter calibration)")
     return p.parse_args()
+
+
+def _copy_probe(torch):
+    """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE per dispatch
+    calibrate the same counters taken on the stream-collide kernel."""
+    n = (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
 
 
 def _run_gpu(args, storage, torch, P, W):
@@ -107,6 +121,8 @@ def main():
     import workloads as W
     import paper_2010_01847_amd as P
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        _copy_probe(torch)
     main_row = _run_gpu(args, args.storage, torch, P, W)
     rows = [main_row]
     for st in [s for s in args.rows.split(",") if s and s != args.storage]:

@@ -92,6 +92,16 @@ typedef struct {
     double scale;          /* storage scale s (a power of two), 0 = chosen at init */
 } lbm_instance;
 
+/* Device layout of the populations (both hold the same values; the choice
+ * only changes where they sit in memory).
+ *   PLANES : eight direction planes of ny rows, x contiguous, each row padded
+ *            to 256 bytes and each plane followed by a 4 KB pad.
+ *   CHUNKED: rows cut into 64-node segments; a segment stores its eight
+ *            direction runs back to back (2 KB in FP32), so the eight loads of
+ *            a wavefront read one contiguous region.
+ *   AUTO   : CHUNKED. */
+typedef enum { LBM_LAYOUT_AUTO = 0, LBM_LAYOUT_PLANES = 1, LBM_LAYOUT_CHUNKED = 2 } lbm_layout;
+
 typedef struct {
     int32_t n_instances;         /* >= 1 */
     int32_t storage;             /* lbm_storage */
@@ -100,6 +110,8 @@ typedef struct {
     int32_t flags;               /* LBM_FLAG_* */
     const lbm_instance* inst;    /* n_instances entries, copied at create */
     void* stream;                /* hipStream_t to enqueue on; NULL = null stream */
+    int32_t layout;              /* lbm_layout */
+    int32_t reserved;            /* must be 0 */
 } lbm_config;
 
 /* Do not allocate device memory at create: the caller provides it with lbm_bind

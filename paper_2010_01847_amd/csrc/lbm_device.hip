@@ -16,8 +16,11 @@
 // to each pulled population, which turns the seam of Eqs. 59-60 into plain
 // periodic wrap.
 //
-// Layout: per instance, eight planes (one per direction) of ny rows of
-// `pitch` elements, x contiguous; two such buffers (ping-pong).
+// Layout (see InstDesc): either eight direction planes of ny rows each, x
+// contiguous, or "chunked": each 64-node row segment stores its eight
+// direction runs back to back, so the eight loads of a wavefront fall in one
+// contiguous 2 KB (FP32) region instead of eight streams a plane apart.  Two
+// such buffers, ping-pong.
 #include "lbm_internal.h"
 
 #include <stdint.h>
@@ -35,8 +38,15 @@ template <> struct Cvt<float> {
 };
 template <> struct Cvt<_Float16> {
     static __device__ __forceinline__ float ld(_Float16 v) { return (float)v; }
-    // v_cvt_f16_f32 rounds to nearest even in the default mode; overflow -> Inf
-    static __device__ __forceinline__ _Float16 st(float f) { return (_Float16)f; }
+    // Round the FP32 value to FP16, nearest even (default mode); overflow -> Inf.
+    // The empty asm pins f as an FP32 register value: without it the backend
+    // may fold the producing FMA and this narrowing into one mixed-precision
+    // FMA (a single rounding straight to FP16) in some template instances and
+    // not in others, and results would then depend on the launch shape.
+    static __device__ __forceinline__ _Float16 st(float f) {
+        asm volatile("" : "+v"(f));
+        return (_Float16)f;
+    }
 };
 template <> struct Cvt<bf16_bits> {
     static __device__ __forceinline__ float ld(bf16_bits v) {
@@ -178,30 +188,42 @@ __device__ __forceinline__ constexpr int src_row(int i) {
     return (i == 1 || i == 4 || i == 5) ? 1 : ((i == 3 || i == 6 || i == 7) ? 2 : 0);
 }
 
-// V elements starting at x0 + dx (V-aligned x0, so the dx == 0 run is
-// V-element aligned).  FP32: one wide load, dword aligned.  16-bit storage:
-// the aligned run at x0 plus one aligned pair on the side the shift reaches
-// into, so no access is below dword alignment.  Caller guarantees
-// x0 + dx >= 0 and, for 16-bit dx = +1, that x0 + V + 1 < nx.
+// V elements starting at x0 + dx, given p0 = the address of x0 (V-aligned,
+// so the dx == 0 run is V-element aligned).  FP32: one wide load, dword
+// aligned.  16-bit storage: the aligned run at x0 plus one aligned pair on
+// the side the shift reaches into, so no access is below dword alignment.
+// Caller guarantees the touched elements are in range and in one chunk:
+// [x0 + dx, x0 + V - 1 + dx] (FP32), [x0 - 2, x0 + V - 1] or [x0, x0 + V + 1]
+// (16-bit, dx = -1 / +1).
 template <class S, int V>
-__device__ __forceinline__ void load_shifted(const S* __restrict__ row, int x0, int dx, float* out) {
+__device__ __forceinline__ void load_shifted(const S* __restrict__ p0, int dx, float* out) {
     if (dx == 0 || sizeof(S) == 4 || V == 1) {
-        load_run<S, V>(row + x0 + dx, out);
+        load_run<S, V>(p0 + dx, out);
         return;
     }
     float a[V], b[2];
-    load_run<S, V>(row + x0, a);
+    load_run<S, V>(p0, a);
     if (dx < 0) {
-        load_run<S, 2>(row + x0 - 2, b);
+        load_run<S, 2>(p0 - 2, b);
         out[0] = b[1];
 #pragma unroll
         for (int k = 1; k < V; ++k) out[k] = a[k - 1];
     } else {
-        load_run<S, 2>(row + x0 + V, b);
+        load_run<S, 2>(p0 + V, b);
 #pragma unroll
         for (int k = 0; k < V - 1; ++k) out[k] = a[k + 1];
         out[V - 1] = b[0];
     }
+}
+
+// Offset of column x within a row (layout-independent).
+__device__ __forceinline__ int64_t col_off(const InstDesc& d, int x) {
+    return (int64_t)(x >> d.cshift) * d.chunk + (x & d.cmask);
+}
+
+// Periodic wrap of a column index that is at most one period out of range.
+__device__ __forceinline__ int wrapx(int x, int nx) {
+    return x < 0 ? x + nx : (x >= nx ? x - nx : x);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -260,23 +282,26 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t sna
         S* __restrict__ dst = reinterpret_cast<S*>(a.dst) + d.off;
         const int ym = (y == 0) ? ny - 1 : y - 1;
         const int yp = (y == ny - 1) ? 0 : y + 1;
-        const int64_t rows[3] = {(int64_t)y * d.pitch, (int64_t)ym * d.pitch, (int64_t)yp * d.pitch};
+        const int64_t rows[3] = {(int64_t)y * d.row, (int64_t)ym * d.row, (int64_t)yp * d.row};
+        const int64_t xo = col_off(d, x0);
         const bool full = (x0 + V <= nx);
+        const int cs = d.cshift;
         float g[V][8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int dx = src_dx(i);
-            const S* row = src + (int64_t)i * d.plane + rows[src_row(i)];
+            const S* base = src + (int64_t)i * d.plane + rows[src_row(i)];
             float v[V];
-            const int hi = (sizeof(S) == 2 && V > 1 && dx > 0) ? x0 + V + 1 : x0 + V - 1 + dx;
-            if (full && x0 + dx >= 0 && hi < nx) {
-                load_shifted<S, V>(row, x0, dx, v);
+            // elements the fast path touches: contiguous only within a chunk
+            const int lo = (sizeof(S) == 2 && V > 1 && dx < 0) ? x0 - 2 : (dx < 0 ? x0 + dx : x0);
+            const int hi = (sizeof(S) == 2 && V > 1 && dx > 0) ? x0 + V + 1 : x0 + V - 1 + (dx > 0 ? dx : 0);
+            if (full && lo >= 0 && hi < nx && (lo >> cs) == (hi >> cs)) {
+                load_shifted<S, V>(base + xo, dx, v);
             } else {
 #pragma unroll
                 for (int k = 0; k < V; ++k) {
-                    int xs = x0 + k + dx;
-                    xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
-                    v[k] = (x0 + k < nx) ? Cvt<S>::ld(row[xs]) : 0.0f;
+                    const int xs = wrapx(x0 + k + dx, nx);
+                    v[k] = (x0 + k < nx) ? Cvt<S>::ld(base[col_off(d, xs)]) : 0.0f;
                 }
             }
 #pragma unroll
@@ -321,7 +346,8 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t sna
         }
 #pragma unroll
         for (int k = 0; k < V; ++k) relax(g[k], d.inv_tau, d.kb_axis, d.kb_diag);
-        S* out = dst + rows[0] + x0;
+        // a V-aligned run never crosses a 64-node chunk
+        S* out = dst + rows[0] + xo;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             float v[V];
@@ -335,6 +361,98 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t sna
                 for (int k = 0; k < V; ++k)
                     if (x0 + k < nx) p[k] = Cvt<S>::st(v[k]);
             }
+        }
+    }
+    if (MODE == kCheck) block_partials(acc, a.partials + (int64_t)t * kPartials);
+}
+
+// Wavefront-centric step for one node per lane.  Each wave owns one 64-node
+// row segment (chunk cx of row y), so the row, chunk and plane bases are
+// wave-uniform scalars and every load is a scalar base plus a 32-bit lane
+// offset; the boundary and ramp branches are taken per wave, not per lane.
+// Same per-node arithmetic as step_kernel, hence the same bits.
+template <class S, int MODE>
+__global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t snap_stride, int xcd,
+                                                          int nontemporal) {
+    const int b = blockIdx.x;
+    int t = b;
+    if (xcd) {
+        const int nb = a.ntiles, q = nb >> 3, r = nb & 7, k = b & 7, j = b >> 3;
+        t = k * q + (k < r ? k : r) + j;
+    }
+    t += a.tile_base;
+    const InstDesc& d = a.desc[a.tile_inst[t]];
+    const int local = t - d.tile_begin;
+    const int ty = local / d.tiles_x;
+    const int tx = local - ty * d.tiles_x;
+    const int wpx = blockDim.x >> 6;                                   // waves per block along x
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wy = __builtin_amdgcn_readfirstlane(threadIdx.y);
+    const int lane = threadIdx.x & 63;
+    const int cx = tx * wpx + wid;                                     // chunk index (uniform)
+    const int y = ty * blockDim.y + wy;                                // row (uniform)
+    const int nx = d.nx, ny = d.ny;
+    const int xc = cx * 64;                                            // first node of the chunk
+    const int x = xc + lane;
+    const bool wave_live = (y < ny) && (xc < nx);
+
+    double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (wave_live && x < nx) {
+        const int ym = (y == 0) ? ny - 1 : y - 1;
+        const int yp = (y == ny - 1) ? 0 : y + 1;
+        // wave-uniform row bases; per-lane 32-bit byte offsets within a row
+        // (a row of one instance is far below 4 GB), so each access is the
+        // scalar-base + vector-offset form of the global load/store
+        const char* src = reinterpret_cast<const char*>(a.src) + d.off * (int64_t)sizeof(S);
+        const int64_t rb = d.row * (int64_t)sizeof(S);
+        const char* rows[3] = {src + (int64_t)y * rb, src + (int64_t)ym * rb, src + (int64_t)yp * rb};
+        const int64_t pb = d.plane * (int64_t)sizeof(S);
+        const uint32_t es = sizeof(S);
+        // column offsets of x, x - 1 and x + 1 (periodic wrap at the row ends)
+        const uint32_t c0 = ((uint32_t)col_off(d, xc) + lane) * es;
+        const uint32_t cm_edge = (uint32_t)col_off(d, xc == 0 ? nx - 1 : xc - 1) * es;
+        const uint32_t cp_edge = (uint32_t)col_off(d, xc + 64 < nx ? xc + 64 : 0) * es;
+        const uint32_t cm = lane > 0 ? c0 - es : cm_edge;
+        const uint32_t cp = (lane < 63 && x + 1 < nx) ? c0 + es : (x + 1 == nx ? 0u : cp_edge);
+        float g[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int dx = src_dx(i);
+            const char* base = rows[src_row(i)] + i * pb;
+            g[i] = Cvt<S>::ld(*reinterpret_cast<const S*>(base + (dx < 0 ? cm : (dx > 0 ? cp : c0))));
+        }
+        if (d.bc_x == 3) ramp_term(g, d.grad_term);
+        const bool edge_y = (d.bc_y != 0) && (y == 0 || y == ny - 1);
+        const bool edge_x = (d.bc_x == 1 || d.bc_x == 2) && (xc == 0 || xc + 64 >= nx);
+        if (edge_y || edge_x) boundary(g, d, x, y);
+        if (MODE != kPlain) {
+            double E = 0.0;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) E += (double)g[i];
+            const double jx = ((double)g[0] - (double)g[2]) + ((double)g[4] - (double)g[6])
+                            + ((double)g[7] - (double)g[5]);
+            const double jy = ((double)g[1] - (double)g[3]) + ((double)g[4] - (double)g[6])
+                            + ((double)g[5] - (double)g[7]);
+            const double dT = d.s_cv * E, qx = d.s_beta * jx, qy = d.s_beta * jy;
+            const int64_t n = d.node_off + (int64_t)y * nx + x;
+            if (MODE == kSnap) {
+                a.snap[n] = dT;
+                a.snap[n + snap_stride] = qx;
+                a.snap[n + 2 * snap_stride] = qy;
+            } else {
+                const double p0 = a.snap[n], p1 = a.snap[n + snap_stride], p2 = a.snap[n + 2 * snap_stride];
+                acc[0] = d.s * E;
+                acc[1] = qx;
+                acc[2] = qy;
+                acc[3] = (dT - p0) * (dT - p0) + (qx - p1) * (qx - p1) + (qy - p2) * (qy - p2);
+                acc[4] = dT * dT + qx * qx + qy * qy;
+            }
+        }
+        relax(g, d.inv_tau, d.kb_axis, d.kb_diag);
+        char* out = reinterpret_cast<char*>(a.dst) + d.off * (int64_t)sizeof(S) + (int64_t)y * rb;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            store_run<S, 1>(reinterpret_cast<S*>(out + i * pb + c0), &g[i], nontemporal);
         }
     }
     if (MODE == kCheck) block_partials(acc, a.partials + (int64_t)t * kPartials);
@@ -354,9 +472,22 @@ static hipError_t launch_step_v(const Shape& sh, int mode, const StepArgs& a, in
 }
 
 template <class S>
+static hipError_t launch_wave(const Shape& sh, int mode, const StepArgs& a, int64_t snap_stride,
+                              hipStream_t st) {
+    dim3 grid(a.ntiles), block(sh.bx, sh.by);
+    if (mode == kPlain)
+        hipLaunchKernelGGL((wave_kernel<S, kPlain>), grid, block, 0, st, a, snap_stride, sh.xcd, sh.nt);
+    else if (mode == kSnap)
+        hipLaunchKernelGGL((wave_kernel<S, kSnap>), grid, block, 0, st, a, snap_stride, sh.xcd, sh.nt);
+    else
+        hipLaunchKernelGGL((wave_kernel<S, kCheck>), grid, block, 0, st, a, snap_stride, sh.xcd, sh.nt);
+    return hipGetLastError();
+}
+
+template <class S>
 static hipError_t launch_step_s(const Shape& sh, int mode, const StepArgs& a, int64_t ss, hipStream_t st) {
     switch (sh.vec) {
-        case 1: return launch_step_v<S, 1>(sh, mode, a, ss, st);
+        case 1: return launch_wave<S>(sh, mode, a, ss, st);
         case 2: return launch_step_v<S, 2>(sh, mode, a, ss, st);
         case 4: return launch_step_v<S, 4>(sh, mode, a, ss, st);
         default: return hipErrorInvalidValue;
@@ -396,16 +527,15 @@ __global__ __launch_bounds__(256) void moments_kernel(const InstDesc* __restrict
             const int rows[3] = {y, ym, yp};
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                int xs = x + src_dx(i);
-                xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
-                g[i] = Cvt<S>::ld(src[(int64_t)i * d.plane + (int64_t)rows[src_row(i)] * d.pitch + xs]);
+                const int xs = wrapx(x + src_dx(i), nx);
+                g[i] = Cvt<S>::ld(src[(int64_t)i * d.plane + (int64_t)rows[src_row(i)] * d.row + col_off(d, xs)]);
             }
             if (d.bc_x == 3) ramp_term(g, d.grad_term);
             boundary(g, d, x, y);
         } else {
 #pragma unroll
             for (int i = 0; i < 8; ++i)
-                g[i] = Cvt<S>::ld(src[(int64_t)i * d.plane + (int64_t)y * d.pitch + x]);
+                g[i] = Cvt<S>::ld(src[(int64_t)i * d.plane + (int64_t)y * d.row + col_off(d, x)]);
         }
         double E = 0.0;
 #pragma unroll
@@ -481,8 +611,8 @@ __global__ __launch_bounds__(256) void init_kernel(const InstDesc* __restrict__ 
     const bool wall = (d.bc_x == 1 && (x == 0 || x == d.nx - 1)) ||
                       (d.bc_y == 1 && (y == 0 || y == d.ny - 1));
     if (wall) boundary(g, d, x, y);
-    S* p = reinterpret_cast<S*>(pre) + d.off + (int64_t)y * d.pitch + x;
-    S* q = reinterpret_cast<S*>(post) + d.off + (int64_t)y * d.pitch + x;
+    S* p = reinterpret_cast<S*>(pre) + d.off + (int64_t)y * d.row + col_off(d, x);
+    S* q = reinterpret_cast<S*>(post) + d.off + (int64_t)y * d.row + col_off(d, x);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
         const S v = Cvt<S>::st(g[i]);

@@ -11,17 +11,29 @@ namespace plbm {
 constexpr int kMaxBlock = 512;     // threads per block upper bound (launch bounds)
 constexpr int kPartials = 5;       // per-tile FP64 partials: sum dE, sum qx, sum qy, |dm|^2, |m|^2
 
-// Per-instance descriptor, resident in device memory (one 128-byte record).
+// Per-instance descriptor, resident in device memory (one 192-byte record).
 // g-form: stored g_i = (e_i - omega_i C_V T_ref(x)) / s, T_ref = t0 - grad * x.
-struct alignas(128) InstDesc {
+//
+// Element address of direction i at node (x, y):
+//     off + y * row + (x >> cshift) * chunk + (x & cmask) + i * plane
+//   planes layout : row = pitch, plane = ny * pitch + pad, chunk = 0,
+//                   cshift = 31, cmask = 0x7fffffff   (x contiguous per plane)
+//   chunked layout: 64-node row segments, each holding its 8 direction runs
+//                   back to back: row = nchunks * 512, chunk = 512, plane = 64,
+//                   cshift = 6, cmask = 63
+struct alignas(64) InstDesc {
     int32_t nx, ny;
-    int32_t pitch;          // elements per row (>= nx, row bytes a multiple of 256)
     int32_t bc_x, bc_y;
     int32_t tiles_x;        // tiles along x for the current launch shape
     int32_t tile_begin;     // first global tile index of this instance
     int32_t ntiles;         // tiles of this instance
-    int64_t plane;          // elements between consecutive direction planes
-    int64_t off;            // element offset of plane 0 of this instance in a buffer
+    int32_t cshift;         // log2 of the chunk width (31: no chunking)
+    int32_t cmask;          // chunk width - 1
+    int32_t layout;         // 1 = planes, 2 = chunked
+    int64_t row;            // elements between rows
+    int64_t plane;          // elements between direction runs
+    int64_t chunk;          // elements between 64-node chunks (0: planes layout)
+    int64_t off;            // element offset of this instance in a buffer
     int64_t node_off;       // offset of this instance in node-indexed arrays (snapshot)
     float inv_tau;          // 1 / tau
     float kb_axis;          // kappa * beta / 3  (flux term of axis directions)
@@ -33,7 +45,7 @@ struct alignas(128) InstDesc {
     double s;               // storage scale
     double cv;
 };
-static_assert(sizeof(InstDesc) == 128, "descriptor layout");
+static_assert(sizeof(InstDesc) == 192, "descriptor layout");
 
 // Launch shape chosen by the runtime (or the autotuner).
 struct Shape {

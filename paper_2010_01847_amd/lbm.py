@@ -27,6 +27,8 @@ LBM_F32, LBM_F16, LBM_BF16 = 0, 1, 2
 LBM_BC_PERIODIC, LBM_BC_ISOTHERMAL, LBM_BC_DIFFUSE, LBM_BC_GRADIENT = 0, 1, 2, 3
 LBM_SCHED_BATCHED, LBM_SCHED_PER_INSTANCE, LBM_SCHED_GRAPH = 0, 1, 2
 LBM_FLAG_EXTERNAL_MEMORY = 0x1
+LBM_LAYOUT_AUTO, LBM_LAYOUT_PLANES, LBM_LAYOUT_CHUNKED = 0, 1, 2
+LAYOUT = {"auto": LBM_LAYOUT_AUTO, "planes": LBM_LAYOUT_PLANES, "chunked": LBM_LAYOUT_CHUNKED}
 
 STORAGE = {"f32": LBM_F32, "f16": LBM_F16, "bf16": LBM_BF16}
 BC = {"periodic": LBM_BC_PERIODIC, "isothermal": LBM_BC_ISOTHERMAL, "diffuse": LBM_BC_DIFFUSE,
@@ -46,7 +48,8 @@ class lbm_instance(ctypes.Structure):
 class lbm_config(ctypes.Structure):
     _fields_ = [("n_instances", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("check_interval", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("inst", ctypes.POINTER(lbm_instance)), ("stream", ctypes.c_void_p)]
+                ("inst", ctypes.POINTER(lbm_instance)), ("stream", ctypes.c_void_p),
+                ("layout", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class lbm_check_info(ctypes.Structure):
@@ -256,7 +259,7 @@ class Lattice:
     """One handle over one or more instances, memory from torch, stream from torch."""
 
     def __init__(self, instances: Iterable[lbm_instance], storage="f32", check_interval: int = 0,
-                 device=None, stream=None):
+                 device=None, stream=None, layout="auto"):
         import torch
         self._torch = torch
         self.instances: List[lbm_instance] = list(instances)
@@ -271,6 +274,7 @@ class Lattice:
         cfg.flags = LBM_FLAG_EXTERNAL_MEMORY
         cfg.inst = ctypes.cast(arr, ctypes.POINTER(lbm_instance))
         cfg.stream = ctypes.c_void_p(self.stream.cuda_stream)
+        cfg.layout = LAYOUT[layout] if isinstance(layout, str) else int(layout)
         self.cfg = cfg
         self.nbytes = lbm_required_bytes(cfg)
         with torch.cuda.device(self.device):

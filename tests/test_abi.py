@@ -29,12 +29,29 @@ def test_header_symbols_exported():
     assert set(names) == bound, set(names) ^ bound
 
 
-def test_struct_sizes_match_header():
-    # lbm_instance: 4 int32 + 9 doubles + 4-double array = 16 + 72 + 32 -> 120
-    assert ctypes.sizeof(P.lbm_instance) == 4 * 4 + 5 * 8 + 4 * 8 + 8
-    assert ctypes.sizeof(P.lbm_config) == 4 * 4 + 8 + 8
-    assert ctypes.sizeof(P.lbm_check_info) == 8 + 8 + 24
-    assert ctypes.sizeof(P.lbm_launch_shape) == 20
+def test_struct_layouts_match_header(tmp_path):
+    """Sizes and field offsets of the ctypes structs equal those a C compiler
+    gives the header's structs."""
+    import subprocess
+    structs = {"lbm_instance": P.lbm_instance, "lbm_config": P.lbm_config,
+               "lbm_check_info": P.lbm_check_info, "lbm_launch_shape": P.lbm_launch_shape}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "phonon_lbm.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{name}.{fname} %zu\\n", offsetof({name}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert int(got[name]) == ctypes.sizeof(cls), name
+        for fname, _ in cls._fields_:
+            assert int(got[f"{name}.{fname}"]) == getattr(cls, fname).offset, (name, fname)
 
 
 def _cfg(insts, storage=P.LBM_F32, check=0, flags=P.LBM_FLAG_EXTERNAL_MEMORY):

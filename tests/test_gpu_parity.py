@@ -48,20 +48,22 @@ def test_periodic_random_state(storage):
     assert e_t < tol and e_q < tol
 
 
-def test_launch_shapes_bitwise():
-    """Every launch shape runs the same per-node arithmetic: identical bits."""
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_launch_shapes_and_layouts_bitwise(storage):
+    """Every launch shape and both memory layouts run the same per-node
+    arithmetic: identical bits."""
     case, T0, qx, qy = _random_case(131, 37, 0.55, 50.0, 9)
     ref_out = None
-    for sh in SHAPES:
-        out = gpu_fields(case, 23, T0, qx, qy, shape=sh, check=5)
+    for sh, layout in [(s, "chunked") for s in SHAPES] + [(s, "planes") for s in SHAPES]:
+        out = gpu_fields(case, 23, T0, qx, qy, shape=sh, check=5, storage=storage, layout=layout)
         if ref_out is None:
             ref_out = out
             e = eps(case, out, oracle_fields(case, 23, T0, qx, qy))
-            log(f"shapes 131x37: eps={e}")
-            assert max(e) < 1e-5
+            log(f"shapes 131x37 {storage}: eps={e}")
+            assert max(e) < (1e-5 if storage == "f32" else 5e-3)
         else:
             for a, b in zip(out, ref_out):
-                assert np.array_equal(a, b), sh
+                assert np.array_equal(a, b), (sh, layout)
 
 
 @pytest.mark.parametrize("nx,ny", [(2, 2), (2, 5), (3, 2), (5, 3), (64, 2), (65, 3), (257, 4)])
@@ -72,8 +74,8 @@ def test_minimal_and_ragged_grids(nx, ny):
     noise floor (rho = 0.6 per step here)."""
     case, T0, qx, qy = _random_case(nx, ny, 0.8, 2.0, nx * 100 + ny)
     ora = oracle_fields(case, 5, T0, qx, qy)
-    for sh in (SHAPES[0], SHAPES[4]):
-        e = eps(case, gpu_fields(case, 5, T0, qx, qy, shape=sh), ora)
+    for sh, layout in ((SHAPES[0], "planes"), (SHAPES[4], "chunked"), (SHAPES[2], "chunked")):
+        e = eps(case, gpu_fields(case, 5, T0, qx, qy, shape=sh, layout=layout), ora)
         assert max(e) < 1e-5, (nx, ny, sh, e)
 
 
@@ -105,8 +107,8 @@ def test_boundaries_random_state(bc_x, bc_y):
               t_wall=(1.004, 0.997, 1.003, 0.995))
     case, T0, qx, qy = _random_case(75, 46, 0.6, 7.0, 31, **kw)
     ora = oracle_fields(case, 40, T0, qx, qy)
-    for sh in (SHAPES[0], SHAPES[3], SHAPES[5]):
-        e_t, e_q = eps(case, gpu_fields(case, 40, T0, qx, qy, shape=sh), ora)
+    for sh, layout in ((SHAPES[0], "chunked"), (SHAPES[3], "planes"), (SHAPES[5], "chunked")):
+        e_t, e_q = eps(case, gpu_fields(case, 40, T0, qx, qy, shape=sh, layout=layout), ora)
         log(f"{bc_x}/{bc_y} {sh['vec']}x{sh['block_x']}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
         assert e_t < 1e-5 and e_q < 1e-5
 
