@@ -29,13 +29,35 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 BYTES_PER_NODE = {"f32": 64, "f16": 32, "bf16": 32}   # 8 reads + 8 writes per node
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2010_01847_amd", "csrc", "lbm_device.hip")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def _measured_traffic(storage: str, n: int):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy), or
+    None when no summary covers this workload or the kernel source changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(PROFILES, f"stream_collide_{storage}_second_sound_{n}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("|", "#")):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    if fields.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
+        return None
+    return int(float(fields["traffic_bytes_per_launch"]))
 
 
 def _parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=400)
-    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--steps", type=int, default=1000)
+    p.add_argument("--warmup", type=int, default=50)
     p.add_argument("--n", type=int, default=8192, help="lattice side")
     p.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     p.add_argument("--rows", default="f16,bf16", help="extra storage rows ('' for none)")
@@ -85,7 +107,8 @@ def _run_gpu(args, storage, torch, P, W):
     step_s = ms / 1e3 / args.steps
     mlups = nodes / step_s / 1e6
     gbs = BYTES_PER_NODE[storage] * nodes / step_s / 1e9
-    info = lat.last_check(0) if args.check_interval > 0 else None
+    done = args.warmup + args.steps
+    info = lat.last_check(0) if 0 < args.check_interval <= done else None
     shape = lat.launch_shape()
     lat.close()
     return dict(storage=storage, mlups=mlups, ms_per_step=ms / args.steps, gbs=gbs,
@@ -146,7 +169,10 @@ def main():
                    "tau_n": 0.55, "tau_r": 50.0, "storage": args.storage,
                    "check_interval": args.check_interval, "launch_shape": main_row["shape"]},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None},
+                     "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": _measured_traffic(args.storage, args.n),
+                     "kernel": "wave_kernel (fused pull-advection + boundary + moments + relaxation)",
+                     "bytes_per_launch": BYTES_PER_NODE[args.storage] * args.n * args.n},
         "cpu_baseline": cpu,
         "rows": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items() if k != "tune"}
                  for r in rows],
