@@ -1,0 +1,181 @@
+"""The five workloads at their full sizes on the HIP path, checked against the
+FP64 oracle.
+
+* second sound 8192^2 and smooth modes 16384^2: exact periodic solutions
+  (separable spectral route / 16-mode solution), compared on sampled rows;
+* Poiseuille channels 1024 x 256: run to steady state on the GPU and against
+  the oracle's FP64 steady state (the solution is uniform along x, so the
+  oracle runs 4 columns);
+* Knudsen sweep: 256 uneven channel instances in one batched handle, a subset
+  stepped by the oracle, and the batched / per-instance / graph schedules.
+
+Tolerances: FP32 storage 1e-5, FP16 5e-3 (relative L2 of the temperature
+deviation and of the heat flux); BF16 is reported, with a sanity bound only.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import bloch, closed_forms as cf, ref
+from parity_util import eps, log, oracle_fields
+from paper_2010_01847_amd import Lattice, instance_from_case
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "f16": 5e-3, "bf16": 0.1}
+
+
+def _rel(a, b, base):
+    den = math.sqrt(float(np.sum(base ** 2)))
+    return math.sqrt(float(np.sum((a - b) ** 2))) / den if den > 0 else 0.0
+
+
+def _run_rows(case, storage, scale, steps, rows, T0, check=100):
+    lat = Lattice([instance_from_case(case, scale)], storage=storage, check_interval=check)
+    lat.init(0, T0)
+    lat.step(steps)
+    dT, qx, qy = lat.moments_device(0)
+    idx = torch.as_tensor(np.asarray(rows), device=dT.device)
+    out = [t.index_select(0, idx).cpu().numpy() for t in (dT, qx, qy)]
+    info = lat.last_check(0) if check > 0 and steps >= check else None
+    del dT, qx, qy
+    lat.close()
+    torch.cuda.empty_cache()
+    return out, info
+
+
+# ---------------------------------------------------------------- second sound
+
+@pytest.fixture(scope="module")
+def second_sound_exact():
+    case = W.second_sound_case()
+    a = case.init_args
+    x = np.arange(case.nx, dtype=np.float64)
+    f = np.exp(-(x - a["cx"]) ** 2 / (2 * a["sigma"] ** 2))
+    sol = bloch.SeparableSolution(f, f, a["amp"], case.steps, case.tau_n, case.tau_r)
+    rows = list(range(0, case.ny, 32)) + [a["cy"] + k for k in (-1, 1, 2)]
+    return case, rows, sol.rows(rows)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_second_sound_8192(second_sound_exact, storage):
+    """8192^2 periodic, Gaussian pulse, tau_N = 0.55, tau_R = 50, 4000 steps."""
+    case, rows, (To, qxo, qyo) = second_sound_exact
+    scale = 2.0 ** -20 if storage == "f16" else 0.0
+    T0 = W.initial_field(case)
+    (dT, qx, qy), info = _run_rows(case, storage, scale, case.steps, rows, T0)
+    e_t = _rel(dT, To - 1.0, To - 1.0)
+    e_q = math.sqrt(float(np.sum((qx - qxo) ** 2 + (qy - qyo) ** 2))) / math.sqrt(float(np.sum(qxo ** 2 + qyo ** 2)))
+    exact_total = 0.01 * 2 * math.pi * 20.0 ** 2            # sum of the pulse over the plane
+    log(f"second sound 8192^2 {storage}: eps_T={e_t:.3e} eps_q={e_q:.3e} "
+        f"total E={info['totals'][0]:.8f} (exact {exact_total:.8f}) r={info['residual']:.3e}")
+    assert e_t < TOL[storage] and e_q < TOL[storage]
+    if storage == "f32":
+        assert info["totals"][0] == pytest.approx(exact_total, rel=1e-6)
+
+
+# ---------------------------------------------------------------- smooth modes
+
+@pytest.mark.parametrize("storage", ["f16", "f32", "bf16"])
+def test_smooth_modes_16384(storage):
+    """16384^2 periodic, 16 seeded Fourier modes (total amplitude 1e-3),
+    tau_N = 0.6, tau_R = 5, 1000 steps; FP16 with scale 2^-22."""
+    case = W.smooth_modes_case()
+    modes = case.init_args["modes"]
+    rows = list(range(0, case.ny, 64))
+    sol = bloch.ModeSolution(modes, case.nx, case.ny, case.steps, case.tau_n, case.tau_r)
+    To, qxo, qyo = sol.rows(rows)
+    T0 = W.modes_field_torch(modes, case.nx, case.ny, case.t0, device="cuda")
+    scale = 2.0 ** -22 if storage == "f16" else 0.0
+    (dT, qx, qy), info = _run_rows(case, storage, scale, case.steps, rows, T0)
+    del T0
+    torch.cuda.empty_cache()
+    e_t = _rel(dT, To - 1.0, To - 1.0)
+    e_q = math.sqrt(float(np.sum((qx - qxo) ** 2 + (qy - qyo) ** 2))) / math.sqrt(float(np.sum(qxo ** 2 + qyo ** 2)))
+    log(f"smooth modes 16384^2 {storage}: eps_T={e_t:.3e} eps_q={e_q:.3e} total E={info['totals'][0]:.3e}")
+    assert e_t < TOL[storage] and e_q < TOL[storage]
+
+
+# ---------------------------------------------------------------- Poiseuille
+
+def _oracle_steady(case):
+    o = ref.Oracle(case)
+    prev = None
+    while o.steps < 200000:
+        o.run(1000)
+        _, qx, _ = o.moments()
+        if prev is not None and np.abs(qx - prev).max() <= 1e-12 * np.abs(qx).max():
+            break
+        prev = qx.copy()
+    return o.moments(), o.steps
+
+
+@pytest.mark.parametrize("ratio", W.POISEUILLE_RATIOS)
+@pytest.mark.parametrize("tau_n", W.POISEUILLE_TAU_N)
+def test_poiseuille_steady_1024x256(tau_n, ratio):
+    """Channel 1024 x 256 (gradient seam G = 1e-3, diffuse walls) run to steady
+    state on the GPU (check every 1000 steps until r < 1e-10 or r = 0, the
+    rounded map's fixed point) against the oracle's FP64 steady state."""
+    case = W.poiseuille_case(tau_n, ratio)
+    small = W.poiseuille_case(tau_n, ratio, nx=4)
+    (To, qxo, qyo), osteps = _oracle_steady(small)
+    lat = Lattice([instance_from_case(case)], check_interval=1000)
+    lat.set_schedule("graph")
+    lat.init(0)
+    r = 1.0
+    while lat.steps < 200000:
+        lat.step(1000)
+        r = lat.residual(0)
+        if r < 1e-10:
+            break
+    dT, qx, qy = lat.moments(0)
+    steps = lat.steps
+    lat.close()
+    # the GPU solution is exactly uniform along x
+    assert np.array_equal(qx, np.tile(qx[:, :1], (1, case.nx)))
+    q_o = qxo[:, 0]
+    e_q = float(np.linalg.norm(qx[:, 0] - q_o) / np.linalg.norm(q_o))
+    e_qy = float(np.abs(qy[:, 0] - qyo[:, 0]).max() / np.abs(q_o).max())
+    d = case.ny - 1
+    kn_c = cf.knudsen(cf.scheme_constants(tau_n, case.tau_r)["tau_c"], d)
+    kn_r = cf.knudsen(case.tau_r, d)
+    Q = qx[:, 0] / cf.poiseuille_q_scale(case.tau_r, case.grad_x)
+    cond = float(Q.mean())
+    log(f"poiseuille tn={tau_n} ratio={ratio:g}: gpu steps={steps} r={r:.2e} oracle steps={osteps} "
+        f"eps_q={e_q:.3e} eps_qy={e_qy:.1e} lambda_eff/lambda={cond:.5f} (Eq.69 "
+        f"{cf.poiseuille_conductivity_eq69(kn_c, kn_r):.5f})")
+    assert e_q < 1e-5 and e_qy < 1e-5
+    assert cond == pytest.approx(cf.poiseuille_conductivity_eq69(kn_c, kn_r), rel=0.01)
+
+
+# ---------------------------------------------------------------- Knudsen sweep
+
+def test_knudsen_sweep_256_instances():
+    """256 uneven channel instances in one handle, 2000 steps batched; six of
+    them against the oracle; the three schedules agree bit for bit."""
+    cases = W.knudsen_sweep()
+    insts = [instance_from_case(c) for c in cases]
+    steps = 2000
+    outs = {}
+    for sched in ("graph", "batched", "per_instance"):
+        lat = Lattice(insts, check_interval=100)
+        lat.set_schedule(sched)
+        for k in range(len(cases)):
+            lat.init(k)
+        lat.step(steps if sched == "graph" else 200)
+        outs[sched] = [lat.moments(k) for k in (0, 1, 2, 3, 4, 5, 255)]
+        lat.close()
+    for k, out in zip((0, 1, 2, 3, 4, 5, 255), outs["batched"]):
+        for a, b in zip(out, outs["per_instance"][(0, 1, 2, 3, 4, 5, 255).index(k)]):
+            assert np.array_equal(a, b), k
+    worst = 0.0
+    for j, k in enumerate((0, 1, 2, 3, 4, 5)):
+        case = cases[k]
+        e_t, e_q = eps(case, outs["graph"][j], oracle_fields(case, steps))
+        worst = max(worst, e_t, e_q)
+        log(f"sweep instance {k} {case.nx}x{case.ny} tau_n={case.tau_n:.3f} tau_r={case.tau_r:.3g}: "
+            f"eps_T={e_t:.3e} eps_q={e_q:.3e}")
+    assert worst < 1e-5

@@ -237,3 +237,41 @@ def test_tau_max_values(golden_dir):
     miss = [abs(round(cf.tau_from_knudsen(c["nodes"], cf.overall_knudsen(c["kn_n"], c["kn_r"])), 4)
                 - c["tau_max"]) > 1e-9 for c in g["cases"]]
     assert any(miss)
+
+
+def test_separable_route_equals_full_fft_and_stepper():
+    """The separable spectral route (used at 8192^2) gives the same rows as the
+    full 2D FFT route and as the C stepper on a small lattice."""
+    nx, ny, n = 96, 80, 150
+    fx = np.exp(-(np.arange(nx) - 40) ** 2 / (2 * 6.0 ** 2))
+    fy = np.exp(-(np.arange(ny) - 47) ** 2 / (2 * 5.0 ** 2))
+    T0 = 1.0 + 0.01 * np.outer(fy, fx)
+    S = bloch.SeparableSolution(fx, fy, 0.01, n, 0.55, 50.0)
+    rows = [0, 13, 47, 79]
+    Ts, qxs, qys = S.rows(rows)
+    Tf, qxf, qyf = bloch.evolve_temperature_field(T0, n, 0.55, 50.0)
+    assert np.abs(Ts - Tf[rows]).max() < 1e-15
+    assert np.abs(qxs - qxf[rows]).max() < 1e-15 and np.abs(qys - qyf[rows]).max() < 1e-15
+    o = ref.Oracle(W.Case("s", nx, ny, 0.55, 50.0), T0)
+    o.run(n)
+    To, qxo, qyo = o.moments()
+    assert np.abs(Ts - To[rows]).max() < 1e-14
+    assert np.abs(qxs - qxo[rows]).max() < 1e-14
+
+
+def test_mode_solution_equals_stepper():
+    """The few-mode exact solution (used at 16384^2) equals the C stepper on a
+    small lattice with the same kind of seeded modes."""
+    nx, ny, n = 64, 48, 90
+    modes = W.draw_modes(n_modes=5, kmax=3, amp_total=1e-3, seed=3)
+    T0 = W.modes_field(modes, nx, ny, 1.0)
+    sol = bloch.ModeSolution(modes, nx, ny, n, 0.6, 5.0)
+    o = ref.Oracle(W.Case("m", nx, ny, 0.6, 5.0), T0)
+    o.run(n)
+    To, qxo, qyo = o.moments()
+    Tm, qxm, qym = sol.rows(range(ny))
+    # the stepper carries T ~ 1 in absolute FP64: a few ulps of 1.0 of rounding
+    assert np.abs(Tm - To).max() < 2e-14 and np.abs(qxm - qxo).max() < 1e-15
+    ys, xs = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    Ta, _, qya = sol.at(xs, ys)
+    assert np.abs(Ta - To).max() < 2e-14 and np.abs(qya - qyo).max() < 1e-15
