@@ -111,12 +111,25 @@ typedef struct {
     const lbm_instance* inst;    /* n_instances entries, copied at create */
     void* stream;                /* hipStream_t to enqueue on; NULL = null stream */
     int32_t layout;              /* lbm_layout */
-    int32_t reserved;            /* must be 0 */
+    uint32_t seed;               /* stream of the stochastic-rounding bits (any value) */
 } lbm_config;
 
 /* Do not allocate device memory at create: the caller provides it with lbm_bind
  * (for example a torch tensor), sized by lbm_required_bytes. */
 #define LBM_FLAG_EXTERNAL_MEMORY 0x1
+
+/* Round the stored populations stochastically instead of to nearest.  With
+ * round-to-nearest a very smooth field can freeze: once the per-step change
+ * of a population is below half a unit in the last place of its stored value,
+ * every node rounds the same way (the rounded map reaches a spurious fixed
+ * point).  Stochastic rounding picks the upper or lower neighbour with
+ * probability proportional to distance, so the stored state is unbiased.  The
+ * random bits are a counter-based hash of (global node, step, direction, seed):
+ * runs are deterministic and do not depend on launch shape or schedule.
+ * FP32: the update is added exactly (two-sum) and the result rounded to one of
+ * its two FP32 neighbours; FP16/BF16: random bits below the kept mantissa are
+ * added before truncation.  Requires one node per lane (launch shape vec 1). */
+#define LBM_FLAG_STOCHASTIC_ROUNDING 0x2
 
 /* Version string of the library. */
 const char* lbm_version(void);

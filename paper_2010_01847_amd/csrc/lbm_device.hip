@@ -130,6 +130,90 @@ __device__ __forceinline__ void relax(float g[8], float inv_tau, float kb_a, flo
     g[7] = __builtin_fmaf(kb_d, jm, __builtin_fmaf(inv_tau, ed - g[7], g[7]));
 }
 
+// ------------------------------------------------------------------ stochastic rounding
+//
+// Round-to-nearest storage stalls on very smooth fields: when the per-step
+// change of a population is below half a unit in the last place of the stored
+// value, every node rounds the same way and the stored map freezes (a bias,
+// not noise).  Stochastic rounding moves to the upper or lower neighbour with
+// probabilities proportional to the distance, which is unbiased.  The random
+// bits come from a counter-based hash of (global node, step, direction), so a
+// run is deterministic and independent of the launch shape and schedule.
+
+// Integer finaliser "lowbias32" (C. Wellons, hash-prospector): a bijective
+// mix of 32 bits with low bias, two multiplies.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+// 16 random bits for direction i from four 32-bit words.
+__device__ __forceinline__ uint32_t bits16(const uint32_t r[4], int i) {
+    return (r[i >> 1] >> ((i & 1) * 16)) & 0xffffu;
+}
+
+// FP32 storage: the exact sum a + b (TwoSum, contraction off) rounded to one
+// of its two FP32 neighbours; the farther one is chosen with probability
+// |error| / gap, resolved with 16 random bits.
+__device__ __forceinline__ float sr_add_f32(float a, float b, uint32_t r16) {
+    const float s = a + b;
+    const float bb = s - a;
+    const float err = (a - (s - bb)) + (b - bb);
+    if (err == 0.0f || s == 0.0f) return s;
+    const uint32_t u = __float_as_uint(s);
+    const uint32_t un = ((err > 0.0f) == (s > 0.0f)) ? u + 1u : u - 1u;   // neighbour toward a + b
+    const float nb = __uint_as_float(un);
+    const float gap = fabsf(nb - s);
+    const float p = ((float)r16 + 0.5f) * (1.0f / 65536.0f);
+    return fabsf(err) > gap * p ? nb : s;
+}
+
+// 16-bit storage: add random bits below the kept mantissa and truncate.  FP16
+// keeps 10 of FP32's 23 mantissa bits (exact for values in FP16's normal
+// range; the converter then rounds the already short value), BF16 keeps 7.
+__device__ __forceinline__ _Float16 sr_f16(float v, uint32_t r16) {
+    uint32_t u = __float_as_uint(v);
+    u = (u + (r16 >> 3)) & ~0x1fffu;
+    float t = __uint_as_float(u);
+    asm volatile("" : "+v"(t));
+    return (_Float16)t;
+}
+__device__ __forceinline__ bf16_bits sr_bf16(float v, uint32_t r16) {
+    bf16_bits o;
+    const uint32_t u = __float_as_uint(v);
+    if ((u & 0x7f800000u) == 0x7f800000u) return Cvt<bf16_bits>::st(v);   // Inf/NaN unchanged
+    o.b = (uint16_t)((u + r16) >> 16);
+    return o;
+}
+
+// Relaxation with stochastic rounding of the stored result.  For FP32 the
+// update is formed first and added with sr_add_f32; for 16-bit storage the
+// round-to-nearest FP32 result of relax() is narrowed stochastically.
+template <class S> struct SRStore;
+template <> struct SRStore<float> {
+    static __device__ __forceinline__ void relax_store(float g[8], float it, float kb_a, float kb_d,
+                                                       const uint32_t r[4], float out[8]) {
+        const float E = ((g[0] + g[2]) + (g[1] + g[3])) + ((g[4] + g[6]) + (g[5] + g[7]));
+        const float jx = ((g[0] - g[2]) + (g[4] - g[6])) + (g[7] - g[5]);
+        const float jy = ((g[1] - g[3]) + (g[4] - g[6])) + (g[5] - g[7]);
+        const float ea = W_AXIS * E;
+        const float ed = (E - 4.0f * ea) * 0.25f;
+        const float jp = jx + jy, jm = jx - jy;
+        const float fl[8] = {kb_a * jx, kb_a * jy, -kb_a * jx, -kb_a * jy,
+                             kb_d * jp, -kb_d * jm, -kb_d * jp, kb_d * jm};
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float eq = i < 4 ? ea : ed;
+            const float delta = __builtin_fmaf(it, eq - g[i], fl[i]);
+            out[i] = sr_add_f32(g[i], delta, bits16(r, i));
+        }
+    }
+};
+
 // Boundary treatment after advection (Sec. 2.5) on one node, given its
 // position.  Directions 0..7 are the paper's 1..8.  Written with selects only:
 // every write has a fixed index, so the eight values stay in registers.
@@ -267,6 +351,7 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t sna
         t = k * q + (k < r ? k : r) + j;
     }
     t += a.tile_base;
+    if (t == 0 && threadIdx.x == 0 && threadIdx.y == 0) a.ctr_out[0] = a.ctr_in[0] + 1u;
     const InstDesc& d = a.desc[a.tile_inst[t]];
     const int local = t - d.tile_begin;
     const int ty = local / d.tiles_x;
@@ -371,7 +456,7 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t sna
 // wave-uniform scalars and every load is a scalar base plus a 32-bit lane
 // offset; the boundary and ramp branches are taken per wave, not per lane.
 // Same per-node arithmetic as step_kernel, hence the same bits.
-template <class S, int MODE>
+template <class S, int MODE, int SR>
 __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t snap_stride, int xcd,
                                                           int nontemporal) {
     const int b = blockIdx.x;
@@ -395,6 +480,10 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
     const int xc = cx * 64;                                            // first node of the chunk
     const int x = xc + lane;
     const bool wave_live = (y < ny) && (xc < nx);
+    // step counter: every block reads the count before this step; the block of
+    // global tile 0 publishes count + 1 in the other slot for the next step
+    const uint32_t step = a.ctr_in[0];
+    if (t == 0 && threadIdx.x == 0 && threadIdx.y == 0) a.ctr_out[0] = step + 1u;
 
     double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (wave_live && x < nx) {
@@ -448,11 +537,40 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
                 acc[4] = dT * dT + qx * qx + qy * qy;
             }
         }
-        relax(g, d.inv_tau, d.kb_axis, d.kb_diag);
         char* out = reinterpret_cast<char*>(a.dst) + d.off * (int64_t)sizeof(S) + (int64_t)y * rb;
+        if (SR) {
+            // four 32-bit random words per node and step: hash of the node index
+            // keyed by a hash of (step, word, seed)
+            const uint32_t node = (uint32_t)(d.node_off + (int64_t)y * nx + x);
+            uint32_t r[4];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            store_run<S, 1>(reinterpret_cast<S*>(out + i * pb + c0), &g[i], nontemporal);
+            for (int k = 0; k < 4; ++k) r[k] = mix32(node ^ mix32(step * 4u + (uint32_t)k + a.seed * 0x9e3779b9u));
+            if (sizeof(S) == 4) {
+                float o[8];
+                SRStore<float>::relax_store(g, d.inv_tau, d.kb_axis, d.kb_diag, r, o);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) store_run<S, 1>(reinterpret_cast<S*>(out + i * pb + c0), &o[i], nontemporal);
+            } else {
+                relax(g, d.inv_tau, d.kb_axis, d.kb_diag);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    S v;
+                    if constexpr (sizeof(S) == 2 && __is_same(S, _Float16)) v = sr_f16(g[i], bits16(r, i));
+                    else if constexpr (sizeof(S) == 2) v = sr_bf16(g[i], bits16(r, i));
+                    typedef typename RawT<sizeof(S)>::T R;
+                    R raw;
+                    __builtin_memcpy(&raw, &v, sizeof(R));
+                    R* q = reinterpret_cast<R*>(out + i * pb + c0);
+                    if (nontemporal) __builtin_nontemporal_store(raw, q);
+                    else *q = raw;
+                }
+            }
+        } else {
+            relax(g, d.inv_tau, d.kb_axis, d.kb_diag);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                store_run<S, 1>(reinterpret_cast<S*>(out + i * pb + c0), &g[i], nontemporal);
+            }
         }
     }
     if (MODE == kCheck) block_partials(acc, a.partials + (int64_t)t * kPartials);
@@ -471,21 +589,29 @@ static hipError_t launch_step_v(const Shape& sh, int mode, const StepArgs& a, in
     return hipGetLastError();
 }
 
-template <class S>
-static hipError_t launch_wave(const Shape& sh, int mode, const StepArgs& a, int64_t snap_stride,
-                              hipStream_t st) {
+template <class S, int SR>
+static hipError_t launch_wave_sr(const Shape& sh, int mode, const StepArgs& a, int64_t snap_stride,
+                                 hipStream_t st) {
     dim3 grid(a.ntiles), block(sh.bx, sh.by);
     if (mode == kPlain)
-        hipLaunchKernelGGL((wave_kernel<S, kPlain>), grid, block, 0, st, a, snap_stride, sh.xcd, sh.nt);
+        hipLaunchKernelGGL((wave_kernel<S, kPlain, SR>), grid, block, 0, st, a, snap_stride, sh.xcd, sh.nt);
     else if (mode == kSnap)
-        hipLaunchKernelGGL((wave_kernel<S, kSnap>), grid, block, 0, st, a, snap_stride, sh.xcd, sh.nt);
+        hipLaunchKernelGGL((wave_kernel<S, kSnap, SR>), grid, block, 0, st, a, snap_stride, sh.xcd, sh.nt);
     else
-        hipLaunchKernelGGL((wave_kernel<S, kCheck>), grid, block, 0, st, a, snap_stride, sh.xcd, sh.nt);
+        hipLaunchKernelGGL((wave_kernel<S, kCheck, SR>), grid, block, 0, st, a, snap_stride, sh.xcd, sh.nt);
     return hipGetLastError();
 }
 
 template <class S>
+static hipError_t launch_wave(const Shape& sh, int mode, const StepArgs& a, int64_t snap_stride,
+                              hipStream_t st) {
+    return a.sr ? launch_wave_sr<S, 1>(sh, mode, a, snap_stride, st)
+                : launch_wave_sr<S, 0>(sh, mode, a, snap_stride, st);
+}
+
+template <class S>
 static hipError_t launch_step_s(const Shape& sh, int mode, const StepArgs& a, int64_t ss, hipStream_t st) {
+    if (a.sr && sh.vec != 1) return hipErrorInvalidValue;
     switch (sh.vec) {
         case 1: return launch_wave<S>(sh, mode, a, ss, st);
         case 2: return launch_step_v<S, 2>(sh, mode, a, ss, st);

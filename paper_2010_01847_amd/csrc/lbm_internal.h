@@ -68,6 +68,10 @@ struct StepArgs {
     double* partials;           // kPartials per global tile, CHECK
     int32_t tile_base;          // first global tile of this launch
     int32_t ntiles;             // tiles in this launch
+    const uint32_t* ctr_in;     // steps completed before this step (device counter)
+    uint32_t* ctr_out;          // written with ctr_in + 1 by the block of global tile 0
+    uint32_t seed;              // stream of the stochastic-rounding bits
+    int32_t sr;                 // 1: round stores stochastically (nodes per lane must be 1)
 };
 
 // Host-side launchers defined in lbm_device.hip; they return hipError_t.

@@ -158,7 +158,7 @@ struct Layout {
     size_t buf_bytes = 0;      // one population buffer
     size_t off_buf[2] = {0, 0};
     size_t off_snap = 0, off_part = 0, off_res = 0, off_mpart = 0, off_mres = 0, off_desc = 0,
-           off_tiles = 0, total = 0;
+           off_tiles = 0, off_ctr = 0, total = 0;
     int64_t nodes = 0, tiles_max = 0, mparts_max = 0;
 };
 
@@ -183,6 +183,7 @@ Layout layout_of(const std::vector<lbm_instance>& v, int storage, int check, int
     L.off_mres = o; o += align_up(kPartials * sizeof(double), kAlign);
     L.off_desc = o; o += align_up(v.size() * sizeof(InstDesc), kAlign);
     L.off_tiles = o; o += align_up((size_t)L.tiles_max * sizeof(int32_t), kAlign);
+    L.off_ctr = o; o += kAlign;                 // two 32-bit step counters (ping-pong)
     L.total = o;
     return L;
 }
@@ -196,6 +197,8 @@ struct lbm_ctx {
     hipStream_t capture_stream = nullptr;
     int storage = 0;
     int layout = LBM_LAYOUT_CHUNKED;
+    int sr = 0;                      // stochastic rounding of stores
+    uint32_t seed = 0;
     int K = 100;                     // check interval, 0 = off
     std::vector<lbm_instance> inst;
     std::vector<InstDesc> desc;
@@ -228,6 +231,7 @@ struct lbm_ctx {
     double* d_res() const { return reinterpret_cast<double*>(base + L.off_res); }
     double* d_mpart() const { return reinterpret_cast<double*>(base + L.off_mpart); }
     double* d_mres() const { return reinterpret_cast<double*>(base + L.off_mres); }
+    uint32_t* d_ctr() const { return reinterpret_cast<uint32_t*>(base + L.off_ctr); }
 
     int fail(int code, const std::string& m) {
         err = m;
@@ -317,9 +321,10 @@ static Status check_config(const lbm_config* cfg, std::vector<lbm_instance>* out
     if (cfg->storage < 0 || cfg->storage > 2) return {LBM_EINVAL, "storage must be LBM_F32, LBM_F16 or LBM_BF16"};
     if (cfg->check_interval != 0 && cfg->check_interval != -1 && cfg->check_interval < 2)
         return {LBM_EINVAL, "check_interval must be 0 (default 100), -1 (off) or >= 2"};
-    if (cfg->flags & ~LBM_FLAG_EXTERNAL_MEMORY) return {LBM_EINVAL, "unknown flags"};
-    if (cfg->layout < 0 || cfg->layout > 2 || cfg->reserved != 0)
-        return {LBM_EINVAL, "layout must be LBM_LAYOUT_AUTO, _PLANES or _CHUNKED and reserved 0"};
+    if (cfg->flags & ~(LBM_FLAG_EXTERNAL_MEMORY | LBM_FLAG_STOCHASTIC_ROUNDING))
+        return {LBM_EINVAL, "unknown flags"};
+    if (cfg->layout < 0 || cfg->layout > 2)
+        return {LBM_EINVAL, "layout must be LBM_LAYOUT_AUTO, _PLANES or _CHUNKED"};
     out->assign(cfg->inst, cfg->inst + cfg->n_instances);
     for (int k = 0; k < cfg->n_instances; ++k) {
         lbm_instance& in = (*out)[k];
@@ -371,6 +376,8 @@ int lbm_create(const lbm_config* cfg, lbm_handle* out) {
     h->K = check_of(cfg);
     h->stream = reinterpret_cast<hipStream_t>(cfg->stream);
     h->external = (cfg->flags & LBM_FLAG_EXTERNAL_MEMORY) != 0;
+    h->sr = (cfg->flags & LBM_FLAG_STOCHASTIC_ROUNDING) ? 1 : 0;
+    h->seed = cfg->seed;
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) {
         g_create_error = std::string("hipGetDevice: ") + hipGetErrorString(e);
@@ -514,6 +521,7 @@ static int do_init(lbm_ctx* h, int32_t k, const double* dT, const double* dqx, c
     const double grad = in.bc_x == LBM_BC_GRADIENT ? in.grad_x : 0.0;
     HIPCALL(h, launch_init(h->storage, h->d_desc(), k, d, h->buf(1 - h->cur), h->buf(h->cur), dT, dqx,
                            dqy, in.t0, grad, h->co[k].beta, h->stream));
+    HIPCALL(h, hipMemsetAsync(h->d_ctr(), 0, 2 * sizeof(uint32_t), h->stream));
     HIPCALL(h, hipStreamSynchronize(h->stream));
     if (h->steps != 0) {
         // the handle restarts at n = 0: every other instance must be re-initialised
@@ -597,6 +605,10 @@ static int issue_step(lbm_ctx* h, int64_t m, int src_k, hipStream_t st, int sche
     a.dst = h->buf(1 - src_k);
     a.snap = h->d_snap();
     a.partials = h->d_part();
+    a.ctr_in = h->d_ctr() + src_k;
+    a.ctr_out = h->d_ctr() + (1 - src_k);
+    a.seed = h->seed;
+    a.sr = h->sr;
     if (sched == LBM_SCHED_PER_INSTANCE) {
         for (size_t k = 0; k < h->inst.size(); ++k) {
             a.tile_base = h->desc[k].tile_begin;
@@ -806,6 +818,7 @@ int lbm_set_launch_shape(lbm_handle h, const lbm_launch_shape* s) {
     if (!valid(h)) return LBM_EINVAL;
     Status st = shape_ok(s);
     if (st.code) return h->fail(st.code, st.msg);
+    if (h->sr && s->vec != 1) return h->fail(LBM_EINVAL, "stochastic rounding needs vec = 1");
     h->shape.vec = s->vec;
     h->shape.bx = s->block_x;
     h->shape.by = s->block_y;
@@ -887,11 +900,15 @@ static int time_shape(lbm_ctx* h, const Shape& s, int steps, hipEvent_t e0, hipE
     a.partials = nullptr;
     a.tile_base = 0;
     a.ntiles = (int32_t)h->ntiles;
+    a.seed = h->seed;
+    a.sr = h->sr;
     int src = 0;
     for (int w = 0; w < 3 + steps; ++w) {
         if (w == 3) HIPCALL(h, hipEventRecord(e0, h->stream));
         a.src = h->buf(src);
         a.dst = h->buf(1 - src);
+        a.ctr_in = h->d_ctr() + src;
+        a.ctr_out = h->d_ctr() + (1 - src);
         HIPCALL(h, launch_step(h->storage, s, kPlain, a, h->L.nodes, h->stream));
         src = 1 - src;
     }
@@ -947,6 +964,7 @@ int lbm_autotune(lbm_handle h, int32_t steps, char* report, size_t report_len) {
     };
     for (int v : vecs)
         for (auto& b : blocks) {
+            if (h->sr && v != 1) continue;     // stochastic rounding runs one node per lane
             Shape s;
             s.vec = v;
             s.bx = b[0];

@@ -27,6 +27,7 @@ LBM_F32, LBM_F16, LBM_BF16 = 0, 1, 2
 LBM_BC_PERIODIC, LBM_BC_ISOTHERMAL, LBM_BC_DIFFUSE, LBM_BC_GRADIENT = 0, 1, 2, 3
 LBM_SCHED_BATCHED, LBM_SCHED_PER_INSTANCE, LBM_SCHED_GRAPH = 0, 1, 2
 LBM_FLAG_EXTERNAL_MEMORY = 0x1
+LBM_FLAG_STOCHASTIC_ROUNDING = 0x2
 LBM_LAYOUT_AUTO, LBM_LAYOUT_PLANES, LBM_LAYOUT_CHUNKED = 0, 1, 2
 LAYOUT = {"auto": LBM_LAYOUT_AUTO, "planes": LBM_LAYOUT_PLANES, "chunked": LBM_LAYOUT_CHUNKED}
 
@@ -49,7 +50,7 @@ class lbm_config(ctypes.Structure):
     _fields_ = [("n_instances", ctypes.c_int32), ("storage", ctypes.c_int32),
                 ("check_interval", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("inst", ctypes.POINTER(lbm_instance)), ("stream", ctypes.c_void_p),
-                ("layout", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("layout", ctypes.c_int32), ("seed", ctypes.c_uint32)]
 
 
 class lbm_check_info(ctypes.Structure):
@@ -259,7 +260,7 @@ class Lattice:
     """One handle over one or more instances, memory from torch, stream from torch."""
 
     def __init__(self, instances: Iterable[lbm_instance], storage="f32", check_interval: int = 0,
-                 device=None, stream=None, layout="auto"):
+                 device=None, stream=None, layout="auto", rounding="nearest", seed: int = 0):
         import torch
         self._torch = torch
         self.instances: List[lbm_instance] = list(instances)
@@ -271,7 +272,10 @@ class Lattice:
         cfg.n_instances = len(self.instances)
         cfg.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
         cfg.check_interval = int(check_interval)
-        cfg.flags = LBM_FLAG_EXTERNAL_MEMORY
+        if rounding not in ("nearest", "stochastic"):
+            raise ValueError("rounding must be 'nearest' or 'stochastic'")
+        cfg.flags = LBM_FLAG_EXTERNAL_MEMORY | (LBM_FLAG_STOCHASTIC_ROUNDING if rounding == "stochastic" else 0)
+        cfg.seed = int(seed) & 0xffffffff
         cfg.inst = ctypes.cast(arr, ctypes.POINTER(lbm_instance))
         cfg.stream = ctypes.c_void_p(self.stream.cuda_stream)
         cfg.layout = LAYOUT[layout] if isinstance(layout, str) else int(layout)

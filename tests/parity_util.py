@@ -23,8 +23,9 @@ def oracle_fields(case, steps, T0=None, qx=None, qy=None):
 
 
 def gpu_fields(case, steps, T0=None, qx=None, qy=None, storage="f32", scale=0.0, check=0,
-               shape=None, schedule=None, layout="auto"):
-    lat = Lattice([instance_from_case(case, scale)], storage=storage, check_interval=check, layout=layout)
+               shape=None, schedule=None, layout="auto", rounding="nearest", seed=0):
+    lat = Lattice([instance_from_case(case, scale)], storage=storage, check_interval=check, layout=layout,
+                  rounding=rounding, seed=seed)
     if shape:
         lat.set_launch_shape(**shape)
     if schedule:

@@ -66,6 +66,38 @@ def test_launch_shapes_and_layouts_bitwise(storage):
                 assert np.array_equal(a, b), (sh, layout)
 
 
+SR_SHAPES = [(dict(vec=1, block_x=64, block_y=1, xcd_remap=0, nontemporal=0), "chunked"),
+             (dict(vec=1, block_x=256, block_y=2, xcd_remap=1, nontemporal=0), "chunked"),
+             (dict(vec=1, block_x=512, block_y=1, xcd_remap=1, nontemporal=1), "planes"),
+             (dict(vec=1, block_x=128, block_y=4, xcd_remap=0, nontemporal=0), "planes")]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_stochastic_rounding_deterministic_and_close(storage):
+    """Stochastic rounding draws its bits from (node, step, direction, seed):
+    identical bits for every launch shape and layout, different bits for
+    another seed, and within the storage tolerance of the oracle."""
+    case, T0, qx, qy = _random_case(131, 37, 0.55, 50.0, 9)
+    ora = oracle_fields(case, 23, T0, qx, qy)
+    ref_out = None
+    for sh, layout in SR_SHAPES:
+        out = gpu_fields(case, 23, T0, qx, qy, shape=sh, check=5, storage=storage, layout=layout,
+                         rounding="stochastic", seed=11)
+        if ref_out is None:
+            ref_out = out
+            e = eps(case, out, ora)
+            log(f"stochastic 131x37 {storage}: eps={e}")
+            assert max(e) < {"f32": 1e-5, "f16": 5e-3, "bf16": 5e-2}[storage]
+        else:
+            for a, b in zip(out, ref_out):
+                assert np.array_equal(a, b), (sh, layout)
+    other = gpu_fields(case, 23, T0, qx, qy, storage=storage, rounding="stochastic", seed=12)
+    assert not np.array_equal(other[1], ref_out[1])
+    with pytest.raises(LBMError) as e:
+        gpu_fields(case, 1, T0, storage=storage, rounding="stochastic", shape=SHAPES[4])
+    assert e.value.code == LBM_EINVAL
+
+
 @pytest.mark.parametrize("nx,ny", [(2, 2), (2, 5), (3, 2), (5, 3), (64, 2), (65, 3), (257, 4)])
 def test_minimal_and_ragged_grids(nx, ny):
     """Indexing on the smallest grids (x - 1 and x + 1 wrap to the same node
@@ -181,18 +213,23 @@ def test_batched_schedules_bitwise_and_parity():
     cases = W.knudsen_sweep(n_inst=6, seed=7, side_lo=20, side_hi=140, steps=0)
     insts = [instance_from_case(c) for c in cases]
     outs = {}
-    for sched in ("batched", "per_instance", "graph"):
-        lat = Lattice(insts, check_interval=10)
+    for sched in ("batched", "per_instance", "graph", "sr_batched", "sr_per_instance", "sr_graph"):
+        sr = sched.startswith("sr_")
+        lat = Lattice(insts, check_interval=10, rounding="stochastic" if sr else "nearest", seed=5)
+        sched = sched[3:] if sr else sched
         lat.set_schedule(sched)
         for k in range(len(cases)):
             lat.init(k)
         lat.step(45)
-        outs[sched] = [lat.moments(k) for k in range(len(cases))]
+        outs[("sr_" if sr else "") + sched] = [lat.moments(k) for k in range(len(cases))]
         lat.close()
     for k, case in enumerate(cases):
-        for sched in ("per_instance", "graph"):
-            for a, b in zip(outs[sched][k], outs["batched"][k]):
-                assert np.array_equal(a, b), (sched, k)
+        for pre in ("", "sr_"):
+            for sched in ("per_instance", "graph"):
+                for a, b in zip(outs[pre + sched][k], outs[pre + "batched"][k]):
+                    assert np.array_equal(a, b), (pre + sched, k)
+        e_t, e_q = eps(case, outs["sr_batched"][k], oracle_fields(case, 45))
+        assert e_q < 1e-5 and e_t < 1e-5, ("stochastic", k, e_t, e_q)
         e_t, e_q = eps(case, outs["batched"][k], oracle_fields(case, 45))
         log(f"batched inst {k} {case.nx}x{case.ny} tr={case.tau_r:.3g}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
         assert e_q < 1e-5 and e_t < 1e-5
