@@ -218,10 +218,12 @@ typedef struct {
 } lbm_check_info;
 int lbm_last_check(lbm_handle h, int32_t inst, lbm_check_info* out);
 
-/* Coefficients the kernels use for instance `inst`, as doubles:
+/* Coefficients the kernels use for instance `inst`, as doubles.  The
+ * relaxation is applied in its eigen-decomposition: energy kept, heat-flux
+ * share times rho, the rest times 1 - 1/tau (from Eqs. 13, 15, 16, 54).
  * out[0] = 1/tau (FP32-rounded), out[1] = beta (FP32-rounded),
- * out[2] = kappa * beta with kappa = 1/tau - (1 - 1/(2 tau)) / tau_r (FP32-rounded),
- * out[3] = s, out[4] = tau (exact), out[5] = rho = (2 tau_r - 1)/(2 tau_r + 1) (exact). */
+ * out[2] = 1 - rho = 2/(2 tau_r + 1) (FP32-rounded), out[3] = s,
+ * out[4] = tau (exact), out[5] = rho = (2 tau_r - 1)/(2 tau_r + 1) (exact). */
 int lbm_coefficients(lbm_handle h, int32_t inst, double out[6]);
 
 /* Select how multi-instance steps are issued (lbm_schedule).  GRAPH captures

@@ -105,29 +105,44 @@ __device__ __forceinline__ void store_run(S* __restrict__ p, const float* v, int
 #define W_DIAG 0.027777777777777778f   // 1/36
 
 // Relaxation of one node (Eq. 13 right-hand side with Eqs. 15-16, dt = c = 1)
-// in g-form.  E = sum g, j = sum c_i g (Eq. 53 and the sum of Eq. 54); the
-// equilibrium energy share is split so that 4 ea + 4 ed == E holds exactly
-// (E - 4 ea is exact by Sterbenz' lemma), and the flux share of Eq. 15 minus
-// the source of Eq. 16 is kappa * beta * (5 a_i / 3) c_i . j.  The library is
-// built with contraction off and the fused multiply-adds are written out, so
-// every kernel instance (any nodes-per-thread, any launch shape) performs the
-// same operations and produces the same bits:
-//   g* = fma(kb_i, c_i . j, fma(1/tau, eq_i - g, g)).
-__device__ __forceinline__ void relax(float g[8], float inv_tau, float kb_a, float kb_d) {
+// in g-form, applied in the operator's eigen-decomposition.  With
+// E = sum g, j = sum c_i g (Eqs. 53-54 up to the factor beta), the flux share
+// f_i = (5 a_i / 3) c_i . j and the remainder h_i = g_i - omega_i E - f_i,
+// Eqs. 13, 15 and 16 give
+//     g*_i = omega_i E + rho f_i + (1 - 1/tau) h_i
+//          = g_i - (1/tau) h_i - (1 - rho) f_i,
+// rho = (2 tau_r - 1)/(2 tau_r + 1): energy is kept, the heat flux decays by
+// rho per step, everything else by 1 - 1/tau.  Writing it this way keeps the
+// small per-step flux decay 1 - rho = 2/(2 tau_r + 1) as its own coefficient
+// (rounded once): forming it as the difference of two FP32 coefficients of
+// order 1 loses ~5 digits when tau_r ~ 1e3.  The equilibrium energy share is
+// split so that 4 ea + 4 ed == E holds exactly (E - 4 ea is exact by
+// Sterbenz' lemma).  The library is built with contraction off and the fused
+// multiply-adds are written out, so every kernel instance produces the same
+// bits.
+#define W_FA 0.333333333333333333f      // 5 a_i / 3, axis directions
+#define W_FD 0.083333333333333333f      // 5 a_i / 3, diagonal directions
+
+__device__ __forceinline__ void relax_parts(const float g[8], float eqf[8], float fl[8]) {
     const float E = ((g[0] + g[2]) + (g[1] + g[3])) + ((g[4] + g[6]) + (g[5] + g[7]));
     const float jx = ((g[0] - g[2]) + (g[4] - g[6])) + (g[7] - g[5]);
     const float jy = ((g[1] - g[3]) + (g[4] - g[6])) + (g[5] - g[7]);
     const float ea = W_AXIS * E;
     const float ed = (E - 4.0f * ea) * 0.25f;
-    const float jp = jx + jy, jm = jx - jy;
-    g[0] = __builtin_fmaf(kb_a, jx, __builtin_fmaf(inv_tau, ea - g[0], g[0]));
-    g[1] = __builtin_fmaf(kb_a, jy, __builtin_fmaf(inv_tau, ea - g[1], g[1]));
-    g[2] = __builtin_fmaf(-kb_a, jx, __builtin_fmaf(inv_tau, ea - g[2], g[2]));
-    g[3] = __builtin_fmaf(-kb_a, jy, __builtin_fmaf(inv_tau, ea - g[3], g[3]));
-    g[4] = __builtin_fmaf(kb_d, jp, __builtin_fmaf(inv_tau, ed - g[4], g[4]));
-    g[5] = __builtin_fmaf(-kb_d, jm, __builtin_fmaf(inv_tau, ed - g[5], g[5]));
-    g[6] = __builtin_fmaf(-kb_d, jp, __builtin_fmaf(inv_tau, ed - g[6], g[6]));
-    g[7] = __builtin_fmaf(kb_d, jm, __builtin_fmaf(inv_tau, ed - g[7], g[7]));
+    const float fx = W_FA * jx, fy = W_FA * jy;
+    const float fp = W_FD * (jx + jy), fm = W_FD * (jx - jy);
+    fl[0] = fx;  fl[1] = fy;  fl[2] = -fx;  fl[3] = -fy;
+    fl[4] = fp;  fl[5] = -fm; fl[6] = -fp;  fl[7] = fm;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) eqf[i] = (i < 4 ? ea : ed) + fl[i];
+}
+
+__device__ __forceinline__ void relax(float g[8], float inv_tau, float sigma) {
+    float eqf[8], fl[8];
+    relax_parts(g, eqf, fl);
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        g[i] = __builtin_fmaf(-sigma, fl[i], __builtin_fmaf(-inv_tau, g[i] - eqf[i], g[i]));
 }
 
 // ------------------------------------------------------------------ stochastic rounding
@@ -190,29 +205,20 @@ __device__ __forceinline__ bf16_bits sr_bf16(float v, uint32_t r16) {
     return o;
 }
 
-// Relaxation with stochastic rounding of the stored result.  For FP32 the
-// update is formed first and added with sr_add_f32; for 16-bit storage the
-// round-to-nearest FP32 result of relax() is narrowed stochastically.
-template <class S> struct SRStore;
-template <> struct SRStore<float> {
-    static __device__ __forceinline__ void relax_store(float g[8], float it, float kb_a, float kb_d,
-                                                       const uint32_t r[4], float out[8]) {
-        const float E = ((g[0] + g[2]) + (g[1] + g[3])) + ((g[4] + g[6]) + (g[5] + g[7]));
-        const float jx = ((g[0] - g[2]) + (g[4] - g[6])) + (g[7] - g[5]);
-        const float jy = ((g[1] - g[3]) + (g[4] - g[6])) + (g[5] - g[7]);
-        const float ea = W_AXIS * E;
-        const float ed = (E - 4.0f * ea) * 0.25f;
-        const float jp = jx + jy, jm = jx - jy;
-        const float fl[8] = {kb_a * jx, kb_a * jy, -kb_a * jx, -kb_a * jy,
-                             kb_d * jp, -kb_d * jm, -kb_d * jp, kb_d * jm};
+// Relaxation with stochastic rounding of the stored result (FP32 storage):
+// the update -(1/tau) h_i - (1 - rho) f_i is formed first and added to g_i
+// with sr_add_f32.  16-bit storage narrows the round-to-nearest FP32 result
+// of relax() stochastically instead.
+__device__ __forceinline__ void relax_sr_f32(const float g[8], float inv_tau, float sigma,
+                                             const uint32_t r[4], float out[8]) {
+    float eqf[8], fl[8];
+    relax_parts(g, eqf, fl);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const float eq = i < 4 ? ea : ed;
-            const float delta = __builtin_fmaf(it, eq - g[i], fl[i]);
-            out[i] = sr_add_f32(g[i], delta, bits16(r, i));
-        }
+    for (int i = 0; i < 8; ++i) {
+        const float delta = __builtin_fmaf(-sigma, fl[i], -inv_tau * (g[i] - eqf[i]));
+        out[i] = sr_add_f32(g[i], delta, bits16(r, i));
     }
-};
+}
 
 // Boundary treatment after advection (Sec. 2.5) on one node, given its
 // position.  Directions 0..7 are the paper's 1..8.  Written with selects only:
@@ -430,7 +436,7 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t sna
             }
         }
 #pragma unroll
-        for (int k = 0; k < V; ++k) relax(g[k], d.inv_tau, d.kb_axis, d.kb_diag);
+        for (int k = 0; k < V; ++k) relax(g[k], d.inv_tau, d.sigma);
         // a V-aligned run never crosses a 64-node chunk
         S* out = dst + rows[0] + xo;
 #pragma unroll
@@ -547,11 +553,11 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
             for (int k = 0; k < 4; ++k) r[k] = mix32(node ^ mix32(step * 4u + (uint32_t)k + a.seed * 0x9e3779b9u));
             if (sizeof(S) == 4) {
                 float o[8];
-                SRStore<float>::relax_store(g, d.inv_tau, d.kb_axis, d.kb_diag, r, o);
+                relax_sr_f32(g, d.inv_tau, d.sigma, r, o);
 #pragma unroll
                 for (int i = 0; i < 8; ++i) store_run<S, 1>(reinterpret_cast<S*>(out + i * pb + c0), &o[i], nontemporal);
             } else {
-                relax(g, d.inv_tau, d.kb_axis, d.kb_diag);
+                relax(g, d.inv_tau, d.sigma);
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     S v;
@@ -566,7 +572,7 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
                 }
             }
         } else {
-            relax(g, d.inv_tau, d.kb_axis, d.kb_diag);
+            relax(g, d.inv_tau, d.sigma);
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 store_run<S, 1>(reinterpret_cast<S*>(out + i * pb + c0), &g[i], nontemporal);
@@ -745,7 +751,7 @@ __global__ __launch_bounds__(256) void init_kernel(const InstDesc* __restrict__ 
         p[(int64_t)i * d.plane] = v;
         g[i] = Cvt<S>::ld(v);
     }
-    relax(g, d.inv_tau, d.kb_axis, d.kb_diag);
+    relax(g, d.inv_tau, d.sigma);
 #pragma unroll
     for (int i = 0; i < 8; ++i) q[(int64_t)i * d.plane] = Cvt<S>::st(g[i]);
 }

@@ -35,9 +35,9 @@ struct alignas(64) InstDesc {
     int64_t chunk;          // elements between 64-node chunks (0: planes layout)
     int64_t off;            // element offset of this instance in a buffer
     int64_t node_off;       // offset of this instance in node-indexed arrays (snapshot)
-    float inv_tau;          // 1 / tau
-    float kb_axis;          // kappa * beta / 3  (flux term of axis directions)
-    float kb_diag;          // kappa * beta / 12 (flux term of diagonal directions)
+    float inv_tau;          // 1 / tau: decay of the non-equilibrium share per step
+    float sigma;            // 1 - rho = 2 / (2 tau_r + 1): decay of the flux share per step
+    float pad0;
     float grad_term;        // C_V * grad / s  (times omega_i c_ix after the pull)
     float wall_g[4];        // C_V (T_wall - T_ref) / s for isothermal walls (times omega_i)
     double s_cv;            // s / C_V   (dT = s E / C_V)

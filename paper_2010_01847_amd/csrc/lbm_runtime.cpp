@@ -84,13 +84,14 @@ Geometry geometry_of(const lbm_instance& in, int es, int layout) {
 int resolve_layout(int layout) { return layout == LBM_LAYOUT_PLANES ? LBM_LAYOUT_PLANES : LBM_LAYOUT_CHUNKED; }
 
 struct Coeffs {
-    double tau, tau_c, beta, kappa, rho;
+    double tau, tau_c, beta, rho, one_minus_rho;
 };
 
 // tau = tau_C + 1/2 (Eq. 49), 1/tau_C = 1/tau_N + 1/tau_R; beta of Eq. 54;
-// kappa = 1/tau - (1 - 1/(2 tau)) / tau_R combines the flux share of the
-// equilibrium (Eq. 15) with the source (Eq. 16); rho = 1 - beta / tau_R is the
-// resulting per-step factor on the heat flux.
+// rho = (2 tau_r - 1)/(2 tau_r + 1), the per-step factor on the heat flux that
+// Eqs. 13, 15, 16 and 54 give; 1 - rho = 2/(2 tau_r + 1) is kept separately
+// (computed directly, not as 1 - rho) because the kernels apply it as the
+// flux decay coefficient.
 Coeffs coeffs_of(const lbm_instance& in) {
     Coeffs c;
     const bool inf_r = std::isinf(in.tau_r);
@@ -98,8 +99,8 @@ Coeffs coeffs_of(const lbm_instance& in) {
     c.tau_c = 1.0 / inv_tc;
     c.tau = c.tau_c + 0.5;
     c.beta = inf_r ? 1.0 : 2.0 * in.tau_r / (2.0 * in.tau_r + 1.0);
-    c.kappa = 1.0 / c.tau - (inf_r ? 0.0 : (1.0 - 1.0 / (2.0 * c.tau)) / in.tau_r);
     c.rho = inf_r ? 1.0 : (2.0 * in.tau_r - 1.0) / (2.0 * in.tau_r + 1.0);
+    c.one_minus_rho = inf_r ? 0.0 : 2.0 / (2.0 * in.tau_r + 1.0);
     return c;
 }
 
@@ -293,8 +294,7 @@ static void fill_desc(lbm_ctx* h, size_t k, double s) {
     const Coeffs& c = h->co[k];
     InstDesc& d = h->desc[k];
     d.inv_tau = (float)(1.0 / c.tau);
-    d.kb_axis = (float)(c.kappa * c.beta / 3.0);
-    d.kb_diag = (float)(c.kappa * c.beta / 12.0);
+    d.sigma = (float)c.one_minus_rho;
     d.grad_term = in.bc_x == LBM_BC_GRADIENT ? (float)(in.cv * in.grad_x / s) : 0.0f;
     for (int w = 0; w < 4; ++w) d.wall_g[w] = (float)(in.cv * (in.t_wall[w] - in.t0) / s);
     d.s = s;
@@ -790,7 +790,7 @@ int lbm_coefficients(lbm_handle h, int32_t k, double out[6]) {
     const Coeffs& c = h->co[k];
     out[0] = d.inv_tau;
     out[1] = (float)c.beta;
-    out[2] = (float)(c.kappa * c.beta);
+    out[2] = d.sigma;
     out[3] = d.s;
     out[4] = c.tau;
     out[5] = c.rho;

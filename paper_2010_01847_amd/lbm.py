@@ -202,7 +202,7 @@ def lbm_last_check(h, inst: int) -> dict:
 def lbm_coefficients(h, inst: int) -> dict:
     out = np.zeros(6)
     _check(library().lbm_coefficients(h, inst, _dptr(out)), "lbm_coefficients", h)
-    return dict(inv_tau=out[0], beta=out[1], kappa_beta=out[2], scale=out[3], tau=out[4], rho=out[5])
+    return dict(inv_tau=out[0], beta=out[1], one_minus_rho=out[2], scale=out[3], tau=out[4], rho=out[5])
 
 
 def lbm_set_schedule(h, schedule: int) -> None:
