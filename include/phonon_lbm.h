@@ -61,7 +61,10 @@ typedef enum { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2 } lbm_storage;
  *                omega_i (Eq. 58); the wall node then relaxes like any node.
  *   GRADIENT   : periodic temperature-gradient seam along x (Eqs. 59-60) with
  *                period nx and T_h - T_c = grad_x * nx; handled exactly as a
- *                periodic deviation around the ramp T_ref(x) = t0 - grad_x * x.
+ *                periodic deviation from the bulk steady state of the imposed
+ *                gradient (ramp T_ref(x) = t0 - grad_x * x carrying Fourier's
+ *                heat flux (5/9) C_V grad_x tau_r), so the seam needs no branch
+ *                and the stored values are the departures from that state.
  * Supported pairs: (any x, PERIODIC y), (PERIODIC x, ISOTHERMAL or DIFFUSE y),
  * (GRADIENT x, DIFFUSE y).  Walls on both axes need corners, which the paper
  * leaves undefined: LBM_EUNSUPPORTED. */

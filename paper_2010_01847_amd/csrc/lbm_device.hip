@@ -9,12 +9,15 @@
 // flop per 64 bytes in FP32), so there is no matrix-core work: the design
 // goals are coalesced, wide HBM accesses and enough bytes in flight.
 //
-// Stored quantity: g_i = (e_i - omega_i C_V T_ref(x)) / s.  The scheme is
-// affine in e, and a uniform (or, with the gradient seam, ramp) equilibrium
-// with zero flux is a fixed point of the relaxation, so the g-form update is
-// the same relaxation applied to g; the ramp only adds omega_i C_V G c_ix / s
-// to each pulled population, which turns the seam of Eqs. 59-60 into plain
-// periodic wrap.
+// Stored quantity: g_i = (e_i - R_i(x)) / s, the deviation from a reference
+// state R that one step (advection, then relaxation) maps exactly onto itself:
+// a uniform equilibrium, or with the gradient seam of Eqs. 59-60 the bulk
+// steady state of the imposed gradient (the ramp T_ref = t0 - G x with
+// Fourier's heat flux and its constant non-equilibrium share).  The scheme is
+// affine in e, so the update of g is the bare relaxation with plain periodic
+// wrap (the seam disappears), and the stored values are the small departures
+// from that state, which is what keeps FP32 steady states accurate when
+// tau_R is large.
 //
 // Layout (see InstDesc): either eight direction planes of ny rows each, x
 // contiguous, or "chunked": each 64-node row segment stores its eight
@@ -137,12 +140,25 @@ __device__ __forceinline__ void relax_parts(const float g[8], float eqf[8], floa
     for (int i = 0; i < 8; ++i) eqf[i] = (i < 4 ? ea : ed) + fl[i];
 }
 
-__device__ __forceinline__ void relax(float g[8], float inv_tau, float sigma) {
+// Per-step change of population i: -(1/tau) h_i - (1 - rho) f_i plus the
+// forcing of the reference state (nonzero only for a gradient with tau_R
+// infinite), formed at the size of the change itself and added to g once.
+__device__ __forceinline__ void relax_delta(const float g[8], const InstDesc& d, float delta[8]) {
     float eqf[8], fl[8];
     relax_parts(g, eqf, fl);
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
-        g[i] = __builtin_fmaf(-sigma, fl[i], __builtin_fmaf(-inv_tau, g[i] - eqf[i], g[i]));
+    for (int i = 0; i < 8; ++i) {
+        const float cx = (float)(i == 0 || i == 4 || i == 7) - (float)(i == 2 || i == 5 || i == 6);
+        const float force = d.has_force ? cx * (i < 4 ? d.force_a : d.force_d) : 0.0f;
+        delta[i] = __builtin_fmaf(-d.sigma, fl[i], __builtin_fmaf(-d.inv_tau, g[i] - eqf[i], force));
+    }
+}
+
+__device__ __forceinline__ void relax(float g[8], const InstDesc& d) {
+    float delta[8];
+    relax_delta(g, d, delta);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) g[i] = g[i] + delta[i];
 }
 
 // ------------------------------------------------------------------ stochastic rounding
@@ -206,18 +222,14 @@ __device__ __forceinline__ bf16_bits sr_bf16(float v, uint32_t r16) {
 }
 
 // Relaxation with stochastic rounding of the stored result (FP32 storage):
-// the update -(1/tau) h_i - (1 - rho) f_i is formed first and added to g_i
-// with sr_add_f32.  16-bit storage narrows the round-to-nearest FP32 result
-// of relax() stochastically instead.
-__device__ __forceinline__ void relax_sr_f32(const float g[8], float inv_tau, float sigma,
-                                             const uint32_t r[4], float out[8]) {
-    float eqf[8], fl[8];
-    relax_parts(g, eqf, fl);
+// the change is added to g_i with sr_add_f32.  16-bit storage narrows the
+// round-to-nearest FP32 result of relax() stochastically instead.
+__device__ __forceinline__ void relax_sr_f32(const float g[8], const InstDesc& d, const uint32_t r[4],
+                                             float out[8]) {
+    float delta[8];
+    relax_delta(g, d, delta);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const float delta = __builtin_fmaf(-sigma, fl[i], -inv_tau * (g[i] - eqf[i]));
-        out[i] = sr_add_f32(g[i], delta, bits16(r, i));
-    }
+    for (int i = 0; i < 8; ++i) out[i] = sr_add_f32(g[i], delta[i], bits16(r, i));
 }
 
 // Boundary treatment after advection (Sec. 2.5) on one node, given its
@@ -234,8 +246,11 @@ __device__ __forceinline__ void boundary(float g[8], const InstDesc& d, int x, i
         const float Sh = g[1] + g[4] + g[5];      // incident at y = ny-1: 2, 5, 6
         const float dl = 0.1f * Sl, dh = 0.1f * Sh;
         const float al = Sl - dl - dl, ah = Sh - dh - dh;
-        g[1] = lo ? al : g[1];  g[4] = lo ? dl : g[4];  g[5] = lo ? dl : g[5];
-        g[3] = hi ? ah : g[3];  g[6] = hi ? dh : g[6];  g[7] = hi ? dh : g[7];
+        // the reference state's diagonal shares (c_ix p_diag) are not part of
+        // the reflected energy: the leaving diagonals carry -c_ix p_diag / s
+        const float k = d.wall_kd;
+        g[1] = lo ? al : g[1];  g[4] = lo ? dl - k : g[4];  g[5] = lo ? dl + k : g[5];
+        g[3] = hi ? ah : g[3];  g[6] = hi ? dh + k : g[6];  g[7] = hi ? dh - k : g[7];
     } else if (d.bc_y == 1) {
         const bool w = (y == 0) || (y == d.ny - 1);
         const float t = (y == 0) ? d.wall_g[2] : d.wall_g[3];
@@ -260,13 +275,6 @@ __device__ __forceinline__ void boundary(float g[8], const InstDesc& d, int x, i
     }
 }
 
-// Seam of Eqs. 59-60 in g-form: every pulled population gains
-// omega_i C_V G c_ix / s.
-__device__ __forceinline__ void ramp_term(float g[8], float gt) {
-    const float a = W_AXIS * gt, b = W_DIAG * gt;
-    g[0] += a; g[4] += b; g[7] += b;
-    g[2] -= a; g[5] -= b; g[6] -= b;
-}
 
 // x shift of the source of direction i (pull from x - c_ix), and the row of the
 // source: 0 = y, 1 = y - 1 (c_iy = +1), 2 = y + 1 (c_iy = -1).  Compile-time
@@ -398,12 +406,10 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t sna
 #pragma unroll
             for (int k = 0; k < V; ++k) g[k][i] = v[k];
         }
-        const bool ramp = (d.bc_x == 3);
         const bool edge_y = (d.bc_y != 0) && (y == 0 || y == ny - 1);
         const bool edge_x = (d.bc_x == 1 || d.bc_x == 2) && (x0 == 0 || x0 + V > nx - 1);
 #pragma unroll
         for (int k = 0; k < V; ++k) {
-            if (ramp) ramp_term(g[k], d.grad_term);
             if (edge_y || edge_x) boundary(g[k], d, x0 + k, y);
         }
         if (MODE != kPlain) {
@@ -418,7 +424,7 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t sna
                    + ((double)g[k][7] - (double)g[k][5]);
                 jy = ((double)g[k][1] - (double)g[k][3]) + ((double)g[k][4] - (double)g[k][6])
                    + ((double)g[k][5] - (double)g[k][7]);
-                const double dT = d.s_cv * E, qx = d.s_beta * jx, qy = d.s_beta * jy;
+                const double dT = d.s_cv * E, qx = d.q_ref + d.s_beta * jx, qy = d.s_beta * jy;
                 const int64_t n = nbase + x0 + k;
                 if (MODE == kSnap) {
                     a.snap[n] = dT;
@@ -436,7 +442,7 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t sna
             }
         }
 #pragma unroll
-        for (int k = 0; k < V; ++k) relax(g[k], d.inv_tau, d.sigma);
+        for (int k = 0; k < V; ++k) relax(g[k], d);
         // a V-aligned run never crosses a 64-node chunk
         S* out = dst + rows[0] + xo;
 #pragma unroll
@@ -460,7 +466,7 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t sna
 // Wavefront-centric step for one node per lane.  Each wave owns one 64-node
 // row segment (chunk cx of row y), so the row, chunk and plane bases are
 // wave-uniform scalars and every load is a scalar base plus a 32-bit lane
-// offset; the boundary and ramp branches are taken per wave, not per lane.
+// offset; the boundary branches are taken per wave, not per lane.
 // Same per-node arithmetic as step_kernel, hence the same bits.
 template <class S, int MODE, int SR>
 __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t snap_stride, int xcd,
@@ -516,7 +522,6 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
             const char* base = rows[src_row(i)] + i * pb;
             g[i] = Cvt<S>::ld(*reinterpret_cast<const S*>(base + (dx < 0 ? cm : (dx > 0 ? cp : c0))));
         }
-        if (d.bc_x == 3) ramp_term(g, d.grad_term);
         const bool edge_y = (d.bc_y != 0) && (y == 0 || y == ny - 1);
         const bool edge_x = (d.bc_x == 1 || d.bc_x == 2) && (xc == 0 || xc + 64 >= nx);
         if (edge_y || edge_x) boundary(g, d, x, y);
@@ -528,7 +533,7 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
                             + ((double)g[7] - (double)g[5]);
             const double jy = ((double)g[1] - (double)g[3]) + ((double)g[4] - (double)g[6])
                             + ((double)g[5] - (double)g[7]);
-            const double dT = d.s_cv * E, qx = d.s_beta * jx, qy = d.s_beta * jy;
+            const double dT = d.s_cv * E, qx = d.q_ref + d.s_beta * jx, qy = d.s_beta * jy;
             const int64_t n = d.node_off + (int64_t)y * nx + x;
             if (MODE == kSnap) {
                 a.snap[n] = dT;
@@ -553,11 +558,11 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
             for (int k = 0; k < 4; ++k) r[k] = mix32(node ^ mix32(step * 4u + (uint32_t)k + a.seed * 0x9e3779b9u));
             if (sizeof(S) == 4) {
                 float o[8];
-                relax_sr_f32(g, d.inv_tau, d.sigma, r, o);
+                relax_sr_f32(g, d, r, o);
 #pragma unroll
                 for (int i = 0; i < 8; ++i) store_run<S, 1>(reinterpret_cast<S*>(out + i * pb + c0), &o[i], nontemporal);
             } else {
-                relax(g, d.inv_tau, d.sigma);
+                relax(g, d);
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     S v;
@@ -572,7 +577,7 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
                 }
             }
         } else {
-            relax(g, d.inv_tau, d.sigma);
+            relax(g, d);
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 store_run<S, 1>(reinterpret_cast<S*>(out + i * pb + c0), &g[i], nontemporal);
@@ -662,8 +667,7 @@ __global__ __launch_bounds__(256) void moments_kernel(const InstDesc* __restrict
                 const int xs = wrapx(x + src_dx(i), nx);
                 g[i] = Cvt<S>::ld(src[(int64_t)i * d.plane + (int64_t)rows[src_row(i)] * d.row + col_off(d, xs)]);
             }
-            if (d.bc_x == 3) ramp_term(g, d.grad_term);
-            boundary(g, d, x, y);
+                boundary(g, d, x, y);
         } else {
 #pragma unroll
             for (int i = 0; i < 8; ++i)
@@ -676,7 +680,7 @@ __global__ __launch_bounds__(256) void moments_kernel(const InstDesc* __restrict
                         + ((double)g[7] - (double)g[5]);
         const double jy = ((double)g[1] - (double)g[3]) + ((double)g[4] - (double)g[6])
                         + ((double)g[5] - (double)g[7]);
-        const double dT = d.s_cv * E, vx = d.s_beta * jx, vy = d.s_beta * jy;
+        const double dT = d.s_cv * E, vx = d.q_ref + d.s_beta * jx, vy = d.s_beta * jy;
         const int64_t n = (int64_t)y * nx + x;
         if (out_kind == 0) {
             const double tref = t0 - grad * (double)x;
@@ -731,15 +735,17 @@ __global__ __launch_bounds__(256) void init_kernel(const InstDesc* __restrict__ 
     const double jx = qx ? qx[n] / beta : 0.0, jy = qy ? qy[n] / beta : 0.0;
     const double inv_s = 1.0 / d.s;
     const double ea = (2.0 / 9.0) * d.cv * dT, ed = (1.0 / 36.0) * d.cv * dT;
+    // minus the reference state's shares c_ix p_i
+    const double pa = d.p_axis, pd = d.p_diag;
     float g[8];
-    g[0] = (float)((ea + jx / 3.0) * inv_s);
+    g[0] = (float)((ea + jx / 3.0 - pa) * inv_s);
     g[1] = (float)((ea + jy / 3.0) * inv_s);
-    g[2] = (float)((ea - jx / 3.0) * inv_s);
+    g[2] = (float)((ea - jx / 3.0 + pa) * inv_s);
     g[3] = (float)((ea - jy / 3.0) * inv_s);
-    g[4] = (float)((ed + (jx + jy) / 12.0) * inv_s);
-    g[5] = (float)((ed + (-jx + jy) / 12.0) * inv_s);
-    g[6] = (float)((ed - (jx + jy) / 12.0) * inv_s);
-    g[7] = (float)((ed + (jx - jy) / 12.0) * inv_s);
+    g[4] = (float)((ed + (jx + jy) / 12.0 - pd) * inv_s);
+    g[5] = (float)((ed + (-jx + jy) / 12.0 + pd) * inv_s);
+    g[6] = (float)((ed - (jx + jy) / 12.0 + pd) * inv_s);
+    g[7] = (float)((ed + (jx - jy) / 12.0 - pd) * inv_s);
     const bool wall = (d.bc_x == 1 && (x == 0 || x == d.nx - 1)) ||
                       (d.bc_y == 1 && (y == 0 || y == d.ny - 1));
     if (wall) boundary(g, d, x, y);
@@ -751,7 +757,7 @@ __global__ __launch_bounds__(256) void init_kernel(const InstDesc* __restrict__ 
         p[(int64_t)i * d.plane] = v;
         g[i] = Cvt<S>::ld(v);
     }
-    relax(g, d.inv_tau, d.sigma);
+    relax(g, d);
 #pragma unroll
     for (int i = 0; i < 8; ++i) q[(int64_t)i * d.plane] = Cvt<S>::st(g[i]);
 }

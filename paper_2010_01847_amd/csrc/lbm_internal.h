@@ -12,7 +12,14 @@ constexpr int kMaxBlock = 512;     // threads per block upper bound (launch boun
 constexpr int kPartials = 5;       // per-tile FP64 partials: sum dE, sum qx, sum qy, |dm|^2, |m|^2
 
 // Per-instance descriptor, resident in device memory (one 192-byte record).
-// g-form: stored g_i = (e_i - omega_i C_V T_ref(x)) / s, T_ref = t0 - grad * x.
+// Stored quantity: g_i = (e_i - R_i(x)) / s, the deviation from a reference
+// state R that one step maps exactly onto itself (advection then relaxation):
+//   R_i(x) = omega_i C_V T_ref(x) + c_ix p_i,   T_ref = t0 - grad * x,
+// where p_i (one value for axis, one for diagonal directions) is the flux and
+// non-equilibrium share of the bulk steady state under the imposed gradient
+// (zero without a gradient).  The interior update is then the bare relaxation
+// of g; diffuse walls get the constant offset wall_kd; with tau_R infinite no
+// bulk steady state exists and the per-step forcing force_a/force_d is used.
 //
 // Element address of direction i at node (x, y):
 //     off + y * row + (x >> cshift) * chunk + (x & cmask) + i * plane
@@ -37,13 +44,17 @@ struct alignas(64) InstDesc {
     int64_t node_off;       // offset of this instance in node-indexed arrays (snapshot)
     float inv_tau;          // 1 / tau: decay of the non-equilibrium share per step
     float sigma;            // 1 - rho = 2 / (2 tau_r + 1): decay of the flux share per step
-    float pad0;
-    float grad_term;        // C_V * grad / s  (times omega_i c_ix after the pull)
+    float force_a;          // per-step forcing c_ix * force_{a,d} (gradient with tau_R = inf)
+    float force_d;
     float wall_g[4];        // C_V (T_wall - T_ref) / s for isothermal walls (times omega_i)
+    float wall_kd;          // diffuse-wall offset p_diag / s of the leaving diagonal populations
+    int32_t has_force;      // force_a/force_d nonzero
     double s_cv;            // s / C_V   (dT = s E / C_V)
-    double s_beta;          // s * beta  (q = s beta j)
+    double s_beta;          // s * beta  (q = q_ref + s beta j)
     double s;               // storage scale
     double cv;
+    double q_ref;           // heat flux (x) of the reference state
+    double p_axis, p_diag;  // reference shares p_i (energy density units)
 };
 static_assert(sizeof(InstDesc) == 192, "descriptor layout");
 

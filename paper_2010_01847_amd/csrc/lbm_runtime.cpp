@@ -288,19 +288,66 @@ static int upload_tables(lbm_ctx* h) {
     return LBM_OK;
 }
 
+// Reference state of the stored deviations (see InstDesc): with the gradient
+// seam, the bulk steady state of the imposed gradient G.  Per step the ramp
+// feeds the flux share j_b = (5/9) C_V G (the first moment of
+// omega_i C_V G c_ix), the relaxation multiplies the flux by rho and the rest
+// by 1 - 1/tau, so the steady post-relaxation flux is J = rho j_b / (1 - rho)
+// = j_b (tau_r - 1/2) and the steady non-equilibrium share is (tau - 1) times
+// that of the ramp vector, (1/27, -1/54) C_V G c_ix for axis / diagonal
+// directions.  The pre-relaxation reference is then
+//     R_i = omega_i C_V T_ref(x) + c_ix p_i,
+//     p_axis = J/3 + (2/9) C_V G + (tau - 1) C_V G / 27,
+//     p_diag = J/12 + C_V G / 36 - (tau - 1) C_V G / 54,
+// whose heat flux beta (J + j_b) is Fourier's (5/9) C_V G tau_r.  With tau_R
+// infinite the flux grows without bound (no steady state): the reference is
+// then the ramp alone and each step adds the relaxed ramp vector as forcing.
+struct Reference {
+    double p_axis = 0.0, p_diag = 0.0, q_ref = 0.0, force_a = 0.0, force_d = 0.0;
+    bool force = false;
+};
+
+static Reference reference_of(const lbm_instance& in, const Coeffs& c) {
+    Reference r;
+    if (in.bc_x != LBM_BC_GRADIENT || in.grad_x == 0.0) return r;
+    const double Gp = in.cv * in.grad_x;
+    const double jb = 5.0 / 9.0 * Gp;
+    if (std::isinf(in.tau_r)) {
+        r.p_axis = 2.0 / 9.0 * Gp;
+        r.p_diag = Gp / 36.0;
+        r.q_ref = jb;
+        r.force = true;
+        r.force_a = (2.0 / 9.0 - 1.0 / (27.0 * c.tau)) * Gp;
+        r.force_d = (1.0 / 36.0 + 1.0 / (54.0 * c.tau)) * Gp;
+        return r;
+    }
+    const double J = jb * (in.tau_r - 0.5);
+    r.p_axis = J / 3.0 + 2.0 / 9.0 * Gp + (c.tau - 1.0) * Gp / 27.0;
+    r.p_diag = J / 12.0 + Gp / 36.0 - (c.tau - 1.0) * Gp / 54.0;
+    r.q_ref = c.beta * (J + jb);
+    return r;
+}
+
 // Kernel coefficients of instance k for the effective storage scale s.
 static void fill_desc(lbm_ctx* h, size_t k, double s) {
     const lbm_instance& in = h->inst[k];
     const Coeffs& c = h->co[k];
     InstDesc& d = h->desc[k];
+    const Reference r = reference_of(in, c);
     d.inv_tau = (float)(1.0 / c.tau);
     d.sigma = (float)c.one_minus_rho;
-    d.grad_term = in.bc_x == LBM_BC_GRADIENT ? (float)(in.cv * in.grad_x / s) : 0.0f;
+    d.has_force = r.force ? 1 : 0;
+    d.force_a = (float)(r.force_a / s);
+    d.force_d = (float)(r.force_d / s);
+    d.wall_kd = (float)(r.p_diag / s);
     for (int w = 0; w < 4; ++w) d.wall_g[w] = (float)(in.cv * (in.t_wall[w] - in.t0) / s);
     d.s = s;
     d.cv = in.cv;
     d.s_cv = s / in.cv;
     d.s_beta = s * c.beta;
+    d.q_ref = r.q_ref;
+    d.p_axis = r.p_axis;
+    d.p_diag = r.p_diag;
 }
 
 // ------------------------------------------------------------------ C ABI
