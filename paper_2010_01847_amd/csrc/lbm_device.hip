@@ -10,14 +10,15 @@
 // goals are coalesced, wide HBM accesses and enough bytes in flight.
 //
 // Stored quantity: g_i = (e_i - R_i(x)) / s, the deviation from a reference
-// state R that one step (advection, then relaxation) maps exactly onto itself:
-// a uniform equilibrium, or with the gradient seam of Eqs. 59-60 the bulk
-// steady state of the imposed gradient (the ramp T_ref = t0 - G x with
-// Fourier's heat flux and its constant non-equilibrium share).  The scheme is
-// affine in e, so the update of g is the bare relaxation with plain periodic
-// wrap (the seam disappears), and the stored values are the small departures
-// from that state, which is what keeps FP32 steady states accurate when
-// tau_R is large.
+// state R (RefState) that one step (advection, then relaxation) maps onto
+// itself up to a uniform forcing: the ramp T_ref = t0 - G x of the gradient
+// seam of Eqs. 59-60 (G = 0 without it) with a uniform x-flux J and the
+// non-equilibrium share that the ramp sustains.  The scheme is affine in e,
+// so the update of g is the bare relaxation with plain periodic wrap (the
+// seam disappears) plus that forcing.  J follows the lattice's mean flux
+// (updated at check steps), so the stored values are the small departures
+// from the current state's own bulk part, which is what keeps FP32 accurate
+// when tau_R is large, in transients and at steady state.
 //
 // Layout (see InstDesc): either eight direction planes of ny rows each, x
 // contiguous, or "chunked": each 64-node row segment stores its eight
@@ -140,25 +141,53 @@ __device__ __forceinline__ void relax_parts(const float g[8], float eqf[8], floa
     for (int i = 0; i < 8; ++i) eqf[i] = (i < 4 ? ea : ed) + fl[i];
 }
 
+// x component of velocity i (directions 0..7 are the paper's 1..8 of Eq. 14).
+__device__ __forceinline__ constexpr int vel_x(int i) {
+    return (i == 0 || i == 4 || i == 7) ? 1 : ((i == 2 || i == 5 || i == 6) ? -1 : 0);
+}
+
+// c_ix times a per-class value (axis / diagonal); a compile-time select once
+// the direction loop is unrolled, so directions with c_ix = 0 get an exact 0.
+__device__ __forceinline__ float cx_times(int i, float va, float vd) {
+    const float v = i < 4 ? va : vd;
+    return vel_x(i) > 0 ? v : (vel_x(i) < 0 ? -v : 0.0f);
+}
+
+// Reference-state values a kernel needs per instance (see RefState).
+struct RefView {
+    float force_a, force_d, shift_a, shift_d, wall_kd;
+};
+__device__ __forceinline__ RefView ref_view(const RefState& r) {
+    return RefView{r.force_a, r.force_d, r.shift_a, r.shift_d, r.wall_kd};
+}
+
 // Per-step change of population i: -(1/tau) h_i - (1 - rho) f_i plus the
-// forcing of the reference state (nonzero only for a gradient with tau_R
-// infinite), formed at the size of the change itself and added to g once.
-__device__ __forceinline__ void relax_delta(const float g[8], const InstDesc& d, float delta[8]) {
+// reference state's forcing, formed at the size of the change itself and
+// added to g once.
+__device__ __forceinline__ void relax_delta(const float g[8], const InstDesc& d, const RefView& rv,
+                                            float delta[8]) {
     float eqf[8], fl[8];
     relax_parts(g, eqf, fl);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const float cx = (float)(i == 0 || i == 4 || i == 7) - (float)(i == 2 || i == 5 || i == 6);
-        const float force = d.has_force ? cx * (i < 4 ? d.force_a : d.force_d) : 0.0f;
+        const float force = cx_times(i, rv.force_a, rv.force_d);
         delta[i] = __builtin_fmaf(-d.sigma, fl[i], __builtin_fmaf(-d.inv_tau, g[i] - eqf[i], force));
     }
 }
 
-__device__ __forceinline__ void relax(float g[8], const InstDesc& d) {
+__device__ __forceinline__ void relax(float g[8], const InstDesc& d, const RefView& rv) {
     float delta[8];
-    relax_delta(g, d, delta);
+    relax_delta(g, d, rv, delta);
 #pragma unroll
     for (int i = 0; i < 8; ++i) g[i] = g[i] + delta[i];
+}
+
+// Pending change of reference flux: the pulled values are re-expressed
+// against the new reference (a uniform c_ix w_i (J_old - J_new) / s).
+__device__ __forceinline__ void apply_shift(float g[8], const RefView& rv) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        if (vel_x(i) != 0) g[i] = g[i] + cx_times(i, rv.shift_a, rv.shift_d);
 }
 
 // ------------------------------------------------------------------ stochastic rounding
@@ -224,22 +253,22 @@ __device__ __forceinline__ bf16_bits sr_bf16(float v, uint32_t r16) {
 // Relaxation with stochastic rounding of the stored result (FP32 storage):
 // the change is added to g_i with sr_add_f32.  16-bit storage narrows the
 // round-to-nearest FP32 result of relax() stochastically instead.
-__device__ __forceinline__ void relax_sr_f32(const float g[8], const InstDesc& d, const uint32_t r[4],
-                                             float out[8]) {
+__device__ __forceinline__ void relax_sr_f32(const float g[8], const InstDesc& d, const RefView& rv,
+                                             const uint32_t r[4], float out[8]) {
     float delta[8];
-    relax_delta(g, d, delta);
+    relax_delta(g, d, rv, delta);
 #pragma unroll
     for (int i = 0; i < 8; ++i) out[i] = sr_add_f32(g[i], delta[i], bits16(r, i));
 }
 
 // Boundary treatment after advection (Sec. 2.5) on one node, given its
-// position.  Directions 0..7 are the paper's 1..8.  Written with selects only:
+// position and the reference's diagonal offset kd = p_diag / s.  Directions 0..7 are the paper's 1..8.  Written with selects only:
 // every write has a fixed index, so the eight values stay in registers.
 //   diffuse (Eq. 58): the three populations leaving a wall get 4/5, 1/10, 1/10
 //     (omega_i over the sum of the leaving omegas) of the incident sum S; the
 //     axis share is formed as S - 2 (S/10) so the three add up to S;
 //   isothermal (Eq. 55): all eight take omega_i C_V (T_s - T_ref) / s.
-__device__ __forceinline__ void boundary(float g[8], const InstDesc& d, int x, int y) {
+__device__ __forceinline__ void boundary(float g[8], const InstDesc& d, float kd, int x, int y) {
     if (d.bc_y == 2) {
         const bool lo = (y == 0), hi = (y == d.ny - 1);
         const float Sl = g[3] + g[6] + g[7];      // incident at y = 0: 4, 7, 8
@@ -248,7 +277,7 @@ __device__ __forceinline__ void boundary(float g[8], const InstDesc& d, int x, i
         const float al = Sl - dl - dl, ah = Sh - dh - dh;
         // the reference state's diagonal shares (c_ix p_diag) are not part of
         // the reflected energy: the leaving diagonals carry -c_ix p_diag / s
-        const float k = d.wall_kd;
+        const float k = kd;
         g[1] = lo ? al : g[1];  g[4] = lo ? dl - k : g[4];  g[5] = lo ? dl + k : g[5];
         g[3] = hi ? ah : g[3];  g[6] = hi ? dh + k : g[6];  g[7] = hi ? dh - k : g[7];
     } else if (d.bc_y == 1) {
@@ -366,7 +395,10 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t sna
     }
     t += a.tile_base;
     if (t == 0 && threadIdx.x == 0 && threadIdx.y == 0) a.ctr_out[0] = a.ctr_in[0] + 1u;
-    const InstDesc& d = a.desc[a.tile_inst[t]];
+    const int inst = a.tile_inst[t];
+    const InstDesc& d = a.desc[inst];
+    const RefState& ref = a.ref[inst];
+    const RefView rv = ref_view(ref);
     const int local = t - d.tile_begin;
     const int ty = local / d.tiles_x;
     const int tx = local - ty * d.tiles_x;
@@ -406,11 +438,15 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t sna
 #pragma unroll
             for (int k = 0; k < V; ++k) g[k][i] = v[k];
         }
+        if (a.apply_shift) {
+#pragma unroll
+            for (int k = 0; k < V; ++k) apply_shift(g[k], rv);
+        }
         const bool edge_y = (d.bc_y != 0) && (y == 0 || y == ny - 1);
         const bool edge_x = (d.bc_x == 1 || d.bc_x == 2) && (x0 == 0 || x0 + V > nx - 1);
 #pragma unroll
         for (int k = 0; k < V; ++k) {
-            if (edge_y || edge_x) boundary(g[k], d, x0 + k, y);
+            if (edge_y || edge_x) boundary(g[k], d, rv.wall_kd, x0 + k, y);
         }
         if (MODE != kPlain) {
             const int64_t nbase = d.node_off + (int64_t)y * nx;
@@ -424,7 +460,7 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t sna
                    + ((double)g[k][7] - (double)g[k][5]);
                 jy = ((double)g[k][1] - (double)g[k][3]) + ((double)g[k][4] - (double)g[k][6])
                    + ((double)g[k][5] - (double)g[k][7]);
-                const double dT = d.s_cv * E, qx = d.q_ref + d.s_beta * jx, qy = d.s_beta * jy;
+                const double dT = d.s_cv * E, qx = ref.q_ref + d.s_beta * jx, qy = d.s_beta * jy;
                 const int64_t n = nbase + x0 + k;
                 if (MODE == kSnap) {
                     a.snap[n] = dT;
@@ -442,7 +478,7 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t sna
             }
         }
 #pragma unroll
-        for (int k = 0; k < V; ++k) relax(g[k], d);
+        for (int k = 0; k < V; ++k) relax(g[k], d, rv);
         // a V-aligned run never crosses a 64-node chunk
         S* out = dst + rows[0] + xo;
 #pragma unroll
@@ -478,7 +514,9 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
         t = k * q + (k < r ? k : r) + j;
     }
     t += a.tile_base;
-    const InstDesc& d = a.desc[a.tile_inst[t]];
+    const int inst = a.tile_inst[t];
+    const InstDesc& d = a.desc[inst];
+    const RefState& ref = a.ref[inst];
     const int local = t - d.tile_begin;
     const int ty = local / d.tiles_x;
     const int tx = local - ty * d.tiles_x;
@@ -499,6 +537,7 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
 
     double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (wave_live && x < nx) {
+        const RefView rv = ref_view(ref);
         const int ym = (y == 0) ? ny - 1 : y - 1;
         const int yp = (y == ny - 1) ? 0 : y + 1;
         // wave-uniform row bases; per-lane 32-bit byte offsets within a row
@@ -522,9 +561,10 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
             const char* base = rows[src_row(i)] + i * pb;
             g[i] = Cvt<S>::ld(*reinterpret_cast<const S*>(base + (dx < 0 ? cm : (dx > 0 ? cp : c0))));
         }
+        if (a.apply_shift) apply_shift(g, rv);
         const bool edge_y = (d.bc_y != 0) && (y == 0 || y == ny - 1);
         const bool edge_x = (d.bc_x == 1 || d.bc_x == 2) && (xc == 0 || xc + 64 >= nx);
-        if (edge_y || edge_x) boundary(g, d, x, y);
+        if (edge_y || edge_x) boundary(g, d, rv.wall_kd, x, y);
         if (MODE != kPlain) {
             double E = 0.0;
 #pragma unroll
@@ -533,7 +573,7 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
                             + ((double)g[7] - (double)g[5]);
             const double jy = ((double)g[1] - (double)g[3]) + ((double)g[4] - (double)g[6])
                             + ((double)g[5] - (double)g[7]);
-            const double dT = d.s_cv * E, qx = d.q_ref + d.s_beta * jx, qy = d.s_beta * jy;
+            const double dT = d.s_cv * E, qx = ref.q_ref + d.s_beta * jx, qy = d.s_beta * jy;
             const int64_t n = d.node_off + (int64_t)y * nx + x;
             if (MODE == kSnap) {
                 a.snap[n] = dT;
@@ -558,11 +598,11 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
             for (int k = 0; k < 4; ++k) r[k] = mix32(node ^ mix32(step * 4u + (uint32_t)k + a.seed * 0x9e3779b9u));
             if (sizeof(S) == 4) {
                 float o[8];
-                relax_sr_f32(g, d, r, o);
+                relax_sr_f32(g, d, rv, r, o);
 #pragma unroll
                 for (int i = 0; i < 8; ++i) store_run<S, 1>(reinterpret_cast<S*>(out + i * pb + c0), &o[i], nontemporal);
             } else {
-                relax(g, d);
+                relax(g, d, rv);
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     S v;
@@ -577,7 +617,7 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
                 }
             }
         } else {
-            relax(g, d);
+            relax(g, d, rv);
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 store_run<S, 1>(reinterpret_cast<S*>(out + i * pb + c0), &g[i], nontemporal);
@@ -646,11 +686,14 @@ hipError_t launch_step(int storage, const Shape& sh, int mode, const StepArgs& a
 
 // One node per thread, 256 threads along x, one row per block row.
 template <class S>
-__global__ __launch_bounds__(256) void moments_kernel(const InstDesc* __restrict__ descs, int inst,
-                                                      const void* buf, int pull, int out_kind,
-                                                      void* T, void* qx, void* qy, double t0,
-                                                      double grad, double* partials) {
+__global__ __launch_bounds__(256) void moments_kernel(const InstDesc* __restrict__ descs,
+                                                      const RefState* __restrict__ refs, int inst,
+                                                      const void* buf, int pull, int pending_shift,
+                                                      int out_kind, void* T, void* qx, void* qy,
+                                                      double t0, double grad, double* partials) {
     const InstDesc& d = descs[inst];
+    const RefState& ref = refs[inst];
+    const RefView rv = ref_view(ref);
     const int x = blockIdx.x * 256 + threadIdx.x;
     const int y = blockIdx.y;
     const int nx = d.nx, ny = d.ny;
@@ -667,7 +710,8 @@ __global__ __launch_bounds__(256) void moments_kernel(const InstDesc* __restrict
                 const int xs = wrapx(x + src_dx(i), nx);
                 g[i] = Cvt<S>::ld(src[(int64_t)i * d.plane + (int64_t)rows[src_row(i)] * d.row + col_off(d, xs)]);
             }
-                boundary(g, d, x, y);
+            if (pending_shift) apply_shift(g, rv);
+            boundary(g, d, rv.wall_kd, x, y);
         } else {
 #pragma unroll
             for (int i = 0; i < 8; ++i)
@@ -680,7 +724,7 @@ __global__ __launch_bounds__(256) void moments_kernel(const InstDesc* __restrict
                         + ((double)g[7] - (double)g[5]);
         const double jy = ((double)g[1] - (double)g[3]) + ((double)g[4] - (double)g[6])
                         + ((double)g[5] - (double)g[7]);
-        const double dT = d.s_cv * E, vx = d.q_ref + d.s_beta * jx, vy = d.s_beta * jy;
+        const double dT = d.s_cv * E, vx = ref.q_ref + d.s_beta * jx, vy = d.s_beta * jy;
         const int64_t n = (int64_t)y * nx + x;
         if (out_kind == 0) {
             const double tref = t0 - grad * (double)x;
@@ -699,17 +743,18 @@ __global__ __launch_bounds__(256) void moments_kernel(const InstDesc* __restrict
     if (partials) block_partials(acc, partials + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kPartials);
 }
 
-hipError_t launch_moments(int storage, const InstDesc* d_desc, int inst, const InstDesc& h,
-                          const void* buf, int pull, int out_kind, void* T, void* qx, void* qy,
-                          double t0, double grad, double* partials, hipStream_t st) {
+hipError_t launch_moments(int storage, const InstDesc* d_desc, const RefState* d_ref, int inst,
+                          const InstDesc& h, const void* buf, int pull, int pending_shift, int out_kind,
+                          void* T, void* qx, void* qy, double t0, double grad, double* partials,
+                          hipStream_t st) {
     dim3 grid((h.nx + 255) / 256, h.ny), block(256);
     switch (storage) {
-        case 0: hipLaunchKernelGGL(moments_kernel<float>, grid, block, 0, st, d_desc, inst, buf, pull,
-                                   out_kind, T, qx, qy, t0, grad, partials); break;
-        case 1: hipLaunchKernelGGL(moments_kernel<_Float16>, grid, block, 0, st, d_desc, inst, buf, pull,
-                                   out_kind, T, qx, qy, t0, grad, partials); break;
-        case 2: hipLaunchKernelGGL(moments_kernel<bf16_bits>, grid, block, 0, st, d_desc, inst, buf, pull,
-                                   out_kind, T, qx, qy, t0, grad, partials); break;
+        case 0: hipLaunchKernelGGL(moments_kernel<float>, grid, block, 0, st, d_desc, d_ref, inst, buf, pull,
+                                   pending_shift, out_kind, T, qx, qy, t0, grad, partials); break;
+        case 1: hipLaunchKernelGGL(moments_kernel<_Float16>, grid, block, 0, st, d_desc, d_ref, inst, buf,
+                                   pull, pending_shift, out_kind, T, qx, qy, t0, grad, partials); break;
+        case 2: hipLaunchKernelGGL(moments_kernel<bf16_bits>, grid, block, 0, st, d_desc, d_ref, inst, buf,
+                                   pull, pending_shift, out_kind, T, qx, qy, t0, grad, partials); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -721,12 +766,15 @@ hipError_t launch_moments(int storage, const InstDesc* d_desc, int inst, const I
 // nodes at their Eq. 55 equilibrium), stored rounded to `pre`; its relaxation,
 // computed from the rounded values exactly as a step would, goes to `post`.
 template <class S>
-__global__ __launch_bounds__(256) void init_kernel(const InstDesc* __restrict__ descs, int inst,
+__global__ __launch_bounds__(256) void init_kernel(const InstDesc* __restrict__ descs,
+                                                   const RefState* __restrict__ refs, int inst,
                                                    void* pre, void* post, const double* __restrict__ T,
                                                    const double* __restrict__ qx,
                                                    const double* __restrict__ qy, double t0,
                                                    double grad, double beta) {
     const InstDesc& d = descs[inst];
+    const RefState& ref = refs[inst];
+    const RefView rv = ref_view(ref);
     const int x = blockIdx.x * 256 + threadIdx.x;
     const int y = blockIdx.y;
     if (x >= d.nx) return;
@@ -736,7 +784,7 @@ __global__ __launch_bounds__(256) void init_kernel(const InstDesc* __restrict__ 
     const double inv_s = 1.0 / d.s;
     const double ea = (2.0 / 9.0) * d.cv * dT, ed = (1.0 / 36.0) * d.cv * dT;
     // minus the reference state's shares c_ix p_i
-    const double pa = d.p_axis, pd = d.p_diag;
+    const double pa = ref.p_axis, pd = ref.p_diag;
     float g[8];
     g[0] = (float)((ea + jx / 3.0 - pa) * inv_s);
     g[1] = (float)((ea + jy / 3.0) * inv_s);
@@ -748,7 +796,7 @@ __global__ __launch_bounds__(256) void init_kernel(const InstDesc* __restrict__ 
     g[7] = (float)((ed + (jx - jy) / 12.0 - pd) * inv_s);
     const bool wall = (d.bc_x == 1 && (x == 0 || x == d.nx - 1)) ||
                       (d.bc_y == 1 && (y == 0 || y == d.ny - 1));
-    if (wall) boundary(g, d, x, y);
+    if (wall) boundary(g, d, rv.wall_kd, x, y);
     S* p = reinterpret_cast<S*>(pre) + d.off + (int64_t)y * d.row + col_off(d, x);
     S* q = reinterpret_cast<S*>(post) + d.off + (int64_t)y * d.row + col_off(d, x);
 #pragma unroll
@@ -757,22 +805,22 @@ __global__ __launch_bounds__(256) void init_kernel(const InstDesc* __restrict__ 
         p[(int64_t)i * d.plane] = v;
         g[i] = Cvt<S>::ld(v);
     }
-    relax(g, d);
+    relax(g, d, rv);
 #pragma unroll
     for (int i = 0; i < 8; ++i) q[(int64_t)i * d.plane] = Cvt<S>::st(g[i]);
 }
 
-hipError_t launch_init(int storage, const InstDesc* d_desc, int inst, const InstDesc& h, void* pre,
-                       void* post, const double* T, const double* qx, const double* qy, double t0,
-                       double grad, double beta, hipStream_t st) {
+hipError_t launch_init(int storage, const InstDesc* d_desc, const RefState* d_ref, int inst,
+                       const InstDesc& h, void* pre, void* post, const double* T, const double* qx,
+                       const double* qy, double t0, double grad, double beta, hipStream_t st) {
     dim3 grid((h.nx + 255) / 256, h.ny), block(256);
     switch (storage) {
-        case 0: hipLaunchKernelGGL(init_kernel<float>, grid, block, 0, st, d_desc, inst, pre, post, T, qx,
-                                   qy, t0, grad, beta); break;
-        case 1: hipLaunchKernelGGL(init_kernel<_Float16>, grid, block, 0, st, d_desc, inst, pre, post, T,
+        case 0: hipLaunchKernelGGL(init_kernel<float>, grid, block, 0, st, d_desc, d_ref, inst, pre, post, T,
                                    qx, qy, t0, grad, beta); break;
-        case 2: hipLaunchKernelGGL(init_kernel<bf16_bits>, grid, block, 0, st, d_desc, inst, pre, post, T,
-                                   qx, qy, t0, grad, beta); break;
+        case 1: hipLaunchKernelGGL(init_kernel<_Float16>, grid, block, 0, st, d_desc, d_ref, inst, pre, post,
+                                   T, qx, qy, t0, grad, beta); break;
+        case 2: hipLaunchKernelGGL(init_kernel<bf16_bits>, grid, block, 0, st, d_desc, d_ref, inst, pre, post,
+                                   T, qx, qy, t0, grad, beta); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -804,11 +852,32 @@ __device__ void reduce_records(const double* __restrict__ partials, int64_t firs
         for (int c = 0; c < kPartials; ++c) out[c] = red[0][c];
 }
 
+// Per instance: the check-step totals, then (adaptive instances) the move of
+// the reference flux to the mean flux of the state just checked.  The shift
+// is rounded to FP32 first and J is moved by the rounded amount (in FP64), so
+// J and the stored populations stay consistent; shift_d = shift_a / 4 is
+// exact.
 __global__ __launch_bounds__(256) void finalize_kernel(const InstDesc* __restrict__ descs,
+                                                       RefState* __restrict__ refs,
                                                        const double* __restrict__ partials,
                                                        double* __restrict__ results) {
     const InstDesc& d = descs[blockIdx.x];
-    reduce_records(partials, d.tile_begin, d.ntiles, results + (int64_t)blockIdx.x * kPartials);
+    double* out = results + (int64_t)blockIdx.x * kPartials;
+    reduce_records(partials, d.tile_begin, d.ntiles, out);
+    if (threadIdx.x != 0) return;
+    RefState& r = refs[blockIdx.x];
+    if (!r.adapt) return;
+    // mean heat flux = beta (mean first moment); reference's first moment J + j_b
+    const double target = out[1] * r.inv_nodes / r.beta - r.jb;
+    float sa = 0.0f;
+    double J = r.J;
+    if (isfinite(target)) {
+        sa = (float)((r.J - target) / (3.0 * r.s));
+        J = r.J - 3.0 * r.s * (double)sa;
+    }
+    r.shift_a = sa;
+    r.shift_d = 0.25f * sa;
+    ref_set_flux(r, J);
 }
 
 __global__ __launch_bounds__(256) void finalize_range_kernel(const double* __restrict__ partials,
@@ -816,9 +885,9 @@ __global__ __launch_bounds__(256) void finalize_range_kernel(const double* __res
     reduce_records(partials, 0, count, out);
 }
 
-hipError_t launch_finalize(const InstDesc* d_desc, int ninst, const double* partials, double* results,
-                           hipStream_t st) {
-    hipLaunchKernelGGL(finalize_kernel, dim3(ninst), dim3(256), 0, st, d_desc, partials, results);
+hipError_t launch_finalize(const InstDesc* d_desc, RefState* d_ref, int ninst, const double* partials,
+                           double* results, hipStream_t st) {
+    hipLaunchKernelGGL(finalize_kernel, dim3(ninst), dim3(256), 0, st, d_desc, d_ref, partials, results);
     return hipGetLastError();
 }
 

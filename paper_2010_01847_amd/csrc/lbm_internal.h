@@ -12,14 +12,6 @@ constexpr int kMaxBlock = 512;     // threads per block upper bound (launch boun
 constexpr int kPartials = 5;       // per-tile FP64 partials: sum dE, sum qx, sum qy, |dm|^2, |m|^2
 
 // Per-instance descriptor, resident in device memory (one 192-byte record).
-// Stored quantity: g_i = (e_i - R_i(x)) / s, the deviation from a reference
-// state R that one step maps exactly onto itself (advection then relaxation):
-//   R_i(x) = omega_i C_V T_ref(x) + c_ix p_i,   T_ref = t0 - grad * x,
-// where p_i (one value for axis, one for diagonal directions) is the flux and
-// non-equilibrium share of the bulk steady state under the imposed gradient
-// (zero without a gradient).  The interior update is then the bare relaxation
-// of g; diffuse walls get the constant offset wall_kd; with tau_R infinite no
-// bulk steady state exists and the per-step forcing force_a/force_d is used.
 //
 // Element address of direction i at node (x, y):
 //     off + y * row + (x >> cshift) * chunk + (x & cmask) + i * plane
@@ -44,19 +36,59 @@ struct alignas(64) InstDesc {
     int64_t node_off;       // offset of this instance in node-indexed arrays (snapshot)
     float inv_tau;          // 1 / tau: decay of the non-equilibrium share per step
     float sigma;            // 1 - rho = 2 / (2 tau_r + 1): decay of the flux share per step
-    float force_a;          // per-step forcing c_ix * force_{a,d} (gradient with tau_R = inf)
-    float force_d;
     float wall_g[4];        // C_V (T_wall - T_ref) / s for isothermal walls (times omega_i)
-    float wall_kd;          // diffuse-wall offset p_diag / s of the leaving diagonal populations
-    int32_t has_force;      // force_a/force_d nonzero
     double s_cv;            // s / C_V   (dT = s E / C_V)
     double s_beta;          // s * beta  (q = q_ref + s beta j)
     double s;               // storage scale
     double cv;
-    double q_ref;           // heat flux (x) of the reference state
-    double p_axis, p_diag;  // reference shares p_i (energy density units)
 };
 static_assert(sizeof(InstDesc) == 192, "descriptor layout");
+
+// Reference state of the stored deviations, one per instance, in device
+// memory (kept apart from InstDesc: the device updates it, the host does not
+// rewrite it when the launch shape changes).  Stored quantity:
+// g_i = (e_i - R_i(x)) / s before relaxation, with
+//     R_i(x) = omega_i C_V T_ref(x) + c_ix p_i,   T_ref = t0 - G x,
+//     p_axis = J/3 + pa0,   pa0 = (2/9) C_V G + (tau - 1) C_V G / 27,
+//     p_diag = J/12 + pd0,  pd0 = C_V G / 36 - (tau - 1) C_V G / 54,
+// (G = 0 without the gradient seam).  sum_i c_ix R_i = J + j_b with
+// j_b = (5/9) C_V G, and J is the x-flux of R after relaxation.  One step
+// (advection across the seam of Eqs. 59-60, relaxation of Eqs. 13, 15, 16)
+// maps R onto itself plus the uniform forcing c_ix w_i (rho (J + j_b) - J)
+// (w = 1/3 axis, 1/12 diagonal), which vanishes at the bulk steady state
+// J = j_b (tau_r - 1/2).  For an adaptive instance the finalisation kernel
+// moves J to the lattice's mean x-flux at every check step, which keeps the
+// stored values small in transients and at steady state alike; the stored
+// populations then change by the uniform c_ix w_i (J_old - J_new) / s
+// ("shift"), which the next step adds to its pulled values once.
+struct alignas(64) RefState {
+    double J;               // post-relaxation reference x-flux (energy units)
+    double q_ref;           // heat flux of R: beta (J + j_b)
+    double p_axis, p_diag;  // c_ix shares of R (energy units)
+    double jb, pa0, pd0;    // j_b and the J-independent parts of p
+    double rho, sigma;      // flux factor per step and 1 - rho (computed directly)
+    double beta, s;         // Eq. 54 factor; storage scale
+    double inv_nodes;       // 1 / (nx ny)
+    float force_a, force_d; // forcing per step / s, axis and diagonal (times c_ix)
+    float shift_a, shift_d; // pending shift / s (times c_ix); shift_d = shift_a / 4 exactly
+    float wall_kd;          // p_diag / s: offset of the diagonals leaving a diffuse y wall
+    int32_t adapt;          // 1: J follows the mean flux at check steps
+};
+static_assert(sizeof(RefState) == 128, "reference state layout");
+
+// Set the J-dependent fields of r for reference flux J (host at
+// initialisation, device at check steps).
+__host__ __device__ inline void ref_set_flux(RefState& r, double J) {
+    r.J = J;
+    r.q_ref = r.beta * (J + r.jb);
+    r.p_axis = J / 3.0 + r.pa0;
+    r.p_diag = J / 12.0 + r.pd0;
+    // rho (J + j_b) - J, with 1 - rho kept as its own (accurate) coefficient
+    const double f = r.rho * r.jb - r.sigma * J;
+    r.force_a = (float)(f / (3.0 * r.s));
+    r.force_d = (float)(f / (12.0 * r.s));
+    r.wall_kd = (float)(r.p_diag / r.s);
+}
 
 // Launch shape chosen by the runtime (or the autotuner).
 struct Shape {
@@ -79,6 +111,8 @@ struct StepArgs {
     double* partials;           // kPartials per global tile, CHECK
     int32_t tile_base;          // first global tile of this launch
     int32_t ntiles;             // tiles in this launch
+    const RefState* ref;        // per-instance reference states
+    int32_t apply_shift;        // 1: add the pending reference shift to the pulled values
     const uint32_t* ctr_in;     // steps completed before this step (device counter)
     uint32_t* ctr_out;          // written with ctr_in + 1 by the block of global tile 0
     uint32_t seed;              // stream of the stochastic-rounding bits
@@ -95,19 +129,22 @@ hipError_t launch_step(int storage, const Shape& sh, int mode, const StepArgs& a
 // boundary treatment), else read in place (time 0, pre-relaxation state).
 // out_kind: 0 = FP32 absolute T (+ q) ; 1 = FP64 deviation dT (+ q).
 // partials (may be null): kPartials per tile of this instance (block) for totals.
-hipError_t launch_moments(int storage, const InstDesc* d_desc, int inst, const InstDesc& h_desc,
-                          const void* buf, int pull, int out_kind, void* T, void* qx, void* qy,
-                          double t0, double grad, double* partials, hipStream_t st);
+hipError_t launch_moments(int storage, const InstDesc* d_desc, const RefState* d_ref, int inst,
+                          const InstDesc& h_desc, const void* buf, int pull, int pending_shift,
+                          int out_kind, void* T, void* qx, void* qy, double t0, double grad,
+                          double* partials, hipStream_t st);
 
 // Equilibrium initialisation: writes the pre-relaxation state to `pre` and its
 // relaxation to `post`.  T, qx, qy: device FP64 (qx, qy may be null).
-hipError_t launch_init(int storage, const InstDesc* d_desc, int inst, const InstDesc& h_desc,
-                       void* pre, void* post, const double* T, const double* qx,
-                       const double* qy, double t0, double grad, double beta, hipStream_t st);
+hipError_t launch_init(int storage, const InstDesc* d_desc, const RefState* d_ref, int inst,
+                       const InstDesc& h_desc, void* pre, void* post, const double* T,
+                       const double* qx, const double* qy, double t0, double grad, double beta,
+                       hipStream_t st);
 
 // Deterministic per-instance reduction of tile partials into results
 // (kPartials doubles per instance).  One block per instance.
-hipError_t launch_finalize(const InstDesc* d_desc, int ninst, const double* partials,
+// Also moves each adaptive instance's reference flux to its mean heat flux.
+hipError_t launch_finalize(const InstDesc* d_desc, RefState* d_ref, int ninst, const double* partials,
                            double* results, hipStream_t st);
 
 // Reduction of moments-kernel partials (tiles of 256 nodes) of one instance.

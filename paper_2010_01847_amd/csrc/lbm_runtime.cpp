@@ -159,7 +159,7 @@ struct Layout {
     size_t buf_bytes = 0;      // one population buffer
     size_t off_buf[2] = {0, 0};
     size_t off_snap = 0, off_part = 0, off_res = 0, off_mpart = 0, off_mres = 0, off_desc = 0,
-           off_tiles = 0, off_ctr = 0, total = 0;
+           off_ref = 0, off_tiles = 0, off_ctr = 0, total = 0;
     int64_t nodes = 0, tiles_max = 0, mparts_max = 0;
 };
 
@@ -183,6 +183,7 @@ Layout layout_of(const std::vector<lbm_instance>& v, int storage, int check, int
     L.off_mpart = o; o += align_up((size_t)L.mparts_max * kPartials * sizeof(double), kAlign);
     L.off_mres = o; o += align_up(kPartials * sizeof(double), kAlign);
     L.off_desc = o; o += align_up(v.size() * sizeof(InstDesc), kAlign);
+    L.off_ref = o; o += align_up(v.size() * sizeof(RefState), kAlign);
     L.off_tiles = o; o += align_up((size_t)L.tiles_max * sizeof(int32_t), kAlign);
     L.off_ctr = o; o += kAlign;                 // two 32-bit step counters (ping-pong)
     L.total = o;
@@ -203,6 +204,7 @@ struct lbm_ctx {
     int K = 100;                     // check interval, 0 = off
     std::vector<lbm_instance> inst;
     std::vector<InstDesc> desc;
+    std::vector<RefState> ref;       // initial reference states (the device copy evolves)
     std::vector<Coeffs> co;
     std::vector<char> inited;
     Shape shape;
@@ -226,6 +228,7 @@ struct lbm_ctx {
     char* ptr(size_t off) const { return base + off; }
     void* buf(int k) const { return base + L.off_buf[k]; }
     InstDesc* d_desc() const { return reinterpret_cast<InstDesc*>(base + L.off_desc); }
+    RefState* d_ref() const { return reinterpret_cast<RefState*>(base + L.off_ref); }
     int32_t* d_tiles() const { return reinterpret_cast<int32_t*>(base + L.off_tiles); }
     double* d_snap() const { return K ? reinterpret_cast<double*>(base + L.off_snap) : nullptr; }
     double* d_part() const { return reinterpret_cast<double*>(base + L.off_part); }
@@ -279,6 +282,9 @@ static void build_tiles(lbm_ctx* h) {
     }
 }
 
+// Descriptors and the tile table.  The reference states are not part of it:
+// the device moves them at check steps, and a launch-shape change must not
+// reset them (see upload_ref).
 static int upload_tables(lbm_ctx* h) {
     HIPCALL(h, hipMemcpyAsync(h->d_desc(), h->desc.data(), h->desc.size() * sizeof(InstDesc),
                               hipMemcpyHostToDevice, h->stream));
@@ -288,44 +294,36 @@ static int upload_tables(lbm_ctx* h) {
     return LBM_OK;
 }
 
-// Reference state of the stored deviations (see InstDesc): with the gradient
-// seam, the bulk steady state of the imposed gradient G.  Per step the ramp
-// feeds the flux share j_b = (5/9) C_V G (the first moment of
+// Reference state of instance k (see RefState).  Per step the ramp
+// T_ref = t0 - G x feeds the flux share j_b = (5/9) C_V G (the first moment of
 // omega_i C_V G c_ix), the relaxation multiplies the flux by rho and the rest
-// by 1 - 1/tau, so the steady post-relaxation flux is J = rho j_b / (1 - rho)
-// = j_b (tau_r - 1/2) and the steady non-equilibrium share is (tau - 1) times
-// that of the ramp vector, (1/27, -1/54) C_V G c_ix for axis / diagonal
-// directions.  The pre-relaxation reference is then
-//     R_i = omega_i C_V T_ref(x) + c_ix p_i,
-//     p_axis = J/3 + (2/9) C_V G + (tau - 1) C_V G / 27,
-//     p_diag = J/12 + C_V G / 36 - (tau - 1) C_V G / 54,
-// whose heat flux beta (J + j_b) is Fourier's (5/9) C_V G tau_r.  With tau_R
-// infinite the flux grows without bound (no steady state): the reference is
-// then the ramp alone and each step adds the relaxed ramp vector as forcing.
-struct Reference {
-    double p_axis = 0.0, p_diag = 0.0, q_ref = 0.0, force_a = 0.0, force_d = 0.0;
-    bool force = false;
-};
-
-static Reference reference_of(const lbm_instance& in, const Coeffs& c) {
-    Reference r;
-    if (in.bc_x != LBM_BC_GRADIENT || in.grad_x == 0.0) return r;
-    const double Gp = in.cv * in.grad_x;
-    const double jb = 5.0 / 9.0 * Gp;
-    if (std::isinf(in.tau_r)) {
-        r.p_axis = 2.0 / 9.0 * Gp;
-        r.p_diag = Gp / 36.0;
-        r.q_ref = jb;
-        r.force = true;
-        r.force_a = (2.0 / 9.0 - 1.0 / (27.0 * c.tau)) * Gp;
-        r.force_d = (1.0 / 36.0 + 1.0 / (54.0 * c.tau)) * Gp;
-        return r;
-    }
-    const double J = jb * (in.tau_r - 0.5);
-    r.p_axis = J / 3.0 + 2.0 / 9.0 * Gp + (c.tau - 1.0) * Gp / 27.0;
-    r.p_diag = J / 12.0 + Gp / 36.0 - (c.tau - 1.0) * Gp / 54.0;
-    r.q_ref = c.beta * (J + jb);
-    return r;
+// of the non-equilibrium part by 1 - 1/tau; the ramp then sustains the
+// non-equilibrium share (tau - 1) (1/27, -1/54) C_V G c_ix (axis / diagonal)
+// and the bulk steady flux J = rho j_b / (1 - rho) = j_b (tau_r - 1/2), whose
+// heat flux beta (J + j_b) is Fourier's (5/9) C_V G tau_r.
+//   adaptive (check steps on, x periodic or gradient seam, no isothermal
+//   y walls): J starts at -j_b (the reference carries no first moment, like
+//   a state initialised without heat flux) and follows the mean flux;
+//   otherwise J is the bulk steady flux (-j_b when tau_R is infinite: there
+//   is no steady state, and the forcing j_b is the ramp's whole feed).
+static void ref_init(lbm_ctx* h, size_t k, double s) {
+    const lbm_instance& in = h->inst[k];
+    const Coeffs& c = h->co[k];
+    RefState& r = h->ref[k];
+    std::memset(&r, 0, sizeof r);
+    const double Gp = in.bc_x == LBM_BC_GRADIENT ? in.cv * in.grad_x : 0.0;
+    r.jb = 5.0 / 9.0 * Gp;
+    r.pa0 = 2.0 / 9.0 * Gp + (c.tau - 1.0) * Gp / 27.0;
+    r.pd0 = Gp / 36.0 - (c.tau - 1.0) * Gp / 54.0;
+    r.rho = c.rho;
+    r.sigma = c.one_minus_rho;
+    r.beta = c.beta;
+    r.s = s;
+    r.inv_nodes = 1.0 / ((double)in.nx * (double)in.ny);
+    r.adapt = (h->K > 0 && (in.bc_x == LBM_BC_PERIODIC || in.bc_x == LBM_BC_GRADIENT) &&
+               in.bc_y != LBM_BC_ISOTHERMAL) ? 1 : 0;
+    const double J = (r.adapt || std::isinf(in.tau_r)) ? -r.jb : r.jb * (in.tau_r - 0.5);
+    ref_set_flux(r, J);
 }
 
 // Kernel coefficients of instance k for the effective storage scale s.
@@ -333,21 +331,24 @@ static void fill_desc(lbm_ctx* h, size_t k, double s) {
     const lbm_instance& in = h->inst[k];
     const Coeffs& c = h->co[k];
     InstDesc& d = h->desc[k];
-    const Reference r = reference_of(in, c);
     d.inv_tau = (float)(1.0 / c.tau);
     d.sigma = (float)c.one_minus_rho;
-    d.has_force = r.force ? 1 : 0;
-    d.force_a = (float)(r.force_a / s);
-    d.force_d = (float)(r.force_d / s);
-    d.wall_kd = (float)(r.p_diag / s);
     for (int w = 0; w < 4; ++w) d.wall_g[w] = (float)(in.cv * (in.t_wall[w] - in.t0) / s);
     d.s = s;
     d.cv = in.cv;
     d.s_cv = s / in.cv;
     d.s_beta = s * c.beta;
-    d.q_ref = r.q_ref;
-    d.p_axis = r.p_axis;
-    d.p_diag = r.p_diag;
+    ref_init(h, k, s);
+}
+
+// Reference state of instance k (k < 0: all) to the device.
+static int upload_ref(lbm_ctx* h, int k) {
+    const size_t first = k < 0 ? 0 : (size_t)k;
+    const size_t n = k < 0 ? h->ref.size() : 1;
+    HIPCALL(h, hipMemcpyAsync(h->d_ref() + first, h->ref.data() + first, n * sizeof(RefState),
+                              hipMemcpyHostToDevice, h->stream));
+    HIPCALL(h, hipStreamSynchronize(h->stream));
+    return LBM_OK;
 }
 
 // ------------------------------------------------------------------ C ABI
@@ -435,6 +436,7 @@ int lbm_create(const lbm_config* cfg, lbm_handle* out) {
     h->layout = resolve_layout(cfg->layout);
     h->L = layout_of(v, h->storage, h->K, h->layout);
     h->desc.resize(v.size());
+    h->ref.resize(v.size());
     h->co.resize(v.size());
     h->inited.assign(v.size(), 0);
     size_t eoff = 0;
@@ -487,6 +489,7 @@ int lbm_create(const lbm_config* cfg, lbm_handle* out) {
         }
         h->owned = true;
         int rc = upload_tables(h);
+        if (!rc) rc = upload_ref(h, -1);
         if (rc) {
             g_create_error = h->err;
             (void)hipFree(h->base);
@@ -509,7 +512,8 @@ int lbm_bind(lbm_handle h, void* device_buf, size_t bytes) {
     if (reinterpret_cast<uintptr_t>(device_buf) % kAlign)
         return h->fail(LBM_EINVAL, "buffer must be 256-byte aligned");
     h->base = static_cast<char*>(device_buf);
-    return upload_tables(h);
+    const int rc = upload_tables(h);
+    return rc ? rc : upload_ref(h, -1);
 }
 
 void lbm_destroy(lbm_handle h) {
@@ -565,9 +569,11 @@ static int do_init(lbm_ctx* h, int32_t k, const double* dT, const double* dqx, c
     const InstDesc& d = h->desc[k];
     HIPCALL(h, hipMemcpyAsync(h->d_desc(), h->desc.data(), h->desc.size() * sizeof(InstDesc),
                               hipMemcpyHostToDevice, h->stream));
+    HIPCALL(h, hipMemcpyAsync(h->d_ref() + k, &h->ref[k], sizeof(RefState), hipMemcpyHostToDevice,
+                              h->stream));
     const double grad = in.bc_x == LBM_BC_GRADIENT ? in.grad_x : 0.0;
-    HIPCALL(h, launch_init(h->storage, h->d_desc(), k, d, h->buf(1 - h->cur), h->buf(h->cur), dT, dqx,
-                           dqy, in.t0, grad, h->co[k].beta, h->stream));
+    HIPCALL(h, launch_init(h->storage, h->d_desc(), h->d_ref(), k, d, h->buf(1 - h->cur), h->buf(h->cur),
+                           dT, dqx, dqy, in.t0, grad, h->co[k].beta, h->stream));
     HIPCALL(h, hipMemsetAsync(h->d_ctr(), 0, 2 * sizeof(uint32_t), h->stream));
     HIPCALL(h, hipStreamSynchronize(h->stream));
     if (h->steps != 0) {
@@ -656,6 +662,10 @@ static int issue_step(lbm_ctx* h, int64_t m, int src_k, hipStream_t st, int sche
     a.ctr_out = h->d_ctr() + (1 - src_k);
     a.seed = h->seed;
     a.sr = h->sr;
+    a.ref = h->d_ref();
+    // the step after a check step applies the reference shift that the check
+    // step's finalisation set (zero for non-adaptive instances and at n = 0)
+    a.apply_shift = (h->K > 0 && (m - 1) % h->K == 0) ? 1 : 0;
     if (sched == LBM_SCHED_PER_INSTANCE) {
         for (size_t k = 0; k < h->inst.size(); ++k) {
             a.tile_base = h->desc[k].tile_begin;
@@ -668,7 +678,7 @@ static int issue_step(lbm_ctx* h, int64_t m, int src_k, hipStream_t st, int sche
         HIPCALL(h, launch_step(h->storage, h->shape, mode, a, h->L.nodes, st));
     }
     if (mode == kCheck)
-        HIPCALL(h, launch_finalize(h->d_desc(), (int)h->inst.size(), h->d_part(), h->d_res(), st));
+        HIPCALL(h, launch_finalize(h->d_desc(), h->d_ref(), (int)h->inst.size(), h->d_part(), h->d_res(), st));
     return LBM_OK;
 }
 
@@ -740,8 +750,11 @@ int lbm_step(lbm_handle h, int64_t nsteps) {
 static int run_moments(lbm_ctx* h, int32_t k, int out_kind, void* T, void* qx, void* qy, double* partials) {
     const lbm_instance& in = h->inst[k];
     const double grad = in.bc_x == LBM_BC_GRADIENT ? in.grad_x : 0.0;
-    HIPCALL(h, launch_moments(h->storage, h->d_desc(), k, h->desc[k], h->buf(1 - h->cur), h->steps > 0 ? 1 : 0,
-                              out_kind, T, qx, qy, in.t0, grad, partials, h->stream));
+    // after a check step the reference has moved and its shift is still pending
+    const int pending = (h->K > 0 && h->steps > 0 && h->steps % h->K == 0) ? 1 : 0;
+    HIPCALL(h, launch_moments(h->storage, h->d_desc(), h->d_ref(), k, h->desc[k], h->buf(1 - h->cur),
+                              h->steps > 0 ? 1 : 0, pending, out_kind, T, qx, qy, in.t0, grad, partials,
+                              h->stream));
     return LBM_OK;
 }
 
@@ -949,6 +962,8 @@ static int time_shape(lbm_ctx* h, const Shape& s, int steps, hipEvent_t e0, hipE
     a.ntiles = (int32_t)h->ntiles;
     a.seed = h->seed;
     a.sr = h->sr;
+    a.ref = h->d_ref();
+    a.apply_shift = 0;
     int src = 0;
     for (int w = 0; w < 3 + steps; ++w) {
         if (w == 3) HIPCALL(h, hipEventRecord(e0, h->stream));

@@ -229,6 +229,7 @@ def test_batched_schedules_bitwise_and_parity():
                 for a, b in zip(outs[pre + sched][k], outs[pre + "batched"][k]):
                     assert np.array_equal(a, b), (pre + sched, k)
         e_t, e_q = eps(case, outs["sr_batched"][k], oracle_fields(case, 45))
+        log(f"batched SR inst {k}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
         assert e_q < 1e-5 and e_t < 1e-5, ("stochastic", k, e_t, e_q)
         e_t, e_q = eps(case, outs["batched"][k], oracle_fields(case, 45))
         log(f"batched inst {k} {case.nx}x{case.ny} tr={case.tau_r:.3g}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
