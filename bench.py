@@ -11,10 +11,13 @@ reductions.
 
 Prints one JSON line.  `value` is MLUPS (million lattice-node updates per
 second) of the timed steps, with the populations resident in HBM before the
-timed region starts.  Extra storage types (FP16 scaled, BF16) of the same
-workload are reported under "rows".  The oracle (plain FP64 C stepper) is
-timed on a bounded window of the same workload on the host cores
-("cpu_baseline").
+timed region starts.  Extra storage types (FP16 scaled, BF16; stochastic
+rounding of the stores, which keeps smooth fields from stalling) of the same
+workload are reported under "rows".  "sweep" reports the batched Knudsen
+sweep (256 uneven channel instances in one handle) under the three
+schedules: one launch for all instances, the same captured in HIP graphs,
+and one launch per instance.  The oracle (plain FP64 C stepper) is timed on
+a bounded window of the same workload on the host cores ("cpu_baseline").
 """
 from __future__ import annotations
 
@@ -28,7 +31,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
-BYTES_PER_NODE = {"f32": 64, "f16": 32, "bf16": 32}   # 8 reads + 8 writes per node
+# 8 population reads + 8 writes per node; split storage adds the FP32 energy
+BYTES_PER_NODE = {"f32": 64, "f16": 32, "bf16": 32, "f16_split": 40, "bf16_split": 40}
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2010_01847_amd", "csrc", "lbm_device.hip")
 PROFILES = os.path.join(ROOT, "profiles")
 
@@ -59,8 +63,13 @@ def _parse():
     p.add_argument("--steps", type=int, default=1000)
     p.add_argument("--warmup", type=int, default=50)
     p.add_argument("--n", type=int, default=8192, help="lattice side")
-    p.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
-    p.add_argument("--rows", default="f16,bf16", help="extra storage rows ('' for none)")
+    p.add_argument("--storage", default="f32", choices=list(BYTES_PER_NODE))
+    p.add_argument("--rows", default="f16:stochastic,bf16:stochastic,f16_split,bf16_split",
+                   help="extra rows, storage[:rounding] ('' for none)")
+    p.add_argument("--rounding", default=None, choices=["nearest", "stochastic"],
+                   help="rounding of the main row's stores (default: stochastic for plain 16-bit "
+                        "storage, which stalls on smooth fields otherwise; nearest for the rest)")
+    p.add_argument("--sweep-steps", type=int, default=300, help="timed steps per sweep schedule (0: skip)")
     p.add_argument("--check-interval", type=int, default=100)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -82,11 +91,11 @@ def _copy_probe(torch):
     del a, b
 
 
-def _run_gpu(args, storage, torch, P, W):
+def _run_gpu(args, storage, rounding, torch, P, W):
     case = W.second_sound_case(n=args.n)
-    scale = {"f32": 0.0, "bf16": 0.0, "f16": 2.0 ** -20}[storage]
+    scale = 2.0 ** -20 if storage.startswith("f16") else 0.0
     lat = P.Lattice([P.instance_from_case(case, scale)], storage=storage,
-                    check_interval=args.check_interval)
+                    check_interval=args.check_interval, rounding=rounding, seed=1847)
     tune = lat.autotune(10) if args.autotune else None
     T0 = torch.from_numpy(W.initial_field(case)).to("cuda")
     lat.init(0, T0)
@@ -111,8 +120,44 @@ def _run_gpu(args, storage, torch, P, W):
     info = lat.last_check(0) if 0 < args.check_interval <= done else None
     shape = lat.launch_shape()
     lat.close()
-    return dict(storage=storage, mlups=mlups, ms_per_step=ms / args.steps, gbs=gbs,
+    return dict(storage=storage, rounding=rounding, mlups=mlups, ms_per_step=ms / args.steps, gbs=gbs,
                 wall_s=wall, check=info, shape=shape, tune=tune)
+
+
+def _run_sweep(args, torch, P, W):
+    """Knudsen sweep: 256 channel instances (sides uniform in [64, 512],
+    tau_N uniform in [0.51, 1], tau_R log-uniform in [0.6, 1000], gradient
+    seam and diffuse walls), FP32, check steps every 100.  MLUPS of each
+    schedule over the same timed steps from the same initial state."""
+    cases = W.knudsen_sweep()
+    insts = [P.instance_from_case(c) for c in cases]
+    nodes = sum(c.nx * c.ny for c in cases)
+    out = {"instances": len(cases), "nodes": nodes, "steps": args.sweep_steps, "storage": "f32"}
+    for sched in ("graph", "batched", "per_instance"):
+        lat = P.Lattice(insts, check_interval=100)
+        lat.set_schedule(sched)
+        for k in range(len(cases)):
+            lat.init(k)
+        lat.step(100)                      # warm-up; captures the graphs
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(lat.stream)
+        lat.step(args.sweep_steps)
+        e1.record(lat.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        lat.close()
+        step_s = ms / 1e3 / args.sweep_steps
+        out[sched] = {"mlups": round(nodes / step_s / 1e6, 1), "ms_per_step": round(ms / args.sweep_steps, 4),
+                      "gbs": round(64 * nodes / step_s / 1e9, 1)}
+    out["batched_over_per_instance"] = round(out["batched"]["mlups"] / out["per_instance"]["mlups"], 2)
+    out["graph_over_per_instance"] = round(out["graph"]["mlups"] / out["per_instance"]["mlups"], 2)
+    return out
+
+
+def _default_rounding(storage):
+    return "stochastic" if storage in ("f16", "bf16") else "nearest"
 
 
 def _cpu_baseline(args, W):
@@ -146,10 +191,15 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_probe:
         _copy_probe(torch)
-    main_row = _run_gpu(args, args.storage, torch, P, W)
+    main_rounding = args.rounding or _default_rounding(args.storage)
+    main_row = _run_gpu(args, args.storage, main_rounding, torch, P, W)
     rows = [main_row]
-    for st in [s for s in args.rows.split(",") if s and s != args.storage]:
-        rows.append(_run_gpu(args, st, torch, P, W))
+    for item in [r for r in args.rows.split(",") if r]:
+        st, _, rnd = item.partition(":")
+        rnd = rnd or _default_rounding(st)
+        if (st, rnd) != (args.storage, main_rounding):
+            rows.append(_run_gpu(args, st, rnd, torch, P, W))
+    sweep = _run_sweep(args, torch, P, W) if args.sweep_steps > 0 else None
     cpu = None if args.no_cpu_baseline else _cpu_baseline(args, W)
     gbs = main_row["gbs"]
     out = {
@@ -166,7 +216,7 @@ def main():
         "dtype": args.storage,
         "data": "synthetic",
         "config": {"workload": f"second_sound_{args.n}x{args.n}_periodic", "nx": args.n, "ny": args.n,
-                   "tau_n": 0.55, "tau_r": 50.0, "storage": args.storage,
+                   "tau_n": 0.55, "tau_r": 50.0, "storage": args.storage, "rounding": main_rounding,
                    "check_interval": args.check_interval, "launch_shape": main_row["shape"]},
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4),
@@ -174,6 +224,7 @@ def main():
                      "kernel": "wave_kernel (fused pull-advection + boundary + moments + relaxation)",
                      "bytes_per_launch": BYTES_PER_NODE[args.storage] * args.n * args.n},
         "cpu_baseline": cpu,
+        "sweep": sweep,
         "rows": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items() if k != "tune"}
                  for r in rows],
     }

@@ -50,8 +50,25 @@ typedef enum {
 } lbm_status;
 
 /* Storage type of the populations.  Arithmetic is FP32 in every case; what is
- * stored is the scaled deviation g_i = (e_i - omega_i C_V T_ref(x)) / s. */
-typedef enum { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2 } lbm_storage;
+ * stored is the scaled deviation g_i = (e_i - R_i(x)) / s from a reference
+ * state R: the equilibrium omega_i C_V T_ref(x) plus a uniform x-flux (and,
+ * with the GRADIENT seam, the non-equilibrium share the ramp sustains).  With
+ * check steps on, the reference flux follows the lattice's mean heat flux.
+ *   F32, F16, BF16 : the eight g_i in that type (64 / 32 / 32 bytes per node
+ *                    and step, read plus write).
+ *   F16_SPLIT, BF16_SPLIT : the energy E = sum_i g_i in FP32 and the eight
+ *                    non-equilibrium shares h_i = g_i - omega_i E (Eq. 17
+ *                    weights) in 16 bits (40 bytes per node and step).  The
+ *                    heat flux lives in the h_i alone, so it keeps 16-bit
+ *                    precision relative to itself rather than to the energy;
+ *                    one node per lane only (vec 1), CHUNKED layout only. */
+typedef enum {
+    LBM_F32 = 0,
+    LBM_F16 = 1,
+    LBM_BF16 = 2,
+    LBM_F16_SPLIT = 3,
+    LBM_BF16_SPLIT = 4
+} lbm_storage;
 
 /* Boundary kinds (Sec. 2.5), per axis.  Walls are the nodes 0 and n-1.
  *   PERIODIC   : wrap-around advection.
@@ -61,10 +78,10 @@ typedef enum { LBM_F32 = 0, LBM_F16 = 1, LBM_BF16 = 2 } lbm_storage;
  *                omega_i (Eq. 58); the wall node then relaxes like any node.
  *   GRADIENT   : periodic temperature-gradient seam along x (Eqs. 59-60) with
  *                period nx and T_h - T_c = grad_x * nx; handled exactly as a
- *                periodic deviation from the bulk steady state of the imposed
- *                gradient (ramp T_ref(x) = t0 - grad_x * x carrying Fourier's
- *                heat flux (5/9) C_V grad_x tau_r), so the seam needs no branch
- *                and the stored values are the departures from that state.
+ *                periodic deviation from a reference state built on the ramp
+ *                T_ref(x) = t0 - grad_x * x (with the non-equilibrium share
+ *                the ramp sustains and a uniform flux), so the seam needs no
+ *                branch and the stored values are the departures from it.
  * Supported pairs: (any x, PERIODIC y), (PERIODIC x, ISOTHERMAL or DIFFUSE y),
  * (GRADIENT x, DIFFUSE y).  Walls on both axes need corners, which the paper
  * leaves undefined: LBM_EUNSUPPORTED. */

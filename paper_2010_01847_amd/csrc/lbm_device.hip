@@ -499,12 +499,64 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t sna
     if (MODE == kCheck) block_partials(acc, a.partials + (int64_t)t * kPartials);
 }
 
+// Split storage (16-bit h_i = g_i - omega_i E plus FP32 E per node): within a
+// 64-node chunk the eight h runs come first, then the E run, at this element
+// offset (elements of the 16-bit type).
+constexpr int kSplitE = 512;
+
+// omega_i E with the energy-exact split used by the relaxation (4 ea + 4 ed
+// equals E exactly): the equilibrium part of population i at energy E.
+__device__ __forceinline__ float omega_e(int i, float E) {
+    const float ea = W_AXIS * E;
+    return i < 4 ? ea : (E - 4.0f * ea) * 0.25f;
+}
+
+// Byte offset, within a row, of the FP32 energy of node x (split storage).
+__device__ __forceinline__ uint32_t e_off(const InstDesc& d, int x) {
+    return (uint32_t)(((x >> 6) * d.chunk + kSplitE) * 2 + (x & 63) * 4);
+}
+
+// Whole-wave lane shifts (DPP wave_shr:1 / wave_shl:1): lane i receives v of
+// lane i - 1 (from_left) or i + 1 (from_right); the lane with no source (0,
+// resp. 63) keeps `edge`.  All 64 lanes must be active.
+__device__ __forceinline__ float from_left(float v, float edge) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_right(float v, float edge) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+
+// v rounded to S: to nearest, or (SR, 16-bit) stochastically with 16 random bits.
+template <class S, int SR>
+__device__ __forceinline__ S round_to(float v, uint32_t r16) {
+    if constexpr (SR && __is_same(S, _Float16)) return sr_f16(v, r16);
+    else if constexpr (SR && __is_same(S, bf16_bits)) return sr_bf16(v, r16);
+    else return Cvt<S>::st(v);
+}
+
+template <class S>
+__device__ __forceinline__ void store_raw(char* p, S o, int nontemporal) {
+    typedef typename RawT<sizeof(S)>::T R;
+    R raw;
+    __builtin_memcpy(&raw, &o, sizeof(R));
+    R* q = reinterpret_cast<R*>(p);
+    if (nontemporal) __builtin_nontemporal_store(raw, q);
+    else *q = raw;
+}
+
+template <class S, int SR>
+__device__ __forceinline__ void store_one(char* p, float v, uint32_t r16, int nontemporal) {
+    store_raw<S>(p, round_to<S, SR>(v, r16), nontemporal);
+}
+
 // Wavefront-centric step for one node per lane.  Each wave owns one 64-node
 // row segment (chunk cx of row y), so the row, chunk and plane bases are
 // wave-uniform scalars and every load is a scalar base plus a 32-bit lane
 // offset; the boundary branches are taken per wave, not per lane.
-// Same per-node arithmetic as step_kernel, hence the same bits.
-template <class S, int MODE, int SR>
+// Same per-node arithmetic as step_kernel, hence the same bits.  SPLIT: the
+// populations are rebuilt as h_i + omega_i E from the source node's 16-bit
+// h_i and FP32 E, and stored back in that form.
+template <class S, int MODE, int SR, int SPLIT>
 __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t snap_stride, int xcd,
                                                           int nontemporal) {
     const int b = blockIdx.x;
@@ -532,8 +584,8 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
     const bool wave_live = (y < ny) && (xc < nx);
     // step counter: every block reads the count before this step; the block of
     // global tile 0 publishes count + 1 in the other slot for the next step
+    // (at the end, so no store precedes the kernel's loads)
     const uint32_t step = a.ctr_in[0];
-    if (t == 0 && threadIdx.x == 0 && threadIdx.y == 0) a.ctr_out[0] = step + 1u;
 
     double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (wave_live && x < nx) {
@@ -549,17 +601,49 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
         const int64_t pb = d.plane * (int64_t)sizeof(S);
         const uint32_t es = sizeof(S);
         // column offsets of x, x - 1 and x + 1 (periodic wrap at the row ends)
+        const int xm_edge = xc == 0 ? nx - 1 : xc - 1;
+        const int xp_edge = xc + 64 < nx ? xc + 64 : 0;
+        const bool in_m = lane > 0, in_p = lane < 63 && x + 1 < nx;
         const uint32_t c0 = ((uint32_t)col_off(d, xc) + lane) * es;
-        const uint32_t cm_edge = (uint32_t)col_off(d, xc == 0 ? nx - 1 : xc - 1) * es;
-        const uint32_t cp_edge = (uint32_t)col_off(d, xc + 64 < nx ? xc + 64 : 0) * es;
-        const uint32_t cm = lane > 0 ? c0 - es : cm_edge;
-        const uint32_t cp = (lane < 63 && x + 1 < nx) ? c0 + es : (x + 1 == nx ? 0u : cp_edge);
+        const uint32_t cm = in_m ? c0 - es : (uint32_t)col_off(d, xm_edge) * es;
+        const uint32_t cp = in_p ? c0 + es : (x + 1 == nx ? 0u : (uint32_t)col_off(d, xp_edge) * es);
         float g[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int dx = src_dx(i);
-            const char* base = rows[src_row(i)] + i * pb;
-            g[i] = Cvt<S>::ld(*reinterpret_cast<const S*>(base + (dx < 0 ? cm : (dx > 0 ? cp : c0))));
+            g[i] = Cvt<S>::ld(*reinterpret_cast<const S*>(rows[src_row(i)] + i * pb + (dx < 0 ? cm : (dx > 0 ? cp : c0))));
+        }
+        const uint32_t e0 = SPLIT ? e_off(d, x) : 0u;
+        if (SPLIT) {
+            // energies of the source nodes: rows y, y - 1, y + 1 at x - 1, x, x + 1
+            float El[3], Ec[3], Er[3];
+            if (xc + 64 <= nx) {
+                // full chunk: one load per row, neighbours by lane shifts; lanes 0
+                // and 63 load the energies beyond the chunk ends in the same
+                // instruction (every other lane repeats lane 63's address)
+                const uint32_t eo = lane == 0 ? e_off(d, xm_edge) : e_off(d, xp_edge);
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    Ec[r] = *reinterpret_cast<const float*>(rows[r] + e0);
+                    const float Eb = *reinterpret_cast<const float*>(rows[r] + eo);
+                    El[r] = from_left(Ec[r], Eb);
+                    Er[r] = from_right(Ec[r], Eb);
+                }
+            } else {
+                const uint32_t em = in_m ? e0 - 4u : e_off(d, xm_edge);
+                const uint32_t ep = in_p ? e0 + 4u : e_off(d, x + 1 == nx ? 0 : xp_edge);
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    Ec[r] = *reinterpret_cast<const float*>(rows[r] + e0);
+                    El[r] = *reinterpret_cast<const float*>(rows[r] + em);
+                    Er[r] = *reinterpret_cast<const float*>(rows[r] + ep);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int dx = src_dx(i), r = src_row(i);
+                g[i] = g[i] + omega_e(i, dx < 0 ? El[r] : (dx > 0 ? Er[r] : Ec[r]));
+            }
         }
         if (a.apply_shift) apply_shift(g, rv);
         const bool edge_y = (d.bc_y != 0) && (y == 0 || y == ny - 1);
@@ -589,41 +673,45 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
             }
         }
         char* out = reinterpret_cast<char*>(a.dst) + d.off * (int64_t)sizeof(S) + (int64_t)y * rb;
+        // four 32-bit random words per node and step (SR): hash of the node
+        // index keyed by a hash of (step, word, seed)
+        uint32_t r[4] = {0u, 0u, 0u, 0u};
         if (SR) {
-            // four 32-bit random words per node and step: hash of the node index
-            // keyed by a hash of (step, word, seed)
             const uint32_t node = (uint32_t)(d.node_off + (int64_t)y * nx + x);
-            uint32_t r[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) r[k] = mix32(node ^ mix32(step * 4u + (uint32_t)k + a.seed * 0x9e3779b9u));
-            if (sizeof(S) == 4) {
-                float o[8];
-                relax_sr_f32(g, d, rv, r, o);
-#pragma unroll
-                for (int i = 0; i < 8; ++i) store_run<S, 1>(reinterpret_cast<S*>(out + i * pb + c0), &o[i], nontemporal);
-            } else {
-                relax(g, d, rv);
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    S v;
-                    if constexpr (sizeof(S) == 2 && __is_same(S, _Float16)) v = sr_f16(g[i], bits16(r, i));
-                    else if constexpr (sizeof(S) == 2) v = sr_bf16(g[i], bits16(r, i));
-                    typedef typename RawT<sizeof(S)>::T R;
-                    R raw;
-                    __builtin_memcpy(&raw, &v, sizeof(R));
-                    R* q = reinterpret_cast<R*>(out + i * pb + c0);
-                    if (nontemporal) __builtin_nontemporal_store(raw, q);
-                    else *q = raw;
-                }
-            }
-        } else {
-            relax(g, d, rv);
+        }
+        if (SPLIT) {
+            // h*_i = (g_i - omega_i E) + delta_i; the collision keeps E (the
+            // FP32 sum of the populations before relaxation).  The rounding
+            // residual of the eight h is added to the stored E, so the node's
+            // stored populations still sum to E: 16-bit rounding moves energy
+            // between directions but creates or destroys none.
+            float delta[8];
+            relax_delta(g, d, rv, delta);
+            const float E = ((g[0] + g[2]) + (g[1] + g[3])) + ((g[4] + g[6]) + (g[5] + g[7]));
+            float res = 0.0f;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                store_run<S, 1>(reinterpret_cast<S*>(out + i * pb + c0), &g[i], nontemporal);
+                const float hv = (g[i] - omega_e(i, E)) + delta[i];
+                const S o = round_to<S, SR>(hv, bits16(r, i));
+                res = res + (hv - Cvt<S>::ld(o));
+                store_raw<S>(out + i * pb + c0, o, nontemporal);
             }
+            store_one<float, 0>(out + e0, E + res, 0u, nontemporal);
+        } else if (SR && sizeof(S) == 4) {
+            float o[8];
+            relax_sr_f32(g, d, rv, r, o);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) store_one<S, 0>(out + i * pb + c0, o[i], 0u, nontemporal);
+        } else {
+            // 16-bit SR narrows the round-to-nearest FP32 result stochastically
+            relax(g, d, rv);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) store_one<S, SR>(out + i * pb + c0, g[i], bits16(r, i), nontemporal);
         }
     }
+    if (t == 0 && threadIdx.x == 0 && threadIdx.y == 0) a.ctr_out[0] = step + 1u;
     if (MODE == kCheck) block_partials(acc, a.partials + (int64_t)t * kPartials);
 }
 
@@ -640,31 +728,31 @@ static hipError_t launch_step_v(const Shape& sh, int mode, const StepArgs& a, in
     return hipGetLastError();
 }
 
-template <class S, int SR>
+template <class S, int SR, int SPLIT>
 static hipError_t launch_wave_sr(const Shape& sh, int mode, const StepArgs& a, int64_t snap_stride,
                                  hipStream_t st) {
     dim3 grid(a.ntiles), block(sh.bx, sh.by);
     if (mode == kPlain)
-        hipLaunchKernelGGL((wave_kernel<S, kPlain, SR>), grid, block, 0, st, a, snap_stride, sh.xcd, sh.nt);
+        hipLaunchKernelGGL((wave_kernel<S, kPlain, SR, SPLIT>), grid, block, 0, st, a, snap_stride, sh.xcd, sh.nt);
     else if (mode == kSnap)
-        hipLaunchKernelGGL((wave_kernel<S, kSnap, SR>), grid, block, 0, st, a, snap_stride, sh.xcd, sh.nt);
+        hipLaunchKernelGGL((wave_kernel<S, kSnap, SR, SPLIT>), grid, block, 0, st, a, snap_stride, sh.xcd, sh.nt);
     else
-        hipLaunchKernelGGL((wave_kernel<S, kCheck, SR>), grid, block, 0, st, a, snap_stride, sh.xcd, sh.nt);
+        hipLaunchKernelGGL((wave_kernel<S, kCheck, SR, SPLIT>), grid, block, 0, st, a, snap_stride, sh.xcd, sh.nt);
     return hipGetLastError();
 }
 
-template <class S>
+template <class S, int SPLIT>
 static hipError_t launch_wave(const Shape& sh, int mode, const StepArgs& a, int64_t snap_stride,
                               hipStream_t st) {
-    return a.sr ? launch_wave_sr<S, 1>(sh, mode, a, snap_stride, st)
-                : launch_wave_sr<S, 0>(sh, mode, a, snap_stride, st);
+    return a.sr ? launch_wave_sr<S, 1, SPLIT>(sh, mode, a, snap_stride, st)
+                : launch_wave_sr<S, 0, SPLIT>(sh, mode, a, snap_stride, st);
 }
 
 template <class S>
 static hipError_t launch_step_s(const Shape& sh, int mode, const StepArgs& a, int64_t ss, hipStream_t st) {
     if (a.sr && sh.vec != 1) return hipErrorInvalidValue;
     switch (sh.vec) {
-        case 1: return launch_wave<S>(sh, mode, a, ss, st);
+        case 1: return launch_wave<S, 0>(sh, mode, a, ss, st);
         case 2: return launch_step_v<S, 2>(sh, mode, a, ss, st);
         case 4: return launch_step_v<S, 4>(sh, mode, a, ss, st);
         default: return hipErrorInvalidValue;
@@ -674,18 +762,59 @@ static hipError_t launch_step_s(const Shape& sh, int mode, const StepArgs& a, in
 hipError_t launch_step(int storage, const Shape& sh, int mode, const StepArgs& a, int64_t snap_stride,
                        hipStream_t st) {
     if (a.ntiles <= 0) return hipSuccess;
+    if (storage >= 3 && sh.vec != 1) return hipErrorInvalidValue;
     switch (storage) {
         case 0: return launch_step_s<float>(sh, mode, a, snap_stride, st);
         case 1: return launch_step_s<_Float16>(sh, mode, a, snap_stride, st);
         case 2: return launch_step_s<bf16_bits>(sh, mode, a, snap_stride, st);
+        case 3: return launch_wave<_Float16, 1>(sh, mode, a, snap_stride, st);
+        case 4: return launch_wave<bf16_bits, 1>(sh, mode, a, snap_stride, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 // ------------------------------------------------------------------ moments
 
+// Population i of node (x, y) as stored in the instance's buffer (`base`
+// points at its first element); SPLIT rebuilds it as h_i + omega_i E.
+template <class S, int SPLIT>
+__device__ __forceinline__ float load_pop(const S* base, const InstDesc& d, int i, int x, int y) {
+    const S* row = base + (int64_t)y * d.row;
+    float v = Cvt<S>::ld(row[(int64_t)i * d.plane + col_off(d, x)]);
+    if (SPLIT) v = v + omega_e(i, *reinterpret_cast<const float*>(reinterpret_cast<const char*>(row) + e_off(d, x)));
+    return v;
+}
+
+// Store the relaxation of the populations g of node (x, y), rounded to
+// nearest: as in the step kernels, SPLIT stores h*_i = (g_i - omega_i E) +
+// delta_i and E.
+template <class S, int SPLIT>
+__device__ __forceinline__ void relax_store(S* base, const InstDesc& d, const RefView& rv, float g[8], int x,
+                                            int y) {
+    S* row = base + (int64_t)y * d.row;
+    S* p = row + col_off(d, x);
+    if (SPLIT) {
+        float delta[8];
+        relax_delta(g, d, rv, delta);
+        const float E = ((g[0] + g[2]) + (g[1] + g[3])) + ((g[4] + g[6]) + (g[5] + g[7]));
+        float res = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float hv = (g[i] - omega_e(i, E)) + delta[i];
+            const S o = Cvt<S>::st(hv);
+            res = res + (hv - Cvt<S>::ld(o));
+            p[(int64_t)i * d.plane] = o;
+        }
+        *reinterpret_cast<float*>(reinterpret_cast<char*>(row) + e_off(d, x)) = E + res;
+    } else {
+        relax(g, d, rv);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) p[(int64_t)i * d.plane] = Cvt<S>::st(g[i]);
+    }
+}
+
 // One node per thread, 256 threads along x, one row per block row.
-template <class S>
+template <class S, int SPLIT>
 __global__ __launch_bounds__(256) void moments_kernel(const InstDesc* __restrict__ descs,
                                                       const RefState* __restrict__ refs, int inst,
                                                       const void* buf, int pull, int pending_shift,
@@ -706,16 +835,12 @@ __global__ __launch_bounds__(256) void moments_kernel(const InstDesc* __restrict
             const int yp = (y == ny - 1) ? 0 : y + 1;
             const int rows[3] = {y, ym, yp};
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int xs = wrapx(x + src_dx(i), nx);
-                g[i] = Cvt<S>::ld(src[(int64_t)i * d.plane + (int64_t)rows[src_row(i)] * d.row + col_off(d, xs)]);
-            }
+            for (int i = 0; i < 8; ++i) g[i] = load_pop<S, SPLIT>(src, d, i, wrapx(x + src_dx(i), nx), rows[src_row(i)]);
             if (pending_shift) apply_shift(g, rv);
             boundary(g, d, rv.wall_kd, x, y);
         } else {
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                g[i] = Cvt<S>::ld(src[(int64_t)i * d.plane + (int64_t)y * d.row + col_off(d, x)]);
+            for (int i = 0; i < 8; ++i) g[i] = load_pop<S, SPLIT>(src, d, i, x, y);
         }
         double E = 0.0;
 #pragma unroll
@@ -749,12 +874,15 @@ hipError_t launch_moments(int storage, const InstDesc* d_desc, const RefState* d
                           hipStream_t st) {
     dim3 grid((h.nx + 255) / 256, h.ny), block(256);
     switch (storage) {
-        case 0: hipLaunchKernelGGL(moments_kernel<float>, grid, block, 0, st, d_desc, d_ref, inst, buf, pull,
-                                   pending_shift, out_kind, T, qx, qy, t0, grad, partials); break;
-        case 1: hipLaunchKernelGGL(moments_kernel<_Float16>, grid, block, 0, st, d_desc, d_ref, inst, buf,
-                                   pull, pending_shift, out_kind, T, qx, qy, t0, grad, partials); break;
-        case 2: hipLaunchKernelGGL(moments_kernel<bf16_bits>, grid, block, 0, st, d_desc, d_ref, inst, buf,
-                                   pull, pending_shift, out_kind, T, qx, qy, t0, grad, partials); break;
+#define PLBM_MOMENTS(S, SPLIT)                                                                         \
+    hipLaunchKernelGGL((moments_kernel<S, SPLIT>), grid, block, 0, st, d_desc, d_ref, inst, buf, pull,  \
+                       pending_shift, out_kind, T, qx, qy, t0, grad, partials)
+        case 0: PLBM_MOMENTS(float, 0); break;
+        case 1: PLBM_MOMENTS(_Float16, 0); break;
+        case 2: PLBM_MOMENTS(bf16_bits, 0); break;
+        case 3: PLBM_MOMENTS(_Float16, 1); break;
+        case 4: PLBM_MOMENTS(bf16_bits, 1); break;
+#undef PLBM_MOMENTS
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -765,7 +893,7 @@ hipError_t launch_moments(int storage, const InstDesc* d_desc, const RefState* d
 // Pre-relaxation state at n = 0 (equilibrium of Eq. 15 with j = q / beta, wall
 // nodes at their Eq. 55 equilibrium), stored rounded to `pre`; its relaxation,
 // computed from the rounded values exactly as a step would, goes to `post`.
-template <class S>
+template <class S, int SPLIT>
 __global__ __launch_bounds__(256) void init_kernel(const InstDesc* __restrict__ descs,
                                                    const RefState* __restrict__ refs, int inst,
                                                    void* pre, void* post, const double* __restrict__ T,
@@ -797,17 +925,34 @@ __global__ __launch_bounds__(256) void init_kernel(const InstDesc* __restrict__ 
     const bool wall = (d.bc_x == 1 && (x == 0 || x == d.nx - 1)) ||
                       (d.bc_y == 1 && (y == 0 || y == d.ny - 1));
     if (wall) boundary(g, d, rv.wall_kd, x, y);
-    S* p = reinterpret_cast<S*>(pre) + d.off + (int64_t)y * d.row + col_off(d, x);
-    S* q = reinterpret_cast<S*>(post) + d.off + (int64_t)y * d.row + col_off(d, x);
+    S* pb = reinterpret_cast<S*>(pre) + d.off;
+    S* row = pb + (int64_t)y * d.row;
+    S* p = row + col_off(d, x);
+    if (SPLIT) {
+        const float E = ((g[0] + g[2]) + (g[1] + g[3])) + ((g[4] + g[6]) + (g[5] + g[7]));
+        float hq[8], res = 0.0f;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const S v = Cvt<S>::st(g[i]);
-        p[(int64_t)i * d.plane] = v;
-        g[i] = Cvt<S>::ld(v);
+        for (int i = 0; i < 8; ++i) {
+            const float hv = g[i] - omega_e(i, E);
+            const S v = Cvt<S>::st(hv);
+            p[(int64_t)i * d.plane] = v;
+            hq[i] = Cvt<S>::ld(v);
+            res = res + (hv - hq[i]);
+        }
+        const float Es = E + res;
+        *reinterpret_cast<float*>(reinterpret_cast<char*>(row) + e_off(d, x)) = Es;
+        // the populations as the next read will rebuild them
+#pragma unroll
+        for (int i = 0; i < 8; ++i) g[i] = hq[i] + omega_e(i, Es);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const S v = Cvt<S>::st(g[i]);
+            p[(int64_t)i * d.plane] = v;
+            g[i] = Cvt<S>::ld(v);
+        }
     }
-    relax(g, d, rv);
-#pragma unroll
-    for (int i = 0; i < 8; ++i) q[(int64_t)i * d.plane] = Cvt<S>::st(g[i]);
+    relax_store<S, SPLIT>(reinterpret_cast<S*>(post) + d.off, d, rv, g, x, y);
 }
 
 hipError_t launch_init(int storage, const InstDesc* d_desc, const RefState* d_ref, int inst,
@@ -815,12 +960,15 @@ hipError_t launch_init(int storage, const InstDesc* d_desc, const RefState* d_re
                        const double* qy, double t0, double grad, double beta, hipStream_t st) {
     dim3 grid((h.nx + 255) / 256, h.ny), block(256);
     switch (storage) {
-        case 0: hipLaunchKernelGGL(init_kernel<float>, grid, block, 0, st, d_desc, d_ref, inst, pre, post, T,
-                                   qx, qy, t0, grad, beta); break;
-        case 1: hipLaunchKernelGGL(init_kernel<_Float16>, grid, block, 0, st, d_desc, d_ref, inst, pre, post,
-                                   T, qx, qy, t0, grad, beta); break;
-        case 2: hipLaunchKernelGGL(init_kernel<bf16_bits>, grid, block, 0, st, d_desc, d_ref, inst, pre, post,
-                                   T, qx, qy, t0, grad, beta); break;
+#define PLBM_INIT(S, SPLIT)                                                                            \
+    hipLaunchKernelGGL((init_kernel<S, SPLIT>), grid, block, 0, st, d_desc, d_ref, inst, pre, post, T, qx, \
+                       qy, t0, grad, beta)
+        case 0: PLBM_INIT(float, 0); break;
+        case 1: PLBM_INIT(_Float16, 0); break;
+        case 2: PLBM_INIT(bf16_bits, 0); break;
+        case 3: PLBM_INIT(_Float16, 1); break;
+        case 4: PLBM_INIT(bf16_bits, 1); break;
+#undef PLBM_INIT
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

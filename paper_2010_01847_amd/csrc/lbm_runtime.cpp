@@ -33,6 +33,8 @@ struct Status {
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 int esize_of(int storage) { return storage == LBM_F32 ? 4 : 2; }
+bool is_split(int storage) { return storage == LBM_F16_SPLIT || storage == LBM_BF16_SPLIT; }
+bool is_f16(int storage) { return storage == LBM_F16 || storage == LBM_F16_SPLIT; }
 
 // Row pitch in elements for the planes layout: row bytes a multiple of 256.
 int32_t pitch_of(int32_t nx, int es) {
@@ -59,9 +61,21 @@ struct Geometry {
 
 // Element geometry of one instance (see InstDesc for the address formula).
 // Every instance's size is a multiple of 64 elements, so every instance and
-// plane start stays 256-byte (FP32) / 128-byte (16-bit) aligned.
-Geometry geometry_of(const lbm_instance& in, int es, int layout) {
+// plane start stays 256-byte (FP32) / 128-byte (16-bit) aligned.  Split
+// storage (chunked only): a chunk holds the eight 16-bit h runs and then the
+// FP32 energy run, 640 16-bit elements (1280 bytes).
+Geometry geometry_of(const lbm_instance& in, int es, int layout, bool split = false) {
     Geometry g;
+    if (split) {
+        const int64_t nch = ((int64_t)in.nx + 63) / 64;
+        g.row = nch * 640;
+        g.plane = 64;
+        g.chunk = 640;
+        g.cshift = 6;
+        g.cmask = 63;
+        g.elems = (int64_t)in.ny * g.row;
+        return g;
+    }
     if (layout == LBM_LAYOUT_PLANES) {
         g.row = pitch_of(in.nx, es);
         g.plane = (int64_t)in.ny * g.row + (int64_t)(plane_pad_bytes() / es);
@@ -168,7 +182,7 @@ Layout layout_of(const std::vector<lbm_instance>& v, int storage, int check, int
     const int es = esize_of(storage);
     size_t elems = 0;
     for (auto& in : v) {
-        elems += (size_t)geometry_of(in, es, layout).elems;
+        elems += (size_t)geometry_of(in, es, layout, is_split(storage)).elems;
         L.nodes += (int64_t)in.nx * in.ny;
         L.mparts_max = std::max<int64_t>(L.mparts_max, (int64_t)((in.nx + 255) / 256) * in.ny);
     }
@@ -366,7 +380,10 @@ const char* lbm_last_error(lbm_handle h) {
 static Status check_config(const lbm_config* cfg, std::vector<lbm_instance>* out) {
     if (!cfg) return {LBM_EINVAL, "config is NULL"};
     if (cfg->n_instances < 1 || !cfg->inst) return {LBM_EINVAL, "need n_instances >= 1 and inst != NULL"};
-    if (cfg->storage < 0 || cfg->storage > 2) return {LBM_EINVAL, "storage must be LBM_F32, LBM_F16 or LBM_BF16"};
+    if (cfg->storage < 0 || cfg->storage > 4)
+        return {LBM_EINVAL, "storage must be LBM_F32, LBM_F16, LBM_BF16, LBM_F16_SPLIT or LBM_BF16_SPLIT"};
+    if (is_split(cfg->storage) && cfg->layout == LBM_LAYOUT_PLANES)
+        return {LBM_EUNSUPPORTED, "split storage uses the chunked layout only"};
     if (cfg->check_interval != 0 && cfg->check_interval != -1 && cfg->check_interval < 2)
         return {LBM_EINVAL, "check_interval must be 0 (default 100), -1 (off) or >= 2"};
     if (cfg->flags & ~(LBM_FLAG_EXTERNAL_MEMORY | LBM_FLAG_STOCHASTIC_ROUNDING))
@@ -444,7 +461,7 @@ int lbm_create(const lbm_config* cfg, lbm_handle* out) {
     for (size_t k = 0; k < v.size(); ++k) {
         InstDesc& d = h->desc[k];
         std::memset(&d, 0, sizeof d);
-        const Geometry geo = geometry_of(v[k], es, h->layout);
+        const Geometry geo = geometry_of(v[k], es, h->layout, is_split(h->storage));
         d.nx = v[k].nx;
         d.ny = v[k].ny;
         d.bc_x = v[k].bc_x;
@@ -553,7 +570,7 @@ static int check_inst(lbm_ctx* h, int32_t k) {
 // Automatic storage scale: FP16 keeps the largest expected |g| near 2^12 or
 // below, far under its 65504 limit and well above its normal range floor.
 static double auto_scale(const lbm_ctx* h, const lbm_instance& in, double amp) {
-    if (h->storage != LBM_F16) return 1.0;
+    if (!is_f16(h->storage)) return 1.0;
     if (in.bc_x == LBM_BC_ISOTHERMAL) amp = std::max({amp, std::fabs(in.t_wall[0] - in.t0), std::fabs(in.t_wall[1] - in.t0)});
     if (in.bc_y == LBM_BC_ISOTHERMAL) amp = std::max({amp, std::fabs(in.t_wall[2] - in.t0), std::fabs(in.t_wall[3] - in.t0)});
     if (in.bc_x == LBM_BC_GRADIENT) {
@@ -633,7 +650,7 @@ int lbm_init_device(lbm_handle h, int32_t k, const double* T, const double* qx, 
     if (rc) return rc;
     if (!T) return h->fail(LBM_EINVAL, "T is NULL (device init needs a temperature field)");
     const lbm_instance& in = h->inst[k];
-    if (h->storage == LBM_F16 && in.scale == 0.0)
+    if (is_f16(h->storage) && in.scale == 0.0)
         return h->fail(LBM_EINVAL, "FP16 storage with device init needs an explicit scale");
     fill_desc(h, k, in.scale > 0.0 ? in.scale : 1.0);
     return do_init(h, k, T, qx, qy);
@@ -879,6 +896,7 @@ int lbm_set_launch_shape(lbm_handle h, const lbm_launch_shape* s) {
     Status st = shape_ok(s);
     if (st.code) return h->fail(st.code, st.msg);
     if (h->sr && s->vec != 1) return h->fail(LBM_EINVAL, "stochastic rounding needs vec = 1");
+    if (is_split(h->storage) && s->vec != 1) return h->fail(LBM_EINVAL, "split storage needs vec = 1");
     h->shape.vec = s->vec;
     h->shape.bx = s->block_x;
     h->shape.by = s->block_y;
@@ -1026,7 +1044,8 @@ int lbm_autotune(lbm_handle h, int32_t steps, char* report, size_t report_len) {
     };
     for (int v : vecs)
         for (auto& b : blocks) {
-            if (h->sr && v != 1) continue;     // stochastic rounding runs one node per lane
+            // stochastic rounding and split storage run one node per lane
+            if ((h->sr || is_split(h->storage)) && v != 1) continue;
             Shape s;
             s.vec = v;
             s.bx = b[0];

@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libphonon_lbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_ESTATE, LBM_EUNSUPPORTED, LBM_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
-LBM_F32, LBM_F16, LBM_BF16 = 0, 1, 2
+LBM_F32, LBM_F16, LBM_BF16, LBM_F16_SPLIT, LBM_BF16_SPLIT = 0, 1, 2, 3, 4
 LBM_BC_PERIODIC, LBM_BC_ISOTHERMAL, LBM_BC_DIFFUSE, LBM_BC_GRADIENT = 0, 1, 2, 3
 LBM_SCHED_BATCHED, LBM_SCHED_PER_INSTANCE, LBM_SCHED_GRAPH = 0, 1, 2
 LBM_FLAG_EXTERNAL_MEMORY = 0x1
@@ -31,7 +31,8 @@ LBM_FLAG_STOCHASTIC_ROUNDING = 0x2
 LBM_LAYOUT_AUTO, LBM_LAYOUT_PLANES, LBM_LAYOUT_CHUNKED = 0, 1, 2
 LAYOUT = {"auto": LBM_LAYOUT_AUTO, "planes": LBM_LAYOUT_PLANES, "chunked": LBM_LAYOUT_CHUNKED}
 
-STORAGE = {"f32": LBM_F32, "f16": LBM_F16, "bf16": LBM_BF16}
+STORAGE = {"f32": LBM_F32, "f16": LBM_F16, "bf16": LBM_BF16,
+           "f16_split": LBM_F16_SPLIT, "bf16_split": LBM_BF16_SPLIT}
 BC = {"periodic": LBM_BC_PERIODIC, "isothermal": LBM_BC_ISOTHERMAL, "diffuse": LBM_BC_DIFFUSE,
       "gradient": LBM_BC_GRADIENT}
 ERRNAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP", -4: "LBM_ESTATE",

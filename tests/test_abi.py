@@ -76,6 +76,16 @@ def test_required_bytes_and_layout():
     assert b32 > b16
     # check-step snapshot adds 3 doubles per node
     assert P.lbm_required_bytes(_cfg([it], check=10)) - b32 >= 3 * 8 * 100 * 30
+    # split storage: per 64-node chunk eight 16-bit runs plus one FP32 energy
+    # run (1280 bytes), chunked layout only
+    bs = P.lbm_required_bytes(_cfg([it], storage=P.LBM_F16_SPLIT, check=-1))
+    assert bs >= 2 * 30 * 2 * 1280
+    assert bs - P.lbm_required_bytes(_cfg([it], storage=P.LBM_BF16_SPLIT, check=-1)) == 0
+    cfg = _cfg([it], storage=P.LBM_BF16_SPLIT, check=-1)
+    cfg.layout = P.LBM_LAYOUT_PLANES
+    with pytest.raises(P.LBMError) as e:
+        P.lbm_required_bytes(cfg)
+    assert e.value.code == P.LBM_EUNSUPPORTED
 
 
 @pytest.mark.parametrize("kw,code", [
