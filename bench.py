@@ -72,7 +72,7 @@ def _parse():
     p.add_argument("--sweep-steps", type=int, default=300, help="timed steps per sweep schedule (0: skip)")
     p.add_argument("--check-interval", type=int, default=100)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-seconds", type=float, default=10.0)
+    p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--autotune", action="store_true")
     p.add_argument("--copy-probe", action="store_true",
                    help="also run a 1 GiB torch device copy 5 times (counter calibration)")
@@ -91,15 +91,22 @@ def _copy_probe(torch):
     del a, b
 
 
-def _run_gpu(args, storage, rounding, torch, P, W):
+def _run_gpu(args, storage, rounding, torch, P, W, host_io=False):
     case = W.second_sound_case(n=args.n)
     scale = 2.0 ** -20 if storage.startswith("f16") else 0.0
     lat = P.Lattice([P.instance_from_case(case, scale)], storage=storage,
                     check_interval=args.check_interval, rounding=rounding, seed=1847)
     tune = lat.autotune(10) if args.autotune else None
-    T0 = torch.from_numpy(W.initial_field(case)).to("cuda")
-    lat.init(0, T0)
-    del T0
+    T0 = W.initial_field(case)
+    io = None
+    if host_io:
+        # host FP64 field -> device (PCIe) -> equilibrium init, synchronous
+        t = time.perf_counter()
+        lat.init(0, T0)
+        io = {"init_from_host_s": time.perf_counter() - t}
+    Td = torch.from_numpy(T0).to("cuda")
+    lat.init(0, Td)
+    del Td, T0
     stream = lat.stream
     lat.step(args.warmup)
     torch.cuda.synchronize()
@@ -118,10 +125,36 @@ def _run_gpu(args, storage, rounding, torch, P, W):
     gbs = BYTES_PER_NODE[storage] * nodes / step_s / 1e9
     done = args.warmup + args.steps
     info = lat.last_check(0) if 0 < args.check_interval <= done else None
+    if host_io:
+        # FP64 (dT, qx, qy) of the final state back to the host
+        t = time.perf_counter()
+        lat.moments(0)
+        io["moments_to_host_s"] = time.perf_counter() - t
+        io["pcie_inclusive_mlups"] = nodes * args.steps / (io["init_from_host_s"] + ms / 1e3
+                                                           + io["moments_to_host_s"]) / 1e6
+    kernel_ms = _plain_kernel_ms(lat, args.check_interval, torch)
     shape = lat.launch_shape()
     lat.close()
     return dict(storage=storage, rounding=rounding, mlups=mlups, ms_per_step=ms / args.steps, gbs=gbs,
-                wall_s=wall, check=info, shape=shape, tune=tune)
+                kernel_ms=kernel_ms, kernel_gbs=BYTES_PER_NODE[storage] * nodes / (kernel_ms / 1e3) / 1e9,
+                wall_s=wall, check=info, shape=shape, tune=tune, host_io=io)
+
+
+def _plain_kernel_ms(lat, K, torch, n=98):
+    """Average duration of the plain stream-collide launch: HIP events on the
+    launch stream around a run of steps that holds no check-step work (the
+    steps strictly between two check steps, snapshot step excluded)."""
+    if K > 2:
+        lat.step((-lat.steps) % K + 1)      # past the next check step and the shift step after it
+        n = min(n, K - 3)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(lat.stream)
+    lat.step(n)
+    e1.record(lat.stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n
 
 
 def _run_sweep(args, torch, P, W):
@@ -169,14 +202,23 @@ def _cpu_baseline(args, W):
     n = 2048
     case = W.second_sound_case(n=n)
     o = ref.Oracle(case, W.initial_field(case))
-    t1 = o.run(2)
-    per_step = max(t1 / 2, 1e-6)
+    o.run(2)                               # thread start-up, first touch
+    per_step = max(o.run(4) / 4, 1e-6)
     steps = max(2, int(args.cpu_seconds / per_step))
     t = o.run(steps)
     mlups = n * n * steps / t / 1e6
+    # the same stepper on one thread (512^2 window, about 2 s)
+    ref.set_threads(1)
+    small = W.second_sound_case(n=512)
+    o1 = ref.Oracle(small, W.initial_field(small))
+    t1 = o1.run(2)
+    s1 = max(2, int(2.0 / max(t1 / 2, 1e-6)))
+    t1 = o1.run(s1)
+    ref.set_threads(threads)
     return dict(value=mlups, unit="MLUPS", cores=threads, kind="oracle",
                 sample=f"{n}x{n} window of the 8192^2 second-sound lattice, {steps} steps, "
-                       f"{t:.1f} s, FP64 C stepper with OpenMP over rows")
+                       f"{t:.1f} s, FP64 C stepper with OpenMP over rows",
+                value_1_thread=512 * 512 * s1 / t1 / 1e6)
 
 
 def main():
@@ -192,7 +234,7 @@ def main():
     if args.copy_probe:
         _copy_probe(torch)
     main_rounding = args.rounding or _default_rounding(args.storage)
-    main_row = _run_gpu(args, args.storage, main_rounding, torch, P, W)
+    main_row = _run_gpu(args, args.storage, main_rounding, torch, P, W, host_io=True)
     rows = [main_row]
     for item in [r for r in args.rows.split(",") if r]:
         st, _, rnd = item.partition(":")
@@ -201,7 +243,7 @@ def main():
             rows.append(_run_gpu(args, st, rnd, torch, P, W))
     sweep = _run_sweep(args, torch, P, W) if args.sweep_steps > 0 else None
     cpu = None if args.no_cpu_baseline else _cpu_baseline(args, W)
-    gbs = main_row["gbs"]
+    gbs = main_row["kernel_gbs"]
     out = {
         "metric": "MLUPS and % of HBM roofline, FP32 vs 16-bit storage vs FP64 oracle error",
         "value": round(main_row["mlups"], 1),
@@ -222,11 +264,13 @@ def main():
                      "frac": round(gbs / HBM_PEAK_GBS, 4),
                      "traffic": _measured_traffic(args.storage, args.n),
                      "kernel": "wave_kernel (fused pull-advection + boundary + moments + relaxation)",
+                     "kernel_us": round(main_row["kernel_ms"] * 1e3, 1),
                      "bytes_per_launch": BYTES_PER_NODE[args.storage] * args.n * args.n},
         "cpu_baseline": cpu,
         "sweep": sweep,
-        "rows": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items() if k != "tune"}
-                 for r in rows],
+        "host_io": {k: round(v, 4) for k, v in main_row["host_io"].items()},
+        "rows": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()
+                  if k not in ("tune", "host_io")} for r in rows],
     }
     print(json.dumps(out), flush=True)
 

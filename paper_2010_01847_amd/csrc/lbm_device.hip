@@ -1000,18 +1000,31 @@ __device__ void reduce_records(const double* __restrict__ partials, int64_t firs
         for (int c = 0; c < kPartials; ++c) out[c] = red[0][c];
 }
 
-// Per instance: the check-step totals, then (adaptive instances) the move of
-// the reference flux to the mean flux of the state just checked.  The shift
-// is rounded to FP32 first and J is moved by the rounded amount (in FP64), so
-// J and the stored populations stay consistent; shift_d = shift_a / 4 is
-// exact.
+// First stage: group b of the tile records of its instance.
+__global__ __launch_bounds__(256) void group_reduce_kernel(const InstDesc* __restrict__ descs,
+                                                           const int32_t* __restrict__ group_inst,
+                                                           const double* __restrict__ partials,
+                                                           double* __restrict__ gpart) {
+    const int b = blockIdx.x;
+    const InstDesc& d = descs[group_inst[b]];
+    const int j = b - d.group_begin;
+    const int rest = d.ntiles - j * kGroup;
+    reduce_records(partials, (int64_t)d.tile_begin + (int64_t)j * kGroup, rest < kGroup ? rest : kGroup,
+                   gpart + (int64_t)b * kPartials);
+}
+
+// Second stage, per instance: the check-step totals, then (adaptive
+// instances) the move of the reference flux to the mean flux of the state just
+// checked.  The shift is rounded to FP32 first and J is moved by the rounded
+// amount (in FP64), so J and the stored populations stay consistent;
+// shift_d = shift_a / 4 is exact.
 __global__ __launch_bounds__(256) void finalize_kernel(const InstDesc* __restrict__ descs,
                                                        RefState* __restrict__ refs,
-                                                       const double* __restrict__ partials,
+                                                       const double* __restrict__ gpart,
                                                        double* __restrict__ results) {
     const InstDesc& d = descs[blockIdx.x];
     double* out = results + (int64_t)blockIdx.x * kPartials;
-    reduce_records(partials, d.tile_begin, d.ntiles, out);
+    reduce_records(gpart, d.group_begin, d.ngroups, out);
     if (threadIdx.x != 0) return;
     RefState& r = refs[blockIdx.x];
     if (!r.adapt) return;
@@ -1028,19 +1041,27 @@ __global__ __launch_bounds__(256) void finalize_kernel(const InstDesc* __restric
     ref_set_flux(r, J);
 }
 
-__global__ __launch_bounds__(256) void finalize_range_kernel(const double* __restrict__ partials,
-                                                             int count, double* __restrict__ out) {
-    reduce_records(partials, 0, count, out);
+// Block b reduces records [b * span, min((b + 1) * span, count)).
+__global__ __launch_bounds__(256) void range_reduce_kernel(const double* __restrict__ partials, int count,
+                                                           int span, double* __restrict__ out) {
+    const int64_t first = (int64_t)blockIdx.x * span;
+    const int64_t rest = count - first;
+    reduce_records(partials, first, (int)(rest < span ? rest : span), out + (int64_t)blockIdx.x * kPartials);
 }
 
-hipError_t launch_finalize(const InstDesc* d_desc, RefState* d_ref, int ninst, const double* partials,
-                           double* results, hipStream_t st) {
-    hipLaunchKernelGGL(finalize_kernel, dim3(ninst), dim3(256), 0, st, d_desc, d_ref, partials, results);
+hipError_t launch_finalize(const InstDesc* d_desc, const int32_t* group_inst, int ngroups, RefState* d_ref,
+                           int ninst, const double* partials, double* gpart, double* results,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(group_reduce_kernel, dim3(ngroups), dim3(256), 0, st, d_desc, group_inst, partials, gpart);
+    hipLaunchKernelGGL(finalize_kernel, dim3(ninst), dim3(256), 0, st, d_desc, d_ref, gpart, results);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize_range(const double* partials, int nparts, double* result, hipStream_t st) {
-    hipLaunchKernelGGL(finalize_range_kernel, dim3(1), dim3(256), 0, st, partials, nparts, result);
+hipError_t launch_finalize_range(const double* partials, int nparts, double* gpart, double* result,
+                                 hipStream_t st) {
+    const int ng = (nparts + kGroup - 1) / kGroup;
+    hipLaunchKernelGGL(range_reduce_kernel, dim3(ng), dim3(256), 0, st, partials, nparts, kGroup, gpart);
+    hipLaunchKernelGGL(range_reduce_kernel, dim3(1), dim3(256), 0, st, gpart, ng, ng, result);
     return hipGetLastError();
 }
 

@@ -10,6 +10,7 @@ namespace plbm {
 
 constexpr int kMaxBlock = 512;     // threads per block upper bound (launch bounds)
 constexpr int kPartials = 5;       // per-tile FP64 partials: sum dE, sum qx, sum qy, |dm|^2, |m|^2
+constexpr int kGroup = 1024;       // tile records per first-stage reduction block
 
 // Per-instance descriptor, resident in device memory (one 192-byte record).
 //
@@ -29,6 +30,8 @@ struct alignas(64) InstDesc {
     int32_t cshift;         // log2 of the chunk width (31: no chunking)
     int32_t cmask;          // chunk width - 1
     int32_t layout;         // 1 = planes, 2 = chunked
+    int32_t group_begin;    // first reduction group of this instance (kGroup tiles each)
+    int32_t ngroups;        // reduction groups of this instance
     int64_t row;            // elements between rows
     int64_t plane;          // elements between direction runs
     int64_t chunk;          // elements between 64-node chunks (0: planes layout)
@@ -142,13 +145,17 @@ hipError_t launch_init(int storage, const InstDesc* d_desc, const RefState* d_re
                        hipStream_t st);
 
 // Deterministic per-instance reduction of tile partials into results
-// (kPartials doubles per instance).  One block per instance.
-// Also moves each adaptive instance's reference flux to its mean heat flux.
-hipError_t launch_finalize(const InstDesc* d_desc, RefState* d_ref, int ninst, const double* partials,
-                           double* results, hipStream_t st);
+// (kPartials doubles per instance), in two fixed-order stages: groups of
+// kGroup tile records (group_inst: group -> instance, ngroups in total) into
+// gpart, then one block per instance over its groups.  The second stage also
+// moves each adaptive instance's reference flux to its mean heat flux.
+hipError_t launch_finalize(const InstDesc* d_desc, const int32_t* group_inst, int ngroups, RefState* d_ref,
+                           int ninst, const double* partials, double* gpart, double* results,
+                           hipStream_t st);
 
-// Reduction of moments-kernel partials (tiles of 256 nodes) of one instance.
-hipError_t launch_finalize_range(const double* partials, int nparts, double* result,
+// Reduction of nparts moments-kernel partials (tiles of 256 nodes) of one
+// instance, through gpart (ceil(nparts / kGroup) records).
+hipError_t launch_finalize_range(const double* partials, int nparts, double* gpart, double* result,
                                  hipStream_t st);
 
 }  // namespace plbm

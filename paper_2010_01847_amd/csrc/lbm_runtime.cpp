@@ -169,12 +169,20 @@ int64_t max_tiles(const std::vector<lbm_instance>& v) {
     return n;
 }
 
+// Worst-case count of first-stage reduction groups (per instance, kGroup
+// tiles each).
+int64_t max_groups(const std::vector<lbm_instance>& v) {
+    int64_t n = 0;
+    for (auto& in : v) n += ((int64_t)((in.nx + 63) / 64) * in.ny + kGroup - 1) / kGroup;
+    return n;
+}
+
 struct Layout {
     size_t buf_bytes = 0;      // one population buffer
     size_t off_buf[2] = {0, 0};
     size_t off_snap = 0, off_part = 0, off_res = 0, off_mpart = 0, off_mres = 0, off_desc = 0,
-           off_ref = 0, off_tiles = 0, off_ctr = 0, total = 0;
-    int64_t nodes = 0, tiles_max = 0, mparts_max = 0;
+           off_ref = 0, off_tiles = 0, off_groups = 0, off_gpart = 0, off_ctr = 0, total = 0;
+    int64_t nodes = 0, tiles_max = 0, mparts_max = 0, groups_max = 0;
 };
 
 Layout layout_of(const std::vector<lbm_instance>& v, int storage, int check, int layout) {
@@ -188,6 +196,9 @@ Layout layout_of(const std::vector<lbm_instance>& v, int storage, int check, int
     }
     L.buf_bytes = align_up(elems * es, kAlign);
     L.tiles_max = max_tiles(v);
+    L.groups_max = max_groups(v);
+    // the same scratch serves the first stage of lbm_totals' reduction
+    const int64_t gscratch = std::max<int64_t>(L.groups_max, (L.mparts_max + kGroup - 1) / kGroup);
     size_t o = 0;
     L.off_buf[0] = o; o += L.buf_bytes;
     L.off_buf[1] = o; o += L.buf_bytes;
@@ -199,6 +210,8 @@ Layout layout_of(const std::vector<lbm_instance>& v, int storage, int check, int
     L.off_desc = o; o += align_up(v.size() * sizeof(InstDesc), kAlign);
     L.off_ref = o; o += align_up(v.size() * sizeof(RefState), kAlign);
     L.off_tiles = o; o += align_up((size_t)L.tiles_max * sizeof(int32_t), kAlign);
+    L.off_groups = o; o += align_up((size_t)L.groups_max * sizeof(int32_t), kAlign);
+    L.off_gpart = o; o += align_up((size_t)gscratch * kPartials * sizeof(double), kAlign);
     L.off_ctr = o; o += kAlign;                 // two 32-bit step counters (ping-pong)
     L.total = o;
     return L;
@@ -225,6 +238,8 @@ struct lbm_ctx {
     Layout L;
     int64_t ntiles = 0;
     std::vector<int32_t> tile_inst;
+    std::vector<int32_t> group_inst;
+    int64_t ngroups = 0;
     bool external = false;
     char* base = nullptr;            // device memory (owned unless external)
     bool owned = false;
@@ -244,6 +259,8 @@ struct lbm_ctx {
     InstDesc* d_desc() const { return reinterpret_cast<InstDesc*>(base + L.off_desc); }
     RefState* d_ref() const { return reinterpret_cast<RefState*>(base + L.off_ref); }
     int32_t* d_tiles() const { return reinterpret_cast<int32_t*>(base + L.off_tiles); }
+    int32_t* d_groups() const { return reinterpret_cast<int32_t*>(base + L.off_groups); }
+    double* d_gpart() const { return reinterpret_cast<double*>(base + L.off_gpart); }
     double* d_snap() const { return K ? reinterpret_cast<double*>(base + L.off_snap) : nullptr; }
     double* d_part() const { return reinterpret_cast<double*>(base + L.off_part); }
     double* d_res() const { return reinterpret_cast<double*>(base + L.off_res); }
@@ -283,7 +300,9 @@ static bool valid(lbm_handle h) { return h && h->magic == kMagic; }
 static void build_tiles(lbm_ctx* h) {
     const Shape& s = h->shape;
     h->ntiles = 0;
+    h->ngroups = 0;
     h->tile_inst.clear();
+    h->group_inst.clear();
     for (size_t k = 0; k < h->inst.size(); ++k) {
         InstDesc& d = h->desc[k];
         const int tw = s.tile_w();
@@ -293,6 +312,10 @@ static void build_tiles(lbm_ctx* h) {
         d.ntiles = d.tiles_x * tys;
         h->ntiles += d.ntiles;
         h->tile_inst.insert(h->tile_inst.end(), (size_t)d.ntiles, (int32_t)k);
+        d.group_begin = (int32_t)h->ngroups;
+        d.ngroups = (d.ntiles + kGroup - 1) / kGroup;
+        h->ngroups += d.ngroups;
+        h->group_inst.insert(h->group_inst.end(), (size_t)d.ngroups, (int32_t)k);
     }
 }
 
@@ -303,6 +326,8 @@ static int upload_tables(lbm_ctx* h) {
     HIPCALL(h, hipMemcpyAsync(h->d_desc(), h->desc.data(), h->desc.size() * sizeof(InstDesc),
                               hipMemcpyHostToDevice, h->stream));
     HIPCALL(h, hipMemcpyAsync(h->d_tiles(), h->tile_inst.data(), h->tile_inst.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, h->stream));
+    HIPCALL(h, hipMemcpyAsync(h->d_groups(), h->group_inst.data(), h->group_inst.size() * sizeof(int32_t),
                               hipMemcpyHostToDevice, h->stream));
     HIPCALL(h, hipStreamSynchronize(h->stream));
     return LBM_OK;
@@ -695,7 +720,8 @@ static int issue_step(lbm_ctx* h, int64_t m, int src_k, hipStream_t st, int sche
         HIPCALL(h, launch_step(h->storage, h->shape, mode, a, h->L.nodes, st));
     }
     if (mode == kCheck)
-        HIPCALL(h, launch_finalize(h->d_desc(), h->d_ref(), (int)h->inst.size(), h->d_part(), h->d_res(), st));
+        HIPCALL(h, launch_finalize(h->d_desc(), h->d_groups(), (int)h->ngroups, h->d_ref(), (int)h->inst.size(),
+                                   h->d_part(), h->d_gpart(), h->d_res(), st));
     return LBM_OK;
 }
 
@@ -820,7 +846,7 @@ int lbm_totals(lbm_handle h, int32_t k, double out[3]) {
     if (rc) return rc;
     const InstDesc& d = h->desc[k];
     const int nparts = ((d.nx + 255) / 256) * d.ny;
-    HIPCALL(h, launch_finalize_range(h->d_mpart(), nparts, h->d_mres(), h->stream));
+    HIPCALL(h, launch_finalize_range(h->d_mpart(), nparts, h->d_gpart(), h->d_mres(), h->stream));
     double r[kPartials];
     HIPCALL(h, hipMemcpyAsync(r, h->d_mres(), sizeof r, hipMemcpyDeviceToHost, h->stream));
     HIPCALL(h, hipStreamSynchronize(h->stream));

@@ -13,6 +13,7 @@ import pytest
 
 import workloads as W
 from oracle import bloch, closed_forms as cf, ref
+from measure import front_radius
 
 CX = np.array([1, 0, -1, 0, 1, -1, -1, 1])
 CY = np.array([0, 1, 0, -1, 1, 1, -1, -1])
@@ -181,17 +182,6 @@ def test_second_sound_phase_speed():
     assert np.max(s.real) == pytest.approx(0.0, abs=1e-4)
 
 
-def _front_radius(prof):
-    """Outermost local maximum of significant height, refined by a parabola
-    (the slowly decaying diffusive hump left at the centre can be higher)."""
-    big = prof > 0.05 * prof.max()
-    peaks = [r for r in range(1, prof.size - 1)
-             if big[r] and prof[r] >= prof[r - 1] and prof[r] > prof[r + 1]]
-    r = peaks[-1]
-    a, b, c = prof[r - 1], prof[r], prof[r + 1]
-    return r + 0.5 * (a - c) / (a - 2 * b + c)
-
-
 def test_second_sound_front_speed_1d():
     """With normal scattering dominant (tau_R / tau_N ~ 2e5, as in the second
     sound case of Sec. 3.4) a plane heat pulse travels at v_g / sqrt(3):
@@ -202,7 +192,7 @@ def test_second_sound_front_speed_1d():
     radii = []
     for t in ts:
         T, _, _ = bloch.evolve_temperature_field(T0, int(t), 0.55, 1e5)
-        radii.append(_front_radius(T[0, nx // 2:] - 1.0))
+        radii.append(front_radius(T[0, nx // 2:] - 1.0))
     slope = np.polyfit(ts, radii, 1)[0]
     assert slope == pytest.approx(cf.second_sound_speed(), rel=5e-3)
 
@@ -216,7 +206,7 @@ def test_second_sound_front_speed_2d():
     radii = []
     for t in ts:
         T, _, _ = bloch.evolve_temperature_field(T0, int(t), 0.55, 1e5)
-        radii.append(_front_radius(T[n // 2, n // 2:] - 1.0))
+        radii.append(front_radius(T[n // 2, n // 2:] - 1.0))
     slope = np.polyfit(ts, radii, 1)[0]
     assert slope == pytest.approx(cf.second_sound_speed(), rel=0.03)
 
