@@ -152,3 +152,71 @@ def telegraph_rates(k: float, tau_r: float, tau_c: float) -> np.ndarray:
 def second_sound_speed() -> float:
     """v_g / sqrt(3) (Sec. 3.4), = sqrt(5)/3 lattice nodes per step."""
     return VG / math.sqrt(3.0)
+
+
+# --------------------------------------------------------------------------
+# Sec. 3.4, Appendix B: heat pulse through a plate, hydrodynamic model
+# (Eqs. 72-80) solved by the Laplace transform
+# --------------------------------------------------------------------------
+
+def heat_pulse_transforms(X, s, kn_n: float, kn_r: float, t_pulse: float = 100.0):
+    """Laplace transforms (Theta_bar, Q_bar) at positions X (0..1) and complex
+    s (broadcast against each other), Eqs. B9-B13 with the boundary data of
+    Eq. B7 (pulse of t_pulse in units of tau_N).
+
+    Eq. B10 with B12 is rewritten with decaying exponentials only,
+    C1 e^{AX} = -C2 e^{-A(2-X)}, so large |A| cannot overflow; A is the root
+    of Eq. B9 with positive real part."""
+    X = np.asarray(X, dtype=np.float64)
+    s = np.asarray(s, dtype=np.complex128)
+    kn_c = overall_knudsen(kn_n, kn_r)
+    A = np.sqrt((kn_r / kn_n * s + 1.0) / (kn_n * kn_r / (3.0 * s) + 4.0 / 15.0 * kn_c * kn_r))   # Eq. B9
+    A = np.where(A.real < 0, -A, A)
+    C2 = (1.0 - np.exp(-t_pulse * s)) / (s * (1.0 - np.exp(-2.0 * A)))                            # Eq. B11
+    e1, e2 = np.exp(-A * X), np.exp(-A * (2.0 - X))
+    Q = C2 * (e1 - e2)                                            # Eq. B10 with C1 = -C2 e^{-2A} (B12)
+    Theta = kn_n / s * C2 * A * (e1 + e2)                         # Eq. B13
+    return Theta, Q
+
+
+def heat_pulse_solution(X, t_star: float, kn_n: float, kn_r: float, t_pulse: float = 100.0,
+                        gamma_t: float = 3.0, n_terms: int = 200000, chunk: int = 20000):
+    """Theta(X, t*) and Q(X, t*) of the hydrodynamic model (Eqs. 77-80) by the
+    Riemann-sum inverse Laplace transform of Eqs. B14-B15 with gamma t* =
+    gamma_t (3 in the paper), summed over n_terms terms.  Theta = (T - T0) C_V
+    v_g / q0, Q = q_x / q0, t* = t / tau_N, X = x / d (Eq. 76)."""
+    X = np.atleast_1d(np.asarray(X, dtype=np.float64))
+    t = float(t_star)
+    gam = gamma_t / t
+    th0, q0 = heat_pulse_transforms(X, np.array([gam + 0j]), kn_n, kn_r, t_pulse)
+    sum_t = 0.5 * th0.real.copy()
+    sum_q = 0.5 * q0.real.copy()
+    for start in range(1, n_terms + 1, chunk):
+        n = np.arange(start, min(start + chunk, n_terms + 1), dtype=np.float64)
+        s = gam + 1j * np.pi * n / t
+        th, q = heat_pulse_transforms(X[None, :], s[:, None], kn_n, kn_r, t_pulse)
+        sign = np.where(n % 2 == 1, -1.0, 1.0)[:, None]
+        sum_t += (th * sign).real.sum(axis=0)
+        sum_q += (q * sign).real.sum(axis=0)
+    f = math.exp(gam * t) / t
+    return f * sum_t, f * sum_q
+
+
+def heat_pulse_diffusive_limit(X, t_star: float, kn_n: float, kn_r: float, t_pulse: float = 100.0):
+    """Theta(X, t*) of Eqs. 77-78 in the limit Kn_R << Kn_N with Kn_C Kn_R
+    negligible: Theta_t* = D Theta_XX, D = Kn_N Kn_R / 3, inflow Kn_N Q(0) with
+    Q(0) the pulse of Eq. 80, X = 1 insulated.  For a constant inflow F from
+    t* = 0 the solution is F t + (F/D)[(1 - X)^2/2 - 1/6]
+    - (2F/D) sum_n cos(n pi X) exp(-D n^2 pi^2 t) / (n pi)^2; the pulse is that
+    minus the same delayed by t_pulse."""
+    X = np.asarray(X, dtype=np.float64)
+    D, F = kn_n * kn_r / 3.0, kn_n
+    n = np.arange(1, 20001, dtype=np.float64)
+
+    def step(t):
+        if t <= 0.0:
+            return np.zeros_like(X)
+        series = (np.cos(np.pi * np.multiply.outer(X, n)) * (np.exp(-D * (n * np.pi) ** 2 * t) / (n * np.pi) ** 2)).sum(axis=-1)
+        return F * t + F / D * ((1.0 - X) ** 2 / 2.0 - 1.0 / 6.0) - 2.0 * F / D * series
+
+    return step(float(t_star)) - step(float(t_star) - t_pulse)

@@ -15,7 +15,7 @@
  *   - one step, in the paper's order: moments (Eqs. 53-54) -> equilibrium
  *     (Eq. 15) and source (Eq. 16) -> relaxation (Eq. 13 right-hand side) ->
  *     advection (Eq. 13 left-hand side) -> boundary treatment of the unknown
- *     populations after advection (Sec. 2.5: Eqs. 55, 58, 59-60);
+ *     populations after advection (Sec. 2.5: Eqs. 55, 57, 58, 59-60);
  *   - lattice units: dx = dt = c = 1 (so the group speed is sqrt(5/3), Eq. 48),
  *     tau = tau_C/dt + 1/2 (Eq. 49) with 1/tau_C = 1/tau_N + 1/tau_R (Sec. 2.1),
  *     tau_r = tau_R/dt (Sec. 2.4).
@@ -32,7 +32,7 @@
 #endif
 
 /* Boundary kinds (Sec. 2.5). */
-enum { ORA_PERIODIC = 0, ORA_ISOTHERMAL = 1, ORA_DIFFUSE = 2, ORA_GRADIENT = 3 };
+enum { ORA_PERIODIC = 0, ORA_ISOTHERMAL = 1, ORA_DIFFUSE = 2, ORA_GRADIENT = 3, ORA_HEATFLUX = 4 };
 
 typedef struct {
     int nx, ny;
@@ -42,6 +42,7 @@ typedef struct {
     double t0;             /* reference temperature (at x = 0 for the gradient seam) */
     double grad_x;         /* gradient seam: temperature drop per node along +x */
     double t_wall[4];      /* isothermal walls: x=0, x=nx-1, y=0, y=ny-1 */
+    double q_wall[4];      /* heat-flux walls: heat flux q_0 into the domain (Eq. 56), same order */
 } ora_case;
 
 /* D2Q8 velocities, Eq. 14 with c = 1, in the paper's numbering 1..8
@@ -58,14 +59,15 @@ static double a_w(int i) { return i < 4 ? 1.0 / 5.0 : 1.0 / 20.0; }
 
 /* Validity of a case: sizes, relaxation times, and the boundary pairs whose
  * treatment the paper defines (no corners: walls on at most one axis; the
- * gradient seam only along x, with periodic or diffuse walls across it). */
+ * gradient seam only along x, with periodic, diffuse or heat-flux walls across
+ * it). */
 int ora_check(const ora_case* c)
 {
     if (!c || c->nx < 2 || c->ny < 2) return -1;
     if (!(c->tau_n > 0.0) || !(c->tau_r > 0.0) || !(c->cv > 0.0)) return -1;
-    if (c->bc_x < 0 || c->bc_x > 3 || c->bc_y < 0 || c->bc_y > 2) return -1;
-    int wx = (c->bc_x == ORA_ISOTHERMAL || c->bc_x == ORA_DIFFUSE);
-    int wy = (c->bc_y == ORA_ISOTHERMAL || c->bc_y == ORA_DIFFUSE);
+    if (c->bc_x < 0 || c->bc_x > 4 || c->bc_y < 0 || c->bc_y > 4 || c->bc_y == ORA_GRADIENT) return -1;
+    int wx = (c->bc_x == ORA_ISOTHERMAL || c->bc_x == ORA_DIFFUSE || c->bc_x == ORA_HEATFLUX);
+    int wy = (c->bc_y == ORA_ISOTHERMAL || c->bc_y == ORA_DIFFUSE || c->bc_y == ORA_HEATFLUX);
     if (wx && wy) return -2;
     if (c->bc_x == ORA_GRADIENT && c->bc_y == ORA_ISOTHERMAL) return -2;
     return 0;
@@ -167,6 +169,25 @@ static void diffuse_node(const ora_case* c, double* e, int x, int y, int nxo, in
             e[IDX(c, i, x, y)] = omega_w(i) / wsum * incident;
 }
 
+/* Heat-flux boundary (Eq. 57) at one wall node: as Eq. 58, with the incident
+ * sum raised by q_0 / c times (2 tau_r + 1) / (2 tau_r), so that Eq. 56 holds
+ * for the populations after the treatment (c = 1; the factor is 1 when tau_r
+ * is infinite). */
+static void heatflux_node(const ora_case* c, double* e, int x, int y, int nxo, int nyo, double q0)
+{
+    double incident = 0.0, wsum = 0.0;
+    for (int i = 0; i < 8; ++i) {
+        int cn = CX[i] * nxo + CY[i] * nyo;
+        if (cn > 0) incident += e[IDX(c, i, x, y)];
+        if (cn < 0) wsum += omega_w(i);
+    }
+    const double inv_factor = isinf(c->tau_r) ? 1.0 : (2.0 * c->tau_r + 1.0) / (2.0 * c->tau_r);
+    const double total = incident + q0 * inv_factor;
+    for (int i = 0; i < 8; ++i)
+        if (CX[i] * nxo + CY[i] * nyo < 0)
+            e[IDX(c, i, x, y)] = omega_w(i) / wsum * total;
+}
+
 /* Advance n steps.  e: state at the start of a step (in/out), work: scratch
  * of the same size (8*ny*nx doubles). */
 void ora_run(const ora_case* c, double* e, double* work, long nsteps)
@@ -227,6 +248,11 @@ void ora_run(const ora_case* c, double* e, double* work, long nsteps)
                 diffuse_node(c, e, 0, y, -1, 0);                                /* Eq. 58 */
                 diffuse_node(c, e, nx - 1, y, 1, 0);
             }
+        } else if (c->bc_x == ORA_HEATFLUX) {
+            for (int y = 0; y < ny; ++y) {
+                heatflux_node(c, e, 0, y, -1, 0, c->q_wall[0]);                 /* Eq. 57 */
+                heatflux_node(c, e, nx - 1, y, 1, 0, c->q_wall[1]);
+            }
         }
         if (c->bc_y == ORA_ISOTHERMAL) {
             for (int x = 0; x < nx; ++x)
@@ -238,6 +264,11 @@ void ora_run(const ora_case* c, double* e, double* work, long nsteps)
             for (int x = 0; x < nx; ++x) {
                 diffuse_node(c, e, x, 0, 0, -1);
                 diffuse_node(c, e, x, ny - 1, 0, 1);
+            }
+        } else if (c->bc_y == ORA_HEATFLUX) {
+            for (int x = 0; x < nx; ++x) {
+                heatflux_node(c, e, x, 0, 0, -1, c->q_wall[2]);
+                heatflux_node(c, e, x, ny - 1, 0, 1, c->q_wall[3]);
             }
         }
     }

@@ -6,7 +6,7 @@ CPU-baseline leg of the benchmark, never by the product package.
 The stepper follows the paper's order for one step (Sec. 2.2-2.5): moments
 (Eqs. 53-54), equilibrium and source (Eqs. 15-16), relaxation (Eq. 13),
 advection, then the boundary treatment of the unknown populations (Eqs. 55,
-58, 59-60).  The kept state is the pre-collision distribution at time n, so
+57, 58, 59-60).  The kept state is the pre-collision distribution at time n, so
 ``moments()`` after ``run(n)`` are the fields at time n.
 """
 from __future__ import annotations
@@ -20,7 +20,7 @@ import numpy as np
 
 from . import build as _build
 
-_BC = {"periodic": 0, "isothermal": 1, "diffuse": 2, "gradient": 3}
+_BC = {"periodic": 0, "isothermal": 1, "diffuse": 2, "gradient": 3, "heatflux": 4}
 
 
 class _Case(ctypes.Structure):
@@ -29,7 +29,7 @@ class _Case(ctypes.Structure):
                 ("cv", ctypes.c_double),
                 ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int),
                 ("t0", ctypes.c_double), ("grad_x", ctypes.c_double),
-                ("t_wall", ctypes.c_double * 4)]
+                ("t_wall", ctypes.c_double * 4), ("q_wall", ctypes.c_double * 4)]
 
 
 _lib = None
@@ -77,6 +77,8 @@ def make_case(case) -> _Case:
     c.grad_x = float(getattr(case, "grad_x", 0.0))
     for k, v in enumerate(getattr(case, "t_wall", (0.0,) * 4)):
         c.t_wall[k] = float(v)
+    for k, v in enumerate(getattr(case, "q_wall", (0.0,) * 4)):
+        c.q_wall[k] = float(v)
     return c
 
 
@@ -107,6 +109,11 @@ class Oracle:
         lib().ora_run(ctypes.byref(self.c), _dptr(self.e), _dptr(self.work), int(n))
         self.steps += int(n)
         return time.perf_counter() - t
+
+    def set_wall_flux(self, wall: int, q0: float) -> None:
+        """Heat flux into the domain at a heat-flux wall (Eq. 56) for the steps
+        that follow; wall 0: x = 0, 1: x = nx-1, 2: y = 0, 3: y = ny-1."""
+        self.c.q_wall[wall] = float(q0)
 
     def moments(self) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
         ny, nx = self.case.ny, self.case.nx

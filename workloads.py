@@ -49,6 +49,7 @@ class Case:
     t0: float = 1.0
     cv: float = 1.0
     t_wall: Tuple[float, float, float, float] = (0.0, 0.0, 0.0, 0.0)
+    q_wall: Tuple[float, float, float, float] = (0.0, 0.0, 0.0, 0.0)
     grad_x: float = 0.0
     steps: int = 0
     init: str = "uniform"          # "uniform" | "gaussian" | "modes" | "field"
@@ -190,6 +191,21 @@ def poiseuille_case(tau_n: float, ratio: float, nx: int = 1024, ny: int = 256,
     y = 0 and y = ny-1, start from the ramp (zero deviation)."""
     return Case(f"poiseuille_tn{tau_n}_r{ratio:g}", nx, ny, tau_n, tau_n * ratio,
                 bc_x="gradient", bc_y="diffuse", t0=t0, grad_x=grad_x, steps=steps)
+
+
+# Sec. 3.4 heat pulse: Kn_N and the three Kn_R values, pulse length 100 tau_N
+HEAT_PULSE_KN_N = 1.29e-3
+HEAT_PULSE_KN_R = (1.29e3, 1.29, 1.29e-3)
+
+
+def heat_pulse_case(tau_n: float, tau_r: float, nodes: int = 401, ny: int = 3,
+                    q0: float = 1e-3, t0: float = 1.0) -> Case:
+    """Plate of nodes - 1 spacings along x, heat-flux wall at x = 0 carrying q0
+    into the plate (switched off by the caller after the pulse), adiabatic
+    (heat-flux wall with zero flux) at x = nodes - 1, periodic in y (1D), at
+    T0 everywhere with no heat flux."""
+    return Case(f"heat_pulse_{nodes}_{tau_r:g}", nodes, ny, tau_n, tau_r, bc_x="heatflux",
+                bc_y="periodic", t0=t0, q_wall=(q0, 0.0, 0.0, 0.0))
 
 
 def poiseuille_cases(**kw) -> List[Case]:
