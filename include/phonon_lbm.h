@@ -82,14 +82,20 @@ typedef enum {
  *                T_ref(x) = t0 - grad_x * x (with the non-equilibrium share
  *                the ramp sustains and a uniform flux), so the seam needs no
  *                branch and the stored values are the departures from it.
- * Supported pairs: (any x, PERIODIC y), (PERIODIC x, ISOTHERMAL or DIFFUSE y),
- * (GRADIENT x, DIFFUSE y).  Walls on both axes need corners, which the paper
- * leaves undefined: LBM_EUNSUPPORTED. */
+ *   HEATFLUX   : prescribed heat flux q_0 into the domain (Eq. 56): the
+ *                populations leaving the wall share the incident energy plus
+ *                q_0 (2 tau_r + 1)/(2 tau_r) in proportion to omega_i (Eq. 57),
+ *                so the heat flux of the wall node is exactly q_0.  q_0 is set
+ *                per wall with lbm_set_wall_flux (0 until then: DIFFUSE).
+ * Supported pairs: (any x, PERIODIC y), (PERIODIC x, ISOTHERMAL, DIFFUSE or
+ * HEATFLUX y), (GRADIENT x, DIFFUSE or HEATFLUX y).  Walls on both axes need
+ * corners, which the paper leaves undefined: LBM_EUNSUPPORTED. */
 typedef enum {
     LBM_BC_PERIODIC = 0,
     LBM_BC_ISOTHERMAL = 1,
     LBM_BC_DIFFUSE = 2,
-    LBM_BC_GRADIENT = 3
+    LBM_BC_GRADIENT = 3,
+    LBM_BC_HEATFLUX = 4
 } lbm_bc;
 
 /* How lbm_step issues the per-step work of a multi-instance handle. */
@@ -245,6 +251,19 @@ int lbm_last_check(lbm_handle h, int32_t inst, lbm_check_info* out);
  * out[2] = 1 - rho = 2/(2 tau_r + 1) (FP32-rounded), out[3] = s,
  * out[4] = tau (exact), out[5] = rho = (2 tau_r - 1)/(2 tau_r + 1) (exact). */
 int lbm_coefficients(lbm_handle h, int32_t inst, double out[6]);
+
+/* Heat flux q0 (energy per unit length and time step, lattice units) into the
+ * domain through wall `wall` of instance `inst` (0: x = 0, 1: x = nx-1,
+ * 2: y = 0, 3: y = ny-1), which must be a HEATFLUX wall (Eqs. 56-57).  It
+ * applies to the steps enqueued after the call (the value is written by a
+ * one-thread kernel on the handle's stream, so no synchronisation is needed
+ * and captured graphs replay with the current value); it survives lbm_init.
+ * Switching q0 to 0 after some steps gives the heat pulse of Sec. 3.4.
+ * The automatic FP16 scale is taken from the initial field at lbm_init and
+ * knows nothing of later wall fluxes: with a uniform start give the instance
+ * an explicit scale (about the expected temperature rise / 2^11).
+ * Errors: EINVAL (index, wall not HEATFLUX, non-finite q0), ESTATE (no memory). */
+int lbm_set_wall_flux(lbm_handle h, int32_t inst, int32_t wall, double q0);
 
 /* Select how multi-instance steps are issued (lbm_schedule).  GRAPH captures
  * K batched steps (the check interval, or 64 when checks are off) once per

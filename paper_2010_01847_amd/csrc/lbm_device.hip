@@ -267,12 +267,14 @@ __device__ __forceinline__ void relax_sr_f32(const float g[8], const InstDesc& d
 //   diffuse (Eq. 58): the three populations leaving a wall get 4/5, 1/10, 1/10
 //     (omega_i over the sum of the leaving omegas) of the incident sum S; the
 //     axis share is formed as S - 2 (S/10) so the three add up to S;
+//   heat flux (Eq. 57): the same with S raised by q_0 / beta (wall_q, 0 for a
+//     diffuse wall);
 //   isothermal (Eq. 55): all eight take omega_i C_V (T_s - T_ref) / s.
 __device__ __forceinline__ void boundary(float g[8], const InstDesc& d, float kd, int x, int y) {
-    if (d.bc_y == 2) {
+    if (d.bc_y == 2 || d.bc_y == 4) {
         const bool lo = (y == 0), hi = (y == d.ny - 1);
-        const float Sl = g[3] + g[6] + g[7];      // incident at y = 0: 4, 7, 8
-        const float Sh = g[1] + g[4] + g[5];      // incident at y = ny-1: 2, 5, 6
+        const float Sl = (g[3] + g[6] + g[7]) + d.wall_q[2];      // incident at y = 0: 4, 7, 8
+        const float Sh = (g[1] + g[4] + g[5]) + d.wall_q[3];      // incident at y = ny-1: 2, 5, 6
         const float dl = 0.1f * Sl, dh = 0.1f * Sh;
         const float al = Sl - dl - dl, ah = Sh - dh - dh;
         // the reference state's diagonal shares (c_ix p_diag) are not part of
@@ -287,10 +289,10 @@ __device__ __forceinline__ void boundary(float g[8], const InstDesc& d, float kd
 #pragma unroll
         for (int i = 0; i < 8; ++i) g[i] = w ? (i < 4 ? a : b) : g[i];
     }
-    if (d.bc_x == 2) {
+    if (d.bc_x == 2 || d.bc_x == 4) {
         const bool lo = (x == 0), hi = (x == d.nx - 1);
-        const float Sl = g[2] + g[5] + g[6];      // incident at x = 0: 3, 6, 7
-        const float Sh = g[0] + g[4] + g[7];      // incident at x = nx-1: 1, 5, 8
+        const float Sl = (g[2] + g[5] + g[6]) + d.wall_q[0];      // incident at x = 0: 3, 6, 7
+        const float Sh = (g[0] + g[4] + g[7]) + d.wall_q[1];      // incident at x = nx-1: 1, 5, 8
         const float dl = 0.1f * Sl, dh = 0.1f * Sh;
         const float al = Sl - dl - dl, ah = Sh - dh - dh;
         g[0] = lo ? al : g[0];  g[4] = lo ? dl : g[4];  g[7] = lo ? dl : g[7];
@@ -443,7 +445,7 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t sna
             for (int k = 0; k < V; ++k) apply_shift(g[k], rv);
         }
         const bool edge_y = (d.bc_y != 0) && (y == 0 || y == ny - 1);
-        const bool edge_x = (d.bc_x == 1 || d.bc_x == 2) && (x0 == 0 || x0 + V > nx - 1);
+        const bool edge_x = (d.bc_x == 1 || d.bc_x == 2 || d.bc_x == 4) && (x0 == 0 || x0 + V > nx - 1);
 #pragma unroll
         for (int k = 0; k < V; ++k) {
             if (edge_y || edge_x) boundary(g[k], d, rv.wall_kd, x0 + k, y);
@@ -647,7 +649,7 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
         }
         if (a.apply_shift) apply_shift(g, rv);
         const bool edge_y = (d.bc_y != 0) && (y == 0 || y == ny - 1);
-        const bool edge_x = (d.bc_x == 1 || d.bc_x == 2) && (xc == 0 || xc + 64 >= nx);
+        const bool edge_x = (d.bc_x == 1 || d.bc_x == 2 || d.bc_x == 4) && (xc == 0 || xc + 64 >= nx);
         if (edge_y || edge_x) boundary(g, d, rv.wall_kd, x, y);
         if (MODE != kPlain) {
             double E = 0.0;
@@ -1054,6 +1056,13 @@ hipError_t launch_finalize(const InstDesc* d_desc, const int32_t* group_inst, in
                            hipStream_t st) {
     hipLaunchKernelGGL(group_reduce_kernel, dim3(ngroups), dim3(256), 0, st, d_desc, group_inst, partials, gpart);
     hipLaunchKernelGGL(finalize_kernel, dim3(ninst), dim3(256), 0, st, d_desc, d_ref, gpart, results);
+    return hipGetLastError();
+}
+
+__global__ void set_float_kernel(float* dst, float v) { *dst = v; }
+
+hipError_t launch_set_float(float* dst, float v, hipStream_t st) {
+    hipLaunchKernelGGL(set_float_kernel, dim3(1), dim3(1), 0, st, dst, v);
     return hipGetLastError();
 }
 

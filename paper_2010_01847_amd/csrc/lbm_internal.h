@@ -40,6 +40,7 @@ struct alignas(64) InstDesc {
     float inv_tau;          // 1 / tau: decay of the non-equilibrium share per step
     float sigma;            // 1 - rho = 2 / (2 tau_r + 1): decay of the flux share per step
     float wall_g[4];        // C_V (T_wall - T_ref) / s for isothermal walls (times omega_i)
+    float wall_q[4];        // q_0 / (beta s) for heat-flux walls (added to the incident sum)
     double s_cv;            // s / C_V   (dT = s E / C_V)
     double s_beta;          // s * beta  (q = q_ref + s beta j)
     double s;               // storage scale
@@ -152,6 +153,10 @@ hipError_t launch_init(int storage, const InstDesc* d_desc, const RefState* d_re
 hipError_t launch_finalize(const InstDesc* d_desc, const int32_t* group_inst, int ngroups, RefState* d_ref,
                            int ninst, const double* partials, double* gpart, double* results,
                            hipStream_t st);
+
+// One-thread kernel writing *dst = v on the stream (stream-ordered updates of
+// descriptor fields between steps).
+hipError_t launch_set_float(float* dst, float v, hipStream_t st);
 
 // Reduction of nparts moments-kernel partials (tiles of 256 nodes) of one
 // instance, through gpart (ceil(nparts / kGroup) records).

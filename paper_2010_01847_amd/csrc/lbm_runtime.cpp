@@ -8,6 +8,7 @@
 #include "lbm_internal.h"
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -137,13 +138,16 @@ Status validate_instance(const lbm_instance& in, int k) {
         snprintf(b, sizeof b, "instance %d: cv must be finite and >= 0", k);
         return {LBM_EINVAL, b};
     }
-    if (in.bc_x < 0 || in.bc_x > 3 || in.bc_y < 0 || in.bc_y > 2) {
+    if (in.bc_x < 0 || in.bc_x > 4 || in.bc_y < 0 || in.bc_y > 4 || in.bc_y == LBM_BC_GRADIENT) {
         snprintf(b, sizeof b, "instance %d: bad boundary kind (bc_x %d, bc_y %d; GRADIENT is x only)",
                  k, in.bc_x, in.bc_y);
         return {LBM_EINVAL, b};
     }
-    const bool wx = in.bc_x == LBM_BC_ISOTHERMAL || in.bc_x == LBM_BC_DIFFUSE;
-    const bool wy = in.bc_y == LBM_BC_ISOTHERMAL || in.bc_y == LBM_BC_DIFFUSE;
+    auto walled = [](int bc) {
+        return bc == LBM_BC_ISOTHERMAL || bc == LBM_BC_DIFFUSE || bc == LBM_BC_HEATFLUX;
+    };
+    const bool wx = walled(in.bc_x);
+    const bool wy = walled(in.bc_y);
     if (wx && wy) {
         snprintf(b, sizeof b, "instance %d: walls on both axes need corner treatment (undefined)", k);
         return {LBM_EUNSUPPORTED, b};
@@ -232,6 +236,7 @@ struct lbm_ctx {
     std::vector<lbm_instance> inst;
     std::vector<InstDesc> desc;
     std::vector<RefState> ref;       // initial reference states (the device copy evolves)
+    std::vector<std::array<double, 4>> qwall;   // heat flux into the domain per wall (HEATFLUX walls)
     std::vector<Coeffs> co;
     std::vector<char> inited;
     Shape shape;
@@ -373,6 +378,7 @@ static void fill_desc(lbm_ctx* h, size_t k, double s) {
     d.inv_tau = (float)(1.0 / c.tau);
     d.sigma = (float)c.one_minus_rho;
     for (int w = 0; w < 4; ++w) d.wall_g[w] = (float)(in.cv * (in.t_wall[w] - in.t0) / s);
+    for (int w = 0; w < 4; ++w) d.wall_q[w] = (float)(h->qwall[k][w] / (c.beta * s));
     d.s = s;
     d.cv = in.cv;
     d.s_cv = s / in.cv;
@@ -479,6 +485,7 @@ int lbm_create(const lbm_config* cfg, lbm_handle* out) {
     h->L = layout_of(v, h->storage, h->K, h->layout);
     h->desc.resize(v.size());
     h->ref.resize(v.size());
+    h->qwall.assign(v.size(), std::array<double, 4>{0.0, 0.0, 0.0, 0.0});
     h->co.resize(v.size());
     h->inited.assign(v.size(), 0);
     size_t eoff = 0;
@@ -897,6 +904,22 @@ int lbm_coefficients(lbm_handle h, int32_t k, double out[6]) {
     out[3] = d.s;
     out[4] = c.tau;
     out[5] = c.rho;
+    return LBM_OK;
+}
+
+int lbm_set_wall_flux(lbm_handle h, int32_t k, int32_t wall, double q0) {
+    if (!valid(h)) return LBM_EINVAL;
+    int rc = check_inst(h, k);
+    if (rc) return rc;
+    if (wall < 0 || wall > 3) return h->fail(LBM_EINVAL, "wall must be 0..3 (x=0, x=nx-1, y=0, y=ny-1)");
+    const lbm_instance& in = h->inst[k];
+    if ((wall < 2 ? in.bc_x : in.bc_y) != LBM_BC_HEATFLUX)
+        return h->fail(LBM_EINVAL, "wall is not a HEATFLUX wall");
+    if (!std::isfinite(q0)) return h->fail(LBM_EINVAL, "q0 must be finite");
+    h->qwall[k][wall] = q0;
+    InstDesc& d = h->desc[k];
+    d.wall_q[wall] = (float)(q0 / (h->co[k].beta * d.s));
+    HIPCALL(h, launch_set_float(&h->d_desc()[k].wall_q[wall], d.wall_q[wall], h->stream));
     return LBM_OK;
 }
 

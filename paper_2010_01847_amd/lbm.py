@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libphonon_lbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_ESTATE, LBM_EUNSUPPORTED, LBM_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 LBM_F32, LBM_F16, LBM_BF16, LBM_F16_SPLIT, LBM_BF16_SPLIT = 0, 1, 2, 3, 4
-LBM_BC_PERIODIC, LBM_BC_ISOTHERMAL, LBM_BC_DIFFUSE, LBM_BC_GRADIENT = 0, 1, 2, 3
+LBM_BC_PERIODIC, LBM_BC_ISOTHERMAL, LBM_BC_DIFFUSE, LBM_BC_GRADIENT, LBM_BC_HEATFLUX = 0, 1, 2, 3, 4
 LBM_SCHED_BATCHED, LBM_SCHED_PER_INSTANCE, LBM_SCHED_GRAPH = 0, 1, 2
 LBM_FLAG_EXTERNAL_MEMORY = 0x1
 LBM_FLAG_STOCHASTIC_ROUNDING = 0x2
@@ -34,7 +34,7 @@ LAYOUT = {"auto": LBM_LAYOUT_AUTO, "planes": LBM_LAYOUT_PLANES, "chunked": LBM_L
 STORAGE = {"f32": LBM_F32, "f16": LBM_F16, "bf16": LBM_BF16,
            "f16_split": LBM_F16_SPLIT, "bf16_split": LBM_BF16_SPLIT}
 BC = {"periodic": LBM_BC_PERIODIC, "isothermal": LBM_BC_ISOTHERMAL, "diffuse": LBM_BC_DIFFUSE,
-      "gradient": LBM_BC_GRADIENT}
+      "gradient": LBM_BC_GRADIENT, "heatflux": LBM_BC_HEATFLUX}
 ERRNAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EHIP", -4: "LBM_ESTATE",
             -5: "LBM_EUNSUPPORTED", -6: "LBM_ENONFINITE"}
 
@@ -84,6 +84,7 @@ SIGNATURES = [
     ("lbm_residual", ctypes.c_int, [_P, ctypes.c_int32, _D]),
     ("lbm_last_check", ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(lbm_check_info)]),
     ("lbm_coefficients", ctypes.c_int, [_P, ctypes.c_int32, _D]),
+    ("lbm_set_wall_flux", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]),
     ("lbm_set_schedule", ctypes.c_int, [_P, ctypes.c_int32]),
     ("lbm_set_launch_shape", ctypes.c_int, [_P, ctypes.POINTER(lbm_launch_shape)]),
     ("lbm_get_launch_shape", ctypes.c_int, [_P, ctypes.POINTER(lbm_launch_shape)]),
@@ -204,6 +205,10 @@ def lbm_coefficients(h, inst: int) -> dict:
     out = np.zeros(6)
     _check(library().lbm_coefficients(h, inst, _dptr(out)), "lbm_coefficients", h)
     return dict(inv_tau=out[0], beta=out[1], one_minus_rho=out[2], scale=out[3], tau=out[4], rho=out[5])
+
+
+def lbm_set_wall_flux(h, inst: int, wall: int, q0: float) -> None:
+    _check(library().lbm_set_wall_flux(h, int(inst), int(wall), float(q0)), "lbm_set_wall_flux", h)
 
 
 def lbm_set_schedule(h, schedule: int) -> None:
@@ -351,6 +356,11 @@ class Lattice:
 
     def coefficients(self, inst: int = 0) -> dict:
         return lbm_coefficients(self.h, inst)
+
+    def set_wall_flux(self, inst: int, wall: int, q0: float) -> None:
+        """Heat flux into the domain through a HEATFLUX wall (0: x=0, 1: x=nx-1,
+        2: y=0, 3: y=ny-1) for the steps enqueued afterwards."""
+        lbm_set_wall_flux(self.h, inst, wall, float(q0))
 
     def set_schedule(self, name: str) -> None:
         lbm_set_schedule(self.h, {"batched": LBM_SCHED_BATCHED, "per_instance": LBM_SCHED_PER_INSTANCE,

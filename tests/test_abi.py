@@ -97,6 +97,9 @@ def test_required_bytes_and_layout():
     (dict(nx=8, ny=8, tau_n=0.6, tau_r=0.8, bc_x="gradient", bc_y="isothermal"), P.LBM_EUNSUPPORTED),
     (dict(nx=8, ny=8, tau_n=0.6, tau_r=0.8, bc_y=P.LBM_BC_GRADIENT), P.LBM_EINVAL),
     (dict(nx=8, ny=8, tau_n=0.6, tau_r=0.8, scale=3.0), P.LBM_EINVAL),
+    (dict(nx=8, ny=8, tau_n=0.6, tau_r=0.8, bc_x="heatflux", bc_y="diffuse"), P.LBM_EUNSUPPORTED),
+    (dict(nx=8, ny=8, tau_n=0.6, tau_r=0.8, bc_x="heatflux", bc_y="isothermal"), P.LBM_EUNSUPPORTED),
+    (dict(nx=8, ny=8, tau_n=0.6, tau_r=0.8, bc_x=5), P.LBM_EINVAL),
 ])
 def test_config_validation(kw, code):
     with pytest.raises(P.LBMError) as e:
@@ -116,6 +119,11 @@ def test_bad_config_fields():
     cfg.n_instances = 0
     with pytest.raises(P.LBMError):
         P.lbm_required_bytes(cfg)
+
+
+def test_heatflux_pairs_accepted():
+    for bx, by in (("heatflux", "periodic"), ("periodic", "heatflux"), ("gradient", "heatflux")):
+        assert P.lbm_required_bytes(_cfg([P.make_instance(16, 8, 0.6, 0.8, bc_x=bx, bc_y=by)])) > 0
 
 
 def test_tau_r_infinite_and_small_accepted():

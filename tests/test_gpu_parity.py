@@ -207,6 +207,108 @@ def test_channel_gradient_diffuse_3000_steps():
         assert e_q < 5e-3 and e_t < 5e-3
 
 
+# ---------------------------------------------------------------- heat-flux walls
+
+def _pulse_run(case, pulse, stops, **lat_kw):
+    """GPU heat pulse: flux q0 into x = 0 for `pulse` steps, then 0; (dT, qx,
+    qy) at each step count in `stops`."""
+    sched = lat_kw.pop("schedule", None)
+    scale = lat_kw.pop("scale", 0.0)
+    lat = Lattice([instance_from_case(case, scale)], **lat_kw)
+    if sched:
+        lat.set_schedule(sched)
+    lat.init(0)
+    lat.set_wall_flux(0, 0, case.q_wall[0])
+    out = []
+    for n in stops:
+        if lat.steps < pulse <= n:
+            lat.step(pulse - lat.steps)
+            lat.set_wall_flux(0, 0, 0.0)
+        lat.step(n - lat.steps)
+        out.append(lat.moments(0))
+    lat.close()
+    return out
+
+
+@pytest.mark.parametrize("kn_r", W.HEAT_PULSE_KN_R)
+def test_heat_pulse_401x3(kn_r):
+    """The heat pulse of Sec. 3.4 (401 x 3 plate, heat-flux wall switched off
+    after 100 tau_N, adiabatic far wall) against the oracle at 100, 280 and 500
+    steps: FP32 (batched, and graph replay with check steps every 20, equal
+    bits), split FP16 (both roundings)."""
+    tn, tr = cf.lattice_relaxation_times(400, W.HEAT_PULSE_KN_N, kn_r)
+    case = W.heat_pulse_case(tn, tr)
+    pulse = round(100 * tn)
+    stops = [100, 280, 500]
+    o = ref.Oracle(case)
+    ora = []
+    for n in stops:
+        if o.steps < pulse <= n:
+            o.run(pulse - o.steps)
+            o.set_wall_flux(0, 0.0)
+        o.run(n - o.steps)
+        T, qx, qy = o.moments()
+        ora.append((T - case.t0, qx, qy))
+    g = _pulse_run(case, pulse, stops)
+    gg = _pulse_run(case, pulse, stops, check_interval=20, schedule="graph")
+    # the plate starts uniform, so FP16 needs an explicit scale: the pulse
+    # raises T by ~2e-3, so s = 2^-20 keeps the stored values near 2^11
+    gs = _pulse_run(case, pulse, stops, storage="f16_split", scale=2.0 ** -20)
+    gsr = _pulse_run(case, pulse, stops, storage="f16_split", scale=2.0 ** -20, rounding="stochastic", seed=3)
+    for n, a, b, c, d, r in zip(stops, g, gg, gs, gsr, ora):
+        e = eps(case, a, r)
+        e16, e16s = eps(case, c, r), eps(case, d, r)
+        log(f"heat pulse kn_r={kn_r:g} n={n}: f32 eps={e[0]:.3e}/{e[1]:.3e}  f16_split eps={e16[0]:.3e}/{e16[1]:.3e}"
+            f"  (stochastic {e16s[0]:.3e}/{e16s[1]:.3e})")
+        assert max(e) < 1e-5
+        assert max(e16) < 5e-3 and max(e16s) < 5e-3
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v)
+        # Eq. 56 at the heated wall node: q_x is q0 during the pulse, 0 after
+        assert np.allclose(a[1][:, 0], 0.0, atol=1e-6 * case.q_wall[0])
+
+
+def test_heatflux_walls_across_y():
+    """Heat-flux walls at y = 0 and y = ny - 1 (periodic x) from a rough random
+    state, and a gradient channel with one heated wall; 60 steps against the
+    oracle, with the flux changed half way."""
+    kw = dict(bc_x="periodic", bc_y="heatflux")
+    case, T0, qx, qy = _random_case(75, 46, 0.6, 7.0, 33, **kw)
+    chan = W.Case("chan_hf", 70, 40, 0.7, 40.0, bc_x="gradient", bc_y="heatflux", grad_x=1e-3)
+    for c, init, q in ((case, (T0, qx, qy), (2e-3, 5e-4)), (chan, (None, None, None), (1e-3, 0.0))):
+        o = ref.Oracle(c, *init)
+        lat = Lattice([instance_from_case(c)], check_interval=10)
+        lat.init(0, *init)
+        for w, v in zip((2, 3), q):
+            o.set_wall_flux(w, v)
+            lat.set_wall_flux(0, w, v)
+        o.run(30)
+        lat.step(30)
+        o.set_wall_flux(2, -q[0])
+        lat.set_wall_flux(0, 2, -q[0])
+        o.run(30)
+        lat.step(30)
+        T, qxo, qyo = o.moments()
+        ref_f = (T - np.tile(c.t_ref(), (c.ny, 1)), qxo, qyo)
+        got = lat.moments(0)
+        lat.close()
+        e_t, e_q = eps(c, got, ref_f)
+        log(f"heat-flux y walls {c.name}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
+        assert e_t < 1e-5 and e_q < 1e-5
+        assert np.allclose(got[2][0], -q[0], rtol=1e-5)
+
+
+def test_set_wall_flux_errors():
+    case = W.Case("e", 16, 8, 0.6, 0.8, bc_x="heatflux")
+    lat = Lattice([instance_from_case(case)])
+    for args in ((0, 2, 1e-3), (0, 4, 1e-3), (1, 0, 1e-3), (0, 0, float("nan"))):
+        with pytest.raises(LBMError) as e:
+            lat.set_wall_flux(*args)
+        assert e.value.code == LBM_EINVAL
+    lat.set_wall_flux(0, 1, 1e-3)
+    lat.close()
+
+
 def test_totals_and_invariants():
     """FP64 totals: energy constant up to FP32 storage rounding; total heat flux
     multiplied by rho per step (periodic)."""
