@@ -220,3 +220,27 @@ def heat_pulse_diffusive_limit(X, t_star: float, kn_n: float, kn_r: float, t_pul
         return F * t + F / D * ((1.0 - X) ** 2 / 2.0 - 1.0 / 6.0) - 2.0 * F / D * series
 
     return step(float(t_star)) - step(float(t_star) - t_pulse)
+
+
+# --------------------------------------------------------------------------
+# Sec. 3.1.2: square with a heat flux on the top side, Fourier solution
+# --------------------------------------------------------------------------
+
+def square_eq65_67(X, Y, n_terms: int = 4000):
+    """(Theta, Q_x, Q_y) / Q0 of Eqs. 65-67 (Fourier's law in the unit square,
+    Theta = 0 on X = 0, X = 1, Y = 0, heat flux Q0 into the square through
+    Y = 1).  The hyperbolic ratios are written with decaying exponentials
+    (sinh(n pi Y) / cosh(n pi) and cosh(n pi Y) / cosh(n pi)), which is the
+    same series without overflow."""
+    X = np.asarray(X, dtype=np.float64)[..., None]
+    Y = np.asarray(Y, dtype=np.float64)[..., None]
+    n = np.arange(1, n_terms + 1, dtype=np.float64)
+    k = n * np.pi
+    odd = 1.0 - np.cos(k)                                   # 2 for odd n, 0 for even n
+    den = 1.0 + np.exp(-2.0 * k)
+    sh = (np.exp(k * (Y - 1.0)) - np.exp(-k * (Y + 1.0))) / den
+    ch = (np.exp(k * (Y - 1.0)) + np.exp(-k * (Y + 1.0))) / den
+    theta = (2.0 / k ** 2 * odd * np.sin(k * X) * sh).sum(axis=-1)          # Eq. 65
+    qx = -(2.0 / k * odd * np.cos(k * X) * sh).sum(axis=-1)                # Eq. 66
+    qy = -(2.0 / k * odd * np.sin(k * X) * ch).sum(axis=-1)                # Eq. 67
+    return theta, qx, qy

@@ -43,6 +43,7 @@ typedef struct {
     double grad_x;         /* gradient seam: temperature drop per node along +x */
     double t_wall[4];      /* isothermal walls: x=0, x=nx-1, y=0, y=ny-1 */
     double q_wall[4];      /* heat-flux walls: heat flux q_0 into the domain (Eq. 56), same order */
+    int wall_kind[4];      /* kind of each wall, same order; 0 = the kind of its axis */
 } ora_case;
 
 /* D2Q8 velocities, Eq. 14 with c = 1, in the paper's numbering 1..8
@@ -57,19 +58,34 @@ static double a_w(int i) { return i < 4 ? 1.0 / 5.0 : 1.0 / 20.0; }
 
 #define IDX(c, i, x, y) (((size_t)(i) * (size_t)(c)->ny + (size_t)(y)) * (size_t)(c)->nx + (size_t)(x))
 
-/* Validity of a case: sizes, relaxation times, and the boundary pairs whose
- * treatment the paper defines (no corners: walls on at most one axis; the
- * gradient seam only along x, with periodic, diffuse or heat-flux walls across
- * it). */
+static int is_wall_kind(int k) { return k == ORA_ISOTHERMAL || k == ORA_DIFFUSE || k == ORA_HEATFLUX; }
+
+/* Kind of wall w (0: x = 0, 1: x = nx-1, 2: y = 0, 3: y = ny-1). */
+static int kind_of(const ora_case* c, int w)
+{
+    int k = c->wall_kind[w];
+    return k ? k : (w < 2 ? c->bc_x : c->bc_y);
+}
+
+/* Validity of a case: sizes, relaxation times, and the boundary sets whose
+ * treatment the paper defines.  The gradient seam is along x only, with
+ * periodic, diffuse or heat-flux walls across it.  Corners (walls on both
+ * axes) are not defined by the paper; they are accepted only when both x
+ * walls are isothermal, which then own the corner nodes (the Sec. 3.1.2
+ * square).  A per-wall kind may differ from its axis kind only on a walled
+ * axis. */
 int ora_check(const ora_case* c)
 {
     if (!c || c->nx < 2 || c->ny < 2) return -1;
     if (!(c->tau_n > 0.0) || !(c->tau_r > 0.0) || !(c->cv > 0.0)) return -1;
     if (c->bc_x < 0 || c->bc_x > 4 || c->bc_y < 0 || c->bc_y > 4 || c->bc_y == ORA_GRADIENT) return -1;
-    int wx = (c->bc_x == ORA_ISOTHERMAL || c->bc_x == ORA_DIFFUSE || c->bc_x == ORA_HEATFLUX);
-    int wy = (c->bc_y == ORA_ISOTHERMAL || c->bc_y == ORA_DIFFUSE || c->bc_y == ORA_HEATFLUX);
-    if (wx && wy) return -2;
-    if (c->bc_x == ORA_GRADIENT && c->bc_y == ORA_ISOTHERMAL) return -2;
+    for (int w = 0; w < 4; ++w)
+        if (c->wall_kind[w] && (!is_wall_kind(c->wall_kind[w]) || !is_wall_kind(w < 2 ? c->bc_x : c->bc_y)))
+            return -1;
+    int wx = is_wall_kind(c->bc_x), wy = is_wall_kind(c->bc_y);
+    if (wx && wy && !(kind_of(c, 0) == ORA_ISOTHERMAL && kind_of(c, 1) == ORA_ISOTHERMAL)) return -2;
+    if (c->bc_x == ORA_GRADIENT && (kind_of(c, 2) == ORA_ISOTHERMAL || kind_of(c, 3) == ORA_ISOTHERMAL))
+        return -2;
     return 0;
 }
 
@@ -138,19 +154,16 @@ void ora_init(const ora_case* c, const double* T, const double* qx, const double
                 e[IDX(c, i, x, y)] = omega_w(i) * c->cv * T[n]
                                    + 5.0 * a_w(i) * (CX[i] * jx + CY[i] * jy) / 3.0;
         }
-    /* Eq. 55 on isothermal wall nodes */
-    if (c->bc_x == ORA_ISOTHERMAL)
-        for (int y = 0; y < c->ny; ++y)
-            for (int i = 0; i < 8; ++i) {
-                e[IDX(c, i, 0, y)] = omega_w(i) * c->cv * c->t_wall[0];
-                e[IDX(c, i, c->nx - 1, y)] = omega_w(i) * c->cv * c->t_wall[1];
-            }
-    if (c->bc_y == ORA_ISOTHERMAL)
-        for (int x = 0; x < c->nx; ++x)
-            for (int i = 0; i < 8; ++i) {
-                e[IDX(c, i, x, 0)] = omega_w(i) * c->cv * c->t_wall[2];
-                e[IDX(c, i, x, c->ny - 1)] = omega_w(i) * c->cv * c->t_wall[3];
-            }
+    /* Eq. 55 on isothermal wall nodes (y walls first: x walls own corners) */
+    for (int w = 3; w >= 0; --w) {
+        if (kind_of(c, w) != ORA_ISOTHERMAL) continue;
+        const int n = w < 2 ? c->ny : c->nx;
+        for (int k = 0; k < n; ++k) {
+            const int x = w < 2 ? (w == 0 ? 0 : c->nx - 1) : k;
+            const int y = w < 2 ? k : (w == 2 ? 0 : c->ny - 1);
+            for (int i = 0; i < 8; ++i) e[IDX(c, i, x, y)] = omega_w(i) * c->cv * c->t_wall[w];
+        }
+    }
 }
 
 /* Diffuse reflection (Eq. 58) at one wall node: the populations leaving the
@@ -186,6 +199,24 @@ static void heatflux_node(const ora_case* c, double* e, int x, int y, int nxo, i
     for (int i = 0; i < 8; ++i)
         if (CX[i] * nxo + CY[i] * nyo < 0)
             e[IDX(c, i, x, y)] = omega_w(i) / wsum * total;
+}
+
+/* Boundary treatment of wall w after advection, by its kind: Eq. 55, 57 or 58. */
+static void treat_wall(const ora_case* c, double* e, int w)
+{
+    const int kind = kind_of(c, w);
+    const int n = w < 2 ? c->ny : c->nx;
+    const int nxo = w == 0 ? -1 : (w == 1 ? 1 : 0), nyo = w == 2 ? -1 : (w == 3 ? 1 : 0);
+    for (int k = 0; k < n; ++k) {
+        const int x = w < 2 ? (w == 0 ? 0 : c->nx - 1) : k;
+        const int y = w < 2 ? k : (w == 2 ? 0 : c->ny - 1);
+        if (kind == ORA_ISOTHERMAL)
+            for (int i = 0; i < 8; ++i) e[IDX(c, i, x, y)] = omega_w(i) * c->cv * c->t_wall[w];
+        else if (kind == ORA_DIFFUSE)
+            diffuse_node(c, e, x, y, nxo, nyo);
+        else if (kind == ORA_HEATFLUX)
+            heatflux_node(c, e, x, y, nxo, nyo, c->q_wall[w]);
+    }
 }
 
 /* Advance n steps.  e: state at the start of a step (in/out), work: scratch
@@ -236,40 +267,15 @@ void ora_run(const ora_case* c, double* e, double* work, long nsteps)
                      * treatment below overwrites every one of these */
                     e[IDX(c, i, x, y)] = outside ? 0.0 : work[IDX(c, i, sx, sy)] + jump;
                 }
-        /* boundary treatment after advection (Sec. 2.5) */
-        if (c->bc_x == ORA_ISOTHERMAL) {
-            for (int y = 0; y < ny; ++y)
-                for (int i = 0; i < 8; ++i) {
-                    e[IDX(c, i, 0, y)] = omega_w(i) * c->cv * c->t_wall[0];       /* Eq. 55 */
-                    e[IDX(c, i, nx - 1, y)] = omega_w(i) * c->cv * c->t_wall[1];
-                }
-        } else if (c->bc_x == ORA_DIFFUSE) {
-            for (int y = 0; y < ny; ++y) {
-                diffuse_node(c, e, 0, y, -1, 0);                                /* Eq. 58 */
-                diffuse_node(c, e, nx - 1, y, 1, 0);
-            }
-        } else if (c->bc_x == ORA_HEATFLUX) {
-            for (int y = 0; y < ny; ++y) {
-                heatflux_node(c, e, 0, y, -1, 0, c->q_wall[0]);                 /* Eq. 57 */
-                heatflux_node(c, e, nx - 1, y, 1, 0, c->q_wall[1]);
-            }
+        /* boundary treatment after advection (Sec. 2.5); the y walls first,
+         * so that (isothermal) x walls own the corner nodes */
+        if (!py) {
+            treat_wall(c, e, 2);
+            treat_wall(c, e, 3);
         }
-        if (c->bc_y == ORA_ISOTHERMAL) {
-            for (int x = 0; x < nx; ++x)
-                for (int i = 0; i < 8; ++i) {
-                    e[IDX(c, i, x, 0)] = omega_w(i) * c->cv * c->t_wall[2];
-                    e[IDX(c, i, x, ny - 1)] = omega_w(i) * c->cv * c->t_wall[3];
-                }
-        } else if (c->bc_y == ORA_DIFFUSE) {
-            for (int x = 0; x < nx; ++x) {
-                diffuse_node(c, e, x, 0, 0, -1);
-                diffuse_node(c, e, x, ny - 1, 0, 1);
-            }
-        } else if (c->bc_y == ORA_HEATFLUX) {
-            for (int x = 0; x < nx; ++x) {
-                heatflux_node(c, e, x, 0, 0, -1, c->q_wall[2]);
-                heatflux_node(c, e, x, ny - 1, 0, 1, c->q_wall[3]);
-            }
+        if (!px) {
+            treat_wall(c, e, 0);
+            treat_wall(c, e, 1);
         }
     }
 }

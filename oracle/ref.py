@@ -29,7 +29,8 @@ class _Case(ctypes.Structure):
                 ("cv", ctypes.c_double),
                 ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int),
                 ("t0", ctypes.c_double), ("grad_x", ctypes.c_double),
-                ("t_wall", ctypes.c_double * 4), ("q_wall", ctypes.c_double * 4)]
+                ("t_wall", ctypes.c_double * 4), ("q_wall", ctypes.c_double * 4),
+                ("wall_kind", ctypes.c_int * 4)]
 
 
 _lib = None
@@ -79,6 +80,8 @@ def make_case(case) -> _Case:
         c.t_wall[k] = float(v)
     for k, v in enumerate(getattr(case, "q_wall", (0.0,) * 4)):
         c.q_wall[k] = float(v)
+    for k, v in enumerate(getattr(case, "wall_bc", (0,) * 4)):
+        c.wall_kind[k] = _BC[v] if isinstance(v, str) else int(v)
     return c
 
 

@@ -256,3 +256,53 @@ def test_closed_forms_self_consistent():
     alpha_t = 1.29e-3 ** 2 * 2e5 / 3.0
     assert np.allclose(cf.fourier_1d_theta(X, alpha_t, 1.0, 1.0, 0.0), cf.fourier_1d_theta_eq61(X, 2e5, 1.29e-3),
                        atol=1e-12)
+
+
+# ---------------------------------------------------------------- Sec. 3.1.2 square
+
+def test_square_closed_forms_eq65_67():
+    """Eqs. 65-67 as transcribed: Theta harmonic, Q = -grad Theta, Theta = 0 on
+    the three isothermal sides, Q_y = -1 (heat flux Q0 into the square) on the
+    top side."""
+    X = np.linspace(0.05, 0.95, 19)
+    XX, YY = np.meshgrid(X, X)
+    h = 1e-4
+    th, qx, qy = cf.square_eq65_67(XX, YY)
+    f = lambda dx, dy: cf.square_eq65_67(XX + dx, YY + dy)[0]
+    lap = (f(h, 0) + f(-h, 0) + f(0, h) + f(0, -h) - 4.0 * th) / h ** 2
+    assert np.abs(lap).max() < 1e-4
+    assert np.abs(qx + (f(h, 0) - f(-h, 0)) / (2 * h)).max() < 1e-6
+    assert np.abs(qy + (f(0, h) - f(0, -h)) / (2 * h)).max() < 1e-6
+    e = np.linspace(0.0, 1.0, 7)
+    assert np.abs(cf.square_eq65_67(np.zeros(7), e)[0]).max() < 1e-15
+    assert np.abs(cf.square_eq65_67(np.ones(7), e)[0]).max() < 1e-12
+    assert np.abs(cf.square_eq65_67(e, np.zeros(7))[0]).max() < 1e-15
+    xt = np.linspace(0.1, 0.9, 9)
+    assert np.allclose(cf.square_eq65_67(xt, np.ones(9), n_terms=20000)[2], -1.0, atol=2e-4)
+
+
+def test_square_heatflux_top_eq65():
+    """Sec. 3.1.2 (Kn_R = 2e-3, Kn_N = 2e3; heat flux on the top side, the other
+    three sides isothermal, corners owned by the isothermal x walls), run to
+    steady state (14 time constants of the slowest mode) on 21 and 41 nodes
+    per side: the temperature approaches Eq. 65 (relative L2 0.19 -> 0.077,
+    more than halving per grid doubling; the wall temperature jump and the
+    corner singularities where the flux meets the cold sides are grid-scale
+    effects), and the top wall carries exactly q0 (Eq. 56)."""
+    q0 = 1e-3
+    errs = []
+    for nodes in (21, 41):
+        d = nodes - 1
+        tn, tr = cf.lattice_relaxation_times(d, 2e3, 2e-3)
+        case = W.square_case(nodes, tn, tr, q0=q0)
+        o = ref.Oracle(case)
+        lam = cf.diffusivity(tr)                  # conductivity with C_V = 1
+        o.run(int(14 * d * d / (1.25 * math.pi ** 2 * lam)))
+        T, _, qy = o.moments()
+        assert np.allclose(qy[-1, 1:-1], -q0, rtol=1e-12)
+        X = np.arange(nodes) / d
+        XX, YY = np.meshgrid(X, X)
+        th = cf.square_eq65_67(XX, YY)[0]
+        got = (T - case.t0) / (q0 * d / lam)      # Theta / Q0 = (T - T_c) lambda / (q0 L)
+        errs.append(float(np.linalg.norm(got - th) / np.linalg.norm(th)))
+    assert errs[1] < 0.08 and errs[1] < 0.5 * errs[0], errs

@@ -50,6 +50,7 @@ class Case:
     cv: float = 1.0
     t_wall: Tuple[float, float, float, float] = (0.0, 0.0, 0.0, 0.0)
     q_wall: Tuple[float, float, float, float] = (0.0, 0.0, 0.0, 0.0)
+    wall_bc: Tuple = (0, 0, 0, 0)   # per-wall kind overriding the axis kind (0 = the axis kind)
     grad_x: float = 0.0
     steps: int = 0
     init: str = "uniform"          # "uniform" | "gaussian" | "modes" | "field"
@@ -206,6 +207,14 @@ def heat_pulse_case(tau_n: float, tau_r: float, nodes: int = 401, ny: int = 3,
     T0 everywhere with no heat flux."""
     return Case(f"heat_pulse_{nodes}_{tau_r:g}", nodes, ny, tau_n, tau_r, bc_x="heatflux",
                 bc_y="periodic", t0=t0, q_wall=(q0, 0.0, 0.0, 0.0))
+
+
+def square_case(nodes: int, tau_n: float, tau_r: float, q0: float = 1e-3, t_c: float = 1.0) -> Case:
+    """Sec. 3.1.2 square: heat flux q0 into the domain through the top wall
+    (y = nodes - 1), the other three walls isothermal at t_c, uniform start."""
+    return Case(f"square_{nodes}", nodes, nodes, tau_n, tau_r, bc_x="isothermal", bc_y="isothermal",
+                t0=t_c, t_wall=(t_c, t_c, t_c, t_c), q_wall=(0.0, 0.0, 0.0, q0),
+                wall_bc=(0, 0, 0, "heatflux"))
 
 
 def poiseuille_cases(**kw) -> List[Case]:
