@@ -87,9 +87,11 @@ typedef enum {
  *                q_0 (2 tau_r + 1)/(2 tau_r) in proportion to omega_i (Eq. 57),
  *                so the heat flux of the wall node is exactly q_0.  q_0 is set
  *                per wall with lbm_set_wall_flux (0 until then: DIFFUSE).
- * Supported pairs: (any x, PERIODIC y), (PERIODIC x, ISOTHERMAL, DIFFUSE or
- * HEATFLUX y), (GRADIENT x, DIFFUSE or HEATFLUX y).  Walls on both axes need
- * corners, which the paper leaves undefined: LBM_EUNSUPPORTED. */
+ * Each wall may take its own kind (lbm_instance.wall_bc).  Supported: walls on
+ * one axis with the other PERIODIC (GRADIENT x only with non-isothermal y
+ * walls); walls on both axes only when both x walls are ISOTHERMAL: the paper
+ * leaves corner nodes undefined, and here the isothermal x walls own them
+ * (enough for the square of Sec. 3.1.2).  Anything else: LBM_EUNSUPPORTED. */
 typedef enum {
     LBM_BC_PERIODIC = 0,
     LBM_BC_ISOTHERMAL = 1,
@@ -116,6 +118,9 @@ typedef struct {
     double grad_x;         /* GRADIENT only: temperature drop per node along +x */
     double t_wall[4];      /* ISOTHERMAL wall temperatures: x=0, x=nx-1, y=0, y=ny-1 */
     double scale;          /* storage scale s (a power of two), 0 = chosen at init */
+    int32_t wall_bc[4];    /* per-wall kind (x=0, x=nx-1, y=0, y=ny-1) overriding the axis
+                              kind: 0 = the axis kind, else ISOTHERMAL, DIFFUSE or HEATFLUX,
+                              on a walled axis only */
 } lbm_instance;
 
 /* Device layout of the populations (both hold the same values; the choice

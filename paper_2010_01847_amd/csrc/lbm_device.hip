@@ -270,9 +270,14 @@ __device__ __forceinline__ void relax_sr_f32(const float g[8], const InstDesc& d
 //   heat flux (Eq. 57): the same with S raised by q_0 / beta (wall_q, 0 for a
 //     diffuse wall);
 //   isothermal (Eq. 55): all eight take omega_i C_V (T_s - T_ref) / s.
+// Each wall has its own kind (InstDesc::wk); walls on both axes occur only
+// with isothermal x walls, which own the corner nodes.
 __device__ __forceinline__ void boundary(float g[8], const InstDesc& d, float kd, int x, int y) {
-    if (d.bc_y == 2 || d.bc_y == 4) {
+    if (d.bc_y != 0) {
+        // walls y = 0 and y = ny-1, each of its own kind (wk[2], wk[3])
         const bool lo = (y == 0), hi = (y == d.ny - 1);
+        const int kl = d.wk[2], kh = d.wk[3];
+        const bool rl = lo && (kl == 2 || kl == 4), rh = hi && (kh == 2 || kh == 4);
         const float Sl = (g[3] + g[6] + g[7]) + d.wall_q[2];      // incident at y = 0: 4, 7, 8
         const float Sh = (g[1] + g[4] + g[5]) + d.wall_q[3];      // incident at y = ny-1: 2, 5, 6
         const float dl = 0.1f * Sl, dh = 0.1f * Sh;
@@ -280,26 +285,28 @@ __device__ __forceinline__ void boundary(float g[8], const InstDesc& d, float kd
         // the reference state's diagonal shares (c_ix p_diag) are not part of
         // the reflected energy: the leaving diagonals carry -c_ix p_diag / s
         const float k = kd;
-        g[1] = lo ? al : g[1];  g[4] = lo ? dl - k : g[4];  g[5] = lo ? dl + k : g[5];
-        g[3] = hi ? ah : g[3];  g[6] = hi ? dh + k : g[6];  g[7] = hi ? dh - k : g[7];
-    } else if (d.bc_y == 1) {
-        const bool w = (y == 0) || (y == d.ny - 1);
-        const float t = (y == 0) ? d.wall_g[2] : d.wall_g[3];
+        g[1] = rl ? al : g[1];  g[4] = rl ? dl - k : g[4];  g[5] = rl ? dl + k : g[5];
+        g[3] = rh ? ah : g[3];  g[6] = rh ? dh + k : g[6];  g[7] = rh ? dh - k : g[7];
+        const bool w = (lo && kl == 1) || (hi && kh == 1);
+        const float t = lo ? d.wall_g[2] : d.wall_g[3];
         const float a = W_AXIS * t, b = W_DIAG * t;
 #pragma unroll
         for (int i = 0; i < 8; ++i) g[i] = w ? (i < 4 ? a : b) : g[i];
     }
-    if (d.bc_x == 2 || d.bc_x == 4) {
+    if (d.bc_x == 1 || d.bc_x == 2 || d.bc_x == 4) {
+        // walls x = 0 and x = nx-1 (wk[0], wk[1]); applied after the y walls,
+        // so isothermal x walls own the corner nodes
         const bool lo = (x == 0), hi = (x == d.nx - 1);
+        const int kl = d.wk[0], kh = d.wk[1];
+        const bool rl = lo && (kl == 2 || kl == 4), rh = hi && (kh == 2 || kh == 4);
         const float Sl = (g[2] + g[5] + g[6]) + d.wall_q[0];      // incident at x = 0: 3, 6, 7
         const float Sh = (g[0] + g[4] + g[7]) + d.wall_q[1];      // incident at x = nx-1: 1, 5, 8
         const float dl = 0.1f * Sl, dh = 0.1f * Sh;
         const float al = Sl - dl - dl, ah = Sh - dh - dh;
-        g[0] = lo ? al : g[0];  g[4] = lo ? dl : g[4];  g[7] = lo ? dl : g[7];
-        g[2] = hi ? ah : g[2];  g[5] = hi ? dh : g[5];  g[6] = hi ? dh : g[6];
-    } else if (d.bc_x == 1) {
-        const bool w = (x == 0) || (x == d.nx - 1);
-        const float t = (x == 0) ? d.wall_g[0] : d.wall_g[1];
+        g[0] = rl ? al : g[0];  g[4] = rl ? dl : g[4];  g[7] = rl ? dl : g[7];
+        g[2] = rh ? ah : g[2];  g[5] = rh ? dh : g[5];  g[6] = rh ? dh : g[6];
+        const bool w = (lo && kl == 1) || (hi && kh == 1);
+        const float t = lo ? d.wall_g[0] : d.wall_g[1];
         const float a = W_AXIS * t, b = W_DIAG * t;
 #pragma unroll
         for (int i = 0; i < 8; ++i) g[i] = w ? (i < 4 ? a : b) : g[i];
@@ -924,8 +931,8 @@ __global__ __launch_bounds__(256) void init_kernel(const InstDesc* __restrict__ 
     g[5] = (float)((ed + (-jx + jy) / 12.0 + pd) * inv_s);
     g[6] = (float)((ed - (jx + jy) / 12.0 + pd) * inv_s);
     g[7] = (float)((ed + (jx - jy) / 12.0 - pd) * inv_s);
-    const bool wall = (d.bc_x == 1 && (x == 0 || x == d.nx - 1)) ||
-                      (d.bc_y == 1 && (y == 0 || y == d.ny - 1));
+    const bool wall = (x == 0 && d.wk[0] == 1) || (x == d.nx - 1 && d.wk[1] == 1) ||
+                      (y == 0 && d.wk[2] == 1) || (y == d.ny - 1 && d.wk[3] == 1);
     if (wall) boundary(g, d, rv.wall_kd, x, y);
     S* pb = reinterpret_cast<S*>(pre) + d.off;
     S* row = pb + (int64_t)y * d.row;

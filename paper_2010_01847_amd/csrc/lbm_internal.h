@@ -32,6 +32,7 @@ struct alignas(64) InstDesc {
     int32_t layout;         // 1 = planes, 2 = chunked
     int32_t group_begin;    // first reduction group of this instance (kGroup tiles each)
     int32_t ngroups;        // reduction groups of this instance
+    int32_t wk[4];          // boundary kind of each wall (x=0, x=nx-1, y=0, y=ny-1); 0 on periodic axes
     int64_t row;            // elements between rows
     int64_t plane;          // elements between direction runs
     int64_t chunk;          // elements between 64-node chunks (0: planes layout)

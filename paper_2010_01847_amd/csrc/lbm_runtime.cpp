@@ -119,6 +119,15 @@ Coeffs coeffs_of(const lbm_instance& in) {
     return c;
 }
 
+bool walled(int bc) { return bc == LBM_BC_ISOTHERMAL || bc == LBM_BC_DIFFUSE || bc == LBM_BC_HEATFLUX; }
+
+// Kind of wall w (0: x = 0, 1: x = nx-1, 2: y = 0, 3: y = ny-1), 0 on a periodic axis.
+int wall_kind(const lbm_instance& in, int w) {
+    const int axis = w < 2 ? in.bc_x : in.bc_y;
+    if (!walled(axis)) return 0;
+    return in.wall_bc[w] ? in.wall_bc[w] : axis;
+}
+
 Status validate_instance(const lbm_instance& in, int k) {
     char b[256];
     if (in.nx < 2 || in.ny < 2) {
@@ -143,16 +152,22 @@ Status validate_instance(const lbm_instance& in, int k) {
                  k, in.bc_x, in.bc_y);
         return {LBM_EINVAL, b};
     }
-    auto walled = [](int bc) {
-        return bc == LBM_BC_ISOTHERMAL || bc == LBM_BC_DIFFUSE || bc == LBM_BC_HEATFLUX;
-    };
     const bool wx = walled(in.bc_x);
     const bool wy = walled(in.bc_y);
-    if (wx && wy) {
-        snprintf(b, sizeof b, "instance %d: walls on both axes need corner treatment (undefined)", k);
+    for (int w = 0; w < 4; ++w) {
+        if (in.wall_bc[w] != 0 && (!walled(in.wall_bc[w]) || !(w < 2 ? wx : wy))) {
+            snprintf(b, sizeof b, "instance %d: wall_bc[%d] = %d must be 0, or a wall kind on a walled axis",
+                     k, w, in.wall_bc[w]);
+            return {LBM_EINVAL, b};
+        }
+    }
+    if (wx && wy && !(wall_kind(in, 0) == LBM_BC_ISOTHERMAL && wall_kind(in, 1) == LBM_BC_ISOTHERMAL)) {
+        snprintf(b, sizeof b, "instance %d: walls on both axes need corner nodes, defined here only when "
+                              "both x walls are isothermal", k);
         return {LBM_EUNSUPPORTED, b};
     }
-    if (in.bc_x == LBM_BC_GRADIENT && in.bc_y == LBM_BC_ISOTHERMAL) {
+    if (in.bc_x == LBM_BC_GRADIENT &&
+        (wall_kind(in, 2) == LBM_BC_ISOTHERMAL || wall_kind(in, 3) == LBM_BC_ISOTHERMAL)) {
         snprintf(b, sizeof b, "instance %d: isothermal walls across a gradient seam are undefined", k);
         return {LBM_EUNSUPPORTED, b};
     }
@@ -365,7 +380,7 @@ static void ref_init(lbm_ctx* h, size_t k, double s) {
     r.s = s;
     r.inv_nodes = 1.0 / ((double)in.nx * (double)in.ny);
     r.adapt = (h->K > 0 && (in.bc_x == LBM_BC_PERIODIC || in.bc_x == LBM_BC_GRADIENT) &&
-               in.bc_y != LBM_BC_ISOTHERMAL) ? 1 : 0;
+               wall_kind(in, 2) != LBM_BC_ISOTHERMAL && wall_kind(in, 3) != LBM_BC_ISOTHERMAL) ? 1 : 0;
     const double J = (r.adapt || std::isinf(in.tau_r)) ? -r.jb : r.jb * (in.tau_r - 0.5);
     ref_set_flux(r, J);
 }
@@ -498,6 +513,7 @@ int lbm_create(const lbm_config* cfg, lbm_handle* out) {
         d.ny = v[k].ny;
         d.bc_x = v[k].bc_x;
         d.bc_y = v[k].bc_y;
+        for (int w = 0; w < 4; ++w) d.wk[w] = wall_kind(v[k], w);
         d.layout = h->layout;
         d.row = geo.row;
         d.plane = geo.plane;
@@ -603,8 +619,8 @@ static int check_inst(lbm_ctx* h, int32_t k) {
 // below, far under its 65504 limit and well above its normal range floor.
 static double auto_scale(const lbm_ctx* h, const lbm_instance& in, double amp) {
     if (!is_f16(h->storage)) return 1.0;
-    if (in.bc_x == LBM_BC_ISOTHERMAL) amp = std::max({amp, std::fabs(in.t_wall[0] - in.t0), std::fabs(in.t_wall[1] - in.t0)});
-    if (in.bc_y == LBM_BC_ISOTHERMAL) amp = std::max({amp, std::fabs(in.t_wall[2] - in.t0), std::fabs(in.t_wall[3] - in.t0)});
+    for (int w = 0; w < 4; ++w)
+        if (wall_kind(in, w) == LBM_BC_ISOTHERMAL) amp = std::max(amp, std::fabs(in.t_wall[w] - in.t0));
     if (in.bc_x == LBM_BC_GRADIENT) {
         const double tr = std::isinf(in.tau_r) ? 1e6 : in.tau_r;
         amp = std::max(amp, 5.0 / 9.0 * in.cv * std::fabs(in.grad_x) * std::max(tr, 1.0));
@@ -913,7 +929,7 @@ int lbm_set_wall_flux(lbm_handle h, int32_t k, int32_t wall, double q0) {
     if (rc) return rc;
     if (wall < 0 || wall > 3) return h->fail(LBM_EINVAL, "wall must be 0..3 (x=0, x=nx-1, y=0, y=ny-1)");
     const lbm_instance& in = h->inst[k];
-    if ((wall < 2 ? in.bc_x : in.bc_y) != LBM_BC_HEATFLUX)
+    if (wall_kind(in, wall) != LBM_BC_HEATFLUX)
         return h->fail(LBM_EINVAL, "wall is not a HEATFLUX wall");
     if (!std::isfinite(q0)) return h->fail(LBM_EINVAL, "q0 must be finite");
     h->qwall[k][wall] = q0;

@@ -44,7 +44,8 @@ class lbm_instance(ctypes.Structure):
                 ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
                 ("tau_n", ctypes.c_double), ("tau_r", ctypes.c_double),
                 ("cv", ctypes.c_double), ("t0", ctypes.c_double), ("grad_x", ctypes.c_double),
-                ("t_wall", ctypes.c_double * 4), ("scale", ctypes.c_double)]
+                ("t_wall", ctypes.c_double * 4), ("scale", ctypes.c_double),
+                ("wall_bc", ctypes.c_int32 * 4)]
 
 
 class lbm_config(ctypes.Structure):
@@ -242,7 +243,8 @@ def lbm_destroy(h) -> None:
 
 def make_instance(nx: int, ny: int, tau_n: float, tau_r: float, bc_x="periodic", bc_y="periodic",
                   cv: float = 1.0, t0: float = 1.0, grad_x: float = 0.0,
-                  t_wall: Sequence[float] = (0.0, 0.0, 0.0, 0.0), scale: float = 0.0) -> lbm_instance:
+                  t_wall: Sequence[float] = (0.0, 0.0, 0.0, 0.0), scale: float = 0.0,
+                  wall_bc: Sequence = (0, 0, 0, 0)) -> lbm_instance:
     it = lbm_instance()
     it.nx, it.ny = int(nx), int(ny)
     it.bc_x = BC[bc_x] if isinstance(bc_x, str) else int(bc_x)
@@ -252,6 +254,9 @@ def make_instance(nx: int, ny: int, tau_n: float, tau_r: float, bc_x="periodic",
     for k in range(4):
         it.t_wall[k] = float(t_wall[k])
     it.scale = float(scale)
+    for k in range(4):
+        v = wall_bc[k]
+        it.wall_bc[k] = BC[v] if isinstance(v, str) else int(v)
     return it
 
 
@@ -259,7 +264,7 @@ def instance_from_case(case, scale: float = 0.0) -> lbm_instance:
     """From any object with the fields of ``workloads.Case``."""
     return make_instance(case.nx, case.ny, case.tau_n, case.tau_r, case.bc_x, case.bc_y,
                          getattr(case, "cv", 1.0), case.t0, getattr(case, "grad_x", 0.0),
-                         getattr(case, "t_wall", (0.0,) * 4), scale)
+                         getattr(case, "t_wall", (0.0,) * 4), scale, getattr(case, "wall_bc", (0,) * 4))
 
 
 class Lattice:

@@ -93,7 +93,13 @@ def test_required_bytes_and_layout():
     (dict(nx=8, ny=8, tau_n=0.0, tau_r=0.8), P.LBM_EINVAL),
     (dict(nx=8, ny=8, tau_n=0.6, tau_r=-1.0), P.LBM_EINVAL),
     (dict(nx=8, ny=8, tau_n=math.inf, tau_r=1.0), P.LBM_EINVAL),
-    (dict(nx=8, ny=8, tau_n=0.6, tau_r=0.8, bc_x="isothermal", bc_y="diffuse"), P.LBM_EUNSUPPORTED),
+    (dict(nx=8, ny=8, tau_n=0.6, tau_r=0.8, bc_x="diffuse", bc_y="isothermal"), P.LBM_EUNSUPPORTED),
+    (dict(nx=8, ny=8, tau_n=0.6, tau_r=0.8, bc_x="isothermal", bc_y="diffuse", wall_bc=(0, "heatflux", 0, 0)),
+     P.LBM_EUNSUPPORTED),
+    (dict(nx=8, ny=8, tau_n=0.6, tau_r=0.8, wall_bc=(0, 0, "isothermal", 0)), P.LBM_EINVAL),
+    (dict(nx=8, ny=8, tau_n=0.6, tau_r=0.8, bc_y="diffuse", wall_bc=(0, 0, "gradient", 0)), P.LBM_EINVAL),
+    (dict(nx=8, ny=8, tau_n=0.6, tau_r=0.8, bc_x="gradient", bc_y="diffuse", wall_bc=(0, 0, 0, "isothermal")),
+     P.LBM_EUNSUPPORTED),
     (dict(nx=8, ny=8, tau_n=0.6, tau_r=0.8, bc_x="gradient", bc_y="isothermal"), P.LBM_EUNSUPPORTED),
     (dict(nx=8, ny=8, tau_n=0.6, tau_r=0.8, bc_y=P.LBM_BC_GRADIENT), P.LBM_EINVAL),
     (dict(nx=8, ny=8, tau_n=0.6, tau_r=0.8, scale=3.0), P.LBM_EINVAL),
@@ -124,6 +130,16 @@ def test_bad_config_fields():
 def test_heatflux_pairs_accepted():
     for bx, by in (("heatflux", "periodic"), ("periodic", "heatflux"), ("gradient", "heatflux")):
         assert P.lbm_required_bytes(_cfg([P.make_instance(16, 8, 0.6, 0.8, bc_x=bx, bc_y=by)])) > 0
+
+
+def test_per_wall_kinds_and_corners_accepted():
+    """Mixed kinds on one axis, and walls on both axes when both x walls are
+    isothermal (they own the corners; the Sec. 3.1.2 square)."""
+    for kw in (dict(bc_x="isothermal", bc_y="isothermal", wall_bc=(0, 0, 0, "heatflux")),
+               dict(bc_x="isothermal", bc_y="diffuse"),
+               dict(bc_y="diffuse", wall_bc=(0, 0, "isothermal", "heatflux")),
+               dict(bc_x="gradient", bc_y="diffuse", wall_bc=(0, 0, "heatflux", 0))):
+        assert P.lbm_required_bytes(_cfg([P.make_instance(16, 8, 0.6, 0.8, **kw)])) > 0
 
 
 def test_tau_r_infinite_and_small_accepted():

@@ -298,6 +298,81 @@ def test_heatflux_walls_across_y():
         assert np.allclose(got[2][0], -q[0], rtol=1e-5)
 
 
+def _square(nodes, q0=1e-3):
+    d = nodes - 1
+    tn, tr = cf.lattice_relaxation_times(d, 2e3, 2e-3)
+    return W.square_case(nodes, tn, tr, q0=q0), d, cf.diffusivity(tr)
+
+
+def _gpu_square(case, steps, schedule=None, **kw):
+    lat = Lattice([instance_from_case(case)], **kw)
+    if schedule:
+        lat.set_schedule(schedule)
+    lat.init(0)
+    lat.set_wall_flux(0, 3, case.q_wall[3])
+    lat.step(steps)
+    out = lat.moments(0)
+    lat.close()
+    return out
+
+
+def test_square_sec312():
+    """Sec. 3.1.2 square (Kn_R = 2e-3, Kn_N = 2e3, heat flux on the top side,
+    isothermal elsewhere, corners owned by the isothermal x walls): 41^2 at
+    the oracle's steady state and the paper's 201^2 after 3000 steps match the
+    oracle; the 201^2 steady state on the GPU approaches Eq. 65 (relative L2
+    0.077 at 41^2 on the oracle, falling about 2.7x per grid doubling)."""
+    case, d, lam = _square(41)
+    steps = int(14 * d * d / (1.25 * math.pi ** 2 * lam))
+    o = ref.Oracle(case)
+    o.run(steps)
+    T, qxo, qyo = o.moments()
+    e = eps(case, _gpu_square(case, steps), (T - case.t0, qxo, qyo))
+    log(f"square 41^2 steady ({steps} steps): eps={e}")
+    assert max(e) < 1e-5
+    case, d, lam = _square(201)
+    o = ref.Oracle(case)
+    o.run(3000)
+    T, qxo, qyo = o.moments()
+    e = eps(case, _gpu_square(case, 3000), (T - case.t0, qxo, qyo))
+    log(f"square 201^2 after 3000 steps: eps={e}")
+    assert max(e) < 1e-5
+    steps = int(14 * d * d / (1.25 * math.pi ** 2 * lam))
+    dT, qx, qy = _gpu_square(case, steps, check_interval=1000, schedule="graph")
+    X = np.arange(case.nx) / d
+    XX, YY = np.meshgrid(X, X)
+    th = cf.square_eq65_67(XX, YY)[0]
+    got = dT / (case.q_wall[3] * d / lam)
+    err = float(np.linalg.norm(got - th) / np.linalg.norm(th))
+    log(f"square 201^2 steady ({steps} steps) vs Eq. 65: rel L2 {err:.3e}; top centre {got[-1, d // 2]:.5f} "
+        f"(Eq. 65 {th[-1, d // 2]:.5f})")
+    assert err < 0.015
+    assert np.allclose(qy[-1, 1:-1], -case.q_wall[3], rtol=1e-5)
+
+
+@pytest.mark.parametrize("walls", [("isothermal", "diffuse", (0, 0, 0, "heatflux")),
+                                   ("periodic", "diffuse", (0, 0, "isothermal", "heatflux")),
+                                   ("isothermal", "isothermal", (0, 0, "heatflux", 0))])
+def test_mixed_walls_and_corners_random_state(walls):
+    """Per-wall kinds, and corners under isothermal x walls, from a rough
+    random state (40 steps) against the oracle."""
+    bx, by, wb = walls
+    kw = dict(bc_x=bx, bc_y=by, wall_bc=wb, t_wall=(1.004, 0.997, 1.003, 0.995), q_wall=(0, 0, 1.5e-3, -7e-4))
+    case, T0, qx, qy = _random_case(75, 46, 0.6, 7.0, 35, **kw)
+    ora = oracle_fields(case, 40, T0, qx, qy)
+    lat = Lattice([instance_from_case(case)], check_interval=10)
+    lat.init(0, T0, qx, qy)
+    for w in range(4):
+        kind = wb[w] if wb[w] else (bx if w < 2 else by)
+        if kind == "heatflux":
+            lat.set_wall_flux(0, w, case.q_wall[w])
+    lat.step(40)
+    e_t, e_q = eps(case, lat.moments(0), ora)
+    lat.close()
+    log(f"mixed walls {walls}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
+    assert e_t < 1e-5 and e_q < 1e-5
+
+
 def test_set_wall_flux_errors():
     case = W.Case("e", 16, 8, 0.6, 0.8, bc_x="heatflux")
     lat = Lattice([instance_from_case(case)])
