@@ -70,6 +70,8 @@ def _parse():
                    help="rounding of the main row's stores (default: stochastic for plain 16-bit "
                         "storage, which stalls on smooth fields otherwise; nearest for the rest)")
     p.add_argument("--sweep-steps", type=int, default=300, help="timed steps per sweep schedule (0: skip)")
+    p.add_argument("--fusion", default="auto", choices=["auto", "1", "2"],
+                   help="time steps per launch (auto: the library's default, 1 for the FP16 kinds, 2 otherwise)")
     p.add_argument("--check-interval", type=int, default=100)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -96,6 +98,8 @@ def _run_gpu(args, storage, rounding, torch, P, W, host_io=False):
     scale = 2.0 ** -20 if storage.startswith("f16") else 0.0
     lat = P.Lattice([P.instance_from_case(case, scale)], storage=storage,
                     check_interval=args.check_interval, rounding=rounding, seed=1847)
+    fuse = (1 if storage in ("f16", "f16_split") else 2) if args.fusion == "auto" else int(args.fusion)
+    lat.set_step_fusion(fuse)
     tune = lat.autotune(10) if args.autotune else None
     T0 = W.initial_field(case)
     io = None
@@ -132,29 +136,41 @@ def _run_gpu(args, storage, rounding, torch, P, W, host_io=False):
         io["moments_to_host_s"] = time.perf_counter() - t
         io["pcie_inclusive_mlups"] = nodes * args.steps / (io["init_from_host_s"] + ms / 1e3
                                                            + io["moments_to_host_s"]) / 1e6
-    kernel_ms = _plain_kernel_ms(lat, args.check_interval, torch)
+    launch_ms = _plain_launch_ms(lat, args.check_interval, fuse, torch)
     shape = lat.launch_shape()
     lat.close()
-    return dict(storage=storage, rounding=rounding, mlups=mlups, ms_per_step=ms / args.steps, gbs=gbs,
-                kernel_ms=kernel_ms, kernel_gbs=BYTES_PER_NODE[storage] * nodes / (kernel_ms / 1e3) / 1e9,
+    # algorithmic bytes per launch: the per-update figure (read and write the
+    # eight populations once) times the updates one launch performs
+    alg = BYTES_PER_NODE[storage] * nodes * fuse
+    return dict(storage=storage, rounding=rounding, fusion=fuse, mlups=mlups, ms_per_step=ms / args.steps,
+                gbs=gbs, launch_ms=launch_ms, kernel_gbs=alg / (launch_ms / 1e3) / 1e9,
                 wall_s=wall, check=info, shape=shape, tune=tune, host_io=io)
 
 
-def _plain_kernel_ms(lat, K, torch, n=98):
-    """Average duration of the plain stream-collide launch: HIP events on the
-    launch stream around a run of steps that holds no check-step work (the
-    steps strictly between two check steps, snapshot step excluded)."""
+def _plain_launch_ms(lat, K, fuse, torch, n=95):
+    """Average duration of the dominant launch (the plain stream-collide
+    launch, or the two-step launch when steps are fused), by HIP events on
+    the launch stream around steps that hold no check-step work (strictly
+    between two check steps, snapshot step excluded).  With fusion a call of
+    n steps issues (n - 1) / 2 two-step launches and one single step (the last
+    step of a call is never fused), timed by a separate one-step call."""
     if K > 2:
         lat.step((-lat.steps) % K + 1)      # past the next check step and the shift step after it
-        n = min(n, K - 3)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(lat.stream)
-    lat.step(n)
-    e1.record(lat.stream)
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / n
+        n = min(n, K - 4) | 1
+    def timed(k):
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(lat.stream)
+        lat.step(k)
+        e1.record(lat.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+    t_run = timed(n)
+    t_one = timed(1)
+    if fuse == 2:
+        return (t_run - t_one) / ((n - 1) // 2)
+    return (t_run + t_one) / (n + 1)
 
 
 def _run_sweep(args, torch, P, W):
@@ -263,9 +279,12 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4),
                      "traffic": _measured_traffic(args.storage, args.n),
-                     "kernel": "wave_kernel (fused pull-advection + boundary + moments + relaxation)",
-                     "kernel_us": round(main_row["kernel_ms"] * 1e3, 1),
-                     "bytes_per_launch": BYTES_PER_NODE[args.storage] * args.n * args.n},
+                     "kernel": ("pair_kernel (two time steps per launch, LDS temporal blocking)"
+                                if main_row["fusion"] == 2 else
+                                "wave_kernel (fused pull-advection + boundary + moments + relaxation)"),
+                     "steps_per_launch": main_row["fusion"],
+                     "kernel_us": round(main_row["launch_ms"] * 1e3, 1),
+                     "bytes_per_launch": BYTES_PER_NODE[args.storage] * args.n * args.n * main_row["fusion"]},
         "cpu_baseline": cpu,
         "sweep": sweep,
         "host_io": {k: round(v, 4) for k, v in main_row["host_io"].items()},

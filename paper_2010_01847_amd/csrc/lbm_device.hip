@@ -897,6 +897,198 @@ hipError_t launch_moments(int storage, const InstDesc* d_desc, const RefState* d
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ two-step kernel
+//
+// Temporal blocking: two time steps per pass over HBM.  The LDS tile holds the
+// post-relaxation populations (FP32, as a single step would read them back) of
+// a 64 x (kPairH + 4) window starting two nodes left of and below the output
+// tile, every position mapped to its periodic image (as the single-step pull
+// wraps).  Step m advances the inner 62 x (kPairH + 2) window (whose pulls stay
+// inside the tile), rounded exactly as a stored step; step m + 1 advances the
+// 60 x kPairH outputs and stores them.  Per node and step the arithmetic is the
+// single-step kernels' (same functions, same order), so the bits are the same.
+
+// y component of velocity i.
+__device__ __forceinline__ constexpr int vel_y(int i) {
+    return (i == 1 || i == 4 || i == 5) ? 1 : ((i == 3 || i == 6 || i == 7) ? -1 : 0);
+}
+
+// Periodic image of v on 0..n-1; v is at most one period outside when
+// n >= span (the window's extent), else it may wrap several times.
+__device__ __forceinline__ int wrapm(int v, int n, int span) {
+    if (n >= span) return v < 0 ? v + n : (v >= n ? v - n : v);
+    const int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+// Relaxation of node g and its rounding to the storage type, exactly as the
+// single-step kernels store it: o (raw values), E (FP32 energy, split only).
+template <class S, int SR, int SPLIT>
+__device__ __forceinline__ void relax_round(float g[8], const InstDesc& d, const RefView& rv, const uint32_t r[4],
+                                            S o[8], float& E_out) {
+    if (SPLIT) {
+        float delta[8];
+        relax_delta(g, d, rv, delta);
+        const float E = ((g[0] + g[2]) + (g[1] + g[3])) + ((g[4] + g[6]) + (g[5] + g[7]));
+        float res = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float hv = (g[i] - omega_e(i, E)) + delta[i];
+            o[i] = round_to<S, SR>(hv, bits16(r, i));
+            res = res + (hv - Cvt<S>::ld(o[i]));
+        }
+        E_out = E + res;
+    } else if (SR && sizeof(S) == 4) {
+        float f[8];
+        relax_sr_f32(g, d, rv, r, f);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) o[i] = Cvt<S>::st(f[i]);
+        E_out = 0.0f;
+    } else {
+        relax(g, d, rv);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) o[i] = round_to<S, SR>(g[i], bits16(r, i));
+        E_out = 0.0f;
+    }
+}
+
+// The populations the next step reads back from a stored node.
+template <class S, int SPLIT>
+__device__ __forceinline__ void reload(const S o[8], float E, float out[8]) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) out[i] = SPLIT ? Cvt<S>::ld(o[i]) + omega_e(i, E) : Cvt<S>::ld(o[i]);
+}
+
+__device__ __forceinline__ void sr_words(uint32_t r[4], uint32_t node, uint32_t step, uint32_t seed) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[k] = mix32(node ^ mix32(step * 4u + (uint32_t)k + seed * 0x9e3779b9u));
+}
+
+__device__ __forceinline__ bool on_wall(const InstDesc& d, int x, int y) {
+    return ((d.bc_y != 0) && (y == 0 || y == d.ny - 1)) ||
+           ((d.bc_x == 1 || d.bc_x == 2 || d.bc_x == 4) && (x == 0 || x == d.nx - 1));
+}
+
+template <class S, int SR, int SPLIT>
+__global__ __launch_bounds__(256) void pair_kernel(StepArgs a, int xcd, int nontemporal) {
+    constexpr int kRows = kPairH + 4;
+    __shared__ float lds[8][kRows][64];
+    const int b = blockIdx.x;
+    int t = b;
+    if (xcd) {
+        const int nb = a.ntiles, q = nb >> 3, r = nb & 7, k = b & 7, j = b >> 3;
+        t = k * q + (k < r ? k : r) + j;
+    }
+    t += a.tile_base;
+    const int inst = a.tile_inst[t];
+    const InstDesc& d = a.desc[inst];
+    const RefView rv = ref_view(a.ref[inst]);
+    const int local = t - d.p_tile_begin;
+    const int ty = local / d.p_tiles_x;
+    const int tx = local - ty * d.p_tiles_x;
+    const int x0 = tx * kPairW, y0 = ty * kPairH;
+    const int nx = d.nx, ny = d.ny;
+    const int lx = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index: rows are wave-uniform
+    const uint32_t step = a.ctr_in[0];
+    const S* __restrict__ src = reinterpret_cast<const S*>(a.src) + d.off;
+    S* __restrict__ dst = reinterpret_cast<S*>(a.dst) + d.off;
+    const int gx = wrapm(x0 - 2 + lx, nx, 64);
+
+    // window loads: the post-relaxation state of step m - 1
+    for (int ly = wv; ly < kRows; ly += 4) {
+        const int gy = wrapm(y0 - 2 + ly, ny, kRows);
+        S v[8];
+        const S* row = src + (int64_t)gy * d.row;
+        const int64_t c = col_off(d, gx);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = row[(int64_t)i * d.plane + c];
+        float E = 0.0f;
+        if (SPLIT) E = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(row) + e_off(d, gx));
+        float f[8];
+        reload<S, SPLIT>(v, E, f);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) lds[i][ly][lx] = f[i];
+    }
+    __syncthreads();
+
+    // step m on the inner window (rows 1 .. kPairH + 2, columns 1 .. 62)
+    constexpr int kHold = (kPairH + 2 + 3) / 4;
+    float hold[kHold][8];
+#pragma unroll
+    for (int j = 0; j < kHold; ++j) {
+        const int ly = 1 + wv + 4 * j;
+        if (ly > kPairH + 2 || lx == 0 || lx == 63) continue;
+        const int gy = wrapm(y0 - 2 + ly, ny, kRows);
+        float g[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) g[i] = lds[i][ly - vel_y(i)][lx - vel_x(i)];
+        if (a.apply_shift) apply_shift(g, rv);
+        if (on_wall(d, gx, gy)) boundary(g, d, rv.wall_kd, gx, gy);
+        uint32_t r[4] = {0u, 0u, 0u, 0u};
+        if (SR) sr_words(r, (uint32_t)(d.node_off + (int64_t)gy * nx + gx), step, a.seed);
+        S o[8];
+        float E;
+        relax_round<S, SR, SPLIT>(g, d, rv, r, o, E);
+        reload<S, SPLIT>(o, E, hold[j]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kHold; ++j) {
+        const int ly = 1 + wv + 4 * j;
+        if (ly > kPairH + 2 || lx == 0 || lx == 63) continue;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) lds[i][ly][lx] = hold[j][i];
+    }
+    __syncthreads();
+
+    // step m + 1 on the outputs (rows 2 .. kPairH + 1, columns 2 .. 61)
+    const int ox = x0 + lx - 2;
+    if (lx >= 2 && lx <= 61 && ox < nx) {
+        for (int ly = 2 + wv; ly <= kPairH + 1; ly += 4) {
+            const int oy = y0 + ly - 2;
+            if (oy >= ny) break;
+            float g[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) g[i] = lds[i][ly - vel_y(i)][lx - vel_x(i)];
+            if (on_wall(d, ox, oy)) boundary(g, d, rv.wall_kd, ox, oy);
+            uint32_t r[4] = {0u, 0u, 0u, 0u};
+            if (SR) sr_words(r, (uint32_t)(d.node_off + (int64_t)oy * nx + ox), step + 1u, a.seed);
+            S o[8];
+            float E;
+            relax_round<S, SR, SPLIT>(g, d, rv, r, o, E);
+            S* row = dst + (int64_t)oy * d.row;
+            const int64_t c = col_off(d, ox);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) store_raw<S>(reinterpret_cast<char*>(row + (int64_t)i * d.plane + c), o[i], nontemporal);
+            if (SPLIT) store_one<float, 0>(reinterpret_cast<char*>(row) + e_off(d, ox), E, 0u, nontemporal);
+        }
+    }
+    if (t == 0 && threadIdx.x == 0) a.ctr_out[0] = step + 2u;
+}
+
+template <class S, int SPLIT>
+static hipError_t launch_pair_s(const Shape& sh, const StepArgs& a, hipStream_t st) {
+    dim3 grid(a.ntiles), block(256);
+    if (a.sr)
+        hipLaunchKernelGGL((pair_kernel<S, 1, SPLIT>), grid, block, 0, st, a, sh.xcd, sh.nt);
+    else
+        hipLaunchKernelGGL((pair_kernel<S, 0, SPLIT>), grid, block, 0, st, a, sh.xcd, sh.nt);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair(int storage, const Shape& sh, const StepArgs& a, hipStream_t st) {
+    if (a.ntiles <= 0) return hipSuccess;
+    switch (storage) {
+        case 0: return launch_pair_s<float, 0>(sh, a, st);
+        case 1: return launch_pair_s<_Float16, 0>(sh, a, st);
+        case 2: return launch_pair_s<bf16_bits, 0>(sh, a, st);
+        case 3: return launch_pair_s<_Float16, 1>(sh, a, st);
+        case 4: return launch_pair_s<bf16_bits, 1>(sh, a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 // ------------------------------------------------------------------ init
 
 // Pre-relaxation state at n = 0 (equilibrium of Eq. 15 with j = q / beta, wall

@@ -33,6 +33,9 @@ struct alignas(64) InstDesc {
     int32_t group_begin;    // first reduction group of this instance (kGroup tiles each)
     int32_t ngroups;        // reduction groups of this instance
     int32_t wk[4];          // boundary kind of each wall (x=0, x=nx-1, y=0, y=ny-1); 0 on periodic axes
+    int32_t p_tiles_x;      // two-step kernel: tiles along x (kPairW columns each)
+    int32_t p_tile_begin;   // two-step kernel: first global tile of this instance
+    int32_t p_ntiles;       // two-step kernel: tiles of this instance
     int64_t row;            // elements between rows
     int64_t plane;          // elements between direction runs
     int64_t chunk;          // elements between 64-node chunks (0: planes layout)
@@ -107,6 +110,20 @@ struct Shape {
 
 enum StepMode { kPlain = 0, kSnap = 1, kCheck = 2 };
 
+// Two-step (temporally blocked) kernel: a block of 256 threads takes a tile of
+// kPairW x kPairH output nodes, loads it with a two-node halo (64 x
+// (kPairH + 4) nodes) into LDS, advances the inner 62 x (kPairH + 2) nodes one
+// step in place, then the 60 x kPairH outputs a second step.
+// 6 output rows: the 20 KB window lets eight blocks (the 32-wave limit) share
+// a CU; measured on MI355X (8192^2 FP32): 6 rows 135, 8 rows 132, 12 rows 118,
+// 20 rows 107, 28 rows 87 GLUPS -- the kernel is latency bound, and occupancy
+// outweighs the halo recomputation.
+#ifndef PLBM_PAIR_ROWS
+#define PLBM_PAIR_ROWS 6
+#endif
+constexpr int kPairW = 60;
+constexpr int kPairH = PLBM_PAIR_ROWS;
+
 struct StepArgs {
     const InstDesc* desc;
     const int32_t* tile_inst;   // global tile -> instance
@@ -128,6 +145,11 @@ struct StepArgs {
 // snap_stride: nodes of the whole handle (the snapshot holds dT, qx, qy planes).
 hipError_t launch_step(int storage, const Shape& sh, int mode, const StepArgs& a,
                        int64_t snap_stride, hipStream_t st);
+
+// Two time steps (m, m + 1) in one pass over HBM: both plain (no check work);
+// a.apply_shift refers to the first of them; a.tile_inst / tile_base / ntiles
+// index the two-step tile table.  Same bits as two single steps.
+hipError_t launch_pair(int storage, const Shape& sh, const StepArgs& a, hipStream_t st);
 
 // Moments of the state at time n of one instance.  With pull != 0 the state is
 // rebuilt from the post-relaxation populations of step n-1 (advection plus

@@ -86,6 +86,7 @@ SIGNATURES = [
     ("lbm_last_check", ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(lbm_check_info)]),
     ("lbm_coefficients", ctypes.c_int, [_P, ctypes.c_int32, _D]),
     ("lbm_set_wall_flux", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]),
+    ("lbm_set_step_fusion", ctypes.c_int, [_P, ctypes.c_int32]),
     ("lbm_set_schedule", ctypes.c_int, [_P, ctypes.c_int32]),
     ("lbm_set_launch_shape", ctypes.c_int, [_P, ctypes.POINTER(lbm_launch_shape)]),
     ("lbm_get_launch_shape", ctypes.c_int, [_P, ctypes.POINTER(lbm_launch_shape)]),
@@ -210,6 +211,10 @@ def lbm_coefficients(h, inst: int) -> dict:
 
 def lbm_set_wall_flux(h, inst: int, wall: int, q0: float) -> None:
     _check(library().lbm_set_wall_flux(h, int(inst), int(wall), float(q0)), "lbm_set_wall_flux", h)
+
+
+def lbm_set_step_fusion(h, steps: int) -> None:
+    _check(library().lbm_set_step_fusion(h, int(steps)), "lbm_set_step_fusion", h)
 
 
 def lbm_set_schedule(h, schedule: int) -> None:
@@ -366,6 +371,10 @@ class Lattice:
         """Heat flux into the domain through a HEATFLUX wall (0: x=0, 1: x=nx-1,
         2: y=0, 3: y=ny-1) for the steps enqueued afterwards."""
         lbm_set_wall_flux(self.h, inst, wall, float(q0))
+
+    def set_step_fusion(self, steps: int) -> None:
+        """Time steps per launch where allowed (2: two-step kernel, 1: off)."""
+        lbm_set_step_fusion(self.h, steps)
 
     def set_schedule(self, name: str) -> None:
         lbm_set_schedule(self.h, {"batched": LBM_SCHED_BATCHED, "per_instance": LBM_SCHED_PER_INSTANCE,

@@ -384,6 +384,78 @@ def test_set_wall_flux_errors():
     lat.close()
 
 
+FUSION_CASES = [
+    ("periodic f32", dict(), "f32", "nearest"),
+    ("periodic f16 sr", dict(), "f16", "stochastic"),
+    ("periodic f32 sr", dict(), "f32", "stochastic"),
+    ("periodic bf16_split", dict(), "bf16_split", "nearest"),
+    ("periodic f16_split sr", dict(), "f16_split", "stochastic"),
+    ("periodic f16", dict(), "f16", "nearest"),
+    ("periodic bf16 sr", dict(), "bf16", "stochastic"),
+    ("walls x", dict(bc_x="isothermal", t_wall=(1.004, 0.997, 0, 0)), "f32", "nearest"),
+    ("diffuse y", dict(bc_y="diffuse"), "f32", "nearest"),
+    ("gradient channel", dict(bc_x="gradient", bc_y="diffuse", grad_x=2e-3), "f32", "nearest"),
+    ("heat flux y split", dict(bc_y="heatflux", q_wall=(0, 0, 1e-3, -4e-4)), "f16_split", "nearest"),
+    ("square corners", dict(bc_x="isothermal", bc_y="isothermal", wall_bc=(0, 0, 0, "heatflux"),
+                            t_wall=(1.0, 1.0, 1.0, 0.0), q_wall=(0, 0, 0, 1e-3)), "f32", "nearest"),
+]
+
+
+def _fused_run(case, T0, qx, qy, storage, rounding, fuse, steps, check, schedule=None, n_inst=1):
+    """Run with `fuse` steps per launch (1: single steps only; 2: two-step
+    launches wherever allowed, also for the kinds whose default is 1)."""
+    lat = Lattice([instance_from_case(case)] * n_inst, storage=storage, check_interval=check,
+                  rounding=rounding, seed=9)
+    lat.set_step_fusion(fuse)
+    if schedule:
+        lat.set_schedule(schedule)
+    for k in range(n_inst):
+        lat.init(k, T0, qx, qy)
+        for w in range(4):
+            if case.q_wall[w]:
+                lat.set_wall_flux(k, w, case.q_wall[w])
+    out = []
+    for n in steps:
+        lat.step(n)
+        out.append([lat.moments(k) for k in range(n_inst)])
+    lat.close()
+    return out
+
+
+@pytest.mark.parametrize("name,kw,storage,rounding", FUSION_CASES, ids=[c[0] for c in FUSION_CASES])
+def test_two_step_kernel_bitwise(name, kw, storage, rounding):
+    """The two-step (temporally blocked) kernel gives the same bits as single
+    steps: storage kinds and roundings, every boundary kind, corners, check
+    steps every 10 (pairs stop before snapshot/check steps), call lengths that
+    leave odd remainders, and the per-instance and graph schedules."""
+    case, T0, qx, qy = _random_case(131, 37, 0.6, 7.0, 51, **kw)
+    steps = (1, 2, 3, 7, 26)
+    ref_out = _fused_run(case, T0, qx, qy, storage, rounding, 1, steps, 10)
+    for fuse, sched in ((2, None), (2, "per_instance"), (2, "graph")):
+        got = _fused_run(case, T0, qx, qy, storage, rounding, fuse, steps, 10, sched)
+        for a_list, b_list in zip(got, ref_out):
+            for a, b in zip(a_list[0], b_list[0]):
+                assert np.array_equal(a, b), (name, fuse, sched)
+    e = eps(case, ref_out[-1][0], oracle_fields(case, sum(steps), T0, qx, qy))
+    log(f"two-step {name}: eps={e}")
+    assert max(e) < TOL_STORAGE[storage]
+
+
+@pytest.mark.parametrize("nx,ny", [(2, 2), (3, 2), (5, 3), (61, 13), (65, 14), (121, 25)])
+def test_two_step_kernel_small_and_ragged(nx, ny):
+    """Tiles larger than the lattice (the window wraps several times), and
+    lattices one node past a tile edge: same bits as single steps, and the
+    oracle."""
+    case, T0, qx, qy = _random_case(nx, ny, 0.8, 2.0, nx * 7 + ny)
+    # five steps (two pairs and a single): the random flux decays by 0.6 per
+    # step, and later it nears the FP32 noise floor on the tiniest grids
+    a = _fused_run(case, T0, qx, qy, "f32", "nearest", 1, (5,), 0)[0][0]
+    b = _fused_run(case, T0, qx, qy, "f32", "nearest", 2, (5,), 0)[0][0]
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v), (nx, ny)
+    assert max(eps(case, b, oracle_fields(case, 5, T0, qx, qy))) < 1e-5
+
+
 def test_totals_and_invariants():
     """FP64 totals: energy constant up to FP32 storage rounding; total heat flux
     multiplied by rho per step (periodic)."""
