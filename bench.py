@@ -33,7 +33,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 # 8 population reads + 8 writes per node; split storage adds the FP32 energy
 BYTES_PER_NODE = {"f32": 64, "f16": 32, "bf16": 32, "f16_split": 40, "bf16_split": 40}
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2010_01847_amd", "csrc", "lbm_device.hip")
+# the device code and the shared header that fixes its tiles and descriptors
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2010_01847_amd", "csrc", f) for f in ("lbm_device.hip", "lbm_internal.h")]
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -41,7 +42,7 @@ def _measured_traffic(storage: str, n: int):
     """HBM bytes per launch of the step kernel from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy), or
     None when no summary covers this workload or the kernel source changed
-    since the counters were taken."""
+    since the counters were taken (hash of the device sources)."""
     import hashlib
     path = os.path.join(PROFILES, f"stream_collide_{storage}_second_sound_{n}.md")
     if not os.path.exists(path):
@@ -51,7 +52,7 @@ def _measured_traffic(storage: str, n: int):
         if ":" in line and not line.startswith(("|", "#")):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()
     if fields.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
         return None
     return int(float(fields["traffic_bytes_per_launch"]))
