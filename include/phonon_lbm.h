@@ -301,9 +301,10 @@ int lbm_set_launch_shape(lbm_handle h, const lbm_launch_shape* shape);
 int lbm_get_launch_shape(lbm_handle h, lbm_launch_shape* shape);
 
 /* Time every candidate launch shape on this handle's own instances and keep
- * the fastest.  Must be called after lbm_create and before lbm_init (it runs
- * steps on scratch contents); each candidate is timed over `steps` steps
- * (0 = 20) with HIP events.  If the environment variable LBM_AUTOTUNE_CACHE
+ * the fastest, then time two-step launches against it and set the steps per
+ * launch (lbm_set_step_fusion) to the faster.  Must be called after
+ * lbm_create and before lbm_init (it runs steps on scratch contents); each
+ * candidate is timed over `steps` steps (0 = 20) with HIP events.  If the environment variable LBM_AUTOTUNE_CACHE
  * names a file, a result for the same device, storage and instance shapes is
  * read from it instead of timing, and new results are appended to it.
  * report (may be NULL) receives a JSON summary of the timings.

@@ -1092,7 +1092,7 @@ static std::string tune_key(lbm_ctx* h) {
     return b;
 }
 
-static bool cache_lookup(const char* path, const std::string& key, Shape* out) {
+static bool cache_lookup(const char* path, const std::string& key, Shape* out, int* fuse) {
     FILE* fp = fopen(path, "r");
     if (!fp) return false;
     char line[512];
@@ -1105,6 +1105,8 @@ static bool cache_lookup(const char* path, const std::string& key, Shape* out) {
                    k, &s.vec, &s.bx, &s.by, &s.xcd, &s.nt) == 6 &&
             key == k) {
             *out = s;
+            const char* f = strstr(line, "\"fuse\": ");
+            *fuse = (f && f[8] == '2') ? 2 : 1;   // the digit after '"fuse": '
             found = true;   // the last matching line wins
         }
     }
@@ -1146,6 +1148,38 @@ static int time_shape(lbm_ctx* h, const Shape& s, int steps, hipEvent_t e0, hipE
     return LBM_OK;
 }
 
+// Average time per step of two-step launches (the launch shape's XCD remap and
+// store hint), on scratch contents.
+static int time_pair(lbm_ctx* h, int launches, hipEvent_t e0, hipEvent_t e1, float* us) {
+    StepArgs a;
+    a.desc = h->d_desc();
+    a.tile_inst = h->d_ptiles();
+    a.snap = nullptr;
+    a.partials = nullptr;
+    a.tile_base = 0;
+    a.ntiles = (int32_t)h->ptile_inst.size();
+    a.seed = h->seed;
+    a.sr = h->sr;
+    a.ref = h->d_ref();
+    a.apply_shift = 0;
+    int src = 0;
+    for (int w = 0; w < 2 + launches; ++w) {
+        if (w == 2) HIPCALL(h, hipEventRecord(e0, h->stream));
+        a.src = h->buf(src);
+        a.dst = h->buf(1 - src);
+        a.ctr_in = h->d_ctr() + src;
+        a.ctr_out = h->d_ctr() + (1 - src);
+        HIPCALL(h, launch_pair(h->storage, h->shape, a, h->stream));
+        src = 1 - src;
+    }
+    HIPCALL(h, hipEventRecord(e1, h->stream));
+    HIPCALL(h, hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HIPCALL(h, hipEventElapsedTime(&ms, e0, e1));
+    *us = 1000.0f * ms / (2 * launches);
+    return LBM_OK;
+}
+
 int lbm_autotune(lbm_handle h, int32_t steps, char* report, size_t report_len) {
     if (!valid(h)) return LBM_EINVAL;
     if (!h->base) return h->fail(LBM_ESTATE, "no device memory bound");
@@ -1155,10 +1189,13 @@ int lbm_autotune(lbm_handle h, int32_t steps, char* report, size_t report_len) {
     const std::string key = tune_key(h);
     const char* path = getenv("LBM_AUTOTUNE_CACHE");
     Shape cached;
-    if (path && *path && cache_lookup(path, key, &cached)) {
+    int cached_fuse = 1;
+    if (path && *path && cache_lookup(path, key, &cached, &cached_fuse)) {
         lbm_launch_shape ls = {cached.vec, cached.bx, cached.by, cached.xcd, cached.nt};
         if (report && report_len) snprintf(report, report_len, "{\"key\": \"%s\", \"cached\": true}", key.c_str());
-        return lbm_set_launch_shape(h, &ls);
+        const int rc = lbm_set_launch_shape(h, &ls);
+        if (!rc) h->fuse = cached_fuse;
+        return rc;
     }
     // scratch contents: zeros, so no timing depends on garbage bit patterns
     HIPCALL(h, hipMemsetAsync(h->buf(0), 0, h->L.buf_bytes, h->stream));
@@ -1209,25 +1246,37 @@ int lbm_autotune(lbm_handle h, int32_t steps, char* report, size_t report_len) {
             s.nt = nt;
             try_shape(s);
         }
+    // steps per launch: the two-step kernel (with the best shape's XCD remap
+    // and store hint) against the best single-step shape
+    float pair_us = 1e30f;
+    if (!rc) {
+        h->shape = best;
+        build_tiles(h);
+        rc = upload_tables(h);
+        if (!rc) rc = time_pair(h, (steps + 1) / 2, e0, e1, &pair_us);
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    char b[256];
-    snprintf(b, sizeof b, "], \"best\": [%d, %d, %d, %d, %d, %.2f]}", best.vec, best.bx, best.by, best.xcd,
-             best.nt, best_us);
+    const int fuse = pair_us < best_us ? 2 : 1;
+    char b[320];
+    snprintf(b, sizeof b, "], \"best\": [%d, %d, %d, %d, %d, %.2f], \"pair_us_per_step\": %.2f, "
+             "\"steps_per_launch\": %d}", best.vec, best.bx, best.by, best.xcd, best.nt, best_us, pair_us, fuse);
     rep += b;
     if (report && report_len) snprintf(report, report_len, "%s", rep.c_str());
     if (path && *path) {
         FILE* fp = fopen(path, "a");
         if (fp) {
             fprintf(fp, "{\"key\": \"%s\", \"vec\": %d, \"block_x\": %d, \"block_y\": %d, \"xcd\": %d, \"nt\": %d, "
-                        "\"us\": %.2f}\n",
-                    key.c_str(), best.vec, best.bx, best.by, best.xcd, best.nt, best_us);
+                        "\"us\": %.2f, \"fuse\": %d}\n",
+                    key.c_str(), best.vec, best.bx, best.by, best.xcd, best.nt, best_us, fuse);
             fclose(fp);
         }
     }
     lbm_launch_shape ls = {best.vec, best.bx, best.by, best.xcd, best.nt};
-    return lbm_set_launch_shape(h, &ls);
+    rc = lbm_set_launch_shape(h, &ls);
+    if (!rc) h->fuse = fuse;
+    return rc;
 }
 
 }  // extern "C"

@@ -456,6 +456,39 @@ def test_two_step_kernel_small_and_ragged(nx, ny):
     assert max(eps(case, b, oracle_fields(case, 5, T0, qx, qy))) < 1e-5
 
 
+def test_autotune_choices_cache_and_results(tmp_path, monkeypatch):
+    """lbm_autotune times the launch shapes and the two-step kernel on the
+    handle's own instances, applies the fastest, and records the choice in
+    the cache file; a second handle of the same shapes reads it back.  A
+    tuned handle still matches the oracle; tuning after init is refused."""
+    import json
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("LBM_AUTOTUNE_CACHE", str(cache))
+    case, T0, qx, qy = _random_case(257, 130, 0.6, 7.0, 61)
+    lat = Lattice([instance_from_case(case)], check_interval=10)
+    rep = json.loads(lat.autotune(6))
+    assert rep["cached"] is False and rep["steps_per_launch"] in (1, 2)
+    best = rep["best"]
+    got = lat.launch_shape()
+    assert [got["vec"], got["block_x"], got["block_y"], got["xcd_remap"], got["nontemporal"]] == best[:5]
+    log(f"autotune 257x130: best {best}, two-step {rep['pair_us_per_step']:.1f} us/step, "
+        f"steps per launch {rep['steps_per_launch']}")
+    lat.init(0, T0, qx, qy)
+    with pytest.raises(LBMError) as e:
+        lat.autotune(2)
+    assert e.value.code == LBM_ESTATE
+    lat.step(23)
+    e_fields = eps(case, lat.moments(0), oracle_fields(case, 23, T0, qx, qy))
+    lat.close()
+    assert max(e_fields) < 1e-5
+    line = json.loads(cache.read_text().strip().splitlines()[-1])
+    assert line["fuse"] == rep["steps_per_launch"]
+    lat2 = Lattice([instance_from_case(case)], check_interval=10)
+    assert json.loads(lat2.autotune(6))["cached"] is True
+    assert lat2.launch_shape() == got
+    lat2.close()
+
+
 def test_totals_and_invariants():
     """FP64 totals: energy constant up to FP32 storage rounding; total heat flux
     multiplied by rho per step (periodic)."""
