@@ -1,4 +1,5 @@
-"""Compile the C oracle into ``oracle/libphonon_oracle.so`` (gcc, OpenMP, -O2, no fast-math).
+"""Compile the C oracles (D2Q8 and D3Q14 steppers) into ``oracle/libphonon_oracle.so``
+(gcc, OpenMP, -O2, no fast-math).
 
 Test infrastructure: the product build never links this library.
 """
@@ -9,14 +10,14 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "phonon_oracle.c")
+SRCS = [os.path.join(HERE, f) for f in ("phonon_oracle.c", "phonon_oracle_d3q14.c")]
 LIB = os.path.join(HERE, "libphonon_oracle.so")
 
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + f".tmp{os.getpid()}"
     cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-fno-fast-math", "-o", tmp, SRC, "-lm"]
+           "-fno-fast-math", "-o", tmp] + SRCS + ["-lm"]
     if verbose:
         print(" ".join(cmd), file=sys.stderr)
     subprocess.run(cmd, check=True)

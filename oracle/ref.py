@@ -33,6 +33,12 @@ class _Case(ctypes.Structure):
                 ("wall_kind", ctypes.c_int * 4)]
 
 
+class _Case3(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("tau_n", ctypes.c_double), ("tau_r", ctypes.c_double),
+                ("cv", ctypes.c_double), ("t0", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -40,7 +46,7 @@ def lib():
     """Load the oracle library, compiling it first if it is missing or stale."""
     global _lib
     if _lib is None:
-        src_m = os.path.getmtime(_build.SRC)
+        src_m = max(os.path.getmtime(f) for f in _build.SRCS)
         if not os.path.exists(_build.LIB) or os.path.getmtime(_build.LIB) < src_m:
             _build.build()
         L = ctypes.CDLL(_build.LIB)
@@ -56,6 +62,14 @@ def lib():
         L.ora_totals.argtypes = [c, d, d]
         L.ora_max_threads.restype = ctypes.c_int
         L.ora_set_threads.argtypes = [ctypes.c_int]
+        c3 = P(_Case3)
+        L.ora3_check.argtypes = [c3]
+        L.ora3_check.restype = ctypes.c_int
+        L.ora3_collide_node.argtypes = [c3, d, d]
+        L.ora3_init.argtypes = [c3, d, d, d, d, d]
+        L.ora3_run.argtypes = [c3, d, d, ctypes.c_long]
+        L.ora3_moments.argtypes = [c3, d, d, d, d, d]
+        L.ora3_totals.argtypes = [c3, d, d]
         _lib = L
     return _lib
 
@@ -140,6 +154,68 @@ def collide_node(case, e_in: np.ndarray) -> np.ndarray:
     e_in = np.ascontiguousarray(e_in, dtype=np.float64)
     out = np.zeros(8)
     lib().ora_collide_node(ctypes.byref(c), _dptr(e_in), _dptr(out))
+    return out
+
+
+class Oracle3D:
+    """One fully periodic D3Q14 lattice advanced by the C stepper in FP64.
+
+    Fields are (nz, ny, nx) arrays, x fastest.  The populations are indexed
+    0..5 for the axis movers +x -x +y -y +z -z and 6..13 for the corner movers
+    (see ``phonon_oracle_d3q14.c``)."""
+
+    def __init__(self, nx: int, ny: int, nz: int, tau_n: float, tau_r: float,
+                 T0: Optional[np.ndarray] = None, q: Optional[Tuple] = None,
+                 cv: float = 1.0, t0: float = 1.0):
+        c = _Case3()
+        c.nx, c.ny, c.nz = int(nx), int(ny), int(nz)
+        c.tau_n, c.tau_r, c.cv, c.t0 = float(tau_n), float(tau_r), float(cv), float(t0)
+        if lib().ora3_check(ctypes.byref(c)) != 0:
+            raise ValueError(f"oracle rejects D3Q14 case {nx}x{ny}x{nz}, tau_n={tau_n}, tau_r={tau_r}")
+        self.c, self.shape = c, (int(nz), int(ny), int(nx))
+        n = 14 * nx * ny * nz
+        self.e = np.zeros(n, dtype=np.float64)
+        self.work = np.zeros(n, dtype=np.float64)
+        if T0 is None:
+            T0 = np.full(self.shape, float(t0))
+        T0 = np.ascontiguousarray(np.broadcast_to(T0, self.shape), dtype=np.float64)
+        qs = [None, None, None] if q is None else \
+            [None if v is None else np.ascontiguousarray(np.broadcast_to(v, self.shape), dtype=np.float64)
+             for v in q]
+        lib().ora3_init(ctypes.byref(c), _dptr(T0), *[_dptr(v) for v in qs], _dptr(self.e))
+        self.steps = 0
+
+    def run(self, n: int) -> float:
+        """Advance n steps; returns wall seconds spent in the stepper."""
+        t = time.perf_counter()
+        lib().ora3_run(ctypes.byref(self.c), _dptr(self.e), _dptr(self.work), int(n))
+        self.steps += int(n)
+        return time.perf_counter() - t
+
+    def moments(self) -> Tuple[np.ndarray, np.ndarray, np.ndarray, np.ndarray]:
+        out = [np.empty(self.shape) for _ in range(4)]
+        lib().ora3_moments(ctypes.byref(self.c), _dptr(self.e), *[_dptr(v) for v in out])
+        return tuple(out)
+
+    def totals(self) -> np.ndarray:
+        """[C_V sum (T - t0), sum q_x, sum q_y, sum q_z]."""
+        out = np.zeros(4)
+        lib().ora3_totals(ctypes.byref(self.c), _dptr(self.e), _dptr(out))
+        return out
+
+    def populations(self) -> np.ndarray:
+        """State as (14, nz, ny, nx)."""
+        return self.e.reshape((14,) + self.shape)
+
+
+def collide_node_3d(tau_n: float, tau_r: float, e_in: np.ndarray, cv: float = 1.0) -> np.ndarray:
+    """Apply the single-node D3Q14 relaxation (Eq. 13 with Eqs. 15-16) to 14 populations."""
+    c = _Case3()
+    c.nx = c.ny = c.nz = 1
+    c.tau_n, c.tau_r, c.cv, c.t0 = float(tau_n), float(tau_r), float(cv), 0.0
+    e_in = np.ascontiguousarray(e_in, dtype=np.float64)
+    out = np.zeros(14)
+    lib().ora3_collide_node(ctypes.byref(c), _dptr(e_in), _dptr(out))
     return out
 
 

@@ -1,4 +1,5 @@
-"""Seeded synthetic inputs for the phonon D2Q8 lattice Boltzmann workloads.
+"""Seeded synthetic inputs for the phonon lattice Boltzmann workloads (D2Q8, and
+periodic D3Q14 boxes).
 
 This module holds no arithmetic of the lattice Boltzmann scheme.  It only
 describes grid shapes, relaxation-time pairs, boundary kinds and wall values,
@@ -254,3 +255,134 @@ def knudsen_sweep(n_inst: int = 256, seed: int = SEED, side_lo: int = 64,
     return [Case(f"sweep_{k}", int(nx[k]), int(ny[k]), float(tn[k]), float(tr[k]),
                  bc_x="gradient", bc_y="diffuse", t0=1.0, grad_x=grad_x, steps=steps)
             for k in range(n_inst)]
+
+
+# --------------------------------------------------------------------------
+# three-dimensional (D3Q14) lattices: fully periodic boxes
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Mode3:
+    """One real Fourier mode amp * cos(2 pi (kx x/nx + ky y/ny + kz z/nz) + phase)."""
+    kx: int
+    ky: int
+    kz: int
+    amp: float
+    phase: float
+
+
+@dataclasses.dataclass
+class Case3D:
+    """One periodic nx x ny x nz box: relaxation times and initial field.
+    Fields are (nz, ny, nx) arrays, x fastest."""
+
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    tau_n: float
+    tau_r: float
+    t0: float = 1.0
+    cv: float = 1.0
+    steps: int = 0
+    init: str = "uniform"          # "uniform" | "modes" | "gaussian" | "field"
+    init_args: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def nodes(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+def draw_modes_3d(n_modes: int = 16, kmax: int = 8, amp_total: float = 1e-3,
+                  seed: int = SEED) -> List[Mode3]:
+    """Distinct integer wave vectors in [-kmax, kmax]^3 minus 0, no +/- pairs,
+    amplitude amp_total / n_modes each, phases uniform in [0, 2 pi)."""
+    rng = np.random.Generator(np.random.PCG64(seed + 3))
+    modes: List[Mode3] = []
+    seen = set()
+    while len(modes) < n_modes:
+        k = tuple(int(v) for v in rng.integers(-kmax, kmax + 1, size=3))
+        if k == (0, 0, 0) or k in seen or tuple(-v for v in k) in seen:
+            continue
+        seen.add(k)
+        modes.append(Mode3(*k, amp_total / n_modes, float(rng.uniform(0.0, 2.0 * math.pi))))
+    return modes
+
+
+def modes_field_3d(modes: Sequence[Mode3], nx: int, ny: int, nz: int, t0: float) -> np.ndarray:
+    """t0 + sum of modes on the whole box, shape (nz, ny, nx)."""
+    x = np.arange(nx, dtype=np.float64)
+    y = np.arange(ny, dtype=np.float64)
+    z = np.arange(nz, dtype=np.float64)
+    out = np.full((nz, ny, nx), t0, dtype=np.float64)
+    for m in modes:
+        ex = np.exp(1j * (2.0 * math.pi * m.kx * x / nx + m.phase))
+        ey = np.exp(1j * (2.0 * math.pi * m.ky * y / ny))
+        ez = np.exp(1j * (2.0 * math.pi * m.kz * z / nz))
+        out += m.amp * np.real(ez[:, None, None] * ey[None, :, None] * ex[None, None, :])
+    return out
+
+
+def modes_field_3d_torch(modes: Sequence[Mode3], nx: int, ny: int, nz: int, t0: float, device):
+    """Same field as :func:`modes_field_3d`, built with torch on ``device`` in
+    FP64 (one plane of phases at a time), so a 512^3 field needs no host copy."""
+    import torch
+    x = torch.arange(nx, dtype=torch.float64, device=device)
+    y = torch.arange(ny, dtype=torch.float64, device=device)
+    out = torch.full((nz, ny, nx), t0, dtype=torch.float64, device=device)
+    for m in modes:
+        pxy = (2.0 * math.pi * m.ky / ny) * y[:, None] + (2.0 * math.pi * m.kx / nx) * x[None, :] + m.phase
+        for z in range(nz):
+            out[z].add_(torch.cos(pxy + 2.0 * math.pi * m.kz * z / nz), alpha=m.amp)
+    return out
+
+
+def gaussian_field_3d(nx: int, ny: int, nz: int, center, amp: float, sigma: float,
+                      t0: float) -> np.ndarray:
+    """t0 + amp * exp(-r^2 / (2 sigma^2)) around center = (cx, cy, cz); (nz, ny, nx)."""
+    g = [np.exp(-((np.arange(n, dtype=np.float64) - c) ** 2) / (2.0 * sigma * sigma))
+         for n, c in zip((nx, ny, nz), center)]
+    return t0 + amp * g[2][:, None, None] * g[1][None, :, None] * g[0][None, None, :]
+
+
+def random_field_3d(nx: int, ny: int, nz: int, amp: float, t0: float, seed: int) -> np.ndarray:
+    """Uniform random field t0 + amp * U[-1, 1) (rough; parity tests only)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return t0 + amp * rng.uniform(-1.0, 1.0, size=(nz, ny, nx))
+
+
+def random_flux_3d(nx: int, ny: int, nz: int, amp: float, seed: int):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return tuple(amp * rng.uniform(-1.0, 1.0, size=(nz, ny, nx)) for _ in range(3))
+
+
+def initial_field_3d(case: Case3D) -> np.ndarray:
+    """Initial temperature field of a 3D case, shape (nz, ny, nx)."""
+    shape = (case.nz, case.ny, case.nx)
+    if case.init == "uniform":
+        return np.full(shape, case.t0)
+    if case.init == "modes":
+        return modes_field_3d(case.init_args["modes"], case.nx, case.ny, case.nz, case.t0)
+    if case.init == "gaussian":
+        a = case.init_args
+        return gaussian_field_3d(case.nx, case.ny, case.nz, a["center"], a["amp"], a["sigma"], case.t0)
+    if case.init == "field":
+        return np.asarray(case.init_args["T"], dtype=np.float64).reshape(shape)
+    raise ValueError(f"unknown init {case.init!r}")
+
+
+def thermal_waves_3d_case(n: int = 512, tau_n: float = 0.6, tau_r: float = 5.0,
+                          steps: int = 200, seed: int = SEED, n_modes: int = 16,
+                          kmax: int = 8, amp_total: float = 1e-3) -> Case3D:
+    """Periodic n^3 box, T0 = 1 plus n_modes seeded Fourier modes (integer wave
+    numbers up to kmax per axis, total amplitude amp_total), no initial flux."""
+    return Case3D(f"thermal_waves_{n}", n, n, n, tau_n, tau_r, t0=1.0, steps=steps,
+                  init="modes", init_args=dict(modes=draw_modes_3d(n_modes, kmax, amp_total, seed)))
+
+
+def second_sound_3d_case(n: int = 96, tau_n: float = 0.55, tau_r: float = 50.0,
+                         amp: float = 0.01, sigma: float = 4.0, steps: int = 40) -> Case3D:
+    """Periodic n^3 box, Gaussian pulse amp * exp(-r^2 / (2 sigma^2)) on T0 = 1 at
+    the centre node."""
+    return Case3D(f"second_sound_3d_{n}", n, n, n, tau_n, tau_r, t0=1.0, steps=steps,
+                  init="gaussian", init_args=dict(center=(n // 2, n // 2, n // 2), amp=amp, sigma=sigma))
