@@ -16,7 +16,8 @@ rounding of the stores, which keeps smooth fields from stalling) of the same
 workload are reported under "rows".  "sweep" reports the batched Knudsen
 sweep (256 uneven channel instances in one handle) under the three
 schedules: one launch for all instances, the same captured in HIP graphs,
-and one launch per instance.  The oracle (plain FP64 C stepper) is timed on
+and one launch per instance.  "d3q14" reports the three-dimensional lattice
+on a 512^3 periodic box (FP32, BF16 and FP16 storage) with its own roofline.  The oracle (plain FP64 C stepper) is timed on
 a bounded window of the same workload on the host cores ("cpu_baseline").
 """
 from __future__ import annotations
@@ -33,18 +34,25 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 # 8 population reads + 8 writes per node; split storage adds the FP32 energy
 BYTES_PER_NODE = {"f32": 64, "f16": 32, "bf16": 32, "f16_split": 40, "bf16_split": 40}
-# the device code and the shared header that fixes its tiles and descriptors
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2010_01847_amd", "csrc", f) for f in ("lbm_device.hip", "lbm_internal.h")]
+# D3Q14: 14 population reads + 14 writes per node
+BYTES_PER_NODE_3D = {"f32": 112, "f16": 56, "bf16": 56}
+_CSRC = os.path.join(ROOT, "paper_2010_01847_amd", "csrc")
+# the device code and the headers that fix its tiles, descriptors and rounding
+KERNEL_SOURCES = [os.path.join(_CSRC, f) for f in ("lbm_device.hip", "lbm_internal.h", "lbm_numeric.h")]
+KERNEL_SOURCES_3D = [os.path.join(_CSRC, f) for f in ("d3q14_device.hip", "d3q14_internal.h", "lbm_numeric.h")]
 PROFILES = os.path.join(ROOT, "profiles")
 
 
 def _measured_traffic(storage: str, n: int):
-    """HBM bytes per launch of the step kernel from the committed rocprofv3
-    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy), or
-    None when no summary covers this workload or the kernel source changed
-    since the counters were taken (hash of the device sources)."""
+    """HBM bytes per launch of the D2Q8 step kernel from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB
+    copy), or None when no summary covers this workload or the kernel source
+    changed since the counters were taken (hash of the device sources)."""
+    return _traffic_from(os.path.join(PROFILES, f"stream_collide_{storage}_second_sound_{n}.md"), KERNEL_SOURCES)
+
+
+def _traffic_from(path: str, sources):
     import hashlib
-    path = os.path.join(PROFILES, f"stream_collide_{storage}_second_sound_{n}.md")
     if not os.path.exists(path):
         return None
     fields = {}
@@ -52,7 +60,7 @@ def _measured_traffic(storage: str, n: int):
         if ":" in line and not line.startswith(("|", "#")):
             k, v = line.split(":", 1)
             fields[k.strip()] = v.strip()
-    sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)).hexdigest()
+    sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in sources)).hexdigest()
     if fields.get("kernel_source_sha256") != sha or "traffic_bytes_per_launch" not in fields:
         return None
     return int(float(fields["traffic_bytes_per_launch"]))
@@ -77,6 +85,10 @@ def _parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
     p.add_argument("--autotune", action="store_true")
+    p.add_argument("--d3q14-steps", type=int, default=200, help="timed steps of the D3Q14 box (0: skip)")
+    p.add_argument("--d3q14-n", type=int, default=512, help="side of the periodic D3Q14 box")
+    p.add_argument("--d3q14-rows", default="f32,bf16:stochastic,f16:stochastic",
+                   help="storage[:rounding] rows of the D3Q14 box")
     p.add_argument("--copy-probe", action="store_true",
                    help="also run a 1 GiB torch device copy 5 times (counter calibration)")
     return p.parse_args()
@@ -206,6 +218,53 @@ def _run_sweep(args, torch, P, W):
     return out
 
 
+def _run_d3q14(args, torch, W):
+    """D3Q14 thermal-wave box: periodic n^3 (n = 512 by default), T0 = 1 plus
+    16 seeded Fourier modes (wave numbers up to 8 per axis, total amplitude
+    1e-3), tau_N = 0.6, tau_R = 5, no initial flux.  One launch per step; the
+    per-launch time is the HIP-event time over the timed steps (consecutive
+    launches on one stream) divided by their number."""
+    from paper_2010_01847_amd.d3q14 import Box
+    case = W.thermal_waves_3d_case(args.d3q14_n)
+    nodes = case.nodes
+    out = {"workload": f"thermal_waves_{case.nx}^3_periodic_d3q14", "nodes": nodes, "tau_n": case.tau_n,
+           "tau_r": case.tau_r, "steps": args.d3q14_steps, "rows": []}
+    for item in [r for r in args.d3q14_rows.split(",") if r]:
+        st, _, rnd = item.partition(":")
+        rnd = rnd or "nearest"
+        scale = 2.0 ** -23 if st == "f16" else 0.0
+        box = Box(case.nx, case.ny, case.nz, case.tau_n, case.tau_r, storage=st, scale=scale,
+                  stochastic=rnd == "stochastic", seed=1847)
+        T0 = W.modes_field_3d_torch(case.init_args["modes"], case.nx, case.ny, case.nz, case.t0, "cuda")
+        box.init(T0)
+        del T0
+        stream = torch.cuda.current_stream()
+        box.step(20)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        box.step(args.d3q14_steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.d3q14_steps
+        box.close()
+        gbs = BYTES_PER_NODE_3D[st] * nodes / (ms / 1e3) / 1e9
+        out["rows"].append({"storage": st, "rounding": rnd, "mlups": round(nodes / (ms / 1e3) / 1e6, 1),
+                            "ms_per_step": round(ms, 4), "gbs": round(gbs, 1),
+                            "frac": round(gbs / HBM_PEAK_GBS, 4)})
+    f32 = [r for r in out["rows"] if r["storage"] == "f32"]
+    if f32:
+        r = f32[0]
+        out["roofline"] = {"bound": "hbm", "achieved": r["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": r["frac"], "kernel": "d3q14 step_kernel (FP32 storage)",
+                           "kernel_us": round(r["ms_per_step"] * 1e3, 1),
+                           "bytes_per_launch": BYTES_PER_NODE_3D["f32"] * nodes,
+                           "traffic": _traffic_from(os.path.join(
+                               PROFILES, f"stream_collide_d3q14_f32_thermal_waves_{case.nx}.md"), KERNEL_SOURCES_3D)}
+    return out
+
+
 def _default_rounding(storage):
     return "stochastic" if storage in ("f16", "bf16") else "nearest"
 
@@ -259,6 +318,7 @@ def main():
         if (st, rnd) != (args.storage, main_rounding):
             rows.append(_run_gpu(args, st, rnd, torch, P, W))
     sweep = _run_sweep(args, torch, P, W) if args.sweep_steps > 0 else None
+    d3q14 = _run_d3q14(args, torch, W) if args.d3q14_steps > 0 else None
     cpu = None if args.no_cpu_baseline else _cpu_baseline(args, W)
     gbs = main_row["kernel_gbs"]
     out = {
@@ -288,6 +348,7 @@ def main():
                      "bytes_per_launch": BYTES_PER_NODE[args.storage] * args.n * args.n * main_row["fusion"]},
         "cpu_baseline": cpu,
         "sweep": sweep,
+        "d3q14": d3q14,
         "host_io": {k: round(v, 4) for k, v in main_row["host_io"].items()},
         "rows": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()
                   if k not in ("tune", "host_io")} for r in rows],

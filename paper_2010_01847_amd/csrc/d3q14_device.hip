@@ -1,0 +1,455 @@
+// Device code of the D3Q14 phonon lattice Boltzmann path for gfx950 (CDNA4,
+// wave64): a fully periodic box advanced by one fused kernel per time step.
+//
+// The scheme is the paper's (Eq. 13 with the equilibrium of Eq. 15, the
+// resistive source of Eq. 16, the moments of Eqs. 53-54, tau = tau_C + 1/2 by
+// Eq. 49, lattice units dx = dt = c = 1) on the three-dimensional lattice the
+// paper names as its direct extension (Sec. 2.2): 6 axis movers and 8 corner
+// movers, no rest population, with the weights that make the moment
+// identities of Sec. 2.3 (Eqs. 22-28) hold on this velocity set,
+//     omega = 1/9 (axis), 1/24 (corner);   a = 1/5 (axis), 1/40 (corner).
+//
+// Stored quantity: g_i = (e_i - omega_i C_V t0) / s, the scaled deviation from
+// the uniform equilibrium at the reference temperature.  Because sum omega_i = 1
+// and sum omega_i c_i = 0, the relaxation of g has exactly the form of the
+// relaxation of e, and it is homogeneous, so the scale s only rescales the
+// stored numbers (FP16 needs s to keep small deviations out of subnormals).
+//
+// Per node and step: pull the 14 populations g_i(x - c_i) written by the
+// previous step (periodic wrap on every axis), form E = sum g_i and
+// J = sum c_i g_i in registers, relax
+//     g_i <- g_i + (omega_i E - g_i) / tau + k_i (c_i . J),
+//     k_i = (5/3) a_i beta (1/tau - (1 - 1/(2 tau)) / tau_R),
+// which is Eq. 13 with q = beta J (Eq. 54) folded into the equilibrium and
+// source terms, and store to the other buffer at x.  The path moves 14 loads
+// and 14 stores per node for about 90 FP32 operations: it is bound by HBM
+// bandwidth, so the design is about coalescing, not arithmetic: a wavefront
+// covers 64 consecutive nodes of a row, every one of its 28 accesses is one
+// contiguous 256-byte (FP32) span, and the x-shifted loads reuse in L2 the
+// lines the neighbouring wavefront of the same row brings in.
+#include "d3q14_internal.h"
+#include "lbm_numeric.h"
+
+#include <stdint.h>
+
+#include <utility>
+
+namespace plbm3 {
+
+using plbm::bf16_bits;
+using plbm::bits16;
+using plbm::Cvt;
+using plbm::mix32;
+using plbm::sr_add_f32;
+using plbm::sr_bf16;
+using plbm::sr_f16;
+
+// ------------------------------------------------------------------ lattice
+
+// Velocities: 0..5 the axis movers +x -x +y -y +z -z; 6..13 the corner movers
+// (sx, sy, sz) with sx = -1 for odd i - 6, sy = -1 when bit 1 of i - 6 is set,
+// sz = -1 when bit 2 is set.
+__host__ __device__ constexpr int cx(int i) {
+    return i == 0 ? 1 : i == 1 ? -1 : i < 6 ? 0 : (((i - 6) & 1) ? -1 : 1);
+}
+__host__ __device__ constexpr int cy(int i) {
+    return i == 2 ? 1 : i == 3 ? -1 : i < 6 ? 0 : (((i - 6) & 2) ? -1 : 1);
+}
+__host__ __device__ constexpr int cz(int i) {
+    return i == 4 ? 1 : i == 5 ? -1 : i < 6 ? 0 : (((i - 6) & 4) ? -1 : 1);
+}
+
+// v * c for c in {-1, 0, 1}, as an add/negate only (no multiply by zero).
+__device__ __forceinline__ float signed_add(float acc, float v, int c) {
+    return c > 0 ? acc + v : c < 0 ? acc - v : acc;
+}
+
+// c_i . J for direction I: one signed term on an axis mover, three (x, y, z
+// in that order) on a corner mover.
+template <int I>
+__device__ __forceinline__ float c_dot(float jx, float jy, float jz) {
+    if constexpr (I < 6) {
+        if constexpr (cx(I) != 0) return cx(I) > 0 ? jx : -jx;
+        else if constexpr (cy(I) != 0) return cy(I) > 0 ? jy : -jy;
+        else return cz(I) > 0 ? jz : -jz;
+    } else {
+        const float s = cx(I) > 0 ? jx : -jx;
+        return signed_add(signed_add(s, jy, cy(I)), jz, cz(I));
+    }
+}
+
+// ------------------------------------------------------------------ tiles
+
+// Node of this thread: tiles of 64 x rows_per_tile nodes, x-tiles fastest,
+// then y, then z.  With xcd_remap the 8 XCDs (which take blocks round-robin)
+// each get one contiguous range of tiles, so the neighbouring tiles of a row,
+// whose x-shifted loads share cache lines, meet in the same L2.
+__device__ __forceinline__ bool node_of_thread(const Geometry& g, int xcd_remap, int& x, int& y, int& z) {
+    uint32_t tile = blockIdx.x;
+    if (xcd_remap) {
+        const uint32_t per = (g.ntiles + 7u) >> 3;
+        tile = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+    }
+    if (tile >= g.ntiles) return false;
+    const uint32_t tx = tile % g.ntx;
+    const uint32_t r = tile / g.ntx;
+    const uint32_t ty = r % g.nty;
+    z = (int)(r / g.nty);
+    x = (int)(tx * kTileX + (threadIdx.x & 63u));
+    y = (int)(ty * g.rows_per_tile + (threadIdx.x >> 6));
+    return x < g.nx && y < g.ny;
+}
+
+// In-plane element offsets of the 14 pull sources of node (x, y, z): direction
+// i reads the node x - c_i, wrapped on every axis.
+struct PullOffsets {
+    uint32_t off[kQ];
+};
+
+__device__ __forceinline__ PullOffsets pull_offsets(const Geometry& g, int x, int y, int z) {
+    const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
+    const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
+    const uint32_t P = (uint32_t)g.pitch, NY = (uint32_t)g.ny;
+    PullOffsets o;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const int xs = cx(i) > 0 ? xm : cx(i) < 0 ? xp : x;
+        const int ys = cy(i) > 0 ? ym : cy(i) < 0 ? yp : y;
+        const int zs = cz(i) > 0 ? zm : cz(i) < 0 ? zp : z;
+        o.off[i] = ((uint32_t)zs * NY + (uint32_t)ys) * P + (uint32_t)xs;
+    }
+    return o;
+}
+
+template <class S>
+__device__ __forceinline__ void pull(const Geometry& g, const void* src, const PullOffsets& o, float v[kQ]) {
+    const S* base = reinterpret_cast<const S*>(src);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) v[i] = Cvt<S>::ld(base[(int64_t)i * g.plane + o.off[i]]);
+}
+
+// E = sum g_i, J = sum c_i g_i (fixed order).
+__device__ __forceinline__ void moments(const float v[kQ], float& E, float& jx, float& jy, float& jz) {
+    E = 0.0f;
+    jx = 0.0f;
+    jy = 0.0f;
+    jz = 0.0f;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        E = E + v[i];
+        jx = signed_add(jx, v[i], cx(i));
+        jy = signed_add(jy, v[i], cy(i));
+        jz = signed_add(jz, v[i], cz(i));
+    }
+}
+
+template <class S, int SR>
+__device__ __forceinline__ S rounded(float v, uint32_t r16) {
+    if constexpr (SR && __is_same(S, _Float16)) return sr_f16(v, r16);
+    else if constexpr (SR && __is_same(S, bf16_bits)) return sr_bf16(v, r16);
+    else return Cvt<S>::st(v);
+}
+
+template <class S>
+__device__ __forceinline__ void put(S* p, S v, int nontemporal) {
+    if constexpr (sizeof(S) == 4) {
+        uint32_t raw;
+        __builtin_memcpy(&raw, &v, 4);
+        if (nontemporal) __builtin_nontemporal_store(raw, reinterpret_cast<uint32_t*>(p));
+        else *reinterpret_cast<uint32_t*>(p) = raw;
+    } else {
+        uint16_t raw;
+        __builtin_memcpy(&raw, &v, 2);
+        if (nontemporal) __builtin_nontemporal_store(raw, reinterpret_cast<uint16_t*>(p));
+        else *reinterpret_cast<uint16_t*>(p) = raw;
+    }
+}
+
+// One relaxation of direction I and its store.
+template <class S, int SR, int I>
+__device__ __forceinline__ void relax_store_one(const Coeffs& c, const float v[kQ], float wE_axis, float wE_corner,
+                                                float jx, float jy, float jz, const uint32_t r[7], S* dst,
+                                                int64_t plane, uint32_t off, int nontemporal) {
+    const float wE = I < 6 ? wE_axis : wE_corner;
+    const float k = I < 6 ? c.k_axis : c.k_corner;
+    const float delta = fmaf(c.inv_tau, wE - v[I], k * c_dot<I>(jx, jy, jz));
+    S o;
+    if constexpr (SR && __is_same(S, float)) o = sr_add_f32(v[I], delta, bits16(r, I));
+    else o = rounded<S, SR>(v[I] + delta, SR ? bits16(r, I) : 0u);
+    put<S>(dst + (int64_t)I * plane + off, o, nontemporal);
+}
+
+template <class S, int SR, int... Is>
+__device__ __forceinline__ void relax_store_all(const Coeffs& c, const float v[kQ], float wE_axis, float wE_corner,
+                                                float jx, float jy, float jz, const uint32_t r[7], S* dst,
+                                                int64_t plane, uint32_t off, int nontemporal,
+                                                std::integer_sequence<int, Is...>) {
+    (relax_store_one<S, SR, Is>(c, v, wE_axis, wE_corner, jx, jy, jz, r, dst, plane, off, nontemporal), ...);
+}
+
+// ------------------------------------------------------------------ step
+
+template <class S, int SR>
+__global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
+    int x, y, z;
+    if (!node_of_thread(a.g, a.xcd_remap, x, y, z)) return;
+    const PullOffsets o = pull_offsets(a.g, x, y, z);
+    float v[kQ];
+    pull<S>(a.g, a.src, o, v);
+    float E, jx, jy, jz;
+    moments(v, E, jx, jy, jz);
+    uint32_t r[7] = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    if (SR) {
+        const uint32_t node = ((uint32_t)z * (uint32_t)a.g.ny + (uint32_t)y) * (uint32_t)a.g.nx + (uint32_t)x;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) r[k] = mix32(node ^ mix32(a.step * 8u + (uint32_t)k + a.seed * 0x9e3779b9u));
+    }
+    const uint32_t own = ((uint32_t)z * (uint32_t)a.g.ny + (uint32_t)y) * (uint32_t)a.g.pitch + (uint32_t)x;
+    relax_store_all<S, SR>(a.c, v, a.c.omega_axis * E, a.c.omega_corner * E, jx, jy, jz, r,
+                           reinterpret_cast<S*>(a.dst), a.g.plane, own, a.nontemporal,
+                           std::make_integer_sequence<int, kQ>{});
+}
+
+static unsigned step_grid(const StepArgs& a) {
+    return a.xcd_remap ? 8u * ((a.g.ntiles + 7u) / 8u) : a.g.ntiles;
+}
+
+template <class S>
+static hipError_t launch_step_s(int sr, const StepArgs& a, hipStream_t st) {
+    const dim3 grid(step_grid(a)), block(64u * a.g.rows_per_tile);
+    if (sr) hipLaunchKernelGGL((step_kernel<S, 1>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((step_kernel<S, 0>), grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_step(int storage, int sr, const StepArgs& a, hipStream_t st) {
+    switch (storage) {
+        case 0: return launch_step_s<float>(sr, a, st);
+        case 1: return launch_step_s<_Float16>(sr, a, st);
+        case 2: return launch_step_s<bf16_bits>(sr, a, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------------------------ init
+
+// Thread per stored element position (x, y, z): for each direction i the
+// Eq. 15 equilibrium of node x + c_i, as a scaled deviation.  (5/3) a_i is
+// 1/3 on the axis movers and 1/24 on the corner movers.
+template <class S>
+__global__ __launch_bounds__(256) void init_kernel(Geometry g, S* dst, const double* __restrict__ T,
+                                                   const double* __restrict__ qx, const double* __restrict__ qy,
+                                                   const double* __restrict__ qz, double t0, double cv,
+                                                   double inv_beta, double inv_s) {
+    int x, y, z;
+    if (!node_of_thread(g, 0, x, y, z)) return;
+    const uint32_t own = ((uint32_t)z * (uint32_t)g.ny + (uint32_t)y) * (uint32_t)g.pitch + (uint32_t)x;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        int xs = x + cx(i), ys = y + cy(i), zs = z + cz(i);
+        xs = xs < 0 ? xs + g.nx : xs >= g.nx ? xs - g.nx : xs;
+        ys = ys < 0 ? ys + g.ny : ys >= g.ny ? ys - g.ny : ys;
+        zs = zs < 0 ? zs + g.nz : zs >= g.nz ? zs - g.nz : zs;
+        const int64_t n = ((int64_t)zs * g.ny + ys) * g.nx + xs;
+        const double dT = T ? T[n] - t0 : 0.0;
+        double cq = 0.0;
+        if (qx && cx(i)) cq += cx(i) * qx[n];
+        if (qy && cy(i)) cq += cy(i) * qy[n];
+        if (qz && cz(i)) cq += cz(i) * qz[n];
+        const double w = i < 6 ? 1.0 / 9.0 : 1.0 / 24.0;
+        const double a53 = i < 6 ? 1.0 / 3.0 : 1.0 / 24.0;
+        const double e = (w * cv * dT + a53 * cq * inv_beta) * inv_s;
+        put<S>(dst + (int64_t)i * g.plane + own, Cvt<S>::st((float)e), 0);
+    }
+}
+
+hipError_t launch_init(int storage, const Geometry& g, void* dst, const double* T, const double* qx,
+                       const double* qy, const double* qz, double t0, double cv, double inv_beta, double inv_s,
+                       hipStream_t st) {
+    const dim3 grid(g.ntiles), block(64u * g.rows_per_tile);
+    switch (storage) {
+        case 0:
+            hipLaunchKernelGGL((init_kernel<float>), grid, block, 0, st, g, reinterpret_cast<float*>(dst), T, qx,
+                               qy, qz, t0, cv, inv_beta, inv_s);
+            break;
+        case 1:
+            hipLaunchKernelGGL((init_kernel<_Float16>), grid, block, 0, st, g, reinterpret_cast<_Float16*>(dst), T,
+                               qx, qy, qz, t0, cv, inv_beta, inv_s);
+            break;
+        case 2:
+            hipLaunchKernelGGL((init_kernel<bf16_bits>), grid, block, 0, st, g, reinterpret_cast<bf16_bits*>(dst), T,
+                               qx, qy, qz, t0, cv, inv_beta, inv_s);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ moments
+
+// FP64 moments (Eqs. 53-54) of the populations the next step would pull at
+// node (x, y, z).
+template <class S>
+__device__ __forceinline__ void node_moments(const Geometry& g, const void* src, int x, int y, int z,
+                                             double& E, double& jx, double& jy, double& jz) {
+    const PullOffsets o = pull_offsets(g, x, y, z);
+    const S* base = reinterpret_cast<const S*>(src);
+    E = 0.0;
+    jx = 0.0;
+    jy = 0.0;
+    jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) {
+        const double v = (double)Cvt<S>::ld(base[(int64_t)i * g.plane + o.off[i]]);
+        E += v;
+        if (cx(i)) jx += cx(i) > 0 ? v : -v;
+        if (cy(i)) jy += cy(i) > 0 ? v : -v;
+        if (cz(i)) jz += cz(i) > 0 ? v : -v;
+    }
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void moments_kernel(Geometry g, const void* src, double e_scale, double q_scale,
+                                                      double* dT, double* qx, double* qy, double* qz) {
+    int x, y, z;
+    if (!node_of_thread(g, 0, x, y, z)) return;
+    double E, jx, jy, jz;
+    node_moments<S>(g, src, x, y, z, E, jx, jy, jz);
+    const int64_t n = ((int64_t)z * g.ny + y) * g.nx + x;
+    if (dT) dT[n] = E * e_scale;
+    if (qx) qx[n] = jx * q_scale;
+    if (qy) qy[n] = jy * q_scale;
+    if (qz) qz[n] = jz * q_scale;
+}
+
+template <class S>
+__global__ __launch_bounds__(256) void sample_kernel(Geometry g, const void* src, double e_scale, double q_scale,
+                                                     const int64_t* __restrict__ nodes, int64_t count,
+                                                     double* __restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= count) return;
+    const int64_t n = nodes[k];
+    if (n < 0 || n >= (int64_t)g.nx * g.ny * g.nz) {
+        // an index outside the box yields NaN rather than a stray read
+        const double nan = __builtin_nan("");
+        out[4 * k + 0] = nan;
+        out[4 * k + 1] = nan;
+        out[4 * k + 2] = nan;
+        out[4 * k + 3] = nan;
+        return;
+    }
+    const int x = (int)(n % g.nx);
+    const int64_t r = n / g.nx;
+    const int y = (int)(r % g.ny);
+    const int z = (int)(r / g.ny);
+    double E, jx, jy, jz;
+    node_moments<S>(g, src, x, y, z, E, jx, jy, jz);
+    out[4 * k + 0] = E * e_scale;
+    out[4 * k + 1] = jx * q_scale;
+    out[4 * k + 2] = jy * q_scale;
+    out[4 * k + 3] = jz * q_scale;
+}
+
+hipError_t launch_moments(int storage, const Geometry& g, const void* src, double e_scale, double q_scale,
+                          double* dT, double* qx, double* qy, double* qz, hipStream_t st) {
+    const dim3 grid(g.ntiles), block(64u * g.rows_per_tile);
+    switch (storage) {
+        case 0: hipLaunchKernelGGL((moments_kernel<float>), grid, block, 0, st, g, src, e_scale, q_scale, dT, qx, qy, qz); break;
+        case 1: hipLaunchKernelGGL((moments_kernel<_Float16>), grid, block, 0, st, g, src, e_scale, q_scale, dT, qx, qy, qz); break;
+        case 2: hipLaunchKernelGGL((moments_kernel<bf16_bits>), grid, block, 0, st, g, src, e_scale, q_scale, dT, qx, qy, qz); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sample(int storage, const Geometry& g, const void* src, double e_scale, double q_scale,
+                         const int64_t* nodes, int64_t count, double* out, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((count + 255) / 256)), block(256);
+    switch (storage) {
+        case 0: hipLaunchKernelGGL((sample_kernel<float>), grid, block, 0, st, g, src, e_scale, q_scale, nodes, count, out); break;
+        case 1: hipLaunchKernelGGL((sample_kernel<_Float16>), grid, block, 0, st, g, src, e_scale, q_scale, nodes, count, out); break;
+        case 2: hipLaunchKernelGGL((sample_kernel<bf16_bits>), grid, block, 0, st, g, src, e_scale, q_scale, nodes, count, out); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ totals
+
+constexpr int kTotalsMaxBlocks = 2048;
+
+int totals_blocks(const Geometry& g) {
+    const int64_t rows = (int64_t)g.ny * g.nz;
+    return (int)(rows < kTotalsMaxBlocks ? rows : kTotalsMaxBlocks);
+}
+
+// Fixed tree over 256 threads of 4 running sums.
+__device__ void block_sum4(double s[4], double* out) {
+    __shared__ double red[4][256];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) red[c][t] = s[c];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) red[c][t] += red[c][t + w];
+        __syncthreads();
+    }
+    if (t == 0)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) out[c] = red[c][0];
+}
+
+// Stage 1: block b sums rows b, b + G, ... of every direction plane (thread t
+// takes x = t, t + 256, ...).  Row order and tree are fixed, so the result
+// does not depend on the device.
+template <class S>
+__global__ __launch_bounds__(256) void totals_kernel(Geometry g, const void* src, double* partials) {
+    const S* base = reinterpret_cast<const S*>(src);
+    const int64_t rows = (int64_t)g.ny * g.nz;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
+        const int y = (int)(r % g.ny), z = (int)(r / g.ny);
+        const int64_t row = ((int64_t)z * g.ny + y) * g.pitch;
+#pragma unroll
+        for (int i = 0; i < kQ; ++i)
+            for (int x = threadIdx.x; x < g.nx; x += 256) {
+                const double v = (double)Cvt<S>::ld(base[(int64_t)i * g.plane + row + x]);
+                s[0] += v;
+                if (cx(i)) s[1] += cx(i) > 0 ? v : -v;
+                if (cy(i)) s[2] += cy(i) > 0 ? v : -v;
+                if (cz(i)) s[3] += cz(i) > 0 ? v : -v;
+            }
+    }
+    block_sum4(s, partials + 4 * (int64_t)blockIdx.x);
+}
+
+// Stage 2: one block over the stage-1 records in order.
+__global__ __launch_bounds__(256) void totals_final_kernel(const double* __restrict__ partials, int n,
+                                                           double* __restrict__ out) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = threadIdx.x; j < n; j += 256)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) s[c] += partials[4 * j + c];
+    block_sum4(s, out);
+}
+
+hipError_t launch_totals(int storage, const Geometry& g, const void* src, double* partials, double* out,
+                         hipStream_t st) {
+    const int nb = totals_blocks(g);
+    switch (storage) {
+        case 0: hipLaunchKernelGGL((totals_kernel<float>), dim3(nb), dim3(256), 0, st, g, src, partials); break;
+        case 1: hipLaunchKernelGGL((totals_kernel<_Float16>), dim3(nb), dim3(256), 0, st, g, src, partials); break;
+        case 2: hipLaunchKernelGGL((totals_kernel<bf16_bits>), dim3(nb), dim3(256), 0, st, g, src, partials); break;
+        default: return hipErrorInvalidValue;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(256), 0, st, partials, nb, out);
+    return hipGetLastError();
+}
+
+}  // namespace plbm3

@@ -1,0 +1,74 @@
+// Shared between the D3Q14 device code (d3q14_device.hip) and its host
+// runtime (d3q14_runtime.cpp): box geometry, relaxation coefficients, launch
+// parameters and the host-side launch entry points of the device file.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace plbm3 {
+
+constexpr int kQ = 14;          // 6 axis movers + 8 corner movers
+constexpr int kTileX = 64;      // nodes of a row per tile (one wavefront)
+constexpr int kRowAlign = 64;   // row pitch in elements is a multiple of this
+
+// Geometry of one periodic box in device memory.  Populations of direction i
+// start at element i * plane; inside a plane node (x, y, z) sits at element
+// (z * ny + y) * pitch + x.  Elements at x >= nx are padding, never read.
+struct Geometry {
+    int32_t nx, ny, nz;
+    int32_t pitch;              // elements per row (nx rounded up to kRowAlign)
+    int64_t plane;              // elements from one direction plane to the next
+    uint32_t ntx, nty;          // tiles along x (kTileX nodes) and y (rows_per_tile rows)
+    uint32_t rows_per_tile;     // 1, 2 or 4: rows of a 64 * rows_per_tile thread block
+    uint32_t ntiles;            // ntx * nty * nz
+};
+
+// Per-direction factors of one relaxation in FP32 (see the device file):
+// g_i + inv_tau (omega_i E - g_i) + k_i (c_i . J).
+struct Coeffs {
+    float inv_tau;
+    float omega_axis, omega_corner;
+    float k_axis, k_corner;
+};
+
+struct StepArgs {
+    Geometry g;
+    Coeffs c;
+    const void* src;            // post-relaxation populations of the previous step
+    void* dst;                  // this step's post-relaxation populations
+    uint32_t step;              // step index (stochastic rounding counter)
+    uint32_t seed;
+    int32_t xcd_remap;          // hand each XCD a contiguous range of tiles
+    int32_t nontemporal;        // streaming (non-temporal) stores
+};
+
+// storage: 0 FP32, 1 FP16, 2 BF16; sr: stochastic rounding of the stores.
+hipError_t launch_step(int storage, int sr, const StepArgs& a, hipStream_t st);
+
+// Equilibrium initial state: element (i, x) holds the scaled deviation of the
+// Eq. 15 equilibrium at node x + c_i, so that the first pull reads e_i(x, 0).
+hipError_t launch_init(int storage, const Geometry& g, void* dst, const double* T, const double* qx,
+                       const double* qy, const double* qz, double t0, double cv, double inv_beta,
+                       double inv_s, hipStream_t st);
+
+// FP64 moments of the pulled populations at every node: dT = E * e_scale,
+// q = J * q_scale.  Null outputs are skipped.
+hipError_t launch_moments(int storage, const Geometry& g, const void* src, double e_scale, double q_scale,
+                          double* dT, double* qx, double* qy, double* qz, hipStream_t st);
+
+// The same at `count` listed nodes (linear index (z * ny + y) * nx + x);
+// out[4k + 0..3] = dT, qx, qy, qz of node k.
+hipError_t launch_sample(int storage, const Geometry& g, const void* src, double e_scale, double q_scale,
+                         const int64_t* nodes, int64_t count, double* out, hipStream_t st);
+
+// Number of first-stage blocks of launch_totals and the FP64 partials they need
+// (4 doubles each).
+int totals_blocks(const Geometry& g);
+
+// FP64 sums over all stored populations: out[0] = sum g, out[1..3] = sum c g
+// (unscaled), two fixed-order stages.
+hipError_t launch_totals(int storage, const Geometry& g, const void* src, double* partials, double* out,
+                         hipStream_t st);
+
+}  // namespace plbm3

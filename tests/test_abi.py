@@ -11,12 +11,13 @@ import paper_2010_01847_amd as P
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "phonon_lbm.h")
+HEADER3 = os.path.join(ROOT, "include", "phonon_d3q14.h")
 
 
-def _declared():
-    src = open(HEADER).read()
+def _declared(path=HEADER, prefix="lbm_"):
+    src = open(path).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(" + prefix + r"[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_symbols_exported():
@@ -29,13 +30,27 @@ def test_header_symbols_exported():
     assert set(names) == bound, set(names) ^ bound
 
 
+def test_d3q14_header_symbols_exported():
+    names = _declared(HEADER3, "lbm3d_")
+    assert "lbm3d_create" in names and "lbm3d_step" in names and "lbm3d_sample" in names
+    L = P.d3q14.library()
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(names) == {s[0] for s in P.d3q14.SIGNATURES3}
+    # every header under include/ is covered by one of the two binding tables
+    inc = os.path.join(ROOT, "include")
+    assert sorted(os.listdir(inc)) == ["phonon_d3q14.h", "phonon_lbm.h"]
+
+
 def test_struct_layouts_match_header(tmp_path):
     """Sizes and field offsets of the ctypes structs equal those a C compiler
     gives the header's structs."""
     import subprocess
     structs = {"lbm_instance": P.lbm_instance, "lbm_config": P.lbm_config,
-               "lbm_check_info": P.lbm_check_info, "lbm_launch_shape": P.lbm_launch_shape}
-    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "phonon_lbm.h"', "int main(void) {"]
+               "lbm_check_info": P.lbm_check_info, "lbm_launch_shape": P.lbm_launch_shape,
+               "lbm3d_config": P.d3q14.lbm3d_config, "lbm3d_launch_shape": P.d3q14.lbm3d_launch_shape}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "phonon_lbm.h"', '#include "phonon_d3q14.h"',
+             "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} %zu\\n", sizeof({name}));')
         for fname, _ in cls._fields_:
@@ -151,3 +166,62 @@ def test_null_handle_calls_are_rejected():
     assert P.library().lbm_step(None, 1) == P.LBM_EINVAL
     assert P.library().lbm_steps_done(None) == -1
     P.library().lbm_destroy(None)   # ignored
+
+
+# ---------------------------------------------------------------- D3Q14
+
+def _cfg3(**kw):
+    c = P.d3q14.lbm3d_config()
+    c.nx, c.ny, c.nz = kw.get("nx", 16), kw.get("ny", 8), kw.get("nz", 4)
+    c.storage = kw.get("storage", P.LBM_F32)
+    c.flags = kw.get("flags", P.LBM_FLAG_EXTERNAL_MEMORY)
+    c.tau_n, c.tau_r = kw.get("tau_n", 0.6), kw.get("tau_r", 0.8)
+    c.cv, c.t0, c.scale = kw.get("cv", 1.0), kw.get("t0", 1.0), kw.get("scale", 0.0)
+    return c
+
+
+def test_d3q14_required_bytes():
+    """Two buffers of 14 direction planes, rows padded to 64 elements."""
+    b32 = P.d3q14.lbm3d_required_bytes(_cfg3(nx=100, ny=30, nz=7))
+    b16 = P.d3q14.lbm3d_required_bytes(_cfg3(nx=100, ny=30, nz=7, storage=P.LBM_BF16))
+    assert b32 >= 2 * 14 * 128 * 30 * 7 * 4
+    assert b16 >= 2 * 14 * 128 * 30 * 7 * 2 and b16 < b32
+    assert P.d3q14.lbm3d_required_bytes(_cfg3(nx=1, ny=1, nz=1)) > 0
+
+
+@pytest.mark.parametrize("kw", [
+    dict(nx=0), dict(ny=0), dict(nz=-1), dict(tau_n=0.0), dict(tau_n=math.inf), dict(tau_r=0.0),
+    dict(tau_r=-2.0), dict(storage=P.LBM_F16_SPLIT), dict(storage=9), dict(flags=0x100),
+    dict(scale=3.0), dict(scale=-1.0), dict(cv=-1.0), dict(t0=math.nan),
+    dict(nx=4096, ny=4096, nz=128),           # 2^31 elements in a plane
+])
+def test_d3q14_config_validation(kw):
+    with pytest.raises(P.LBMError) as e:
+        P.d3q14.lbm3d_required_bytes(_cfg3(**kw))
+    assert e.value.code == P.LBM_EINVAL
+
+
+def test_d3q14_handle_state_without_gpu():
+    """Create and bind take no device action with external memory; stepping
+    before init and bad launch shapes are rejected on the host."""
+    D = P.d3q14
+    h = D.lbm3d_create(_cfg3(tau_r=math.inf))
+    try:
+        with pytest.raises(P.LBMError) as e:
+            D.lbm3d_step(h, 1)
+        assert e.value.code == P.LBM_ESTATE
+        with pytest.raises(P.LBMError) as e:
+            D.lbm3d_bind(h, 0x1000 + 3, 1 << 40)
+        assert e.value.code == P.LBM_EINVAL
+        for bad in ((3, 1, 0), (4, 2, 0), (1, 0, 5)):
+            with pytest.raises(P.LBMError):
+                D.lbm3d_set_launch_shape(h, D.lbm3d_launch_shape(*bad))
+        D.lbm3d_set_launch_shape(h, D.lbm3d_launch_shape(2, 0, 1))
+        s = D.lbm3d_get_launch_shape(h)
+        assert (s.rows_per_tile, s.xcd_remap, s.nontemporal) == (2, 0, 1)
+        assert D.lbm3d_steps_done(h) == 0
+    finally:
+        D.lbm3d_destroy(h)
+    assert P.d3q14.library().lbm3d_step(None, 1) == P.LBM_EINVAL
+    assert P.d3q14.library().lbm3d_steps_done(None) == -1
+    P.d3q14.library().lbm3d_destroy(None)

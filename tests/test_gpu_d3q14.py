@@ -1,0 +1,210 @@
+"""Parity of the D3Q14 HIP path (through the C ABI) with the FP64 D3Q14 oracle.
+
+Metrics as for D2Q8 (relative L2 over the compared nodes):
+  eps_T = ||dT - dT_or|| / ||dT_or||,  eps_q = ||q - q_or|| / ||q_or|| (three components).
+Tolerances: FP32 storage eps <= 1e-5.  Plain 16-bit storage of the scaled
+deviations keeps 11 (FP16) or 8 (BF16) significant bits per population, so on
+rough random states its error sits near the unit roundoff of one stored value
+relative to the field: held to sanity bounds 5e-3 (FP16) and 5e-2 (BF16), as
+for the plain 16-bit D2Q8 kinds.  Results that cannot depend on the launch
+shape (same per-node arithmetic) are compared bit for bit.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import bloch_d3q14 as b3, closed_forms as cf, ref
+from parity_util import log
+from paper_2010_01847_amd import LBMError, LBM_ESTATE
+from paper_2010_01847_amd.d3q14 import Box
+
+pytestmark = pytest.mark.gpu
+
+TOL3 = {"f32": 1e-5, "f16": 5e-3, "bf16": 5e-2}
+
+
+def _random_start(nx, ny, nz, seed):
+    return W.random_field_3d(nx, ny, nz, 0.01, 1.0, seed), W.random_flux_3d(nx, ny, nz, 1e-3, seed + 1)
+
+
+def _oracle(nx, ny, nz, tau_n, tau_r, T0, q, steps):
+    o = ref.Oracle3D(nx, ny, nz, tau_n, tau_r, T0, q)
+    o.run(steps)
+    T, qx, qy, qz = o.moments()
+    return T - 1.0, qx, qy, qz
+
+
+def _gpu(nx, ny, nz, tau_n, tau_r, T0, q, steps, storage="f32", shape=None, stochastic=False, seed=0,
+         scale=0.0):
+    box = Box(nx, ny, nz, tau_n, tau_r, storage=storage, stochastic=stochastic, seed=seed, scale=scale)
+    if shape:
+        box.set_launch_shape(**shape)
+    box.init(T0, q)
+    box.step(steps)
+    out = box.moments()
+    box.close()
+    return out
+
+
+def _eps(g, o):
+    den_t = np.sqrt(np.sum(o[0] ** 2))
+    e_t = np.sqrt(np.sum((g[0] - o[0]) ** 2)) / den_t if den_t > 0 else float(np.abs(g[0]).max())
+    den_q = np.sqrt(sum(np.sum(v ** 2) for v in o[1:]))
+    num_q = np.sqrt(sum(np.sum((a - b) ** 2) for a, b in zip(g[1:], o[1:])))
+    e_q = num_q / den_q if den_q > 0 else float(num_q)
+    return float(e_t), float(e_q)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_random_state_ragged(storage):
+    """Rough random start (T and q) on a 97 x 11 x 6 box (ragged against the
+    64-node tile width and the 4-row tiles), 37 steps."""
+    nx, ny, nz, n = 97, 11, 6, 37
+    T0, q = _random_start(nx, ny, nz, 5)
+    o = _oracle(nx, ny, nz, 0.7, 3.0, T0, q, n)
+    g = _gpu(nx, ny, nz, 0.7, 3.0, T0, q, n, storage=storage)
+    e_t, e_q = _eps(g, o)
+    log(f"d3q14 random 97x11x6 {storage}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
+    assert e_t < TOL3[storage] and e_q < TOL3[storage]
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (2, 1, 1), (1, 5, 3), (3, 2, 2), (64, 4, 1), (65, 5, 2), (5, 130, 3)])
+def test_small_and_degenerate_boxes(dims):
+    """Boxes of one node per axis (every pull wraps onto the node itself), two
+    nodes, exactly one tile, one tile plus one node, and a tall thin box.
+    tau_R = 50 keeps the heat flux of the one-node box (which only decays, by
+    rho = 99/101 per step) well above the rounding of the populations; with
+    tau_R ~ 1 it falls to 1e-6 of its start within 9 steps and a relative
+    error would measure FP32 cancellation, not the path."""
+    nx, ny, nz = dims
+    T0, q = _random_start(nx, ny, nz, 11)
+    o = _oracle(nx, ny, nz, 0.6, 50.0, T0, q, 9)
+    g = _gpu(nx, ny, nz, 0.6, 50.0, T0, q, 9)
+    e_t, e_q = _eps(g, o)
+    log(f"d3q14 box {dims}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
+    assert e_t < 1e-5 and e_q < 1e-5
+
+
+@pytest.mark.parametrize("tau_n,tau_r", [(0.6, 0.8), (0.55, 50.0), (2.3, 0.2), (0.51, math.inf), (1.0, 1000.0)])
+def test_regimes_f32(tau_n, tau_r):
+    nx, ny, nz, n = 40, 12, 9, 30
+    T0, q = _random_start(nx, ny, nz, 21)
+    e_t, e_q = _eps(_gpu(nx, ny, nz, tau_n, tau_r, T0, q, n), _oracle(nx, ny, nz, tau_n, tau_r, T0, q, n))
+    log(f"d3q14 regime ({tau_n}, {tau_r}): eps_T={e_t:.3e} eps_q={e_q:.3e}")
+    assert e_t < 1e-5 and e_q < 1e-5
+
+
+SHAPES3 = [dict(rows_per_tile=r, xcd_remap=x, nontemporal=nt) for r in (1, 2, 4) for x in (0, 1) for nt in (0, 1)]
+
+
+@pytest.mark.parametrize("storage,stochastic", [("f32", False), ("bf16", True)])
+def test_launch_shapes_bitwise(storage, stochastic):
+    """Every launch shape runs the same per-node arithmetic (and the same
+    counter-based random bits): identical results."""
+    nx, ny, nz, n = 131, 7, 5, 13
+    T0, q = _random_start(nx, ny, nz, 31)
+    ref_out = None
+    for sh in SHAPES3:
+        out = _gpu(nx, ny, nz, 0.55, 50.0, T0, q, n, storage=storage, shape=sh, stochastic=stochastic, seed=4)
+        if ref_out is None:
+            ref_out = out
+        else:
+            for a, b in zip(out, ref_out):
+                assert np.array_equal(a, b), sh
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_stochastic_rounding(storage):
+    """Stochastic rounding of the stores: within the storage's bound, repeatable
+    for a fixed seed, and a different seed changes the 16-bit result."""
+    nx, ny, nz, n = 70, 9, 5, 25
+    T0, q = _random_start(nx, ny, nz, 41)
+    o = _oracle(nx, ny, nz, 0.6, 5.0, T0, q, n)
+    a = _gpu(nx, ny, nz, 0.6, 5.0, T0, q, n, storage=storage, stochastic=True, seed=7)
+    b = _gpu(nx, ny, nz, 0.6, 5.0, T0, q, n, storage=storage, stochastic=True, seed=7)
+    c = _gpu(nx, ny, nz, 0.6, 5.0, T0, q, n, storage=storage, stochastic=True, seed=8)
+    e_t, e_q = _eps(a, o)
+    log(f"d3q14 SR {storage}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
+    assert e_t < TOL3[storage] and e_q < TOL3[storage]
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v)
+    assert any(not np.array_equal(u, v) for u, v in zip(a, c))
+
+
+def test_init_returns_inputs_and_sample_matches_moments():
+    """At n = 0 the moments return the initial T and q (Eq. 54 read back, to FP32
+    rounding of the stored populations); sampled nodes equal the full field."""
+    nx, ny, nz = 33, 6, 4
+    T0, q = _random_start(nx, ny, nz, 51)
+    box = Box(nx, ny, nz, 0.6, 0.8)
+    box.init(T0, q)
+    dT, qx, qy, qz = box.moments()
+    assert np.abs(dT - (T0 - 1.0)).max() < 1e-8
+    for a, b in zip((qx, qy, qz), q):
+        assert np.abs(a - b).max() < 1e-9
+    box.step(5)
+    full = box.moments()
+    rng = np.random.default_rng(2)
+    xs, ys, zs = rng.integers(0, nx, 50), rng.integers(0, ny, 50), rng.integers(0, nz, 50)
+    s = box.sample(xs, ys, zs)
+    for k in range(4):
+        assert np.array_equal(s[:, k], full[k][zs, ys, xs])
+    box.close()
+
+
+def test_totals_invariants():
+    """Total energy is constant and the total heat flux decays by
+    rho = (2 tau_r - 1)/(2 tau_r + 1) per step (FP32 storage, FP64 sums)."""
+    nx, ny, nz, n = 48, 10, 6, 40
+    T0, q = _random_start(nx, ny, nz, 61)
+    box = Box(nx, ny, nz, 0.7, 3.0)
+    box.init(T0, q)
+    a = box.totals()
+    box.step(n)
+    b = box.totals()
+    box.close()
+    rho = cf.scheme_constants(0.7, 3.0)["rho"]
+    scale = np.abs(T0 - 1.0).sum()
+    assert abs(b[0] - a[0]) < 1e-6 * scale
+    for k in (1, 2, 3):
+        assert b[k] == pytest.approx(a[k] * rho ** n, rel=1e-4, abs=1e-9)
+
+
+def test_step_before_init_rejected():
+    box = Box(8, 4, 4, 0.6, 0.8)
+    with pytest.raises(LBMError) as e:
+        box.step(1)
+    assert e.value.code == LBM_ESTATE
+    box.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_full_size_thermal_waves(storage):
+    """The benchmark's 512^3 thermal-wave box in its default launch shape,
+    against the exact Fourier-mode solution at 4096 sampled nodes after 100
+    steps (device-side initial field)."""
+    import torch
+    case = W.thermal_waves_3d_case(512)
+    modes = case.init_args["modes"]
+    n = 100
+    log(f"d3q14 full size {storage}: init")
+    scale = 2.0 ** -23 if storage == "f16" else 0.0
+    box = Box(case.nx, case.ny, case.nz, case.tau_n, case.tau_r, storage=storage, scale=scale,
+              stochastic=storage != "f32", seed=3)
+    T0 = W.modes_field_3d_torch(modes, case.nx, case.ny, case.nz, case.t0, "cuda")
+    box.init(T0)
+    del T0
+    box.step(n)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(9)
+    xs, ys, zs = (rng.integers(0, 512, 4096) for _ in range(3))
+    s = box.sample(xs, ys, zs)
+    box.close()
+    sol = b3.ModeSolution(modes, case.nx, case.ny, case.nz, n, case.tau_n, case.tau_r)
+    T, qx, qy, qz = sol.at(xs, ys, zs)
+    e_t, e_q = _eps([s[:, 0], s[:, 1], s[:, 2], s[:, 3]], [T - 1.0, qx, qy, qz])
+    log(f"d3q14 full size {storage}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
+    tol = {"f32": 1e-5, "f16": 5e-3, "bf16": 5e-2}[storage]
+    assert e_t < tol and e_q < tol

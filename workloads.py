@@ -325,15 +325,16 @@ def modes_field_3d(modes: Sequence[Mode3], nx: int, ny: int, nz: int, t0: float)
 
 def modes_field_3d_torch(modes: Sequence[Mode3], nx: int, ny: int, nz: int, t0: float, device):
     """Same field as :func:`modes_field_3d`, built with torch on ``device`` in
-    FP64 (one plane of phases at a time), so a 512^3 field needs no host copy."""
+    FP64, so a 512^3 field needs no host copy."""
     import torch
     x = torch.arange(nx, dtype=torch.float64, device=device)
     y = torch.arange(ny, dtype=torch.float64, device=device)
+    z = torch.arange(nz, dtype=torch.float64, device=device)
     out = torch.full((nz, ny, nx), t0, dtype=torch.float64, device=device)
     for m in modes:
-        pxy = (2.0 * math.pi * m.ky / ny) * y[:, None] + (2.0 * math.pi * m.kx / nx) * x[None, :] + m.phase
-        for z in range(nz):
-            out[z].add_(torch.cos(pxy + 2.0 * math.pi * m.kz * z / nz), alpha=m.amp)
+        ph = ((2.0 * math.pi * m.kz / nz) * z[:, None, None] + (2.0 * math.pi * m.ky / ny) * y[None, :, None]
+              + (2.0 * math.pi * m.kx / nx) * x[None, None, :] + m.phase)
+        out.add_(torch.cos(ph), alpha=m.amp)
     return out
 
 
