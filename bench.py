@@ -89,6 +89,9 @@ def _parse():
     p.add_argument("--d3q14-n", type=int, default=512, help="side of the periodic D3Q14 box")
     p.add_argument("--d3q14-rows", default="f32,bf16:stochastic,f16:stochastic",
                    help="storage[:rounding] rows of the D3Q14 box")
+    p.add_argument("--d3q14-shape", default="auto",
+                   help="D3Q14 launch shape rows_per_tile,xcd_remap,nontemporal,tile_waves "
+                        "(auto: the autotuner's choice)")
     p.add_argument("--copy-probe", action="store_true",
                    help="also run a 1 GiB torch device copy 5 times (counter calibration)")
     return p.parse_args()
@@ -221,7 +224,8 @@ def _run_sweep(args, torch, P, W):
 def _run_d3q14(args, torch, W):
     """D3Q14 thermal-wave box: periodic n^3 (n = 512 by default), T0 = 1 plus
     16 seeded Fourier modes (wave numbers up to 8 per axis, total amplitude
-    1e-3), tau_N = 0.6, tau_R = 5, no initial flux.  One launch per step; the
+    1e-3), tau_N = 0.6, tau_R = 5, no initial flux; chunked layout, launch
+    shape chosen by the library's autotuner.  One launch per step; the
     per-launch time is the HIP-event time over the timed steps (consecutive
     launches on one stream) divided by their number."""
     from paper_2010_01847_amd.d3q14 import Box
@@ -235,6 +239,11 @@ def _run_d3q14(args, torch, W):
         scale = 2.0 ** -23 if st == "f16" else 0.0
         box = Box(case.nx, case.ny, case.nz, case.tau_n, case.tau_r, storage=st, scale=scale,
                   stochastic=rnd == "stochastic", seed=1847)
+        if args.d3q14_shape == "auto":
+            box.autotune(10)
+        else:
+            box.set_launch_shape(*(int(v) for v in args.d3q14_shape.split(",")))
+        shape = box.launch_shape()
         T0 = W.modes_field_3d_torch(case.init_args["modes"], case.nx, case.ny, case.nz, case.t0, "cuda")
         box.init(T0)
         del T0
@@ -252,7 +261,7 @@ def _run_d3q14(args, torch, W):
         gbs = BYTES_PER_NODE_3D[st] * nodes / (ms / 1e3) / 1e9
         out["rows"].append({"storage": st, "rounding": rnd, "mlups": round(nodes / (ms / 1e3) / 1e6, 1),
                             "ms_per_step": round(ms, 4), "gbs": round(gbs, 1),
-                            "frac": round(gbs / HBM_PEAK_GBS, 4)})
+                            "frac": round(gbs / HBM_PEAK_GBS, 4), "layout": "chunked", "launch_shape": shape})
     f32 = [r for r in out["rows"] if r["storage"] == "f32"]
     if f32:
         r = f32[0]

@@ -48,10 +48,12 @@ extern "C" {
 typedef struct lbm3d_ctx* lbm3d_handle;
 
 typedef struct {
-    int32_t nx, ny, nz;     /* nodes per axis, >= 1 each; (pitch * ny * nz) < 2^31, pitch = nx
-                               rounded up to 64 */
+    int32_t nx, ny, nz;     /* nodes per axis, >= 1 each, fewer than 2^32 nodes in all */
     int32_t storage;        /* LBM_F32, LBM_F16 or LBM_BF16 (the split kinds are D2Q8 only) */
     int32_t flags;          /* LBM_FLAG_EXTERNAL_MEMORY, LBM_FLAG_STOCHASTIC_ROUNDING */
+    int32_t layout;         /* lbm_layout: PLANES = 14 direction planes (rows padded to 64
+                               nodes); CHUNKED = 64-node row segments holding their 14
+                               direction runs back to back; AUTO = CHUNKED */
     uint32_t seed;          /* stream of the stochastic-rounding bits */
     double tau_n;           /* tau_N / dt > 0 */
     double tau_r;           /* tau_R / dt > 0, +inf allowed */
@@ -61,11 +63,14 @@ typedef struct {
     void* stream;           /* hipStream_t to enqueue on; NULL = null stream */
 } lbm3d_config;
 
-/* Launch shape of the step kernel. */
+/* Launch shape of the step kernel: a thread block covers a tile of
+ * 64 * tile_waves consecutive nodes in each of rows_per_tile rows, one node per
+ * thread (64 * tile_waves * rows_per_tile <= 512 threads). */
 typedef struct {
-    int32_t rows_per_tile;  /* 1, 2 or 4: rows of a 64-node-wide tile (block of 64 * rows threads) */
+    int32_t rows_per_tile;  /* 1, 2 or 4 */
     int32_t xcd_remap;      /* 1: each of the 8 XCDs takes one contiguous range of tiles */
     int32_t nontemporal;    /* 1: streaming stores */
+    int32_t tile_waves;     /* 1, 2, 4 or 8 wavefronts (64-node segments) along x */
 } lbm3d_launch_shape;
 
 /* Message of the last failing call on this handle ("" if none); with NULL, the
@@ -123,10 +128,20 @@ int lbm3d_sample(lbm3d_handle h, const int64_t* nodes, int64_t count, double* ou
  * Errors: ENONFINITE if any total is not finite. */
 int lbm3d_totals(lbm3d_handle h, double out[4]);
 
-/* Launch shape of the step kernel (default: 4 rows per tile, XCD remap on,
- * ordinary stores).  Errors: EINVAL. */
+/* Launch shape of the step kernel (default: 4 rows of one segment per tile,
+ * ordinary stores, XCD remap off for the chunked layout and on for planes).
+ * Errors: EINVAL. */
 int lbm3d_set_launch_shape(lbm3d_handle h, const lbm3d_launch_shape* shape);
 int lbm3d_get_launch_shape(lbm3d_handle h, lbm3d_launch_shape* shape);
+
+/* Time every tile shape (rows_per_tile x tile_waves) with and without the XCD
+ * remap, then streaming stores on the fastest, for `steps` steps each (0
+ * selects 20) on zeroed buffers, and keep the fastest.  Must run before
+ * lbm3d_init (it overwrites the buffers).  report, if not NULL, receives a
+ * JSON summary ({"timings_us": [[rows, xcd, nt, tile_waves, us], ...],
+ * "best": [...]}) truncated to report_len.  Errors: ESTATE (memory not bound,
+ * or already initialised), EHIP. */
+int lbm3d_autotune(lbm3d_handle h, int32_t steps, char* report, size_t report_len);
 
 /* Free the handle and the memory it allocated. */
 void lbm3d_destroy(lbm3d_handle h);

@@ -25,8 +25,16 @@
 // and 14 stores per node for about 90 FP32 operations: it is bound by HBM
 // bandwidth, so the design is about coalescing, not arithmetic: a wavefront
 // covers 64 consecutive nodes of a row, every one of its 28 accesses is one
-// contiguous 256-byte (FP32) span, and the x-shifted loads reuse in L2 the
-// lines the neighbouring wavefront of the same row brings in.
+// contiguous 256-byte (FP32) span (plus one element from the neighbouring
+// segment for the x-shifted loads, whose line the neighbouring wavefront of
+// the row also reads).
+//
+// Two layouts of a buffer (Geometry::layout):
+//   planes  (0): 14 direction planes; in a plane, rows of `pitch` elements;
+//   chunked (1): rows cut into 64-node segments, each storing its 14 direction
+//                runs back to back (3.5 KB in FP32), so the 14 stores of a
+//                wavefront fill one contiguous region and its loads come from
+//                at most nine such regions (the nine source rows).
 #include "d3q14_internal.h"
 #include "lbm_numeric.h"
 
@@ -78,12 +86,23 @@ __device__ __forceinline__ float c_dot(float jx, float jy, float jz) {
     }
 }
 
-// ------------------------------------------------------------------ tiles
+// ------------------------------------------------------------------ addressing
 
-// Node of this thread: tiles of 64 x rows_per_tile nodes, x-tiles fastest,
-// then y, then z.  With xcd_remap the 8 XCDs (which take blocks round-robin)
-// each get one contiguous range of tiles, so the neighbouring tiles of a row,
-// whose x-shifted loads share cache lines, meet in the same L2.
+// Element index of direction i at node (xs, row) of a buffer, row = z * ny + y.
+template <int L>
+__device__ __forceinline__ int64_t elem(const Geometry& g, int i, int64_t row, int xs) {
+    if constexpr (L == 0) return (int64_t)i * g.plane + row * g.pitch + xs;
+    else return ((row * g.nseg + (xs >> 6)) * kQ + i) * kTileX + (xs & 63);
+}
+
+// Node of this thread: tiles of 64 * tile_waves x rows_per_tile nodes, x-tiles
+// fastest, then y, then z; wavefront w of a block takes segment w % tile_waves
+// of row w / tile_waves.  Wider tiles keep the x-neighbouring segments of a
+// row, whose x-shifted loads share cache lines, on one compute unit.  With
+// xcd_remap the 8 XCDs (which take blocks round-robin) each get one
+// contiguous range of tiles, so neighbouring tiles meet in the same L2.  y
+// and z are the same on all lanes of a wavefront; they are read from the first
+// lane so that the row arithmetic stays scalar.
 __device__ __forceinline__ bool node_of_thread(const Geometry& g, int xcd_remap, int& x, int& y, int& z) {
     uint32_t tile = blockIdx.x;
     if (xcd_remap) {
@@ -95,38 +114,32 @@ __device__ __forceinline__ bool node_of_thread(const Geometry& g, int xcd_remap,
     const uint32_t r = tile / g.ntx;
     const uint32_t ty = r % g.nty;
     z = (int)(r / g.nty);
-    x = (int)(tx * kTileX + (threadIdx.x & 63u));
-    y = (int)(ty * g.rows_per_tile + (threadIdx.x >> 6));
+    const uint32_t w = threadIdx.x >> 6;
+    x = (int)((tx * g.tile_waves + w % g.tile_waves) * kTileX + (threadIdx.x & 63u));
+    y = __builtin_amdgcn_readfirstlane((int)(ty * g.rows_per_tile + w / g.tile_waves));
     return x < g.nx && y < g.ny;
 }
 
-// In-plane element offsets of the 14 pull sources of node (x, y, z): direction
-// i reads the node x - c_i, wrapped on every axis.
+// Element indices of the 14 pull sources of node (x, y, z): direction i reads
+// the node x - c_i, wrapped on every axis.
 struct PullOffsets {
-    uint32_t off[kQ];
+    int64_t off[kQ];
 };
 
+template <int L>
 __device__ __forceinline__ PullOffsets pull_offsets(const Geometry& g, int x, int y, int z) {
     const int xm = x == 0 ? g.nx - 1 : x - 1, xp = x == g.nx - 1 ? 0 : x + 1;
     const int ym = y == 0 ? g.ny - 1 : y - 1, yp = y == g.ny - 1 ? 0 : y + 1;
     const int zm = z == 0 ? g.nz - 1 : z - 1, zp = z == g.nz - 1 ? 0 : z + 1;
-    const uint32_t P = (uint32_t)g.pitch, NY = (uint32_t)g.ny;
     PullOffsets o;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
         const int xs = cx(i) > 0 ? xm : cx(i) < 0 ? xp : x;
         const int ys = cy(i) > 0 ? ym : cy(i) < 0 ? yp : y;
         const int zs = cz(i) > 0 ? zm : cz(i) < 0 ? zp : z;
-        o.off[i] = ((uint32_t)zs * NY + (uint32_t)ys) * P + (uint32_t)xs;
+        o.off[i] = elem<L>(g, i, (int64_t)zs * g.ny + ys, xs);
     }
     return o;
-}
-
-template <class S>
-__device__ __forceinline__ void pull(const Geometry& g, const void* src, const PullOffsets& o, float v[kQ]) {
-    const S* base = reinterpret_cast<const S*>(src);
-#pragma unroll
-    for (int i = 0; i < kQ; ++i) v[i] = Cvt<S>::ld(base[(int64_t)i * g.plane + o.off[i]]);
 }
 
 // E = sum g_i, J = sum c_i g_i (fixed order).
@@ -166,37 +179,39 @@ __device__ __forceinline__ void put(S* p, S v, int nontemporal) {
     }
 }
 
-// One relaxation of direction I and its store.
-template <class S, int SR, int I>
-__device__ __forceinline__ void relax_store_one(const Coeffs& c, const float v[kQ], float wE_axis, float wE_corner,
-                                                float jx, float jy, float jz, const uint32_t r[7], S* dst,
-                                                int64_t plane, uint32_t off, int nontemporal) {
+// One relaxation of direction I and its store at the node's own position.
+template <class S, int SR, int L, int I>
+__device__ __forceinline__ void relax_store_one(const Geometry& g, const Coeffs& c, const float v[kQ], float wE_axis,
+                                                float wE_corner, float jx, float jy, float jz, const uint32_t r[7],
+                                                S* dst, int64_t row, int x, int nontemporal) {
     const float wE = I < 6 ? wE_axis : wE_corner;
     const float k = I < 6 ? c.k_axis : c.k_corner;
     const float delta = fmaf(c.inv_tau, wE - v[I], k * c_dot<I>(jx, jy, jz));
     S o;
     if constexpr (SR && __is_same(S, float)) o = sr_add_f32(v[I], delta, bits16(r, I));
     else o = rounded<S, SR>(v[I] + delta, SR ? bits16(r, I) : 0u);
-    put<S>(dst + (int64_t)I * plane + off, o, nontemporal);
+    put<S>(dst + elem<L>(g, I, row, x), o, nontemporal);
 }
 
-template <class S, int SR, int... Is>
-__device__ __forceinline__ void relax_store_all(const Coeffs& c, const float v[kQ], float wE_axis, float wE_corner,
-                                                float jx, float jy, float jz, const uint32_t r[7], S* dst,
-                                                int64_t plane, uint32_t off, int nontemporal,
+template <class S, int SR, int L, int... Is>
+__device__ __forceinline__ void relax_store_all(const Geometry& g, const Coeffs& c, const float v[kQ], float wE_axis,
+                                                float wE_corner, float jx, float jy, float jz, const uint32_t r[7],
+                                                S* dst, int64_t row, int x, int nontemporal,
                                                 std::integer_sequence<int, Is...>) {
-    (relax_store_one<S, SR, Is>(c, v, wE_axis, wE_corner, jx, jy, jz, r, dst, plane, off, nontemporal), ...);
+    (relax_store_one<S, SR, L, Is>(g, c, v, wE_axis, wE_corner, jx, jy, jz, r, dst, row, x, nontemporal), ...);
 }
 
 // ------------------------------------------------------------------ step
 
-template <class S, int SR>
-__global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
+template <class S, int SR, int L>
+__global__ __launch_bounds__(512) void step_kernel(StepArgs a) {
     int x, y, z;
     if (!node_of_thread(a.g, a.xcd_remap, x, y, z)) return;
-    const PullOffsets o = pull_offsets(a.g, x, y, z);
+    const PullOffsets o = pull_offsets<L>(a.g, x, y, z);
+    const S* src = reinterpret_cast<const S*>(a.src);
     float v[kQ];
-    pull<S>(a.g, a.src, o, v);
+#pragma unroll
+    for (int i = 0; i < kQ; ++i) v[i] = Cvt<S>::ld(src[o.off[i]]);
     float E, jx, jy, jz;
     moments(v, E, jx, jy, jz);
     uint32_t r[7] = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
@@ -205,21 +220,26 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs a) {
 #pragma unroll
         for (int k = 0; k < 7; ++k) r[k] = mix32(node ^ mix32(a.step * 8u + (uint32_t)k + a.seed * 0x9e3779b9u));
     }
-    const uint32_t own = ((uint32_t)z * (uint32_t)a.g.ny + (uint32_t)y) * (uint32_t)a.g.pitch + (uint32_t)x;
-    relax_store_all<S, SR>(a.c, v, a.c.omega_axis * E, a.c.omega_corner * E, jx, jy, jz, r,
-                           reinterpret_cast<S*>(a.dst), a.g.plane, own, a.nontemporal,
-                           std::make_integer_sequence<int, kQ>{});
+    relax_store_all<S, SR, L>(a.g, a.c, v, a.c.omega_axis * E, a.c.omega_corner * E, jx, jy, jz, r,
+                              reinterpret_cast<S*>(a.dst), (int64_t)z * a.g.ny + y, x, a.nontemporal,
+                              std::make_integer_sequence<int, kQ>{});
 }
 
 static unsigned step_grid(const StepArgs& a) {
     return a.xcd_remap ? 8u * ((a.g.ntiles + 7u) / 8u) : a.g.ntiles;
 }
 
+template <class S, int L>
+static void launch_step_l(int sr, const StepArgs& a, hipStream_t st) {
+    const dim3 grid(step_grid(a)), block(64u * a.g.tile_waves * a.g.rows_per_tile);
+    if (sr) hipLaunchKernelGGL((step_kernel<S, 1, L>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((step_kernel<S, 0, L>), grid, block, 0, st, a);
+}
+
 template <class S>
 static hipError_t launch_step_s(int sr, const StepArgs& a, hipStream_t st) {
-    const dim3 grid(step_grid(a)), block(64u * a.g.rows_per_tile);
-    if (sr) hipLaunchKernelGGL((step_kernel<S, 1>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((step_kernel<S, 0>), grid, block, 0, st, a);
+    if (a.g.layout) launch_step_l<S, 1>(sr, a, st);
+    else launch_step_l<S, 0>(sr, a, st);
     return hipGetLastError();
 }
 
@@ -232,19 +252,31 @@ hipError_t launch_step(int storage, int sr, const StepArgs& a, hipStream_t st) {
     }
 }
 
+// Instantiate kernel K<S, L> for the storage and layout of a call.
+#define PLBM3_DISPATCH(storage, layout, CALL)                         \
+    switch ((storage) * 2 + ((layout) ? 1 : 0)) {                     \
+        case 0: CALL(float, 0); break;                                \
+        case 1: CALL(float, 1); break;                                \
+        case 2: CALL(_Float16, 0); break;                             \
+        case 3: CALL(_Float16, 1); break;                             \
+        case 4: CALL(bf16_bits, 0); break;                            \
+        case 5: CALL(bf16_bits, 1); break;                            \
+        default: return hipErrorInvalidValue;                         \
+    }
+
 // ------------------------------------------------------------------ init
 
 // Thread per stored element position (x, y, z): for each direction i the
 // Eq. 15 equilibrium of node x + c_i, as a scaled deviation.  (5/3) a_i is
 // 1/3 on the axis movers and 1/24 on the corner movers.
-template <class S>
-__global__ __launch_bounds__(256) void init_kernel(Geometry g, S* dst, const double* __restrict__ T,
+template <class S, int L>
+__global__ __launch_bounds__(512) void init_kernel(Geometry g, S* dst, const double* __restrict__ T,
                                                    const double* __restrict__ qx, const double* __restrict__ qy,
                                                    const double* __restrict__ qz, double t0, double cv,
                                                    double inv_beta, double inv_s) {
     int x, y, z;
     if (!node_of_thread(g, 0, x, y, z)) return;
-    const uint32_t own = ((uint32_t)z * (uint32_t)g.ny + (uint32_t)y) * (uint32_t)g.pitch + (uint32_t)x;
+    const int64_t row = (int64_t)z * g.ny + y;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
         int xs = x + cx(i), ys = y + cy(i), zs = z + cz(i);
@@ -260,29 +292,19 @@ __global__ __launch_bounds__(256) void init_kernel(Geometry g, S* dst, const dou
         const double w = i < 6 ? 1.0 / 9.0 : 1.0 / 24.0;
         const double a53 = i < 6 ? 1.0 / 3.0 : 1.0 / 24.0;
         const double e = (w * cv * dT + a53 * cq * inv_beta) * inv_s;
-        put<S>(dst + (int64_t)i * g.plane + own, Cvt<S>::st((float)e), 0);
+        put<S>(dst + elem<L>(g, i, row, x), Cvt<S>::st((float)e), 0);
     }
 }
 
 hipError_t launch_init(int storage, const Geometry& g, void* dst, const double* T, const double* qx,
                        const double* qy, const double* qz, double t0, double cv, double inv_beta, double inv_s,
                        hipStream_t st) {
-    const dim3 grid(g.ntiles), block(64u * g.rows_per_tile);
-    switch (storage) {
-        case 0:
-            hipLaunchKernelGGL((init_kernel<float>), grid, block, 0, st, g, reinterpret_cast<float*>(dst), T, qx,
-                               qy, qz, t0, cv, inv_beta, inv_s);
-            break;
-        case 1:
-            hipLaunchKernelGGL((init_kernel<_Float16>), grid, block, 0, st, g, reinterpret_cast<_Float16*>(dst), T,
-                               qx, qy, qz, t0, cv, inv_beta, inv_s);
-            break;
-        case 2:
-            hipLaunchKernelGGL((init_kernel<bf16_bits>), grid, block, 0, st, g, reinterpret_cast<bf16_bits*>(dst), T,
-                               qx, qy, qz, t0, cv, inv_beta, inv_s);
-            break;
-        default: return hipErrorInvalidValue;
-    }
+    const dim3 grid(g.ntiles), block(64u * g.tile_waves * g.rows_per_tile);
+#define PLBM3_INIT(S, L)                                                                                        \
+    hipLaunchKernelGGL((init_kernel<S, L>), grid, block, 0, st, g, reinterpret_cast<S*>(dst), T, qx, qy, qz, t0, \
+                       cv, inv_beta, inv_s)
+    PLBM3_DISPATCH(storage, g.layout, PLBM3_INIT)
+#undef PLBM3_INIT
     return hipGetLastError();
 }
 
@@ -290,10 +312,10 @@ hipError_t launch_init(int storage, const Geometry& g, void* dst, const double* 
 
 // FP64 moments (Eqs. 53-54) of the populations the next step would pull at
 // node (x, y, z).
-template <class S>
+template <class S, int L>
 __device__ __forceinline__ void node_moments(const Geometry& g, const void* src, int x, int y, int z,
                                              double& E, double& jx, double& jy, double& jz) {
-    const PullOffsets o = pull_offsets(g, x, y, z);
+    const PullOffsets o = pull_offsets<L>(g, x, y, z);
     const S* base = reinterpret_cast<const S*>(src);
     E = 0.0;
     jx = 0.0;
@@ -301,7 +323,7 @@ __device__ __forceinline__ void node_moments(const Geometry& g, const void* src,
     jz = 0.0;
 #pragma unroll
     for (int i = 0; i < kQ; ++i) {
-        const double v = (double)Cvt<S>::ld(base[(int64_t)i * g.plane + o.off[i]]);
+        const double v = (double)Cvt<S>::ld(base[o.off[i]]);
         E += v;
         if (cx(i)) jx += cx(i) > 0 ? v : -v;
         if (cy(i)) jy += cy(i) > 0 ? v : -v;
@@ -309,13 +331,13 @@ __device__ __forceinline__ void node_moments(const Geometry& g, const void* src,
     }
 }
 
-template <class S>
-__global__ __launch_bounds__(256) void moments_kernel(Geometry g, const void* src, double e_scale, double q_scale,
+template <class S, int L>
+__global__ __launch_bounds__(512) void moments_kernel(Geometry g, const void* src, double e_scale, double q_scale,
                                                       double* dT, double* qx, double* qy, double* qz) {
     int x, y, z;
     if (!node_of_thread(g, 0, x, y, z)) return;
     double E, jx, jy, jz;
-    node_moments<S>(g, src, x, y, z, E, jx, jy, jz);
+    node_moments<S, L>(g, src, x, y, z, E, jx, jy, jz);
     const int64_t n = ((int64_t)z * g.ny + y) * g.nx + x;
     if (dT) dT[n] = E * e_scale;
     if (qx) qx[n] = jx * q_scale;
@@ -323,7 +345,7 @@ __global__ __launch_bounds__(256) void moments_kernel(Geometry g, const void* sr
     if (qz) qz[n] = jz * q_scale;
 }
 
-template <class S>
+template <class S, int L>
 __global__ __launch_bounds__(256) void sample_kernel(Geometry g, const void* src, double e_scale, double q_scale,
                                                      const int64_t* __restrict__ nodes, int64_t count,
                                                      double* __restrict__ out) {
@@ -344,7 +366,7 @@ __global__ __launch_bounds__(256) void sample_kernel(Geometry g, const void* src
     const int y = (int)(r % g.ny);
     const int z = (int)(r / g.ny);
     double E, jx, jy, jz;
-    node_moments<S>(g, src, x, y, z, E, jx, jy, jz);
+    node_moments<S, L>(g, src, x, y, z, E, jx, jy, jz);
     out[4 * k + 0] = E * e_scale;
     out[4 * k + 1] = jx * q_scale;
     out[4 * k + 2] = jy * q_scale;
@@ -353,13 +375,11 @@ __global__ __launch_bounds__(256) void sample_kernel(Geometry g, const void* src
 
 hipError_t launch_moments(int storage, const Geometry& g, const void* src, double e_scale, double q_scale,
                           double* dT, double* qx, double* qy, double* qz, hipStream_t st) {
-    const dim3 grid(g.ntiles), block(64u * g.rows_per_tile);
-    switch (storage) {
-        case 0: hipLaunchKernelGGL((moments_kernel<float>), grid, block, 0, st, g, src, e_scale, q_scale, dT, qx, qy, qz); break;
-        case 1: hipLaunchKernelGGL((moments_kernel<_Float16>), grid, block, 0, st, g, src, e_scale, q_scale, dT, qx, qy, qz); break;
-        case 2: hipLaunchKernelGGL((moments_kernel<bf16_bits>), grid, block, 0, st, g, src, e_scale, q_scale, dT, qx, qy, qz); break;
-        default: return hipErrorInvalidValue;
-    }
+    const dim3 grid(g.ntiles), block(64u * g.tile_waves * g.rows_per_tile);
+#define PLBM3_MOM(S, L) \
+    hipLaunchKernelGGL((moments_kernel<S, L>), grid, block, 0, st, g, src, e_scale, q_scale, dT, qx, qy, qz)
+    PLBM3_DISPATCH(storage, g.layout, PLBM3_MOM)
+#undef PLBM3_MOM
     return hipGetLastError();
 }
 
@@ -367,12 +387,10 @@ hipError_t launch_sample(int storage, const Geometry& g, const void* src, double
                          const int64_t* nodes, int64_t count, double* out, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     const dim3 grid((unsigned)((count + 255) / 256)), block(256);
-    switch (storage) {
-        case 0: hipLaunchKernelGGL((sample_kernel<float>), grid, block, 0, st, g, src, e_scale, q_scale, nodes, count, out); break;
-        case 1: hipLaunchKernelGGL((sample_kernel<_Float16>), grid, block, 0, st, g, src, e_scale, q_scale, nodes, count, out); break;
-        case 2: hipLaunchKernelGGL((sample_kernel<bf16_bits>), grid, block, 0, st, g, src, e_scale, q_scale, nodes, count, out); break;
-        default: return hipErrorInvalidValue;
-    }
+#define PLBM3_SAMPLE(S, L) \
+    hipLaunchKernelGGL((sample_kernel<S, L>), grid, block, 0, st, g, src, e_scale, q_scale, nodes, count, out)
+    PLBM3_DISPATCH(storage, g.layout, PLBM3_SAMPLE)
+#undef PLBM3_SAMPLE
     return hipGetLastError();
 }
 
@@ -403,21 +421,19 @@ __device__ void block_sum4(double s[4], double* out) {
         for (int c = 0; c < 4; ++c) out[c] = red[c][0];
 }
 
-// Stage 1: block b sums rows b, b + G, ... of every direction plane (thread t
-// takes x = t, t + 256, ...).  Row order and tree are fixed, so the result
-// does not depend on the device.
-template <class S>
+// Stage 1: block b sums rows b, b + G, ... of every direction (thread t takes
+// x = t, t + 256, ...; padding is never read).  Row order and tree are fixed,
+// so the result does not depend on the device.
+template <class S, int L>
 __global__ __launch_bounds__(256) void totals_kernel(Geometry g, const void* src, double* partials) {
     const S* base = reinterpret_cast<const S*>(src);
     const int64_t rows = (int64_t)g.ny * g.nz;
     double s[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t r = blockIdx.x; r < rows; r += gridDim.x) {
-        const int y = (int)(r % g.ny), z = (int)(r / g.ny);
-        const int64_t row = ((int64_t)z * g.ny + y) * g.pitch;
 #pragma unroll
         for (int i = 0; i < kQ; ++i)
             for (int x = threadIdx.x; x < g.nx; x += 256) {
-                const double v = (double)Cvt<S>::ld(base[(int64_t)i * g.plane + row + x]);
+                const double v = (double)Cvt<S>::ld(base[elem<L>(g, i, r, x)]);
                 s[0] += v;
                 if (cx(i)) s[1] += cx(i) > 0 ? v : -v;
                 if (cy(i)) s[2] += cy(i) > 0 ? v : -v;
@@ -440,12 +456,9 @@ __global__ __launch_bounds__(256) void totals_final_kernel(const double* __restr
 hipError_t launch_totals(int storage, const Geometry& g, const void* src, double* partials, double* out,
                          hipStream_t st) {
     const int nb = totals_blocks(g);
-    switch (storage) {
-        case 0: hipLaunchKernelGGL((totals_kernel<float>), dim3(nb), dim3(256), 0, st, g, src, partials); break;
-        case 1: hipLaunchKernelGGL((totals_kernel<_Float16>), dim3(nb), dim3(256), 0, st, g, src, partials); break;
-        case 2: hipLaunchKernelGGL((totals_kernel<bf16_bits>), dim3(nb), dim3(256), 0, st, g, src, partials); break;
-        default: return hipErrorInvalidValue;
-    }
+#define PLBM3_TOT(S, L) hipLaunchKernelGGL((totals_kernel<S, L>), dim3(nb), dim3(256), 0, st, g, src, partials)
+    PLBM3_DISPATCH(storage, g.layout, PLBM3_TOT)
+#undef PLBM3_TOT
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(256), 0, st, partials, nb, out);

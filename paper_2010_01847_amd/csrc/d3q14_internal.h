@@ -12,15 +12,22 @@ constexpr int kQ = 14;          // 6 axis movers + 8 corner movers
 constexpr int kTileX = 64;      // nodes of a row per tile (one wavefront)
 constexpr int kRowAlign = 64;   // row pitch in elements is a multiple of this
 
-// Geometry of one periodic box in device memory.  Populations of direction i
-// start at element i * plane; inside a plane node (x, y, z) sits at element
-// (z * ny + y) * pitch + x.  Elements at x >= nx are padding, never read.
+// Geometry of one periodic box in device memory, with row = z * ny + y:
+//   layout 0 (planes):  element i * plane + row * pitch + x;
+//   layout 1 (chunked): element ((row * nseg + x / 64) * 14 + i) * 64 + x % 64.
+// Elements at x >= nx are padding, never read.
+//
+// Work split: a thread block covers a tile of 64 * tile_waves consecutive
+// nodes of each of rows_per_tile rows (one wavefront per 64-node segment).
 struct Geometry {
     int32_t nx, ny, nz;
-    int32_t pitch;              // elements per row (nx rounded up to kRowAlign)
-    int64_t plane;              // elements from one direction plane to the next
-    uint32_t ntx, nty;          // tiles along x (kTileX nodes) and y (rows_per_tile rows)
-    uint32_t rows_per_tile;     // 1, 2 or 4: rows of a 64 * rows_per_tile thread block
+    int32_t layout;             // 0 planes, 1 chunked
+    int32_t pitch;              // planes: elements per row (nx rounded up to kRowAlign)
+    int32_t nseg;               // 64-node segments per row
+    int64_t plane;              // planes: elements from one direction plane to the next
+    uint32_t tile_waves;        // 1, 2, 4 or 8 wavefronts along x per tile
+    uint32_t rows_per_tile;     // 1, 2 or 4 rows per tile (tile_waves * rows_per_tile <= 8)
+    uint32_t ntx, nty;          // tiles along x and y
     uint32_t ntiles;            // ntx * nty * nz
 };
 

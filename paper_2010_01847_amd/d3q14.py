@@ -14,20 +14,21 @@ from typing import Optional, Sequence, Tuple
 
 import numpy as np
 
-from .lbm import (LBM_BF16, LBM_F16, LBM_F32, LBM_FLAG_EXTERNAL_MEMORY, LBM_FLAG_STOCHASTIC_ROUNDING, LBM_OK,
-                  LBMError, library as _library)
+from .lbm import (LAYOUT, LBM_BF16, LBM_F16, LBM_F32, LBM_FLAG_EXTERNAL_MEMORY, LBM_FLAG_STOCHASTIC_ROUNDING,
+                  LBM_OK, LBMError, library as _library)
 
 
 class lbm3d_config(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-                ("storage", ctypes.c_int32), ("flags", ctypes.c_int32), ("seed", ctypes.c_uint32),
+                ("storage", ctypes.c_int32), ("flags", ctypes.c_int32), ("layout", ctypes.c_int32),
+                ("seed", ctypes.c_uint32),
                 ("tau_n", ctypes.c_double), ("tau_r", ctypes.c_double), ("cv", ctypes.c_double),
                 ("t0", ctypes.c_double), ("scale", ctypes.c_double), ("stream", ctypes.c_void_p)]
 
 
 class lbm3d_launch_shape(ctypes.Structure):
     _fields_ = [("rows_per_tile", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
-                ("nontemporal", ctypes.c_int32)]
+                ("nontemporal", ctypes.c_int32), ("tile_waves", ctypes.c_int32)]
 
 
 STORAGE3 = {"f32": LBM_F32, "f16": LBM_F16, "bf16": LBM_BF16}
@@ -47,6 +48,7 @@ SIGNATURES3 = [
     ("lbm3d_totals", ctypes.c_int, [_P, _D]),
     ("lbm3d_set_launch_shape", ctypes.c_int, [_P, ctypes.POINTER(lbm3d_launch_shape)]),
     ("lbm3d_get_launch_shape", ctypes.c_int, [_P, ctypes.POINTER(lbm3d_launch_shape)]),
+    ("lbm3d_autotune", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_char_p, ctypes.c_size_t]),
     ("lbm3d_destroy", None, [_P]),
 ]
 
@@ -129,6 +131,12 @@ def lbm3d_get_launch_shape(h) -> lbm3d_launch_shape:
     return s
 
 
+def lbm3d_autotune(h, steps: int = 20) -> str:
+    buf = ctypes.create_string_buffer(4096)
+    _check(library().lbm3d_autotune(h, int(steps), buf, len(buf)), "lbm3d_autotune", h)
+    return buf.value.decode()
+
+
 def lbm3d_destroy(h) -> None:
     library().lbm3d_destroy(h)
 
@@ -147,7 +155,7 @@ class Box:
 
     def __init__(self, nx: int, ny: int, nz: int, tau_n: float, tau_r: float, storage: str = "f32",
                  t0: float = 1.0, cv: float = 1.0, scale: float = 0.0, stochastic: bool = False,
-                 seed: int = 0):
+                 seed: int = 0, layout: str = "auto"):
         import torch
         self.torch = torch
         self.shape = (int(nz), int(ny), int(nx))
@@ -155,6 +163,7 @@ class Box:
         cfg.nx, cfg.ny, cfg.nz = int(nx), int(ny), int(nz)
         cfg.storage = STORAGE3[storage]
         cfg.flags = LBM_FLAG_EXTERNAL_MEMORY | (LBM_FLAG_STOCHASTIC_ROUNDING if stochastic else 0)
+        cfg.layout = LAYOUT[layout]
         cfg.seed = int(seed) & 0xffffffff
         cfg.tau_n, cfg.tau_r, cfg.cv, cfg.t0, cfg.scale = float(tau_n), float(tau_r), float(cv), float(t0), float(scale)
         cfg.stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -217,8 +226,19 @@ class Box:
     def totals(self) -> np.ndarray:
         return lbm3d_totals(self.h)
 
-    def set_launch_shape(self, rows_per_tile: int = 4, xcd_remap: int = 1, nontemporal: int = 0) -> None:
-        lbm3d_set_launch_shape(self.h, lbm3d_launch_shape(rows_per_tile, xcd_remap, nontemporal))
+    def set_launch_shape(self, rows_per_tile: int = 4, xcd_remap: int = 0, nontemporal: int = 0,
+                         tile_waves: int = 1) -> None:
+        lbm3d_set_launch_shape(self.h, lbm3d_launch_shape(rows_per_tile, xcd_remap, nontemporal, tile_waves))
+
+    def launch_shape(self) -> dict:
+        s = lbm3d_get_launch_shape(self.h)
+        return {"rows_per_tile": s.rows_per_tile, "xcd_remap": s.xcd_remap, "nontemporal": s.nontemporal,
+                "tile_waves": s.tile_waves}
+
+    def autotune(self, steps: int = 20) -> dict:
+        """Pick the fastest launch shape (before init); returns the timing report."""
+        import json
+        return json.loads(lbm3d_autotune(self.h, steps))
 
     def close(self) -> None:
         if getattr(self, "h", None) is not None:

@@ -175,15 +175,17 @@ def _cfg3(**kw):
     c.nx, c.ny, c.nz = kw.get("nx", 16), kw.get("ny", 8), kw.get("nz", 4)
     c.storage = kw.get("storage", P.LBM_F32)
     c.flags = kw.get("flags", P.LBM_FLAG_EXTERNAL_MEMORY)
+    c.layout = kw.get("layout", P.LBM_LAYOUT_AUTO)
     c.tau_n, c.tau_r = kw.get("tau_n", 0.6), kw.get("tau_r", 0.8)
     c.cv, c.t0, c.scale = kw.get("cv", 1.0), kw.get("t0", 1.0), kw.get("scale", 0.0)
     return c
 
 
-def test_d3q14_required_bytes():
-    """Two buffers of 14 direction planes, rows padded to 64 elements."""
-    b32 = P.d3q14.lbm3d_required_bytes(_cfg3(nx=100, ny=30, nz=7))
-    b16 = P.d3q14.lbm3d_required_bytes(_cfg3(nx=100, ny=30, nz=7, storage=P.LBM_BF16))
+@pytest.mark.parametrize("layout", [P.LBM_LAYOUT_PLANES, P.LBM_LAYOUT_CHUNKED, P.LBM_LAYOUT_AUTO])
+def test_d3q14_required_bytes(layout):
+    """Two buffers of 14 populations per node, rows padded to 64 nodes."""
+    b32 = P.d3q14.lbm3d_required_bytes(_cfg3(nx=100, ny=30, nz=7, layout=layout))
+    b16 = P.d3q14.lbm3d_required_bytes(_cfg3(nx=100, ny=30, nz=7, storage=P.LBM_BF16, layout=layout))
     assert b32 >= 2 * 14 * 128 * 30 * 7 * 4
     assert b16 >= 2 * 14 * 128 * 30 * 7 * 2 and b16 < b32
     assert P.d3q14.lbm3d_required_bytes(_cfg3(nx=1, ny=1, nz=1)) > 0
@@ -193,7 +195,8 @@ def test_d3q14_required_bytes():
     dict(nx=0), dict(ny=0), dict(nz=-1), dict(tau_n=0.0), dict(tau_n=math.inf), dict(tau_r=0.0),
     dict(tau_r=-2.0), dict(storage=P.LBM_F16_SPLIT), dict(storage=9), dict(flags=0x100),
     dict(scale=3.0), dict(scale=-1.0), dict(cv=-1.0), dict(t0=math.nan),
-    dict(nx=4096, ny=4096, nz=128),           # 2^31 elements in a plane
+    dict(nx=4096, ny=4096, nz=256),           # 2^32 nodes
+    dict(layout=3),
 ])
 def test_d3q14_config_validation(kw):
     with pytest.raises(P.LBMError) as e:
@@ -213,13 +216,16 @@ def test_d3q14_handle_state_without_gpu():
         with pytest.raises(P.LBMError) as e:
             D.lbm3d_bind(h, 0x1000 + 3, 1 << 40)
         assert e.value.code == P.LBM_EINVAL
-        for bad in ((3, 1, 0), (4, 2, 0), (1, 0, 5)):
+        for bad in ((3, 1, 0, 1), (4, 2, 0, 1), (1, 0, 5, 1), (1, 0, 0, 3), (2, 0, 0, 8), (1, 0, 0, 0)):
             with pytest.raises(P.LBMError):
                 D.lbm3d_set_launch_shape(h, D.lbm3d_launch_shape(*bad))
-        D.lbm3d_set_launch_shape(h, D.lbm3d_launch_shape(2, 0, 1))
+        D.lbm3d_set_launch_shape(h, D.lbm3d_launch_shape(2, 0, 1, 4))
         s = D.lbm3d_get_launch_shape(h)
-        assert (s.rows_per_tile, s.xcd_remap, s.nontemporal) == (2, 0, 1)
+        assert (s.rows_per_tile, s.xcd_remap, s.nontemporal, s.tile_waves) == (2, 0, 1, 4)
         assert D.lbm3d_steps_done(h) == 0
+        with pytest.raises(P.LBMError) as e:
+            D.lbm3d_autotune(h, 2)           # no memory bound yet
+        assert e.value.code == P.LBM_ESTATE
     finally:
         D.lbm3d_destroy(h)
     assert P.d3q14.library().lbm3d_step(None, 1) == P.LBM_EINVAL

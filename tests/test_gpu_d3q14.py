@@ -37,8 +37,9 @@ def _oracle(nx, ny, nz, tau_n, tau_r, T0, q, steps):
 
 
 def _gpu(nx, ny, nz, tau_n, tau_r, T0, q, steps, storage="f32", shape=None, stochastic=False, seed=0,
-         scale=0.0):
-    box = Box(nx, ny, nz, tau_n, tau_r, storage=storage, stochastic=stochastic, seed=seed, scale=scale)
+         scale=0.0, layout="auto"):
+    box = Box(nx, ny, nz, tau_n, tau_r, storage=storage, stochastic=stochastic, seed=seed, scale=scale,
+              layout=layout)
     if shape:
         box.set_launch_shape(**shape)
     box.init(T0, q)
@@ -57,21 +58,24 @@ def _eps(g, o):
     return float(e_t), float(e_q)
 
 
+@pytest.mark.parametrize("layout", ["planes", "chunked"])
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
-def test_random_state_ragged(storage):
+def test_random_state_ragged(storage, layout):
     """Rough random start (T and q) on a 97 x 11 x 6 box (ragged against the
     64-node tile width and the 4-row tiles), 37 steps."""
     nx, ny, nz, n = 97, 11, 6, 37
     T0, q = _random_start(nx, ny, nz, 5)
     o = _oracle(nx, ny, nz, 0.7, 3.0, T0, q, n)
-    g = _gpu(nx, ny, nz, 0.7, 3.0, T0, q, n, storage=storage)
+    g = _gpu(nx, ny, nz, 0.7, 3.0, T0, q, n, storage=storage, layout=layout)
     e_t, e_q = _eps(g, o)
-    log(f"d3q14 random 97x11x6 {storage}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
+    log(f"d3q14 random 97x11x6 {storage} {layout}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
     assert e_t < TOL3[storage] and e_q < TOL3[storage]
 
 
-@pytest.mark.parametrize("dims", [(1, 1, 1), (2, 1, 1), (1, 5, 3), (3, 2, 2), (64, 4, 1), (65, 5, 2), (5, 130, 3)])
-def test_small_and_degenerate_boxes(dims):
+@pytest.mark.parametrize("layout", ["planes", "chunked"])
+@pytest.mark.parametrize("dims", [(1, 1, 1), (2, 1, 1), (1, 5, 3), (3, 2, 2), (64, 4, 1), (65, 5, 2), (5, 130, 3),
+                                  (129, 3, 2)])
+def test_small_and_degenerate_boxes(dims, layout):
     """Boxes of one node per axis (every pull wraps onto the node itself), two
     nodes, exactly one tile, one tile plus one node, and a tall thin box.
     tau_R = 50 keeps the heat flux of the one-node box (which only decays, by
@@ -81,9 +85,9 @@ def test_small_and_degenerate_boxes(dims):
     nx, ny, nz = dims
     T0, q = _random_start(nx, ny, nz, 11)
     o = _oracle(nx, ny, nz, 0.6, 50.0, T0, q, 9)
-    g = _gpu(nx, ny, nz, 0.6, 50.0, T0, q, 9)
+    g = _gpu(nx, ny, nz, 0.6, 50.0, T0, q, 9, layout=layout)
     e_t, e_q = _eps(g, o)
-    log(f"d3q14 box {dims}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
+    log(f"d3q14 box {dims} {layout}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
     assert e_t < 1e-5 and e_q < 1e-5
 
 
@@ -96,23 +100,27 @@ def test_regimes_f32(tau_n, tau_r):
     assert e_t < 1e-5 and e_q < 1e-5
 
 
-SHAPES3 = [dict(rows_per_tile=r, xcd_remap=x, nontemporal=nt) for r in (1, 2, 4) for x in (0, 1) for nt in (0, 1)]
+SHAPES3 = ([dict(rows_per_tile=r, xcd_remap=x, nontemporal=nt) for r in (1, 2, 4) for x in (0, 1) for nt in (0, 1)]
+           + [dict(rows_per_tile=r, xcd_remap=x, nontemporal=0, tile_waves=tw)
+              for r, tw in ((1, 2), (1, 4), (1, 8), (2, 4), (4, 2)) for x in (0, 1)])
 
 
 @pytest.mark.parametrize("storage,stochastic", [("f32", False), ("bf16", True)])
-def test_launch_shapes_bitwise(storage, stochastic):
-    """Every launch shape runs the same per-node arithmetic (and the same
-    counter-based random bits): identical results."""
+def test_launch_shapes_and_layouts_bitwise(storage, stochastic):
+    """Every launch shape and both layouts run the same per-node arithmetic
+    (and the same counter-based random bits): identical results."""
     nx, ny, nz, n = 131, 7, 5, 13
     T0, q = _random_start(nx, ny, nz, 31)
     ref_out = None
-    for sh in SHAPES3:
-        out = _gpu(nx, ny, nz, 0.55, 50.0, T0, q, n, storage=storage, shape=sh, stochastic=stochastic, seed=4)
-        if ref_out is None:
-            ref_out = out
-        else:
-            for a, b in zip(out, ref_out):
-                assert np.array_equal(a, b), sh
+    for layout in ("planes", "chunked"):
+        for sh in SHAPES3:
+            out = _gpu(nx, ny, nz, 0.55, 50.0, T0, q, n, storage=storage, shape=sh, stochastic=stochastic, seed=4,
+                       layout=layout)
+            if ref_out is None:
+                ref_out = out
+            else:
+                for a, b in zip(out, ref_out):
+                    assert np.array_equal(a, b), (sh, layout)
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
@@ -172,6 +180,31 @@ def test_totals_invariants():
         assert b[k] == pytest.approx(a[k] * rho ** n, rel=1e-4, abs=1e-9)
 
 
+def test_autotune_then_parity():
+    """The autotuner times the 18 tile shapes and streaming stores on the best
+    on zeroed buffers, keeps the fastest, and leaves a handle that initialises
+    and steps to the same bits as the default shape."""
+    nx, ny, nz, n = 70, 9, 5, 11
+    T0, q = _random_start(nx, ny, nz, 71)
+    box = Box(nx, ny, nz, 0.6, 5.0)
+    rep = box.autotune(3)
+    assert len(rep["timings_us"]) == 19
+    assert list(box.launch_shape().values()) == rep["best"][:4]
+    box.init(T0, q)
+    box.step(n)
+    tuned = box.moments()
+    box.close()
+    plain = _gpu(nx, ny, nz, 0.6, 5.0, T0, q, n)
+    for a, b in zip(tuned, plain):
+        assert np.array_equal(a, b)
+    box = Box(8, 4, 4, 0.6, 0.8)
+    box.init()
+    with pytest.raises(LBMError) as e:
+        box.autotune(2)
+    assert e.value.code == LBM_ESTATE
+    box.close()
+
+
 def test_step_before_init_rejected():
     box = Box(8, 4, 4, 0.6, 0.8)
     with pytest.raises(LBMError) as e:
@@ -180,8 +213,9 @@ def test_step_before_init_rejected():
     box.close()
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
-def test_full_size_thermal_waves(storage):
+@pytest.mark.parametrize("storage,layout", [("f32", "auto"), ("f16", "auto"), ("bf16", "auto"), ("f32", "planes"),
+                                            ("f32", "chunked")])
+def test_full_size_thermal_waves(storage, layout):
     """The benchmark's 512^3 thermal-wave box in its default launch shape,
     against the exact Fourier-mode solution at 4096 sampled nodes after 100
     steps (device-side initial field)."""
@@ -192,7 +226,7 @@ def test_full_size_thermal_waves(storage):
     log(f"d3q14 full size {storage}: init")
     scale = 2.0 ** -23 if storage == "f16" else 0.0
     box = Box(case.nx, case.ny, case.nz, case.tau_n, case.tau_r, storage=storage, scale=scale,
-              stochastic=storage != "f32", seed=3)
+              stochastic=storage != "f32", seed=3, layout=layout)
     T0 = W.modes_field_3d_torch(modes, case.nx, case.ny, case.nz, case.t0, "cuda")
     box.init(T0)
     del T0
@@ -205,6 +239,6 @@ def test_full_size_thermal_waves(storage):
     sol = b3.ModeSolution(modes, case.nx, case.ny, case.nz, n, case.tau_n, case.tau_r)
     T, qx, qy, qz = sol.at(xs, ys, zs)
     e_t, e_q = _eps([s[:, 0], s[:, 1], s[:, 2], s[:, 3]], [T - 1.0, qx, qy, qz])
-    log(f"d3q14 full size {storage}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
+    log(f"d3q14 full size {storage} {layout}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
     tol = {"f32": 1e-5, "f16": 5e-3, "bf16": 5e-2}[storage]
     assert e_t < tol and e_q < tol
