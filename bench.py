@@ -80,7 +80,7 @@ def _parse():
                         "storage, which stalls on smooth fields otherwise; nearest for the rest)")
     p.add_argument("--sweep-steps", type=int, default=300, help="timed steps per sweep schedule (0: skip)")
     p.add_argument("--fusion", default="auto", choices=["auto", "1", "2"],
-                   help="time steps per launch (auto: the library's default, 1 for the FP16 kinds, 2 otherwise)")
+                   help="time steps per launch (auto: the library's default, 2)")
     p.add_argument("--check-interval", type=int, default=100)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -114,7 +114,7 @@ def _run_gpu(args, storage, rounding, torch, P, W, host_io=False):
     scale = 2.0 ** -20 if storage.startswith("f16") else 0.0
     lat = P.Lattice([P.instance_from_case(case, scale)], storage=storage,
                     check_interval=args.check_interval, rounding=rounding, seed=1847)
-    fuse = (1 if storage in ("f16", "f16_split") else 2) if args.fusion == "auto" else int(args.fusion)
+    fuse = 2 if args.fusion == "auto" else int(args.fusion)
     lat.set_step_fusion(fuse)
     tune = lat.autotune(10) if args.autotune else None
     T0 = W.initial_field(case)

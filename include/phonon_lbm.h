@@ -274,10 +274,9 @@ int lbm_set_wall_flux(lbm_handle h, int32_t inst, int32_t wall, double q0);
  * HBM (temporal blocking: tiles with a two-node halo in LDS, the intermediate
  * state rounded exactly as a stored step), for pairs of plain steps (no
  * check-step work) that are not the last step of an lbm_step call; 1 issues
- * every step on its own.  Results are identical either way.  Default: 2,
- * except 1 for LBM_F16 and LBM_F16_SPLIT (two-step launches are latency
- * bound rather than HBM bound; measured, they beat single steps for FP32,
- * BF16 and BF16_SPLIT storage but not for the FP16 kinds).  Drops captured
+ * every step on its own.  Results are identical either way.  Default: 2
+ * (measured faster than single steps for every storage kind; the tile height
+ * and block size of the two-step kernel depend on the kind).  Drops captured
  * graphs.  Errors: EINVAL (steps not 1 or 2). */
 int lbm_set_step_fusion(lbm_handle h, int32_t steps);
 

@@ -803,11 +803,12 @@ hipError_t launch_moments(int storage, const InstDesc* d_desc, const RefState* d
 //
 // Temporal blocking: two time steps per pass over HBM.  The LDS tile holds the
 // post-relaxation populations (FP32, as a single step would read them back) of
-// a 64 x (kPairH + 4) window starting two nodes left of and below the output
-// tile, every position mapped to its periodic image (as the single-step pull
-// wraps).  Step m advances the inner 62 x (kPairH + 2) window (whose pulls stay
-// inside the tile), rounded exactly as a stored step; step m + 1 advances the
-// 60 x kPairH outputs and stores them.  Per node and step the arithmetic is the
+// a 64 x (H + 4) window starting two nodes left of and below the output tile
+// (H = pair_rows of the storage kind, NW = pair_waves waves per block), every
+// position mapped to its periodic image (as the single-step pull wraps).  Step
+// m advances the inner 62 x (H + 2) window (whose pulls stay inside the tile),
+// rounded exactly as a stored step; step m + 1 advances the 60 x H outputs and
+// stores them.  Per node and step the arithmetic is the
 // single-step kernels' (same functions, same order), so the bits are the same.
 
 // y component of velocity i.
@@ -871,9 +872,9 @@ __device__ __forceinline__ bool on_wall(const InstDesc& d, int x, int y) {
            ((d.bc_x == 1 || d.bc_x == 2 || d.bc_x == 4) && (x == 0 || x == d.nx - 1));
 }
 
-template <class S, int SR, int SPLIT>
-__global__ __launch_bounds__(256) void pair_kernel(StepArgs a, int xcd, int nontemporal) {
-    constexpr int kRows = kPairH + 4;
+template <class S, int SR, int SPLIT, int H, int NW>
+__global__ __launch_bounds__(64 * NW) void pair_kernel(StepArgs a, int xcd, int nontemporal) {
+    constexpr int kRows = H + 4;
     __shared__ float lds[8][kRows][64];
     const int b = blockIdx.x;
     int t = b;
@@ -888,7 +889,7 @@ __global__ __launch_bounds__(256) void pair_kernel(StepArgs a, int xcd, int nont
     const int local = t - d.p_tile_begin;
     const int ty = local / d.p_tiles_x;
     const int tx = local - ty * d.p_tiles_x;
-    const int x0 = tx * kPairW, y0 = ty * kPairH;
+    const int x0 = tx * kPairW, y0 = ty * H;
     const int nx = d.nx, ny = d.ny;
     const int lx = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index: rows are wave-uniform
@@ -898,7 +899,7 @@ __global__ __launch_bounds__(256) void pair_kernel(StepArgs a, int xcd, int nont
     const int gx = wrapm(x0 - 2 + lx, nx, 64);
 
     // window loads: the post-relaxation state of step m - 1
-    for (int ly = wv; ly < kRows; ly += 4) {
+    for (int ly = wv; ly < kRows; ly += NW) {
         const int gy = wrapm(y0 - 2 + ly, ny, kRows);
         S v[8];
         const S* row = src + (int64_t)gy * d.row;
@@ -914,13 +915,13 @@ __global__ __launch_bounds__(256) void pair_kernel(StepArgs a, int xcd, int nont
     }
     __syncthreads();
 
-    // step m on the inner window (rows 1 .. kPairH + 2, columns 1 .. 62)
-    constexpr int kHold = (kPairH + 2 + 3) / 4;
+    // step m on the inner window (rows 1 .. H + 2, columns 1 .. 62)
+    constexpr int kHold = (H + 2 + NW - 1) / NW;
     float hold[kHold][8];
 #pragma unroll
     for (int j = 0; j < kHold; ++j) {
-        const int ly = 1 + wv + 4 * j;
-        if (ly > kPairH + 2 || lx == 0 || lx == 63) continue;
+        const int ly = 1 + wv + NW * j;
+        if (ly > H + 2 || lx == 0 || lx == 63) continue;
         const int gy = wrapm(y0 - 2 + ly, ny, kRows);
         float g[8];
 #pragma unroll
@@ -937,17 +938,17 @@ __global__ __launch_bounds__(256) void pair_kernel(StepArgs a, int xcd, int nont
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kHold; ++j) {
-        const int ly = 1 + wv + 4 * j;
-        if (ly > kPairH + 2 || lx == 0 || lx == 63) continue;
+        const int ly = 1 + wv + NW * j;
+        if (ly > H + 2 || lx == 0 || lx == 63) continue;
 #pragma unroll
         for (int i = 0; i < 8; ++i) lds[i][ly][lx] = hold[j][i];
     }
     __syncthreads();
 
-    // step m + 1 on the outputs (rows 2 .. kPairH + 1, columns 2 .. 61)
+    // step m + 1 on the outputs (rows 2 .. H + 1, columns 2 .. 61)
     const int ox = x0 + lx - 2;
     if (lx >= 2 && lx <= 61 && ox < nx) {
-        for (int ly = 2 + wv; ly <= kPairH + 1; ly += 4) {
+        for (int ly = 2 + wv; ly <= H + 1; ly += NW) {
             const int oy = y0 + ly - 2;
             if (oy >= ny) break;
             float g[8];
@@ -969,24 +970,24 @@ __global__ __launch_bounds__(256) void pair_kernel(StepArgs a, int xcd, int nont
     if (t == 0 && threadIdx.x == 0) a.ctr_out[0] = step + 2u;
 }
 
-template <class S, int SPLIT>
+template <class S, int SPLIT, int H, int NW>
 static hipError_t launch_pair_s(const Shape& sh, const StepArgs& a, hipStream_t st) {
-    dim3 grid(a.ntiles), block(256);
+    dim3 grid(a.ntiles), block(64 * NW);
     if (a.sr)
-        hipLaunchKernelGGL((pair_kernel<S, 1, SPLIT>), grid, block, 0, st, a, sh.xcd, sh.nt);
+        hipLaunchKernelGGL((pair_kernel<S, 1, SPLIT, H, NW>), grid, block, 0, st, a, sh.xcd, sh.nt);
     else
-        hipLaunchKernelGGL((pair_kernel<S, 0, SPLIT>), grid, block, 0, st, a, sh.xcd, sh.nt);
+        hipLaunchKernelGGL((pair_kernel<S, 0, SPLIT, H, NW>), grid, block, 0, st, a, sh.xcd, sh.nt);
     return hipGetLastError();
 }
 
 hipError_t launch_pair(int storage, const Shape& sh, const StepArgs& a, hipStream_t st) {
     if (a.ntiles <= 0) return hipSuccess;
     switch (storage) {
-        case 0: return launch_pair_s<float, 0>(sh, a, st);
-        case 1: return launch_pair_s<_Float16, 0>(sh, a, st);
-        case 2: return launch_pair_s<bf16_bits, 0>(sh, a, st);
-        case 3: return launch_pair_s<_Float16, 1>(sh, a, st);
-        case 4: return launch_pair_s<bf16_bits, 1>(sh, a, st);
+        case 0: return launch_pair_s<float, 0, pair_rows(0), pair_waves(0)>(sh, a, st);
+        case 1: return launch_pair_s<_Float16, 0, pair_rows(1), pair_waves(1)>(sh, a, st);
+        case 2: return launch_pair_s<bf16_bits, 0, pair_rows(2), pair_waves(2)>(sh, a, st);
+        case 3: return launch_pair_s<_Float16, 1, pair_rows(3), pair_waves(3)>(sh, a, st);
+        case 4: return launch_pair_s<bf16_bits, 1, pair_rows(4), pair_waves(4)>(sh, a, st);
         default: return hipErrorInvalidValue;
     }
 }

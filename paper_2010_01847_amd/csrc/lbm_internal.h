@@ -110,19 +110,23 @@ struct Shape {
 
 enum StepMode { kPlain = 0, kSnap = 1, kCheck = 2 };
 
-// Two-step (temporally blocked) kernel: a block of 256 threads takes a tile of
-// kPairW x kPairH output nodes, loads it with a two-node halo (64 x
-// (kPairH + 4) nodes) into LDS, advances the inner 62 x (kPairH + 2) nodes one
-// step in place, then the 60 x kPairH outputs a second step.
-// 6 output rows: the 20 KB window lets eight blocks (the 32-wave limit) share
-// a CU; measured on MI355X (8192^2 FP32): 6 rows 135, 8 rows 132, 12 rows 118,
-// 20 rows 107, 28 rows 87 GLUPS -- the kernel is latency bound, and occupancy
-// outweighs the halo recomputation.
-#ifndef PLBM_PAIR_ROWS
-#define PLBM_PAIR_ROWS 6
-#endif
+// Two-step (temporally blocked) kernel: a block of 64 * pair_waves threads
+// takes a tile of kPairW x pair_rows output nodes, loads it with a two-node
+// halo (64 x (pair_rows + 4) nodes) into LDS, advances the inner
+// 62 x (pair_rows + 2) nodes one step in place, then the 60 x pair_rows outputs
+// a second step.  The tile height and block size depend on the storage kind;
+// both are limited by the 32-wave and 160 KB LDS budgets of a CU.  Measured on
+// MI355X (8192^2, GLUPS):
+//   FP32:   6 rows x 4 waves 135 (20 KB, 8 blocks per CU); 6 x 8 136;
+//           8 x 4 132; 14 x 8 131; 12 x 4 118; 20 x 4 107
+//   BF16-SR / BF16_SPLIT: 6 x 4 157 / 138; 14 x 8 172 / 150 (37 KB, 4 blocks
+//           of 8 waves per CU); 22 x 8 165 / 140; 10 x 8 152 / 135
+// (the window is FP32 in LDS for every kind; the 16-bit kinds gain from the
+// smaller halo share of the taller tile, FP32 from the occupancy of the
+// small one).
 constexpr int kPairW = 60;
-constexpr int kPairH = PLBM_PAIR_ROWS;
+__host__ __device__ constexpr int pair_rows(int storage) { return storage == 0 ? 6 : 14; }
+__host__ __device__ constexpr int pair_waves(int storage) { return storage == 0 ? 4 : 8; }
 
 struct StepArgs {
     const InstDesc* desc;

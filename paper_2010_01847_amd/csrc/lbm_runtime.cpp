@@ -219,7 +219,8 @@ Layout layout_of(const std::vector<lbm_instance>& v, int storage, int check, int
     L.buf_bytes = align_up(elems * es, kAlign);
     L.tiles_max = max_tiles(v);
     L.groups_max = max_groups(v);
-    for (auto& in : v) L.ptiles += pair_tiles_x(in) * (int64_t)((in.ny + kPairH - 1) / kPairH);
+    const int ph = pair_rows(storage);
+    for (auto& in : v) L.ptiles += pair_tiles_x(in) * (int64_t)((in.ny + ph - 1) / ph);
     // the same scratch serves the first stage of lbm_totals' reduction
     const int64_t gscratch = std::max<int64_t>(L.groups_max, (L.mparts_max + kGroup - 1) / kGroup);
     size_t o = 0;
@@ -348,7 +349,7 @@ static void build_tiles(lbm_ctx* h) {
         h->group_inst.insert(h->group_inst.end(), (size_t)d.ngroups, (int32_t)k);
         d.p_tiles_x = (int32_t)pair_tiles_x(h->inst[k]);
         d.p_tile_begin = (int32_t)h->ptile_inst.size();
-        d.p_ntiles = d.p_tiles_x * ((d.ny + kPairH - 1) / kPairH);
+        d.p_ntiles = d.p_tiles_x * ((d.ny + pair_rows(h->storage) - 1) / pair_rows(h->storage));
         h->ptile_inst.insert(h->ptile_inst.end(), (size_t)d.p_ntiles, (int32_t)k);
     }
 }
@@ -500,10 +501,11 @@ int lbm_create(const lbm_config* cfg, lbm_handle* out) {
     }
     h->inst = v;
     h->storage = cfg->storage;
-    // two-step launches: measured on MI355X (8192^2), faster than single steps
-    // for FP32 (135 vs 90 GLUPS), BF16 (155 vs 128) and BF16_SPLIT (138 vs
-    // 131), slower for FP16 (137 vs 147) and F16_SPLIT (130 vs 137)
-    h->fuse = (cfg->storage == LBM_F16 || cfg->storage == LBM_F16_SPLIT) ? 1 : 2;
+    // two-step launches: measured on MI355X (8192^2, GLUPS), faster than
+    // single steps for every storage kind with its tile geometry
+    // (pair_rows/pair_waves): FP32 135 vs 90, BF16-SR 174 vs 128, BF16_SPLIT
+    // 150 vs 131, FP16-SR 149 vs 147, F16_SPLIT 146 vs 137
+    h->fuse = 2;
     h->K = check_of(cfg);
     h->stream = reinterpret_cast<hipStream_t>(cfg->stream);
     h->external = (cfg->flags & LBM_FLAG_EXTERNAL_MEMORY) != 0;
