@@ -90,8 +90,8 @@ def _parse():
     p.add_argument("--d3q14-rows", default="f32,bf16:stochastic,f16:stochastic",
                    help="storage[:rounding] rows of the D3Q14 box")
     p.add_argument("--d3q14-shape", default="auto",
-                   help="D3Q14 launch shape rows_per_tile,xcd_remap,nontemporal,tile_waves "
-                        "(auto: the autotuner's choice)")
+                   help="D3Q14 launch shape rows_per_tile,xcd_remap,nontemporal,tile_waves[,zchunk[,steps "
+                        "per launch]] (auto: the autotuner's choice)")
     p.add_argument("--copy-probe", action="store_true",
                    help="also run a 1 GiB torch device copy 5 times (counter calibration)")
     return p.parse_args()
@@ -225,9 +225,10 @@ def _run_d3q14(args, torch, W):
     """D3Q14 thermal-wave box: periodic n^3 (n = 512 by default), T0 = 1 plus
     16 seeded Fourier modes (wave numbers up to 8 per axis, total amplitude
     1e-3), tau_N = 0.6, tau_R = 5, no initial flux; chunked layout, launch
-    shape chosen by the library's autotuner.  One launch per step; the
-    per-launch time is the HIP-event time over the timed steps (consecutive
-    launches on one stream) divided by their number."""
+    shape and steps per launch (one, or two with the z-marching kernel) chosen
+    by the library's autotuner.  The per-launch time is the HIP-event time
+    over the timed steps (consecutive launches on one stream) divided by the
+    number of launches."""
     from paper_2010_01847_amd.d3q14 import Box
     case = W.thermal_waves_3d_case(args.d3q14_n)
     nodes = case.nodes
@@ -240,9 +241,12 @@ def _run_d3q14(args, torch, W):
         box = Box(case.nx, case.ny, case.nz, case.tau_n, case.tau_r, storage=st, scale=scale,
                   stochastic=rnd == "stochastic", seed=1847)
         if args.d3q14_shape == "auto":
-            box.autotune(10)
+            fuse = box.autotune(10)["steps_per_launch"]
         else:
-            box.set_launch_shape(*(int(v) for v in args.d3q14_shape.split(",")))
+            vals = [int(v) for v in args.d3q14_shape.split(",")]
+            box.set_launch_shape(*vals[:5])
+            fuse = vals[5] if len(vals) > 5 else (2 if st == "f32" else 1)
+            box.set_step_fusion(fuse)
         shape = box.launch_shape()
         T0 = W.modes_field_3d_torch(case.init_args["modes"], case.nx, case.ny, case.nz, case.t0, "cuda")
         box.init(T0)
@@ -258,19 +262,26 @@ def _run_d3q14(args, torch, W):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / args.d3q14_steps
         box.close()
+        # algorithmic bytes per launch: 14 reads + 14 writes per update, times
+        # the updates one launch performs (fuse = 2 for the z-marching kernel)
         gbs = BYTES_PER_NODE_3D[st] * nodes / (ms / 1e3) / 1e9
         out["rows"].append({"storage": st, "rounding": rnd, "mlups": round(nodes / (ms / 1e3) / 1e6, 1),
-                            "ms_per_step": round(ms, 4), "gbs": round(gbs, 1),
+                            "ms_per_step": round(ms, 4), "steps_per_launch": fuse,
+                            "launch_us": round(ms * fuse * 1e3, 1), "gbs": round(gbs, 1),
                             "frac": round(gbs / HBM_PEAK_GBS, 4), "layout": "chunked", "launch_shape": shape})
     f32 = [r for r in out["rows"] if r["storage"] == "f32"]
     if f32:
         r = f32[0]
+        two = r["steps_per_launch"] == 2
         out["roofline"] = {"bound": "hbm", "achieved": r["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": r["frac"], "kernel": "d3q14 step_kernel (FP32 storage)",
-                           "kernel_us": round(r["ms_per_step"] * 1e3, 1),
-                           "bytes_per_launch": BYTES_PER_NODE_3D["f32"] * nodes,
+                           "frac": r["frac"],
+                           "kernel": ("d3q14 pair_kernel (two steps per launch, z-marching)" if two
+                                      else "d3q14 step_kernel"),
+                           "steps_per_launch": r["steps_per_launch"], "kernel_us": r["launch_us"],
+                           "bytes_per_launch": BYTES_PER_NODE_3D["f32"] * nodes * r["steps_per_launch"],
                            "traffic": _traffic_from(os.path.join(
-                               PROFILES, f"stream_collide_d3q14_f32_thermal_waves_{case.nx}.md"), KERNEL_SOURCES_3D)}
+                               PROFILES, f"stream_collide_d3q14_f32{'_pair' if two else ''}_thermal_waves_{case.nx}.md"),
+                               KERNEL_SOURCES_3D)}
     return out
 
 

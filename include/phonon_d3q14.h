@@ -71,6 +71,8 @@ typedef struct {
     int32_t xcd_remap;      /* 1: each of the 8 XCDs takes one contiguous range of tiles */
     int32_t nontemporal;    /* 1: streaming stores */
     int32_t tile_waves;     /* 1, 2, 4 or 8 wavefronts (64-node segments) along x */
+    int32_t zchunk;         /* two steps per launch: planes each block marches through (>= 1;
+                               default 32) */
 } lbm3d_launch_shape;
 
 /* Message of the last failing call on this handle ("" if none); with NULL, the
@@ -128,19 +130,30 @@ int lbm3d_sample(lbm3d_handle h, const int64_t* nodes, int64_t count, double* ou
  * Errors: ENONFINITE if any total is not finite. */
 int lbm3d_totals(lbm3d_handle h, double out[4]);
 
+/* Time steps per launch: 2 advances two steps in one pass over HBM where an
+ * lbm3d_step call has at least two steps left (temporal blocking: each block
+ * owns 60 x 4 nodes of every plane of a z-range, marches along z, and keeps
+ * the intermediate state, rounded exactly as a stored step, in LDS and
+ * registers); 1 issues every step on its own.  Results are identical either
+ * way.  Default: 2 for FP32 storage, 1 for FP16/BF16 (measured faster at
+ * 512^3).  Errors: EINVAL (steps not 1 or 2). */
+int lbm3d_set_step_fusion(lbm3d_handle h, int32_t steps);
+
 /* Launch shape of the step kernel (default: 4 rows of one segment per tile,
  * ordinary stores, XCD remap off for the chunked layout and on for planes).
  * Errors: EINVAL. */
 int lbm3d_set_launch_shape(lbm3d_handle h, const lbm3d_launch_shape* shape);
 int lbm3d_get_launch_shape(lbm3d_handle h, lbm3d_launch_shape* shape);
 
-/* Time every tile shape (rows_per_tile x tile_waves) with and without the XCD
- * remap, then streaming stores on the fastest, for `steps` steps each (0
- * selects 20) on zeroed buffers, and keep the fastest.  Must run before
- * lbm3d_init (it overwrites the buffers).  report, if not NULL, receives a
- * JSON summary ({"timings_us": [[rows, xcd, nt, tile_waves, us], ...],
- * "best": [...]}) truncated to report_len.  Errors: ESTATE (memory not bound,
- * or already initialised), EHIP. */
+/* Time every single-step tile shape (rows_per_tile x tile_waves) with and
+ * without the XCD remap, then streaming stores on the fastest, then two steps
+ * per launch over z ranges of 16, 32 and 64 planes, for `steps` steps each (0
+ * selects 20) on zeroed buffers; keep the fastest shape, z range and steps per
+ * launch.  Must run before lbm3d_init (it overwrites the buffers).  report, if
+ * not NULL, receives a JSON summary ({"timings_us": [[rows, xcd, nt,
+ * tile_waves, us], ...], "best": [...], "pair_us_per_step": [[zchunk, us],
+ * ...], "zchunk": z, "steps_per_launch": 1 or 2}) truncated to report_len.
+ * Errors: ESTATE (memory not bound, or already initialised), EHIP. */
 int lbm3d_autotune(lbm3d_handle h, int32_t steps, char* report, size_t report_len);
 
 /* Free the handle and the memory it allocated. */

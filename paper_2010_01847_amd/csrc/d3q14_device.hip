@@ -179,18 +179,39 @@ __device__ __forceinline__ void put(S* p, S v, int nontemporal) {
     }
 }
 
+// The stored value of direction I after one relaxation.
+template <class S, int SR, int I>
+__device__ __forceinline__ S relax_round_one(const Coeffs& c, const float v[kQ], float wE_axis, float wE_corner,
+                                             float jx, float jy, float jz, const uint32_t r[7]) {
+    const float wE = I < 6 ? wE_axis : wE_corner;
+    const float k = I < 6 ? c.k_axis : c.k_corner;
+    const float delta = fmaf(c.inv_tau, wE - v[I], k * c_dot<I>(jx, jy, jz));
+    if constexpr (SR && __is_same(S, float)) return sr_add_f32(v[I], delta, bits16(r, I));
+    else return rounded<S, SR>(v[I] + delta, SR ? bits16(r, I) : 0u);
+}
+
 // One relaxation of direction I and its store at the node's own position.
 template <class S, int SR, int L, int I>
 __device__ __forceinline__ void relax_store_one(const Geometry& g, const Coeffs& c, const float v[kQ], float wE_axis,
                                                 float wE_corner, float jx, float jy, float jz, const uint32_t r[7],
                                                 S* dst, int64_t row, int x, int nontemporal) {
-    const float wE = I < 6 ? wE_axis : wE_corner;
-    const float k = I < 6 ? c.k_axis : c.k_corner;
-    const float delta = fmaf(c.inv_tau, wE - v[I], k * c_dot<I>(jx, jy, jz));
-    S o;
-    if constexpr (SR && __is_same(S, float)) o = sr_add_f32(v[I], delta, bits16(r, I));
-    else o = rounded<S, SR>(v[I] + delta, SR ? bits16(r, I) : 0u);
-    put<S>(dst + elem<L>(g, I, row, x), o, nontemporal);
+    put<S>(dst + elem<L>(g, I, row, x), relax_round_one<S, SR, I>(c, v, wE_axis, wE_corner, jx, jy, jz, r),
+           nontemporal);
+}
+
+// One relaxation of all 14 directions, each rounded to S and read back as
+// the next step would load it.
+template <class S, int SR, int... Is>
+__device__ __forceinline__ void relax_reload_all(const Coeffs& c, const float v[kQ], float wE_axis, float wE_corner,
+                                                 float jx, float jy, float jz, const uint32_t r[7], float out[kQ],
+                                                 std::integer_sequence<int, Is...>) {
+    ((out[Is] = Cvt<S>::ld(relax_round_one<S, SR, Is>(c, v, wE_axis, wE_corner, jx, jy, jz, r))), ...);
+}
+
+// Stochastic-rounding words of global node `node` at step `step`.
+__device__ __forceinline__ void sr_words(uint32_t r[7], uint32_t node, uint32_t step, uint32_t seed) {
+#pragma unroll
+    for (int k = 0; k < 7; ++k) r[k] = mix32(node ^ mix32(step * 8u + (uint32_t)k + seed * 0x9e3779b9u));
 }
 
 template <class S, int SR, int L, int... Is>
@@ -215,11 +236,7 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs a) {
     float E, jx, jy, jz;
     moments(v, E, jx, jy, jz);
     uint32_t r[7] = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
-    if (SR) {
-        const uint32_t node = ((uint32_t)z * (uint32_t)a.g.ny + (uint32_t)y) * (uint32_t)a.g.nx + (uint32_t)x;
-#pragma unroll
-        for (int k = 0; k < 7; ++k) r[k] = mix32(node ^ mix32(a.step * 8u + (uint32_t)k + a.seed * 0x9e3779b9u));
-    }
+    if (SR) sr_words(r, ((uint32_t)z * (uint32_t)a.g.ny + (uint32_t)y) * (uint32_t)a.g.nx + (uint32_t)x, a.step, a.seed);
     relax_store_all<S, SR, L>(a.g, a.c, v, a.c.omega_axis * E, a.c.omega_corner * E, jx, jy, jz, r,
                               reinterpret_cast<S*>(a.dst), (int64_t)z * a.g.ny + y, x, a.nontemporal,
                               std::make_integer_sequence<int, kQ>{});
@@ -250,6 +267,211 @@ hipError_t launch_step(int storage, int sr, const StepArgs& a, hipStream_t st) {
         case 2: return launch_step_s<bf16_bits>(sr, a, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+// ------------------------------------------------------------------ two steps per launch
+//
+// Temporal blocking for the 3D lattice: a block owns a tile of 60 x YO output
+// nodes of every plane of a z-range and marches along z.  Its window is
+// 64 x (YO + 4) nodes (a two-node halo in x and y, each position mapped to its
+// periodic image).  Iteration `it` loads input plane zi = z0 - 2 + it, advances
+// plane zi - 1 one step on the inner 62 x (YO + 2) window (rounded exactly as a
+// stored step and read back), and advances plane zi - 2 a second step on the
+// outputs, which it stores.  A node pulls direction i from the plane z - c_iz,
+// so of a loaded plane the movers with c_z = -1 are needed at once, those with
+// c_z = 0 one iteration later and those with c_z = +1 two iterations later:
+// each thread keeps the later ones in registers, and per iteration a single
+// LDS plane per stage holds, direction by direction, exactly the values that
+// stage pulls.  Per node and step the arithmetic is the single-step kernel's
+// (same functions, same order, same random bits), so the result equals two
+// single steps bit for bit.
+
+// Directions by c_z: -1 (5), 0 (4), +1 (5).
+__host__ __device__ constexpr int dir_dn(int k) { return k == 0 ? 5 : 9 + k; }
+__host__ __device__ constexpr int dir_mid(int k) { return k; }
+__host__ __device__ constexpr int dir_up(int k) { return k == 0 ? 4 : 5 + k; }
+
+__device__ __forceinline__ int wrap_mod(int v, int n) {
+    const int r = v % n;
+    return r < 0 ? r + n : r;
+}
+
+template <class S, int SR, int L, int YO, int NW>
+__global__ __launch_bounds__(64 * NW) void pair_kernel(PairArgs a) {
+    constexpr int WR = YO + 4;                // window rows
+    constexpr int NJ = (WR + NW - 1) / NW;    // window rows per wavefront (NW wavefronts)
+    __shared__ float lds_a[kQ][WR][64];       // stage 1 pulls (input values)
+    __shared__ float lds_b[kQ][YO + 2][64];   // stage 2 pulls (stage-1 values, inner rows)
+    const Geometry& g = a.g;
+    uint32_t tile = blockIdx.x;
+    if (a.xcd_remap) {
+        const uint32_t per = (a.ntiles + 7u) >> 3;
+        tile = (blockIdx.x & 7u) * per + (blockIdx.x >> 3);
+    }
+    if (tile >= a.ntiles) return;             // whole block: no barrier is skipped by part of it
+    const uint32_t tx = tile % a.ptx;
+    const uint32_t rr = tile / a.ptx;
+    const uint32_t ty = rr % a.pty;
+    const uint32_t tz = rr / a.pty;
+    const int x0 = (int)tx * kPairW3, y0 = (int)ty * YO, z0 = (int)tz * a.zchunk;
+    const int zend = min(z0 + a.zchunk, g.nz);
+    const int iters = zend - z0 + 4;
+    const int lx = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int gx = wrap_mod(x0 - 2 + lx, g.nx);
+    const S* __restrict__ src = reinterpret_cast<const S*>(a.src);
+    S* __restrict__ dst = reinterpret_cast<S*>(a.dst);
+
+    int gy[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) gy[j] = wrap_mod(y0 - 2 + wv + NW * j, g.ny);
+
+    float nv[NJ][kQ];                         // the input plane of this iteration
+    float a_mid[NJ][4], a_up1[NJ][5], a_up2[NJ][5];   // later-needed input values
+    float b_mid[NJ][4], b_up1[NJ][5], b_up2[NJ][5];   // later-needed stage-1 values
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a_mid[j][k] = b_mid[j][k] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) a_up1[j][k] = a_up2[j][k] = b_up1[j][k] = b_up2[j][k] = 0.0f;
+    }
+
+    auto load_plane = [&](int zi) {
+        const int64_t zrow = (int64_t)wrap_mod(zi, g.nz) * g.ny;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            if (wv + NW * j >= WR) continue;
+            const int64_t row = zrow + gy[j];
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) nv[j][i] = Cvt<S>::ld(src[elem<L>(g, i, row, gx)]);
+        }
+    };
+
+    load_plane(z0 - 2);
+    for (int it = 0; it < iters; ++it) {
+        const int zi = z0 - 2 + it;
+        // stage 1 pulls: c_z = -1 movers of plane zi, 0 of zi - 1, +1 of zi - 2
+        if (it >= 2) {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const int ly = wv + NW * j;
+                if (ly >= WR) continue;
+#pragma unroll
+                for (int k = 0; k < 5; ++k) lds_a[dir_dn(k)][ly][lx] = nv[j][dir_dn(k)];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) lds_a[dir_mid(k)][ly][lx] = a_mid[j][k];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) lds_a[dir_up(k)][ly][lx] = a_up2[j][k];
+            }
+        }
+        __syncthreads();
+        // stage 1: plane zi - 1 on the inner window
+        float s1[NJ][kQ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) s1[j][i] = 0.0f;
+        if (it >= 2) {
+            const int zw = wrap_mod(zi - 1, g.nz);
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const int ly = wv + NW * j;
+                if (ly < 1 || ly > YO + 2 || lx < 1 || lx > 62) continue;
+                float v[kQ];
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) v[i] = lds_a[i][ly - cy(i)][lx - cx(i)];
+                float E, jx, jy, jz;
+                moments(v, E, jx, jy, jz);
+                uint32_t r[7] = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
+                if (SR) sr_words(r, ((uint32_t)zw * (uint32_t)g.ny + (uint32_t)gy[j]) * (uint32_t)g.nx + (uint32_t)gx,
+                                 a.step, a.seed);
+                relax_reload_all<S, SR>(a.c, v, a.c.omega_axis * E, a.c.omega_corner * E, jx, jy, jz, r, s1[j],
+                                        std::make_integer_sequence<int, kQ>{});
+            }
+        }
+        // the loaded plane's later-needed movers wait in registers
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                a_up2[j][k] = a_up1[j][k];
+                a_up1[j][k] = nv[j][dir_up(k)];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) a_mid[j][k] = nv[j][dir_mid(k)];
+        }
+        if (it + 1 < iters) load_plane(zi + 1);
+        // stage 2 pulls: c_z = -1 movers of stage-1 plane zi - 1, 0 of zi - 2, +1 of zi - 3
+        if (it >= 4) {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const int ly = wv + NW * j;
+                if (ly < 1 || ly > YO + 2 || lx < 1 || lx > 62) continue;
+#pragma unroll
+                for (int k = 0; k < 5; ++k) lds_b[dir_dn(k)][ly - 1][lx] = s1[j][dir_dn(k)];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) lds_b[dir_mid(k)][ly - 1][lx] = b_mid[j][k];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) lds_b[dir_up(k)][ly - 1][lx] = b_up2[j][k];
+            }
+        }
+        __syncthreads();
+        // stage 2: plane zi - 2 on the outputs, stored
+        if (it >= 4) {
+            const int zo = zi - 2;
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const int ly = wv + NW * j;
+                const int ox = x0 + lx - 2, oy = y0 + ly - 2;
+                if (ly < 2 || ly > YO + 1 || lx < 2 || lx > 61 || ox >= g.nx || oy >= g.ny) continue;
+                float v[kQ];
+#pragma unroll
+                for (int i = 0; i < kQ; ++i) v[i] = lds_b[i][ly - 1 - cy(i)][lx - cx(i)];
+                float E, jx, jy, jz;
+                moments(v, E, jx, jy, jz);
+                uint32_t r[7] = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
+                if (SR) sr_words(r, ((uint32_t)zo * (uint32_t)g.ny + (uint32_t)oy) * (uint32_t)g.nx + (uint32_t)ox,
+                                 a.step + 1u, a.seed);
+                relax_store_all<S, SR, L>(g, a.c, v, a.c.omega_axis * E, a.c.omega_corner * E, jx, jy, jz, r, dst,
+                                          (int64_t)zo * g.ny + oy, ox, a.nontemporal,
+                                          std::make_integer_sequence<int, kQ>{});
+            }
+        }
+        if (it >= 2) {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    b_up2[j][k] = b_up1[j][k];
+                    b_up1[j][k] = s1[j][dir_up(k)];
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) b_mid[j][k] = s1[j][dir_mid(k)];
+            }
+        }
+    }
+}
+
+template <class S, int L>
+static void launch_pair_l(int sr, const PairArgs& a, hipStream_t st) {
+    const dim3 grid(a.xcd_remap ? 8u * ((a.ntiles + 7u) / 8u) : a.ntiles), block(64 * kPairNW);
+    if (sr) hipLaunchKernelGGL((pair_kernel<S, 1, L, kPairYO, kPairNW>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((pair_kernel<S, 0, L, kPairYO, kPairNW>), grid, block, 0, st, a);
+}
+
+hipError_t launch_pair(int storage, int sr, const PairArgs& a, hipStream_t st) {
+    if (a.ntiles == 0) return hipSuccess;
+    switch (storage * 2 + (a.g.layout ? 1 : 0)) {
+        case 0: launch_pair_l<float, 0>(sr, a, st); break;
+        case 1: launch_pair_l<float, 1>(sr, a, st); break;
+        case 2: launch_pair_l<_Float16, 0>(sr, a, st); break;
+        case 3: launch_pair_l<_Float16, 1>(sr, a, st); break;
+        case 4: launch_pair_l<bf16_bits, 0>(sr, a, st); break;
+        case 5: launch_pair_l<bf16_bits, 1>(sr, a, st); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 // Instantiate kernel K<S, L> for the storage and layout of a call.

@@ -53,6 +53,39 @@ struct StepArgs {
 // storage: 0 FP32, 1 FP16, 2 BF16; sr: stochastic rounding of the stores.
 hipError_t launch_step(int storage, int sr, const StepArgs& a, hipStream_t st);
 
+// Two steps per launch (steps `step` and `step + 1`): a block of 64 * kPairNW
+// threads owns 60 x kPairYO output nodes of each plane of a range of zchunk
+// planes and marches along z (see the device file).  Measured at 512^3 FP32
+// (GLUPS, best z range, XCD remap on; single steps 50):
+//   rows x waves  4 x 4: 58.8 (50 KB LDS, 142 VGPRs)   4 x 8: 57.0
+//                 6 x 10: 65.7   8 x 12: 69.8   12 x 16: 71.1 (107 KB LDS,
+//                 88 VGPRs, one block of 16 wavefronts per CU)
+// 12 x 16 is the largest tile that keeps one window row per wavefront
+// (88 VGPRs) within the 1024-thread block and 160 KB LDS limits.
+constexpr int kPairW3 = 60;
+#ifndef PLBM3_PAIR_ROWS
+#define PLBM3_PAIR_ROWS 12
+#endif
+#ifndef PLBM3_PAIR_WAVES
+#define PLBM3_PAIR_WAVES 16
+#endif
+constexpr int kPairYO = PLBM3_PAIR_ROWS;
+constexpr int kPairNW = PLBM3_PAIR_WAVES;
+struct PairArgs {
+    Geometry g;
+    Coeffs c;
+    const void* src;
+    void* dst;
+    uint32_t step;
+    uint32_t seed;
+    int32_t xcd_remap;
+    int32_t nontemporal;
+    uint32_t ptx, pty, ptz;     // tiles along x (60 nodes), y (kPairYO rows), z (zchunk planes)
+    uint32_t ntiles;            // ptx * pty * ptz
+    int32_t zchunk;
+};
+hipError_t launch_pair(int storage, int sr, const PairArgs& a, hipStream_t st);
+
 // Equilibrium initial state: element (i, x) holds the scaled deviation of the
 // Eq. 15 equilibrium at node x + c_i, so that the first pull reads e_i(x, 0).
 hipError_t launch_init(int storage, const Geometry& g, void* dst, const double* T, const double* qx,

@@ -28,7 +28,7 @@ class lbm3d_config(ctypes.Structure):
 
 class lbm3d_launch_shape(ctypes.Structure):
     _fields_ = [("rows_per_tile", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
-                ("nontemporal", ctypes.c_int32), ("tile_waves", ctypes.c_int32)]
+                ("nontemporal", ctypes.c_int32), ("tile_waves", ctypes.c_int32), ("zchunk", ctypes.c_int32)]
 
 
 STORAGE3 = {"f32": LBM_F32, "f16": LBM_F16, "bf16": LBM_BF16}
@@ -48,6 +48,7 @@ SIGNATURES3 = [
     ("lbm3d_totals", ctypes.c_int, [_P, _D]),
     ("lbm3d_set_launch_shape", ctypes.c_int, [_P, ctypes.POINTER(lbm3d_launch_shape)]),
     ("lbm3d_get_launch_shape", ctypes.c_int, [_P, ctypes.POINTER(lbm3d_launch_shape)]),
+    ("lbm3d_set_step_fusion", ctypes.c_int, [_P, ctypes.c_int32]),
     ("lbm3d_autotune", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_char_p, ctypes.c_size_t]),
     ("lbm3d_destroy", None, [_P]),
 ]
@@ -123,6 +124,10 @@ def lbm3d_totals(h) -> np.ndarray:
 
 def lbm3d_set_launch_shape(h, shape: lbm3d_launch_shape) -> None:
     _check(library().lbm3d_set_launch_shape(h, ctypes.byref(shape)), "lbm3d_set_launch_shape", h)
+
+
+def lbm3d_set_step_fusion(h, steps: int) -> None:
+    _check(library().lbm3d_set_step_fusion(h, int(steps)), "lbm3d_set_step_fusion", h)
 
 
 def lbm3d_get_launch_shape(h) -> lbm3d_launch_shape:
@@ -227,13 +232,17 @@ class Box:
         return lbm3d_totals(self.h)
 
     def set_launch_shape(self, rows_per_tile: int = 4, xcd_remap: int = 0, nontemporal: int = 0,
-                         tile_waves: int = 1) -> None:
-        lbm3d_set_launch_shape(self.h, lbm3d_launch_shape(rows_per_tile, xcd_remap, nontemporal, tile_waves))
+                         tile_waves: int = 1, zchunk: int = 32) -> None:
+        lbm3d_set_launch_shape(self.h, lbm3d_launch_shape(rows_per_tile, xcd_remap, nontemporal, tile_waves,
+                                                          zchunk))
 
     def launch_shape(self) -> dict:
         s = lbm3d_get_launch_shape(self.h)
         return {"rows_per_tile": s.rows_per_tile, "xcd_remap": s.xcd_remap, "nontemporal": s.nontemporal,
-                "tile_waves": s.tile_waves}
+                "tile_waves": s.tile_waves, "zchunk": s.zchunk}
+
+    def set_step_fusion(self, steps: int) -> None:
+        lbm3d_set_step_fusion(self.h, steps)
 
     def autotune(self, steps: int = 20) -> dict:
         """Pick the fastest launch shape (before init); returns the timing report."""

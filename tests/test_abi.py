@@ -216,12 +216,17 @@ def test_d3q14_handle_state_without_gpu():
         with pytest.raises(P.LBMError) as e:
             D.lbm3d_bind(h, 0x1000 + 3, 1 << 40)
         assert e.value.code == P.LBM_EINVAL
-        for bad in ((3, 1, 0, 1), (4, 2, 0, 1), (1, 0, 5, 1), (1, 0, 0, 3), (2, 0, 0, 8), (1, 0, 0, 0)):
+        for bad in ((3, 1, 0, 1, 8), (4, 2, 0, 1, 8), (1, 0, 5, 1, 8), (1, 0, 0, 3, 8), (2, 0, 0, 8, 8),
+                    (1, 0, 0, 0, 8), (1, 0, 0, 1, 0)):
             with pytest.raises(P.LBMError):
                 D.lbm3d_set_launch_shape(h, D.lbm3d_launch_shape(*bad))
-        D.lbm3d_set_launch_shape(h, D.lbm3d_launch_shape(2, 0, 1, 4))
+        D.lbm3d_set_launch_shape(h, D.lbm3d_launch_shape(2, 0, 1, 4, 16))
         s = D.lbm3d_get_launch_shape(h)
-        assert (s.rows_per_tile, s.xcd_remap, s.nontemporal, s.tile_waves) == (2, 0, 1, 4)
+        assert (s.rows_per_tile, s.xcd_remap, s.nontemporal, s.tile_waves, s.zchunk) == (2, 0, 1, 4, 16)
+        for bad in (0, 3):
+            with pytest.raises(P.LBMError):
+                D.lbm3d_set_step_fusion(h, bad)
+        D.lbm3d_set_step_fusion(h, 2)
         assert D.lbm3d_steps_done(h) == 0
         with pytest.raises(P.LBMError) as e:
             D.lbm3d_autotune(h, 2)           # no memory bound yet

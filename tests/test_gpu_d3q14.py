@@ -37,16 +37,20 @@ def _oracle(nx, ny, nz, tau_n, tau_r, T0, q, steps):
 
 
 def _gpu(nx, ny, nz, tau_n, tau_r, T0, q, steps, storage="f32", shape=None, stochastic=False, seed=0,
-         scale=0.0, layout="auto"):
+         scale=0.0, layout="auto", fuse=1):
+    """Moments after each call of `steps` (an int, or a sequence of call lengths)."""
     box = Box(nx, ny, nz, tau_n, tau_r, storage=storage, stochastic=stochastic, seed=seed, scale=scale,
               layout=layout)
     if shape:
         box.set_launch_shape(**shape)
+    box.set_step_fusion(fuse)
     box.init(T0, q)
-    box.step(steps)
-    out = box.moments()
+    outs = []
+    for n in ([steps] if isinstance(steps, int) else steps):
+        box.step(n)
+        outs.append(box.moments())
     box.close()
-    return out
+    return outs[0] if isinstance(steps, int) else outs
 
 
 def _eps(g, o):
@@ -188,8 +192,9 @@ def test_autotune_then_parity():
     T0, q = _random_start(nx, ny, nz, 71)
     box = Box(nx, ny, nz, 0.6, 5.0)
     rep = box.autotune(3)
-    assert len(rep["timings_us"]) == 19
-    assert list(box.launch_shape().values()) == rep["best"][:4]
+    assert len(rep["timings_us"]) == 19 and len(rep["pair_us_per_step"]) == 3
+    assert rep["steps_per_launch"] in (1, 2)
+    assert list(box.launch_shape().values()) == rep["best"][:4] + [rep["zchunk"]]
     box.init(T0, q)
     box.step(n)
     tuned = box.moments()
@@ -213,9 +218,10 @@ def test_step_before_init_rejected():
     box.close()
 
 
-@pytest.mark.parametrize("storage,layout", [("f32", "auto"), ("f16", "auto"), ("bf16", "auto"), ("f32", "planes"),
-                                            ("f32", "chunked")])
-def test_full_size_thermal_waves(storage, layout):
+@pytest.mark.parametrize("storage,layout,fuse", [("f32", "auto", 1), ("f16", "auto", 1), ("bf16", "auto", 1),
+                                                 ("f32", "planes", 1), ("f32", "chunked", 1), ("f32", "auto", 2),
+                                                 ("bf16", "auto", 2)])
+def test_full_size_thermal_waves(storage, layout, fuse):
     """The benchmark's 512^3 thermal-wave box in its default launch shape,
     against the exact Fourier-mode solution at 4096 sampled nodes after 100
     steps (device-side initial field)."""
@@ -227,6 +233,7 @@ def test_full_size_thermal_waves(storage, layout):
     scale = 2.0 ** -23 if storage == "f16" else 0.0
     box = Box(case.nx, case.ny, case.nz, case.tau_n, case.tau_r, storage=storage, scale=scale,
               stochastic=storage != "f32", seed=3, layout=layout)
+    box.set_step_fusion(fuse)
     T0 = W.modes_field_3d_torch(modes, case.nx, case.ny, case.nz, case.t0, "cuda")
     box.init(T0)
     del T0
@@ -239,6 +246,58 @@ def test_full_size_thermal_waves(storage, layout):
     sol = b3.ModeSolution(modes, case.nx, case.ny, case.nz, n, case.tau_n, case.tau_r)
     T, qx, qy, qz = sol.at(xs, ys, zs)
     e_t, e_q = _eps([s[:, 0], s[:, 1], s[:, 2], s[:, 3]], [T - 1.0, qx, qy, qz])
-    log(f"d3q14 full size {storage} {layout}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
+    log(f"d3q14 full size {storage} {layout} fuse={fuse}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
     tol = {"f32": 1e-5, "f16": 5e-3, "bf16": 5e-2}[storage]
     assert e_t < tol and e_q < tol
+
+
+FUSION3 = [("f32", False, "chunked"), ("f32", False, "planes"), ("f32", True, "chunked"),
+           ("bf16", True, "chunked"), ("f16", True, "planes"), ("f16", False, "chunked")]
+
+
+@pytest.mark.parametrize("storage,stochastic,layout", FUSION3)
+def test_two_step_kernel_bitwise(storage, stochastic, layout):
+    """Two steps per launch (the z-marching kernel) give the same bits as single
+    steps: storage kinds and roundings, both layouts, a box ragged against the
+    60 x 4 tiles and the 32-plane z ranges, and call lengths that leave odd
+    remainders (run as single steps)."""
+    nx, ny, nz = 131, 11, 37
+    T0, q = _random_start(nx, ny, nz, 81)
+    calls = (1, 2, 3, 7, 10)
+    ref_out = _gpu(nx, ny, nz, 0.6, 7.0, T0, q, calls, storage=storage, stochastic=stochastic, seed=5,
+                   layout=layout, fuse=1)
+    got = _gpu(nx, ny, nz, 0.6, 7.0, T0, q, calls, storage=storage, stochastic=stochastic, seed=5,
+               layout=layout, fuse=2)
+    for a_fields, b_fields in zip(got, ref_out):
+        for a, b in zip(a_fields, b_fields):
+            assert np.array_equal(a, b), (storage, stochastic, layout)
+    e_t, e_q = _eps(got[-1], _oracle(nx, ny, nz, 0.6, 7.0, T0, q, sum(calls)))
+    log(f"d3q14 two-step {storage} sr={stochastic} {layout}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
+    assert e_t < TOL3[storage] and e_q < TOL3[storage]
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 1), (2, 3, 1), (5, 2, 4), (61, 5, 3), (64, 4, 33), (59, 9, 2)])
+def test_two_step_small_boxes(dims):
+    """Boxes smaller than one tile or one z range (the window wraps several
+    times), and one node past a tile edge: same bits as single steps."""
+    nx, ny, nz = dims
+    T0, q = _random_start(nx, ny, nz, 91)
+    a = _gpu(nx, ny, nz, 0.6, 50.0, T0, q, 6, fuse=1)
+    b = _gpu(nx, ny, nz, 0.6, 50.0, T0, q, 6, fuse=2)
+    for u, v in zip(a, b):
+        assert np.array_equal(u, v), dims
+    e_t, e_q = _eps(b, _oracle(nx, ny, nz, 0.6, 50.0, T0, q, 6))
+    assert e_t < 1e-5 and e_q < 1e-5
+
+
+def test_two_step_z_ranges_and_remap():
+    """The z range per block and the XCD remap change only the work split."""
+    nx, ny, nz, n = 70, 9, 23, 8
+    T0, q = _random_start(nx, ny, nz, 101)
+    ref_out = _gpu(nx, ny, nz, 0.7, 3.0, T0, q, n, fuse=1)
+    for zc in (1, 2, 7, 32):
+        for xcd in (0, 1):
+            out = _gpu(nx, ny, nz, 0.7, 3.0, T0, q, n, fuse=2,
+                       shape=dict(rows_per_tile=4, xcd_remap=xcd, nontemporal=0, tile_waves=1, zchunk=zc))
+            for a, b in zip(out, ref_out):
+                assert np.array_equal(a, b), (zc, xcd)
