@@ -980,12 +980,174 @@ static hipError_t launch_pair_s(const Shape& sh, const StepArgs& a, hipStream_t 
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ two steps per launch, y-marching
+//
+// The same two steps as pair_kernel without LDS or barriers: a wavefront owns a
+// 64-column window (60 outputs and a two-node halo, periodic images) of a chunk
+// of kMarchRows output rows and marches along y.  Iteration `it` loads input
+// row yi = y0 - 2 + it, advances row yi - 1 one step on lanes 1..62 and row
+// yi - 2 a second step on lanes 2..61, which it stores.  A node pulls direction
+// i from row y - c_iy, so of a loaded row the c_y = -1 movers are used at
+// once, the c_y = 0 movers one iteration later and the c_y = +1 movers two
+// iterations later (kept in registers), and the x neighbours come from the
+// adjacent lanes by DPP.  Per node and step the arithmetic is the single-step
+// kernels' (same functions, same order, same random bits), so the result
+// equals two single steps bit for bit.
+
+// Directions by c_y: -1 {3, 6, 7}, 0 {0, 2}, +1 {1, 4, 5}.
+__device__ __forceinline__ constexpr int ymid(int k) { return 2 * k; }
+__device__ __forceinline__ constexpr int yup(int k) { return k == 0 ? 1 : 3 + k; }
+
+// v of the lane at x - c_ix (the pull along x); all 64 lanes active.
+template <int I>
+__device__ __forceinline__ float xpull(float v) {
+    if constexpr (vel_x(I) > 0) return from_left(v, v);
+    else if constexpr (vel_x(I) < 0) return from_right(v, v);
+    else return v;
+}
+
+// Pulled populations of one stage: direction i from the row at y - c_iy
+// (dn: the newest row, mid: one row back, up: two rows back), shifted by c_ix.
+__device__ __forceinline__ void march_gather(const float dn_row[8], const float mid[2], const float up[3], float g[8]) {
+    g[0] = xpull<0>(mid[0]);
+    g[2] = xpull<2>(mid[1]);
+    g[1] = xpull<1>(up[0]);
+    g[4] = xpull<4>(up[1]);
+    g[5] = xpull<5>(up[2]);
+    g[3] = xpull<3>(dn_row[3]);
+    g[6] = xpull<6>(dn_row[6]);
+    g[7] = xpull<7>(dn_row[7]);
+}
+
+template <class S, int SR, int SPLIT>
+__global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int nontemporal) {
+    const int lane = threadIdx.x & 63;
+    int b = blockIdx.x;
+    if (xcd) {
+        const int nb = gridDim.x, q = nb >> 3, r = nb & 7, k = b & 7, j = b >> 3;
+        b = k * q + (k < r ? k : r) + j;
+    }
+    const int t = b * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    if (t >= a.ntiles) return;                // whole wavefront: no lane is left behind a DPP move
+    const int tg = t + a.tile_base;
+    const int inst = a.tile_inst[tg];
+    const InstDesc& d = a.desc[inst];
+    const RefView rv = ref_view(a.ref[inst]);
+    const int local = tg - d.p_tile_begin;
+    const int ty = local / d.p_tiles_x;
+    const int tx = local - ty * d.p_tiles_x;
+    const int x0 = tx * kPairW, y0 = ty * kMarchRows;
+    const int nx = d.nx, ny = d.ny;
+    const int gx = wrapm(x0 - 2 + lane, nx, 64);
+    const int iters = min(kMarchRows, ny - y0) + 4;
+    const uint32_t step = a.ctr_in[0];
+    const S* __restrict__ src = reinterpret_cast<const S*>(a.src) + d.off;
+    S* __restrict__ dst = reinterpret_cast<S*>(a.dst) + d.off;
+    const int64_t col = col_off(d, gx);
+
+    auto load_row = [&](int yi, float out[8]) {
+        const int gy = wrapm(yi, ny, kMarchRows + 4);
+        const S* row = src + (int64_t)gy * d.row;
+        S v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = row[(int64_t)i * d.plane + col];
+        const float E = SPLIT ? *reinterpret_cast<const float*>(reinterpret_cast<const char*>(row) + e_off(d, gx))
+                              : 0.0f;
+        reload<S, SPLIT>(v, E, out);
+    };
+
+    // rows in flight: q[0] is this iteration's input row, q[k] the row k ahead
+    // (one row ahead measured best; two and three cost registers)
+    constexpr int kMarchAhead = 1;
+    float q[kMarchAhead + 1][8];
+#pragma unroll
+    for (int k = 0; k < kMarchAhead; ++k)
+        if (k < iters) load_row(y0 - 2 + k, q[k]);
+    float a_mid[2] = {0.0f, 0.0f}, a_up1[3] = {0.0f, 0.0f, 0.0f}, a_up2[3] = {0.0f, 0.0f, 0.0f};
+    float b_mid[2] = {0.0f, 0.0f}, b_up1[3] = {0.0f, 0.0f, 0.0f}, b_up2[3] = {0.0f, 0.0f, 0.0f};
+    for (int it = 0; it < iters; ++it) {
+        const int yi = y0 - 2 + it;
+        if (it + kMarchAhead < iters) load_row(yi + kMarchAhead, q[kMarchAhead]);
+        float nv[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) nv[i] = q[0][i];
+        // stage 1: row yi - 1 (lanes 1..62 are exact)
+        float s1[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        if (it >= 2) {
+            float g[8];
+            march_gather(nv, a_mid, a_up2, g);
+            const int gy = wrapm(yi - 1, ny, kMarchRows + 4);
+            if (a.apply_shift) apply_shift(g, rv);
+            if (on_wall(d, gx, gy)) boundary(g, d, rv.wall_kd, gx, gy);
+            uint32_t r[4] = {0u, 0u, 0u, 0u};
+            if (SR) sr_words(r, (uint32_t)(d.node_off + (int64_t)gy * nx + gx), step, a.seed);
+            S o[8];
+            float E;
+            relax_round<S, SR, SPLIT>(g, d, rv, r, o, E);
+            reload<S, SPLIT>(o, E, s1);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            a_up2[k] = a_up1[k];
+            a_up1[k] = nv[yup(k)];
+        }
+#pragma unroll
+        for (int k = 0; k < 2; ++k) a_mid[k] = nv[ymid(k)];
+        // stage 2: row yi - 2 on lanes 2..61, stored
+        if (it >= 4) {
+            float g[8];
+            march_gather(s1, b_mid, b_up2, g);
+            const int ox = x0 + lane - 2, oy = yi - 2;
+            if (lane >= 2 && lane <= 61 && ox < nx) {
+                if (on_wall(d, ox, oy)) boundary(g, d, rv.wall_kd, ox, oy);
+                uint32_t r[4] = {0u, 0u, 0u, 0u};
+                if (SR) sr_words(r, (uint32_t)(d.node_off + (int64_t)oy * nx + ox), step + 1u, a.seed);
+                S o[8];
+                float E;
+                relax_round<S, SR, SPLIT>(g, d, rv, r, o, E);
+                S* row = dst + (int64_t)oy * d.row;
+                const int64_t c = col_off(d, ox);
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+                    store_raw<S>(reinterpret_cast<char*>(row + (int64_t)i * d.plane + c), o[i], nontemporal);
+                if (SPLIT) store_one<float, 0>(reinterpret_cast<char*>(row) + e_off(d, ox), E, 0u, nontemporal);
+            }
+        }
+        if (it >= 2) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                b_up2[k] = b_up1[k];
+                b_up1[k] = s1[yup(k)];
+            }
+#pragma unroll
+            for (int k = 0; k < 2; ++k) b_mid[k] = s1[ymid(k)];
+        }
+#pragma unroll
+        for (int k = 0; k < kMarchAhead; ++k)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) q[k][i] = q[k + 1][i];
+    }
+    if (tg == 0 && lane == 0) a.ctr_out[0] = step + 2u;
+}
+
+template <class S, int SPLIT>
+static hipError_t launch_march_s(const Shape& sh, const StepArgs& a, hipStream_t st) {
+    dim3 grid((a.ntiles + 3) / 4), block(256);
+    if (a.sr)
+        hipLaunchKernelGGL((march_kernel<S, 1, SPLIT>), grid, block, 0, st, a, sh.xcd, sh.nt);
+    else
+        hipLaunchKernelGGL((march_kernel<S, 0, SPLIT>), grid, block, 0, st, a, sh.xcd, sh.nt);
+    return hipGetLastError();
+}
+
 hipError_t launch_pair(int storage, const Shape& sh, const StepArgs& a, hipStream_t st) {
     if (a.ntiles <= 0) return hipSuccess;
+    static_assert(pair_marches(2) && !pair_marches(0) && !pair_marches(1) && !pair_marches(3) && !pair_marches(4),
+                  "the dispatch below follows pair_marches");
     switch (storage) {
         case 0: return launch_pair_s<float, 0, pair_rows(0), pair_waves(0)>(sh, a, st);
         case 1: return launch_pair_s<_Float16, 0, pair_rows(1), pair_waves(1)>(sh, a, st);
-        case 2: return launch_pair_s<bf16_bits, 0, pair_rows(2), pair_waves(2)>(sh, a, st);
+        case 2: return launch_march_s<bf16_bits, 0>(sh, a, st);
         case 3: return launch_pair_s<_Float16, 1, pair_rows(3), pair_waves(3)>(sh, a, st);
         case 4: return launch_pair_s<bf16_bits, 1, pair_rows(4), pair_waves(4)>(sh, a, st);
         default: return hipErrorInvalidValue;

@@ -124,8 +124,21 @@ enum StepMode { kPlain = 0, kSnap = 1, kCheck = 2 };
 // (the window is FP32 in LDS for every kind; the 16-bit kinds gain from the
 // smaller halo share of the taller tile, FP32 from the occupancy of the
 // small one).
+// Plain BF16 storage runs the two steps in a y-marching kernel instead (no
+// LDS, no barriers; see the device file): a wavefront per 60-column strip and
+// chunk of kMarchRows output rows.  Measured (8192^2, GLUPS, the other kinds
+// for comparison, FP32 / FP16-SR / BF16-SR / F16_SPLIT / BF16_SPLIT):
+//   LDS tiles (above)            135 / 149 / 175 / 146 / 150
+//   y-marching, 32-row chunks    119 / 127 / 199 / 112 / 109
+//   y-marching, 64 / 128 rows    114 / 122 / 200 / 111 / 129;  102 / 112 / 182 / 102 / 118
+//   32 rows, two / three input rows loaded ahead   120 / 128 / 197 / 106 / 124;  120 / 122 / 184 / 106 / 123
+// so only BF16 marches (32-row chunks, one row ahead).
 constexpr int kPairW = 60;
-__host__ __device__ constexpr int pair_rows(int storage) { return storage == 0 ? 6 : 14; }
+constexpr int kMarchRows = 32;
+__host__ __device__ constexpr bool pair_marches(int storage) { return storage == 2; }
+__host__ __device__ constexpr int pair_rows(int storage) {
+    return pair_marches(storage) ? kMarchRows : (storage == 0 ? 6 : 14);
+}
 __host__ __device__ constexpr int pair_waves(int storage) { return storage == 0 ? 4 : 8; }
 
 struct StepArgs {

@@ -398,6 +398,11 @@ FUSION_CASES = [
     ("heat flux y split", dict(bc_y="heatflux", q_wall=(0, 0, 1e-3, -4e-4)), "f16_split", "nearest"),
     ("square corners", dict(bc_x="isothermal", bc_y="isothermal", wall_bc=(0, 0, 0, "heatflux"),
                             t_wall=(1.0, 1.0, 1.0, 0.0), q_wall=(0, 0, 0, 1e-3)), "f32", "nearest"),
+    # plain BF16 runs the y-marching two-step kernel: walls on both axes there too
+    ("walls x bf16", dict(bc_x="isothermal", t_wall=(1.004, 0.997, 0, 0)), "bf16", "nearest"),
+    ("gradient channel bf16 sr", dict(bc_x="gradient", bc_y="diffuse", grad_x=2e-3), "bf16", "stochastic"),
+    ("square corners bf16", dict(bc_x="isothermal", bc_y="isothermal", wall_bc=(0, 0, 0, "heatflux"),
+                                 t_wall=(1.0, 1.0, 1.0, 0.0), q_wall=(0, 0, 0, 1e-3)), "bf16", "nearest"),
 ]
 
 
@@ -441,19 +446,20 @@ def test_two_step_kernel_bitwise(name, kw, storage, rounding):
     assert max(e) < TOL_STORAGE[storage]
 
 
-@pytest.mark.parametrize("nx,ny", [(2, 2), (3, 2), (5, 3), (61, 13), (65, 14), (121, 25)])
-def test_two_step_kernel_small_and_ragged(nx, ny):
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("nx,ny", [(2, 2), (3, 2), (5, 3), (61, 13), (65, 14), (121, 25), (70, 33)])
+def test_two_step_kernel_small_and_ragged(nx, ny, storage):
     """Tiles larger than the lattice (the window wraps several times), and
-    lattices one node past a tile edge: same bits as single steps, and the
-    oracle."""
+    lattices one node past a tile edge or a 32-row marching chunk: same bits
+    as single steps, and the oracle."""
     case, T0, qx, qy = _random_case(nx, ny, 0.8, 2.0, nx * 7 + ny)
     # five steps (two pairs and a single): the random flux decays by 0.6 per
     # step, and later it nears the FP32 noise floor on the tiniest grids
-    a = _fused_run(case, T0, qx, qy, "f32", "nearest", 1, (5,), 0)[0][0]
-    b = _fused_run(case, T0, qx, qy, "f32", "nearest", 2, (5,), 0)[0][0]
+    a = _fused_run(case, T0, qx, qy, storage, "nearest", 1, (5,), 0)[0][0]
+    b = _fused_run(case, T0, qx, qy, storage, "nearest", 2, (5,), 0)[0][0]
     for u, v in zip(a, b):
-        assert np.array_equal(u, v), (nx, ny)
-    assert max(eps(case, b, oracle_fields(case, 5, T0, qx, qy))) < 1e-5
+        assert np.array_equal(u, v), (nx, ny, storage)
+    assert max(eps(case, b, oracle_fields(case, 5, T0, qx, qy))) < TOL_STORAGE[storage]
 
 
 def test_autotune_choices_cache_and_results(tmp_path, monkeypatch):
