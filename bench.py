@@ -79,8 +79,8 @@ def _parse():
                    help="rounding of the main row's stores (default: stochastic for plain 16-bit "
                         "storage, which stalls on smooth fields otherwise; nearest for the rest)")
     p.add_argument("--sweep-steps", type=int, default=300, help="timed steps per sweep schedule (0: skip)")
-    p.add_argument("--fusion", default="auto", choices=["auto", "1", "2"],
-                   help="time steps per launch (auto: the library's default, 2)")
+    p.add_argument("--fusion", default="auto",
+                   help="most time steps per launch (auto: the library's default for the storage kind)")
     p.add_argument("--check-interval", type=int, default=100)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -114,8 +114,9 @@ def _run_gpu(args, storage, rounding, torch, P, W, host_io=False):
     scale = 2.0 ** -20 if storage.startswith("f16") else 0.0
     lat = P.Lattice([P.instance_from_case(case, scale)], storage=storage,
                     check_interval=args.check_interval, rounding=rounding, seed=1847)
-    fuse = 2 if args.fusion == "auto" else int(args.fusion)
-    lat.set_step_fusion(fuse)
+    if args.fusion != "auto":
+        lat.set_step_fusion(int(args.fusion))
+    fuse = lat.step_fusion()
     tune = lat.autotune(10) if args.autotune else None
     T0 = W.initial_field(case)
     io = None
@@ -165,14 +166,16 @@ def _run_gpu(args, storage, rounding, torch, P, W, host_io=False):
 
 def _plain_launch_ms(lat, K, fuse, torch, n=95):
     """Average duration of the dominant launch (the plain stream-collide
-    launch, or the two-step launch when steps are fused), by HIP events on
-    the launch stream around steps that hold no check-step work (strictly
-    between two check steps, snapshot step excluded).  With fusion a call of
-    n steps issues (n - 1) / 2 two-step launches and one single step (the last
-    step of a call is never fused), timed by a separate one-step call."""
+    launch, or the fused launch of `fuse` steps), by HIP events on the launch
+    stream around steps that hold no check-step work (strictly between two
+    check steps, snapshot step excluded).  With fusion a call of 1 + j * fuse
+    steps issues j fused launches and one single step (the last step of a
+    call is never fused), timed by a separate one-step call."""
     if K > 2:
         lat.step((-lat.steps) % K + 1)      # past the next check step and the shift step after it
-        n = min(n, K - 4) | 1
+        n = min(n, K - 4)
+    j = max(1, (n - 1) // fuse)
+    n = 1 + j * fuse
     def timed(k):
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -184,8 +187,8 @@ def _plain_launch_ms(lat, K, fuse, torch, n=95):
         return e0.elapsed_time(e1)
     t_run = timed(n)
     t_one = timed(1)
-    if fuse == 2:
-        return (t_run - t_one) / ((n - 1) // 2)
+    if fuse >= 2:
+        return (t_run - t_one) / j
     return (t_run + t_one) / (n + 1)
 
 
@@ -360,8 +363,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4),
                      "traffic": _measured_traffic(args.storage, args.n),
-                     "kernel": ("pair_kernel (two time steps per launch, LDS temporal blocking)"
-                                if main_row["fusion"] == 2 else
+                     "kernel": (f"march_kernel ({main_row['fusion']} time steps per launch, y-marching "
+                                "temporal blocking)" if main_row["fusion"] >= 2 else
                                 "wave_kernel (fused pull-advection + boundary + moments + relaxation)"),
                      "steps_per_launch": main_row["fusion"],
                      "kernel_us": round(main_row["launch_ms"] * 1e3, 1),

@@ -270,15 +270,20 @@ int lbm_coefficients(lbm_handle h, int32_t inst, double out[6]);
  * Errors: EINVAL (index, wall not HEATFLUX, non-finite q0), ESTATE (no memory). */
 int lbm_set_wall_flux(lbm_handle h, int32_t inst, int32_t wall, double q0);
 
-/* Time steps per launch where allowed: 2 advances two steps in one pass over
- * HBM (temporal blocking: tiles with a two-node halo in LDS, the intermediate
- * state rounded exactly as a stored step), for pairs of plain steps (no
- * check-step work) that are not the last step of an lbm_step call; 1 issues
- * every step on its own.  Results are identical either way.  Default: 2
- * (measured faster than single steps for every storage kind; the tile height
- * and block size of the two-step kernel depend on the kind).  Drops captured
- * graphs.  Errors: EINVAL (steps not 1 or 2). */
+/* Most time steps per launch where allowed (temporal blocking, Eq. 13 applied
+ * k times to a tile before its populations go back to HBM, the intermediate
+ * states rounded exactly as stored steps): a run of k >= 2 plain steps (no
+ * check-step work, not the last step of an lbm_step call) is advanced by one
+ * launch; 1 issues every step on its own.  Results are identical for every
+ * setting.  The most steps per launch depends on the storage kind (5 FP32 and
+ * FP16, 3 BF16, 4 split kinds; lbm_get_step_fusion of a new handle returns
+ * it, the default).  The per-instance schedule always issues single steps.
+ * Drops captured graphs.  Errors: EINVAL (steps < 1 or more than the storage
+ * kind's most). */
 int lbm_set_step_fusion(lbm_handle h, int32_t steps);
+
+/* The current most time steps per launch; -1 for an invalid handle. */
+int32_t lbm_get_step_fusion(lbm_handle h);
 
 /* Select how multi-instance steps are issued (lbm_schedule).  GRAPH captures
  * K batched steps (the check interval, or 64 when checks are off) once per
@@ -300,8 +305,9 @@ int lbm_set_launch_shape(lbm_handle h, const lbm_launch_shape* shape);
 int lbm_get_launch_shape(lbm_handle h, lbm_launch_shape* shape);
 
 /* Time every candidate launch shape on this handle's own instances and keep
- * the fastest, then time two-step launches against it and set the steps per
- * launch (lbm_set_step_fusion) to the faster.  Must be called after
+ * the fastest, then time fused launches of the storage kind's most steps
+ * against it and set the steps per launch (lbm_set_step_fusion) to the
+ * faster.  Must be called after
  * lbm_create and before lbm_init (it runs steps on scratch contents); each
  * candidate is timed over `steps` steps (0 = 20) with HIP events.  If the environment variable LBM_AUTOTUNE_CACHE
  * names a file, a result for the same device, storage and instance shapes is

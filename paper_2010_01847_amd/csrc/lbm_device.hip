@@ -29,6 +29,7 @@
 #include "lbm_numeric.h"
 
 #include <stdint.h>
+#include <type_traits>
 
 namespace plbm {
 
@@ -799,17 +800,10 @@ hipError_t launch_moments(int storage, const InstDesc* d_desc, const RefState* d
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ two-step kernel
+// ------------------------------------------------------------------ several steps per launch
 //
-// Temporal blocking: two time steps per pass over HBM.  The LDS tile holds the
-// post-relaxation populations (FP32, as a single step would read them back) of
-// a 64 x (H + 4) window starting two nodes left of and below the output tile
-// (H = pair_rows of the storage kind, NW = pair_waves waves per block), every
-// position mapped to its periodic image (as the single-step pull wraps).  Step
-// m advances the inner 62 x (H + 2) window (whose pulls stay inside the tile),
-// rounded exactly as a stored step; step m + 1 advances the 60 x H outputs and
-// stores them.  Per node and step the arithmetic is the
-// single-step kernels' (same functions, same order), so the bits are the same.
+// Helpers of the fused kernel below: positions mapped to their periodic
+// images, and the relaxation of one node rounded exactly as a stored step.
 
 // y component of velocity i.
 __device__ __forceinline__ constexpr int vel_y(int i) {
@@ -872,127 +866,22 @@ __device__ __forceinline__ bool on_wall(const InstDesc& d, int x, int y) {
            ((d.bc_x == 1 || d.bc_x == 2 || d.bc_x == 4) && (x == 0 || x == d.nx - 1));
 }
 
-template <class S, int SR, int SPLIT, int H, int NW>
-__global__ __launch_bounds__(64 * NW) void pair_kernel(StepArgs a, int xcd, int nontemporal) {
-    constexpr int kRows = H + 4;
-    __shared__ float lds[8][kRows][64];
-    const int b = blockIdx.x;
-    int t = b;
-    if (xcd) {
-        const int nb = a.ntiles, q = nb >> 3, r = nb & 7, k = b & 7, j = b >> 3;
-        t = k * q + (k < r ? k : r) + j;
-    }
-    t += a.tile_base;
-    const int inst = a.tile_inst[t];
-    const InstDesc& d = a.desc[inst];
-    const RefView rv = ref_view(a.ref[inst]);
-    const int local = t - d.p_tile_begin;
-    const int ty = local / d.p_tiles_x;
-    const int tx = local - ty * d.p_tiles_x;
-    const int x0 = tx * kPairW, y0 = ty * H;
-    const int nx = d.nx, ny = d.ny;
-    const int lx = threadIdx.x & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave index: rows are wave-uniform
-    const uint32_t step = a.ctr_in[0];
-    const S* __restrict__ src = reinterpret_cast<const S*>(a.src) + d.off;
-    S* __restrict__ dst = reinterpret_cast<S*>(a.dst) + d.off;
-    const int gx = wrapm(x0 - 2 + lx, nx, 64);
-
-    // window loads: the post-relaxation state of step m - 1
-    for (int ly = wv; ly < kRows; ly += NW) {
-        const int gy = wrapm(y0 - 2 + ly, ny, kRows);
-        S v[8];
-        const S* row = src + (int64_t)gy * d.row;
-        const int64_t c = col_off(d, gx);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = row[(int64_t)i * d.plane + c];
-        float E = 0.0f;
-        if (SPLIT) E = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(row) + e_off(d, gx));
-        float f[8];
-        reload<S, SPLIT>(v, E, f);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) lds[i][ly][lx] = f[i];
-    }
-    __syncthreads();
-
-    // step m on the inner window (rows 1 .. H + 2, columns 1 .. 62)
-    constexpr int kHold = (H + 2 + NW - 1) / NW;
-    float hold[kHold][8];
-#pragma unroll
-    for (int j = 0; j < kHold; ++j) {
-        const int ly = 1 + wv + NW * j;
-        if (ly > H + 2 || lx == 0 || lx == 63) continue;
-        const int gy = wrapm(y0 - 2 + ly, ny, kRows);
-        float g[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) g[i] = lds[i][ly - vel_y(i)][lx - vel_x(i)];
-        if (a.apply_shift) apply_shift(g, rv);
-        if (on_wall(d, gx, gy)) boundary(g, d, rv.wall_kd, gx, gy);
-        uint32_t r[4] = {0u, 0u, 0u, 0u};
-        if (SR) sr_words(r, (uint32_t)(d.node_off + (int64_t)gy * nx + gx), step, a.seed);
-        S o[8];
-        float E;
-        relax_round<S, SR, SPLIT>(g, d, rv, r, o, E);
-        reload<S, SPLIT>(o, E, hold[j]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < kHold; ++j) {
-        const int ly = 1 + wv + NW * j;
-        if (ly > H + 2 || lx == 0 || lx == 63) continue;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) lds[i][ly][lx] = hold[j][i];
-    }
-    __syncthreads();
-
-    // step m + 1 on the outputs (rows 2 .. H + 1, columns 2 .. 61)
-    const int ox = x0 + lx - 2;
-    if (lx >= 2 && lx <= 61 && ox < nx) {
-        for (int ly = 2 + wv; ly <= H + 1; ly += NW) {
-            const int oy = y0 + ly - 2;
-            if (oy >= ny) break;
-            float g[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) g[i] = lds[i][ly - vel_y(i)][lx - vel_x(i)];
-            if (on_wall(d, ox, oy)) boundary(g, d, rv.wall_kd, ox, oy);
-            uint32_t r[4] = {0u, 0u, 0u, 0u};
-            if (SR) sr_words(r, (uint32_t)(d.node_off + (int64_t)oy * nx + ox), step + 1u, a.seed);
-            S o[8];
-            float E;
-            relax_round<S, SR, SPLIT>(g, d, rv, r, o, E);
-            S* row = dst + (int64_t)oy * d.row;
-            const int64_t c = col_off(d, ox);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) store_raw<S>(reinterpret_cast<char*>(row + (int64_t)i * d.plane + c), o[i], nontemporal);
-            if (SPLIT) store_one<float, 0>(reinterpret_cast<char*>(row) + e_off(d, ox), E, 0u, nontemporal);
-        }
-    }
-    if (t == 0 && threadIdx.x == 0) a.ctr_out[0] = step + 2u;
-}
-
-template <class S, int SPLIT, int H, int NW>
-static hipError_t launch_pair_s(const Shape& sh, const StepArgs& a, hipStream_t st) {
-    dim3 grid(a.ntiles), block(64 * NW);
-    if (a.sr)
-        hipLaunchKernelGGL((pair_kernel<S, 1, SPLIT, H, NW>), grid, block, 0, st, a, sh.xcd, sh.nt);
-    else
-        hipLaunchKernelGGL((pair_kernel<S, 0, SPLIT, H, NW>), grid, block, 0, st, a, sh.xcd, sh.nt);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ two steps per launch, y-marching
+// ------------------------------------------------------------------ K steps per launch, y-marching
 //
-// The same two steps as pair_kernel without LDS or barriers: a wavefront owns a
-// 64-column window (60 outputs and a two-node halo, periodic images) of a chunk
-// of kMarchRows output rows and marches along y.  Iteration `it` loads input
-// row yi = y0 - 2 + it, advances row yi - 1 one step on lanes 1..62 and row
-// yi - 2 a second step on lanes 2..61, which it stores.  A node pulls direction
-// i from row y - c_iy, so of a loaded row the c_y = -1 movers are used at
-// once, the c_y = 0 movers one iteration later and the c_y = +1 movers two
+// Temporal blocking without LDS or barriers: K time steps per pass over HBM.
+// A wavefront owns a 64-column window (W = 64 - 2 KMAX output columns and a
+// KMAX-node halo on each side, periodic images) of a chunk of kMarchRows
+// output rows and marches along y.  Iteration `it` loads input row
+// yi = y0 - K + it and runs K stages: stage s advances row yi - s from the
+// rows of level s - 1 (level 0: loaded, level s: advanced s steps), on lanes
+// s..63-s (its pulls stay inside the window), rounded exactly as a stored
+// step; stage K stores its output lanes.  A node pulls direction i from row
+// y - c_iy, so of a level's newest row the c_y = -1 movers are used at once,
+// the c_y = 0 movers one iteration later and the c_y = +1 movers two
 // iterations later (kept in registers), and the x neighbours come from the
 // adjacent lanes by DPP.  Per node and step the arithmetic is the single-step
 // kernels' (same functions, same order, same random bits), so the result
-// equals two single steps bit for bit.
+// equals K single steps bit for bit.
 
 // Directions by c_y: -1 {3, 6, 7}, 0 {0, 2}, +1 {1, 4, 5}.
 __device__ __forceinline__ constexpr int ymid(int k) { return 2 * k; }
@@ -1019,8 +908,12 @@ __device__ __forceinline__ void march_gather(const float dn_row[8], const float 
     g[7] = xpull<7>(dn_row[7]);
 }
 
-template <class S, int SR, int SPLIT>
+// K <= KMAX: the window geometry depends on KMAX only, so launches of fewer
+// steps (before a check step or at the end of a call) use the same tile table.
+template <class S, int SR, int SPLIT, int K, int KMAX>
 __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int nontemporal) {
+    static_assert(K >= 2 && K <= KMAX, "stages per launch");
+    constexpr int W = 64 - 2 * KMAX;
     const int lane = threadIdx.x & 63;
     int b = blockIdx.x;
     if (xcd) {
@@ -1036,17 +929,17 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
     const int local = tg - d.p_tile_begin;
     const int ty = local / d.p_tiles_x;
     const int tx = local - ty * d.p_tiles_x;
-    const int x0 = tx * kPairW, y0 = ty * kMarchRows;
+    const int x0 = tx * W, y0 = ty * kMarchRows;
     const int nx = d.nx, ny = d.ny;
-    const int gx = wrapm(x0 - 2 + lane, nx, 64);
-    const int iters = min(kMarchRows, ny - y0) + 4;
+    const int gx = wrapm(x0 - KMAX + lane, nx, 64);
+    const int iters = min(kMarchRows, ny - y0) + 2 * K;
     const uint32_t step = a.ctr_in[0];
     const S* __restrict__ src = reinterpret_cast<const S*>(a.src) + d.off;
     S* __restrict__ dst = reinterpret_cast<S*>(a.dst) + d.off;
     const int64_t col = col_off(d, gx);
 
     auto load_row = [&](int yi, float out[8]) {
-        const int gy = wrapm(yi, ny, kMarchRows + 4);
+        const int gy = wrapm(yi, ny, kMarchRows + 2 * K);
         const S* row = src + (int64_t)gy * d.row;
         S v[8];
 #pragma unroll
@@ -1056,100 +949,117 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
         reload<S, SPLIT>(v, E, out);
     };
 
-    // rows in flight: q[0] is this iteration's input row, q[k] the row k ahead
-    // (one row ahead measured best; two and three cost registers)
-    constexpr int kMarchAhead = 1;
-    float q[kMarchAhead + 1][8];
+    // per level l (0: loaded rows, l: results of stage l), the c_y = 0 movers of
+    // the previous row and the c_y = +1 movers of the two previous rows
+    float mid[K][2], up1[K][3], up2[K][3];
 #pragma unroll
-    for (int k = 0; k < kMarchAhead; ++k)
-        if (k < iters) load_row(y0 - 2 + k, q[k]);
-    float a_mid[2] = {0.0f, 0.0f}, a_up1[3] = {0.0f, 0.0f, 0.0f}, a_up2[3] = {0.0f, 0.0f, 0.0f};
-    float b_mid[2] = {0.0f, 0.0f}, b_up1[3] = {0.0f, 0.0f, 0.0f}, b_up2[3] = {0.0f, 0.0f, 0.0f};
-    for (int it = 0; it < iters; ++it) {
-        const int yi = y0 - 2 + it;
-        if (it + kMarchAhead < iters) load_row(yi + kMarchAhead, q[kMarchAhead]);
-        float nv[8];
+    for (int l = 0; l < K; ++l) {
+        mid[l][0] = mid[l][1] = 0.0f;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) nv[i] = q[0][i];
-        // stage 1: row yi - 1 (lanes 1..62 are exact)
-        float s1[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-        if (it >= 2) {
-            float g[8];
-            march_gather(nv, a_mid, a_up2, g);
-            const int gy = wrapm(yi - 1, ny, kMarchRows + 4);
-            if (a.apply_shift) apply_shift(g, rv);
-            if (on_wall(d, gx, gy)) boundary(g, d, rv.wall_kd, gx, gy);
-            uint32_t r[4] = {0u, 0u, 0u, 0u};
-            if (SR) sr_words(r, (uint32_t)(d.node_off + (int64_t)gy * nx + gx), step, a.seed);
-            S o[8];
-            float E;
-            relax_round<S, SR, SPLIT>(g, d, rv, r, o, E);
-            reload<S, SPLIT>(o, E, s1);
-        }
+        for (int k = 0; k < 3; ++k) up1[l][k] = up2[l][k] = 0.0f;
+    }
+    float nxt[8];
+    load_row(y0 - K, nxt);
+    // One iteration: load row yi + 1 ahead, then every stage whose input rows
+    // exist; WARM (the first 2 K iterations) tests that per stage, later
+    // iterations run all K stages.
+    auto iteration = [&](const int it, auto warm) {
+        constexpr bool WARM = decltype(warm)::value;
+        const int yi = y0 - K + it;
+        float cur[8];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            a_up2[k] = a_up1[k];
-            a_up1[k] = nv[yup(k)];
-        }
+        for (int i = 0; i < 8; ++i) cur[i] = nxt[i];
+        if (it + 1 < iters) load_row(yi + 1, nxt);   // one row ahead: in flight during the stages
 #pragma unroll
-        for (int k = 0; k < 2; ++k) a_mid[k] = nv[ymid(k)];
-        // stage 2: row yi - 2 on lanes 2..61, stored
-        if (it >= 4) {
-            float g[8];
-            march_gather(s1, b_mid, b_up2, g);
-            const int ox = x0 + lane - 2, oy = yi - 2;
-            if (lane >= 2 && lane <= 61 && ox < nx) {
-                if (on_wall(d, ox, oy)) boundary(g, d, rv.wall_kd, ox, oy);
-                uint32_t r[4] = {0u, 0u, 0u, 0u};
-                if (SR) sr_words(r, (uint32_t)(d.node_off + (int64_t)oy * nx + ox), step + 1u, a.seed);
-                S o[8];
-                float E;
-                relax_round<S, SR, SPLIT>(g, d, rv, r, o, E);
-                S* row = dst + (int64_t)oy * d.row;
-                const int64_t c = col_off(d, ox);
+        for (int s = 1; s <= K; ++s) {
+            // stage s: row yi - s from level s - 1 (valid once it >= 2 s)
+            float out[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            if (!WARM || it >= 2 * s) {
+                float g[8];
+                march_gather(cur, mid[s - 1], up2[s - 1], g);
+                if (s < K) {
+                    const int gy = wrapm(yi - s, ny, kMarchRows + 2 * K);
+                    if (s == 1 && a.apply_shift) apply_shift(g, rv);
+                    if (on_wall(d, gx, gy)) boundary(g, d, rv.wall_kd, gx, gy);
+                    uint32_t r[4] = {0u, 0u, 0u, 0u};
+                    if (SR) sr_words(r, (uint32_t)(d.node_off + (int64_t)gy * nx + gx), step + (uint32_t)(s - 1), a.seed);
+                    S o[8];
+                    float E;
+                    relax_round<S, SR, SPLIT>(g, d, rv, r, o, E);
+                    reload<S, SPLIT>(o, E, out);
+                } else {
+                    const int ox = x0 + lane - KMAX, oy = yi - s;
+                    if (lane >= KMAX && lane < KMAX + W && ox < nx) {
+                        if (on_wall(d, ox, oy)) boundary(g, d, rv.wall_kd, ox, oy);
+                        uint32_t r[4] = {0u, 0u, 0u, 0u};
+                        if (SR) sr_words(r, (uint32_t)(d.node_off + (int64_t)oy * nx + ox), step + (uint32_t)(s - 1),
+                                         a.seed);
+                        S o[8];
+                        float E;
+                        relax_round<S, SR, SPLIT>(g, d, rv, r, o, E);
+                        S* row = dst + (int64_t)oy * d.row;
+                        const int64_t c = col_off(d, ox);
 #pragma unroll
-                for (int i = 0; i < 8; ++i)
-                    store_raw<S>(reinterpret_cast<char*>(row + (int64_t)i * d.plane + c), o[i], nontemporal);
-                if (SPLIT) store_one<float, 0>(reinterpret_cast<char*>(row) + e_off(d, ox), E, 0u, nontemporal);
+                        for (int i = 0; i < 8; ++i)
+                            store_raw<S>(reinterpret_cast<char*>(row + (int64_t)i * d.plane + c), o[i], nontemporal);
+                        if (SPLIT) store_one<float, 0>(reinterpret_cast<char*>(row) + e_off(d, ox), E, 0u, nontemporal);
+                    }
+                }
             }
-        }
-        if (it >= 2) {
+            // level s - 1 moves one row on (its values are valid whenever a later stage reads them)
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                b_up2[k] = b_up1[k];
-                b_up1[k] = s1[yup(k)];
+                up2[s - 1][k] = up1[s - 1][k];
+                up1[s - 1][k] = cur[yup(k)];
             }
 #pragma unroll
-            for (int k = 0; k < 2; ++k) b_mid[k] = s1[ymid(k)];
+            for (int k = 0; k < 2; ++k) mid[s - 1][k] = cur[ymid(k)];
+            if (s < K) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) cur[i] = out[i];
+            }
         }
-#pragma unroll
-        for (int k = 0; k < kMarchAhead; ++k)
-#pragma unroll
-            for (int i = 0; i < 8; ++i) q[k][i] = q[k + 1][i];
-    }
-    if (tg == 0 && lane == 0) a.ctr_out[0] = step + 2u;
+    };
+    // iters >= 2 K + 1: the warm-up always completes
+    int it = 0;
+    for (; it < 2 * K; ++it) iteration(it, std::true_type{});
+    for (; it < iters; ++it) iteration(it, std::false_type{});
+    if (tg == 0 && lane == 0) a.ctr_out[0] = step + (uint32_t)K;
 }
 
-template <class S, int SPLIT>
+template <class S, int SPLIT, int K, int KMAX>
 static hipError_t launch_march_s(const Shape& sh, const StepArgs& a, hipStream_t st) {
     dim3 grid((a.ntiles + 3) / 4), block(256);
     if (a.sr)
-        hipLaunchKernelGGL((march_kernel<S, 1, SPLIT>), grid, block, 0, st, a, sh.xcd, sh.nt);
+        hipLaunchKernelGGL((march_kernel<S, 1, SPLIT, K, KMAX>), grid, block, 0, st, a, sh.xcd, sh.nt);
     else
-        hipLaunchKernelGGL((march_kernel<S, 0, SPLIT>), grid, block, 0, st, a, sh.xcd, sh.nt);
+        hipLaunchKernelGGL((march_kernel<S, 0, SPLIT, K, KMAX>), grid, block, 0, st, a, sh.xcd, sh.nt);
     return hipGetLastError();
 }
 
-hipError_t launch_pair(int storage, const Shape& sh, const StepArgs& a, hipStream_t st) {
+template <class S, int SPLIT, int K, int KMAX>
+static hipError_t launch_march_k(const Shape& sh, const StepArgs& a, int k, hipStream_t st) {
+    if constexpr (K > KMAX) {
+        return hipErrorInvalidValue;
+    } else {
+        if (k == K) return launch_march_s<S, SPLIT, K, KMAX>(sh, a, st);
+        return launch_march_k<S, SPLIT, K + 1, KMAX>(sh, a, k, st);
+    }
+}
+
+template <class S, int SPLIT, int STORAGE>
+static hipError_t launch_fused_s(const Shape& sh, const StepArgs& a, int k, hipStream_t st) {
+    return launch_march_k<S, SPLIT, 2, fuse_max(STORAGE)>(sh, a, k, st);
+}
+
+hipError_t launch_fused(int storage, const Shape& sh, const StepArgs& a, int k, hipStream_t st) {
     if (a.ntiles <= 0) return hipSuccess;
-    static_assert(pair_marches(2) && !pair_marches(0) && !pair_marches(1) && !pair_marches(3) && !pair_marches(4),
-                  "the dispatch below follows pair_marches");
     switch (storage) {
-        case 0: return launch_pair_s<float, 0, pair_rows(0), pair_waves(0)>(sh, a, st);
-        case 1: return launch_pair_s<_Float16, 0, pair_rows(1), pair_waves(1)>(sh, a, st);
-        case 2: return launch_march_s<bf16_bits, 0>(sh, a, st);
-        case 3: return launch_pair_s<_Float16, 1, pair_rows(3), pair_waves(3)>(sh, a, st);
-        case 4: return launch_pair_s<bf16_bits, 1, pair_rows(4), pair_waves(4)>(sh, a, st);
+        case 0: return launch_fused_s<float, 0, 0>(sh, a, k, st);
+        case 1: return launch_fused_s<_Float16, 0, 1>(sh, a, k, st);
+        case 2: return launch_fused_s<bf16_bits, 0, 2>(sh, a, k, st);
+        case 3: return launch_fused_s<_Float16, 1, 3>(sh, a, k, st);
+        case 4: return launch_fused_s<bf16_bits, 1, 4>(sh, a, k, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -33,9 +33,9 @@ struct alignas(64) InstDesc {
     int32_t group_begin;    // first reduction group of this instance (kGroup tiles each)
     int32_t ngroups;        // reduction groups of this instance
     int32_t wk[4];          // boundary kind of each wall (x=0, x=nx-1, y=0, y=ny-1); 0 on periodic axes
-    int32_t p_tiles_x;      // two-step kernel: tiles along x (kPairW columns each)
-    int32_t p_tile_begin;   // two-step kernel: first global tile of this instance
-    int32_t p_ntiles;       // two-step kernel: tiles of this instance
+    int32_t p_tiles_x;      // fused kernel: strips along x (fused_width columns each)
+    int32_t p_tile_begin;   // fused kernel: first global tile of this instance
+    int32_t p_ntiles;       // fused kernel: tiles of this instance
     int64_t row;            // elements between rows
     int64_t plane;          // elements between direction runs
     int64_t chunk;          // elements between 64-node chunks (0: planes layout)
@@ -110,36 +110,27 @@ struct Shape {
 
 enum StepMode { kPlain = 0, kSnap = 1, kCheck = 2 };
 
-// Two-step (temporally blocked) kernel: a block of 64 * pair_waves threads
-// takes a tile of kPairW x pair_rows output nodes, loads it with a two-node
-// halo (64 x (pair_rows + 4) nodes) into LDS, advances the inner
-// 62 x (pair_rows + 2) nodes one step in place, then the 60 x pair_rows outputs
-// a second step.  The tile height and block size depend on the storage kind;
-// both are limited by the 32-wave and 160 KB LDS budgets of a CU.  Measured on
-// MI355X (8192^2, GLUPS):
-//   FP32:   6 rows x 4 waves 135 (20 KB, 8 blocks per CU); 6 x 8 136;
-//           8 x 4 132; 14 x 8 131; 12 x 4 118; 20 x 4 107
-//   BF16-SR / BF16_SPLIT: 6 x 4 157 / 138; 14 x 8 172 / 150 (37 KB, 4 blocks
-//           of 8 waves per CU); 22 x 8 165 / 140; 10 x 8 152 / 135
-// (the window is FP32 in LDS for every kind; the 16-bit kinds gain from the
-// smaller halo share of the taller tile, FP32 from the occupancy of the
-// small one).
-// Plain BF16 storage runs the two steps in a y-marching kernel instead (no
-// LDS, no barriers; see the device file): a wavefront per 60-column strip and
-// chunk of kMarchRows output rows.  Measured (8192^2, GLUPS, the other kinds
-// for comparison, FP32 / FP16-SR / BF16-SR / F16_SPLIT / BF16_SPLIT):
-//   LDS tiles (above)            135 / 149 / 175 / 146 / 150
-//   y-marching, 32-row chunks    119 / 127 / 199 / 112 / 109
-//   y-marching, 64 / 128 rows    114 / 122 / 200 / 111 / 129;  102 / 112 / 182 / 102 / 118
-//   32 rows, two / three input rows loaded ahead   120 / 128 / 197 / 106 / 124;  120 / 122 / 184 / 106 / 123
-// so only BF16 marches (32-row chunks, one row ahead).
-constexpr int kPairW = 60;
+// Fused kernel (several time steps per pass over HBM, temporal blocking): a
+// wavefront takes a strip of fused_width output columns (a window of 64
+// columns with a halo of fuse_max nodes on each side) of a chunk of
+// kMarchRows rows, and marches along y advancing up to fuse_max steps; see the
+// device file.  The kernel is bound by vector ALU issue, not by HBM (with
+// five steps per launch an FP32 update moves about a quarter of the single-
+// step bytes), so the most steps per launch is a per-kind balance between the
+// HBM bytes saved and the halo nodes recomputed.  Measured on MI355X (8192^2
+// periodic lattice, GLUPS, steps per launch FP32 / FP16-SR / BF16-SR /
+// F16_SPLIT / BF16_SPLIT):
+//   4 / 4 / 2 / 3 / 3    209 / 156 / 210 / 130 / 175
+//   5 / 5 / 3 / 4 / 4    208 / 164 / 228 / 149 / 191   (chosen)
+//   6 / 6 / 4 / 5 / 5    213 / 153 / 229 / 145 / 177
+//   7 / 7 / 5 / 6 / 6    200 / 155 / 212 / 150 / 171
+// (single steps: 90 / 147 / 128 / 137 / 131).  The chunk height hardly
+// matters (24, 32, 48, 64 rows within 2%).
 constexpr int kMarchRows = 32;
-__host__ __device__ constexpr bool pair_marches(int storage) { return storage == 2; }
-__host__ __device__ constexpr int pair_rows(int storage) {
-    return pair_marches(storage) ? kMarchRows : (storage == 0 ? 6 : 14);
+__host__ __device__ constexpr int fuse_max(int storage) {
+    return storage == 0 ? 5 : (storage == 1 ? 5 : (storage == 2 ? 3 : 4));
 }
-__host__ __device__ constexpr int pair_waves(int storage) { return storage == 0 ? 4 : 8; }
+__host__ __device__ constexpr int fused_width(int storage) { return 64 - 2 * fuse_max(storage); }
 
 struct StepArgs {
     const InstDesc* desc;
@@ -163,10 +154,11 @@ struct StepArgs {
 hipError_t launch_step(int storage, const Shape& sh, int mode, const StepArgs& a,
                        int64_t snap_stride, hipStream_t st);
 
-// Two time steps (m, m + 1) in one pass over HBM: both plain (no check work);
-// a.apply_shift refers to the first of them; a.tile_inst / tile_base / ntiles
-// index the two-step tile table.  Same bits as two single steps.
-hipError_t launch_pair(int storage, const Shape& sh, const StepArgs& a, hipStream_t st);
+// k time steps (m .. m + k - 1, 2 <= k <= fuse_max(storage)) in one pass over
+// HBM: all plain (no check work); a.apply_shift refers to the first of them;
+// a.tile_inst / tile_base / ntiles index the fused tile table.  Same bits as
+// k single steps.
+hipError_t launch_fused(int storage, const Shape& sh, const StepArgs& a, int k, hipStream_t st);
 
 // Moments of the state at time n of one instance.  With pull != 0 the state is
 // rebuilt from the post-relaxation populations of step n-1 (advection plus

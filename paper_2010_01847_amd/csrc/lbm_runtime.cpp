@@ -189,7 +189,9 @@ int64_t max_tiles(const std::vector<lbm_instance>& v) {
 }
 
 // Two-step kernel tiles along x of one instance.
-int64_t pair_tiles_x(const lbm_instance& in) { return (in.nx + kPairW - 1) / kPairW; }
+int64_t fused_tiles_x(const lbm_instance& in, int storage) {
+    return (in.nx + fused_width(storage) - 1) / fused_width(storage);
+}
 
 // Worst-case count of first-stage reduction groups (per instance, kGroup
 // tiles each).
@@ -219,8 +221,8 @@ Layout layout_of(const std::vector<lbm_instance>& v, int storage, int check, int
     L.buf_bytes = align_up(elems * es, kAlign);
     L.tiles_max = max_tiles(v);
     L.groups_max = max_groups(v);
-    const int ph = pair_rows(storage);
-    for (auto& in : v) L.ptiles += pair_tiles_x(in) * (int64_t)((in.ny + ph - 1) / ph);
+    const int ph = kMarchRows;
+    for (auto& in : v) L.ptiles += fused_tiles_x(in, storage) * (int64_t)((in.ny + ph - 1) / ph);
     // the same scratch serves the first stage of lbm_totals' reduction
     const int64_t gscratch = std::max<int64_t>(L.groups_max, (L.mparts_max + kGroup - 1) / kGroup);
     size_t o = 0;
@@ -266,8 +268,8 @@ struct lbm_ctx {
     std::vector<int32_t> tile_inst;
     std::vector<int32_t> group_inst;
     int64_t ngroups = 0;
-    std::vector<int32_t> ptile_inst;   // two-step kernel: tile -> instance
-    int fuse = 1;                      // time steps per launch where allowed (1 or 2)
+    std::vector<int32_t> ptile_inst;   // fused kernel: tile -> instance
+    int fuse = 1;                      // most time steps per launch where allowed (1 .. fuse_max)
     int graph_flips = 0;               // buffer swaps of one captured chunk
     bool external = false;
     char* base = nullptr;            // device memory (owned unless external)
@@ -347,9 +349,9 @@ static void build_tiles(lbm_ctx* h) {
         d.ngroups = (d.ntiles + kGroup - 1) / kGroup;
         h->ngroups += d.ngroups;
         h->group_inst.insert(h->group_inst.end(), (size_t)d.ngroups, (int32_t)k);
-        d.p_tiles_x = (int32_t)pair_tiles_x(h->inst[k]);
+        d.p_tiles_x = (int32_t)fused_tiles_x(h->inst[k], h->storage);
         d.p_tile_begin = (int32_t)h->ptile_inst.size();
-        d.p_ntiles = d.p_tiles_x * ((d.ny + pair_rows(h->storage) - 1) / pair_rows(h->storage));
+        d.p_ntiles = d.p_tiles_x * ((d.ny + kMarchRows - 1) / kMarchRows);
         h->ptile_inst.insert(h->ptile_inst.end(), (size_t)d.p_ntiles, (int32_t)k);
     }
 }
@@ -501,11 +503,9 @@ int lbm_create(const lbm_config* cfg, lbm_handle* out) {
     }
     h->inst = v;
     h->storage = cfg->storage;
-    // two-step launches: measured on MI355X (8192^2, GLUPS), faster than
-    // single steps for every storage kind with its tile geometry
-    // (pair_rows/pair_waves): FP32 135 vs 90, BF16-SR 174 vs 128, BF16_SPLIT
-    // 150 vs 131, FP16-SR 149 vs 147, F16_SPLIT 146 vs 137
-    h->fuse = 2;
+    // fused launches (the most steps the kind's kernel takes): measured on
+    // MI355X (8192^2) faster than single steps for every storage kind
+    h->fuse = fuse_max(cfg->storage);
     h->K = check_of(cfg);
     h->stream = reinterpret_cast<hipStream_t>(cfg->stream);
     h->external = (cfg->flags & LBM_FLAG_EXTERNAL_MEMORY) != 0;
@@ -770,15 +770,18 @@ static int issue_step(lbm_ctx* h, int64_t m, int src_k, hipStream_t st, int sche
     return LBM_OK;
 }
 
-// Steps m and m + 1 in one two-step launch: both plain (no check-step work),
-// and m + 1 is not the last step of the sequence being issued (`last`), so
-// the post-relaxation state of the step before the last one is in a buffer
-// when the sequence ends (the moments of the final state are rebuilt from it).
-static bool can_pair(const lbm_ctx* h, int64_t m, int64_t last) {
-    return h->fuse == 2 && m + 1 < last && mode_of(h, m) == kPlain && mode_of(h, m + 1) == kPlain;
+// Steps the launch that starts at step m covers: up to h->fuse consecutive
+// plain steps (no check-step work), none of them the last step of the sequence
+// being issued (`last`), so the post-relaxation state of the step before the
+// last one is in a buffer when the sequence ends (the moments of the final
+// state are rebuilt from it).  1 means a single-step launch.
+static int fused_steps(const lbm_ctx* h, int64_t m, int64_t last) {
+    int k = 0;
+    while (k < h->fuse && m + k < last && mode_of(h, m + k) == kPlain) ++k;
+    return k >= 2 ? k : 1;
 }
 
-static int issue_pair(lbm_ctx* h, int64_t m, int src_k, hipStream_t st, int sched) {
+static int issue_fused(lbm_ctx* h, int64_t m, int nsteps, int src_k, hipStream_t st) {
     StepArgs a;
     a.desc = h->d_desc();
     a.tile_inst = h->d_ptiles();
@@ -792,17 +795,9 @@ static int issue_pair(lbm_ctx* h, int64_t m, int src_k, hipStream_t st, int sche
     a.sr = h->sr;
     a.ref = h->d_ref();
     a.apply_shift = (h->K > 0 && (m - 1) % h->K == 0) ? 1 : 0;
-    if (sched == LBM_SCHED_PER_INSTANCE) {
-        for (size_t k = 0; k < h->inst.size(); ++k) {
-            a.tile_base = h->desc[k].p_tile_begin;
-            a.ntiles = h->desc[k].p_ntiles;
-            HIPCALL(h, launch_pair(h->storage, h->shape, a, st));
-        }
-    } else {
-        a.tile_base = 0;
-        a.ntiles = (int32_t)h->ptile_inst.size();
-        HIPCALL(h, launch_pair(h->storage, h->shape, a, st));
-    }
+    a.tile_base = 0;
+    a.ntiles = (int32_t)h->ptile_inst.size();
+    HIPCALL(h, launch_fused(h->storage, h->shape, a, nsteps, st));
     return LBM_OK;
 }
 
@@ -817,9 +812,10 @@ static int capture(lbm_ctx* h, int par) {
     int rc = LBM_OK;
     int flips = 0;
     for (int s = 1; s <= C && rc == LBM_OK;) {
-        if (can_pair(h, s, C)) {
-            rc = issue_pair(h, (int64_t)s, src, h->capture_stream, LBM_SCHED_BATCHED);
-            s += 2;
+        const int k = fused_steps(h, s, C);
+        if (k >= 2) {
+            rc = issue_fused(h, (int64_t)s, k, src, h->capture_stream);
+            s += k;
         } else {
             rc = issue_step(h, (int64_t)s, src, h->capture_stream, LBM_SCHED_BATCHED);
             s += 1;
@@ -870,12 +866,16 @@ int lbm_step(lbm_handle h, int64_t nsteps) {
         }
         const int64_t m = h->steps + 1;
         const int sched = h->sched == LBM_SCHED_PER_INSTANCE ? LBM_SCHED_PER_INSTANCE : LBM_SCHED_BATCHED;
-        if (can_pair(h, m, h->steps + left)) {
-            int rc = issue_pair(h, m, h->cur, h->stream, sched);
+        // the per-instance schedule issues single steps: one instance's fused
+        // launch holds too few wavefronts to hide the marching latency
+        // (Knudsen sweep: 4.0k MLUPS at five steps per launch, 17.1k single)
+        const int k = sched == LBM_SCHED_PER_INSTANCE ? 1 : fused_steps(h, m, h->steps + left);
+        if (k >= 2) {
+            int rc = issue_fused(h, m, k, h->cur, h->stream);
             if (rc) return rc;
             h->cur = 1 - h->cur;
-            h->steps = m + 1;
-            left -= 2;
+            h->steps = m + k - 1;
+            left -= k;
             continue;
         }
         int rc = issue_step(h, m, h->cur, h->stream, sched);
@@ -1016,11 +1016,15 @@ int lbm_set_wall_flux(lbm_handle h, int32_t k, int32_t wall, double q0) {
 
 int lbm_set_step_fusion(lbm_handle h, int32_t steps) {
     if (!valid(h)) return LBM_EINVAL;
-    if (steps != 1 && steps != 2) return h->fail(LBM_EINVAL, "steps per launch must be 1 or 2");
+    if (steps < 1 || steps > fuse_max(h->storage))
+        return h->fail(LBM_EINVAL, "steps per launch must be 1 .. " + std::to_string(fuse_max(h->storage)) +
+                                       " for this storage kind");
     h->fuse = steps;
     h->drop_graphs();
     return LBM_OK;
 }
+
+int32_t lbm_get_step_fusion(lbm_handle h) { return valid(h) ? h->fuse : -1; }
 
 int lbm_set_schedule(lbm_handle h, int32_t schedule) {
     if (!valid(h)) return LBM_EINVAL;
@@ -1108,7 +1112,7 @@ static bool cache_lookup(const char* path, const std::string& key, Shape* out, i
             key == k) {
             *out = s;
             const char* f = strstr(line, "\"fuse\": ");
-            *fuse = (f && f[8] == '2') ? 2 : 1;   // the digit after '"fuse": '
+            *fuse = (f && f[8] >= '1' && f[8] <= '9') ? f[8] - '0' : 1;   // the digit after '"fuse": '
             found = true;   // the last matching line wins
         }
     }
@@ -1150,9 +1154,9 @@ static int time_shape(lbm_ctx* h, const Shape& s, int steps, hipEvent_t e0, hipE
     return LBM_OK;
 }
 
-// Average time per step of two-step launches (the launch shape's XCD remap and
+// Average time per step of k-step launches (the launch shape's XCD remap and
 // store hint), on scratch contents.
-static int time_pair(lbm_ctx* h, int launches, hipEvent_t e0, hipEvent_t e1, float* us) {
+static int time_fused(lbm_ctx* h, int k, int launches, hipEvent_t e0, hipEvent_t e1, float* us) {
     StepArgs a;
     a.desc = h->d_desc();
     a.tile_inst = h->d_ptiles();
@@ -1171,14 +1175,14 @@ static int time_pair(lbm_ctx* h, int launches, hipEvent_t e0, hipEvent_t e1, flo
         a.dst = h->buf(1 - src);
         a.ctr_in = h->d_ctr() + src;
         a.ctr_out = h->d_ctr() + (1 - src);
-        HIPCALL(h, launch_pair(h->storage, h->shape, a, h->stream));
+        HIPCALL(h, launch_fused(h->storage, h->shape, a, k, h->stream));
         src = 1 - src;
     }
     HIPCALL(h, hipEventRecord(e1, h->stream));
     HIPCALL(h, hipEventSynchronize(e1));
     float ms = 0.0f;
     HIPCALL(h, hipEventElapsedTime(&ms, e0, e1));
-    *us = 1000.0f * ms / (2 * launches);
+    *us = 1000.0f * ms / (k * launches);
     return LBM_OK;
 }
 
@@ -1196,7 +1200,7 @@ int lbm_autotune(lbm_handle h, int32_t steps, char* report, size_t report_len) {
         lbm_launch_shape ls = {cached.vec, cached.bx, cached.by, cached.xcd, cached.nt};
         if (report && report_len) snprintf(report, report_len, "{\"key\": \"%s\", \"cached\": true}", key.c_str());
         const int rc = lbm_set_launch_shape(h, &ls);
-        if (!rc) h->fuse = cached_fuse;
+        if (!rc) h->fuse = std::min(std::max(cached_fuse, 1), fuse_max(h->storage));
         return rc;
     }
     // scratch contents: zeros, so no timing depends on garbage bit patterns
@@ -1248,22 +1252,24 @@ int lbm_autotune(lbm_handle h, int32_t steps, char* report, size_t report_len) {
             s.nt = nt;
             try_shape(s);
         }
-    // steps per launch: the two-step kernel (with the best shape's XCD remap
-    // and store hint) against the best single-step shape
-    float pair_us = 1e30f;
+    // steps per launch: the fused kernel at the kind's most steps per launch
+    // (with the best shape's XCD remap and store hint) against the best
+    // single-step shape
+    float fused_us = 1e30f;
     if (!rc) {
         h->shape = best;
         build_tiles(h);
         rc = upload_tables(h);
-        if (!rc) rc = time_pair(h, (steps + 1) / 2, e0, e1, &pair_us);
+        const int kmax = fuse_max(h->storage);
+        if (!rc) rc = time_fused(h, kmax, (steps + kmax - 1) / kmax, e0, e1, &fused_us);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    const int fuse = pair_us < best_us ? 2 : 1;
+    const int fuse = fused_us < best_us ? fuse_max(h->storage) : 1;
     char b[320];
-    snprintf(b, sizeof b, "], \"best\": [%d, %d, %d, %d, %d, %.2f], \"pair_us_per_step\": %.2f, "
-             "\"steps_per_launch\": %d}", best.vec, best.bx, best.by, best.xcd, best.nt, best_us, pair_us, fuse);
+    snprintf(b, sizeof b, "], \"best\": [%d, %d, %d, %d, %d, %.2f], \"fused_us_per_step\": %.2f, "
+             "\"steps_per_launch\": %d}", best.vec, best.bx, best.by, best.xcd, best.nt, best_us, fused_us, fuse);
     rep += b;
     if (report && report_len) snprintf(report, report_len, "%s", rep.c_str());
     if (path && *path) {

@@ -87,6 +87,7 @@ SIGNATURES = [
     ("lbm_coefficients", ctypes.c_int, [_P, ctypes.c_int32, _D]),
     ("lbm_set_wall_flux", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]),
     ("lbm_set_step_fusion", ctypes.c_int, [_P, ctypes.c_int32]),
+    ("lbm_get_step_fusion", ctypes.c_int32, [_P]),
     ("lbm_set_schedule", ctypes.c_int, [_P, ctypes.c_int32]),
     ("lbm_set_launch_shape", ctypes.c_int, [_P, ctypes.POINTER(lbm_launch_shape)]),
     ("lbm_get_launch_shape", ctypes.c_int, [_P, ctypes.POINTER(lbm_launch_shape)]),
@@ -215,6 +216,10 @@ def lbm_set_wall_flux(h, inst: int, wall: int, q0: float) -> None:
 
 def lbm_set_step_fusion(h, steps: int) -> None:
     _check(library().lbm_set_step_fusion(h, int(steps)), "lbm_set_step_fusion", h)
+
+
+def lbm_get_step_fusion(h) -> int:
+    return int(library().lbm_get_step_fusion(h))
 
 
 def lbm_set_schedule(h, schedule: int) -> None:
@@ -373,8 +378,13 @@ class Lattice:
         lbm_set_wall_flux(self.h, inst, wall, float(q0))
 
     def set_step_fusion(self, steps: int) -> None:
-        """Time steps per launch where allowed (2: two-step kernel, 1: off)."""
+        """Most time steps per launch where allowed (1: every step on its own)."""
         lbm_set_step_fusion(self.h, steps)
+
+    def step_fusion(self) -> int:
+        """Most time steps per launch; on a new handle, the most the storage
+        kind's fused kernel takes."""
+        return lbm_get_step_fusion(self.h)
 
     def set_schedule(self, name: str) -> None:
         lbm_set_schedule(self.h, {"batched": LBM_SCHED_BATCHED, "per_instance": LBM_SCHED_PER_INSTANCE,

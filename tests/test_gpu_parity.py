@@ -398,7 +398,7 @@ FUSION_CASES = [
     ("heat flux y split", dict(bc_y="heatflux", q_wall=(0, 0, 1e-3, -4e-4)), "f16_split", "nearest"),
     ("square corners", dict(bc_x="isothermal", bc_y="isothermal", wall_bc=(0, 0, 0, "heatflux"),
                             t_wall=(1.0, 1.0, 1.0, 0.0), q_wall=(0, 0, 0, 1e-3)), "f32", "nearest"),
-    # plain BF16 runs the y-marching two-step kernel: walls on both axes there too
+    # walls on both axes and stochastic rounding with the 16-bit kinds
     ("walls x bf16", dict(bc_x="isothermal", t_wall=(1.004, 0.997, 0, 0)), "bf16", "nearest"),
     ("gradient channel bf16 sr", dict(bc_x="gradient", bc_y="diffuse", grad_x=2e-3), "bf16", "stochastic"),
     ("square corners bf16", dict(bc_x="isothermal", bc_y="isothermal", wall_bc=(0, 0, 0, "heatflux"),
@@ -407,11 +407,12 @@ FUSION_CASES = [
 
 
 def _fused_run(case, T0, qx, qy, storage, rounding, fuse, steps, check, schedule=None, n_inst=1):
-    """Run with `fuse` steps per launch (1: single steps only; 2: two-step
-    launches wherever allowed, also for the kinds whose default is 1)."""
+    """Run with at most `fuse` steps per launch (1: single steps only; None:
+    the storage kind's most, the default)."""
     lat = Lattice([instance_from_case(case)] * n_inst, storage=storage, check_interval=check,
                   rounding=rounding, seed=9)
-    lat.set_step_fusion(fuse)
+    if fuse is not None:
+        lat.set_step_fusion(fuse)
     if schedule:
         lat.set_schedule(schedule)
     for k in range(n_inst):
@@ -427,43 +428,73 @@ def _fused_run(case, T0, qx, qy, storage, rounding, fuse, steps, check, schedule
     return out
 
 
+def _fuse_max(storage):
+    lat = Lattice([instance_from_case(W.Case("probe", 8, 8, 0.6, 5.0))], storage=storage)
+    k = lat.step_fusion()
+    lat.close()
+    return k
+
+
+@pytest.mark.parametrize("storage,kmax", [("f32", 5), ("f16", 5), ("bf16", 3), ("f16_split", 4),
+                                          ("bf16_split", 4)])
+def test_step_fusion_range(storage, kmax):
+    """A new handle fuses up to its storage kind's most steps per launch;
+    1 .. that most are accepted, 0 and one more are refused."""
+    lat = Lattice([instance_from_case(W.Case("probe", 8, 8, 0.6, 5.0))], storage=storage)
+    assert lat.step_fusion() == kmax
+    for bad in (0, kmax + 1):
+        with pytest.raises(LBMError) as e:
+            lat.set_step_fusion(bad)
+        assert e.value.code == LBM_EINVAL
+    for k in range(1, kmax + 1):
+        lat.set_step_fusion(k)
+        assert lat.step_fusion() == k
+    lat.close()
+
+
 @pytest.mark.parametrize("name,kw,storage,rounding", FUSION_CASES, ids=[c[0] for c in FUSION_CASES])
-def test_two_step_kernel_bitwise(name, kw, storage, rounding):
-    """The two-step (temporally blocked) kernel gives the same bits as single
+def test_fused_kernel_bitwise(name, kw, storage, rounding):
+    """The fused (temporally blocked) kernel gives the same bits as single
     steps: storage kinds and roundings, every boundary kind, corners, check
-    steps every 10 (pairs stop before snapshot/check steps), call lengths that
-    leave odd remainders, and the per-instance and graph schedules."""
+    steps every 10 (fused runs stop before snapshot/check steps), call
+    lengths that leave short remainders, every number of steps per launch
+    up to the kind's most, and the per-instance and graph schedules."""
     case, T0, qx, qy = _random_case(131, 37, 0.6, 7.0, 51, **kw)
     steps = (1, 2, 3, 7, 26)
     ref_out = _fused_run(case, T0, qx, qy, storage, rounding, 1, steps, 10)
-    for fuse, sched in ((2, None), (2, "per_instance"), (2, "graph")):
+    kmax = _fuse_max(storage)
+    runs = [(k, None) for k in range(2, kmax + 1)] + [(kmax, "per_instance"), (kmax, "graph")]
+    for fuse, sched in runs:
         got = _fused_run(case, T0, qx, qy, storage, rounding, fuse, steps, 10, sched)
         for a_list, b_list in zip(got, ref_out):
             for a, b in zip(a_list[0], b_list[0]):
                 assert np.array_equal(a, b), (name, fuse, sched)
     e = eps(case, ref_out[-1][0], oracle_fields(case, sum(steps), T0, qx, qy))
-    log(f"two-step {name}: eps={e}")
+    log(f"fused {name}: up to {kmax} steps per launch, eps={e}")
     assert max(e) < TOL_STORAGE[storage]
 
 
-@pytest.mark.parametrize("storage", ["f32", "bf16"])
-@pytest.mark.parametrize("nx,ny", [(2, 2), (3, 2), (5, 3), (61, 13), (65, 14), (121, 25), (70, 33)])
-def test_two_step_kernel_small_and_ragged(nx, ny, storage):
-    """Tiles larger than the lattice (the window wraps several times), and
-    lattices one node past a tile edge or a 32-row marching chunk: same bits
-    as single steps, and the oracle."""
-    case, T0, qx, qy = _random_case(nx, ny, 0.8, 2.0, nx * 7 + ny)
-    # five steps (two pairs and a single): the random flux decays by 0.6 per
-    # step, and later it nears the FP32 noise floor on the tiniest grids
-    a = _fused_run(case, T0, qx, qy, storage, "nearest", 1, (5,), 0)[0][0]
-    b = _fused_run(case, T0, qx, qy, storage, "nearest", 2, (5,), 0)[0][0]
-    for u, v in zip(a, b):
-        assert np.array_equal(u, v), (nx, ny, storage)
-    assert max(eps(case, b, oracle_fields(case, 5, T0, qx, qy))) < TOL_STORAGE[storage]
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16_split"])
+@pytest.mark.parametrize("nx,ny", [(2, 2), (3, 2), (5, 3), (55, 13), (59, 14), (61, 13), (121, 25),
+                                   (70, 33), (109, 65)])
+def test_fused_kernel_small_and_ragged(nx, ny, storage):
+    """Strips wider than the lattice (the window wraps several times), and
+    lattices one node past a strip edge (54, 56 or 58 output columns by kind)
+    or a 32-row marching chunk: same bits as single steps for two and for the
+    most steps per launch, and the oracle."""
+    case, T0, qx, qy = _random_case(nx, ny, 0.8, 8.0, nx * 7 + ny)
+    steps = (5, 6)        # fused launches of every length up to five, and singles
+    a = _fused_run(case, T0, qx, qy, storage, "nearest", 1, steps, 0)
+    for fuse in sorted({2, _fuse_max(storage)}):
+        b = _fused_run(case, T0, qx, qy, storage, "nearest", fuse, steps, 0)
+        for ra, rb in zip(a, b):
+            for u, v in zip(ra[0], rb[0]):
+                assert np.array_equal(u, v), (nx, ny, storage, fuse)
+    assert max(eps(case, a[-1][0], oracle_fields(case, sum(steps), T0, qx, qy))) < TOL_STORAGE[storage]
 
 
 def test_autotune_choices_cache_and_results(tmp_path, monkeypatch):
-    """lbm_autotune times the launch shapes and the two-step kernel on the
+    """lbm_autotune times the launch shapes and the fused kernel on the
     handle's own instances, applies the fastest, and records the choice in
     the cache file; a second handle of the same shapes reads it back.  A
     tuned handle still matches the oracle; tuning after init is refused."""
@@ -472,12 +503,14 @@ def test_autotune_choices_cache_and_results(tmp_path, monkeypatch):
     monkeypatch.setenv("LBM_AUTOTUNE_CACHE", str(cache))
     case, T0, qx, qy = _random_case(257, 130, 0.6, 7.0, 61)
     lat = Lattice([instance_from_case(case)], check_interval=10)
+    kmax = lat.step_fusion()
     rep = json.loads(lat.autotune(6))
-    assert rep["cached"] is False and rep["steps_per_launch"] in (1, 2)
+    assert rep["cached"] is False and rep["steps_per_launch"] in (1, kmax)
+    assert lat.step_fusion() == rep["steps_per_launch"]
     best = rep["best"]
     got = lat.launch_shape()
     assert [got["vec"], got["block_x"], got["block_y"], got["xcd_remap"], got["nontemporal"]] == best[:5]
-    log(f"autotune 257x130: best {best}, two-step {rep['pair_us_per_step']:.1f} us/step, "
+    log(f"autotune 257x130: best {best}, fused {rep['fused_us_per_step']:.1f} us/step, "
         f"steps per launch {rep['steps_per_launch']}")
     lat.init(0, T0, qx, qy)
     with pytest.raises(LBMError) as e:
@@ -492,6 +525,7 @@ def test_autotune_choices_cache_and_results(tmp_path, monkeypatch):
     lat2 = Lattice([instance_from_case(case)], check_interval=10)
     assert json.loads(lat2.autotune(6))["cached"] is True
     assert lat2.launch_shape() == got
+    assert lat2.step_fusion() == rep["steps_per_launch"]
     lat2.close()
 
 
