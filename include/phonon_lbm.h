@@ -275,9 +275,9 @@ int lbm_set_wall_flux(lbm_handle h, int32_t inst, int32_t wall, double q0);
  * states rounded exactly as stored steps): a run of k >= 2 plain steps (no
  * check-step work, not the last step of an lbm_step call) is advanced by one
  * launch; 1 issues every step on its own.  Results are identical for every
- * setting.  The most steps per launch depends on the storage kind (5 FP32 and
- * FP16, 3 BF16, 4 split kinds; lbm_get_step_fusion of a new handle returns
- * it, the default).  The per-instance schedule always issues single steps.
+ * setting.  The most steps per launch depends on the storage kind (6 FP32,
+ * 5 F16_SPLIT, 4 FP16, BF16 and BF16_SPLIT; lbm_get_step_fusion of a new
+ * handle returns it, the default).  The per-instance schedule always issues single steps.
  * Drops captured graphs.  Errors: EINVAL (steps < 1 or more than the storage
  * kind's most). */
 int lbm_set_step_fusion(lbm_handle h, int32_t steps);

@@ -913,6 +913,10 @@ __device__ __forceinline__ void march_gather(const float dn_row[8], const float 
 template <class S, int SR, int SPLIT, int K, int KMAX>
 __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int nontemporal) {
     static_assert(K >= 2 && K <= KMAX, "stages per launch");
+    // input rows loaded ahead (measured on MI355X: two or three rows ahead are
+    // no faster than one, and take 8 more VGPRs per row)
+    constexpr int PF = 1;
+    static_assert(PF >= 1 && PF <= 2 * K + 1, "the first PF rows are all input rows");
     constexpr int W = 64 - 2 * KMAX;
     const int lane = threadIdx.x & 63;
     int b = blockIdx.x;
@@ -923,8 +927,10 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
     const int t = b * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     if (t >= a.ntiles) return;                // whole wavefront: no lane is left behind a DPP move
     const int tg = t + a.tile_base;
-    const int inst = a.tile_inst[tg];
-    const InstDesc& d = a.desc[inst];
+    // a private copy of the descriptor, read once before the first store (the
+    // compiler cannot keep fields of device memory in registers across stores)
+    const int inst = __builtin_amdgcn_readfirstlane(a.tile_inst[tg]);
+    const InstDesc d = a.desc[inst];
     const RefView rv = ref_view(a.ref[inst]);
     const int local = tg - d.p_tile_begin;
     const int ty = local / d.p_tiles_x;
@@ -938,15 +944,14 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
     S* __restrict__ dst = reinterpret_cast<S*>(a.dst) + d.off;
     const int64_t col = col_off(d, gx);
 
-    auto load_row = [&](int yi, float out[8]) {
-        const int gy = wrapm(yi, ny, kMarchRows + 2 * K);
+    // raw loads of input row yi (converted only where the row is used, so
+    // the loads stay in flight across the iterations in between)
+    auto fetch_row = [&](int yi, S v[8], float& E) {
+        const int gy = wrapm(yi, ny, kMarchRows + 2 * K + PF);
         const S* row = src + (int64_t)gy * d.row;
-        S v[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) v[i] = row[(int64_t)i * d.plane + col];
-        const float E = SPLIT ? *reinterpret_cast<const float*>(reinterpret_cast<const char*>(row) + e_off(d, gx))
-                              : 0.0f;
-        reload<S, SPLIT>(v, E, out);
+        E = SPLIT ? *reinterpret_cast<const float*>(reinterpret_cast<const char*>(row) + e_off(d, gx)) : 0.0f;
     };
 
     // per level l (0: loaded rows, l: results of stage l), the c_y = 0 movers of
@@ -958,18 +963,26 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
 #pragma unroll
         for (int k = 0; k < 3; ++k) up1[l][k] = up2[l][k] = 0.0f;
     }
-    float nxt[8];
-    load_row(y0 - K, nxt);
-    // One iteration: load row yi + 1 ahead, then every stage whose input rows
-    // exist; WARM (the first 2 K iterations) tests that per stage, later
-    // iterations run all K stages.
+    // rows yi .. yi + PF - 1 of the coming iterations, in flight
+    S ring[PF][8];
+    float ringE[PF];
+#pragma unroll
+    for (int j = 0; j < PF; ++j) fetch_row(y0 - K + j, ring[j], ringE[j]);
+    // One iteration: take row yi from the ring and load row yi + PF into it,
+    // then every stage whose input rows exist; WARM (the first 2 K
+    // iterations) tests that per stage, later iterations run all K stages.
     auto iteration = [&](const int it, auto warm) {
         constexpr bool WARM = decltype(warm)::value;
         const int yi = y0 - K + it;
         float cur[8];
+        reload<S, SPLIT>(ring[0], ringE[0], cur);
 #pragma unroll
-        for (int i = 0; i < 8; ++i) cur[i] = nxt[i];
-        if (it + 1 < iters) load_row(yi + 1, nxt);   // one row ahead: in flight during the stages
+        for (int j = 0; j + 1 < PF; ++j) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) ring[j][i] = ring[j + 1][i];
+            ringE[j] = ringE[j + 1];
+        }
+        if (it + PF < iters) fetch_row(yi + PF, ring[PF - 1], ringE[PF - 1]);
 #pragma unroll
         for (int s = 1; s <= K; ++s) {
             // stage s: row yi - s from level s - 1 (valid once it >= 2 s)
@@ -978,7 +991,7 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
                 float g[8];
                 march_gather(cur, mid[s - 1], up2[s - 1], g);
                 if (s < K) {
-                    const int gy = wrapm(yi - s, ny, kMarchRows + 2 * K);
+                    const int gy = wrapm(yi - s, ny, kMarchRows + 2 * K + PF);
                     if (s == 1 && a.apply_shift) apply_shift(g, rv);
                     if (on_wall(d, gx, gy)) boundary(g, d, rv.wall_kd, gx, gy);
                     uint32_t r[4] = {0u, 0u, 0u, 0u};

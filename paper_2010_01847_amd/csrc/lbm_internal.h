@@ -114,21 +114,23 @@ enum StepMode { kPlain = 0, kSnap = 1, kCheck = 2 };
 // wavefront takes a strip of fused_width output columns (a window of 64
 // columns with a halo of fuse_max nodes on each side) of a chunk of
 // kMarchRows rows, and marches along y advancing up to fuse_max steps; see the
-// device file.  The kernel is bound by vector ALU issue, not by HBM (with
-// five steps per launch an FP32 update moves about a quarter of the single-
-// step bytes), so the most steps per launch is a per-kind balance between the
-// HBM bytes saved and the halo nodes recomputed.  Measured on MI355X (8192^2
-// periodic lattice, GLUPS, steps per launch FP32 / FP16-SR / BF16-SR /
-// F16_SPLIT / BF16_SPLIT):
-//   4 / 4 / 2 / 3 / 3    209 / 156 / 210 / 130 / 175
-//   5 / 5 / 3 / 4 / 4    208 / 164 / 228 / 149 / 191   (chosen)
-//   6 / 6 / 4 / 5 / 5    213 / 153 / 229 / 145 / 177
-//   7 / 7 / 5 / 6 / 6    200 / 155 / 212 / 150 / 171
-// (single steps: 90 / 147 / 128 / 137 / 131).  The chunk height hardly
-// matters (24, 32, 48, 64 rows within 2%).
+// device file.  The kernel is bound by vector ALU issue, not by HBM (with six
+// steps per launch an FP32 update moves about a fifth of the single-step
+// bytes), so the most steps per launch is a per-kind balance between the HBM
+// bytes saved, the halo nodes recomputed and the registers the delay lines
+// take (FP32: 88 / 102 / 116 / 130 VGPRs at 4 / 5 / 6 / 7 steps).  Measured on
+// MI355X (8192^2 periodic lattice, GLUPS, steps per launch FP32 / FP16-SR /
+// BF16-SR / F16_SPLIT / BF16_SPLIT):
+//   4 / 4 / 2 / 3 / 3    221 / 244 / 212 / 255 / 211
+//   5 / 5 / 3 / 4 / 4    277 / 232 / 232 / 267 / 217
+//   6 / 6 / 4 / 5 / 5    315 / 217 / 235 / 271 / 214
+//   7 / 7 / 5 / 6 / 6    293 / 199 / 217 / 245 / 190
+//   8 / 8 / 6 / 7 / 7    280 / 189 / 187 / 245 / 186
+// (single steps: 90 / 147 / 128 / 137 / 131).  Chunks of 64 or 128 rows
+// instead of 32: FP32 302 / 289 at six steps.
 constexpr int kMarchRows = 32;
 __host__ __device__ constexpr int fuse_max(int storage) {
-    return storage == 0 ? 5 : (storage == 1 ? 5 : (storage == 2 ? 3 : 4));
+    return storage == 0 ? 6 : (storage == 3 ? 5 : 4);
 }
 __host__ __device__ constexpr int fused_width(int storage) { return 64 - 2 * fuse_max(storage); }
 
