@@ -92,10 +92,13 @@ __device__ __forceinline__ void store_run(S* __restrict__ p, const float* v, int
 
 __device__ __forceinline__ void relax_parts(const float g[8], float eqf[8], float fl[8]) {
     const float E = ((g[0] + g[2]) + (g[1] + g[3])) + ((g[4] + g[6]) + (g[5] + g[7]));
-    const float jx = ((g[0] - g[2]) + (g[4] - g[6])) + (g[7] - g[5]);
-    const float jy = ((g[1] - g[3]) + (g[4] - g[6])) + (g[5] - g[7]);
+    // (g5 - g7) = -(g7 - g5) and 4 ea is exact, so the shared difference and
+    // the fused form below round exactly as the plain expressions
+    const float d46 = g[4] - g[6], d75 = g[7] - g[5];
+    const float jx = ((g[0] - g[2]) + d46) + d75;
+    const float jy = ((g[1] - g[3]) + d46) - d75;
     const float ea = W_AXIS * E;
-    const float ed = (E - 4.0f * ea) * 0.25f;
+    const float ed = __builtin_fmaf(-4.0f, ea, E) * 0.25f;
     const float fx = W_FA * jx, fy = W_FA * jy;
     const float fp = W_FD * (jx + jy), fm = W_FD * (jx - jy);
     fl[0] = fx;  fl[1] = fy;  fl[2] = -fx;  fl[3] = -fy;
