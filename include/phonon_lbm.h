@@ -272,9 +272,10 @@ int lbm_set_wall_flux(lbm_handle h, int32_t inst, int32_t wall, double q0);
 
 /* Most time steps per launch where allowed (temporal blocking, Eq. 13 applied
  * k times to a tile before its populations go back to HBM, the intermediate
- * states rounded exactly as stored steps): a run of k >= 2 plain steps (no
- * check-step work, not the last step of an lbm_step call) is advanced by one
- * launch; 1 issues every step on its own.  Results are identical for every
+ * states rounded exactly as stored steps): a run of k >= 2 steps without a
+ * check step (it may end on the snapshot step before one) that does not hold
+ * the last step of an lbm_step call is advanced by one launch; 1 issues every
+ * step on its own.  Results are identical for every
  * setting.  The most steps per launch depends on the storage kind (6 FP32,
  * 5 F16_SPLIT, 4 FP16, BF16 and BF16_SPLIT; lbm_get_step_fusion of a new
  * handle returns it, the default).  The per-instance schedule always issues single steps.

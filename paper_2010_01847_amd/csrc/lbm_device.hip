@@ -156,6 +156,20 @@ __device__ __forceinline__ void apply_shift(float g[8], const RefView& rv) {
         if (vel_x(i) != 0) g[i] = g[i] + cx_times(i, rv.shift_a, rv.shift_d);
 }
 
+// FP64 moments of a pulled node (Eqs. 53-54) for the check-step snapshot and
+// residual: E = sum g, dT = s E / C_V, q = q_ref + s beta j.
+__device__ __forceinline__ void node_moments_f64(const float g[8], const InstDesc& d, double q_ref, double& E,
+                                                 double& dT, double& qx, double& qy) {
+    E = 0.0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) E += (double)g[i];
+    const double jx = ((double)g[0] - (double)g[2]) + ((double)g[4] - (double)g[6]) + ((double)g[7] - (double)g[5]);
+    const double jy = ((double)g[1] - (double)g[3]) + ((double)g[4] - (double)g[6]) + ((double)g[5] - (double)g[7]);
+    dT = d.s_cv * E;
+    qx = q_ref + d.s_beta * jx;
+    qy = d.s_beta * jy;
+}
+
 // Relaxation with stochastic rounding of the stored result (FP32 storage):
 // the change is added to g_i with sr_add_f32.  16-bit storage narrows the
 // round-to-nearest FP32 result of relax() stochastically instead.
@@ -368,14 +382,8 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t sna
 #pragma unroll
             for (int k = 0; k < V; ++k) {
                 if (x0 + k >= nx) continue;
-                double E = 0.0, jx = 0.0, jy = 0.0;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) E += (double)g[k][i];
-                jx = ((double)g[k][0] - (double)g[k][2]) + ((double)g[k][4] - (double)g[k][6])
-                   + ((double)g[k][7] - (double)g[k][5]);
-                jy = ((double)g[k][1] - (double)g[k][3]) + ((double)g[k][4] - (double)g[k][6])
-                   + ((double)g[k][5] - (double)g[k][7]);
-                const double dT = d.s_cv * E, qx = ref.q_ref + d.s_beta * jx, qy = d.s_beta * jy;
+                double E, dT, qx, qy;
+                node_moments_f64(g[k], d, ref.q_ref, E, dT, qx, qy);
                 const int64_t n = nbase + x0 + k;
                 if (MODE == kSnap) {
                     a.snap[n] = dT;
@@ -565,14 +573,8 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
         const bool edge_x = (d.bc_x == 1 || d.bc_x == 2 || d.bc_x == 4) && (xc == 0 || xc + 64 >= nx);
         if (edge_y || edge_x) boundary(g, d, rv.wall_kd, x, y);
         if (MODE != kPlain) {
-            double E = 0.0;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) E += (double)g[i];
-            const double jx = ((double)g[0] - (double)g[2]) + ((double)g[4] - (double)g[6])
-                            + ((double)g[7] - (double)g[5]);
-            const double jy = ((double)g[1] - (double)g[3]) + ((double)g[4] - (double)g[6])
-                            + ((double)g[5] - (double)g[7]);
-            const double dT = d.s_cv * E, qx = ref.q_ref + d.s_beta * jx, qy = d.s_beta * jy;
+            double E, dT, qx, qy;
+            node_moments_f64(g, d, ref.q_ref, E, dT, qx, qy);
             const int64_t n = d.node_off + (int64_t)y * nx + x;
             if (MODE == kSnap) {
                 a.snap[n] = dT;
@@ -913,8 +915,11 @@ __device__ __forceinline__ void march_gather(const float dn_row[8], const float 
 
 // K <= KMAX: the window geometry depends on KMAX only, so launches of fewer
 // steps (before a check step or at the end of a call) use the same tile table.
-template <class S, int SR, int SPLIT, int K, int KMAX>
-__global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int nontemporal) {
+// SNAP: the last of the K steps is the snapshot step before a check step; its
+// stage also writes the FP64 moments of its pulled nodes, as the single-step
+// kernels do on that step.
+template <class S, int SR, int SPLIT, int K, int KMAX, int SNAP>
+__global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int nontemporal, int64_t snap_stride) {
     static_assert(K >= 2 && K <= KMAX, "stages per launch");
     // input rows loaded ahead (measured on MI355X: two or three rows ahead are
     // no faster than one, and take 8 more VGPRs per row)
@@ -935,6 +940,7 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
     const int inst = __builtin_amdgcn_readfirstlane(a.tile_inst[tg]);
     const InstDesc d = a.desc[inst];
     const RefView rv = ref_view(a.ref[inst]);
+    const double q_ref = SNAP ? a.ref[inst].q_ref : 0.0;
     const int local = tg - d.p_tile_begin;
     const int ty = local / d.p_tiles_x;
     const int tx = local - ty * d.p_tiles_x;
@@ -1007,6 +1013,14 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
                     const int ox = x0 + lane - KMAX, oy = yi - s;
                     if (lane >= KMAX && lane < KMAX + W && ox < nx) {
                         if (on_wall(d, ox, oy)) boundary(g, d, rv.wall_kd, ox, oy);
+                        if constexpr (SNAP != 0) {
+                            double E, dT, qx, qy;
+                            node_moments_f64(g, d, q_ref, E, dT, qx, qy);
+                            const int64_t n = d.node_off + (int64_t)oy * nx + ox;
+                            a.snap[n] = dT;
+                            a.snap[n + snap_stride] = qx;
+                            a.snap[n + 2 * snap_stride] = qy;
+                        }
                         uint32_t r[4] = {0u, 0u, 0u, 0u};
                         if (SR) sr_words(r, (uint32_t)(d.node_off + (int64_t)oy * nx + ox), step + (uint32_t)(s - 1),
                                          a.seed);
@@ -1044,38 +1058,53 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
 }
 
 template <class S, int SPLIT, int K, int KMAX>
-static hipError_t launch_march_s(const Shape& sh, const StepArgs& a, hipStream_t st) {
+static hipError_t launch_march_s(const Shape& sh, const StepArgs& a, int snap, int64_t snap_stride, hipStream_t st) {
     dim3 grid((a.ntiles + 3) / 4), block(256);
-    if (a.sr)
-        hipLaunchKernelGGL((march_kernel<S, 1, SPLIT, K, KMAX>), grid, block, 0, st, a, sh.xcd, sh.nt);
-    else
-        hipLaunchKernelGGL((march_kernel<S, 0, SPLIT, K, KMAX>), grid, block, 0, st, a, sh.xcd, sh.nt);
+    if (a.sr) {
+        if (snap)
+            hipLaunchKernelGGL((march_kernel<S, 1, SPLIT, K, KMAX, 1>), grid, block, 0, st, a, sh.xcd, sh.nt,
+                               snap_stride);
+        else
+            hipLaunchKernelGGL((march_kernel<S, 1, SPLIT, K, KMAX, 0>), grid, block, 0, st, a, sh.xcd, sh.nt,
+                               snap_stride);
+    } else {
+        if (snap)
+            hipLaunchKernelGGL((march_kernel<S, 0, SPLIT, K, KMAX, 1>), grid, block, 0, st, a, sh.xcd, sh.nt,
+                               snap_stride);
+        else
+            hipLaunchKernelGGL((march_kernel<S, 0, SPLIT, K, KMAX, 0>), grid, block, 0, st, a, sh.xcd, sh.nt,
+                               snap_stride);
+    }
     return hipGetLastError();
 }
 
 template <class S, int SPLIT, int K, int KMAX>
-static hipError_t launch_march_k(const Shape& sh, const StepArgs& a, int k, hipStream_t st) {
+static hipError_t launch_march_k(const Shape& sh, const StepArgs& a, int k, int snap, int64_t snap_stride,
+                                 hipStream_t st) {
     if constexpr (K > KMAX) {
         return hipErrorInvalidValue;
     } else {
-        if (k == K) return launch_march_s<S, SPLIT, K, KMAX>(sh, a, st);
-        return launch_march_k<S, SPLIT, K + 1, KMAX>(sh, a, k, st);
+        if (k == K) return launch_march_s<S, SPLIT, K, KMAX>(sh, a, snap, snap_stride, st);
+        return launch_march_k<S, SPLIT, K + 1, KMAX>(sh, a, k, snap, snap_stride, st);
     }
 }
 
 template <class S, int SPLIT, int STORAGE>
-static hipError_t launch_fused_s(const Shape& sh, const StepArgs& a, int k, hipStream_t st) {
-    return launch_march_k<S, SPLIT, 2, fuse_max(STORAGE)>(sh, a, k, st);
+static hipError_t launch_fused_s(const Shape& sh, const StepArgs& a, int k, int snap, int64_t snap_stride,
+                                 hipStream_t st) {
+    return launch_march_k<S, SPLIT, 2, fuse_max(STORAGE)>(sh, a, k, snap, snap_stride, st);
 }
 
-hipError_t launch_fused(int storage, const Shape& sh, const StepArgs& a, int k, hipStream_t st) {
+hipError_t launch_fused(int storage, const Shape& sh, const StepArgs& a, int k, int snap, int64_t snap_stride,
+                        hipStream_t st) {
     if (a.ntiles <= 0) return hipSuccess;
+    if (snap && !a.snap) return hipErrorInvalidValue;
     switch (storage) {
-        case 0: return launch_fused_s<float, 0, 0>(sh, a, k, st);
-        case 1: return launch_fused_s<_Float16, 0, 1>(sh, a, k, st);
-        case 2: return launch_fused_s<bf16_bits, 0, 2>(sh, a, k, st);
-        case 3: return launch_fused_s<_Float16, 1, 3>(sh, a, k, st);
-        case 4: return launch_fused_s<bf16_bits, 1, 4>(sh, a, k, st);
+        case 0: return launch_fused_s<float, 0, 0>(sh, a, k, snap, snap_stride, st);
+        case 1: return launch_fused_s<_Float16, 0, 1>(sh, a, k, snap, snap_stride, st);
+        case 2: return launch_fused_s<bf16_bits, 0, 2>(sh, a, k, snap, snap_stride, st);
+        case 3: return launch_fused_s<_Float16, 1, 3>(sh, a, k, snap, snap_stride, st);
+        case 4: return launch_fused_s<bf16_bits, 1, 4>(sh, a, k, snap, snap_stride, st);
         default: return hipErrorInvalidValue;
     }
 }

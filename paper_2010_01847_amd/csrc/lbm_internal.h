@@ -157,10 +157,12 @@ hipError_t launch_step(int storage, const Shape& sh, int mode, const StepArgs& a
                        int64_t snap_stride, hipStream_t st);
 
 // k time steps (m .. m + k - 1, 2 <= k <= fuse_max(storage)) in one pass over
-// HBM: all plain (no check work); a.apply_shift refers to the first of them;
-// a.tile_inst / tile_base / ntiles index the fused tile table.  Same bits as
-// k single steps.
-hipError_t launch_fused(int storage, const Shape& sh, const StepArgs& a, int k, hipStream_t st);
+// HBM: all plain, except that with snap != 0 the last one is the snapshot step
+// (its FP64 moments go to a.snap, snap_stride doubles per field);
+// a.apply_shift refers to the first of them; a.tile_inst / tile_base / ntiles
+// index the fused tile table.  Same bits as k single steps.
+hipError_t launch_fused(int storage, const Shape& sh, const StepArgs& a, int k, int snap, int64_t snap_stride,
+                        hipStream_t st);
 
 // Moments of the state at time n of one instance.  With pull != 0 the state is
 // rebuilt from the post-relaxation populations of step n-1 (advection plus

@@ -771,23 +771,38 @@ static int issue_step(lbm_ctx* h, int64_t m, int src_k, hipStream_t st, int sche
 }
 
 // Steps the launch that starts at step m covers: up to h->fuse consecutive
-// plain steps (no check-step work), none of them the last step of the sequence
-// being issued (`last`), so the post-relaxation state of the step before the
-// last one is in a buffer when the sequence ends (the moments of the final
-// state are rebuilt from it).  1 means a single-step launch.
-static int fused_steps(const lbm_ctx* h, int64_t m, int64_t last) {
+// steps without check-step work, the last of which may be the snapshot step
+// (the fused kernel writes its snapshot), none of them the last step of the
+// sequence being issued (`last`), so the post-relaxation state of the step
+// before the last one is in a buffer when the sequence ends (the moments of
+// the final state are rebuilt from it).  Returns 1 for a single-step launch;
+// *snap tells whether the run ends on the snapshot step.
+static int fused_steps(const lbm_ctx* h, int64_t m, int64_t last, bool* snap) {
     int k = 0;
-    while (k < h->fuse && m + k < last && mode_of(h, m + k) == kPlain) ++k;
-    return k >= 2 ? k : 1;
+    *snap = false;
+    while (k < h->fuse && m + k < last) {
+        const int mode = mode_of(h, m + k);
+        if (mode == kCheck) break;
+        ++k;
+        if (mode == kSnap) {
+            *snap = true;
+            break;
+        }
+    }
+    if (k < 2) {
+        *snap = false;
+        return 1;
+    }
+    return k;
 }
 
-static int issue_fused(lbm_ctx* h, int64_t m, int nsteps, int src_k, hipStream_t st) {
+static int issue_fused(lbm_ctx* h, int64_t m, int nsteps, bool snap, int src_k, hipStream_t st) {
     StepArgs a;
     a.desc = h->d_desc();
     a.tile_inst = h->d_ptiles();
     a.src = h->buf(src_k);
     a.dst = h->buf(1 - src_k);
-    a.snap = nullptr;
+    a.snap = h->d_snap();
     a.partials = nullptr;
     a.ctr_in = h->d_ctr() + src_k;
     a.ctr_out = h->d_ctr() + (1 - src_k);
@@ -797,7 +812,7 @@ static int issue_fused(lbm_ctx* h, int64_t m, int nsteps, int src_k, hipStream_t
     a.apply_shift = (h->K > 0 && (m - 1) % h->K == 0) ? 1 : 0;
     a.tile_base = 0;
     a.ntiles = (int32_t)h->ptile_inst.size();
-    HIPCALL(h, launch_fused(h->storage, h->shape, a, nsteps, st));
+    HIPCALL(h, launch_fused(h->storage, h->shape, a, nsteps, snap ? 1 : 0, h->L.nodes, st));
     return LBM_OK;
 }
 
@@ -812,9 +827,10 @@ static int capture(lbm_ctx* h, int par) {
     int rc = LBM_OK;
     int flips = 0;
     for (int s = 1; s <= C && rc == LBM_OK;) {
-        const int k = fused_steps(h, s, C);
+        bool snap = false;
+        const int k = fused_steps(h, s, C, &snap);
         if (k >= 2) {
-            rc = issue_fused(h, (int64_t)s, k, src, h->capture_stream);
+            rc = issue_fused(h, (int64_t)s, k, snap, src, h->capture_stream);
             s += k;
         } else {
             rc = issue_step(h, (int64_t)s, src, h->capture_stream, LBM_SCHED_BATCHED);
@@ -869,9 +885,10 @@ int lbm_step(lbm_handle h, int64_t nsteps) {
         // the per-instance schedule issues single steps: one instance's fused
         // launch holds too few wavefronts to hide the marching latency
         // (Knudsen sweep: 4.0k MLUPS at five steps per launch, 17.1k single)
-        const int k = sched == LBM_SCHED_PER_INSTANCE ? 1 : fused_steps(h, m, h->steps + left);
+        bool snap = false;
+        const int k = sched == LBM_SCHED_PER_INSTANCE ? 1 : fused_steps(h, m, h->steps + left, &snap);
         if (k >= 2) {
-            int rc = issue_fused(h, m, k, h->cur, h->stream);
+            int rc = issue_fused(h, m, k, snap, h->cur, h->stream);
             if (rc) return rc;
             h->cur = 1 - h->cur;
             h->steps = m + k - 1;
@@ -1175,7 +1192,7 @@ static int time_fused(lbm_ctx* h, int k, int launches, hipEvent_t e0, hipEvent_t
         a.dst = h->buf(1 - src);
         a.ctr_in = h->d_ctr() + src;
         a.ctr_out = h->d_ctr() + (1 - src);
-        HIPCALL(h, launch_fused(h->storage, h->shape, a, k, h->stream));
+        HIPCALL(h, launch_fused(h->storage, h->shape, a, k, 0, 0, h->stream));
         src = 1 - src;
     }
     HIPCALL(h, hipEventRecord(e1, h->stream));

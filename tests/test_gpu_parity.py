@@ -421,9 +421,14 @@ def _fused_run(case, T0, qx, qy, storage, rounding, fuse, steps, check, schedule
             if case.q_wall[w]:
                 lat.set_wall_flux(k, w, case.q_wall[w])
     out = []
+    done = 0
     for n in steps:
         lat.step(n)
-        out.append([lat.moments(k) for k in range(n_inst)])
+        done += n
+        # the moments, and the last check step's residual and totals (whose
+        # residual compares with the snapshot the step before it wrote)
+        checks = [lat.last_check(k) for k in range(n_inst)] if 0 < check <= done else [None] * n_inst
+        out.append([lat.moments(k) + (checks[k],) for k in range(n_inst)])
     lat.close()
     return out
 
@@ -456,9 +461,10 @@ def test_step_fusion_range(storage, kmax):
 def test_fused_kernel_bitwise(name, kw, storage, rounding):
     """The fused (temporally blocked) kernel gives the same bits as single
     steps: storage kinds and roundings, every boundary kind, corners, check
-    steps every 10 (fused runs stop before snapshot/check steps), call
-    lengths that leave short remainders, every number of steps per launch
-    up to the kind's most, and the per-instance and graph schedules."""
+    steps every 10 (a fused run ends at the latest on the snapshot step,
+    whose FP64 moments it writes: the check steps' residual and totals agree
+    too), call lengths that leave short remainders, every number of steps per
+    launch up to the kind's most, and the per-instance and graph schedules."""
     case, T0, qx, qy = _random_case(131, 37, 0.6, 7.0, 51, **kw)
     steps = (1, 2, 3, 7, 26)
     ref_out = _fused_run(case, T0, qx, qy, storage, rounding, 1, steps, 10)
@@ -467,9 +473,10 @@ def test_fused_kernel_bitwise(name, kw, storage, rounding):
     for fuse, sched in runs:
         got = _fused_run(case, T0, qx, qy, storage, rounding, fuse, steps, 10, sched)
         for a_list, b_list in zip(got, ref_out):
-            for a, b in zip(a_list[0], b_list[0]):
+            for a, b in zip(a_list[0][:3], b_list[0][:3]):
                 assert np.array_equal(a, b), (name, fuse, sched)
-    e = eps(case, ref_out[-1][0], oracle_fields(case, sum(steps), T0, qx, qy))
+            assert a_list[0][3] == b_list[0][3], (name, fuse, sched, a_list[0][3], b_list[0][3])
+    e = eps(case, ref_out[-1][0][:3], oracle_fields(case, sum(steps), T0, qx, qy))
     log(f"fused {name}: up to {kmax} steps per launch, eps={e}")
     assert max(e) < TOL_STORAGE[storage]
 
@@ -488,9 +495,9 @@ def test_fused_kernel_small_and_ragged(nx, ny, storage):
     for fuse in sorted({2, _fuse_max(storage)}):
         b = _fused_run(case, T0, qx, qy, storage, "nearest", fuse, steps, 0)
         for ra, rb in zip(a, b):
-            for u, v in zip(ra[0], rb[0]):
+            for u, v in zip(ra[0][:3], rb[0][:3]):
                 assert np.array_equal(u, v), (nx, ny, storage, fuse)
-    assert max(eps(case, a[-1][0], oracle_fields(case, sum(steps), T0, qx, qy))) < TOL_STORAGE[storage]
+    assert max(eps(case, a[-1][0][:3], oracle_fields(case, sum(steps), T0, qx, qy))) < TOL_STORAGE[storage]
 
 
 def test_autotune_choices_cache_and_results(tmp_path, monkeypatch):
