@@ -92,6 +92,10 @@ def _parse():
     p.add_argument("--d3q14-shape", default="auto",
                    help="D3Q14 launch shape rows_per_tile,xcd_remap,nontemporal,tile_waves[,zchunk[,steps "
                         "per launch]] (auto: the autotuner's choice)")
+    p.add_argument("--large-steps", type=int, default=200,
+                   help="timed steps of each row of the 16384^2 smooth-modes lattice (0: skip)")
+    p.add_argument("--large-rows", default="f16:stochastic,f16_split",
+                   help="storage[:rounding] rows of the 16384^2 smooth-modes lattice")
     p.add_argument("--copy-probe", action="store_true",
                    help="also run a 1 GiB torch device copy 5 times (counter calibration)")
     return p.parse_args()
@@ -288,6 +292,42 @@ def _run_d3q14(args, torch, W):
     return out
 
 
+def _run_large(args, torch, P, W):
+    """Large bandwidth-bound run: 16384^2 periodic, T0 = 1 plus 16 seeded
+    Fourier modes (total amplitude 1e-3), tau_N = 0.6, tau_R = 5, FP16
+    storage scaled by 2^-22 (plain FP16 and the split form), check steps every
+    100; the field is built on the device."""
+    case = W.smooth_modes_case()
+    modes = case.init_args["modes"]
+    nodes = case.nx * case.ny
+    out = {"workload": f"smooth_modes_{case.nx}x{case.ny}_periodic", "nodes": nodes, "tau_n": case.tau_n,
+           "tau_r": case.tau_r, "steps": args.large_steps, "rows": []}
+    for item in [r for r in args.large_rows.split(",") if r]:
+        st, _, rnd = item.partition(":")
+        rnd = rnd or _default_rounding(st)
+        scale = 2.0 ** -22 if st.startswith("f16") else 0.0
+        lat = P.Lattice([P.instance_from_case(case, scale)], storage=st, check_interval=args.check_interval,
+                        rounding=rnd, seed=1847)
+        T0 = W.modes_field_torch(modes, case.nx, case.ny, case.t0, device="cuda")
+        lat.init(0, T0)
+        del T0
+        torch.cuda.empty_cache()
+        lat.step(20)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(lat.stream)
+        lat.step(args.large_steps)
+        e1.record(lat.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.large_steps
+        out["rows"].append({"storage": st, "rounding": rnd, "steps_per_launch": lat.step_fusion(),
+                            "mlups": round(nodes / ms / 1e3, 1), "ms_per_step": round(ms, 4),
+                            "gbs": round(BYTES_PER_NODE[st] * nodes / ms / 1e6, 1)})
+        lat.close()
+    return out
+
+
 def _default_rounding(storage):
     return "stochastic" if storage in ("f16", "bf16") else "nearest"
 
@@ -341,6 +381,7 @@ def main():
         if (st, rnd) != (args.storage, main_rounding):
             rows.append(_run_gpu(args, st, rnd, torch, P, W))
     sweep = _run_sweep(args, torch, P, W) if args.sweep_steps > 0 else None
+    large = _run_large(args, torch, P, W) if args.large_steps > 0 else None
     d3q14 = _run_d3q14(args, torch, W) if args.d3q14_steps > 0 else None
     cpu = None if args.no_cpu_baseline else _cpu_baseline(args, W)
     gbs = main_row["kernel_gbs"]
@@ -371,6 +412,7 @@ def main():
                      "bytes_per_launch": BYTES_PER_NODE[args.storage] * args.n * args.n * main_row["fusion"]},
         "cpu_baseline": cpu,
         "sweep": sweep,
+        "large": large,
         "d3q14": d3q14,
         "host_io": {k: round(v, 4) for k, v in main_row["host_io"].items()},
         "rows": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()
