@@ -33,6 +33,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 # 8 population reads + 8 writes per node; split storage adds the FP32 energy
+# FP32 operations of one D2Q8 relaxation (moments, equilibrium shares, the
+# eight updates; a fused multiply-add counts 2), and MI355X's vector FP32 peak
+FLOP_PER_UPDATE = 81
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 BYTES_PER_NODE = {"f32": 64, "f16": 32, "bf16": 32, "f16_split": 40, "bf16_split": 40}
 # D3Q14: 14 population reads + 14 writes per node
 BYTES_PER_NODE_3D = {"f32": 112, "f16": 56, "bf16": 56}
@@ -409,7 +413,15 @@ def main():
                                 "wave_kernel (fused pull-advection + boundary + moments + relaxation)"),
                      "steps_per_launch": main_row["fusion"],
                      "kernel_us": round(main_row["launch_ms"] * 1e3, 1),
-                     "bytes_per_launch": BYTES_PER_NODE[args.storage] * args.n * args.n * main_row["fusion"]},
+                     "bytes_per_launch": BYTES_PER_NODE[args.storage] * args.n * args.n * main_row["fusion"],
+                     # the fused kernel's real limit is VALU issue: the same launch
+                     # against the vector FP32 peak, 81 algorithmic flops per update
+                     "alu": {"achieved": round(FLOP_PER_UPDATE * args.n * args.n * main_row["fusion"]
+                                               / (main_row["launch_ms"] * 1e-3) / 1e12, 2),
+                             "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": round(FLOP_PER_UPDATE * args.n * args.n * main_row["fusion"]
+                                           / (main_row["launch_ms"] * 1e-3) / 1e12 / FP32_VECTOR_PEAK_TFLOPS, 4),
+                             "flop_per_update": FLOP_PER_UPDATE}},
         "cpu_baseline": cpu,
         "sweep": sweep,
         "large": large,
