@@ -326,7 +326,8 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(PairArgs a) {
 #pragma unroll
     for (int j = 0; j < NJ; ++j) gy[j] = wrap_mod(y0 - 2 + wv + NW * j, g.ny);
 
-    float nv[NJ][kQ];                         // the input plane of this iteration
+    S nvr[NJ][kQ];                            // the input plane, raw (converted where used, so
+                                              // that its loads stay in flight during stage 2)
     float a_mid[NJ][4], a_up1[NJ][5], a_up2[NJ][5];   // later-needed input values
     float b_mid[NJ][4], b_up1[NJ][5], b_up2[NJ][5];   // later-needed stage-1 values
 #pragma unroll
@@ -344,13 +345,18 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(PairArgs a) {
             if (wv + NW * j >= WR) continue;
             const int64_t row = zrow + gy[j];
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) nv[j][i] = Cvt<S>::ld(src[elem<L>(g, i, row, gx)]);
+            for (int i = 0; i < kQ; ++i) nvr[j][i] = src[elem<L>(g, i, row, gx)];
         }
     };
 
     load_plane(z0 - 2);
     for (int it = 0; it < iters; ++it) {
         const int zi = z0 - 2 + it;
+        float nv[NJ][kQ];                     // the input plane of this iteration
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+#pragma unroll
+            for (int i = 0; i < kQ; ++i) nv[j][i] = Cvt<S>::ld(nvr[j][i]);
         // stage 1 pulls: c_z = -1 movers of plane zi, 0 of zi - 1, +1 of zi - 2
         if (it >= 2) {
 #pragma unroll
