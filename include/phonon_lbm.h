@@ -277,14 +277,20 @@ int lbm_set_wall_flux(lbm_handle h, int32_t inst, int32_t wall, double q0);
  * the last step of an lbm_step call is advanced by one launch; 1 issues every
  * step on its own.  Results are identical for every
  * setting.  The most steps per launch depends on the storage kind (6 FP32,
- * 5 F16_SPLIT, 4 FP16, BF16 and BF16_SPLIT; lbm_get_step_fusion of a new
- * handle returns it, the default).  The per-instance schedule always issues single steps.
- * Drops captured graphs.  Errors: EINVAL (steps < 1 or more than the storage
- * kind's most). */
+ * 5 F16_SPLIT, 4 FP16, BF16 and BF16_SPLIT: lbm_max_step_fusion).  Default
+ * for a new handle: that most when its instances hold at least 1024 strips of
+ * the fused kernel in all (64 - 2 k columns by 32 rows each, k the most), so
+ * that a fused launch fills the chip, else 1.  The per-instance schedule
+ * always issues single steps.  Drops captured graphs.  Errors: EINVAL (steps
+ * < 1 or more than the storage kind's most). */
 int lbm_set_step_fusion(lbm_handle h, int32_t steps);
 
 /* The current most time steps per launch; -1 for an invalid handle. */
 int32_t lbm_get_step_fusion(lbm_handle h);
+
+/* The most time steps one fused launch takes for storage kind `storage`
+ * (lbm_storage); -1 for an invalid kind.  Needs no device. */
+int32_t lbm_max_step_fusion(int32_t storage);
 
 /* Select how multi-instance steps are issued (lbm_schedule).  GRAPH captures
  * K batched steps (the check interval, or 64 when checks are off) once per
@@ -306,9 +312,9 @@ int lbm_set_launch_shape(lbm_handle h, const lbm_launch_shape* shape);
 int lbm_get_launch_shape(lbm_handle h, lbm_launch_shape* shape);
 
 /* Time every candidate launch shape on this handle's own instances and keep
- * the fastest, then time fused launches of the storage kind's most steps
- * against it and set the steps per launch (lbm_set_step_fusion) to the
- * faster.  Must be called after
+ * the fastest, then time fused launches of every number of steps up to the
+ * storage kind's most against it and set the steps per launch
+ * (lbm_set_step_fusion) to the fastest.  Must be called after
  * lbm_create and before lbm_init (it runs steps on scratch contents); each
  * candidate is timed over `steps` steps (0 = 20) with HIP events.  If the environment variable LBM_AUTOTUNE_CACHE
  * names a file, a result for the same device, storage and instance shapes is

@@ -133,6 +133,9 @@ __host__ __device__ constexpr int fuse_max(int storage) {
     return storage == 0 ? 6 : (storage == 3 ? 5 : 4);
 }
 __host__ __device__ constexpr int fused_width(int storage) { return 64 - 2 * fuse_max(storage); }
+// Fewest fused-kernel strips (wavefronts) over all instances for which fused
+// launches are the default: one per SIMD of the chip.
+constexpr int64_t kFuseMinStrips = 1024;
 
 struct StepArgs {
     const InstDesc* desc;

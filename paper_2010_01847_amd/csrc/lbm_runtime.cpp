@@ -503,9 +503,6 @@ int lbm_create(const lbm_config* cfg, lbm_handle* out) {
     }
     h->inst = v;
     h->storage = cfg->storage;
-    // fused launches (the most steps the kind's kernel takes): measured on
-    // MI355X (8192^2) faster than single steps for every storage kind
-    h->fuse = fuse_max(cfg->storage);
     h->K = check_of(cfg);
     h->stream = reinterpret_cast<hipStream_t>(cfg->stream);
     h->external = (cfg->flags & LBM_FLAG_EXTERNAL_MEMORY) != 0;
@@ -559,6 +556,13 @@ int lbm_create(const lbm_config* cfg, lbm_handle* out) {
     h->shape.xcd = 1;
     h->shape.nt = 0;
     build_tiles(h);
+    // steps per launch: the kind's most when the instances hold enough strips
+    // of the fused kernel to fill the chip, else single steps.  Measured on
+    // MI355X (FP32, us per step, single / six fused): 1024 x 256 4.5 / 12.2,
+    // 1024^2 10.3 / 12.6 (640 strips), 2048 x 1024 17.7 / 14.4 (1280 strips),
+    // 8192^2 741 / 213: a fused launch takes about one strip's marching time
+    // however few strips there are.
+    h->fuse = (int64_t)h->ptile_inst.size() >= kFuseMinStrips ? fuse_max(cfg->storage) : 1;
     e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         g_create_error = std::string("hipStreamCreate: ") + hipGetErrorString(e);
@@ -1043,6 +1047,10 @@ int lbm_set_step_fusion(lbm_handle h, int32_t steps) {
 
 int32_t lbm_get_step_fusion(lbm_handle h) { return valid(h) ? h->fuse : -1; }
 
+int32_t lbm_max_step_fusion(int32_t storage) {
+    return (storage >= LBM_F32 && storage <= LBM_BF16_SPLIT) ? fuse_max(storage) : -1;
+}
+
 int lbm_set_schedule(lbm_handle h, int32_t schedule) {
     if (!valid(h)) return LBM_EINVAL;
     if (schedule < 0 || schedule > 2) return h->fail(LBM_EINVAL, "unknown schedule");
@@ -1269,24 +1277,39 @@ int lbm_autotune(lbm_handle h, int32_t steps, char* report, size_t report_len) {
             s.nt = nt;
             try_shape(s);
         }
-    // steps per launch: the fused kernel at the kind's most steps per launch
-    // (with the best shape's XCD remap and store hint) against the best
-    // single-step shape
+    // steps per launch: the fused kernel at every number of steps up to the
+    // kind's most (with the best shape's XCD remap and store hint) against the
+    // best single-step shape; small lattices hold few strips and may prefer
+    // fewer steps per launch
     float fused_us = 1e30f;
+    int fused_k = fuse_max(h->storage);
+    std::string fused_rep;
     if (!rc) {
         h->shape = best;
         build_tiles(h);
         rc = upload_tables(h);
-        const int kmax = fuse_max(h->storage);
-        if (!rc) rc = time_fused(h, kmax, (steps + kmax - 1) / kmax, e0, e1, &fused_us);
+        for (int k = 2; k <= fuse_max(h->storage) && !rc; ++k) {
+            float us = 0.0f;
+            rc = time_fused(h, k, (steps + k - 1) / k, e0, e1, &us);
+            char b[64];
+            snprintf(b, sizeof b, "%s[%d, %.2f]", k == 2 ? "" : ", ", k, us);
+            fused_rep += b;
+            if (!rc && us < fused_us) {
+                fused_us = us;
+                fused_k = k;
+            }
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    const int fuse = fused_us < best_us ? fuse_max(h->storage) : 1;
+    const int fuse = fused_us < best_us ? fused_k : 1;
     char b[320];
-    snprintf(b, sizeof b, "], \"best\": [%d, %d, %d, %d, %d, %.2f], \"fused_us_per_step\": %.2f, "
-             "\"steps_per_launch\": %d}", best.vec, best.bx, best.by, best.xcd, best.nt, best_us, fused_us, fuse);
+    snprintf(b, sizeof b, "], \"best\": [%d, %d, %d, %d, %d, %.2f], \"fused_us_per_step\": %.2f, ", best.vec,
+             best.bx, best.by, best.xcd, best.nt, best_us, fused_us);
+    rep += b;
+    rep += "\"fused_timings_us\": [" + fused_rep + "], ";
+    snprintf(b, sizeof b, "\"steps_per_launch\": %d}", fuse);
     rep += b;
     if (report && report_len) snprintf(report, report_len, "%s", rep.c_str());
     if (path && *path) {

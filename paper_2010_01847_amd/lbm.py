@@ -88,6 +88,7 @@ SIGNATURES = [
     ("lbm_set_wall_flux", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]),
     ("lbm_set_step_fusion", ctypes.c_int, [_P, ctypes.c_int32]),
     ("lbm_get_step_fusion", ctypes.c_int32, [_P]),
+    ("lbm_max_step_fusion", ctypes.c_int32, [ctypes.c_int32]),
     ("lbm_set_schedule", ctypes.c_int, [_P, ctypes.c_int32]),
     ("lbm_set_launch_shape", ctypes.c_int, [_P, ctypes.POINTER(lbm_launch_shape)]),
     ("lbm_get_launch_shape", ctypes.c_int, [_P, ctypes.POINTER(lbm_launch_shape)]),
@@ -220,6 +221,10 @@ def lbm_set_step_fusion(h, steps: int) -> None:
 
 def lbm_get_step_fusion(h) -> int:
     return int(library().lbm_get_step_fusion(h))
+
+
+def lbm_max_step_fusion(storage: int) -> int:
+    return int(library().lbm_max_step_fusion(int(storage)))
 
 
 def lbm_set_schedule(h, schedule: int) -> None:
@@ -382,8 +387,8 @@ class Lattice:
         lbm_set_step_fusion(self.h, steps)
 
     def step_fusion(self) -> int:
-        """Most time steps per launch; on a new handle, the most the storage
-        kind's fused kernel takes."""
+        """Most time steps per launch (on a new handle: the most the storage
+        kind's fused kernel takes for large lattices, 1 for small ones)."""
         return lbm_get_step_fusion(self.h)
 
     def set_schedule(self, name: str) -> None:

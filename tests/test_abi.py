@@ -162,6 +162,14 @@ def test_tau_r_infinite_and_small_accepted():
         assert P.lbm_required_bytes(_cfg([P.make_instance(16, 8, 0.6, tr)])) > 0
 
 
+def test_max_step_fusion_per_storage_kind():
+    """The most time steps per fused launch, per storage kind (no device)."""
+    got = [P.lbm_max_step_fusion(k) for k in (P.LBM_F32, P.LBM_F16, P.LBM_BF16, P.LBM_F16_SPLIT,
+                                               P.LBM_BF16_SPLIT)]
+    assert got == [6, 4, 4, 5, 4]
+    assert P.lbm_max_step_fusion(5) == -1 and P.lbm_max_step_fusion(-1) == -1
+
+
 def test_null_handle_calls_are_rejected():
     assert P.library().lbm_step(None, 1) == P.LBM_EINVAL
     assert P.library().lbm_steps_done(None) == -1

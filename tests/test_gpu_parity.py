@@ -434,19 +434,27 @@ def _fused_run(case, T0, qx, qy, storage, rounding, fuse, steps, check, schedule
 
 
 def _fuse_max(storage):
-    lat = Lattice([instance_from_case(W.Case("probe", 8, 8, 0.6, 5.0))], storage=storage)
-    k = lat.step_fusion()
-    lat.close()
-    return k
+    return P.lbm_max_step_fusion(P.STORAGE[storage])
 
 
 @pytest.mark.parametrize("storage,kmax", [("f32", 6), ("f16", 4), ("bf16", 4), ("f16_split", 5),
                                           ("bf16_split", 4)])
 def test_step_fusion_range(storage, kmax):
-    """A new handle fuses up to its storage kind's most steps per launch;
-    1 .. that most are accepted, 0 and one more are refused."""
-    lat = Lattice([instance_from_case(W.Case("probe", 8, 8, 0.6, 5.0))], storage=storage)
+    """A new handle fuses up to its storage kind's most steps per launch when
+    its lattices fill the chip (at least 1024 strips of the fused kernel) and
+    runs single steps otherwise; 1 .. the most are accepted, 0 and one more
+    are refused."""
+    assert P.lbm_max_step_fusion(P.STORAGE[storage]) == kmax
+    width = 64 - 2 * kmax
+    big = W.Case("big", width * 32, 32 * 32, 0.6, 5.0)            # exactly 1024 strips
+    lat = Lattice([instance_from_case(big)], storage=storage)
     assert lat.step_fusion() == kmax
+    lat.close()
+    lat = Lattice([instance_from_case(W.Case("less", width * 31, 32 * 32, 0.6, 5.0))], storage=storage)
+    assert lat.step_fusion() == 1                                     # 31 x 32 strips
+    lat.close()
+    lat = Lattice([instance_from_case(W.Case("probe", 8, 8, 0.6, 5.0))], storage=storage)
+    assert lat.step_fusion() == 1
     for bad in (0, kmax + 1):
         with pytest.raises(LBMError) as e:
             lat.set_step_fusion(bad)
@@ -510,9 +518,12 @@ def test_autotune_choices_cache_and_results(tmp_path, monkeypatch):
     monkeypatch.setenv("LBM_AUTOTUNE_CACHE", str(cache))
     case, T0, qx, qy = _random_case(257, 130, 0.6, 7.0, 61)
     lat = Lattice([instance_from_case(case)], check_interval=10)
-    kmax = lat.step_fusion()
+    kmax = _fuse_max("f32")
     rep = json.loads(lat.autotune(6))
-    assert rep["cached"] is False and rep["steps_per_launch"] in (1, kmax)
+    assert rep["cached"] is False and 1 <= rep["steps_per_launch"] <= kmax
+    assert [k for k, _ in rep["fused_timings_us"]] == list(range(2, kmax + 1))
+    if rep["steps_per_launch"] > 1:
+        assert min(us for _, us in rep["fused_timings_us"]) == rep["fused_us_per_step"]
     assert lat.step_fusion() == rep["steps_per_launch"]
     best = rep["best"]
     got = lat.launch_shape()
