@@ -71,6 +71,9 @@ constexpr int kPairW3 = 60;
 #endif
 constexpr int kPairYO = PLBM3_PAIR_ROWS;
 constexpr int kPairNW = PLBM3_PAIR_WAVES;
+// Fewest two-step tiles (blocks) for which two steps per launch are the
+// default: one per CU.
+constexpr int64_t kPairMinTiles = 256;
 struct PairArgs {
     Geometry g;
     Coeffs c;

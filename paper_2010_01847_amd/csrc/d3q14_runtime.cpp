@@ -114,7 +114,16 @@ struct lbm3d_ctx {
     Layout3 L{};
     lbm3d_launch_shape shape{4, 1, 0, 1, 32};
     int fuse = 1;                // time steps per launch (1, or 2 with the z-marching kernel)
-    void set_default_fuse() { fuse = cfg.storage == LBM_F32 ? 2 : 1; }
+    // two steps per launch for FP32 storage when the z-marching tiles fill the
+    // chip (one block per CU): a launch takes about one tile's marching time,
+    // so small boxes run single steps (measured FP32 us per step, single / two:
+    // 64^3 5.3 / 37.1, 128^3 34.1 / 41.2 with 132 tiles, 192^3 137 / 124 with
+    // 384, 512^3 2730 / 1870)
+    void set_default_fuse() {
+        const int64_t tiles = (int64_t)((cfg.nx + kPairW3 - 1) / kPairW3) * ((cfg.ny + kPairYO - 1) / kPairYO) *
+                              ((cfg.nz + shape.zchunk - 1) / shape.zchunk);
+        fuse = (cfg.storage == LBM_F32 && tiles >= kPairMinTiles) ? 2 : 1;
+    }
     double tau = 0, beta = 1, s = 1, cv = 1;
     Coeffs co{};
     char* base = nullptr;
@@ -439,6 +448,8 @@ int lbm3d_set_step_fusion(lbm3d_handle h, int32_t steps) {
     h->fuse = steps;
     return LBM_OK;
 }
+
+int32_t lbm3d_get_step_fusion(lbm3d_handle h) { return valid3(h) ? h->fuse : -1; }
 
 int lbm3d_get_launch_shape(lbm3d_handle h, lbm3d_launch_shape* shape) {
     if (!valid3(h)) return LBM_EINVAL;

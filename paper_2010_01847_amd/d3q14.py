@@ -49,6 +49,7 @@ SIGNATURES3 = [
     ("lbm3d_set_launch_shape", ctypes.c_int, [_P, ctypes.POINTER(lbm3d_launch_shape)]),
     ("lbm3d_get_launch_shape", ctypes.c_int, [_P, ctypes.POINTER(lbm3d_launch_shape)]),
     ("lbm3d_set_step_fusion", ctypes.c_int, [_P, ctypes.c_int32]),
+    ("lbm3d_get_step_fusion", ctypes.c_int32, [_P]),
     ("lbm3d_autotune", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_char_p, ctypes.c_size_t]),
     ("lbm3d_destroy", None, [_P]),
 ]
@@ -128,6 +129,10 @@ def lbm3d_set_launch_shape(h, shape: lbm3d_launch_shape) -> None:
 
 def lbm3d_set_step_fusion(h, steps: int) -> None:
     _check(library().lbm3d_set_step_fusion(h, int(steps)), "lbm3d_set_step_fusion", h)
+
+
+def lbm3d_get_step_fusion(h) -> int:
+    return int(library().lbm3d_get_step_fusion(h))
 
 
 def lbm3d_get_launch_shape(h) -> lbm3d_launch_shape:
@@ -243,6 +248,9 @@ class Box:
 
     def set_step_fusion(self, steps: int) -> None:
         lbm3d_set_step_fusion(self.h, steps)
+
+    def step_fusion(self) -> int:
+        return lbm3d_get_step_fusion(self.h)
 
     def autotune(self, steps: int = 20) -> dict:
         """Pick the fastest launch shape (before init); returns the timing report."""

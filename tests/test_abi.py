@@ -212,6 +212,19 @@ def test_d3q14_config_validation(kw):
     assert e.value.code == P.LBM_EINVAL
 
 
+@pytest.mark.parametrize("n,storage,fuse", [(128, P.LBM_F32, 1), (192, P.LBM_F32, 2), (512, P.LBM_F32, 2),
+                                             (512, P.LBM_F16, 1)])
+def test_d3q14_default_step_fusion(n, storage, fuse):
+    """Two steps per launch by default for FP32 boxes holding at least 256
+    two-step blocks (60 x 12 x 32 nodes): 128^3 holds 132, 192^3 384."""
+    D = P.d3q14
+    h = D.lbm3d_create(_cfg3(nx=n, ny=n, nz=n, storage=storage))
+    try:
+        assert D.lbm3d_get_step_fusion(h) == fuse
+    finally:
+        D.lbm3d_destroy(h)
+
+
 def test_d3q14_handle_state_without_gpu():
     """Create and bind take no device action with external memory; stepping
     before init and bad launch shapes are rejected on the host."""
@@ -234,7 +247,9 @@ def test_d3q14_handle_state_without_gpu():
         for bad in (0, 3):
             with pytest.raises(P.LBMError):
                 D.lbm3d_set_step_fusion(h, bad)
+        assert D.lbm3d_get_step_fusion(h) == 1        # 16 x 8 x 4: too few two-step blocks
         D.lbm3d_set_step_fusion(h, 2)
+        assert D.lbm3d_get_step_fusion(h) == 2
         assert D.lbm3d_steps_done(h) == 0
         with pytest.raises(P.LBMError) as e:
             D.lbm3d_autotune(h, 2)           # no memory bound yet
@@ -243,4 +258,5 @@ def test_d3q14_handle_state_without_gpu():
         D.lbm3d_destroy(h)
     assert P.d3q14.library().lbm3d_step(None, 1) == P.LBM_EINVAL
     assert P.d3q14.library().lbm3d_steps_done(None) == -1
+    assert P.d3q14.library().lbm3d_get_step_fusion(None) == -1
     P.d3q14.library().lbm3d_destroy(None)
