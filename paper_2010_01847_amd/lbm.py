@@ -105,7 +105,7 @@ def library() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
-                               "(run __graft_entry__.build() or python -m paper_2010_01847_amd.build)")
+                               "(build it with python -m paper_2010_01847_amd.build)")
         L = ctypes.CDLL(LIB_PATH)
         for name, res, args in SIGNATURES:
             f = getattr(L, name)
