@@ -918,7 +918,10 @@ __device__ __forceinline__ void march_gather(const float dn_row[8], const float 
 // SNAP: the last of the K steps is the snapshot step before a check step; its
 // stage also writes the FP64 moments of its pulled nodes, as the single-step
 // kernels do on that step.
-template <class S, int SR, int SPLIT, int K, int KMAX, int SNAP>
+// CH: chunked layout, whose direction runs are kChunkPlane elements apart, so
+// that the eight loads or stores of a row share one address and differ by
+// immediate offsets.
+template <class S, int SR, int SPLIT, int K, int KMAX, int SNAP, int CH>
 __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int nontemporal, int64_t snap_stride) {
     static_assert(K >= 2 && K <= KMAX, "stages per launch");
     // input rows loaded ahead (measured on MI355X: two or three rows ahead are
@@ -952,6 +955,7 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
     const S* __restrict__ src = reinterpret_cast<const S*>(a.src) + d.off;
     S* __restrict__ dst = reinterpret_cast<S*>(a.dst) + d.off;
     const int64_t col = col_off(d, gx);
+    const int64_t plane = CH ? (int64_t)kChunkPlane : d.plane;
 
     // raw loads of input row yi (converted only where the row is used, so
     // the loads stay in flight across the iterations in between)
@@ -959,7 +963,7 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
         const int gy = wrapm(yi, ny, kMarchRows + 2 * K + PF);
         const S* row = src + (int64_t)gy * d.row;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = row[(int64_t)i * d.plane + col];
+        for (int i = 0; i < 8; ++i) v[i] = row[(int64_t)i * plane + col];
         E = SPLIT ? *reinterpret_cast<const float*>(reinterpret_cast<const char*>(row) + e_off(d, gx)) : 0.0f;
     };
 
@@ -1031,7 +1035,7 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
                         const int64_t c = col_off(d, ox);
 #pragma unroll
                         for (int i = 0; i < 8; ++i)
-                            store_raw<S>(reinterpret_cast<char*>(row + (int64_t)i * d.plane + c), o[i], nontemporal);
+                            store_raw<S>(reinterpret_cast<char*>(row + c + (int64_t)i * plane), o[i], nontemporal);
                         if (SPLIT) store_one<float, 0>(reinterpret_cast<char*>(row) + e_off(d, ox), E, 0u, nontemporal);
                     }
                 }
@@ -1057,54 +1061,57 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
     if (tg == 0 && lane == 0) a.ctr_out[0] = step + (uint32_t)K;
 }
 
-template <class S, int SPLIT, int K, int KMAX>
-static hipError_t launch_march_s(const Shape& sh, const StepArgs& a, int snap, int64_t snap_stride, hipStream_t st) {
+template <class S, int SR, int SPLIT, int K, int KMAX, int SNAP>
+static void launch_march_ch(const Shape& sh, const StepArgs& a, int chunked, int64_t snap_stride, hipStream_t st) {
     dim3 grid((a.ntiles + 3) / 4), block(256);
+    if (chunked)
+        hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, SNAP, 1>), grid, block, 0, st, a, sh.xcd, sh.nt,
+                           snap_stride);
+    else
+        hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, SNAP, 0>), grid, block, 0, st, a, sh.xcd, sh.nt,
+                           snap_stride);
+}
+
+template <class S, int SPLIT, int K, int KMAX>
+static hipError_t launch_march_s(const Shape& sh, const StepArgs& a, int snap, int chunked, int64_t snap_stride,
+                                 hipStream_t st) {
     if (a.sr) {
-        if (snap)
-            hipLaunchKernelGGL((march_kernel<S, 1, SPLIT, K, KMAX, 1>), grid, block, 0, st, a, sh.xcd, sh.nt,
-                               snap_stride);
-        else
-            hipLaunchKernelGGL((march_kernel<S, 1, SPLIT, K, KMAX, 0>), grid, block, 0, st, a, sh.xcd, sh.nt,
-                               snap_stride);
+        if (snap) launch_march_ch<S, 1, SPLIT, K, KMAX, 1>(sh, a, chunked, snap_stride, st);
+        else launch_march_ch<S, 1, SPLIT, K, KMAX, 0>(sh, a, chunked, snap_stride, st);
     } else {
-        if (snap)
-            hipLaunchKernelGGL((march_kernel<S, 0, SPLIT, K, KMAX, 1>), grid, block, 0, st, a, sh.xcd, sh.nt,
-                               snap_stride);
-        else
-            hipLaunchKernelGGL((march_kernel<S, 0, SPLIT, K, KMAX, 0>), grid, block, 0, st, a, sh.xcd, sh.nt,
-                               snap_stride);
+        if (snap) launch_march_ch<S, 0, SPLIT, K, KMAX, 1>(sh, a, chunked, snap_stride, st);
+        else launch_march_ch<S, 0, SPLIT, K, KMAX, 0>(sh, a, chunked, snap_stride, st);
     }
     return hipGetLastError();
 }
 
 template <class S, int SPLIT, int K, int KMAX>
-static hipError_t launch_march_k(const Shape& sh, const StepArgs& a, int k, int snap, int64_t snap_stride,
-                                 hipStream_t st) {
+static hipError_t launch_march_k(const Shape& sh, const StepArgs& a, int k, int snap, int chunked,
+                                 int64_t snap_stride, hipStream_t st) {
     if constexpr (K > KMAX) {
         return hipErrorInvalidValue;
     } else {
-        if (k == K) return launch_march_s<S, SPLIT, K, KMAX>(sh, a, snap, snap_stride, st);
-        return launch_march_k<S, SPLIT, K + 1, KMAX>(sh, a, k, snap, snap_stride, st);
+        if (k == K) return launch_march_s<S, SPLIT, K, KMAX>(sh, a, snap, chunked, snap_stride, st);
+        return launch_march_k<S, SPLIT, K + 1, KMAX>(sh, a, k, snap, chunked, snap_stride, st);
     }
 }
 
 template <class S, int SPLIT, int STORAGE>
-static hipError_t launch_fused_s(const Shape& sh, const StepArgs& a, int k, int snap, int64_t snap_stride,
-                                 hipStream_t st) {
-    return launch_march_k<S, SPLIT, 2, fuse_max(STORAGE)>(sh, a, k, snap, snap_stride, st);
+static hipError_t launch_fused_s(const Shape& sh, const StepArgs& a, int k, int snap, int chunked,
+                                 int64_t snap_stride, hipStream_t st) {
+    return launch_march_k<S, SPLIT, 2, fuse_max(STORAGE)>(sh, a, k, snap, chunked, snap_stride, st);
 }
 
-hipError_t launch_fused(int storage, const Shape& sh, const StepArgs& a, int k, int snap, int64_t snap_stride,
-                        hipStream_t st) {
+hipError_t launch_fused(int storage, const Shape& sh, const StepArgs& a, int k, int snap, int chunked,
+                        int64_t snap_stride, hipStream_t st) {
     if (a.ntiles <= 0) return hipSuccess;
     if (snap && !a.snap) return hipErrorInvalidValue;
     switch (storage) {
-        case 0: return launch_fused_s<float, 0, 0>(sh, a, k, snap, snap_stride, st);
-        case 1: return launch_fused_s<_Float16, 0, 1>(sh, a, k, snap, snap_stride, st);
-        case 2: return launch_fused_s<bf16_bits, 0, 2>(sh, a, k, snap, snap_stride, st);
-        case 3: return launch_fused_s<_Float16, 1, 3>(sh, a, k, snap, snap_stride, st);
-        case 4: return launch_fused_s<bf16_bits, 1, 4>(sh, a, k, snap, snap_stride, st);
+        case 0: return launch_fused_s<float, 0, 0>(sh, a, k, snap, chunked, snap_stride, st);
+        case 1: return launch_fused_s<_Float16, 0, 1>(sh, a, k, snap, chunked, snap_stride, st);
+        case 2: return launch_fused_s<bf16_bits, 0, 2>(sh, a, k, snap, chunked, snap_stride, st);
+        case 3: return launch_fused_s<_Float16, 1, 3>(sh, a, k, snap, chunked, snap_stride, st);
+        case 4: return launch_fused_s<bf16_bits, 1, 4>(sh, a, k, snap, chunked, snap_stride, st);
         default: return hipErrorInvalidValue;
     }
 }

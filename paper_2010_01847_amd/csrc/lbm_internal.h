@@ -129,6 +129,8 @@ enum StepMode { kPlain = 0, kSnap = 1, kCheck = 2 };
 // (single steps: 90 / 147 / 128 / 137 / 131).  Chunks of 64 or 128 rows
 // instead of 32: FP32 302 / 289 at six steps.
 constexpr int kMarchRows = 32;
+// Elements between direction runs in the chunked layout (64-node segments).
+constexpr int kChunkPlane = 64;
 __host__ __device__ constexpr int fuse_max(int storage) {
     return storage == 0 ? 6 : (storage == 3 ? 5 : 4);
 }
@@ -161,11 +163,12 @@ hipError_t launch_step(int storage, const Shape& sh, int mode, const StepArgs& a
 
 // k time steps (m .. m + k - 1, 2 <= k <= fuse_max(storage)) in one pass over
 // HBM: all plain, except that with snap != 0 the last one is the snapshot step
-// (its FP64 moments go to a.snap, snap_stride doubles per field);
+// (its FP64 moments go to a.snap, snap_stride doubles per field); chunked
+// != 0 for the chunked layout;
 // a.apply_shift refers to the first of them; a.tile_inst / tile_base / ntiles
 // index the fused tile table.  Same bits as k single steps.
-hipError_t launch_fused(int storage, const Shape& sh, const StepArgs& a, int k, int snap, int64_t snap_stride,
-                        hipStream_t st);
+hipError_t launch_fused(int storage, const Shape& sh, const StepArgs& a, int k, int snap, int chunked,
+                        int64_t snap_stride, hipStream_t st);
 
 // Moments of the state at time n of one instance.  With pull != 0 the state is
 // rebuilt from the post-relaxation populations of step n-1 (advection plus

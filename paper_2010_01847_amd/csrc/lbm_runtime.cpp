@@ -70,7 +70,7 @@ Geometry geometry_of(const lbm_instance& in, int es, int layout, bool split = fa
     if (split) {
         const int64_t nch = ((int64_t)in.nx + 63) / 64;
         g.row = nch * 640;
-        g.plane = 64;
+        g.plane = kChunkPlane;
         g.chunk = 640;
         g.cshift = 6;
         g.cmask = 63;
@@ -87,7 +87,7 @@ Geometry geometry_of(const lbm_instance& in, int es, int layout, bool split = fa
     } else {
         const int64_t nch = ((int64_t)in.nx + 63) / 64;
         g.row = nch * 512;
-        g.plane = 64;
+        g.plane = kChunkPlane;
         g.chunk = 512;
         g.cshift = 6;
         g.cmask = 63;
@@ -816,7 +816,8 @@ static int issue_fused(lbm_ctx* h, int64_t m, int nsteps, bool snap, int src_k, 
     a.apply_shift = (h->K > 0 && (m - 1) % h->K == 0) ? 1 : 0;
     a.tile_base = 0;
     a.ntiles = (int32_t)h->ptile_inst.size();
-    HIPCALL(h, launch_fused(h->storage, h->shape, a, nsteps, snap ? 1 : 0, h->L.nodes, st));
+    HIPCALL(h, launch_fused(h->storage, h->shape, a, nsteps, snap ? 1 : 0, h->layout == LBM_LAYOUT_CHUNKED,
+                            h->L.nodes, st));
     return LBM_OK;
 }
 
@@ -1200,7 +1201,7 @@ static int time_fused(lbm_ctx* h, int k, int launches, hipEvent_t e0, hipEvent_t
         a.dst = h->buf(1 - src);
         a.ctr_in = h->d_ctr() + src;
         a.ctr_out = h->d_ctr() + (1 - src);
-        HIPCALL(h, launch_fused(h->storage, h->shape, a, k, 0, 0, h->stream));
+        HIPCALL(h, launch_fused(h->storage, h->shape, a, k, 0, h->layout == LBM_LAYOUT_CHUNKED, 0, h->stream));
         src = 1 - src;
     }
     HIPCALL(h, hipEventRecord(e1, h->stream));
