@@ -16,9 +16,17 @@ rounding of the stores, which keeps smooth fields from stalling) of the same
 workload are reported under "rows".  "sweep" reports the batched Knudsen
 sweep (256 uneven channel instances in one handle) under the three
 schedules: one launch for all instances, the same captured in HIP graphs,
-and one launch per instance.  "d3q14" reports the three-dimensional lattice
-on a 512^3 periodic box (FP32, BF16 and FP16 storage) with its own roofline.  The oracle (plain FP64 C stepper) is timed on
-a bounded window of the same workload on the host cores ("cpu_baseline").
+and one launch per instance.  "large" reports the 16384^2 smooth-modes
+lattice with FP16 storage.  "d3q14" reports the three-dimensional lattice on
+a 512^3 periodic box (FP32, BF16 and FP16 storage) with its own roofline.
+The oracle (plain FP64 C stepper) is timed on a bounded window of the same
+workload on the host cores ("cpu_baseline").
+
+The dominant launch advances several steps per pass over HBM (temporal
+blocking), so the roofline's "achieved" (algorithmic bytes of the updates it
+performs over its duration) exceeds the HBM peak; "traffic" is the measured
+HBM bytes per launch, and "alu" states the same launch against the vector
+FP32 peak.
 """
 from __future__ import annotations
 
