@@ -155,8 +155,9 @@ typedef struct {
  * every node rounds the same way (the rounded map reaches a spurious fixed
  * point).  Stochastic rounding picks the upper or lower neighbour with
  * probability proportional to distance, so the stored state is unbiased.  The
- * random bits are a counter-based hash of (global node, step, direction, seed):
- * runs are deterministic and do not depend on launch shape or schedule.
+ * random bits are a counter-based hash of (column, row, step, direction, seed)
+ * (a column hash combined with a row-and-step hash): runs are deterministic
+ * and do not depend on launch shape or schedule.
  * FP32: the update is added exactly (two-sum) and the result rounded to one of
  * its two FP32 neighbours; FP16/BF16: random bits below the kept mantissa are
  * added before truncation.  Requires one node per lane (launch shape vec 1). */
@@ -277,7 +278,7 @@ int lbm_set_wall_flux(lbm_handle h, int32_t inst, int32_t wall, double q0);
  * the last step of an lbm_step call is advanced by one launch; 1 issues every
  * step on its own.  Results are identical for every
  * setting.  The most steps per launch depends on the storage kind (6 FP32,
- * 5 F16_SPLIT, 4 FP16, BF16 and BF16_SPLIT: lbm_max_step_fusion).  Default
+ * 5 F16_SPLIT, 4 FP16 and BF16_SPLIT, 3 BF16: lbm_max_step_fusion).  Default
  * for a new handle: that most when its instances hold at least 1024 strips of
  * the fused kernel in all (64 - 2 k columns by 32 rows each, k the most), so
  * that a fused launch fills the chip, else 1.  The per-instance schedule

@@ -467,6 +467,30 @@ __device__ __forceinline__ void store_raw(char* p, S o, int nontemporal) {
     else *q = raw;
 }
 
+// Random words of the stochastic-rounding stores.  Word k (16 bits for each
+// of directions 2k and 2k + 1) of node (x, y) at step n is
+//     col_word_k(x) ^ (row_word(y, n) * m_k),
+// col_word_k a hash of the column keyed by (k, seed), row_word a hash of the
+// global index of the row's first node keyed by (n, seed), m_k fixed odd
+// multipliers (m_0 = 1, a bijection of the row word).  Every word is uniform
+// and independent of the value it rounds (each rounding stays unbiased) and of
+// the words of other rows and steps; in one row and step, two columns' words
+// differ by a fixed pattern.  A pure function of (x, y, n, seed): every kernel
+// and schedule draws the same bits.  A wavefront that marches along y hashes
+// its columns once and each row once on the scalar unit.
+__device__ __forceinline__ uint32_t sr_col_word(uint32_t x, int k, uint32_t seed) {
+    return mix32(x ^ mix32(seed * 0x9e3779b9u + 0x632be5abu * (uint32_t)(k + 1)));
+}
+__device__ __forceinline__ uint32_t sr_row_word(uint32_t row_node, uint32_t step, uint32_t seed) {
+    return mix32(row_node ^ mix32(step * 0x85ebca6bu + seed * 0x9e3779b9u));
+}
+__device__ __forceinline__ void sr_words(uint32_t r[4], const uint32_t colw[4], uint32_t roww) {
+    r[0] = colw[0] ^ roww;
+    r[1] = colw[1] ^ (roww * 0x2c1b3c6du);
+    r[2] = colw[2] ^ (roww * 0x297a2d39u);
+    r[3] = colw[3] ^ (roww * 0x846ca68bu);
+}
+
 template <class S, int SR>
 __device__ __forceinline__ void store_one(char* p, float v, uint32_t r16, int nontemporal) {
     store_raw<S>(p, round_to<S, SR>(v, r16), nontemporal);
@@ -590,13 +614,13 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
             }
         }
         char* out = reinterpret_cast<char*>(a.dst) + d.off * (int64_t)sizeof(S) + (int64_t)y * rb;
-        // four 32-bit random words per node and step (SR): hash of the node
-        // index keyed by a hash of (step, word, seed)
+        // four 32-bit random words per node and step (SR), as in sr_words
         uint32_t r[4] = {0u, 0u, 0u, 0u};
         if (SR) {
-            const uint32_t node = (uint32_t)(d.node_off + (int64_t)y * nx + x);
+            uint32_t colw[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) r[k] = mix32(node ^ mix32(step * 4u + (uint32_t)k + a.seed * 0x9e3779b9u));
+            for (int k = 0; k < 4; ++k) colw[k] = sr_col_word((uint32_t)x, k, a.seed);
+            sr_words(r, colw, sr_row_word((uint32_t)(d.node_off + (int64_t)y * nx), step, a.seed));
         }
         if (SPLIT) {
             // h*_i = (g_i - omega_i E) + delta_i; the collision keeps E (the
@@ -861,11 +885,6 @@ __device__ __forceinline__ void reload(const S o[8], float E, float out[8]) {
     for (int i = 0; i < 8; ++i) out[i] = SPLIT ? Cvt<S>::ld(o[i]) + omega_e(i, E) : Cvt<S>::ld(o[i]);
 }
 
-__device__ __forceinline__ void sr_words(uint32_t r[4], uint32_t node, uint32_t step, uint32_t seed) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) r[k] = mix32(node ^ mix32(step * 4u + (uint32_t)k + seed * 0x9e3779b9u));
-}
-
 __device__ __forceinline__ bool on_wall(const InstDesc& d, int x, int y) {
     return ((d.bc_y != 0) && (y == 0 || y == d.ny - 1)) ||
            ((d.bc_x == 1 || d.bc_x == 2 || d.bc_x == 4) && (x == 0 || x == d.nx - 1));
@@ -956,6 +975,11 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
     S* __restrict__ dst = reinterpret_cast<S*>(a.dst) + d.off;
     const int64_t col = col_off(d, gx);
     const int64_t plane = CH ? (int64_t)kChunkPlane : d.plane;
+    uint32_t colw[4] = {0u, 0u, 0u, 0u};
+    if (SR) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) colw[k] = sr_col_word((uint32_t)gx, k, a.seed);
+    }
 
     // raw loads of input row yi (converted only where the row is used, so
     // the loads stay in flight across the iterations in between)
@@ -1008,7 +1032,9 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
                     if (s == 1 && a.apply_shift) apply_shift(g, rv);
                     if (on_wall(d, gx, gy)) boundary(g, d, rv.wall_kd, gx, gy);
                     uint32_t r[4] = {0u, 0u, 0u, 0u};
-                    if (SR) sr_words(r, (uint32_t)(d.node_off + (int64_t)gy * nx + gx), step + (uint32_t)(s - 1), a.seed);
+                    if (SR)
+                        sr_words(r, colw,
+                                 sr_row_word((uint32_t)(d.node_off + (int64_t)gy * nx), step + (uint32_t)(s - 1), a.seed));
                     S o[8];
                     float E;
                     relax_round<S, SR, SPLIT>(g, d, rv, r, o, E);
@@ -1026,8 +1052,9 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
                             a.snap[n + 2 * snap_stride] = qy;
                         }
                         uint32_t r[4] = {0u, 0u, 0u, 0u};
-                        if (SR) sr_words(r, (uint32_t)(d.node_off + (int64_t)oy * nx + ox), step + (uint32_t)(s - 1),
-                                         a.seed);
+                        if (SR)
+                            sr_words(r, colw,
+                                     sr_row_word((uint32_t)(d.node_off + (int64_t)oy * nx), step + (uint32_t)(s - 1), a.seed));
                         S o[8];
                         float E;
                         relax_round<S, SR, SPLIT>(g, d, rv, r, o, E);

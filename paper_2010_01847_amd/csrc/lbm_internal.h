@@ -127,12 +127,15 @@ enum StepMode { kPlain = 0, kSnap = 1, kCheck = 2 };
 //   7 / 7 / 5 / 6 / 6    293 / 199 / 217 / 245 / 190
 //   8 / 8 / 6 / 7 / 7    280 / 189 / 187 / 245 / 186
 // (single steps: 90 / 147 / 128 / 137 / 131).  Chunks of 64 or 128 rows
-// instead of 32: FP32 302 / 289 at six steps.
+// instead of 32: FP32 302 / 289 at six steps.  The stochastic-rounding words
+// drawn per column and row (device file) instead of per node moved the 16-bit
+// stochastic kinds: FP16-SR 282 / 326 / 317 and BF16-SR 259 / 252 / 247 at
+// 3 / 4 / 5 steps.
 constexpr int kMarchRows = 32;
 // Elements between direction runs in the chunked layout (64-node segments).
 constexpr int kChunkPlane = 64;
 __host__ __device__ constexpr int fuse_max(int storage) {
-    return storage == 0 ? 6 : (storage == 3 ? 5 : 4);
+    return storage == 0 ? 6 : (storage == 3 ? 5 : (storage == 2 ? 3 : 4));
 }
 __host__ __device__ constexpr int fused_width(int storage) { return 64 - 2 * fuse_max(storage); }
 // Fewest fused-kernel strips (wavefronts) over all instances for which fused

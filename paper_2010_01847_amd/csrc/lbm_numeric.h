@@ -58,8 +58,9 @@ template <> struct Cvt<bf16_bits> {
 // value, every node rounds the same way and the stored map freezes (a bias,
 // not noise).  Stochastic rounding moves to the upper or lower neighbour with
 // probabilities proportional to the distance, which is unbiased.  The random
-// bits come from a counter-based hash of (global node, step, direction), so a
-// run is deterministic and independent of the launch shape and schedule.
+// bits are a counter-based hash of the node's position, the step and the
+// direction, so a run is deterministic and independent of the launch shape and
+// schedule.
 
 // Integer finaliser "lowbias32" (C. Wellons, hash-prospector): a bijective
 // mix of 32 bits with low bias, two multiplies.
