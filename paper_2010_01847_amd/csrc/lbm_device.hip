@@ -852,7 +852,34 @@ __device__ __forceinline__ int wrapm(int v, int n, int span) {
 template <class S, int SR, int SPLIT>
 __device__ __forceinline__ void relax_round(float g[8], const InstDesc& d, const RefView& rv, const uint32_t r[4],
                                             S o[8], float& E_out) {
-    if (SPLIT) {
+    if constexpr (SPLIT && !SR && __is_same(S, bf16_bits)) {
+        // BF16 to nearest with one NaN test per node instead of a branch per
+        // value: round the eight shares as finite values, and redo them with
+        // the full conversion when the residual is not finite (a NaN or an
+        // infinity among them; the two differ only on a NaN).  Same bits.
+        float delta[8], hv[8];
+        relax_delta(g, d, rv, delta);
+        const float E = ((g[0] + g[2]) + (g[1] + g[3])) + ((g[4] + g[6]) + (g[5] + g[7]));
+        float res = 0.0f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            hv[i] = (g[i] - omega_e(i, E)) + delta[i];
+            const uint32_t u = __float_as_uint(hv[i]);
+            bf16_bits b;
+            b.b = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+            o[i] = b;
+            res = res + (hv[i] - Cvt<S>::ld(o[i]));
+        }
+        if (!(fabsf(res) <= 3.402823466e38f)) {
+            res = 0.0f;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                o[i] = Cvt<S>::st(hv[i]);
+                res = res + (hv[i] - Cvt<S>::ld(o[i]));
+            }
+        }
+        E_out = E + res;
+    } else if (SPLIT) {
         float delta[8];
         relax_delta(g, d, rv, delta);
         const float E = ((g[0] + g[2]) + (g[1] + g[3])) + ((g[4] + g[6]) + (g[5] + g[7]));
