@@ -1056,7 +1056,12 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
                 march_gather(cur, mid[s - 1], up2[s - 1], g);
                 if (s < K) {
                     const int gy = wrapm(yi - s, ny, kMarchRows + 2 * K + PF);
-                    if (s == 1 && a.apply_shift) apply_shift(g, rv);
+                    if (s == 1 && a.apply_shift) {
+                        // the empty asm keeps this a branch: as selects the
+                        // shift would run on every row of every lattice
+                        asm volatile("");
+                        apply_shift(g, rv);
+                    }
                     if (on_wall(d, gx, gy)) boundary(g, d, rv.wall_kd, gx, gy);
                     uint32_t r[4] = {0u, 0u, 0u, 0u};
                     if (SR)
