@@ -278,7 +278,7 @@ int lbm_set_wall_flux(lbm_handle h, int32_t inst, int32_t wall, double q0);
  * the last step of an lbm_step call is advanced by one launch; 1 issues every
  * step on its own.  Results are identical for every
  * setting.  The most steps per launch depends on the storage kind (6 FP32,
- * 4 FP16, F16_SPLIT and BF16_SPLIT, 3 BF16: lbm_max_step_fusion).  Default
+ * 4 for the 16-bit kinds: lbm_max_step_fusion).  Default
  * for a new handle: that most when its instances hold at least 1024 strips of
  * the fused kernel in all (64 - 2 k columns by 32 rows each, k the most), so
  * that a fused launch fills the chip, else 1.  The per-instance schedule

@@ -899,8 +899,25 @@ __device__ __forceinline__ void relax_round(float g[8], const InstDesc& d, const
         E_out = 0.0f;
     } else {
         relax(g, d, rv);
+        if constexpr (SR && __is_same(S, bf16_bits)) {
+            // one finiteness test per node (the sum of the eight is finite only
+            // if all are) instead of a NaN select per value; same bits
+            const float t = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]));
+            if (fabsf(t) <= 3.402823466e38f) {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) o[i] = round_to<S, SR>(g[i], bits16(r, i));
+                for (int i = 0; i < 8; ++i) {
+                    bf16_bits b;
+                    b.b = (uint16_t)((__float_as_uint(g[i]) + bits16(r, i)) >> 16);
+                    o[i] = b;
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) o[i] = round_to<S, SR>(g[i], bits16(r, i));
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) o[i] = round_to<S, SR>(g[i], bits16(r, i));
+        }
         E_out = 0.0f;
     }
 }

@@ -131,12 +131,13 @@ enum StepMode { kPlain = 0, kSnap = 1, kCheck = 2 };
 // drawn per column and row (device file) instead of per node moved the 16-bit
 // stochastic kinds: FP16-SR 282 / 326 / 317 and BF16-SR 259 / 252 / 247 at
 // 3 / 4 / 5 steps; after the branch changes of the rounding and the shift,
-// F16_SPLIT 289 / 275 / 263 at 4 / 5 / 6 steps.
+// F16_SPLIT 289 / 275 / 263 at 4 / 5 / 6 steps, and with one finiteness test
+// per node in the BF16 stochastic store, BF16-SR 291 / 309 / 304 at 3 / 4 / 5.
 constexpr int kMarchRows = 32;
 // Elements between direction runs in the chunked layout (64-node segments).
 constexpr int kChunkPlane = 64;
 __host__ __device__ constexpr int fuse_max(int storage) {
-    return storage == 0 ? 6 : (storage == 2 ? 3 : 4);
+    return storage == 0 ? 6 : 4;
 }
 __host__ __device__ constexpr int fused_width(int storage) { return 64 - 2 * fuse_max(storage); }
 // Fewest fused-kernel strips (wavefronts) over all instances for which fused

@@ -437,7 +437,7 @@ def _fuse_max(storage):
     return P.lbm_max_step_fusion(P.STORAGE[storage])
 
 
-@pytest.mark.parametrize("storage,kmax", [("f32", 6), ("f16", 4), ("bf16", 3), ("f16_split", 4),
+@pytest.mark.parametrize("storage,kmax", [("f32", 6), ("f16", 4), ("bf16", 4), ("f16_split", 4),
                                           ("bf16_split", 4)])
 def test_step_fusion_range(storage, kmax):
     """A new handle fuses up to its storage kind's most steps per launch when
@@ -494,7 +494,7 @@ def test_fused_kernel_bitwise(name, kw, storage, rounding):
                                    (70, 33), (113, 65), (117, 34)])
 def test_fused_kernel_small_and_ragged(nx, ny, storage):
     """Strips wider than the lattice (the window wraps several times), and
-    lattices one node past a strip edge (52, 56 or 58 output columns by kind)
+    lattices one node past a strip edge (52 or 56 output columns by kind)
     or a 32-row marching chunk, or two of them and one node: same bits as
     single steps for two and for the most steps per launch, and the oracle."""
     case, T0, qx, qy = _random_case(nx, ny, 0.8, 8.0, nx * 7 + ny)
