@@ -171,7 +171,8 @@ const char* lbm_version(void);
  * Valid until the next call on the handle. */
 const char* lbm_last_error(lbm_handle h);
 
-/* Device bytes a handle of this configuration needs (population buffers, the
+/* Device bytes a handle of this configuration needs (the two population
+ * buffers and a third one that readouts rebuild the last time step in, the
  * residual snapshot, reduction partials, tables). */
 int lbm_required_bytes(const lbm_config* cfg, size_t* bytes);
 
@@ -208,8 +209,11 @@ int lbm_init_device(lbm_handle h, int32_t inst, const double* T, const double* q
  * synchronisation).  Each step, per node: pull the eight populations along
  * c_i (periodic wrap, the GRADIENT ramp term omega_i C_V grad_x c_ix / s),
  * apply the boundary treatment to the unknown ones, form E = sum g_i and
- * j = sum c_i g_i, and relax (Eq. 13 with Eqs. 15-16).  At steps K-1 and K
- * (mod K) the FP64 snapshot and reductions of lbm_residual are taken.
+ * j = sum c_i g_i, and relax (Eq. 13 with Eqs. 15-16).  At every K-th step
+ * the FP64 residual and totals of lbm_residual are formed (from the moments
+ * of that step and the one before it).  Several steps may run in one launch
+ * (lbm_set_step_fusion), the last ones of the call included; the results do
+ * not depend on how the steps are grouped.
  * Errors: EINVAL (nsteps < 0), ESTATE (not initialised), EHIP. */
 int lbm_step(lbm_handle h, int64_t nsteps);
 
@@ -273,11 +277,13 @@ int lbm_set_wall_flux(lbm_handle h, int32_t inst, int32_t wall, double q0);
 
 /* Most time steps per launch where allowed (temporal blocking, Eq. 13 applied
  * k times to a tile before its populations go back to HBM, the intermediate
- * states rounded exactly as stored steps): a run of k >= 2 steps without a
- * check step (it may end on the snapshot step before one) that does not hold
- * the last step of an lbm_step call is advanced by one launch; 1 issues every
- * step on its own.  Results are identical for every
- * setting.  The most steps per launch depends on the storage kind (6 FP32,
+ * states rounded exactly as stored steps): a run of k >= 2 steps is advanced
+ * by one launch; a run ends at the latest on a check step (whose residual and
+ * totals the launch forms) or on the last step of an lbm_step call; 1 issues
+ * every step on its own.  Moments read after a call that ended on such a run
+ * are rebuilt by replaying its earlier steps once (same bits).  The populations
+ * are identical for every setting; the check-step residual and totals agree to
+ * the order of their FP64 summation.  The most steps per launch depends on the storage kind (6 FP32,
  * 4 for the 16-bit kinds: lbm_max_step_fusion).  Default
  * for a new handle: that most when its instances hold at least 1024 strips of
  * the fused kernel in all (64 - 2 k columns by 32 rows each, k the most), so

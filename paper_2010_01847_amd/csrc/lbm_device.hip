@@ -978,13 +978,23 @@ __device__ __forceinline__ void march_gather(const float dn_row[8], const float 
 
 // K <= KMAX: the window geometry depends on KMAX only, so launches of fewer
 // steps (before a check step or at the end of a call) use the same tile table.
-// SNAP: the last of the K steps is the snapshot step before a check step; its
-// stage also writes the FP64 moments of its pulled nodes, as the single-step
-// kernels do on that step.
+// END (how the launch ends):
+//   kEndPlain: K plain steps;
+//   kEndSnap : the last step is the snapshot step before a check step; its
+//              stage also writes the FP64 moments of its pulled nodes, as the
+//              single-step kernels do on that step;
+//   kEndCheck: the last step is the check step.  Stage K - 1 forms the FP64
+//              moments of its nodes (the state at time n - 1) and keeps them
+//              in registers for one iteration, until stage K reaches the same
+//              row; stage K forms the moments at time n and accumulates, per
+//              output node, the check-step sums (energy, heat flux, squared
+//              change and squared size of m = (dT, qx, qy)); each wavefront
+//              writes its five FP64 sums to a.partials at its tile index.  No
+//              snapshot goes through HBM.
 // CH: chunked layout, whose direction runs are kChunkPlane elements apart, so
 // that the eight loads or stores of a row share one address and differ by
 // immediate offsets.
-template <class S, int SR, int SPLIT, int K, int KMAX, int SNAP, int CH>
+template <class S, int SR, int SPLIT, int K, int KMAX, int END, int CH>
 __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int nontemporal, int64_t snap_stride) {
     static_assert(K >= 2 && K <= KMAX, "stages per launch");
     // input rows loaded ahead (measured on MI355X: two or three rows ahead are
@@ -1006,7 +1016,7 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
     const int inst = __builtin_amdgcn_readfirstlane(a.tile_inst[tg]);
     const InstDesc d = a.desc[inst];
     const RefView rv = ref_view(a.ref[inst]);
-    const double q_ref = SNAP ? a.ref[inst].q_ref : 0.0;
+    const double q_ref = END != kEndPlain ? a.ref[inst].q_ref : 0.0;
     const int local = tg - d.p_tile_begin;
     const int ty = local / d.p_tiles_x;
     const int tx = local - ty * d.p_tiles_x;
@@ -1044,6 +1054,11 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
 #pragma unroll
         for (int k = 0; k < 3; ++k) up1[l][k] = up2[l][k] = 0.0f;
     }
+    // check launch: moments of the stage K - 1 nodes of this iteration (new)
+    // and of the previous one (old, the row stage K reaches now), and the
+    // output nodes' check sums
+    double pm_new[3] = {0.0, 0.0, 0.0}, pm_old[3] = {0.0, 0.0, 0.0};
+    double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
     // rows yi .. yi + PF - 1 of the coming iterations, in flight
     S ring[PF][8];
     float ringE[PF];
@@ -1080,6 +1095,12 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
                         apply_shift(g, rv);
                     }
                     if (on_wall(d, gx, gy)) boundary(g, d, rv.wall_kd, gx, gy);
+                    if constexpr (END == kEndCheck) {
+                        if (s == K - 1) {
+                            double E;
+                            node_moments_f64(g, d, q_ref, E, pm_new[0], pm_new[1], pm_new[2]);
+                        }
+                    }
                     uint32_t r[4] = {0u, 0u, 0u, 0u};
                     if (SR)
                         sr_words(r, colw,
@@ -1092,13 +1113,24 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
                     const int ox = x0 + lane - KMAX, oy = yi - s;
                     if (lane >= KMAX && lane < KMAX + W && ox < nx) {
                         if (on_wall(d, ox, oy)) boundary(g, d, rv.wall_kd, ox, oy);
-                        if constexpr (SNAP != 0) {
+                        if constexpr (END == kEndSnap) {
                             double E, dT, qx, qy;
                             node_moments_f64(g, d, q_ref, E, dT, qx, qy);
                             const int64_t n = d.node_off + (int64_t)oy * nx + ox;
                             a.snap[n] = dT;
                             a.snap[n + snap_stride] = qx;
                             a.snap[n + 2 * snap_stride] = qy;
+                        } else if constexpr (END == kEndCheck) {
+                            // the same sums, in the same per-node form, as the
+                            // single-step check kernels
+                            double E, dT, qx, qy;
+                            node_moments_f64(g, d, q_ref, E, dT, qx, qy);
+                            const double p0 = pm_old[0], p1 = pm_old[1], p2 = pm_old[2];
+                            acc[0] += d.s * E;
+                            acc[1] += qx;
+                            acc[2] += qy;
+                            acc[3] += (dT - p0) * (dT - p0) + (qx - p1) * (qx - p1) + (qy - p2) * (qy - p2);
+                            acc[4] += dT * dT + qx * qx + qy * qy;
                         }
                         uint32_t r[4] = {0u, 0u, 0u, 0u};
                         if (SR)
@@ -1127,6 +1159,10 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
             if (s < K) {
 #pragma unroll
                 for (int i = 0; i < 8; ++i) cur[i] = out[i];
+            } else if constexpr (END == kEndCheck) {
+                // stage K has used the moments stage K - 1 formed one iteration ago
+#pragma unroll
+                for (int c = 0; c < 3; ++c) pm_old[c] = pm_new[c];
             }
         }
     };
@@ -1135,59 +1171,74 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
     for (; it < 2 * K; ++it) iteration(it, std::true_type{});
     for (; it < iters; ++it) iteration(it, std::false_type{});
     if (tg == 0 && lane == 0) a.ctr_out[0] = step + (uint32_t)K;
+    if constexpr (END == kEndCheck) {
+        // fixed-order wavefront sums; one record per tile (all 64 lanes are
+        // active here: a wavefront leaves early only as a whole)
+#pragma unroll
+        for (int c = 0; c < kPartials; ++c) acc[c] = wave_sum(acc[c]);
+        if (lane == 0) {
+#pragma unroll
+            for (int c = 0; c < kPartials; ++c) a.partials[(int64_t)tg * kPartials + c] = acc[c];
+        }
+    }
 }
 
-template <class S, int SR, int SPLIT, int K, int KMAX, int SNAP>
+template <class S, int SR, int SPLIT, int K, int KMAX, int END>
 static void launch_march_ch(const Shape& sh, const StepArgs& a, int chunked, int64_t snap_stride, hipStream_t st) {
     dim3 grid((a.ntiles + 3) / 4), block(256);
     if (chunked)
-        hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, SNAP, 1>), grid, block, 0, st, a, sh.xcd, sh.nt,
+        hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, END, 1>), grid, block, 0, st, a, sh.xcd, sh.nt,
                            snap_stride);
     else
-        hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, SNAP, 0>), grid, block, 0, st, a, sh.xcd, sh.nt,
+        hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, END, 0>), grid, block, 0, st, a, sh.xcd, sh.nt,
                            snap_stride);
 }
 
+template <class S, int SR, int SPLIT, int K, int KMAX>
+static void launch_march_e(const Shape& sh, const StepArgs& a, int end, int chunked, int64_t snap_stride,
+                           hipStream_t st) {
+    if (end == kEndSnap) launch_march_ch<S, SR, SPLIT, K, KMAX, kEndSnap>(sh, a, chunked, snap_stride, st);
+    else if (end == kEndCheck) launch_march_ch<S, SR, SPLIT, K, KMAX, kEndCheck>(sh, a, chunked, snap_stride, st);
+    else launch_march_ch<S, SR, SPLIT, K, KMAX, kEndPlain>(sh, a, chunked, snap_stride, st);
+}
+
 template <class S, int SPLIT, int K, int KMAX>
-static hipError_t launch_march_s(const Shape& sh, const StepArgs& a, int snap, int chunked, int64_t snap_stride,
+static hipError_t launch_march_s(const Shape& sh, const StepArgs& a, int end, int chunked, int64_t snap_stride,
                                  hipStream_t st) {
-    if (a.sr) {
-        if (snap) launch_march_ch<S, 1, SPLIT, K, KMAX, 1>(sh, a, chunked, snap_stride, st);
-        else launch_march_ch<S, 1, SPLIT, K, KMAX, 0>(sh, a, chunked, snap_stride, st);
-    } else {
-        if (snap) launch_march_ch<S, 0, SPLIT, K, KMAX, 1>(sh, a, chunked, snap_stride, st);
-        else launch_march_ch<S, 0, SPLIT, K, KMAX, 0>(sh, a, chunked, snap_stride, st);
-    }
+    if (a.sr) launch_march_e<S, 1, SPLIT, K, KMAX>(sh, a, end, chunked, snap_stride, st);
+    else launch_march_e<S, 0, SPLIT, K, KMAX>(sh, a, end, chunked, snap_stride, st);
     return hipGetLastError();
 }
 
 template <class S, int SPLIT, int K, int KMAX>
-static hipError_t launch_march_k(const Shape& sh, const StepArgs& a, int k, int snap, int chunked,
+static hipError_t launch_march_k(const Shape& sh, const StepArgs& a, int k, int end, int chunked,
                                  int64_t snap_stride, hipStream_t st) {
     if constexpr (K > KMAX) {
         return hipErrorInvalidValue;
     } else {
-        if (k == K) return launch_march_s<S, SPLIT, K, KMAX>(sh, a, snap, chunked, snap_stride, st);
-        return launch_march_k<S, SPLIT, K + 1, KMAX>(sh, a, k, snap, chunked, snap_stride, st);
+        if (k == K) return launch_march_s<S, SPLIT, K, KMAX>(sh, a, end, chunked, snap_stride, st);
+        return launch_march_k<S, SPLIT, K + 1, KMAX>(sh, a, k, end, chunked, snap_stride, st);
     }
 }
 
 template <class S, int SPLIT, int STORAGE>
-static hipError_t launch_fused_s(const Shape& sh, const StepArgs& a, int k, int snap, int chunked,
+static hipError_t launch_fused_s(const Shape& sh, const StepArgs& a, int k, int end, int chunked,
                                  int64_t snap_stride, hipStream_t st) {
-    return launch_march_k<S, SPLIT, 2, fuse_max(STORAGE)>(sh, a, k, snap, chunked, snap_stride, st);
+    return launch_march_k<S, SPLIT, 2, fuse_max(STORAGE)>(sh, a, k, end, chunked, snap_stride, st);
 }
 
-hipError_t launch_fused(int storage, const Shape& sh, const StepArgs& a, int k, int snap, int chunked,
+hipError_t launch_fused(int storage, const Shape& sh, const StepArgs& a, int k, int end, int chunked,
                         int64_t snap_stride, hipStream_t st) {
     if (a.ntiles <= 0) return hipSuccess;
-    if (snap && !a.snap) return hipErrorInvalidValue;
+    if (end == kEndSnap && !a.snap) return hipErrorInvalidValue;
+    if (end == kEndCheck && !a.partials) return hipErrorInvalidValue;
+    if (end < kEndPlain || end > kEndCheck) return hipErrorInvalidValue;
     switch (storage) {
-        case 0: return launch_fused_s<float, 0, 0>(sh, a, k, snap, chunked, snap_stride, st);
-        case 1: return launch_fused_s<_Float16, 0, 1>(sh, a, k, snap, chunked, snap_stride, st);
-        case 2: return launch_fused_s<bf16_bits, 0, 2>(sh, a, k, snap, chunked, snap_stride, st);
-        case 3: return launch_fused_s<_Float16, 1, 3>(sh, a, k, snap, chunked, snap_stride, st);
-        case 4: return launch_fused_s<bf16_bits, 1, 4>(sh, a, k, snap, chunked, snap_stride, st);
+        case 0: return launch_fused_s<float, 0, 0>(sh, a, k, end, chunked, snap_stride, st);
+        case 1: return launch_fused_s<_Float16, 0, 1>(sh, a, k, end, chunked, snap_stride, st);
+        case 2: return launch_fused_s<bf16_bits, 0, 2>(sh, a, k, end, chunked, snap_stride, st);
+        case 3: return launch_fused_s<_Float16, 1, 3>(sh, a, k, end, chunked, snap_stride, st);
+        case 4: return launch_fused_s<bf16_bits, 1, 4>(sh, a, k, end, chunked, snap_stride, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1304,16 +1355,20 @@ __device__ void reduce_records(const double* __restrict__ partials, int64_t firs
         for (int c = 0; c < kPartials; ++c) out[c] = red[0][c];
 }
 
-// First stage: group b of the tile records of its instance.
+// First stage: group b of the tile records of its instance.  fused != 0:
+// records of the fused kernel's tiles (strips), else of the single-step tiles.
 __global__ __launch_bounds__(256) void group_reduce_kernel(const InstDesc* __restrict__ descs,
                                                            const int32_t* __restrict__ group_inst,
                                                            const double* __restrict__ partials,
-                                                           double* __restrict__ gpart) {
+                                                           double* __restrict__ gpart, int fused) {
     const int b = blockIdx.x;
     const InstDesc& d = descs[group_inst[b]];
-    const int j = b - d.group_begin;
-    const int rest = d.ntiles - j * kGroup;
-    reduce_records(partials, (int64_t)d.tile_begin + (int64_t)j * kGroup, rest < kGroup ? rest : kGroup,
+    const int gb = fused ? d.p_group_begin : d.group_begin;
+    const int tb = fused ? d.p_tile_begin : d.tile_begin;
+    const int nt = fused ? d.p_ntiles : d.ntiles;
+    const int j = b - gb;
+    const int rest = nt - j * kGroup;
+    reduce_records(partials, (int64_t)tb + (int64_t)j * kGroup, rest < kGroup ? rest : kGroup,
                    gpart + (int64_t)b * kPartials);
 }
 
@@ -1321,16 +1376,19 @@ __global__ __launch_bounds__(256) void group_reduce_kernel(const InstDesc* __res
 // instances) the move of the reference flux to the mean flux of the state just
 // checked.  The shift is rounded to FP32 first and J is moved by the rounded
 // amount (in FP64), so J and the stored populations stay consistent;
-// shift_d = shift_a / 4 is exact.
+// shift_d = shift_a / 4 is exact.  The reference state in force before the
+// move is kept in refs_prev (the steps up to the check step ran with it).
 __global__ __launch_bounds__(256) void finalize_kernel(const InstDesc* __restrict__ descs,
                                                        RefState* __restrict__ refs,
+                                                       RefState* __restrict__ refs_prev,
                                                        const double* __restrict__ gpart,
-                                                       double* __restrict__ results) {
+                                                       double* __restrict__ results, int fused) {
     const InstDesc& d = descs[blockIdx.x];
     double* out = results + (int64_t)blockIdx.x * kPartials;
-    reduce_records(gpart, d.group_begin, d.ngroups, out);
+    reduce_records(gpart, fused ? d.p_group_begin : d.group_begin, fused ? d.p_ngroups : d.ngroups, out);
     if (threadIdx.x != 0) return;
     RefState& r = refs[blockIdx.x];
+    refs_prev[blockIdx.x] = r;
     if (!r.adapt) return;
     // mean heat flux = beta (mean first moment); reference's first moment J + j_b
     const double target = out[1] * r.inv_nodes / r.beta - r.jb;
@@ -1354,10 +1412,12 @@ __global__ __launch_bounds__(256) void range_reduce_kernel(const double* __restr
 }
 
 hipError_t launch_finalize(const InstDesc* d_desc, const int32_t* group_inst, int ngroups, RefState* d_ref,
-                           int ninst, const double* partials, double* gpart, double* results,
-                           hipStream_t st) {
-    hipLaunchKernelGGL(group_reduce_kernel, dim3(ngroups), dim3(256), 0, st, d_desc, group_inst, partials, gpart);
-    hipLaunchKernelGGL(finalize_kernel, dim3(ninst), dim3(256), 0, st, d_desc, d_ref, gpart, results);
+                           RefState* d_ref_prev, int ninst, const double* partials, double* gpart,
+                           double* results, int fused, hipStream_t st) {
+    hipLaunchKernelGGL(group_reduce_kernel, dim3(ngroups), dim3(256), 0, st, d_desc, group_inst, partials, gpart,
+                       fused);
+    hipLaunchKernelGGL(finalize_kernel, dim3(ninst), dim3(256), 0, st, d_desc, d_ref, d_ref_prev, gpart, results,
+                       fused);
     return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@ constexpr int kMaxBlock = 512;     // threads per block upper bound (launch boun
 constexpr int kPartials = 5;       // per-tile FP64 partials: sum dE, sum qx, sum qy, |dm|^2, |m|^2
 constexpr int kGroup = 1024;       // tile records per first-stage reduction block
 
-// Per-instance descriptor, resident in device memory (one 192-byte record).
+// Per-instance descriptor, resident in device memory (one 256-byte record).
 //
 // Element address of direction i at node (x, y):
 //     off + y * row + (x >> cshift) * chunk + (x & cmask) + i * plane
@@ -36,6 +36,8 @@ struct alignas(64) InstDesc {
     int32_t p_tiles_x;      // fused kernel: strips along x (fused_width columns each)
     int32_t p_tile_begin;   // fused kernel: first global tile of this instance
     int32_t p_ntiles;       // fused kernel: tiles of this instance
+    int32_t p_group_begin;  // fused kernel: first reduction group (kGroup of its tiles each)
+    int32_t p_ngroups;      // fused kernel: reduction groups of this instance
     int64_t row;            // elements between rows
     int64_t plane;          // elements between direction runs
     int64_t chunk;          // elements between 64-node chunks (0: planes layout)
@@ -50,7 +52,7 @@ struct alignas(64) InstDesc {
     double s;               // storage scale
     double cv;
 };
-static_assert(sizeof(InstDesc) == 192, "descriptor layout");
+static_assert(sizeof(InstDesc) == 256, "descriptor layout");
 
 // Reference state of the stored deviations, one per instance, in device
 // memory (kept apart from InstDesc: the device updates it, the host does not
@@ -109,6 +111,10 @@ struct Shape {
 };
 
 enum StepMode { kPlain = 0, kSnap = 1, kCheck = 2 };
+// How a fused launch ends (see march_kernel): plain steps only, on the
+// snapshot step (FP64 moments written to the snapshot), or on the check step
+// (the snapshot kept in registers, per-tile check sums written).
+enum FusedEnd { kEndPlain = 0, kEndSnap = 1, kEndCheck = 2 };
 
 // Fused kernel (several time steps per pass over HBM, temporal blocking): a
 // wavefront takes a strip of fused_width output columns (a window of 64
@@ -167,12 +173,14 @@ hipError_t launch_step(int storage, const Shape& sh, int mode, const StepArgs& a
                        int64_t snap_stride, hipStream_t st);
 
 // k time steps (m .. m + k - 1, 2 <= k <= fuse_max(storage)) in one pass over
-// HBM: all plain, except that with snap != 0 the last one is the snapshot step
-// (its FP64 moments go to a.snap, snap_stride doubles per field); chunked
-// != 0 for the chunked layout;
-// a.apply_shift refers to the first of them; a.tile_inst / tile_base / ntiles
-// index the fused tile table.  Same bits as k single steps.
-hipError_t launch_fused(int storage, const Shape& sh, const StepArgs& a, int k, int snap, int chunked,
+// HBM, ending as `end` (FusedEnd) says: kEndSnap, the last one is the snapshot
+// step (its FP64 moments go to a.snap, snap_stride doubles per field);
+// kEndCheck, the last one is the check step (kPartials check sums per fused
+// tile go to a.partials, for launch_finalize with fused != 0); chunked != 0
+// for the chunked layout; a.apply_shift refers to the first of them;
+// a.tile_inst / tile_base / ntiles index the fused tile table.  Same bits as k
+// single steps (the check sums equal theirs up to the order of summation).
+hipError_t launch_fused(int storage, const Shape& sh, const StepArgs& a, int k, int end, int chunked,
                         int64_t snap_stride, hipStream_t st);
 
 // Moments of the state at time n of one instance.  With pull != 0 the state is
@@ -195,11 +203,14 @@ hipError_t launch_init(int storage, const InstDesc* d_desc, const RefState* d_re
 // Deterministic per-instance reduction of tile partials into results
 // (kPartials doubles per instance), in two fixed-order stages: groups of
 // kGroup tile records (group_inst: group -> instance, ngroups in total) into
-// gpart, then one block per instance over its groups.  The second stage also
-// moves each adaptive instance's reference flux to its mean heat flux.
+// gpart, then one block per instance over its groups.  fused != 0: the
+// records are per fused-kernel tile (InstDesc p_* fields), else per
+// single-step tile.  The second stage copies each instance's reference state
+// to d_ref_prev and then moves an adaptive instance's reference flux to its
+// mean heat flux.
 hipError_t launch_finalize(const InstDesc* d_desc, const int32_t* group_inst, int ngroups, RefState* d_ref,
-                           int ninst, const double* partials, double* gpart, double* results,
-                           hipStream_t st);
+                           RefState* d_ref_prev, int ninst, const double* partials, double* gpart,
+                           double* results, int fused, hipStream_t st);
 
 // One-thread kernel writing *dst = v on the stream (stream-ordered updates of
 // descriptor fields between steps).

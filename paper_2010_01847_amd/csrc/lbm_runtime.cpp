@@ -203,10 +203,11 @@ int64_t max_groups(const std::vector<lbm_instance>& v) {
 
 struct Layout {
     size_t buf_bytes = 0;      // one population buffer
-    size_t off_buf[2] = {0, 0};
+    size_t off_buf[3] = {0, 0, 0};   // ping-pong pair, and the readout buffer (see replay_tail)
     size_t off_snap = 0, off_part = 0, off_res = 0, off_mpart = 0, off_mres = 0, off_desc = 0,
-           off_ref = 0, off_tiles = 0, off_ptiles = 0, off_groups = 0, off_gpart = 0, off_ctr = 0, total = 0;
-    int64_t nodes = 0, tiles_max = 0, mparts_max = 0, groups_max = 0, ptiles = 0;
+           off_desc_prev = 0, off_ref = 0, off_ref_prev = 0, off_tiles = 0, off_ptiles = 0, off_groups = 0,
+           off_pgroups = 0, off_gpart = 0, off_ctr = 0, total = 0;
+    int64_t nodes = 0, tiles_max = 0, mparts_max = 0, groups_max = 0, ptiles = 0, pgroups = 0;
 };
 
 Layout layout_of(const std::vector<lbm_instance>& v, int storage, int check, int layout) {
@@ -222,24 +223,35 @@ Layout layout_of(const std::vector<lbm_instance>& v, int storage, int check, int
     L.tiles_max = max_tiles(v);
     L.groups_max = max_groups(v);
     const int ph = kMarchRows;
-    for (auto& in : v) L.ptiles += fused_tiles_x(in, storage) * (int64_t)((in.ny + ph - 1) / ph);
-    // the same scratch serves the first stage of lbm_totals' reduction
-    const int64_t gscratch = std::max<int64_t>(L.groups_max, (L.mparts_max + kGroup - 1) / kGroup);
+    for (auto& in : v) {
+        const int64_t pt = fused_tiles_x(in, storage) * (int64_t)((in.ny + ph - 1) / ph);
+        L.ptiles += pt;
+        L.pgroups += (pt + kGroup - 1) / kGroup;
+    }
+    // check-step records: per single-step tile or per fused-kernel tile
+    const int64_t records = std::max(L.tiles_max, L.ptiles);
+    // the same scratch serves the first stage of every check reduction and of
+    // lbm_totals' reduction
+    const int64_t gscratch = std::max({L.groups_max, L.pgroups, (L.mparts_max + kGroup - 1) / kGroup});
     size_t o = 0;
     L.off_buf[0] = o; o += L.buf_bytes;
     L.off_buf[1] = o; o += L.buf_bytes;
+    L.off_buf[2] = o; o += L.buf_bytes;
     L.off_snap = o; o += check ? align_up(3 * (size_t)L.nodes * sizeof(double), kAlign) : 0;
-    L.off_part = o; o += align_up((size_t)L.tiles_max * kPartials * sizeof(double), kAlign);
+    L.off_part = o; o += align_up((size_t)records * kPartials * sizeof(double), kAlign);
     L.off_res = o; o += align_up(v.size() * kPartials * sizeof(double), kAlign);
     L.off_mpart = o; o += align_up((size_t)L.mparts_max * kPartials * sizeof(double), kAlign);
     L.off_mres = o; o += align_up(kPartials * sizeof(double), kAlign);
     L.off_desc = o; o += align_up(v.size() * sizeof(InstDesc), kAlign);
+    L.off_desc_prev = o; o += align_up(v.size() * sizeof(InstDesc), kAlign);
     L.off_ref = o; o += align_up(v.size() * sizeof(RefState), kAlign);
+    L.off_ref_prev = o; o += align_up(v.size() * sizeof(RefState), kAlign);
     L.off_tiles = o; o += align_up((size_t)L.tiles_max * sizeof(int32_t), kAlign);
     L.off_ptiles = o; o += align_up((size_t)L.ptiles * sizeof(int32_t), kAlign);
     L.off_groups = o; o += align_up((size_t)L.groups_max * sizeof(int32_t), kAlign);
+    L.off_pgroups = o; o += align_up((size_t)L.pgroups * sizeof(int32_t), kAlign);
     L.off_gpart = o; o += align_up((size_t)gscratch * kPartials * sizeof(double), kAlign);
-    L.off_ctr = o; o += kAlign;                 // two 32-bit step counters (ping-pong)
+    L.off_ctr = o; o += kAlign;                 // 32-bit step counters: ping-pong pair and the readout's
     L.total = o;
     return L;
 }
@@ -269,8 +281,26 @@ struct lbm_ctx {
     std::vector<int32_t> group_inst;
     int64_t ngroups = 0;
     std::vector<int32_t> ptile_inst;   // fused kernel: tile -> instance
+    std::vector<int32_t> pgroup_inst;  // fused kernel: reduction group -> instance
+    int64_t npgroups = 0;
     int fuse = 1;                      // most time steps per launch where allowed (1 .. fuse_max)
     int graph_flips = 0;               // buffer swaps of one captured chunk
+    // The last launch of the steps issued so far, when it advanced k >= 2
+    // steps: the post-relaxation state of step n - 1, from which the moments
+    // at time n are rebuilt, was never written, so a readout first replays
+    // steps n - k + 1 .. n - 1 from the launch's source buffer (still intact
+    // until the next step) into the readout buffer.
+    struct Tail {
+        int k = 0;             // steps of the last launch (0: the last launch was a single step)
+        int src = 0;           // buffer that launch read
+        int apply_shift = 0;   // its first step applied the pending reference shift
+        int checked = 0;       // it ended on a check step (the reference moved after it)
+    } tail, graph_tail;
+    int graph_tail_flip = 0;           // launches of a captured chunk before its last one, mod 2
+    bool replayed = false;             // the readout buffer holds the replayed state
+    bool desc_saved = false;           // d_desc_prev holds the descriptors of the last step
+    std::vector<std::array<float, 4>> wall_q_last;   // their heat-flux terms (the only field that differs)
+    std::vector<InstDesc> desc_prev_host;            // host source of d_desc_prev uploads
     bool external = false;
     char* base = nullptr;            // device memory (owned unless external)
     bool owned = false;
@@ -287,8 +317,15 @@ struct lbm_ctx {
 
     char* ptr(size_t off) const { return base + off; }
     void* buf(int k) const { return base + L.off_buf[k]; }
+    static constexpr int kReadout = 2;   // index of the readout buffer and of its step counter
     InstDesc* d_desc() const { return reinterpret_cast<InstDesc*>(base + L.off_desc); }
     RefState* d_ref() const { return reinterpret_cast<RefState*>(base + L.off_ref); }
+    RefState* d_ref_prev() const { return reinterpret_cast<RefState*>(base + L.off_ref_prev); }
+    InstDesc* d_desc_prev() const { return reinterpret_cast<InstDesc*>(base + L.off_desc_prev); }
+    int32_t* d_pgroups() const { return reinterpret_cast<int32_t*>(base + L.off_pgroups); }
+    // descriptors the last issued step ran with (a heat-flux change since then
+    // applies to later steps only)
+    const InstDesc* d_desc_last() const { return desc_saved ? d_desc_prev() : d_desc(); }
     int32_t* d_tiles() const { return reinterpret_cast<int32_t*>(base + L.off_tiles); }
     int32_t* d_ptiles() const { return reinterpret_cast<int32_t*>(base + L.off_ptiles); }
     int32_t* d_groups() const { return reinterpret_cast<int32_t*>(base + L.off_groups); }
@@ -336,6 +373,8 @@ static void build_tiles(lbm_ctx* h) {
     h->tile_inst.clear();
     h->group_inst.clear();
     h->ptile_inst.clear();
+    h->pgroup_inst.clear();
+    h->npgroups = 0;
     for (size_t k = 0; k < h->inst.size(); ++k) {
         InstDesc& d = h->desc[k];
         const int tw = s.tile_w();
@@ -353,6 +392,10 @@ static void build_tiles(lbm_ctx* h) {
         d.p_tile_begin = (int32_t)h->ptile_inst.size();
         d.p_ntiles = d.p_tiles_x * ((d.ny + kMarchRows - 1) / kMarchRows);
         h->ptile_inst.insert(h->ptile_inst.end(), (size_t)d.p_ntiles, (int32_t)k);
+        d.p_group_begin = (int32_t)h->npgroups;
+        d.p_ngroups = (d.p_ntiles + kGroup - 1) / kGroup;
+        h->npgroups += d.p_ngroups;
+        h->pgroup_inst.insert(h->pgroup_inst.end(), (size_t)d.p_ngroups, (int32_t)k);
     }
 }
 
@@ -362,11 +405,22 @@ static void build_tiles(lbm_ctx* h) {
 static int upload_tables(lbm_ctx* h) {
     HIPCALL(h, hipMemcpyAsync(h->d_desc(), h->desc.data(), h->desc.size() * sizeof(InstDesc),
                               hipMemcpyHostToDevice, h->stream));
+    if (h->desc_saved) {
+        // the saved descriptors follow the new tile tables too; only their
+        // heat-flux terms are those of the last step
+        h->desc_prev_host = h->desc;
+        for (size_t k = 0; k < h->desc.size(); ++k)
+            for (int w = 0; w < 4; ++w) h->desc_prev_host[k].wall_q[w] = h->wall_q_last[k][w];
+        HIPCALL(h, hipMemcpyAsync(h->d_desc_prev(), h->desc_prev_host.data(), h->desc.size() * sizeof(InstDesc),
+                                  hipMemcpyHostToDevice, h->stream));
+    }
     HIPCALL(h, hipMemcpyAsync(h->d_tiles(), h->tile_inst.data(), h->tile_inst.size() * sizeof(int32_t),
                               hipMemcpyHostToDevice, h->stream));
     HIPCALL(h, hipMemcpyAsync(h->d_groups(), h->group_inst.data(), h->group_inst.size() * sizeof(int32_t),
                               hipMemcpyHostToDevice, h->stream));
     HIPCALL(h, hipMemcpyAsync(h->d_ptiles(), h->ptile_inst.data(), h->ptile_inst.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, h->stream));
+    HIPCALL(h, hipMemcpyAsync(h->d_pgroups(), h->pgroup_inst.data(), h->pgroup_inst.size() * sizeof(int32_t),
                               hipMemcpyHostToDevice, h->stream));
     HIPCALL(h, hipStreamSynchronize(h->stream));
     return LBM_OK;
@@ -425,6 +479,8 @@ static int upload_ref(lbm_ctx* h, int k) {
     const size_t first = k < 0 ? 0 : (size_t)k;
     const size_t n = k < 0 ? h->ref.size() : 1;
     HIPCALL(h, hipMemcpyAsync(h->d_ref() + first, h->ref.data() + first, n * sizeof(RefState),
+                              hipMemcpyHostToDevice, h->stream));
+    HIPCALL(h, hipMemcpyAsync(h->d_ref_prev() + first, h->ref.data() + first, n * sizeof(RefState),
                               hipMemcpyHostToDevice, h->stream));
     HIPCALL(h, hipStreamSynchronize(h->stream));
     return LBM_OK;
@@ -662,6 +718,8 @@ static int do_init(lbm_ctx* h, int32_t k, const double* dT, const double* dqx, c
                               hipMemcpyHostToDevice, h->stream));
     HIPCALL(h, hipMemcpyAsync(h->d_ref() + k, &h->ref[k], sizeof(RefState), hipMemcpyHostToDevice,
                               h->stream));
+    HIPCALL(h, hipMemcpyAsync(h->d_ref_prev() + k, &h->ref[k], sizeof(RefState), hipMemcpyHostToDevice,
+                              h->stream));
     const double grad = in.bc_x == LBM_BC_GRADIENT ? in.grad_x : 0.0;
     HIPCALL(h, launch_init(h->storage, h->d_desc(), h->d_ref(), k, d, h->buf(1 - h->cur), h->buf(h->cur),
                            dT, dqx, dqy, in.t0, grad, h->co[k].beta, h->stream));
@@ -674,6 +732,9 @@ static int do_init(lbm_ctx* h, int32_t k, const double* dT, const double* dqx, c
     }
     h->last_check = -1;
     h->inited[k] = 1;
+    h->tail = lbm_ctx::Tail();
+    h->replayed = false;
+    h->desc_saved = false;
     h->drop_graphs();
     return LBM_OK;
 }
@@ -769,45 +830,49 @@ static int issue_step(lbm_ctx* h, int64_t m, int src_k, hipStream_t st, int sche
         HIPCALL(h, launch_step(h->storage, h->shape, mode, a, h->L.nodes, st));
     }
     if (mode == kCheck)
-        HIPCALL(h, launch_finalize(h->d_desc(), h->d_groups(), (int)h->ngroups, h->d_ref(), (int)h->inst.size(),
-                                   h->d_part(), h->d_gpart(), h->d_res(), st));
+        HIPCALL(h, launch_finalize(h->d_desc(), h->d_groups(), (int)h->ngroups, h->d_ref(), h->d_ref_prev(),
+                                   (int)h->inst.size(), h->d_part(), h->d_gpart(), h->d_res(), 0, st));
     return LBM_OK;
 }
 
-// Steps the launch that starts at step m covers: up to h->fuse consecutive
-// steps without check-step work, the last of which may be the snapshot step
-// (the fused kernel writes its snapshot), none of them the last step of the
-// sequence being issued (`last`), so the post-relaxation state of the step
-// before the last one is in a buffer when the sequence ends (the moments of
-// the final state are rebuilt from it).  Returns 1 for a single-step launch;
-// *snap tells whether the run ends on the snapshot step.
-static int fused_steps(const lbm_ctx* h, int64_t m, int64_t last, bool* snap) {
-    int k = 0;
-    *snap = false;
-    while (k < h->fuse && m + k < last) {
-        const int mode = mode_of(h, m + k);
-        if (mode == kCheck) break;
-        ++k;
-        if (mode == kSnap) {
-            *snap = true;
-            break;
+// Steps the launch that starts at step m covers, in a sequence of steps that
+// ends at step `last`: up to h->fuse consecutive steps, ending at the latest
+// on the next check step (whose residual and totals the fused kernel then
+// forms: *end = kEndCheck) or on `last`; a run cut short by h->fuse may end on
+// the snapshot step before a check step (*end = kEndSnap: the fused kernel
+// writes the snapshot for the single check step that follows).  A check step
+// is not left alone behind a full run: one step fewer leaves two for a fused
+// check launch, which costs less than a single check step (the fused form
+// keeps the snapshot in registers).  Returns 1 for a single-step launch.
+static int plan_launch(const lbm_ctx* h, int64_t m, int64_t last, int* end) {
+    *end = kEndPlain;
+    if (h->fuse < 2) return 1;
+    int64_t seg = last;
+    bool to_check = false;
+    if (h->K) {
+        const int64_t c = (m + h->K - 1) / h->K * h->K;     // first check step >= m
+        if (c <= seg) {
+            seg = c;
+            to_check = true;
         }
     }
-    if (k < 2) {
-        *snap = false;
-        return 1;
-    }
+    const int64_t r = seg - m + 1;
+    if (r < 2) return 1;
+    int k = (int)std::min<int64_t>(h->fuse, r);
+    if (to_check && r - k == 1 && k > 2) --k;
+    const int mode = mode_of(h, m + k - 1);
+    *end = mode == kCheck ? kEndCheck : (mode == kSnap ? kEndSnap : kEndPlain);
     return k;
 }
 
-static int issue_fused(lbm_ctx* h, int64_t m, int nsteps, bool snap, int src_k, hipStream_t st) {
+static int issue_fused(lbm_ctx* h, int64_t m, int nsteps, int end, int src_k, hipStream_t st) {
     StepArgs a;
     a.desc = h->d_desc();
     a.tile_inst = h->d_ptiles();
     a.src = h->buf(src_k);
     a.dst = h->buf(1 - src_k);
     a.snap = h->d_snap();
-    a.partials = nullptr;
+    a.partials = h->d_part();
     a.ctr_in = h->d_ctr() + src_k;
     a.ctr_out = h->d_ctr() + (1 - src_k);
     a.seed = h->seed;
@@ -816,8 +881,11 @@ static int issue_fused(lbm_ctx* h, int64_t m, int nsteps, bool snap, int src_k, 
     a.apply_shift = (h->K > 0 && (m - 1) % h->K == 0) ? 1 : 0;
     a.tile_base = 0;
     a.ntiles = (int32_t)h->ptile_inst.size();
-    HIPCALL(h, launch_fused(h->storage, h->shape, a, nsteps, snap ? 1 : 0, h->layout == LBM_LAYOUT_CHUNKED,
+    HIPCALL(h, launch_fused(h->storage, h->shape, a, nsteps, end, h->layout == LBM_LAYOUT_CHUNKED,
                             h->L.nodes, st));
+    if (end == kEndCheck)
+        HIPCALL(h, launch_finalize(h->d_desc(), h->d_pgroups(), (int)h->npgroups, h->d_ref(), h->d_ref_prev(),
+                                   (int)h->inst.size(), h->d_part(), h->d_gpart(), h->d_res(), 1, st));
     return LBM_OK;
 }
 
@@ -831,11 +899,18 @@ static int capture(lbm_ctx* h, int par) {
     int src = par;
     int rc = LBM_OK;
     int flips = 0;
+    lbm_ctx::Tail tail;
+    int tail_flip = 0;
     for (int s = 1; s <= C && rc == LBM_OK;) {
-        bool snap = false;
-        const int k = fused_steps(h, s, C, &snap);
+        int end = kEndPlain;
+        const int k = plan_launch(h, s, C, &end);
+        tail = lbm_ctx::Tail();
+        tail_flip = flips & 1;
         if (k >= 2) {
-            rc = issue_fused(h, (int64_t)s, k, snap, src, h->capture_stream);
+            rc = issue_fused(h, (int64_t)s, k, end, src, h->capture_stream);
+            tail.k = k;
+            tail.apply_shift = (h->K > 0 && (s - 1) % h->K == 0) ? 1 : 0;
+            tail.checked = end == kEndCheck ? 1 : 0;
             s += k;
         } else {
             rc = issue_step(h, (int64_t)s, src, h->capture_stream, LBM_SCHED_BATCHED);
@@ -861,6 +936,8 @@ static int capture(lbm_ctx* h, int par) {
     h->gexec[par] = x;
     h->graph_chunk = C;
     h->graph_flips = flips;
+    h->graph_tail = tail;
+    h->graph_tail_flip = tail_flip;
     return LBM_OK;
 }
 
@@ -870,18 +947,26 @@ int lbm_step(lbm_handle h, int64_t nsteps) {
     if (!h->base) return h->fail(LBM_ESTATE, "no device memory bound");
     for (char c : h->inited)
         if (!c) return h->fail(LBM_ESTATE, "every instance must be initialised before lbm_step");
+    if (nsteps > 0) {
+        // the readout buffer and the descriptor copy describe the last step so far
+        h->replayed = false;
+        h->desc_saved = false;
+    }
     int64_t left = nsteps;
     while (left > 0) {
         const int C = chunk_of(h);
         if (h->sched == LBM_SCHED_GRAPH && h->steps % C == 0 && left >= C) {
-            if (!h->gexec[h->cur]) {
-                int rc = capture(h, h->cur);
+            const int par = h->cur;
+            if (!h->gexec[par]) {
+                int rc = capture(h, par);
                 if (rc) return rc;
             }
-            HIPCALL(h, hipGraphLaunch(h->gexec[h->cur], h->stream));
+            HIPCALL(h, hipGraphLaunch(h->gexec[par], h->stream));
             h->steps += C;
             if (h->graph_flips & 1) h->cur = 1 - h->cur;
             if (h->K) h->last_check = h->steps;
+            h->tail = h->graph_tail;
+            h->tail.src = par ^ h->graph_tail_flip;
             left -= C;
             continue;
         }
@@ -890,11 +975,17 @@ int lbm_step(lbm_handle h, int64_t nsteps) {
         // the per-instance schedule issues single steps: one instance's fused
         // launch holds too few wavefronts to hide the marching latency
         // (Knudsen sweep: 4.0k MLUPS at five steps per launch, 17.1k single)
-        bool snap = false;
-        const int k = sched == LBM_SCHED_PER_INSTANCE ? 1 : fused_steps(h, m, h->steps + left, &snap);
+        int end = kEndPlain;
+        const int k = sched == LBM_SCHED_PER_INSTANCE ? 1 : plan_launch(h, m, h->steps + left, &end);
+        h->tail = lbm_ctx::Tail();
         if (k >= 2) {
-            int rc = issue_fused(h, m, k, snap, h->cur, h->stream);
+            int rc = issue_fused(h, m, k, end, h->cur, h->stream);
             if (rc) return rc;
+            h->tail.k = k;
+            h->tail.src = h->cur;
+            h->tail.apply_shift = (h->K > 0 && (m - 1) % h->K == 0) ? 1 : 0;
+            h->tail.checked = end == kEndCheck ? 1 : 0;
+            if (end == kEndCheck) h->last_check = m + k - 1;
             h->cur = 1 - h->cur;
             h->steps = m + k - 1;
             left -= k;
@@ -910,12 +1001,57 @@ int lbm_step(lbm_handle h, int64_t nsteps) {
     return LBM_OK;
 }
 
+// Rebuild, in the readout buffer, the post-relaxation state of step n - 1
+// after a last launch of k >= 2 steps (see lbm_ctx::Tail): steps n - k + 1 ..
+// n - 1 again from the launch's source buffer, with the descriptors and the
+// reference state that launch ran with and the stochastic-rounding counter it
+// started from.  Same arithmetic, so the same bits as the original steps.
+static int replay_tail(lbm_ctx* h) {
+    const lbm_ctx::Tail& t = h->tail;
+    StepArgs a;
+    a.desc = h->d_desc_last();
+    a.src = h->buf(t.src);
+    a.dst = h->buf(lbm_ctx::kReadout);
+    a.snap = nullptr;
+    a.partials = nullptr;
+    a.ctr_in = h->d_ctr() + t.src;
+    a.ctr_out = h->d_ctr() + lbm_ctx::kReadout;
+    a.seed = h->seed;
+    a.sr = h->sr;
+    // a launch that ended on a check step ran before the reference moved
+    a.ref = t.checked ? h->d_ref_prev() : h->d_ref();
+    a.apply_shift = t.apply_shift;
+    a.tile_base = 0;
+    if (t.k - 1 >= 2) {
+        a.tile_inst = h->d_ptiles();
+        a.ntiles = (int32_t)h->ptile_inst.size();
+        HIPCALL(h, launch_fused(h->storage, h->shape, a, t.k - 1, kEndPlain, h->layout == LBM_LAYOUT_CHUNKED,
+                                h->L.nodes, h->stream));
+    } else {
+        a.tile_inst = h->d_tiles();
+        a.ntiles = (int32_t)h->ntiles;
+        HIPCALL(h, launch_step(h->storage, h->shape, kPlain, a, h->L.nodes, h->stream));
+    }
+    h->replayed = true;
+    return LBM_OK;
+}
+
 static int run_moments(lbm_ctx* h, int32_t k, int out_kind, void* T, void* qx, void* qy, double* partials) {
     const lbm_instance& in = h->inst[k];
     const double grad = in.bc_x == LBM_BC_GRADIENT ? in.grad_x : 0.0;
     // after a check step the reference has moved and its shift is still pending
     const int pending = (h->K > 0 && h->steps > 0 && h->steps % h->K == 0) ? 1 : 0;
-    HIPCALL(h, launch_moments(h->storage, h->d_desc(), h->d_ref(), k, h->desc[k], h->buf(1 - h->cur),
+    // the post-relaxation state of step n - 1: the buffer the last step read,
+    // or (after a fused last launch) the readout buffer, replayed once
+    int src = 1 - h->cur;
+    if (h->steps > 0 && h->tail.k >= 2) {
+        if (!h->replayed) {
+            int rc = replay_tail(h);
+            if (rc) return rc;
+        }
+        src = lbm_ctx::kReadout;
+    }
+    HIPCALL(h, launch_moments(h->storage, h->d_desc_last(), h->d_ref(), k, h->desc[k], h->buf(src),
                               h->steps > 0 ? 1 : 0, pending, out_kind, T, qx, qy, in.t0, grad, partials,
                               h->stream));
     return LBM_OK;
@@ -1029,6 +1165,15 @@ int lbm_set_wall_flux(lbm_handle h, int32_t k, int32_t wall, double q0) {
     if (wall_kind(in, wall) != LBM_BC_HEATFLUX)
         return h->fail(LBM_EINVAL, "wall is not a HEATFLUX wall");
     if (!std::isfinite(q0)) return h->fail(LBM_EINVAL, "q0 must be finite");
+    // readouts of the current time keep the descriptors its last step ran with
+    if (h->steps > 0 && !h->desc_saved) {
+        HIPCALL(h, hipMemcpyAsync(h->d_desc_prev(), h->d_desc(), h->desc.size() * sizeof(InstDesc),
+                                  hipMemcpyDeviceToDevice, h->stream));
+        h->wall_q_last.resize(h->desc.size());
+        for (size_t j = 0; j < h->desc.size(); ++j)
+            for (int w = 0; w < 4; ++w) h->wall_q_last[j][w] = h->desc[j].wall_q[w];
+        h->desc_saved = true;
+    }
     h->qwall[k][wall] = q0;
     InstDesc& d = h->desc[k];
     d.wall_q[wall] = (float)(q0 / (h->co[k].beta * d.s));

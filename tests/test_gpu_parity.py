@@ -465,16 +465,34 @@ def test_step_fusion_range(storage, kmax):
     lat.close()
 
 
+def _same_check(a, b, what):
+    """Check records of two runs: the same step; residual and totals equal up
+    to the order of the FP64 summation (per fused tile or per single-step
+    tile), 1e-12 relative."""
+    assert a["step"] == b["step"], what
+    assert a["residual"] == pytest.approx(b["residual"], rel=1e-12, abs=1e-300), (what, a, b)
+    for u, v in zip(a["totals"], b["totals"]):
+        assert u == pytest.approx(v, rel=1e-12, abs=1e-14), (what, a, b)
+
+
+# call lengths: the calls end after 1, 3, 6, 10 (on a check step), 19 (on the
+# snapshot step before one), 20 (the lone check step), 39 and 65 steps
+FUSION_STEPS = (1, 2, 3, 4, 9, 1, 19, 26)
+
+
 @pytest.mark.parametrize("name,kw,storage,rounding", FUSION_CASES, ids=[c[0] for c in FUSION_CASES])
 def test_fused_kernel_bitwise(name, kw, storage, rounding):
     """The fused (temporally blocked) kernel gives the same bits as single
     steps: storage kinds and roundings, every boundary kind, corners, check
-    steps every 10 (a fused run ends at the latest on the snapshot step,
-    whose FP64 moments it writes: the check steps' residual and totals agree
-    too), call lengths that leave short remainders, every number of steps per
-    launch up to the kind's most, and the per-instance and graph schedules."""
+    steps every 10 (a fused launch may end on the check step, forming its
+    residual and totals in registers, or on the snapshot step before one),
+    calls that end on a fused launch of every length (the moments of the
+    final state then come from a replay of the launch's earlier steps), on a
+    check step and on the snapshot step, every number of steps per launch up
+    to the kind's most, and the per-instance and graph schedules.  The check
+    records agree to the order of summation."""
     case, T0, qx, qy = _random_case(131, 37, 0.6, 7.0, 51, **kw)
-    steps = (1, 2, 3, 7, 26)
+    steps = FUSION_STEPS
     ref_out = _fused_run(case, T0, qx, qy, storage, rounding, 1, steps, 10)
     kmax = _fuse_max(storage)
     runs = [(k, None) for k in range(2, kmax + 1)] + [(kmax, "per_instance"), (kmax, "graph")]
@@ -483,20 +501,63 @@ def test_fused_kernel_bitwise(name, kw, storage, rounding):
         for a_list, b_list in zip(got, ref_out):
             for a, b in zip(a_list[0][:3], b_list[0][:3]):
                 assert np.array_equal(a, b), (name, fuse, sched)
-            assert a_list[0][3] == b_list[0][3], (name, fuse, sched, a_list[0][3], b_list[0][3])
+            if b_list[0][3] is not None:
+                _same_check(a_list[0][3], b_list[0][3], (name, fuse, sched))
     e = eps(case, ref_out[-1][0][:3], oracle_fields(case, sum(steps), T0, qx, qy))
     log(f"fused {name}: up to {kmax} steps per launch, eps={e}")
     assert max(e) < TOL_STORAGE[storage]
 
 
+@pytest.mark.parametrize("storage", ["f32", "f16_split"])
+def test_readout_keeps_the_last_steps_wall_flux(storage):
+    """A heat-flux change applies to the steps issued after it; the moments of
+    the current time keep the wall flux its last step ran with, also when the
+    last launch was fused (its earlier steps are replayed for the readout):
+    fused and single-step runs agree bit for bit, and with the oracle read
+    before the change."""
+    kw = dict(bc_y="heatflux", q_wall=(0, 0, 1e-3, -4e-4))
+    case, T0, qx, qy = _random_case(131, 37, 0.6, 7.0, 53, **kw)
+    plan = [(7, 2e-3), (11, -1e-3), (5, 5e-4), (6, 0.0)]
+    outs = []
+    for fuse in (1, None):
+        lat = Lattice([instance_from_case(case)], storage=storage, check_interval=10)
+        if fuse:
+            lat.set_step_fusion(fuse)
+        lat.init(0, T0, qx, qy)
+        lat.set_wall_flux(0, 2, case.q_wall[2])
+        lat.set_wall_flux(0, 3, case.q_wall[3])
+        got = []
+        for n, q in plan:
+            lat.step(n)
+            lat.set_wall_flux(0, 2, q)            # applies to later steps only
+            got.append(lat.moments(0))
+        lat.close()
+        outs.append(got)
+    for a, b in zip(*outs):
+        for u, v in zip(a, b):
+            assert np.array_equal(u, v), storage
+    o = ref.Oracle(case, T0, qx, qy)
+    o.set_wall_flux(2, case.q_wall[2])
+    o.set_wall_flux(3, case.q_wall[3])
+    for (n, q), g in zip(plan, outs[1]):
+        o.run(n)
+        T, qxo, qyo = o.moments()
+        e = eps(case, g, (T - case.t0, qxo, qyo))
+        o.set_wall_flux(2, q)
+        log(f"wall flux switched after the step, {storage}: eps={e}")
+        assert max(e) < TOL_STORAGE[storage]
+
+
 @pytest.mark.parametrize("storage", ["f32", "bf16", "f16_split"])
-@pytest.mark.parametrize("nx,ny", [(2, 2), (3, 2), (5, 3), (53, 13), (57, 14), (59, 13), (121, 25),
-                                   (70, 33), (113, 65), (117, 34)])
+@pytest.mark.parametrize("nx,ny", [(2, 2), (3, 2), (5, 3), (53, 13), (57, 14), (104, 13), (105, 25),
+                                   (112, 31), (70, 33), (113, 65), (111, 34)])
 def test_fused_kernel_small_and_ragged(nx, ny, storage):
     """Strips wider than the lattice (the window wraps several times), and
-    lattices one node past a strip edge (52 or 56 output columns by kind)
-    or a 32-row marching chunk, or two of them and one node: same bits as
-    single steps for two and for the most steps per launch, and the oracle."""
+    lattices on a strip edge (52 output columns for FP32, 56 for the 16-bit
+    kinds: 104 = 2 x 52, 112 = 2 x 56) or one node past one (53, 57, 105,
+    113) or one short (111), and one row past a 32-row marching chunk or two
+    (33, 65): same bits as single steps for two and for the most steps per
+    launch, and the oracle."""
     case, T0, qx, qy = _random_case(nx, ny, 0.8, 8.0, nx * 7 + ny)
     steps = (5, 8)        # fused launches of every length up to six, and singles
     a = _fused_run(case, T0, qx, qy, storage, "nearest", 1, steps, 0)
@@ -568,11 +629,17 @@ def test_totals_and_invariants():
     lat.close()
 
 
-def test_residual_and_check_totals():
+@pytest.mark.parametrize("fuse", [1, None])
+def test_residual_and_check_totals(fuse):
     """Check-step FP64 residual r = ||m^n - m^(n-1)|| / ||m^n|| equals the one
-    formed from oracle moments at n-1 and n."""
+    formed from oracle moments at n-1 and n; single steps, and fused launches
+    that end on the check step."""
     case = W.poiseuille_case(0.6, 100.0, nx=40, ny=50)
     lat = Lattice([instance_from_case(case)], check_interval=25)
+    if fuse:
+        lat.set_step_fusion(fuse)
+    else:
+        lat.set_step_fusion(_fuse_max("f32"))
     lat.init(0)
     with pytest.raises(LBMError) as e:
         lat.residual(0)

@@ -153,6 +153,48 @@ def test_periodic_invariants(tau_n, tau_r):
     assert b[2] == pytest.approx(a[2] * rho ** n, abs=1e-12)
 
 
+@pytest.mark.parametrize("tau_n,tau_r", REGIMES)
+def test_initial_flux_reads_back_through_eq54(tau_n, tau_r):
+    """Initial state with a given heat flux (read as the Eq. 15 equilibrium
+    with first moment q / beta, the paper being silent): Eq. 54 on the raw
+    populations at n = 0 returns the given q and Eq. 53 the given T, node by
+    node; the uniform part of the flux then decays by exactly rho per step
+    from the *given* flux (the decay factor fixed by Eqs. 13, 15, 16, 54), so
+    a state that stored q instead of q / beta (off by beta) or dropped the
+    flux share fails.  The temperature is checked against its deviation."""
+    nx, ny, n = 18, 11, 7
+    p = cf.scheme_constants(tau_n, tau_r)
+    beta, rho = p["beta"], p["rho"]
+    cv = 1.3
+    case = _case(nx, ny, tau_n, tau_r, cv=cv)
+    T0 = W.random_field(nx, ny, 0.05, 1.0, 21)
+    qx, qy = W.random_flux(nx, ny, 0.01, 22)
+    qx = qx + 0.004                      # a uniform part, which no advection moves
+    qy = qy - 0.003
+    o = ref.Oracle(case, T0, qx, qy)
+    e = o.populations()
+    E = e.sum(axis=0)
+    jx = np.tensordot(CX, e, axes=1)
+    jy = np.tensordot(CY, e, axes=1)
+    assert np.abs(E / cv - T0).max() <= 1e-13
+    assert np.abs(beta * jx - qx).max() <= 1e-15
+    assert np.abs(beta * jy - qy).max() <= 1e-15
+    # the populations are the Eq. 15 equilibrium itself: its second moments
+    # are (5/9) C_V T delta_ab (Eq. 24), the mixed one vanishes
+    assert np.abs((CX * CX) @ e.reshape(8, -1) - 5.0 / 9.0 * E.ravel()).max() <= 1e-13
+    assert np.abs((CX * CY) @ e.reshape(8, -1)).max() <= 1e-15
+    o.run(n)
+    tot = o.totals()
+    assert tot[1] == pytest.approx(rho ** n * qx.sum(), rel=1e-12, abs=1e-14)
+    assert tot[2] == pytest.approx(rho ** n * qy.sum(), rel=1e-12, abs=1e-14)
+    # a uniform start stays uniform: every node's flux is rho^n times the given one
+    u = ref.Oracle(case, np.full((ny, nx), 1.2), np.full((ny, nx), 0.004), np.full((ny, nx), -0.003))
+    u.run(n)
+    _, ux, uy = u.moments()
+    assert np.abs(ux - rho ** n * 0.004).max() <= 1e-15
+    assert np.abs(uy + rho ** n * 0.003).max() <= 1e-15
+
+
 @pytest.mark.parametrize("tau_n,tau_r", [(0.55, 50.0), (0.6, 5.0), (0.8, 0.8), (0.51, 1000.0)])
 def test_bloch_dispersion_is_eq52(tau_n, tau_r):
     """Slow Bloch eigenvalues reproduce the temperature equation Eq. 52 (the
