@@ -232,6 +232,21 @@ int lbm_moments(lbm_handle h, int32_t inst, float* T, float* qx, float* qy, int3
 int lbm_moments_f64(lbm_handle h, int32_t inst, double* dT, double* qx, double* qy,
                     int32_t on_device);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): lbm_moments_f64 into HOST arrays
+ * without any allocation.  lbm_moments_f64 with host outputs stages the fields
+ * in a device buffer it allocates on first use; this variant stages them in a
+ * fixed device array of the library (24 MiB per device, held until the
+ * process ends; its address is resolved at lbm_create).  dT, qx, qy: host
+ * arrays of ny*nx doubles (any may be NULL), as lbm_moments_f64.  The
+ * instance may have at most 2^20 nodes: larger ones fail with LBM_EINVAL and
+ * nothing is written.  Every call on one device shares the array: calls that
+ * overlap on one device (other threads, other handles) race; a call is
+ * complete when it returns (it synchronises the handle's stream).
+ * Errors: EINVAL (index, size), ESTATE (not initialised), EUNSUPPORTED (the
+ * array is not available on this device), EHIP. */
+int lbm_moments_f64_noalloc(lbm_handle h, int32_t inst, double* dT, double* qx, double* qy);
+
 /* FP64 totals of instance `inst` at the current time, computed now:
  * out[0] = sum (e - C_V T_ref) = C_V sum dT, out[1] = sum q_x, out[2] = sum q_y.
  * Errors: ENONFINITE if any total is not finite. */

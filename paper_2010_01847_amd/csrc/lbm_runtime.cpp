@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -486,6 +487,43 @@ static int upload_ref(lbm_ctx* h, int k) {
     return LBM_OK;
 }
 
+// ------------------------------------------------------------------ static readout scratch
+//
+// Staging of lbm_moments_f64_noalloc: the FP64 fields of one instance, in a
+// file-scope device array, so that the call allocates nothing.  Every device
+// the library runs on holds one copy (24 MiB) until the process ends.  In
+// host code `scratch` only names the symbol; its device address, per device,
+// comes from hipGetSymbolAddress at lbm_create (once per device, with that
+// device current) and only that address is passed to kernels and copies.
+
+constexpr int64_t kNoAllocNodes = int64_t(1) << 20;   // largest instance the call reads out
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) double scratch[3 * kNoAllocNodes];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}
+
+// Resolve (once) the device address of `scratch` on the current device `dev`.
+static hipError_t scratch_setup(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return hipSuccess;   // the no-allocation call reports it
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return hipSuccess;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+    return hipSuccess;
+}
+
+static double* scratch_ptr(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_ptr[dev];
+}
+
 // ------------------------------------------------------------------ C ABI
 
 extern "C" {
@@ -567,6 +605,12 @@ int lbm_create(const lbm_config* cfg, lbm_handle* out) {
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) {
         g_create_error = std::string("hipGetDevice: ") + hipGetErrorString(e);
+        delete h;
+        return LBM_EHIP;
+    }
+    e = scratch_setup(h->device);
+    if (e != hipSuccess) {
+        g_create_error = std::string("hipGetSymbolAddress of the readout scratch: ") + hipGetErrorString(e);
         delete h;
         return LBM_EHIP;
     }
@@ -1090,6 +1134,29 @@ int lbm_moments(lbm_handle h, int32_t k, float* T, float* qx, float* qy, int32_t
 
 int lbm_moments_f64(lbm_handle h, int32_t k, double* dT, double* qx, double* qy, int32_t on_device) {
     return moments_common(h, k, 1, dT, qx, qy, on_device);
+}
+
+int lbm_moments_f64_noalloc(lbm_handle h, int32_t k, double* dT, double* qx, double* qy) {
+    if (!valid(h)) return LBM_EINVAL;
+    int rc = check_inst(h, k);
+    if (rc) return rc;
+    if (!h->inited[k]) return h->fail(LBM_ESTATE, "instance not initialised");
+    const lbm_instance& in = h->inst[k];
+    const int64_t n = (int64_t)in.nx * in.ny;
+    if (n > kNoAllocNodes)
+        return h->fail(LBM_EINVAL, "instance of " + std::to_string(n) + " nodes: lbm_moments_f64_noalloc reads out "
+                                   "at most " + std::to_string(kNoAllocNodes) + " nodes (use lbm_moments_f64)");
+    double* sp = scratch_ptr(h->device);
+    if (!sp) return h->fail(LBM_EUNSUPPORTED, "no readout scratch on this device");
+    double* dv[3] = {dT ? sp : nullptr, qx ? sp + n : nullptr, qy ? sp + 2 * n : nullptr};
+    rc = run_moments(h, k, 1, dv[0], dv[1], dv[2], nullptr);
+    if (rc) return rc;
+    double* hv[3] = {dT, qx, qy};
+    for (int c = 0; c < 3; ++c)
+        if (hv[c]) HIPCALL(h, hipMemcpyAsync(hv[c], dv[c], (size_t)n * sizeof(double), hipMemcpyDeviceToHost,
+                                             h->stream));
+    HIPCALL(h, hipStreamSynchronize(h->stream));
+    return LBM_OK;
 }
 
 int lbm_totals(lbm_handle h, int32_t k, double out[3]) {

@@ -81,6 +81,7 @@ SIGNATURES = [
     ("lbm_steps_done", ctypes.c_int64, [_P]),
     ("lbm_moments", ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, ctypes.c_int32]),
     ("lbm_moments_f64", ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P, ctypes.c_int32]),
+    ("lbm_moments_f64_noalloc", ctypes.c_int, [_P, ctypes.c_int32, _P, _P, _P]),
     ("lbm_totals", ctypes.c_int, [_P, ctypes.c_int32, _D]),
     ("lbm_residual", ctypes.c_int, [_P, ctypes.c_int32, _D]),
     ("lbm_last_check", ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(lbm_check_info)]),
@@ -185,6 +186,10 @@ def lbm_moments(h, inst: int, T_ptr, qx_ptr, qy_ptr, on_device: int) -> None:
 
 def lbm_moments_f64(h, inst: int, dT_ptr, qx_ptr, qy_ptr, on_device: int) -> None:
     _check(library().lbm_moments_f64(h, inst, dT_ptr, qx_ptr, qy_ptr, on_device), "lbm_moments_f64", h)
+
+
+def lbm_moments_f64_noalloc(h, inst: int, dT_ptr, qx_ptr, qy_ptr) -> None:
+    _check(library().lbm_moments_f64_noalloc(h, inst, dT_ptr, qx_ptr, qy_ptr), "lbm_moments_f64_noalloc", h)
 
 
 def lbm_totals(h, inst: int) -> np.ndarray:
@@ -348,6 +353,14 @@ class Lattice:
         it = self.instances[inst]
         out = [np.empty((it.ny, it.nx), dtype=np.float64) for _ in range(3)]
         lbm_moments_f64(self.h, inst, *[o.ctypes.data for o in out], 0)
+        return out[0], out[1], out[2]
+
+    def moments_noalloc(self, inst: int = 0) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+        """As moments(), through lbm_moments_f64_noalloc (no device allocation;
+        instances of at most 2^20 nodes)."""
+        it = self.instances[inst]
+        out = [np.empty((it.ny, it.nx), dtype=np.float64) for _ in range(3)]
+        lbm_moments_f64_noalloc(self.h, inst, *[o.ctypes.data for o in out])
         return out[0], out[1], out[2]
 
     def moments_f32(self, inst: int = 0):
