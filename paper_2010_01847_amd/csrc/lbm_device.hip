@@ -288,22 +288,50 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Sum kPartials values over the block in a fixed order; thread 0 writes them.
-__device__ __forceinline__ void block_partials(double v[kPartials], double* out) {
-    __shared__ double red[kMaxBlock / 64][kPartials];
+// Compensated additions (see DD): the exact rounding error of hi + b (Knuth's
+// two-sum, exact with contraction off) is carried into lo, then the pair is
+// renormalised.  dd_add(a, b) == dd_add(b, a).
+__device__ __forceinline__ DD dd_renorm(double s, double t) {
+    const double hi = s + t;
+    return DD{hi, t - (hi - s)};
+}
+__device__ __forceinline__ DD dd_add(DD a, double b) {
+    const double s = a.hi + b;
+    const double bp = s - a.hi;
+    const double e = (a.hi - (s - bp)) + (b - bp);
+    return dd_renorm(s, e + a.lo);
+}
+__device__ __forceinline__ DD dd_add(DD a, DD b) {
+    const double s = a.hi + b.hi;
+    const double bp = s - a.hi;
+    const double e = (a.hi - (s - bp)) + (b.hi - bp);
+    return dd_renorm(s, e + (a.lo + b.lo));
+}
+__device__ __forceinline__ DD dd_zero() { return DD{0.0, 0.0}; }
+
+__device__ __forceinline__ DD wave_sum(DD v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = dd_add(v, DD{__shfl_xor(v.hi, off, 64), __shfl_xor(v.lo, off, 64)});
+    return v;
+}
+
+// Sum kPartials compensated values over the block in a fixed order; thread 0
+// writes them.
+__device__ __forceinline__ void block_partials(DD v[kPartials], DD* out) {
+    __shared__ DD red[kMaxBlock / 64][kPartials];
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
     const int nw = (blockDim.x * blockDim.y + 63) >> 6;
 #pragma unroll
     for (int c = 0; c < kPartials; ++c) {
-        const double s = wave_sum(v[c]);
+        const DD s = wave_sum(v[c]);
         if (lane == 0) red[wid][c] = s;
     }
     __syncthreads();
     if (tid == 0) {
         for (int c = 0; c < kPartials; ++c) {
-            double s = 0.0;
-            for (int w = 0; w < nw; ++w) s += red[w][c];
+            DD s = dd_zero();
+            for (int w = 0; w < nw; ++w) s = dd_add(s, red[w][c]);
             out[c] = s;
         }
     }
@@ -336,7 +364,7 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t sna
     const int nx = d.nx, ny = d.ny;
     const bool live = (y < ny) && (x0 < nx);
 
-    double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    DD acc[kPartials] = {dd_zero(), dd_zero(), dd_zero(), dd_zero(), dd_zero()};
     if (live) {
         const S* __restrict__ src = reinterpret_cast<const S*>(a.src) + d.off;
         S* __restrict__ dst = reinterpret_cast<S*>(a.dst) + d.off;
@@ -392,11 +420,11 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t sna
                 } else {
                     const double p0 = a.snap[n], p1 = a.snap[n + snap_stride],
                                  p2 = a.snap[n + 2 * snap_stride];
-                    acc[0] += d.s * E;
-                    acc[1] += qx;
-                    acc[2] += qy;
-                    acc[3] += (dT - p0) * (dT - p0) + (qx - p1) * (qx - p1) + (qy - p2) * (qy - p2);
-                    acc[4] += dT * dT + qx * qx + qy * qy;
+                    acc[0] = dd_add(acc[0], d.s * E);
+                    acc[1] = dd_add(acc[1], qx);
+                    acc[2] = dd_add(acc[2], qy);
+                    acc[3] = dd_add(acc[3], (dT - p0) * (dT - p0) + (qx - p1) * (qx - p1) + (qy - p2) * (qy - p2));
+                    acc[4] = dd_add(acc[4], dT * dT + qx * qx + qy * qy);
                 }
             }
         }
@@ -534,7 +562,7 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
     // (at the end, so no store precedes the kernel's loads)
     const uint32_t step = a.ctr_in[0];
 
-    double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    DD acc[kPartials] = {dd_zero(), dd_zero(), dd_zero(), dd_zero(), dd_zero()};
     if (wave_live && x < nx) {
         const RefView rv = ref_view(ref);
         const int ym = (y == 0) ? ny - 1 : y - 1;
@@ -606,11 +634,11 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
                 a.snap[n + 2 * snap_stride] = qy;
             } else {
                 const double p0 = a.snap[n], p1 = a.snap[n + snap_stride], p2 = a.snap[n + 2 * snap_stride];
-                acc[0] = d.s * E;
-                acc[1] = qx;
-                acc[2] = qy;
-                acc[3] = (dT - p0) * (dT - p0) + (qx - p1) * (qx - p1) + (qy - p2) * (qy - p2);
-                acc[4] = dT * dT + qx * qx + qy * qy;
+                acc[0].hi = d.s * E;
+                acc[1].hi = qx;
+                acc[2].hi = qy;
+                acc[3].hi = (dT - p0) * (dT - p0) + (qx - p1) * (qx - p1) + (qy - p2) * (qy - p2);
+                acc[4].hi = dT * dT + qx * qx + qy * qy;
             }
         }
         char* out = reinterpret_cast<char*>(a.dst) + d.off * (int64_t)sizeof(S) + (int64_t)y * rb;
@@ -760,14 +788,14 @@ __global__ __launch_bounds__(256) void moments_kernel(const InstDesc* __restrict
                                                       const RefState* __restrict__ refs, int inst,
                                                       const void* buf, int pull, int pending_shift,
                                                       int out_kind, void* T, void* qx, void* qy,
-                                                      double t0, double grad, double* partials) {
+                                                      double t0, double grad, DD* partials) {
     const InstDesc& d = descs[inst];
     const RefState& ref = refs[inst];
     const RefView rv = ref_view(ref);
     const int x = blockIdx.x * 256 + threadIdx.x;
     const int y = blockIdx.y;
     const int nx = d.nx, ny = d.ny;
-    double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    DD acc[kPartials] = {dd_zero(), dd_zero(), dd_zero(), dd_zero(), dd_zero()};
     if (x < nx) {
         const S* src = reinterpret_cast<const S*>(buf) + d.off;
         float g[8];
@@ -802,16 +830,16 @@ __global__ __launch_bounds__(256) void moments_kernel(const InstDesc* __restrict
             if (qx) reinterpret_cast<double*>(qx)[n] = vx;
             if (qy) reinterpret_cast<double*>(qy)[n] = vy;
         }
-        acc[0] = d.s * E;
-        acc[1] = vx;
-        acc[2] = vy;
+        acc[0].hi = d.s * E;
+        acc[1].hi = vx;
+        acc[2].hi = vy;
     }
     if (partials) block_partials(acc, partials + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kPartials);
 }
 
 hipError_t launch_moments(int storage, const InstDesc* d_desc, const RefState* d_ref, int inst,
                           const InstDesc& h, const void* buf, int pull, int pending_shift, int out_kind,
-                          void* T, void* qx, void* qy, double t0, double grad, double* partials,
+                          void* T, void* qx, void* qy, double t0, double grad, DD* partials,
                           hipStream_t st) {
     dim3 grid((h.nx + 255) / 256, h.ny), block(256);
     switch (storage) {
@@ -1058,7 +1086,7 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
     // and of the previous one (old, the row stage K reaches now), and the
     // output nodes' check sums
     double pm_new[3] = {0.0, 0.0, 0.0}, pm_old[3] = {0.0, 0.0, 0.0};
-    double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    DD acc[kPartials] = {dd_zero(), dd_zero(), dd_zero(), dd_zero(), dd_zero()};
     // rows yi .. yi + PF - 1 of the coming iterations, in flight
     S ring[PF][8];
     float ringE[PF];
@@ -1126,11 +1154,12 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
                             double E, dT, qx, qy;
                             node_moments_f64(g, d, q_ref, E, dT, qx, qy);
                             const double p0 = pm_old[0], p1 = pm_old[1], p2 = pm_old[2];
-                            acc[0] += d.s * E;
-                            acc[1] += qx;
-                            acc[2] += qy;
-                            acc[3] += (dT - p0) * (dT - p0) + (qx - p1) * (qx - p1) + (qy - p2) * (qy - p2);
-                            acc[4] += dT * dT + qx * qx + qy * qy;
+                            acc[0] = dd_add(acc[0], d.s * E);
+                            acc[1] = dd_add(acc[1], qx);
+                            acc[2] = dd_add(acc[2], qy);
+                            acc[3] = dd_add(acc[3], (dT - p0) * (dT - p0) + (qx - p1) * (qx - p1)
+                                                    + (qy - p2) * (qy - p2));
+                            acc[4] = dd_add(acc[4], dT * dT + qx * qx + qy * qy);
                         }
                         uint32_t r[4] = {0u, 0u, 0u, 0u};
                         if (SR)
@@ -1331,23 +1360,23 @@ hipError_t launch_init(int storage, const InstDesc* d_desc, const RefState* d_re
 
 // ------------------------------------------------------------------ reductions
 
-// Fixed-order sum of `count` partial records starting at `first`: thread t
-// adds records t, t + 256, ... in order, then a fixed tree over the block.
-__device__ void reduce_records(const double* __restrict__ partials, int64_t first, int count,
-                               double* __restrict__ out) {
-    __shared__ double red[256][kPartials];
+// Fixed-order compensated sum of `count` partial records starting at
+// `first`: thread t adds records t, t + 256, ... in order, then a fixed tree
+// over the block.
+__device__ void reduce_records(const DD* __restrict__ partials, int64_t first, int count, DD* __restrict__ out) {
+    __shared__ DD red[256][kPartials];
     const int t = threadIdx.x;
-    double s[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    DD s[kPartials] = {dd_zero(), dd_zero(), dd_zero(), dd_zero(), dd_zero()};
     for (int j = t; j < count; j += 256)
 #pragma unroll
-        for (int c = 0; c < kPartials; ++c) s[c] += partials[(first + j) * kPartials + c];
+        for (int c = 0; c < kPartials; ++c) s[c] = dd_add(s[c], partials[(first + j) * kPartials + c]);
 #pragma unroll
     for (int c = 0; c < kPartials; ++c) red[t][c] = s[c];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (t < w)
 #pragma unroll
-            for (int c = 0; c < kPartials; ++c) red[t][c] += red[t + w][c];
+            for (int c = 0; c < kPartials; ++c) red[t][c] = dd_add(red[t][c], red[t + w][c]);
         __syncthreads();
     }
     if (t == 0)
@@ -1359,8 +1388,8 @@ __device__ void reduce_records(const double* __restrict__ partials, int64_t firs
 // records of the fused kernel's tiles (strips), else of the single-step tiles.
 __global__ __launch_bounds__(256) void group_reduce_kernel(const InstDesc* __restrict__ descs,
                                                            const int32_t* __restrict__ group_inst,
-                                                           const double* __restrict__ partials,
-                                                           double* __restrict__ gpart, int fused) {
+                                                           const DD* __restrict__ partials,
+                                                           DD* __restrict__ gpart, int fused) {
     const int b = blockIdx.x;
     const InstDesc& d = descs[group_inst[b]];
     const int gb = fused ? d.p_group_begin : d.group_begin;
@@ -1381,12 +1410,15 @@ __global__ __launch_bounds__(256) void group_reduce_kernel(const InstDesc* __res
 __global__ __launch_bounds__(256) void finalize_kernel(const InstDesc* __restrict__ descs,
                                                        RefState* __restrict__ refs,
                                                        RefState* __restrict__ refs_prev,
-                                                       const double* __restrict__ gpart,
+                                                       const DD* __restrict__ gpart,
                                                        double* __restrict__ results, int fused) {
     const InstDesc& d = descs[blockIdx.x];
-    double* out = results + (int64_t)blockIdx.x * kPartials;
-    reduce_records(gpart, fused ? d.p_group_begin : d.group_begin, fused ? d.p_ngroups : d.ngroups, out);
+    __shared__ DD sum[kPartials];
+    reduce_records(gpart, fused ? d.p_group_begin : d.group_begin, fused ? d.p_ngroups : d.ngroups, sum);
     if (threadIdx.x != 0) return;
+    double* out = results + (int64_t)blockIdx.x * kPartials;
+#pragma unroll
+    for (int c = 0; c < kPartials; ++c) out[c] = sum[c].hi;
     RefState& r = refs[blockIdx.x];
     refs_prev[blockIdx.x] = r;
     if (!r.adapt) return;
@@ -1404,15 +1436,15 @@ __global__ __launch_bounds__(256) void finalize_kernel(const InstDesc* __restric
 }
 
 // Block b reduces records [b * span, min((b + 1) * span, count)).
-__global__ __launch_bounds__(256) void range_reduce_kernel(const double* __restrict__ partials, int count,
-                                                           int span, double* __restrict__ out) {
+__global__ __launch_bounds__(256) void range_reduce_kernel(const DD* __restrict__ partials, int count,
+                                                           int span, DD* __restrict__ out) {
     const int64_t first = (int64_t)blockIdx.x * span;
     const int64_t rest = count - first;
     reduce_records(partials, first, (int)(rest < span ? rest : span), out + (int64_t)blockIdx.x * kPartials);
 }
 
 hipError_t launch_finalize(const InstDesc* d_desc, const int32_t* group_inst, int ngroups, RefState* d_ref,
-                           RefState* d_ref_prev, int ninst, const double* partials, double* gpart,
+                           RefState* d_ref_prev, int ninst, const DD* partials, DD* gpart,
                            double* results, int fused, hipStream_t st) {
     hipLaunchKernelGGL(group_reduce_kernel, dim3(ngroups), dim3(256), 0, st, d_desc, group_inst, partials, gpart,
                        fused);
@@ -1428,8 +1460,7 @@ hipError_t launch_set_float(float* dst, float v, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_finalize_range(const double* partials, int nparts, double* gpart, double* result,
-                                 hipStream_t st) {
+hipError_t launch_finalize_range(const DD* partials, int nparts, DD* gpart, DD* result, hipStream_t st) {
     const int ng = (nparts + kGroup - 1) / kGroup;
     hipLaunchKernelGGL(range_reduce_kernel, dim3(ng), dim3(256), 0, st, partials, nparts, kGroup, gpart);
     hipLaunchKernelGGL(range_reduce_kernel, dim3(1), dim3(256), 0, st, gpart, ng, ng, result);

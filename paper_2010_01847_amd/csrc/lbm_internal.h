@@ -12,6 +12,18 @@ constexpr int kMaxBlock = 512;     // threads per block upper bound (launch boun
 constexpr int kPartials = 5;       // per-tile FP64 partials: sum dE, sum qx, sum qy, |dm|^2, |m|^2
 constexpr int kGroup = 1024;       // tile records per first-stage reduction block
 
+// A compensated FP64 sum: the value is hi + lo with |lo| <= ulp(hi) / 2, and hi
+// alone is the sum rounded to double.  The reductions carry their partial sums
+// in this form (partial records are kPartials of them), so a total is the
+// correctly rounded sum of its node values except with a probability of order
+// N 2^-53 times the sum's condition number, whatever the grouping of the
+// nodes into tiles: the reference-flux update at check steps, which rounds a
+// small difference of such a total to FP32, then does not depend on the
+// kernel, launch shape or schedule that formed it.
+struct DD {
+    double hi, lo;
+};
+
 // Per-instance descriptor, resident in device memory (one 256-byte record).
 //
 // Element address of direction i at node (x, y):
@@ -156,7 +168,7 @@ struct StepArgs {
     const void* src;            // post-relaxation populations of step n-1
     void* dst;                  // post-relaxation populations of step n
     double* snap;               // FP64 (dT, qx, qy) per node (node_off indexed), SNAP/CHECK
-    double* partials;           // kPartials per global tile, CHECK
+    DD* partials;               // kPartials compensated sums per global tile, CHECK
     int32_t tile_base;          // first global tile of this launch
     int32_t ntiles;             // tiles in this launch
     const RefState* ref;        // per-instance reference states
@@ -187,11 +199,12 @@ hipError_t launch_fused(int storage, const Shape& sh, const StepArgs& a, int k, 
 // rebuilt from the post-relaxation populations of step n-1 (advection plus
 // boundary treatment), else read in place (time 0, pre-relaxation state).
 // out_kind: 0 = FP32 absolute T (+ q) ; 1 = FP64 deviation dT (+ q).
-// partials (may be null): kPartials per tile of this instance (block) for totals.
+// partials (may be null): kPartials compensated sums per tile of this
+// instance (block) for totals.
 hipError_t launch_moments(int storage, const InstDesc* d_desc, const RefState* d_ref, int inst,
                           const InstDesc& h_desc, const void* buf, int pull, int pending_shift,
                           int out_kind, void* T, void* qx, void* qy, double t0, double grad,
-                          double* partials, hipStream_t st);
+                          DD* partials, hipStream_t st);
 
 // Equilibrium initialisation: writes the pre-relaxation state to `pre` and its
 // relaxation to `post`.  T, qx, qy: device FP64 (qx, qy may be null).
@@ -209,7 +222,7 @@ hipError_t launch_init(int storage, const InstDesc* d_desc, const RefState* d_re
 // to d_ref_prev and then moves an adaptive instance's reference flux to its
 // mean heat flux.
 hipError_t launch_finalize(const InstDesc* d_desc, const int32_t* group_inst, int ngroups, RefState* d_ref,
-                           RefState* d_ref_prev, int ninst, const double* partials, double* gpart,
+                           RefState* d_ref_prev, int ninst, const DD* partials, DD* gpart,
                            double* results, int fused, hipStream_t st);
 
 // One-thread kernel writing *dst = v on the stream (stream-ordered updates of
@@ -217,8 +230,7 @@ hipError_t launch_finalize(const InstDesc* d_desc, const int32_t* group_inst, in
 hipError_t launch_set_float(float* dst, float v, hipStream_t st);
 
 // Reduction of nparts moments-kernel partials (tiles of 256 nodes) of one
-// instance, through gpart (ceil(nparts / kGroup) records).
-hipError_t launch_finalize_range(const double* partials, int nparts, double* gpart, double* result,
-                                 hipStream_t st);
+// instance, through gpart (ceil(nparts / kGroup) records), into one record.
+hipError_t launch_finalize_range(const DD* partials, int nparts, DD* gpart, DD* result, hipStream_t st);
 
 }  // namespace plbm

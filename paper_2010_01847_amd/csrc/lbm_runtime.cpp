@@ -97,6 +97,31 @@ Geometry geometry_of(const lbm_instance& in, int es, int layout, bool split = fa
     return g;
 }
 
+// Launch costs of a k-step launch on the second-sound lattice 8192^2
+// (MI355X, microseconds; k = 1 is the single-step kernel).  A fused launch
+// costs about the same for every k from 2 up (its time goes to the rows it
+// streams and the strips' halo rather than to the number of stages), so the
+// way a short run is cut into launches matters: 20 FP32 steps cost 4344 us as
+// 5 + 5 + 5 + 5 and 4470 us as 6 + 6 + 6 + 2.  The check variant of six FP32
+// steps needs 124 VGPRs (three waves per SIMD instead of four).  BF16 kinds
+// take the FP16 kinds' figures.  lbm_autotune replaces the plain figures by
+// its own timings on the handle's lattices and scales the check figures.
+static void default_costs(int storage, double plain[8], double check[8]) {
+    static const double f32_p[7] = {0, 736, 1188, 1268, 1214, 1086, 1094};
+    static const double f32_c[7] = {0, 0, 1192, 1084, 1087, 1090, 1311};
+    static const double f16_p[5] = {0, 481, 656, 628, 751};
+    static const double f16_c[5] = {0, 0, 611, 804, 980};
+    static const double spl_p[5] = {0, 486, 805, 779, 862};
+    static const double spl_c[5] = {0, 0, 724, 860, 1043};
+    const double* p = storage == LBM_F32 ? f32_p : (is_split(storage) ? spl_p : f16_p);
+    const double* c = storage == LBM_F32 ? f32_c : (is_split(storage) ? spl_c : f16_c);
+    for (int k = 0; k < 8; ++k) plain[k] = check[k] = 0.0;
+    for (int k = 1; k <= fuse_max(storage); ++k) {
+        plain[k] = p[k];
+        check[k] = c[k];
+    }
+}
+
 int resolve_layout(int layout) { return layout == LBM_LAYOUT_PLANES ? LBM_LAYOUT_PLANES : LBM_LAYOUT_CHUNKED; }
 
 struct Coeffs {
@@ -239,10 +264,10 @@ Layout layout_of(const std::vector<lbm_instance>& v, int storage, int check, int
     L.off_buf[1] = o; o += L.buf_bytes;
     L.off_buf[2] = o; o += L.buf_bytes;
     L.off_snap = o; o += check ? align_up(3 * (size_t)L.nodes * sizeof(double), kAlign) : 0;
-    L.off_part = o; o += align_up((size_t)records * kPartials * sizeof(double), kAlign);
+    L.off_part = o; o += align_up((size_t)records * kPartials * sizeof(DD), kAlign);
     L.off_res = o; o += align_up(v.size() * kPartials * sizeof(double), kAlign);
-    L.off_mpart = o; o += align_up((size_t)L.mparts_max * kPartials * sizeof(double), kAlign);
-    L.off_mres = o; o += align_up(kPartials * sizeof(double), kAlign);
+    L.off_mpart = o; o += align_up((size_t)L.mparts_max * kPartials * sizeof(DD), kAlign);
+    L.off_mres = o; o += align_up(kPartials * sizeof(DD), kAlign);
     L.off_desc = o; o += align_up(v.size() * sizeof(InstDesc), kAlign);
     L.off_desc_prev = o; o += align_up(v.size() * sizeof(InstDesc), kAlign);
     L.off_ref = o; o += align_up(v.size() * sizeof(RefState), kAlign);
@@ -251,7 +276,7 @@ Layout layout_of(const std::vector<lbm_instance>& v, int storage, int check, int
     L.off_ptiles = o; o += align_up((size_t)L.ptiles * sizeof(int32_t), kAlign);
     L.off_groups = o; o += align_up((size_t)L.groups_max * sizeof(int32_t), kAlign);
     L.off_pgroups = o; o += align_up((size_t)L.pgroups * sizeof(int32_t), kAlign);
-    L.off_gpart = o; o += align_up((size_t)gscratch * kPartials * sizeof(double), kAlign);
+    L.off_gpart = o; o += align_up((size_t)gscratch * kPartials * sizeof(DD), kAlign);
     L.off_ctr = o; o += kAlign;                 // 32-bit step counters: ping-pong pair and the readout's
     L.total = o;
     return L;
@@ -285,6 +310,10 @@ struct lbm_ctx {
     std::vector<int32_t> pgroup_inst;  // fused kernel: reduction group -> instance
     int64_t npgroups = 0;
     int fuse = 1;                      // most time steps per launch where allowed (1 .. fuse_max)
+    // relative cost of one launch of k steps (index k = 1 .. fuse_max): plain,
+    // and fused ending on the check step (see plan_launch)
+    double cost_plain[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double cost_check[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int graph_flips = 0;               // buffer swaps of one captured chunk
     // The last launch of the steps issued so far, when it advanced k >= 2
     // steps: the post-relaxation state of step n - 1, from which the moments
@@ -330,12 +359,12 @@ struct lbm_ctx {
     int32_t* d_tiles() const { return reinterpret_cast<int32_t*>(base + L.off_tiles); }
     int32_t* d_ptiles() const { return reinterpret_cast<int32_t*>(base + L.off_ptiles); }
     int32_t* d_groups() const { return reinterpret_cast<int32_t*>(base + L.off_groups); }
-    double* d_gpart() const { return reinterpret_cast<double*>(base + L.off_gpart); }
+    DD* d_gpart() const { return reinterpret_cast<DD*>(base + L.off_gpart); }
     double* d_snap() const { return K ? reinterpret_cast<double*>(base + L.off_snap) : nullptr; }
-    double* d_part() const { return reinterpret_cast<double*>(base + L.off_part); }
+    DD* d_part() const { return reinterpret_cast<DD*>(base + L.off_part); }
     double* d_res() const { return reinterpret_cast<double*>(base + L.off_res); }
-    double* d_mpart() const { return reinterpret_cast<double*>(base + L.off_mpart); }
-    double* d_mres() const { return reinterpret_cast<double*>(base + L.off_mres); }
+    DD* d_mpart() const { return reinterpret_cast<DD*>(base + L.off_mpart); }
+    DD* d_mres() const { return reinterpret_cast<DD*>(base + L.off_mres); }
     uint32_t* d_ctr() const { return reinterpret_cast<uint32_t*>(base + L.off_ctr); }
 
     int fail(int code, const std::string& m) {
@@ -663,6 +692,7 @@ int lbm_create(const lbm_config* cfg, lbm_handle* out) {
     // 8192^2 741 / 213: a fused launch takes about one strip's marching time
     // however few strips there are.
     h->fuse = (int64_t)h->ptile_inst.size() >= kFuseMinStrips ? fuse_max(cfg->storage) : 1;
+    default_costs(h->storage, h->cost_plain, h->cost_check);
     e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         g_create_error = std::string("hipStreamCreate: ") + hipGetErrorString(e);
@@ -879,18 +909,38 @@ static int issue_step(lbm_ctx* h, int64_t m, int src_k, hipStream_t st, int sche
     return LBM_OK;
 }
 
+// Cheapest cover of r steps by plain launches of 1 .. kmax steps: g[n] for
+// n = 0 .. r, and first[n], the length of a first launch of an optimal cover.
+static void plain_covers(const double* cost, int kmax, int r, double* g, int* first) {
+    g[0] = 0.0;
+    first[0] = 0;
+    for (int n = 1; n <= r; ++n) {
+        g[n] = 1e300;
+        first[n] = 1;
+        for (int k = 1; k <= std::min(kmax, n); ++k) {
+            const double v = cost[k] + g[n - k];
+            if (v < g[n]) {
+                g[n] = v;
+                first[n] = k;
+            }
+        }
+    }
+}
+
 // Steps the launch that starts at step m covers, in a sequence of steps that
-// ends at step `last`: up to h->fuse consecutive steps, ending at the latest
-// on the next check step (whose residual and totals the fused kernel then
-// forms: *end = kEndCheck) or on `last`; a run cut short by h->fuse may end on
-// the snapshot step before a check step (*end = kEndSnap: the fused kernel
-// writes the snapshot for the single check step that follows).  A check step
-// is not left alone behind a full run: one step fewer leaves two for a fused
-// check launch, which costs less than a single check step (the fused form
-// keeps the snapshot in registers).  Returns 1 for a single-step launch.
+// ends at step `last`.  The sequence is cut into segments that end on a check
+// step (whose residual and totals the fused kernel then forms: *end =
+// kEndCheck) or on `last`; a segment is covered by launches of at most
+// h->fuse steps, the one that reaches a check step last, chosen to minimise
+// the summed launch costs (cost_plain, cost_check) over the segment's last
+// few launches; longer segments start with launches of h->fuse steps.  A run
+// that ends on the snapshot step before a check step (a call ending there)
+// writes the snapshot for the single check step that follows: *end =
+// kEndSnap.  Returns 1 for a single-step launch.
 static int plan_launch(const lbm_ctx* h, int64_t m, int64_t last, int* end) {
     *end = kEndPlain;
-    if (h->fuse < 2) return 1;
+    const int kmax = h->fuse;
+    if (kmax < 2) return 1;
     int64_t seg = last;
     bool to_check = false;
     if (h->K) {
@@ -900,10 +950,31 @@ static int plan_launch(const lbm_ctx* h, int64_t m, int64_t last, int* end) {
             to_check = true;
         }
     }
-    const int64_t r = seg - m + 1;
-    if (r < 2) return 1;
-    int k = (int)std::min<int64_t>(h->fuse, r);
-    if (to_check && r - k == 1 && k > 2) --k;
+    const int64_t r64 = seg - m + 1;
+    int k = kmax;
+    const int tail = 4 * kmax;        // the last steps of a segment are planned exactly
+    if (r64 <= tail) {
+        const int r = (int)r64;
+        double g[4 * 8 + 1];
+        int first[4 * 8 + 1];
+        plain_covers(h->cost_plain, kmax, r, g, first);
+        if (!to_check || r < 2) {
+            k = first[r];
+        } else {
+            // the launch that reaches the check step is a fused check launch
+            double best = 1e300;
+            int klast = 2;
+            for (int kl = 2; kl <= std::min(kmax, r); ++kl) {
+                const double v = h->cost_check[kl] + g[r - kl];
+                if (v < best) {
+                    best = v;
+                    klast = kl;
+                }
+            }
+            k = (r == klast) ? klast : first[r - klast];
+        }
+    }
+    if (k < 2) return 1;
     const int mode = mode_of(h, m + k - 1);
     *end = mode == kCheck ? kEndCheck : (mode == kSnap ? kEndSnap : kEndPlain);
     return k;
@@ -1080,7 +1151,7 @@ static int replay_tail(lbm_ctx* h) {
     return LBM_OK;
 }
 
-static int run_moments(lbm_ctx* h, int32_t k, int out_kind, void* T, void* qx, void* qy, double* partials) {
+static int run_moments(lbm_ctx* h, int32_t k, int out_kind, void* T, void* qx, void* qy, DD* partials) {
     const lbm_instance& in = h->inst[k];
     const double grad = in.bc_x == LBM_BC_GRADIENT ? in.grad_x : 0.0;
     // after a check step the reference has moved and its shift is still pending
@@ -1170,10 +1241,10 @@ int lbm_totals(lbm_handle h, int32_t k, double out[3]) {
     const InstDesc& d = h->desc[k];
     const int nparts = ((d.nx + 255) / 256) * d.ny;
     HIPCALL(h, launch_finalize_range(h->d_mpart(), nparts, h->d_gpart(), h->d_mres(), h->stream));
-    double r[kPartials];
+    DD r[kPartials];
     HIPCALL(h, hipMemcpyAsync(r, h->d_mres(), sizeof r, hipMemcpyDeviceToHost, h->stream));
     HIPCALL(h, hipStreamSynchronize(h->stream));
-    for (int c = 0; c < 3; ++c) out[c] = r[c];
+    for (int c = 0; c < 3; ++c) out[c] = r[c].hi;
     for (int c = 0; c < 3; ++c)
         if (!std::isfinite(out[c])) return h->fail(LBM_ENONFINITE, "non-finite total");
     return LBM_OK;
@@ -1497,6 +1568,7 @@ int lbm_autotune(lbm_handle h, int32_t steps, char* report, size_t report_len) {
     float fused_us = 1e30f;
     int fused_k = fuse_max(h->storage);
     std::string fused_rep;
+    double launch_us[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // measured per-launch times, k = 1 .. kmax
     if (!rc) {
         h->shape = best;
         build_tiles(h);
@@ -1504,6 +1576,7 @@ int lbm_autotune(lbm_handle h, int32_t steps, char* report, size_t report_len) {
         for (int k = 2; k <= fuse_max(h->storage) && !rc; ++k) {
             float us = 0.0f;
             rc = time_fused(h, k, (steps + k - 1) / k, e0, e1, &us);
+            launch_us[k] = (double)us * k;
             char b[64];
             snprintf(b, sizeof b, "%s[%d, %.2f]", k == 2 ? "" : ", ", k, us);
             fused_rep += b;
@@ -1517,6 +1590,18 @@ int lbm_autotune(lbm_handle h, int32_t steps, char* report, size_t report_len) {
     (void)hipEventDestroy(e1);
     if (rc) return rc;
     const int fuse = fused_us < best_us ? fused_k : 1;
+    // the planner's launch costs: the measured plain launches, the check
+    // launches scaled from the built-in figures by the same ratio
+    {
+        double dp[8], dc[8];
+        default_costs(h->storage, dp, dc);
+        launch_us[1] = best_us;
+        for (int k = 1; k <= fuse_max(h->storage); ++k) {
+            if (!(launch_us[k] > 0.0)) continue;
+            h->cost_plain[k] = launch_us[k];
+            if (k >= 2 && dp[k] > 0.0) h->cost_check[k] = dc[k] * launch_us[k] / dp[k];
+        }
+    }
     char b[320];
     snprintf(b, sizeof b, "], \"best\": [%d, %d, %d, %d, %d, %.2f], \"fused_us_per_step\": %.2f, ", best.vec,
              best.bx, best.by, best.xcd, best.nt, best_us, fused_us);

@@ -35,9 +35,10 @@ def _random_case(nx, ny, tau_n, tau_r, seed, **kw):
     return case, T0, qx, qy
 
 
-# BF16 (8 significant bits) is held to a sanity bound on rough states (the
-# split form meets 5e-3 on the full-size workloads)
-TOL_STORAGE = {"f32": 1e-5, "f16": 5e-3, "bf16": 5e-2, "f16_split": 5e-3, "bf16_split": 5e-2}
+# FP32 1e-5, 16-bit 5e-3.  Plain BF16 (8 significant bits per population)
+# misses the 16-bit bound on the heat flux of rough random states (measured
+# 2.8e-3 .. 6.2e-3): held to 1e-2 and labelled so; the split BF16 form meets it.
+TOL_STORAGE = {"f32": 1e-5, "f16": 5e-3, "bf16": 1e-2, "f16_split": 5e-3, "bf16_split": 5e-3}
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16", "f16_split", "bf16_split"])
@@ -92,7 +93,7 @@ def test_stochastic_rounding_deterministic_and_close(storage):
             ref_out = out
             e = eps(case, out, ora)
             log(f"stochastic 131x37 {storage}: eps={e}")
-            assert max(e) < {"f32": 1e-5, "f16": 5e-3, "bf16": 5e-2}[storage]
+            assert max(e) < TOL_STORAGE[storage]
         else:
             for a, b in zip(out, ref_out):
                 assert np.array_equal(a, b), (sh, layout)
@@ -154,13 +155,14 @@ def test_isothermal_walls_128x64_5000_steps():
     e_t, e_q = eps(case, g, ora)
     log(f"walls 128x64 f32: eps_T={e_t:.3e} eps_q={e_q:.3e}")
     assert e_t < 1e-5 and e_q < 1e-5
-    # 16-bit storage is meant for the large periodic grids; on this slow
+    # plain FP16 to nearest misses the 16-bit bound here: on this slow
     # diffusive transient the per-step change of most populations falls below
-    # half an FP16 ulp and the rounded map stalls: reported, bounded only
+    # half an FP16 ulp and the rounded map stalls (measured 1.233e-2 /
+    # 2.392e-2, a deterministic run: held within 0.8x .. 1.25x of that)
     g16 = gpu_fields(case, case.steps, storage="f16")
     e_t, e_q = eps(case, g16, ora)
-    log(f"walls 128x64 f16: eps_T={e_t:.3e} eps_q={e_q:.3e}")
-    assert e_t < 0.1 and e_q < 0.1
+    log(f"walls 128x64 f16: eps_T={e_t:.3e} eps_q={e_q:.3e} (misses the 16-bit bound)")
+    assert 0.8 * 1.233e-2 <= e_t <= 1.25 * 1.233e-2 and 0.8 * 2.392e-2 <= e_q <= 1.25 * 2.392e-2
     # the split form keeps the energy in FP32 and does not stall
     for storage in ("f16_split", "bf16_split"):
         e_t, e_q = eps(case, gpu_fields(case, case.steps, storage=storage), ora)
@@ -566,7 +568,12 @@ def test_fused_kernel_small_and_ragged(nx, ny, storage):
         for ra, rb in zip(a, b):
             for u, v in zip(ra[0][:3], rb[0][:3]):
                 assert np.array_equal(u, v), (nx, ny, storage, fuse)
-    assert max(eps(case, a[-1][0][:3], oracle_fields(case, sum(steps), T0, qx, qy))) < TOL_STORAGE[storage]
+    e = eps(case, a[-1][0][:3], oracle_fields(case, sum(steps), T0, qx, qy))
+    # plain BF16 misses the 16-bit bound on these rough states, most on the
+    # smallest lattices (measured 1.6e-2 .. 2.6e-2 for 2 x 2 .. 5 x 3): 3e-2
+    tol = 3e-2 if storage == "bf16" else TOL_STORAGE[storage]
+    log(f"fused small {nx}x{ny} {storage}: eps={e}")
+    assert max(e) < tol
 
 
 def test_autotune_choices_cache_and_results(tmp_path, monkeypatch):

@@ -10,11 +10,19 @@ FP64 oracle.
   stepped by the oracle, and the batched / per-instance / graph schedules.
 
 Tolerances (relative L2 of the temperature deviation and of the heat flux):
-FP32 storage 1e-5; split 16-bit storage (FP32 energy, 16-bit non-equilibrium
-shares) 5e-3 for FP16 and BF16.  Plain 16-bit population storage keeps the
-temperature within 5e-3 with stochastic rounding, but on these smooth fields
-the heat flux is about a hundredth of the stored populations, so its 16-bit
-rounding noise is too: its heat-flux error is reported with a sanity bound.
+FP32 storage 1e-5; 16-bit storage 5e-3.  The split 16-bit kinds (FP32 energy,
+16-bit non-equilibrium shares) meet 5e-3 on every workload, in FP16 and BF16.
+Plain 16-bit population storage (the eight populations in 16 bits) meets it
+where stated below and otherwise misses the 16-bit bound: on these smooth
+fields the heat flux is about a hundredth of the stored populations, so its
+16-bit rounding noise is too (and round to nearest stalls the smooth field).
+Those misses are asserted as a band around the measured value (the runs are
+deterministic: fixed seeds), so that a change in either direction shows, and
+every row is also held to the per-node maximum error bound.
+
+Sampled rows of the full-size workloads sit off the 32-row marching chunks'
+first rows (offsets 17 and 31 within a chunk), where the fused kernel's
+carried pipeline state decides the result.
 """
 import math
 
@@ -31,10 +39,23 @@ from paper_2010_01847_amd import Lattice, instance_from_case
 pytestmark = pytest.mark.gpu
 
 TOL = {"f32": 1e-5, "f16_split": 5e-3, "bf16_split": 5e-3}
-# plain 16-bit storage: round to nearest stalls on these smooth fields (see the
-# stochastic-rounding flag), stochastic rounding keeps T but not q
-TOL_RN16 = 0.5
-TOL_SR16_Q = 0.1
+TOL16 = 5e-3
+# plain 16-bit kinds that miss the 16-bit bound on a workload: the measured
+# (eps_T, eps_q) of the fixed-seed run; None where the bound is met
+MISSES = {
+    ("second_sound", "bf16", "stochastic"): (None, 2.835e-2),
+    ("second_sound", "f16", "nearest"): (1.645e-2, 3.106e-2),
+    ("second_sound", "bf16", "nearest"): (1.140e-1, 3.089e-1),
+    ("smooth_modes", "f16", "stochastic"): (None, 1.045e-2),
+    ("smooth_modes", "bf16", "stochastic"): (None, 8.322e-2),
+    ("smooth_modes", "f16", "nearest"): (8.822e-3, 1.749e-2),
+    ("smooth_modes", "bf16", "nearest"): (2.921e-2, 1.264e-1),
+}
+BAND = (0.8, 1.25)
+# per-node maximum error over the field's maximum magnitude: FP32 storage
+# 3e-5 (measured up to 1.07e-5), split 16-bit kinds 3e-2 (measured up to
+# 8.9e-3), plain 16-bit kinds 1 (their L2 misses are bounded by BAND)
+MAXREL = {"f32": 3e-5, "f16_split": 3e-2, "bf16_split": 3e-2, "f16": 1.0, "bf16": 1.0}
 
 
 def _rel(a, b, base):
@@ -42,13 +63,27 @@ def _rel(a, b, base):
     return math.sqrt(float(np.sum((a - b) ** 2))) / den if den > 0 else 0.0
 
 
-def _tol(storage, rounding):
-    """(bound on eps_T, bound on eps_q)"""
+def _max_rel(pairs):
+    """Per-node maximum error relative to the field's maximum magnitude."""
+    num = max(float(np.abs(a - b).max()) for a, b in pairs)
+    den = max(float(np.abs(b).max()) for _, b in pairs)
+    return num / den if den > 0 else num
+
+
+def _assert_eps(workload, storage, rounding, e_t, e_q):
+    """FP32 1e-5, 16-bit 5e-3; a plain 16-bit kind that misses the 16-bit
+    bound is held within BAND of its measured error."""
     if storage in TOL:
-        return TOL[storage], TOL[storage]
-    if rounding == "stochastic":
-        return 5e-3, TOL_SR16_Q
-    return TOL_RN16, TOL_RN16
+        assert e_t < TOL[storage] and e_q < TOL[storage], (workload, storage, rounding, e_t, e_q)
+        return
+    miss = MISSES.get((workload, storage, rounding), (None, None))
+    for got, meas, name in ((e_t, miss[0], "eps_T"), (e_q, miss[1], "eps_q")):
+        if meas is None:
+            assert got < TOL16, (workload, storage, rounding, name, got)
+        else:
+            log(f"  {workload} {storage} {rounding} {name} misses the 16-bit bound: {got:.3e} "
+                f"(measured {meas:.3e})")
+            assert BAND[0] * meas <= got <= BAND[1] * meas, (workload, storage, rounding, name, got, meas)
 
 
 def _run_rows(case, storage, scale, steps, rows, T0, check=100, rounding="nearest"):
@@ -75,7 +110,9 @@ def second_sound_exact():
     x = np.arange(case.nx, dtype=np.float64)
     f = np.exp(-(x - a["cx"]) ** 2 / (2 * a["sigma"] ** 2))
     sol = bloch.SeparableSolution(f, f, a["amp"], case.steps, case.tau_n, case.tau_r)
-    rows = list(range(0, case.ny, 32)) + [a["cy"] + k for k in (-1, 1, 2)]
+    # offsets 17 and 31 within the 32-row chunks, and the pulse's centre rows
+    rows = sorted(set(list(range(17, case.ny, 32)) + list(range(31, case.ny, 64))
+                      + [a["cy"] + k for k in (-1, 0, 1, 2)]))
     return case, rows, sol.rows(rows)
 
 
@@ -94,11 +131,13 @@ def test_second_sound_8192(second_sound_exact, storage, rounding):
     (dT, qx, qy), info = _run_rows(case, storage, scale, case.steps, rows, T0, rounding=rounding)
     e_t = _rel(dT, To - 1.0, To - 1.0)
     e_q = math.sqrt(float(np.sum((qx - qxo) ** 2 + (qy - qyo) ** 2))) / math.sqrt(float(np.sum(qxo ** 2 + qyo ** 2)))
+    m_t = _max_rel([(dT, To - 1.0)])
+    m_q = _max_rel([(qx, qxo), (qy, qyo)])
     exact_total = 0.01 * 2 * math.pi * 20.0 ** 2            # sum of the pulse over the plane
-    log(f"second sound 8192^2 {storage} {rounding}: eps_T={e_t:.3e} eps_q={e_q:.3e} "
-        f"total E={info['totals'][0]:.8f} (exact {exact_total:.8f}) r={info['residual']:.3e}")
-    tol_t, tol_q = _tol(storage, rounding)
-    assert e_t < tol_t and e_q < tol_q
+    log(f"second sound 8192^2 {storage} {rounding}: eps_T={e_t:.3e} eps_q={e_q:.3e} max_T={m_t:.3e} "
+        f"max_q={m_q:.3e} total E={info['totals'][0]:.8f} (exact {exact_total:.8f}) r={info['residual']:.3e}")
+    _assert_eps("second_sound", storage, rounding, e_t, e_q)
+    assert m_t < MAXREL[storage] and m_q < MAXREL[storage]
     if storage == "f32":
         assert info["totals"][0] == pytest.approx(exact_total, rel=1e-6)
 
@@ -152,7 +191,8 @@ def test_smooth_modes_16384(storage, rounding):
     tau_N = 0.6, tau_R = 5, 1000 steps; FP16 with scale 2^-22."""
     case = W.smooth_modes_case()
     modes = case.init_args["modes"]
-    rows = list(range(0, case.ny, 64))
+    # offsets 17 and 31 within the 32-row chunks
+    rows = sorted(list(range(17, case.ny, 64)) + list(range(63, case.ny, 64)))
     sol = bloch.ModeSolution(modes, case.nx, case.ny, case.steps, case.tau_n, case.tau_r)
     To, qxo, qyo = sol.rows(rows)
     T0 = W.modes_field_torch(modes, case.nx, case.ny, case.t0, device="cuda")
@@ -162,10 +202,12 @@ def test_smooth_modes_16384(storage, rounding):
     torch.cuda.empty_cache()
     e_t = _rel(dT, To - 1.0, To - 1.0)
     e_q = math.sqrt(float(np.sum((qx - qxo) ** 2 + (qy - qyo) ** 2))) / math.sqrt(float(np.sum(qxo ** 2 + qyo ** 2)))
-    log(f"smooth modes 16384^2 {storage} {rounding}: eps_T={e_t:.3e} eps_q={e_q:.3e} "
-        f"total E={info['totals'][0]:.3e}")
-    tol_t, tol_q = _tol(storage, rounding)
-    assert e_t < tol_t and e_q < tol_q
+    m_t = _max_rel([(dT, To - 1.0)])
+    m_q = _max_rel([(qx, qxo), (qy, qyo)])
+    log(f"smooth modes 16384^2 {storage} {rounding}: eps_T={e_t:.3e} eps_q={e_q:.3e} max_T={m_t:.3e} "
+        f"max_q={m_q:.3e} total E={info['totals'][0]:.3e}")
+    _assert_eps("smooth_modes", storage, rounding, e_t, e_q)
+    assert m_t < MAXREL[storage] and m_q < MAXREL[storage]
 
 
 # ---------------------------------------------------------------- Poiseuille
@@ -187,12 +229,13 @@ def _oracle_steady(case):
 @pytest.mark.parametrize("tau_n", W.POISEUILLE_TAU_N)
 def test_poiseuille_steady_1024x256(tau_n, ratio, rounding):
     """Channel 1024 x 256 (gradient seam G = 1e-3, diffuse walls) run to steady
-    state on the GPU against the oracle's FP64 steady state.  Round to
-    nearest: check every 1000 steps until r < 1e-10 or r = 0 (the rounded
-    map's fixed point, which for tau_R / tau_N = 1000 is reached before the
-    true steady state: reported, bounded at 1e-4).  Stochastic rounding keeps
-    converging in expectation; the one-step residual then stays at the
-    rounding-noise level, so it runs twice the steps the FP64 oracle needed."""
+    state on the GPU against the oracle's FP64 steady state, both roundings
+    held to the FP32 bound 1e-5 (the reference state tracks the mean flux, so
+    the stored values are the small departures from it even at tau_R / tau_N =
+    1000).  Round to nearest: check every 1000 steps until r < 1e-10 or r = 0
+    (the rounded map's fixed point).  Stochastic rounding keeps converging in
+    expectation; the one-step residual then stays at the rounding-noise level,
+    so it runs twice the steps the FP64 oracle needed."""
     case = W.poiseuille_case(tau_n, ratio)
     small = W.poiseuille_case(tau_n, ratio, nx=4)
     (To, qxo, qyo), osteps = _oracle_steady(small)
@@ -225,8 +268,7 @@ def test_poiseuille_steady_1024x256(tau_n, ratio, rounding):
     log(f"poiseuille tn={tau_n} ratio={ratio:g} {rounding}: gpu steps={steps} r={r:.2e} oracle steps={osteps} "
         f"eps_q={e_q:.3e} eps_qy={e_qy:.1e} lambda_eff/lambda={cond:.5f} (Eq.69 "
         f"{cf.poiseuille_conductivity_eq69(kn_c, kn_r):.5f})")
-    tol = 1e-5 if (rounding == "stochastic" or ratio < 1000) else 1e-4
-    assert e_q < tol and e_qy < tol
+    assert e_q < 1e-5 and e_qy < 1e-5
     assert cond == pytest.approx(cf.poiseuille_conductivity_eq69(kn_c, kn_r), rel=0.01)
 
 
@@ -234,30 +276,31 @@ def test_poiseuille_steady_1024x256(tau_n, ratio, rounding):
 
 @pytest.mark.parametrize("rounding", ["stochastic", "nearest"])
 def test_knudsen_sweep_256_instances(rounding):
-    """256 uneven channel instances in one handle, 2000 steps batched; six of
-    them against the oracle; the three schedules agree bit for bit.  Round to
-    nearest stalls slowly converging channels (tau_R of a few hundred) above
-    1e-5: bounded at 1e-4 and reported."""
+    """256 uneven channel instances in one handle, 2000 steps under each of the
+    batched, per-instance and graph schedules: the three agree bit for bit on
+    the compared instances, and six of them match the oracle to the FP32 bound."""
     cases = W.knudsen_sweep()
     insts = [instance_from_case(c) for c in cases]
     steps = 2000
+    picks = (0, 1, 2, 3, 4, 5, 255)
     outs = {}
     for sched in ("graph", "batched", "per_instance"):
         lat = Lattice(insts, check_interval=100, rounding=rounding, seed=7)
         lat.set_schedule(sched)
         for k in range(len(cases)):
             lat.init(k)
-        lat.step(steps if sched == "graph" else 200)
-        outs[sched] = [lat.moments(k) for k in (0, 1, 2, 3, 4, 5, 255)]
+        lat.step(steps)
+        outs[sched] = [lat.moments(k) for k in picks]
         lat.close()
-    for k, out in zip((0, 1, 2, 3, 4, 5, 255), outs["batched"]):
-        for a, b in zip(out, outs["per_instance"][(0, 1, 2, 3, 4, 5, 255).index(k)]):
-            assert np.array_equal(a, b), k
+    for sched in ("per_instance", "graph"):
+        for j, k in enumerate(picks):
+            for a, b in zip(outs[sched][j], outs["batched"][j]):
+                assert np.array_equal(a, b), (sched, k)
     worst = 0.0
-    for j, k in enumerate((0, 1, 2, 3, 4, 5)):
+    for j, k in enumerate(picks[:6]):
         case = cases[k]
-        e_t, e_q = eps(case, outs["graph"][j], oracle_fields(case, steps))
+        e_t, e_q = eps(case, outs["batched"][j], oracle_fields(case, steps))
         worst = max(worst, e_t, e_q)
         log(f"sweep {rounding} instance {k} {case.nx}x{case.ny} tau_n={case.tau_n:.3f} "
             f"tau_r={case.tau_r:.3g}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
-    assert worst < (1e-5 if rounding == "stochastic" else 1e-4)
+    assert worst < 1e-5
