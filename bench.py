@@ -110,6 +110,7 @@ def _parse():
                    help="steps after which each second-sound row is compared with the exact solution")
     p.add_argument("--sweep-steps", type=int, default=300, help="timed steps per sweep schedule (0: skip)")
     p.add_argument("--small", type=int, default=1, help="walls and channel rows (0: skip)")
+    p.add_argument("--front", type=int, default=1, help="pulse-front speed run (0: skip)")
     p.add_argument("--fusion", default="auto",
                    help="most time steps per launch (auto: the library's default for the storage kind)")
     p.add_argument("--check-interval", type=int, default=100)
@@ -659,7 +660,7 @@ def main():
         rnd = rnd or _default_rounding(st)
         if (st, rnd) != (args.storage, main_rounding):
             rows.append(_run_c3(args, st, rnd, torch, P, W, c3_sample_rows))
-    front = _run_front(args, torch, P, W)
+    front = _run_front(args, torch, P, W) if args.front else None
     walls = _run_walls(torch, P, W) if args.small else None
     channel = _run_channel(torch, P, W) if args.small else None
     sweep = _run_sweep(args, torch, P, W) if args.sweep_steps > 0 else None

@@ -315,6 +315,20 @@ __device__ __forceinline__ DD wave_sum(DD v) {
     return v;
 }
 
+// Add one node's check-step values (energy, heat flux, squared change and
+// squared size of m = (dT, qx, qy) against the previous step's p) to a lane's
+// sums.  The x-flux total decides the reference-flux rebase and is summed
+// compensated from the first node on; the others, only reported, are plain
+// FP64 per lane (lo stays 0) and compensated from the lane sums on.
+__device__ __forceinline__ void check_sums(DD acc[kPartials], double e, double qx, double qy, double dT, double p0,
+                                           double p1, double p2) {
+    acc[0].hi += e;
+    acc[1] = dd_add(acc[1], qx);
+    acc[2].hi += qy;
+    acc[3].hi += (dT - p0) * (dT - p0) + (qx - p1) * (qx - p1) + (qy - p2) * (qy - p2);
+    acc[4].hi += dT * dT + qx * qx + qy * qy;
+}
+
 // Sum kPartials compensated values over the block in a fixed order; thread 0
 // writes them.
 __device__ __forceinline__ void block_partials(DD v[kPartials], DD* out) {
@@ -420,11 +434,7 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t sna
                 } else {
                     const double p0 = a.snap[n], p1 = a.snap[n + snap_stride],
                                  p2 = a.snap[n + 2 * snap_stride];
-                    acc[0] = dd_add(acc[0], d.s * E);
-                    acc[1] = dd_add(acc[1], qx);
-                    acc[2] = dd_add(acc[2], qy);
-                    acc[3] = dd_add(acc[3], (dT - p0) * (dT - p0) + (qx - p1) * (qx - p1) + (qy - p2) * (qy - p2));
-                    acc[4] = dd_add(acc[4], dT * dT + qx * qx + qy * qy);
+                    check_sums(acc, d.s * E, qx, qy, dT, p0, p1, p2);
                 }
             }
         }
@@ -1025,9 +1035,14 @@ __device__ __forceinline__ void march_gather(const float dn_row[8], const float 
 template <class S, int SR, int SPLIT, int K, int KMAX, int END, int CH>
 __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int nontemporal, int64_t snap_stride) {
     static_assert(K >= 2 && K <= KMAX, "stages per launch");
-    // input rows loaded ahead (measured on MI355X: two or three rows ahead are
-    // no faster than one, and take 8 more VGPRs per row)
-    constexpr int PF = 1;
+    // input rows loaded ahead: one iteration's stages must cover a row load's
+    // latency, so launches of few plain steps load further ahead (8 VGPRs per
+    // FP32 row).  Measured on MI355X (8192^2, us per launch, ahead 1 / more):
+    // FP32 three steps 1269 / 1186 (two ahead), two steps 1188 / 1247 (three);
+    // FP16 two steps 656 / 603 (three), three 632 / 607 (two), four 745 / 788
+    // (two); the check launches' FP64 work covers the latency by itself.
+    constexpr int PF = END == kEndCheck ? 1
+                     : (K == 3 ? 2 : ((K == 2 && sizeof(S) == 2) ? 3 : 1));
     static_assert(PF >= 1 && PF <= 2 * K + 1, "the first PF rows are all input rows");
     constexpr int W = 64 - 2 * KMAX;
     const int lane = threadIdx.x & 63;
@@ -1154,12 +1169,7 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
                             double E, dT, qx, qy;
                             node_moments_f64(g, d, q_ref, E, dT, qx, qy);
                             const double p0 = pm_old[0], p1 = pm_old[1], p2 = pm_old[2];
-                            acc[0] = dd_add(acc[0], d.s * E);
-                            acc[1] = dd_add(acc[1], qx);
-                            acc[2] = dd_add(acc[2], qy);
-                            acc[3] = dd_add(acc[3], (dT - p0) * (dT - p0) + (qx - p1) * (qx - p1)
-                                                    + (qy - p2) * (qy - p2));
-                            acc[4] = dd_add(acc[4], dT * dT + qx * qx + qy * qy);
+                            check_sums(acc, d.s * E, qx, qy, dT, p0, p1, p2);
                         }
                         uint32_t r[4] = {0u, 0u, 0u, 0u};
                         if (SR)

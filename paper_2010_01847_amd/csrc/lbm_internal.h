@@ -14,12 +14,13 @@ constexpr int kGroup = 1024;       // tile records per first-stage reduction blo
 
 // A compensated FP64 sum: the value is hi + lo with |lo| <= ulp(hi) / 2, and hi
 // alone is the sum rounded to double.  The reductions carry their partial sums
-// in this form (partial records are kPartials of them), so a total is the
-// correctly rounded sum of its node values except with a probability of order
-// N 2^-53 times the sum's condition number, whatever the grouping of the
-// nodes into tiles: the reference-flux update at check steps, which rounds a
-// small difference of such a total to FP32, then does not depend on the
-// kernel, launch shape or schedule that formed it.
+// in this form (partial records are kPartials of them).  The total x-flux is
+// summed compensated from the first node on, so it is the correctly rounded
+// sum of its node values except with a probability of order N 2^-53 times the
+// sum's condition number, whatever the grouping of the nodes into tiles: the
+// reference-flux update at check steps, which rounds a small difference of
+// that total to FP32, then does not depend on the kernel, launch shape or
+// schedule that formed it.  The other sums are only reported.
 struct DD {
     double hi, lo;
 };

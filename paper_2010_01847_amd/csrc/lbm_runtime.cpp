@@ -98,27 +98,31 @@ Geometry geometry_of(const lbm_instance& in, int es, int layout, bool split = fa
 }
 
 // Launch costs of a k-step launch on the second-sound lattice 8192^2
-// (MI355X, microseconds; k = 1 is the single-step kernel).  A fused launch
-// costs about the same for every k from 2 up (its time goes to the rows it
-// streams and the strips' halo rather than to the number of stages), so the
-// way a short run is cut into launches matters: 20 FP32 steps cost 4344 us as
-// 5 + 5 + 5 + 5 and 4470 us as 6 + 6 + 6 + 2.  The check variant of six FP32
-// steps needs 124 VGPRs (three waves per SIMD instead of four).  BF16 kinds
-// take the FP16 kinds' figures.  lbm_autotune replaces the plain figures by
-// its own timings on the handle's lattices and scales the check figures.
+// (MI355X, microseconds; k = 1 is the single-step kernel), plain and ending on
+// the check step.  A fused launch costs about the same for every k from 2 up
+// (it streams the same rows and the strips' halo whatever the number of
+// stages; below five FP32 steps it is bound by memory requests, above by
+// VALU issue), so the way a short run is cut into launches matters: 20 FP32
+// steps cost 4344 us as 5 + 5 + 5 + 5 and 4470 us as 6 + 6 + 6 + 2.  The
+// check variants of five and six FP32 steps need 130 and 144 VGPRs (three
+// waves per SIMD instead of four).  lbm_autotune replaces the plain figures
+// by its own timings on the handle's lattices and scales the check figures.
 static void default_costs(int storage, double plain[8], double check[8]) {
-    static const double f32_p[7] = {0, 736, 1188, 1268, 1214, 1086, 1094};
-    static const double f32_c[7] = {0, 0, 1192, 1084, 1087, 1090, 1311};
-    static const double f16_p[5] = {0, 481, 656, 628, 751};
-    static const double f16_c[5] = {0, 0, 611, 804, 980};
-    static const double spl_p[5] = {0, 486, 805, 779, 862};
-    static const double spl_c[5] = {0, 0, 724, 860, 1043};
-    const double* p = storage == LBM_F32 ? f32_p : (is_split(storage) ? spl_p : f16_p);
-    const double* c = storage == LBM_F32 ? f32_c : (is_split(storage) ? spl_c : f16_c);
+    static const double p_tab[5][7] = {{0, 736, 1188, 1186, 1214, 1086, 1094},   // F32
+                                       {0, 480, 603, 607, 745, 0, 0},            // F16
+                                       {0, 484, 606, 605, 733, 0, 0},            // BF16
+                                       {0, 486, 713, 722, 861, 0, 0},            // F16_SPLIT
+                                       {0, 509, 710, 744, 909, 0, 0}};           // BF16_SPLIT
+    static const double c_tab[5][7] = {{0, 0, 1194, 1082, 1089, 1189, 1331},
+                                       {0, 0, 643, 833, 1017, 0, 0},
+                                       {0, 0, 685, 856, 1015, 0, 0},
+                                       {0, 0, 740, 890, 1072, 0, 0},
+                                       {0, 0, 751, 932, 1123, 0, 0}};
     for (int k = 0; k < 8; ++k) plain[k] = check[k] = 0.0;
+    if (storage < 0 || storage > 4) return;
     for (int k = 1; k <= fuse_max(storage); ++k) {
-        plain[k] = p[k];
-        check[k] = c[k];
+        plain[k] = p_tab[storage][k];
+        check[k] = c_tab[storage][k];
     }
 }
 
@@ -952,11 +956,11 @@ static int plan_launch(const lbm_ctx* h, int64_t m, int64_t last, int* end) {
     }
     const int64_t r64 = seg - m + 1;
     int k = kmax;
-    const int tail = 4 * kmax;        // the last steps of a segment are planned exactly
+    const int tail = 8 * kmax;        // the last steps of a segment are planned exactly
     if (r64 <= tail) {
         const int r = (int)r64;
-        double g[4 * 8 + 1];
-        int first[4 * 8 + 1];
+        double g[8 * 8 + 1];
+        int first[8 * 8 + 1];
         plain_covers(h->cost_plain, kmax, r, g, first);
         if (!to_check || r < 2) {
             k = first[r];
