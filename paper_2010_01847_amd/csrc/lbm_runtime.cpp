@@ -743,7 +743,7 @@ int lbm_bind(lbm_handle h, void* device_buf, size_t bytes) {
 
 void lbm_destroy(lbm_handle h) {
     if (!valid(h)) return;
-    if (h->stream) hipStreamSynchronize(h->stream);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
     else (void)hipDeviceSynchronize();
     h->drop_graphs();
     if (h->owned && h->base) (void)hipFree(h->base);
