@@ -135,9 +135,8 @@ int lbm3d_totals(lbm3d_handle h, double out[4]);
  * owns 60 x 12 nodes of every plane of a z-range, marches along z, and keeps
  * the intermediate state, rounded exactly as a stored step, in LDS and
  * registers); 1 issues every step on its own.  Results are identical either
- * way.  Default: 2 for FP32 storage when the box holds at least 256 such
- * blocks (60 x 12 nodes of 32 planes each: one per CU), else 1; 1 for
- * FP16/BF16 (measured faster at 512^3).  Errors: EINVAL (steps not 1 or 2). */
+ * way.  Default: 2 when the box holds at least 256 such blocks (60 x 12 nodes
+ * of 32 planes each: one per CU), else 1.  Errors: EINVAL (steps not 1 or 2). */
 int lbm3d_set_step_fusion(lbm3d_handle h, int32_t steps);
 
 /* The current time steps per launch (1 or 2); -1 for an invalid handle. */

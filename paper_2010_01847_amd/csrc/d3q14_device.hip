@@ -199,19 +199,38 @@ __device__ __forceinline__ void relax_store_one(const Geometry& g, const Coeffs&
            nontemporal);
 }
 
-// One relaxation of all 14 directions, each rounded to S and read back as
-// the next step would load it.
+// One relaxation of all 14 directions, each rounded to S (the values a stored
+// step holds).
 template <class S, int SR, int... Is>
-__device__ __forceinline__ void relax_reload_all(const Coeffs& c, const float v[kQ], float wE_axis, float wE_corner,
-                                                 float jx, float jy, float jz, const uint32_t r[7], float out[kQ],
-                                                 std::integer_sequence<int, Is...>) {
-    ((out[Is] = Cvt<S>::ld(relax_round_one<S, SR, Is>(c, v, wE_axis, wE_corner, jx, jy, jz, r))), ...);
+__device__ __forceinline__ void relax_round_all(const Coeffs& c, const float v[kQ], float wE_axis, float wE_corner,
+                                                float jx, float jy, float jz, const uint32_t r[7], S out[kQ],
+                                                std::integer_sequence<int, Is...>) {
+    ((out[Is] = relax_round_one<S, SR, Is>(c, v, wE_axis, wE_corner, jx, jy, jz, r)), ...);
 }
 
-// Stochastic-rounding words of global node `node` at step `step`.
-__device__ __forceinline__ void sr_words(uint32_t r[7], uint32_t node, uint32_t step, uint32_t seed) {
+// Stochastic-rounding words (16 bits for each of directions 2k and 2k + 1 in
+// word k) of node (x, row) at step n, row = z ny + y:
+//     col_k(x) ^ (row_word(row, n) * m_k),
+// col_k a hash of the column keyed by (k, seed), row_word a hash of the row
+// keyed by (n, seed) (C. Wellons' lowbias32 finaliser, mix32), m_k fixed odd
+// multipliers (a bijection of the row word; m_0 = 1).  Each word is uniform and
+// independent of the value it rounds, so every rounding stays unbiased; words
+// of different rows or steps are independent.  A lane's column words are
+// hashed once per launch, a row's word once per wavefront on the scalar unit.
+__device__ __forceinline__ uint32_t sr_col_word3(uint32_t x, int k, uint32_t seed) {
+    return mix32(x ^ mix32(seed * 0x9e3779b9u + 0x632be5abu * (uint32_t)(k + 1)));
+}
+__device__ __forceinline__ uint32_t sr_row_word3(uint32_t row, uint32_t step, uint32_t seed) {
+    return mix32(row ^ mix32(step * 0x85ebca6bu + seed * 0x9e3779b9u));
+}
+__device__ __forceinline__ void sr_cols3(uint32_t colw[7], uint32_t x, uint32_t seed) {
 #pragma unroll
-    for (int k = 0; k < 7; ++k) r[k] = mix32(node ^ mix32(step * 8u + (uint32_t)k + seed * 0x9e3779b9u));
+    for (int k = 0; k < 7; ++k) colw[k] = sr_col_word3(x, k, seed);
+}
+__device__ __forceinline__ void sr_words3(uint32_t r[7], const uint32_t colw[7], uint32_t roww) {
+    constexpr uint32_t m[7] = {1u, 0x2c1b3c6du, 0x297a2d39u, 0x846ca68bu, 0x9e3779b1u, 0xc2b2ae35u, 0x27d4eb2fu};
+#pragma unroll
+    for (int k = 0; k < 7; ++k) r[k] = colw[k] ^ (roww * m[k]);
 }
 
 template <class S, int SR, int L, int... Is>
@@ -236,7 +255,11 @@ __global__ __launch_bounds__(512) void step_kernel(StepArgs a) {
     float E, jx, jy, jz;
     moments(v, E, jx, jy, jz);
     uint32_t r[7] = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
-    if (SR) sr_words(r, ((uint32_t)z * (uint32_t)a.g.ny + (uint32_t)y) * (uint32_t)a.g.nx + (uint32_t)x, a.step, a.seed);
+    if (SR) {
+        uint32_t colw[7];
+        sr_cols3(colw, (uint32_t)x, a.seed);
+        sr_words3(r, colw, sr_row_word3((uint32_t)z * (uint32_t)a.g.ny + (uint32_t)y, a.step, a.seed));
+    }
     relax_store_all<S, SR, L>(a.g, a.c, v, a.c.omega_axis * E, a.c.omega_corner * E, jx, jy, jz, r,
                               reinterpret_cast<S*>(a.dst), (int64_t)z * a.g.ny + y, x, a.nontemporal,
                               std::make_integer_sequence<int, kQ>{});
@@ -300,8 +323,12 @@ template <class S, int SR, int L, int YO, int NW>
 __global__ __launch_bounds__(64 * NW) void pair_kernel(PairArgs a) {
     constexpr int WR = YO + 4;                // window rows
     constexpr int NJ = (WR + NW - 1) / NW;    // window rows per wavefront (NW wavefronts)
-    __shared__ float lds_a[kQ][WR][64];       // stage 1 pulls (input values)
-    __shared__ float lds_b[kQ][YO + 2][64];   // stage 2 pulls (stage-1 values, inner rows)
+    // The window holds stored values (input planes, and stage-1 results rounded
+    // exactly as a stored step): in the storage type itself, so a 16-bit
+    // window takes half the LDS and its values need no conversion to be kept.
+    using LT = S;
+    __shared__ LT lds_a[kQ][WR][64];          // stage 1 pulls (input values)
+    __shared__ LT lds_b[kQ][YO + 2][64];      // stage 2 pulls (stage-1 values, inner rows)
     const Geometry& g = a.g;
     uint32_t tile = blockIdx.x;
     if (a.xcd_remap) {
@@ -325,17 +352,21 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(PairArgs a) {
     int gy[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) gy[j] = wrap_mod(y0 - 2 + wv + NW * j, g.ny);
+    // the lane's column words (stage 2 stores only where x0 + lx - 2 = gx)
+    uint32_t colw[7] = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    if (SR) sr_cols3(colw, (uint32_t)gx, a.seed);
 
-    S nvr[NJ][kQ];                            // the input plane, raw (converted where used, so
-                                              // that its loads stay in flight during stage 2)
-    float a_mid[NJ][4], a_up1[NJ][5], a_up2[NJ][5];   // later-needed input values
-    float b_mid[NJ][4], b_up1[NJ][5], b_up2[NJ][5];   // later-needed stage-1 values
+    S nvr[NJ][kQ];                            // the input plane, raw (it goes to LDS as stored)
+    LT a_mid[NJ][4], a_up1[NJ][5], a_up2[NJ][5];      // later-needed input values
+    LT b_mid[NJ][4], b_up1[NJ][5], b_up2[NJ][5];      // later-needed stage-1 values
+    LT zero;
+    __builtin_memset(&zero, 0, sizeof zero);
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) a_mid[j][k] = b_mid[j][k] = 0.0f;
+        for (int k = 0; k < 4; ++k) a_mid[j][k] = b_mid[j][k] = zero;
 #pragma unroll
-        for (int k = 0; k < 5; ++k) a_up1[j][k] = a_up2[j][k] = b_up1[j][k] = b_up2[j][k] = 0.0f;
+        for (int k = 0; k < 5; ++k) a_up1[j][k] = a_up2[j][k] = b_up1[j][k] = b_up2[j][k] = zero;
     }
 
     auto load_plane = [&](int zi) {
@@ -352,11 +383,11 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(PairArgs a) {
     load_plane(z0 - 2);
     for (int it = 0; it < iters; ++it) {
         const int zi = z0 - 2 + it;
-        float nv[NJ][kQ];                     // the input plane of this iteration
+        LT nv[NJ][kQ];                        // the input plane of this iteration
 #pragma unroll
         for (int j = 0; j < NJ; ++j)
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) nv[j][i] = Cvt<S>::ld(nvr[j][i]);
+            for (int i = 0; i < kQ; ++i) nv[j][i] = nvr[j][i];
         // stage 1 pulls: c_z = -1 movers of plane zi, 0 of zi - 1, +1 of zi - 2
         if (it >= 2) {
 #pragma unroll
@@ -373,11 +404,11 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(PairArgs a) {
         }
         __syncthreads();
         // stage 1: plane zi - 1 on the inner window
-        float s1[NJ][kQ];
+        LT s1[NJ][kQ];
 #pragma unroll
         for (int j = 0; j < NJ; ++j)
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) s1[j][i] = 0.0f;
+            for (int i = 0; i < kQ; ++i) s1[j][i] = zero;
         if (it >= 2) {
             const int zw = wrap_mod(zi - 1, g.nz);
 #pragma unroll
@@ -386,14 +417,13 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(PairArgs a) {
                 if (ly < 1 || ly > YO + 2 || lx < 1 || lx > 62) continue;
                 float v[kQ];
 #pragma unroll
-                for (int i = 0; i < kQ; ++i) v[i] = lds_a[i][ly - cy(i)][lx - cx(i)];
+                for (int i = 0; i < kQ; ++i) v[i] = Cvt<S>::ld(lds_a[i][ly - cy(i)][lx - cx(i)]);
                 float E, jx, jy, jz;
                 moments(v, E, jx, jy, jz);
                 uint32_t r[7] = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
-                if (SR) sr_words(r, ((uint32_t)zw * (uint32_t)g.ny + (uint32_t)gy[j]) * (uint32_t)g.nx + (uint32_t)gx,
-                                 a.step, a.seed);
-                relax_reload_all<S, SR>(a.c, v, a.c.omega_axis * E, a.c.omega_corner * E, jx, jy, jz, r, s1[j],
-                                        std::make_integer_sequence<int, kQ>{});
+                if (SR) sr_words3(r, colw, sr_row_word3((uint32_t)zw * (uint32_t)g.ny + (uint32_t)gy[j], a.step, a.seed));
+                relax_round_all<S, SR>(a.c, v, a.c.omega_axis * E, a.c.omega_corner * E, jx, jy, jz, r, s1[j],
+                                       std::make_integer_sequence<int, kQ>{});
             }
         }
         // the loaded plane's later-needed movers wait in registers
@@ -433,12 +463,11 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(PairArgs a) {
                 if (ly < 2 || ly > YO + 1 || lx < 2 || lx > 61 || ox >= g.nx || oy >= g.ny) continue;
                 float v[kQ];
 #pragma unroll
-                for (int i = 0; i < kQ; ++i) v[i] = lds_b[i][ly - 1 - cy(i)][lx - cx(i)];
+                for (int i = 0; i < kQ; ++i) v[i] = Cvt<S>::ld(lds_b[i][ly - 1 - cy(i)][lx - cx(i)]);
                 float E, jx, jy, jz;
                 moments(v, E, jx, jy, jz);
                 uint32_t r[7] = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
-                if (SR) sr_words(r, ((uint32_t)zo * (uint32_t)g.ny + (uint32_t)oy) * (uint32_t)g.nx + (uint32_t)ox,
-                                 a.step + 1u, a.seed);
+                if (SR) sr_words3(r, colw, sr_row_word3((uint32_t)zo * (uint32_t)g.ny + (uint32_t)oy, a.step + 1u, a.seed));
                 relax_store_all<S, SR, L>(g, a.c, v, a.c.omega_axis * E, a.c.omega_corner * E, jx, jy, jz, r, dst,
                                           (int64_t)zo * g.ny + oy, ox, a.nontemporal,
                                           std::make_integer_sequence<int, kQ>{});
@@ -491,6 +520,30 @@ hipError_t launch_pair(int storage, int sr, const PairArgs& a, hipStream_t st) {
         case 5: CALL(bf16_bits, 1); break;                            \
         default: return hipErrorInvalidValue;                         \
     }
+
+// ------------------------------------------------------------------ scratch contents
+
+// Words of a timing scratch pattern: each 16-bit half is a random sign, the
+// exponent pattern 0x3a and eight random mantissa bits, so the buffer reads as
+// moderate finite values in FP32 (about 1e-3), FP16 (0.75 .. 0.88) and BF16
+// (about 1e-3) with bits that change from element to element, as real data
+// do (zero-filled buffers run faster than real contents and bias timings).
+__global__ __launch_bounds__(256) void fill_kernel(uint32_t* __restrict__ p, int64_t nwords, uint32_t seed) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= nwords) return;
+    const uint32_t h = mix32((uint32_t)i ^ mix32((uint32_t)(i >> 32) + seed));
+    const uint32_t lo = (h & 0x8000u) | 0x3a00u | (h & 0xffu);
+    const uint32_t hi = ((h >> 16) & 0x8000u) | 0x3a00u | ((h >> 8) & 0xffu);
+    p[i] = (hi << 16) | lo;
+}
+
+hipError_t launch_fill(void* buf, size_t bytes, uint32_t seed, hipStream_t st) {
+    const int64_t n = (int64_t)(bytes / 4);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       reinterpret_cast<uint32_t*>(buf), n, seed);
+    return hipGetLastError();
+}
 
 // ------------------------------------------------------------------ init
 

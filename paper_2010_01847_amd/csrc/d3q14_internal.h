@@ -89,6 +89,10 @@ struct PairArgs {
 };
 hipError_t launch_pair(int storage, int sr, const PairArgs& a, hipStream_t st);
 
+// Fill `bytes` (a multiple of 4) with the timing scratch pattern of the
+// device file (moderate finite values in every storage type, changing bits).
+hipError_t launch_fill(void* buf, size_t bytes, uint32_t seed, hipStream_t st);
+
 // Equilibrium initial state: element (i, x) holds the scaled deviation of the
 // Eq. 15 equilibrium at node x + c_i, so that the first pull reads e_i(x, 0).
 hipError_t launch_init(int storage, const Geometry& g, void* dst, const double* T, const double* qx,

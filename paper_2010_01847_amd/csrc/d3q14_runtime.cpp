@@ -114,15 +114,16 @@ struct lbm3d_ctx {
     Layout3 L{};
     lbm3d_launch_shape shape{4, 1, 0, 1, 32};
     int fuse = 1;                // time steps per launch (1, or 2 with the z-marching kernel)
-    // two steps per launch for FP32 storage when the z-marching tiles fill the
-    // chip (one block per CU): a launch takes about one tile's marching time,
-    // so small boxes run single steps (measured FP32 us per step, single / two:
-    // 64^3 5.3 / 37.1, 128^3 34.1 / 41.2 with 132 tiles, 192^3 137 / 124 with
-    // 384, 512^3 2730 / 1870)
+    // two steps per launch when the z-marching tiles fill the chip (one block
+    // per CU): a launch takes about one tile's marching time, so small boxes
+    // run single steps (measured FP32 us per step, single / two: 64^3 5.3 /
+    // 37.1, 128^3 34.1 / 41.2 with 132 tiles, 192^3 137 / 124 with 384, 512^3
+    // 2670 / 1887; 512^3 FP16-SR 1464 / 1338, BF16-SR 1493 / 1378 with the
+    // window kept in 16 bits and column-and-row rounding words)
     void set_default_fuse() {
         const int64_t tiles = (int64_t)((cfg.nx + kPairW3 - 1) / kPairW3) * ((cfg.ny + kPairYO - 1) / kPairYO) *
                               ((cfg.nz + shape.zchunk - 1) / shape.zchunk);
-        fuse = (cfg.storage == LBM_F32 && tiles >= kPairMinTiles) ? 2 : 1;
+        fuse = tiles >= kPairMinTiles ? 2 : 1;
     }
     double tau = 0, beta = 1, s = 1, cv = 1;
     Coeffs co{};
@@ -463,9 +464,11 @@ int lbm3d_autotune(lbm3d_handle h, int32_t steps, char* report, size_t report_le
     if (!h->base) return h->fail(LBM_ESTATE, "no device memory bound");
     if (h->inited) return h->fail(LBM_ESTATE, "lbm3d_autotune must run before lbm3d_init");
     if (steps <= 0) steps = 20;
-    // scratch contents: zeros, so no timing depends on garbage bit patterns
-    HIPCALL3(h, hipMemsetAsync(h->buf(0), 0, h->L.buf_bytes, h->stream));
-    HIPCALL3(h, hipMemsetAsync(h->buf(1), 0, h->L.buf_bytes, h->stream));
+    // scratch contents: a fixed pattern of moderate finite values with
+    // changing bits (zero-filled buffers run the single-step kernel about 8%
+    // faster than real contents: FP16-SR 512^3 1343 against 1464 us per step)
+    HIPCALL3(h, launch_fill(h->buf(0), h->L.buf_bytes & ~(size_t)3, 1u, h->stream));
+    HIPCALL3(h, launch_fill(h->buf(1), h->L.buf_bytes & ~(size_t)3, 2u, h->stream));
     hipEvent_t e0, e1;
     HIPCALL3(h, hipEventCreate(&e0));
     hipError_t e = hipEventCreate(&e1);

@@ -226,6 +226,10 @@ hipError_t launch_finalize(const InstDesc* d_desc, const int32_t* group_inst, in
                            RefState* d_ref_prev, int ninst, const DD* partials, DD* gpart,
                            double* results, int fused, hipStream_t st);
 
+// Fill `bytes` (a multiple of 4) with the timing scratch pattern of the
+// device file (moderate finite values in every storage type, changing bits).
+hipError_t launch_fill(void* buf, size_t bytes, uint32_t seed, hipStream_t st);
+
 // One-thread kernel writing *dst = v on the stream (stream-ordered updates of
 // descriptor fields between steps).
 hipError_t launch_set_float(float* dst, float v, hipStream_t st);

@@ -1516,9 +1516,11 @@ int lbm_autotune(lbm_handle h, int32_t steps, char* report, size_t report_len) {
         if (!rc) h->fuse = std::min(std::max(cached_fuse, 1), fuse_max(h->storage));
         return rc;
     }
-    // scratch contents: zeros, so no timing depends on garbage bit patterns
-    HIPCALL(h, hipMemsetAsync(h->buf(0), 0, h->L.buf_bytes, h->stream));
-    HIPCALL(h, hipMemsetAsync(h->buf(1), 0, h->L.buf_bytes, h->stream));
+    // scratch contents: a fixed pattern of moderate finite values with
+    // changing bits (zero-filled buffers run faster than real contents, which
+    // biases the choice between single and fused launches)
+    HIPCALL(h, launch_fill(h->buf(0), h->L.buf_bytes & ~(size_t)3, 1u, h->stream));
+    HIPCALL(h, launch_fill(h->buf(1), h->L.buf_bytes & ~(size_t)3, 2u, h->stream));
     hipEvent_t e0, e1;
     HIPCALL(h, hipEventCreate(&e0));
     HIPCALL(h, hipEventCreate(&e1));
