@@ -150,11 +150,13 @@ int lbm3d_get_launch_shape(lbm3d_handle h, lbm3d_launch_shape* shape);
 
 /* Time every single-step tile shape (rows_per_tile x tile_waves) with and
  * without the XCD remap, then streaming stores on the fastest, then two steps
- * per launch over z ranges of 16, 32 and 64 planes, for `steps` steps each (0
- * selects 20) on zeroed buffers; keep the fastest shape, z range and steps per
- * launch.  Must run before lbm3d_init (it overwrites the buffers).  report, if
- * not NULL, receives a JSON summary ({"timings_us": [[rows, xcd, nt,
- * tile_waves, us], ...], "best": [...], "pair_us_per_step": [[zchunk, us],
+ * per launch over z ranges of 16, 32 and 64 planes, each with and without
+ * streaming stores, for `steps` steps each (0 selects 20) on buffers filled
+ * with a fixed pattern of moderate finite values; keep the fastest shape, z
+ * range, store kind and steps per launch.  Must run before lbm3d_init (it
+ * overwrites the buffers).  report, if not NULL, receives a JSON summary
+ * ({"timings_us": [[rows, xcd, nt, tile_waves, us], ...], "best": [rows, xcd,
+ * nt, tile_waves, single-step us], "pair_us_per_step": [[zchunk, nt, us],
  * ...], "zchunk": z, "steps_per_launch": 1 or 2}) truncated to report_len.
  * Errors: ESTATE (memory not bound, or already initialised), EHIP. */
 int lbm3d_autotune(lbm3d_handle h, int32_t steps, char* report, size_t report_len);

@@ -49,8 +49,6 @@ using plbm::bits16;
 using plbm::Cvt;
 using plbm::mix32;
 using plbm::sr_add_f32;
-using plbm::sr_bf16;
-using plbm::sr_f16;
 
 // ------------------------------------------------------------------ lattice
 
@@ -157,13 +155,6 @@ __device__ __forceinline__ void moments(const float v[kQ], float& E, float& jx, 
     }
 }
 
-template <class S, int SR>
-__device__ __forceinline__ S rounded(float v, uint32_t r16) {
-    if constexpr (SR && __is_same(S, _Float16)) return sr_f16(v, r16);
-    else if constexpr (SR && __is_same(S, bf16_bits)) return sr_bf16(v, r16);
-    else return Cvt<S>::st(v);
-}
-
 template <class S>
 __device__ __forceinline__ void put(S* p, S v, int nontemporal) {
     if constexpr (sizeof(S) == 4) {
@@ -179,33 +170,30 @@ __device__ __forceinline__ void put(S* p, S v, int nontemporal) {
     }
 }
 
-// The stored value of direction I after one relaxation.
-template <class S, int SR, int I>
-__device__ __forceinline__ S relax_round_one(const Coeffs& c, const float v[kQ], float wE_axis, float wE_corner,
-                                             float jx, float jy, float jz, const uint32_t r[7]) {
+// The change of direction I in one relaxation.
+template <int I>
+__device__ __forceinline__ float relax_delta_one(const Coeffs& c, const float v[kQ], float wE_axis, float wE_corner,
+                                                 float jx, float jy, float jz) {
     const float wE = I < 6 ? wE_axis : wE_corner;
     const float k = I < 6 ? c.k_axis : c.k_corner;
-    const float delta = fmaf(c.inv_tau, wE - v[I], k * c_dot<I>(jx, jy, jz));
-    if constexpr (SR && __is_same(S, float)) return sr_add_f32(v[I], delta, bits16(r, I));
-    else return rounded<S, SR>(v[I] + delta, SR ? bits16(r, I) : 0u);
-}
-
-// One relaxation of direction I and its store at the node's own position.
-template <class S, int SR, int L, int I>
-__device__ __forceinline__ void relax_store_one(const Geometry& g, const Coeffs& c, const float v[kQ], float wE_axis,
-                                                float wE_corner, float jx, float jy, float jz, const uint32_t r[7],
-                                                S* dst, int64_t row, int x, int nontemporal) {
-    put<S>(dst + elem<L>(g, I, row, x), relax_round_one<S, SR, I>(c, v, wE_axis, wE_corner, jx, jy, jz, r),
-           nontemporal);
+    return fmaf(c.inv_tau, wE - v[I], k * c_dot<I>(jx, jy, jz));
 }
 
 // One relaxation of all 14 directions, each rounded to S (the values a stored
-// step holds).
+// step holds), directions 2k and 2k + 1 rounded together (stochastic rounding
+// by the conversion instructions).
 template <class S, int SR, int... Is>
 __device__ __forceinline__ void relax_round_all(const Coeffs& c, const float v[kQ], float wE_axis, float wE_corner,
                                                 float jx, float jy, float jz, const uint32_t r[7], S out[kQ],
                                                 std::integer_sequence<int, Is...>) {
-    ((out[Is] = relax_round_one<S, SR, Is>(c, v, wE_axis, wE_corner, jx, jy, jz, r)), ...);
+    if constexpr (SR && __is_same(S, float)) {
+        ((out[Is] = sr_add_f32(v[Is], relax_delta_one<Is>(c, v, wE_axis, wE_corner, jx, jy, jz), bits16(r, Is))),
+         ...);
+    } else {
+        float u[kQ];
+        ((u[Is] = v[Is] + relax_delta_one<Is>(c, v, wE_axis, wE_corner, jx, jy, jz)), ...);
+        plbm::round_pairs<S, SR, kQ, true>(u, r, out);
+    }
 }
 
 // Stochastic-rounding words (16 bits for each of directions 2k and 2k + 1 in
@@ -233,12 +221,15 @@ __device__ __forceinline__ void sr_words3(uint32_t r[7], const uint32_t colw[7],
     for (int k = 0; k < 7; ++k) r[k] = colw[k] ^ (roww * m[k]);
 }
 
+// One relaxation of all 14 directions and their stores at the node's own position.
 template <class S, int SR, int L, int... Is>
 __device__ __forceinline__ void relax_store_all(const Geometry& g, const Coeffs& c, const float v[kQ], float wE_axis,
                                                 float wE_corner, float jx, float jy, float jz, const uint32_t r[7],
                                                 S* dst, int64_t row, int x, int nontemporal,
-                                                std::integer_sequence<int, Is...>) {
-    (relax_store_one<S, SR, L, Is>(g, c, v, wE_axis, wE_corner, jx, jy, jz, r, dst, row, x, nontemporal), ...);
+                                                std::integer_sequence<int, Is...> seq) {
+    S o[kQ];
+    relax_round_all<S, SR>(c, v, wE_axis, wE_corner, jx, jy, jz, r, o, seq);
+    (put<S>(dst + elem<L>(g, Is, row, x), o[Is], nontemporal), ...);
 }
 
 // ------------------------------------------------------------------ step

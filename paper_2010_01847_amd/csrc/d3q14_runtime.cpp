@@ -515,38 +515,46 @@ int lbm3d_autotune(lbm3d_handle h, int32_t steps, char* report, size_t report_le
         sh.nontemporal = 1;
         try_shape(sh);
     }
-    // two steps per launch over z ranges of 16, 32 and 64 planes (per-step time
-    // over the same number of steps, rounded up to pairs)
+    // two steps per launch over z ranges of 16, 32 and 64 planes, with and
+    // without streaming stores (per-step time over the same number of steps,
+    // rounded up to pairs); the two-step kernel's tile is fixed, so the
+    // single-step kernel's best store kind need not be its best
     const float single_us = best_us;
     float pair_us = 1e30f;
-    int best_z = best.zchunk;
+    int best_z = best.zchunk, best_nt = best.nontemporal;
     std::string prep;
     steps += steps & 1;
     for (int zc : {16, 32, 64}) {
-        if (rc) break;
-        lbm3d_launch_shape sh = best;
-        sh.zchunk = zc;
-        rc = lbm3d_set_launch_shape(h, &sh);
-        h->fuse = 2;
-        if (!rc) rc = lbm3d_step(h, 2);
-        if (!rc && (e = hipEventRecord(e0, h->stream)) != hipSuccess) rc = h->hip_fail(e, "hipEventRecord");
-        if (!rc) rc = lbm3d_step(h, steps);
-        if (!rc && (e = hipEventRecord(e1, h->stream)) != hipSuccess) rc = h->hip_fail(e, "hipEventRecord");
-        if (!rc && (e = hipEventSynchronize(e1)) != hipSuccess) rc = h->hip_fail(e, "hipEventSynchronize");
-        float ms = 0.0f;
-        if (!rc && (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) rc = h->hip_fail(e, "hipEventElapsedTime");
-        if (rc) break;
-        const float us = 1e3f * ms / (float)steps;
-        char b[64];
-        snprintf(b, sizeof b, "%s[%d, %.2f]", prep.empty() ? "" : ", ", zc, us);
-        prep += b;
-        if (us < pair_us) {
-            pair_us = us;
-            best_z = zc;
+        for (int nt = 0; nt < 2; ++nt) {
+            if (rc) break;
+            lbm3d_launch_shape sh = best;
+            sh.zchunk = zc;
+            sh.nontemporal = nt;
+            rc = lbm3d_set_launch_shape(h, &sh);
+            h->fuse = 2;
+            if (!rc) rc = lbm3d_step(h, 2);
+            if (!rc && (e = hipEventRecord(e0, h->stream)) != hipSuccess) rc = h->hip_fail(e, "hipEventRecord");
+            if (!rc) rc = lbm3d_step(h, steps);
+            if (!rc && (e = hipEventRecord(e1, h->stream)) != hipSuccess) rc = h->hip_fail(e, "hipEventRecord");
+            if (!rc && (e = hipEventSynchronize(e1)) != hipSuccess) rc = h->hip_fail(e, "hipEventSynchronize");
+            float ms = 0.0f;
+            if (!rc && (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess)
+                rc = h->hip_fail(e, "hipEventElapsedTime");
+            if (rc) break;
+            const float us = 1e3f * ms / (float)steps;
+            char b[64];
+            snprintf(b, sizeof b, "%s[%d, %d, %.2f]", prep.empty() ? "" : ", ", zc, nt, us);
+            prep += b;
+            if (us < pair_us) {
+                pair_us = us;
+                best_z = zc;
+                best_nt = nt;
+            }
         }
     }
     best.zchunk = best_z;
     h->fuse = pair_us < single_us ? 2 : 1;
+    if (h->fuse == 2) best.nontemporal = best_nt;
     h->inited = false;
     h->steps = 0;
     h->cur = 0;

@@ -666,16 +666,18 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
             // residual of the eight h is added to the stored E, so the node's
             // stored populations still sum to E: 16-bit rounding moves energy
             // between directions but creates or destroys none.
-            float delta[8];
+            float delta[8], hv[8];
+            S o[8];
             relax_delta(g, d, rv, delta);
             const float E = ((g[0] + g[2]) + (g[1] + g[3])) + ((g[4] + g[6]) + (g[5] + g[7]));
+#pragma unroll
+            for (int i = 0; i < 8; ++i) hv[i] = (g[i] - omega_e(i, E)) + delta[i];
+            round_pairs<S, SR, 8>(hv, r, o);
             float res = 0.0f;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                const float hv = (g[i] - omega_e(i, E)) + delta[i];
-                const S o = round_to<S, SR>(hv, bits16(r, i));
-                res = res + (hv - Cvt<S>::ld(o));
-                store_raw<S>(out + i * pb + c0, o, nontemporal);
+                res = res + (hv[i] - Cvt<S>::ld(o[i]));
+                store_raw<S>(out + i * pb + c0, o[i], nontemporal);
             }
             store_one<float, 0>(out + e0, E + res, 0u, nontemporal);
         } else if (SR && sizeof(S) == 4) {
@@ -686,8 +688,10 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
         } else {
             // 16-bit SR narrows the round-to-nearest FP32 result stochastically
             relax(g, d, rv);
+            S o[8];
+            round_pairs<S, SR, 8>(g, r, o);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) store_one<S, SR>(out + i * pb + c0, g[i], bits16(r, i), nontemporal);
+            for (int i = 0; i < 8; ++i) store_raw<S>(out + i * pb + c0, o[i], nontemporal);
         }
     }
     if (t == 0 && threadIdx.x == 0 && threadIdx.y == 0) a.ctr_out[0] = step + 1u;
@@ -890,46 +894,18 @@ __device__ __forceinline__ int wrapm(int v, int n, int span) {
 template <class S, int SR, int SPLIT>
 __device__ __forceinline__ void relax_round(float g[8], const InstDesc& d, const RefView& rv, const uint32_t r[4],
                                             S o[8], float& E_out) {
-    if constexpr (SPLIT && !SR && __is_same(S, bf16_bits)) {
-        // BF16 to nearest with one NaN test per node instead of a branch per
-        // value: round the eight shares as finite values, and redo them with
-        // the full conversion when the residual is not finite (a NaN or an
-        // infinity among them; the two differ only on a NaN).  Same bits.
+    if constexpr (SPLIT) {
         float delta[8], hv[8];
         relax_delta(g, d, rv, delta);
         const float E = ((g[0] + g[2]) + (g[1] + g[3])) + ((g[4] + g[6]) + (g[5] + g[7]));
+#pragma unroll
+        for (int i = 0; i < 8; ++i) hv[i] = (g[i] - omega_e(i, E)) + delta[i];
+        round_pairs<S, SR, 8>(hv, r, o);
         float res = 0.0f;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            hv[i] = (g[i] - omega_e(i, E)) + delta[i];
-            const uint32_t u = __float_as_uint(hv[i]);
-            bf16_bits b;
-            b.b = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-            o[i] = b;
-            res = res + (hv[i] - Cvt<S>::ld(o[i]));
-        }
-        if (!(fabsf(res) <= 3.402823466e38f)) {
-            res = 0.0f;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                o[i] = Cvt<S>::st(hv[i]);
-                res = res + (hv[i] - Cvt<S>::ld(o[i]));
-            }
-        }
+        for (int i = 0; i < 8; ++i) res = res + (hv[i] - Cvt<S>::ld(o[i]));
         E_out = E + res;
-    } else if (SPLIT) {
-        float delta[8];
-        relax_delta(g, d, rv, delta);
-        const float E = ((g[0] + g[2]) + (g[1] + g[3])) + ((g[4] + g[6]) + (g[5] + g[7]));
-        float res = 0.0f;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const float hv = (g[i] - omega_e(i, E)) + delta[i];
-            o[i] = round_to<S, SR>(hv, bits16(r, i));
-            res = res + (hv - Cvt<S>::ld(o[i]));
-        }
-        E_out = E + res;
-    } else if (SR && sizeof(S) == 4) {
+    } else if constexpr (SR && sizeof(S) == 4) {
         float f[8];
         relax_sr_f32(g, d, rv, r, f);
 #pragma unroll
@@ -943,18 +919,12 @@ __device__ __forceinline__ void relax_round(float g[8], const InstDesc& d, const
             const float t = ((g[0] + g[1]) + (g[2] + g[3])) + ((g[4] + g[5]) + (g[6] + g[7]));
             if (fabsf(t) <= 3.402823466e38f) {
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    bf16_bits b;
-                    b.b = (uint16_t)((__float_as_uint(g[i]) + bits16(r, i)) >> 16);
-                    o[i] = b;
-                }
+                for (int i = 0; i < 8; ++i) o[i].b = (uint16_t)((__float_as_uint(g[i]) + bits16(r, i)) >> 16);
             } else {
-#pragma unroll
-                for (int i = 0; i < 8; ++i) o[i] = round_to<S, SR>(g[i], bits16(r, i));
+                round_pairs<S, SR, 8>(g, r, o);
             }
         } else {
-#pragma unroll
-            for (int i = 0; i < 8; ++i) o[i] = round_to<S, SR>(g[i], bits16(r, i));
+            round_pairs<S, SR, 8>(g, r, o);
         }
         E_out = 0.0f;
     }

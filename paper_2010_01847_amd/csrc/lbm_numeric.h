@@ -37,20 +37,14 @@ template <> struct Cvt<bf16_bits> {
     static __device__ __forceinline__ float ld(bf16_bits v) {
         return __uint_as_float((uint32_t)v.b << 16);
     }
-    // round to nearest, ties to even; NaN stays a quiet NaN, overflow -> Inf.
-    // The NaN case compiles to a vector test and a branch that a wavefront
-    // skips when none of its values is a NaN; a branch-free select costs more
-    // vector instructions per stored value and measured slower in the
-    // VALU-bound fused kernel.
+    // round to nearest, ties to even; a NaN becomes a quiet NaN that keeps its
+    // sign and top payload bits, overflow -> Inf (gfx950's v_cvt_pk_bf16_f32;
+    // the empty asm keeps f an FP32 register value, as for FP16)
     static __device__ __forceinline__ bf16_bits st(float f) {
-        uint32_t u = __float_as_uint(f);
+        asm volatile("" : "+v"(f));
+        const __bf16 h = (__bf16)f;
         bf16_bits r;
-        if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) {
-            r.b = (uint16_t)((u >> 16) | 0x0040u);
-        } else {
-            u += 0x7fffu + ((u >> 16) & 1u);
-            r.b = (uint16_t)(u >> 16);
-        }
+        r.b = __builtin_bit_cast(uint16_t, h);
         return r;
     }
 };
@@ -116,6 +110,76 @@ __device__ __forceinline__ bf16_bits sr_bf16(float v, uint32_t r16) {
     bf16_bits o;
     o.b = (uint16_t)(v != v ? (u >> 16) | 0x0040u : (u + r16) >> 16);
     return o;
+}
+
+typedef __fp16 plbm_h2 __attribute__((vector_size(2 * sizeof(__fp16))));   // the SR builtins' pairs
+typedef __bf16 plbm_b2 __attribute__((vector_size(2 * sizeof(__bf16))));
+typedef __bf16 plbm_bf16x2 __attribute__((ext_vector_type(2)));
+typedef float plbm_f32x2 __attribute__((ext_vector_type(2)));
+
+// Stochastic rounding by gfx950's conversion instructions, which add the top
+// bits of their 32-bit random operand below the kept bits (measured faster
+// than the software forms in the D3Q14 kernels, slower in the D2Q8 fused
+// kernel).  BF16: the same bits as sr_bf16, NaNs included.  FP16: the same
+// bits as sr_f16 for results in FP16's normal range; below it the instruction
+// rounds at the subnormal's own spacing (sr_f16 rounds those twice: to 10
+// mantissa bits stochastically, then to the subnormal to nearest).  Each
+// instruction writes the low half of its destination and keeps the high half
+// of its first operand: v's own bits, never read.  (The form that writes the
+// high half is not used: hipcc of ROCm 7.2 then stores the low half for both
+// values of a pair.)
+__device__ __forceinline__ bf16_bits sr_bf16_hw(float v, uint32_t r16) {
+    asm volatile("" : "+v"(v));
+    const plbm_b2 t = __builtin_amdgcn_cvt_sr_bf16_f32(__builtin_bit_cast(plbm_b2, v), v, r16 << 16, false);
+    bf16_bits o;
+    o.b = __builtin_bit_cast(uint16_t, t[0]);
+    return o;
+}
+__device__ __forceinline__ _Float16 sr_f16_hw(float v, uint32_t r16) {
+    asm volatile("" : "+v"(v));
+    const plbm_h2 t = __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(plbm_h2, v), v, r16 << 16, false);
+    return __builtin_bit_cast(_Float16, t[0]);
+}
+
+// Directions 2k and 2k + 1 rounded to S, w the node's random word k (16 bits
+// for direction 2k in its low half, for 2k + 1 in its high half; unused
+// without SR).  BF16 to nearest takes one packed conversion for the pair
+// (gfx950's v_cvt_pk_bf16_f32, the same bits as Cvt<bf16_bits>::st of each
+// value); HW selects the instruction forms of stochastic rounding.  FP16 to
+// nearest rounds each value on its own (packing the pair measured slower: the
+// halves cost register moves).
+template <class S, int SR, bool HW = false>
+__device__ __forceinline__ void round_pair(float a, float b, uint32_t w, S& oa, S& ob) {
+    if constexpr (__is_same(S, float)) {
+        oa = a;
+        ob = b;
+    } else if constexpr (__is_same(S, _Float16)) {
+        if constexpr (SR) {
+            oa = HW ? sr_f16_hw(a, w & 0xffffu) : sr_f16(a, w & 0xffffu);
+            ob = HW ? sr_f16_hw(b, w >> 16) : sr_f16(b, w >> 16);
+        } else {
+            oa = Cvt<_Float16>::st(a);
+            ob = Cvt<_Float16>::st(b);
+        }
+    } else if constexpr (SR) {
+        oa = HW ? sr_bf16_hw(a, w & 0xffffu) : sr_bf16(a, w & 0xffffu);
+        ob = HW ? sr_bf16_hw(b, w >> 16) : sr_bf16(b, w >> 16);
+    } else {
+        asm volatile("" : "+v"(a), "+v"(b));
+        const plbm_f32x2 v = {a, b};
+        const uint32_t u = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, plbm_bf16x2));
+        oa.b = (uint16_t)u;
+        ob.b = (uint16_t)(u >> 16);
+    }
+}
+
+// N values (N even) rounded pairwise as above, word k for values 2k, 2k + 1.
+template <class S, int SR, int N, bool HW = false>
+__device__ __forceinline__ void round_pairs(const float* v, const uint32_t* r, S* o) {
+    static_assert(N % 2 == 0, "pairs");
+#pragma unroll
+    for (int k = 0; k < N / 2; ++k)
+        round_pair<S, SR, HW>(v[2 * k], v[2 * k + 1], SR ? r[k] : 0u, o[2 * k], o[2 * k + 1]);
 }
 
 }  // namespace plbm

@@ -213,10 +213,11 @@ def test_d3q14_config_validation(kw):
 
 
 @pytest.mark.parametrize("n,storage,fuse", [(128, P.LBM_F32, 1), (192, P.LBM_F32, 2), (512, P.LBM_F32, 2),
-                                             (512, P.LBM_F16, 1)])
+                                             (128, P.LBM_F16, 1), (512, P.LBM_F16, 2), (512, P.LBM_BF16, 2)])
 def test_d3q14_default_step_fusion(n, storage, fuse):
-    """Two steps per launch by default for FP32 boxes holding at least 256
-    two-step blocks (60 x 12 x 32 nodes): 128^3 holds 132, 192^3 384."""
+    """Two steps per launch by default, for every storage kind, for boxes
+    holding at least 256 two-step blocks (60 x 12 x 32 nodes): 128^3 holds
+    132, 192^3 384."""
     D = P.d3q14
     h = D.lbm3d_create(_cfg3(nx=n, ny=n, nz=n, storage=storage))
     try:
