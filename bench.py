@@ -314,15 +314,18 @@ def _run_sweep(args, torch, P, W, picks=(0, 1, 2, 3)):
     """Knudsen sweep: 256 channel instances (sides uniform in [64, 512],
     tau_N uniform in [0.51, 1], tau_R log-uniform in [0.6, 1000], gradient
     seam and diffuse walls), FP32, check steps every 100.  MLUPS of each
-    schedule over the same timed steps from the same initial state; the
-    batched run's fields of a few instances for the error."""
+    schedule over the same timed steps from the same initial state (batched:
+    the default two streams, and one); the batched run's fields of a few
+    instances for the error."""
     cases = W.knudsen_sweep()
     insts = [P.instance_from_case(c) for c in cases]
     nodes = sum(c.nx * c.ny for c in cases)
     out = {"instances": len(cases), "nodes": nodes, "steps": args.sweep_steps, "storage": "f32"}
-    for sched in ("graph", "batched", "per_instance"):
+    for sched in ("graph", "batched", "batched_one_stream", "per_instance"):
         lat = P.Lattice(insts, check_interval=100)
-        lat.set_schedule(sched)
+        lat.set_schedule("batched" if sched == "batched_one_stream" else sched)
+        if sched == "batched_one_stream":
+            lat.set_streams(1)
         for k in range(len(cases)):
             lat.init(k)
         lat.step(100)                      # warm-up; captures the graphs
@@ -331,6 +334,7 @@ def _run_sweep(args, torch, P, W, picks=(0, 1, 2, 3)):
             out["_fields"] = {k: lat.moments(k) for k in picks}
             out["fields_at_step"] = lat.steps
             out["steps_per_launch"] = lat.step_fusion()
+            out["batched_streams"] = lat.streams()
         lat.close()
         step_s = ms / 1e3 / args.sweep_steps
         out[sched] = {"mlups": round(nodes / step_s / 1e6, 1), "ms_per_step": round(ms / args.sweep_steps, 4),

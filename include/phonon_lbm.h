@@ -319,6 +319,25 @@ int32_t lbm_max_step_fusion(int32_t storage);
  * buffer parity and replays them; steps not filling a chunk run eagerly. */
 int lbm_set_schedule(lbm_handle h, int32_t schedule);
 
+/* Streams over which the BATCHED schedule spreads a handle's instances
+ * (the batched launches of Sec. 3.2's parameter sweep): 1, or 2, which splits
+ * the instances into two runs of consecutive instances holding about equal
+ * numbers of fused-kernel strips and issues the second run's launches on a
+ * stream the handle creates (default priority) at its first use; each
+ * lbm_step call makes that stream wait for the work issued on the handle's
+ * stream so far and makes the handle's stream wait for it before returning,
+ * so later calls on the handle's stream see every step.  While one run's
+ * launch drains its last wavefronts, the other run's launch fills the chip.
+ * 0 restores the default: 2 for handles of two or more instances, else 1.
+ * The GRAPH schedule captures the two parts as two branches of its graphs
+ * (setting the streams drops captured graphs); PER_INSTANCE uses one stream.
+ * Results are the same bits for every setting.  Errors: EINVAL (n outside
+ * 0 .. 2). */
+int lbm_set_streams(lbm_handle h, int32_t n);
+
+/* Streams the batched schedule uses now (1 or 2); -1 for an invalid handle. */
+int32_t lbm_get_streams(lbm_handle h);
+
 /* Kernel launch shape: nodes per thread along x (1, 2 or 4), threads per
  * block along x (a multiple of 64, <= 512) and rows per block, with
  * block_x * block_y <= 512; xcd_remap != 0 maps consecutive tiles to the same

@@ -364,8 +364,9 @@ __global__ __launch_bounds__(kMaxBlock) void step_kernel(StepArgs a, int64_t sna
         const int nb = a.ntiles, q = nb >> 3, r = nb & 7, k = b & 7, j = b >> 3;
         t = k * q + (k < r ? k : r) + j;
     }
-    t += a.tile_base;
+    // the first tile of the launch advances the step counter
     if (t == 0 && threadIdx.x == 0 && threadIdx.y == 0) a.ctr_out[0] = a.ctr_in[0] + 1u;
+    t += a.tile_base;
     const int inst = a.tile_inst[t];
     const InstDesc& d = a.desc[inst];
     const RefState& ref = a.ref[inst];
@@ -694,7 +695,7 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
             for (int i = 0; i < 8; ++i) store_raw<S>(out + i * pb + c0, o[i], nontemporal);
         }
     }
-    if (t == 0 && threadIdx.x == 0 && threadIdx.y == 0) a.ctr_out[0] = step + 1u;
+    if (t == a.tile_base && threadIdx.x == 0 && threadIdx.y == 0) a.ctr_out[0] = step + 1u;
     if (MODE == kCheck) block_partials(acc, a.partials + (int64_t)t * kPartials);
 }
 
@@ -1179,7 +1180,7 @@ __global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int non
     int it = 0;
     for (; it < 2 * K; ++it) iteration(it, std::true_type{});
     for (; it < iters; ++it) iteration(it, std::false_type{});
-    if (tg == 0 && lane == 0) a.ctr_out[0] = step + (uint32_t)K;
+    if (t == 0 && lane == 0) a.ctr_out[0] = step + (uint32_t)K;
     if constexpr (END == kEndCheck) {
         // fixed-order wavefront sums; one record per tile (all 64 lanes are
         // active here: a wavefront leaves early only as a whole)
@@ -1388,13 +1389,14 @@ __device__ void reduce_records(const DD* __restrict__ partials, int64_t first, i
         for (int c = 0; c < kPartials; ++c) out[c] = red[0][c];
 }
 
-// First stage: group b of the tile records of its instance.  fused != 0:
-// records of the fused kernel's tiles (strips), else of the single-step tiles.
+// First stage: group b = g0 + blockIdx.x of the tile records of its
+// instance.  fused != 0: records of the fused kernel's tiles (strips), else of
+// the single-step tiles.
 __global__ __launch_bounds__(256) void group_reduce_kernel(const InstDesc* __restrict__ descs,
                                                            const int32_t* __restrict__ group_inst,
                                                            const DD* __restrict__ partials,
-                                                           DD* __restrict__ gpart, int fused) {
-    const int b = blockIdx.x;
+                                                           DD* __restrict__ gpart, int fused, int g0) {
+    const int b = g0 + (int)blockIdx.x;
     const InstDesc& d = descs[group_inst[b]];
     const int gb = fused ? d.p_group_begin : d.group_begin;
     const int tb = fused ? d.p_tile_begin : d.tile_begin;
@@ -1405,7 +1407,7 @@ __global__ __launch_bounds__(256) void group_reduce_kernel(const InstDesc* __res
                    gpart + (int64_t)b * kPartials);
 }
 
-// Second stage, per instance: the check-step totals, then (adaptive
+// Second stage, per instance (i0 + blockIdx.x): the check-step totals, then (adaptive
 // instances) the move of the reference flux to the mean flux of the state just
 // checked.  The shift is rounded to FP32 first and J is moved by the rounded
 // amount (in FP64), so J and the stored populations stay consistent;
@@ -1415,16 +1417,17 @@ __global__ __launch_bounds__(256) void finalize_kernel(const InstDesc* __restric
                                                        RefState* __restrict__ refs,
                                                        RefState* __restrict__ refs_prev,
                                                        const DD* __restrict__ gpart,
-                                                       double* __restrict__ results, int fused) {
-    const InstDesc& d = descs[blockIdx.x];
+                                                       double* __restrict__ results, int fused, int i0) {
+    const int inst = i0 + (int)blockIdx.x;
+    const InstDesc& d = descs[inst];
     __shared__ DD sum[kPartials];
     reduce_records(gpart, fused ? d.p_group_begin : d.group_begin, fused ? d.p_ngroups : d.ngroups, sum);
     if (threadIdx.x != 0) return;
-    double* out = results + (int64_t)blockIdx.x * kPartials;
+    double* out = results + (int64_t)inst * kPartials;
 #pragma unroll
     for (int c = 0; c < kPartials; ++c) out[c] = sum[c].hi;
-    RefState& r = refs[blockIdx.x];
-    refs_prev[blockIdx.x] = r;
+    RefState& r = refs[inst];
+    refs_prev[inst] = r;
     if (!r.adapt) return;
     // mean heat flux = beta (mean first moment); reference's first moment J + j_b
     const double target = out[1] * r.inv_nodes / r.beta - r.jb;
@@ -1447,17 +1450,28 @@ __global__ __launch_bounds__(256) void range_reduce_kernel(const DD* __restrict_
     reduce_records(partials, first, (int)(rest < span ? rest : span), out + (int64_t)blockIdx.x * kPartials);
 }
 
-hipError_t launch_finalize(const InstDesc* d_desc, const int32_t* group_inst, int ngroups, RefState* d_ref,
-                           RefState* d_ref_prev, int ninst, const DD* partials, DD* gpart,
+hipError_t launch_finalize(const InstDesc* d_desc, const int32_t* group_inst, int g0, int ngroups, RefState* d_ref,
+                           RefState* d_ref_prev, int i0, int ninst, const DD* partials, DD* gpart,
                            double* results, int fused, hipStream_t st) {
+    if (ngroups <= 0 || ninst <= 0) return hipSuccess;
     hipLaunchKernelGGL(group_reduce_kernel, dim3(ngroups), dim3(256), 0, st, d_desc, group_inst, partials, gpart,
-                       fused);
+                       fused, g0);
     hipLaunchKernelGGL(finalize_kernel, dim3(ninst), dim3(256), 0, st, d_desc, d_ref, d_ref_prev, gpart, results,
-                       fused);
+                       fused, i0);
     return hipGetLastError();
 }
 
 __global__ void set_float_kernel(float* dst, float v) { *dst = v; }
+
+__global__ void copy_u32_kernel(uint32_t* dst, const uint32_t* src, int n) {
+    if ((int)threadIdx.x < n) dst[threadIdx.x] = src[threadIdx.x];
+}
+
+hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, int n, hipStream_t st) {
+    if (n <= 0 || n > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(copy_u32_kernel, dim3(1), dim3(64), 0, st, dst, src, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_set_float(float* dst, float v, hipStream_t st) {
     hipLaunchKernelGGL(set_float_kernel, dim3(1), dim3(1), 0, st, dst, v);

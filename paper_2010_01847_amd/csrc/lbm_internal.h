@@ -175,7 +175,7 @@ struct StepArgs {
     const RefState* ref;        // per-instance reference states
     int32_t apply_shift;        // 1: add the pending reference shift to the pulled values
     const uint32_t* ctr_in;     // steps completed before this step (device counter)
-    uint32_t* ctr_out;          // written with ctr_in + 1 by the block of global tile 0
+    uint32_t* ctr_out;          // written with ctr_in + steps by the launch's first tile
     uint32_t seed;              // stream of the stochastic-rounding bits
     int32_t sr;                 // 1: round stores stochastically (nodes per lane must be 1)
 };
@@ -216,14 +216,15 @@ hipError_t launch_init(int storage, const InstDesc* d_desc, const RefState* d_re
 
 // Deterministic per-instance reduction of tile partials into results
 // (kPartials doubles per instance), in two fixed-order stages: groups of
-// kGroup tile records (group_inst: group -> instance, ngroups in total) into
-// gpart, then one block per instance over its groups.  fused != 0: the
+// kGroup tile records (group_inst: group -> instance; groups g0 .. g0 +
+// ngroups - 1) into gpart, then one block per instance (i0 .. i0 + ninst - 1)
+// over its groups.  fused != 0: the
 // records are per fused-kernel tile (InstDesc p_* fields), else per
 // single-step tile.  The second stage copies each instance's reference state
 // to d_ref_prev and then moves an adaptive instance's reference flux to its
 // mean heat flux.
-hipError_t launch_finalize(const InstDesc* d_desc, const int32_t* group_inst, int ngroups, RefState* d_ref,
-                           RefState* d_ref_prev, int ninst, const DD* partials, DD* gpart,
+hipError_t launch_finalize(const InstDesc* d_desc, const int32_t* group_inst, int g0, int ngroups, RefState* d_ref,
+                           RefState* d_ref_prev, int i0, int ninst, const DD* partials, DD* gpart,
                            double* results, int fused, hipStream_t st);
 
 // Fill `bytes` (a multiple of 4) with the timing scratch pattern of the
@@ -233,6 +234,10 @@ hipError_t launch_fill(void* buf, size_t bytes, uint32_t seed, hipStream_t st);
 // One-thread kernel writing *dst = v on the stream (stream-ordered updates of
 // descriptor fields between steps).
 hipError_t launch_set_float(float* dst, float v, hipStream_t st);
+
+// Copy n <= 64 32-bit words on the device (a kernel, so that it can sit in a
+// captured graph).
+hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, int n, hipStream_t st);
 
 // Reduction of nparts moments-kernel partials (tiles of 256 nodes) of one
 // instance, through gpart (ceil(nparts / kGroup) records), into one record.

@@ -313,6 +313,23 @@ struct lbm_ctx {
     std::vector<int32_t> ptile_inst;   // fused kernel: tile -> instance
     std::vector<int32_t> pgroup_inst;  // fused kernel: reduction group -> instance
     int64_t npgroups = 0;
+    // The instances one launch covers: all of them, or one of the parts that
+    // the batched schedule issues on streams of their own (lbm_set_streams).
+    struct Span {
+        int i0 = 0, ni = 0;                            // instances
+        int32_t t0 = 0, nt = 0, g0 = 0, ng = 0;        // single-step tiles and reduction groups
+        int32_t pt0 = 0, pnt = 0, pg0 = 0, png = 0;    // fused-kernel tiles and reduction groups
+        int ctr = 0;                                   // its step-counter pair: d_ctr()[ctr], [ctr + 1]
+    };
+    static constexpr int kMaxParts = 2;
+    Span all;
+    Span part[kMaxParts];
+    int nparts = 1;
+    int streams_req = 0;               // lbm_set_streams (0: the default)
+    hipStream_t part_stream = nullptr; // the second part's stream (created at first use)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipStream_t cap_part_stream = nullptr;   // the same for graph capture
+    hipEvent_t cap_fork = nullptr, cap_join = nullptr;
     int fuse = 1;                      // most time steps per launch where allowed (1 .. fuse_max)
     // relative cost of one launch of k steps (index k = 1 .. fuse_max): plain,
     // and fused ending on the check step (see plan_launch)
@@ -400,6 +417,8 @@ static bool valid(lbm_handle h) { return h && h->magic == kMagic; }
 
 // ------------------------------------------------------------------ schedule
 
+static void make_parts(lbm_ctx* h);
+
 static void build_tiles(lbm_ctx* h) {
     const Shape& s = h->shape;
     h->ntiles = 0;
@@ -431,6 +450,55 @@ static void build_tiles(lbm_ctx* h) {
         h->npgroups += d.p_ngroups;
         h->pgroup_inst.insert(h->pgroup_inst.end(), (size_t)d.p_ngroups, (int32_t)k);
     }
+    make_parts(h);
+}
+
+static lbm_ctx::Span span_of(const lbm_ctx* h, int i0, int i1, int ctr) {
+    lbm_ctx::Span sp;
+    sp.i0 = i0;
+    sp.ni = i1 - i0;
+    sp.ctr = ctr;
+    if (i1 <= i0) return sp;
+    const InstDesc& a = h->desc[i0];
+    const InstDesc& b = h->desc[i1 - 1];
+    sp.t0 = a.tile_begin;
+    sp.nt = b.tile_begin + b.ntiles - a.tile_begin;
+    sp.g0 = a.group_begin;
+    sp.ng = b.group_begin + b.ngroups - a.group_begin;
+    sp.pt0 = a.p_tile_begin;
+    sp.pnt = b.p_tile_begin + b.p_ntiles - a.p_tile_begin;
+    sp.pg0 = a.p_group_begin;
+    sp.png = b.p_group_begin + b.p_ngroups - a.p_group_begin;
+    return sp;
+}
+
+// The parts of the batched schedule: with two streams, two runs of
+// consecutive instances holding about equal numbers of fused-kernel strips
+// (their tiles and reduction groups are contiguous in the tables); the second
+// part keeps its own step-counter pair (entries 4 and 5), copied from the
+// handle's at every fork, so that its launches never read a counter that the
+// first part's launches are advancing.
+static void make_parts(lbm_ctx* h) {
+    const int n = (int)h->inst.size();
+    h->all = span_of(h, 0, n, 0);
+    h->part[0] = h->all;
+    h->nparts = 1;
+    const int want = h->streams_req ? h->streams_req : (n >= 2 ? 2 : 1);
+    if (want < 2 || n < 2) return;
+    const int64_t total = (int64_t)h->ptile_inst.size();
+    int64_t acc = 0, best = INT64_MAX;
+    int cut = 1;
+    for (int k = 1; k < n; ++k) {
+        acc += h->desc[k - 1].p_ntiles;
+        const int64_t dev = std::llabs(2 * acc - total);
+        if (dev < best) {
+            best = dev;
+            cut = k;
+        }
+    }
+    h->part[0] = span_of(h, 0, cut, 0);
+    h->part[1] = span_of(h, cut, n, 4);
+    h->nparts = 2;
 }
 
 // Descriptors and the tile table.  The reference states are not part of it:
@@ -749,6 +817,15 @@ void lbm_destroy(lbm_handle h) {
     if (h->owned && h->base) (void)hipFree(h->base);
     if (h->staging) (void)hipFree(h->staging);
     if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
+    if (h->part_stream) {
+        (void)hipStreamSynchronize(h->part_stream);
+        (void)hipStreamDestroy(h->part_stream);
+    }
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->cap_part_stream) (void)hipStreamDestroy(h->cap_part_stream);
+    if (h->cap_fork) (void)hipEventDestroy(h->cap_fork);
+    if (h->cap_join) (void)hipEventDestroy(h->cap_join);
     h->magic = 0;
     delete h;
 }
@@ -878,8 +955,9 @@ static int mode_of(const lbm_ctx* h, int64_t m) {
     return kPlain;
 }
 
-// Issue step number m (1-based) on stream st reading buffer `src_k`.
-static int issue_step(lbm_ctx* h, int64_t m, int src_k, hipStream_t st, int sched) {
+// Issue step number m (1-based) of the instances of `sp` on stream st reading
+// buffer `src_k`.
+static int issue_step(lbm_ctx* h, int64_t m, int src_k, hipStream_t st, int sched, const lbm_ctx::Span& sp) {
     const int mode = mode_of(h, m);
     StepArgs a;
     a.desc = h->d_desc();
@@ -888,8 +966,8 @@ static int issue_step(lbm_ctx* h, int64_t m, int src_k, hipStream_t st, int sche
     a.dst = h->buf(1 - src_k);
     a.snap = h->d_snap();
     a.partials = h->d_part();
-    a.ctr_in = h->d_ctr() + src_k;
-    a.ctr_out = h->d_ctr() + (1 - src_k);
+    a.ctr_in = h->d_ctr() + sp.ctr + src_k;
+    a.ctr_out = h->d_ctr() + sp.ctr + (1 - src_k);
     a.seed = h->seed;
     a.sr = h->sr;
     a.ref = h->d_ref();
@@ -897,19 +975,19 @@ static int issue_step(lbm_ctx* h, int64_t m, int src_k, hipStream_t st, int sche
     // step's finalisation set (zero for non-adaptive instances and at n = 0)
     a.apply_shift = (h->K > 0 && (m - 1) % h->K == 0) ? 1 : 0;
     if (sched == LBM_SCHED_PER_INSTANCE) {
-        for (size_t k = 0; k < h->inst.size(); ++k) {
+        for (int k = sp.i0; k < sp.i0 + sp.ni; ++k) {
             a.tile_base = h->desc[k].tile_begin;
             a.ntiles = h->desc[k].ntiles;
             HIPCALL(h, launch_step(h->storage, h->shape, mode, a, h->L.nodes, st));
         }
     } else {
-        a.tile_base = 0;
-        a.ntiles = (int32_t)h->ntiles;
+        a.tile_base = sp.t0;
+        a.ntiles = sp.nt;
         HIPCALL(h, launch_step(h->storage, h->shape, mode, a, h->L.nodes, st));
     }
     if (mode == kCheck)
-        HIPCALL(h, launch_finalize(h->d_desc(), h->d_groups(), (int)h->ngroups, h->d_ref(), h->d_ref_prev(),
-                                   (int)h->inst.size(), h->d_part(), h->d_gpart(), h->d_res(), 0, st));
+        HIPCALL(h, launch_finalize(h->d_desc(), h->d_groups(), sp.g0, sp.ng, h->d_ref(), h->d_ref_prev(), sp.i0,
+                                   sp.ni, h->d_part(), h->d_gpart(), h->d_res(), 0, st));
     return LBM_OK;
 }
 
@@ -984,7 +1062,8 @@ static int plan_launch(const lbm_ctx* h, int64_t m, int64_t last, int* end) {
     return k;
 }
 
-static int issue_fused(lbm_ctx* h, int64_t m, int nsteps, int end, int src_k, hipStream_t st) {
+static int issue_fused(lbm_ctx* h, int64_t m, int nsteps, int end, int src_k, hipStream_t st,
+                       const lbm_ctx::Span& sp) {
     StepArgs a;
     a.desc = h->d_desc();
     a.tile_inst = h->d_ptiles();
@@ -992,19 +1071,41 @@ static int issue_fused(lbm_ctx* h, int64_t m, int nsteps, int end, int src_k, hi
     a.dst = h->buf(1 - src_k);
     a.snap = h->d_snap();
     a.partials = h->d_part();
-    a.ctr_in = h->d_ctr() + src_k;
-    a.ctr_out = h->d_ctr() + (1 - src_k);
+    a.ctr_in = h->d_ctr() + sp.ctr + src_k;
+    a.ctr_out = h->d_ctr() + sp.ctr + (1 - src_k);
     a.seed = h->seed;
     a.sr = h->sr;
     a.ref = h->d_ref();
     a.apply_shift = (h->K > 0 && (m - 1) % h->K == 0) ? 1 : 0;
-    a.tile_base = 0;
-    a.ntiles = (int32_t)h->ptile_inst.size();
+    a.tile_base = sp.pt0;
+    a.ntiles = sp.pnt;
     HIPCALL(h, launch_fused(h->storage, h->shape, a, nsteps, end, h->layout == LBM_LAYOUT_CHUNKED,
                             h->L.nodes, st));
     if (end == kEndCheck)
-        HIPCALL(h, launch_finalize(h->d_desc(), h->d_pgroups(), (int)h->npgroups, h->d_ref(), h->d_ref_prev(),
-                                   (int)h->inst.size(), h->d_part(), h->d_gpart(), h->d_res(), 1, st));
+        HIPCALL(h, launch_finalize(h->d_desc(), h->d_pgroups(), sp.pg0, sp.png, h->d_ref(), h->d_ref_prev(), sp.i0,
+                                   sp.ni, h->d_part(), h->d_gpart(), h->d_res(), 1, st));
+    return LBM_OK;
+}
+
+// Stream `side` (the second part's) waits for everything issued on `main`
+// so far, its step counters starting from the handle's; join: `main` waits
+// for everything issued on `side`.  The events and `side` are created at first
+// use.  Also used under graph capture (with a stream and events of its own).
+static int fork_parts(lbm_ctx* h, hipStream_t main, hipStream_t* side, hipEvent_t* fork, hipEvent_t* join) {
+    if (!*side) {
+        HIPCALL(h, hipStreamCreateWithFlags(side, hipStreamNonBlocking));
+        HIPCALL(h, hipEventCreateWithFlags(fork, hipEventDisableTiming));
+        HIPCALL(h, hipEventCreateWithFlags(join, hipEventDisableTiming));
+    }
+    HIPCALL(h, launch_copy_u32(h->d_ctr() + h->part[1].ctr, h->d_ctr(), 2, main));
+    HIPCALL(h, hipEventRecord(*fork, main));
+    HIPCALL(h, hipStreamWaitEvent(*side, *fork, 0));
+    return LBM_OK;
+}
+
+static int join_parts(lbm_ctx* h, hipStream_t main, hipStream_t side, hipEvent_t join) {
+    HIPCALL(h, hipEventRecord(join, side));
+    HIPCALL(h, hipStreamWaitEvent(main, join, 0));
     return LBM_OK;
 }
 
@@ -1014,9 +1115,18 @@ static int chunk_of(const lbm_ctx* h) { return h->K ? h->K : 64; }
 // buffer parity `par` (the index of the buffer holding the current state).
 static int capture(lbm_ctx* h, int par) {
     const int C = chunk_of(h);
+    // the parts of the batched schedule become two branches of the graph
+    const bool multi = h->nparts > 1;
+    if (multi && !h->cap_part_stream) {
+        HIPCALL(h, hipStreamCreateWithFlags(&h->cap_part_stream, hipStreamNonBlocking));
+        HIPCALL(h, hipEventCreateWithFlags(&h->cap_fork, hipEventDisableTiming));
+        HIPCALL(h, hipEventCreateWithFlags(&h->cap_join, hipEventDisableTiming));
+    }
     HIPCALL(h, hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
     int src = par;
     int rc = LBM_OK;
+    if (multi) rc = fork_parts(h, h->capture_stream, &h->cap_part_stream, &h->cap_fork, &h->cap_join);
+    const int np = multi ? h->nparts : 1;
     int flips = 0;
     lbm_ctx::Tail tail;
     int tail_flip = 0;
@@ -1025,19 +1135,22 @@ static int capture(lbm_ctx* h, int par) {
         const int k = plan_launch(h, s, C, &end);
         tail = lbm_ctx::Tail();
         tail_flip = flips & 1;
+        for (int p = 0; p < np && rc == LBM_OK; ++p) {
+            hipStream_t st = p == 0 ? h->capture_stream : h->cap_part_stream;
+            const lbm_ctx::Span& sp = multi ? h->part[p] : h->all;
+            rc = k >= 2 ? issue_fused(h, (int64_t)s, k, end, src, st, sp)
+                        : issue_step(h, (int64_t)s, src, st, LBM_SCHED_BATCHED, sp);
+        }
         if (k >= 2) {
-            rc = issue_fused(h, (int64_t)s, k, end, src, h->capture_stream);
             tail.k = k;
             tail.apply_shift = (h->K > 0 && (s - 1) % h->K == 0) ? 1 : 0;
             tail.checked = end == kEndCheck ? 1 : 0;
-            s += k;
-        } else {
-            rc = issue_step(h, (int64_t)s, src, h->capture_stream, LBM_SCHED_BATCHED);
-            s += 1;
         }
+        s += k;
         src = 1 - src;
         ++flips;
     }
+    if (multi && rc == LBM_OK) rc = join_parts(h, h->capture_stream, h->cap_part_stream, h->cap_join);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(h->capture_stream, &g);
     if (rc) {
@@ -1060,17 +1173,10 @@ static int capture(lbm_ctx* h, int par) {
     return LBM_OK;
 }
 
-int lbm_step(lbm_handle h, int64_t nsteps) {
-    if (!valid(h)) return LBM_EINVAL;
-    if (nsteps < 0) return h->fail(LBM_EINVAL, "nsteps < 0");
-    if (!h->base) return h->fail(LBM_ESTATE, "no device memory bound");
-    for (char c : h->inited)
-        if (!c) return h->fail(LBM_ESTATE, "every instance must be initialised before lbm_step");
-    if (nsteps > 0) {
-        // the readout buffer and the descriptor copy describe the last step so far
-        h->replayed = false;
-        h->desc_saved = false;
-    }
+static int step_loop(lbm_ctx* h, int64_t nsteps, bool multi) {
+    const int np = multi ? h->nparts : 1;
+    auto stream_of = [&](int p) { return p == 0 ? h->stream : h->part_stream; };
+    auto span_of_part = [&](int p) -> const lbm_ctx::Span& { return multi ? h->part[p] : h->all; };
     int64_t left = nsteps;
     while (left > 0) {
         const int C = chunk_of(h);
@@ -1098,8 +1204,10 @@ int lbm_step(lbm_handle h, int64_t nsteps) {
         const int k = sched == LBM_SCHED_PER_INSTANCE ? 1 : plan_launch(h, m, h->steps + left, &end);
         h->tail = lbm_ctx::Tail();
         if (k >= 2) {
-            int rc = issue_fused(h, m, k, end, h->cur, h->stream);
-            if (rc) return rc;
+            for (int p = 0; p < np; ++p) {
+                int rc = issue_fused(h, m, k, end, h->cur, stream_of(p), span_of_part(p));
+                if (rc) return rc;
+            }
             h->tail.k = k;
             h->tail.src = h->cur;
             h->tail.apply_shift = (h->K > 0 && (m - 1) % h->K == 0) ? 1 : 0;
@@ -1110,14 +1218,41 @@ int lbm_step(lbm_handle h, int64_t nsteps) {
             left -= k;
             continue;
         }
-        int rc = issue_step(h, m, h->cur, h->stream, sched);
-        if (rc) return rc;
+        for (int p = 0; p < np; ++p) {
+            int rc = issue_step(h, m, h->cur, stream_of(p), sched, span_of_part(p));
+            if (rc) return rc;
+        }
         if (mode_of(h, m) == kCheck) h->last_check = m;
         h->cur = 1 - h->cur;
         h->steps = m;
         --left;
     }
     return LBM_OK;
+}
+
+int lbm_step(lbm_handle h, int64_t nsteps) {
+    if (!valid(h)) return LBM_EINVAL;
+    if (nsteps < 0) return h->fail(LBM_EINVAL, "nsteps < 0");
+    if (!h->base) return h->fail(LBM_ESTATE, "no device memory bound");
+    for (char c : h->inited)
+        if (!c) return h->fail(LBM_ESTATE, "every instance must be initialised before lbm_step");
+    if (nsteps > 0) {
+        // the readout buffer and the descriptor copy describe the last step so far
+        h->replayed = false;
+        h->desc_saved = false;
+    }
+    // the batched schedule spreads the instances over the parts' streams
+    const bool multi = nsteps > 0 && h->nparts > 1 && h->sched == LBM_SCHED_BATCHED;
+    if (multi) {
+        const int rc = fork_parts(h, h->stream, &h->part_stream, &h->ev_fork, &h->ev_join);
+        if (rc) return rc;
+    }
+    int rc = step_loop(h, nsteps, multi);
+    if (multi) {
+        const int rj = join_parts(h, h->stream, h->part_stream, h->ev_join);
+        if (!rc) rc = rj;
+    }
+    return rc;
 }
 
 // Rebuild, in the readout buffer, the post-relaxation state of step n - 1
@@ -1345,6 +1480,17 @@ int lbm_set_schedule(lbm_handle h, int32_t schedule) {
     h->sched = schedule;
     return LBM_OK;
 }
+
+int lbm_set_streams(lbm_handle h, int32_t n) {
+    if (!valid(h)) return LBM_EINVAL;
+    if (n < 0 || n > lbm_ctx::kMaxParts) return h->fail(LBM_EINVAL, "streams must be 0, 1 or 2");
+    h->streams_req = n;
+    make_parts(h);
+    h->drop_graphs();
+    return LBM_OK;
+}
+
+int32_t lbm_get_streams(lbm_handle h) { return valid(h) ? h->nparts : -1; }
 
 static Status shape_ok(const lbm_launch_shape* s) {
     if (!s) return {LBM_EINVAL, "shape is NULL"};

@@ -91,6 +91,8 @@ SIGNATURES = [
     ("lbm_get_step_fusion", ctypes.c_int32, [_P]),
     ("lbm_max_step_fusion", ctypes.c_int32, [ctypes.c_int32]),
     ("lbm_set_schedule", ctypes.c_int, [_P, ctypes.c_int32]),
+    ("lbm_set_streams", ctypes.c_int, [_P, ctypes.c_int32]),
+    ("lbm_get_streams", ctypes.c_int32, [_P]),
     ("lbm_set_launch_shape", ctypes.c_int, [_P, ctypes.POINTER(lbm_launch_shape)]),
     ("lbm_get_launch_shape", ctypes.c_int, [_P, ctypes.POINTER(lbm_launch_shape)]),
     ("lbm_autotune", ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_char_p, ctypes.c_size_t]),
@@ -234,6 +236,14 @@ def lbm_max_step_fusion(storage: int) -> int:
 
 def lbm_set_schedule(h, schedule: int) -> None:
     _check(library().lbm_set_schedule(h, int(schedule)), "lbm_set_schedule", h)
+
+
+def lbm_set_streams(h, n: int) -> None:
+    _check(library().lbm_set_streams(h, int(n)), "lbm_set_streams", h)
+
+
+def lbm_get_streams(h) -> int:
+    return int(library().lbm_get_streams(h))
 
 
 def lbm_set_launch_shape(h, vec: int, block_x: int, block_y: int = 1, xcd_remap: int = 1,
@@ -407,6 +417,12 @@ class Lattice:
     def set_schedule(self, name: str) -> None:
         lbm_set_schedule(self.h, {"batched": LBM_SCHED_BATCHED, "per_instance": LBM_SCHED_PER_INSTANCE,
                                   "graph": LBM_SCHED_GRAPH}[name])
+
+    def set_streams(self, n: int) -> None:
+        lbm_set_streams(self.h, n)
+
+    def streams(self) -> int:
+        return lbm_get_streams(self.h)
 
     def set_launch_shape(self, **kw) -> None:
         lbm_set_launch_shape(self.h, **kw)

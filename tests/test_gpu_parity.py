@@ -671,33 +671,63 @@ def test_residual_and_check_totals(fuse):
 
 
 def test_batched_schedules_bitwise_and_parity():
-    """Uneven instances in one handle: batched launch, one launch per instance
-    and the captured graph give identical bits, and each instance matches the
+    """Uneven instances in one handle: batched launches on one stream and on
+    two (the instances split in two parts), one launch per instance and the
+    captured graph give identical bits, with single steps and with fused
+    launches, to nearest and stochastically rounded; each instance matches the
     oracle."""
     cases = W.knudsen_sweep(n_inst=6, seed=7, side_lo=20, side_hi=140, steps=0)
     insts = [instance_from_case(c) for c in cases]
     outs = {}
-    for sched in ("batched", "per_instance", "graph", "sr_batched", "sr_per_instance", "sr_graph"):
-        sr = sched.startswith("sr_")
+    runs = [(sched, streams, fuse, sr) for sr in (False, True)
+            for sched, streams, fuse in (("batched", 0, 1), ("batched", 1, 1), ("per_instance", 0, 1),
+                                         ("graph", 0, 1), ("batched", 0, 6), ("batched", 1, 6), ("graph", 0, 6))]
+    for sched, streams, fuse, sr in runs:
         lat = Lattice(insts, check_interval=10, rounding="stochastic" if sr else "nearest", seed=5)
-        sched = sched[3:] if sr else sched
         lat.set_schedule(sched)
+        lat.set_streams(streams)
+        assert lat.streams() == (1 if streams == 1 else 2)
+        lat.set_step_fusion(fuse)
         for k in range(len(cases)):
             lat.init(k)
         lat.step(45)
-        outs[("sr_" if sr else "") + sched] = [lat.moments(k) for k in range(len(cases))]
+        # a second call: the second part's counters restart from the handle's
+        lat.step(13)
+        outs[(sched, streams, fuse, sr)] = [lat.moments(k) for k in range(len(cases))]
         lat.close()
     for k, case in enumerate(cases):
-        for pre in ("", "sr_"):
-            for sched in ("per_instance", "graph"):
-                for a, b in zip(outs[pre + sched][k], outs[pre + "batched"][k]):
-                    assert np.array_equal(a, b), (pre + sched, k)
-        e_t, e_q = eps(case, outs["sr_batched"][k], oracle_fields(case, 45))
+        for key in runs:
+            ref_key = ("batched", 0, 1, key[3])
+            for a, b in zip(outs[key][k], outs[ref_key][k]):
+                assert np.array_equal(a, b), (key, k)
+        e_t, e_q = eps(case, outs[("batched", 0, 1, True)][k], oracle_fields(case, 58))
         log(f"batched SR inst {k}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
         assert e_q < 1e-5 and e_t < 1e-5, ("stochastic", k, e_t, e_q)
-        e_t, e_q = eps(case, outs["batched"][k], oracle_fields(case, 45))
+        e_t, e_q = eps(case, outs[("batched", 0, 1, False)][k], oracle_fields(case, 58))
         log(f"batched inst {k} {case.nx}x{case.ny} tr={case.tau_r:.3g}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
         assert e_q < 1e-5 and e_t < 1e-5
+
+
+def test_streams_setting():
+    """lbm_set_streams: 0 restores the default (two streams for two or more
+    instances, one for a single instance); values outside 0 .. 2 are rejected."""
+    case = W.Case("s", 40, 12, 0.6, 0.8)
+    one = Lattice([instance_from_case(case)])
+    assert one.streams() == 1
+    one.set_streams(2)
+    assert one.streams() == 1          # a single instance has nothing to split
+    one.close()
+    lat = Lattice([instance_from_case(case), instance_from_case(case)])
+    assert lat.streams() == 2
+    lat.set_streams(1)
+    assert lat.streams() == 1
+    lat.set_streams(0)
+    assert lat.streams() == 2
+    for bad in (-1, 3):
+        with pytest.raises(LBMError) as e:
+            lat.set_streams(bad)
+        assert e.value.code == LBM_EINVAL
+    lat.close()
 
 
 def test_abi_state_errors():

@@ -277,22 +277,26 @@ def test_poiseuille_steady_1024x256(tau_n, ratio, rounding):
 @pytest.mark.parametrize("rounding", ["stochastic", "nearest"])
 def test_knudsen_sweep_256_instances(rounding):
     """256 uneven channel instances in one handle, 2000 steps under each of the
-    batched, per-instance and graph schedules: the three agree bit for bit on
-    the compared instances, and six of them match the oracle to the FP32 bound."""
+    batched (on two streams, the default, and on one), per-instance and graph
+    schedules: all agree bit for bit on the compared instances (from both
+    parts of the two-stream split), and six of them match the oracle to the
+    FP32 bound."""
     cases = W.knudsen_sweep()
     insts = [instance_from_case(c) for c in cases]
     steps = 2000
-    picks = (0, 1, 2, 3, 4, 5, 255)
+    picks = (0, 1, 2, 3, 4, 5, 200, 255)
     outs = {}
-    for sched in ("graph", "batched", "per_instance"):
+    for sched in ("graph", "batched", "batched_one_stream", "per_instance"):
         lat = Lattice(insts, check_interval=100, rounding=rounding, seed=7)
-        lat.set_schedule(sched)
+        lat.set_schedule("batched" if sched == "batched_one_stream" else sched)
+        if sched == "batched_one_stream":
+            lat.set_streams(1)
         for k in range(len(cases)):
             lat.init(k)
         lat.step(steps)
         outs[sched] = [lat.moments(k) for k in picks]
         lat.close()
-    for sched in ("per_instance", "graph"):
+    for sched in ("per_instance", "graph", "batched_one_stream"):
         for j, k in enumerate(picks):
             for a, b in zip(outs[sched][j], outs["batched"][j]):
                 assert np.array_equal(a, b), (sched, k)
