@@ -298,7 +298,7 @@ int lbm_set_wall_flux(lbm_handle h, int32_t inst, int32_t wall, double q0);
  * every step on its own.  Moments read after a call that ended on such a run
  * are rebuilt by replaying its earlier steps once (same bits).  The populations
  * are identical for every setting; the check-step residual and totals agree to
- * the order of their FP64 summation.  The most steps per launch depends on the storage kind (6 FP32,
+ * the order of their FP64 summation.  The most steps per launch depends on the storage kind (7 FP32,
  * 4 for the 16-bit kinds: lbm_max_step_fusion).  Default
  * for a new handle: that most when its instances hold at least 1024 strips of
  * the fused kernel in all (64 - 2 k columns by 32 rows each, k the most), so

@@ -1003,8 +1003,18 @@ __device__ __forceinline__ void march_gather(const float dn_row[8], const float 
 // CH: chunked layout, whose direction runs are kChunkPlane elements apart, so
 // that the eight loads or stores of a row share one address and differ by
 // immediate offsets.
+// Waves per SIMD the register allocation must leave room for (1: no
+// constraint).  The plain seven-step FP32 launch would take 130 VGPRs, three
+// waves per SIMD; held to 128 (four waves, two registers spilled) it runs
+// 1,230 instead of 1,383 us per launch on 8192^2.
+template <class S, int K, int END>
+struct MarchWaves {
+    static constexpr int value = (sizeof(S) == 4 && K == 7 && END == kEndPlain) ? 4 : 1;
+};
+
 template <class S, int SR, int SPLIT, int K, int KMAX, int END, int CH>
-__global__ __launch_bounds__(256) void march_kernel(StepArgs a, int xcd, int nontemporal, int64_t snap_stride) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MarchWaves<S, K, END>::value)))
+void march_kernel(StepArgs a, int xcd, int nontemporal, int64_t snap_stride) {
     static_assert(K >= 2 && K <= KMAX, "stages per launch");
     // input rows loaded ahead: one iteration's stages must cover a row load's
     // latency, so launches of few plain steps load further ahead (8 VGPRs per
@@ -1228,6 +1238,52 @@ static hipError_t launch_march_k(const Shape& sh, const StepArgs& a, int k, int 
     } else {
         if (k == K) return launch_march_s<S, SPLIT, K, KMAX>(sh, a, end, chunked, snap_stride, st);
         return launch_march_k<S, SPLIT, K + 1, KMAX>(sh, a, k, end, chunked, snap_stride, st);
+    }
+}
+
+// Launch every fused-kernel variant a handle may use (its storage kind,
+// rounding and layout; 2 .. fuse_max steps; plain, snapshot and check ends)
+// once with no tiles: each wavefront returns at its first test, touching no
+// memory.  The runtime does its once-per-kernel work (loading the code; for a
+// kernel that spills, setting up scratch memory) at a kernel's first launch,
+// which would otherwise land in the first real launch of each variant.
+template <class S, int SR, int SPLIT, int K, int KMAX>
+static hipError_t preload_march_k(int chunked, hipStream_t st) {
+    if constexpr (K > KMAX) {
+        return hipSuccess;
+    } else {
+        StepArgs a{};
+        a.ntiles = 0;
+        const dim3 grid(1), block(256);
+        if (chunked) {
+            hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, kEndPlain, 1>), grid, block, 0, st, a, 0, 0, 0);
+            hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, kEndSnap, 1>), grid, block, 0, st, a, 0, 0, 0);
+            hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, kEndCheck, 1>), grid, block, 0, st, a, 0, 0, 0);
+        } else {
+            hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, kEndPlain, 0>), grid, block, 0, st, a, 0, 0, 0);
+            hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, kEndSnap, 0>), grid, block, 0, st, a, 0, 0, 0);
+            hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, kEndCheck, 0>), grid, block, 0, st, a, 0, 0, 0);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return preload_march_k<S, SR, SPLIT, K + 1, KMAX>(chunked, st);
+    }
+}
+
+template <class S, int SPLIT, int STORAGE>
+static hipError_t preload_fused_s(int sr, int chunked, hipStream_t st) {
+    return sr ? preload_march_k<S, 1, SPLIT, 2, fuse_max(STORAGE)>(chunked, st)
+              : preload_march_k<S, 0, SPLIT, 2, fuse_max(STORAGE)>(chunked, st);
+}
+
+hipError_t preload_fused(int storage, int sr, int chunked, hipStream_t st) {
+    switch (storage) {
+        case 0: return preload_fused_s<float, 0, 0>(sr, chunked, st);
+        case 1: return preload_fused_s<_Float16, 0, 1>(sr, chunked, st);
+        case 2: return preload_fused_s<bf16_bits, 0, 2>(sr, chunked, st);
+        case 3: return preload_fused_s<_Float16, 1, 3>(sr, chunked, st);
+        case 4: return preload_fused_s<bf16_bits, 1, 4>(sr, chunked, st);
+        default: return hipErrorInvalidValue;
     }
 }
 

@@ -103,12 +103,19 @@ _lib = None
 
 
 def library() -> ctypes.CDLL:
-    """Load ``libphonon_lbm.so`` (raises if it is not built)."""
+    """Load ``libphonon_lbm.so`` (raises if it is not built).
+
+    torch is imported first: its wheel carries its own HIP runtime under the
+    same soname as the system one the library links, and only a process that
+    has loaded torch's before the library's dependency is resolved ends up
+    with one HIP runtime (loaded the other way round, torch brings in a second
+    copy, which claims the GPU, and the library's own calls find no device)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
                                "(build it with python -m paper_2010_01847_amd.build)")
+        import torch  # noqa: F401  (see above)
         L = ctypes.CDLL(LIB_PATH)
         for name, res, args in SIGNATURES:
             f = getattr(L, name)

@@ -166,7 +166,7 @@ def test_max_step_fusion_per_storage_kind():
     """The most time steps per fused launch, per storage kind (no device)."""
     got = [P.lbm_max_step_fusion(k) for k in (P.LBM_F32, P.LBM_F16, P.LBM_BF16, P.LBM_F16_SPLIT,
                                                P.LBM_BF16_SPLIT)]
-    assert got == [6, 4, 4, 4, 4]
+    assert got == [7, 4, 4, 4, 4]
     assert P.lbm_max_step_fusion(5) == -1 and P.lbm_max_step_fusion(-1) == -1
 
 

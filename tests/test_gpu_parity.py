@@ -439,7 +439,7 @@ def _fuse_max(storage):
     return P.lbm_max_step_fusion(P.STORAGE[storage])
 
 
-@pytest.mark.parametrize("storage,kmax", [("f32", 6), ("f16", 4), ("bf16", 4), ("f16_split", 4),
+@pytest.mark.parametrize("storage,kmax", [("f32", 7), ("f16", 4), ("bf16", 4), ("f16_split", 4),
                                           ("bf16_split", 4)])
 def test_step_fusion_range(storage, kmax):
     """A new handle fuses up to its storage kind's most steps per launch when
@@ -551,17 +551,18 @@ def test_readout_keeps_the_last_steps_wall_flux(storage):
 
 
 @pytest.mark.parametrize("storage", ["f32", "bf16", "f16_split"])
-@pytest.mark.parametrize("nx,ny", [(2, 2), (3, 2), (5, 3), (53, 13), (57, 14), (104, 13), (105, 25),
-                                   (112, 31), (70, 33), (113, 65), (111, 34)])
+@pytest.mark.parametrize("nx,ny", [(2, 2), (3, 2), (5, 3), (51, 13), (57, 14), (100, 13), (101, 25),
+                                   (99, 20), (112, 31), (70, 33), (113, 65), (111, 34)])
 def test_fused_kernel_small_and_ragged(nx, ny, storage):
     """Strips wider than the lattice (the window wraps several times), and
-    lattices on a strip edge (52 output columns for FP32, 56 for the 16-bit
-    kinds: 104 = 2 x 52, 112 = 2 x 56) or one node past one (53, 57, 105,
-    113) or one short (111), and one row past a 32-row marching chunk or two
-    (33, 65): same bits as single steps for two and for the most steps per
+    lattices on a strip edge (50 output columns for FP32, 56 for the 16-bit
+    kinds: 100 = 2 x 50, 112 = 2 x 56) or one node past one (51, 57, 101,
+    113) or one short (99, 111), and one row past a 32-row marching chunk or
+    two (33, 65): same bits as single steps for two and for the most steps per
     launch, and the oracle."""
     case, T0, qx, qy = _random_case(nx, ny, 0.8, 8.0, nx * 7 + ny)
-    steps = (5, 8)        # fused launches of every length up to six, and singles
+    # fused launches of every length up to the most (seven FP32, four 16-bit), and singles
+    steps = (5, 8, 7) if storage == "f32" else (5, 8)
     a = _fused_run(case, T0, qx, qy, storage, "nearest", 1, steps, 0)
     for fuse in sorted({2, _fuse_max(storage)}):
         b = _fused_run(case, T0, qx, qy, storage, "nearest", fuse, steps, 0)
