@@ -108,16 +108,16 @@ Geometry geometry_of(const lbm_instance& in, int es, int layout, bool split = fa
 // (three waves per SIMD instead of four).  lbm_autotune replaces the plain figures
 // by its own timings on the handle's lattices and scales the check figures.
 static void default_costs(int storage, double plain[8], double check[8]) {
-    static const double p_tab[5][8] = {{0, 737, 1213, 1208, 1236, 1091, 1098, 1230},   // F32
-                                       {0, 480, 603, 607, 745, 0, 0, 0},            // F16
-                                       {0, 484, 606, 605, 733, 0, 0, 0},            // BF16
-                                       {0, 486, 713, 722, 861, 0, 0, 0},            // F16_SPLIT
-                                       {0, 509, 710, 744, 909, 0, 0, 0}};           // BF16_SPLIT
-    static const double c_tab[5][8] = {{0, 0, 1216, 1093, 1093, 1218, 1361, 1556},
-                                       {0, 0, 643, 833, 1017, 0, 0, 0},
-                                       {0, 0, 685, 856, 1015, 0, 0, 0},
-                                       {0, 0, 740, 890, 1072, 0, 0, 0},
-                                       {0, 0, 751, 932, 1123, 0, 0, 0}};
+    static const double p_tab[5][8] = {{0, 741, 1214, 1208, 1237, 1092, 1098, 1220},   // F32
+                                       {0, 496, 604, 600, 743, 0, 0, 0},               // F16
+                                       {0, 484, 607, 598, 738, 0, 0, 0},               // BF16
+                                       {0, 485, 716, 721, 864, 0, 0, 0},               // F16_SPLIT
+                                       {0, 485, 722, 738, 898, 0, 0, 0}};              // BF16_SPLIT
+    static const double c_tab[5][8] = {{0, 0, 1216, 1093, 1095, 1218, 1360, 1560},
+                                       {0, 0, 638, 834, 1014, 0, 0, 0},
+                                       {0, 0, 679, 852, 1009, 0, 0, 0},
+                                       {0, 0, 734, 894, 1074, 0, 0, 0},
+                                       {0, 0, 739, 912, 1127, 0, 0, 0}};
     for (int k = 0; k < 8; ++k) plain[k] = check[k] = 0.0;
     if (storage < 0 || storage > 4) return;
     for (int k = 1; k <= fuse_max(storage); ++k) {
