@@ -1093,11 +1093,9 @@ static int issue_fused(lbm_ctx* h, int64_t m, int nsteps, int end, int src_k, hi
 // for everything issued on `side`.  The events and `side` are created at first
 // use.  Also used under graph capture (with a stream and events of its own).
 static int fork_parts(lbm_ctx* h, hipStream_t main, hipStream_t* side, hipEvent_t* fork, hipEvent_t* join) {
-    if (!*side) {
-        HIPCALL(h, hipStreamCreateWithFlags(side, hipStreamNonBlocking));
-        HIPCALL(h, hipEventCreateWithFlags(fork, hipEventDisableTiming));
-        HIPCALL(h, hipEventCreateWithFlags(join, hipEventDisableTiming));
-    }
+    if (!*side) HIPCALL(h, hipStreamCreateWithFlags(side, hipStreamNonBlocking));
+    if (!*fork) HIPCALL(h, hipEventCreateWithFlags(fork, hipEventDisableTiming));
+    if (!*join) HIPCALL(h, hipEventCreateWithFlags(join, hipEventDisableTiming));
     HIPCALL(h, launch_copy_u32(h->d_ctr() + h->part[1].ctr, h->d_ctr(), 2, main));
     HIPCALL(h, hipEventRecord(*fork, main));
     HIPCALL(h, hipStreamWaitEvent(*side, *fork, 0));
@@ -1118,10 +1116,11 @@ static int capture(lbm_ctx* h, int par) {
     const int C = chunk_of(h);
     // the parts of the batched schedule become two branches of the graph
     const bool multi = h->nparts > 1;
-    if (multi && !h->cap_part_stream) {
-        HIPCALL(h, hipStreamCreateWithFlags(&h->cap_part_stream, hipStreamNonBlocking));
-        HIPCALL(h, hipEventCreateWithFlags(&h->cap_fork, hipEventDisableTiming));
-        HIPCALL(h, hipEventCreateWithFlags(&h->cap_join, hipEventDisableTiming));
+    if (multi) {
+        // created before the capture begins (fork_parts finds them)
+        if (!h->cap_part_stream) HIPCALL(h, hipStreamCreateWithFlags(&h->cap_part_stream, hipStreamNonBlocking));
+        if (!h->cap_fork) HIPCALL(h, hipEventCreateWithFlags(&h->cap_fork, hipEventDisableTiming));
+        if (!h->cap_join) HIPCALL(h, hipEventCreateWithFlags(&h->cap_join, hipEventDisableTiming));
     }
     HIPCALL(h, hipStreamBeginCapture(h->capture_stream, hipStreamCaptureModeThreadLocal));
     int src = par;
