@@ -141,7 +141,9 @@ int main() {
     expect(lbm_step(nullptr, 1) == LBM_EINVAL, "step(NULL)");
     expect(lbm_steps_done(nullptr) == -1, "steps_done(NULL)");
     expect(lbm_get_step_fusion(nullptr) == -1, "get_step_fusion(NULL)");
-    expect(lbm_max_step_fusion(LBM_F32) == 6 && lbm_max_step_fusion(LBM_BF16_SPLIT) == 4, "max step fusion");
+    expect(lbm_set_streams(nullptr, 2) == LBM_EINVAL, "set_streams(NULL)");
+    expect(lbm_get_streams(nullptr) == -1, "get_streams(NULL)");
+    expect(lbm_max_step_fusion(LBM_F32) == 7 && lbm_max_step_fusion(LBM_BF16_SPLIT) == 4, "max step fusion");
     expect(lbm_max_step_fusion(7) == -1, "max step fusion of a bad kind");
     double out[3];
     expect(lbm_totals(nullptr, 0, out) == LBM_EINVAL, "totals(NULL)");

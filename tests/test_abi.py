@@ -173,6 +173,8 @@ def test_max_step_fusion_per_storage_kind():
 def test_null_handle_calls_are_rejected():
     assert P.library().lbm_step(None, 1) == P.LBM_EINVAL
     assert P.library().lbm_steps_done(None) == -1
+    assert P.library().lbm_set_streams(None, 2) == P.LBM_EINVAL
+    assert P.library().lbm_get_streams(None) == -1
     P.library().lbm_destroy(None)   # ignored
 
 
