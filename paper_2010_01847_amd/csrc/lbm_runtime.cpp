@@ -814,14 +814,14 @@ void lbm_destroy(lbm_handle h) {
     if (!valid(h)) return;
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     else (void)hipDeviceSynchronize();
+    // the second part's launches before the memory goes (every lbm_step call
+    // joins them into the handle's stream; this also covers a call that failed)
+    if (h->part_stream) (void)hipStreamSynchronize(h->part_stream);
     h->drop_graphs();
     if (h->owned && h->base) (void)hipFree(h->base);
     if (h->staging) (void)hipFree(h->staging);
     if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
-    if (h->part_stream) {
-        (void)hipStreamSynchronize(h->part_stream);
-        (void)hipStreamDestroy(h->part_stream);
-    }
+    if (h->part_stream) (void)hipStreamDestroy(h->part_stream);
     if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
     if (h->ev_join) (void)hipEventDestroy(h->ev_join);
     if (h->cap_part_stream) (void)hipStreamDestroy(h->cap_part_stream);
