@@ -709,6 +709,34 @@ def test_batched_schedules_bitwise_and_parity():
         assert e_q < 1e-5 and e_t < 1e-5
 
 
+def test_graph_every_replay_matches_eager():
+    """Each replay of a captured chunk (check steps every 10, so one replay per
+    10-step call; the two parts as two branches; fused launches ending on the
+    check step; stochastic rounding) gives the same bits as the eager batched
+    schedule, with readouts and synchronisation between the replays."""
+    cases = W.knudsen_sweep(n_inst=5, seed=11, side_lo=30, side_hi=150, steps=0)
+    insts = [instance_from_case(c) for c in cases]
+    lats = {}
+    for sched in ("graph", "batched"):
+        lat = Lattice(insts, check_interval=10, rounding="stochastic", seed=21)
+        lat.set_schedule(sched)
+        lat.set_step_fusion(_fuse_max("f32"))
+        for k in range(len(cases)):
+            lat.init(k)
+        lats[sched] = lat
+    for replay in range(8):
+        outs = {}
+        for sched, lat in lats.items():
+            lat.step(10)
+            outs[sched] = [lat.moments(k) for k in range(len(cases))] + [lat.last_check(k) for k in range(len(cases))]
+        for k in range(len(cases)):
+            for a, b in zip(outs["graph"][k], outs["batched"][k]):
+                assert np.array_equal(a, b), (replay, k)
+            _same_check(outs["graph"][len(cases) + k], outs["batched"][len(cases) + k], (replay, k))
+    for lat in lats.values():
+        lat.close()
+
+
 def test_streams_setting():
     """lbm_set_streams: 0 restores the default (two streams for two or more
     instances, one for a single instance); values outside 0 .. 2 are rejected."""
