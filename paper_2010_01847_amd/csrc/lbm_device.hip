@@ -90,7 +90,7 @@ __device__ __forceinline__ void store_run(S* __restrict__ p, const float* v, int
 #define W_FA 0.333333333333333333f      // 5 a_i / 3, axis directions
 #define W_FD 0.083333333333333333f      // 5 a_i / 3, diagonal directions
 
-__device__ __forceinline__ void relax_parts(const float g[8], float eqf[8], float fl[8]) {
+__device__ __forceinline__ void relax_parts(const float g[8], float e[8], float fl[8]) {
     const float E = ((g[0] + g[2]) + (g[1] + g[3])) + ((g[4] + g[6]) + (g[5] + g[7]));
     // (g5 - g7) = -(g7 - g5) and 4 ea is exact, so the shared difference and
     // the fused form below round exactly as the plain expressions
@@ -104,7 +104,7 @@ __device__ __forceinline__ void relax_parts(const float g[8], float eqf[8], floa
     fl[0] = fx;  fl[1] = fy;  fl[2] = -fx;  fl[3] = -fy;
     fl[4] = fp;  fl[5] = -fm; fl[6] = -fp;  fl[7] = fm;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) eqf[i] = (i < 4 ? ea : ed) + fl[i];
+    for (int i = 0; i < 8; ++i) e[i] = i < 4 ? ea : ed;
 }
 
 // x component of velocity i (directions 0..7 are the paper's 1..8 of Eq. 14).
@@ -131,14 +131,21 @@ __device__ __forceinline__ RefView ref_view(const RefState& r) {
 // reference state's forcing, formed at the size of the change itself and
 // added to g once.
 __device__ __forceinline__ void relax_delta(const float g[8], const InstDesc& d, const RefView& rv,
-                                            float delta[8]) {
-    float eqf[8], fl[8];
-    relax_parts(g, eqf, fl);
+                                            float delta[8], float e[8]) {
+    float fl[8];
+    relax_parts(g, e, fl);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
+        // h_i = (g_i - omega_i E) - f_i: the first difference nearly cancels,
+        // so h_i carries the rounding of f_i, not of the energy share
         const float force = cx_times(i, rv.force_a, rv.force_d);
-        delta[i] = __builtin_fmaf(-d.sigma, fl[i], __builtin_fmaf(-d.inv_tau, g[i] - eqf[i], force));
+        delta[i] = __builtin_fmaf(-d.sigma, fl[i], __builtin_fmaf(-d.inv_tau, (g[i] - e[i]) - fl[i], force));
     }
+}
+__device__ __forceinline__ void relax_delta(const float g[8], const InstDesc& d, const RefView& rv,
+                                            float delta[8]) {
+    float e[8];
+    relax_delta(g, d, rv, delta, e);
 }
 
 __device__ __forceinline__ void relax(float g[8], const InstDesc& d, const RefView& rv) {
@@ -667,12 +674,12 @@ __global__ __launch_bounds__(kMaxBlock) void wave_kernel(StepArgs a, int64_t sna
             // residual of the eight h is added to the stored E, so the node's
             // stored populations still sum to E: 16-bit rounding moves energy
             // between directions but creates or destroys none.
-            float delta[8], hv[8];
+            float delta[8], e[8], hv[8];
             S o[8];
-            relax_delta(g, d, rv, delta);
+            relax_delta(g, d, rv, delta, e);
             const float E = ((g[0] + g[2]) + (g[1] + g[3])) + ((g[4] + g[6]) + (g[5] + g[7]));
 #pragma unroll
-            for (int i = 0; i < 8; ++i) hv[i] = (g[i] - omega_e(i, E)) + delta[i];
+            for (int i = 0; i < 8; ++i) hv[i] = (g[i] - e[i]) + delta[i];
             round_pairs<S, SR, 8>(hv, r, o);
             float res = 0.0f;
 #pragma unroll
@@ -778,13 +785,13 @@ __device__ __forceinline__ void relax_store(S* base, const InstDesc& d, const Re
     S* row = base + (int64_t)y * d.row;
     S* p = row + col_off(d, x);
     if (SPLIT) {
-        float delta[8];
-        relax_delta(g, d, rv, delta);
+        float delta[8], e[8];
+        relax_delta(g, d, rv, delta, e);
         const float E = ((g[0] + g[2]) + (g[1] + g[3])) + ((g[4] + g[6]) + (g[5] + g[7]));
         float res = 0.0f;
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            const float hv = (g[i] - omega_e(i, E)) + delta[i];
+            const float hv = (g[i] - e[i]) + delta[i];
             const S o = Cvt<S>::st(hv);
             res = res + (hv - Cvt<S>::ld(o));
             p[(int64_t)i * d.plane] = o;
@@ -896,11 +903,11 @@ template <class S, int SR, int SPLIT>
 __device__ __forceinline__ void relax_round(float g[8], const InstDesc& d, const RefView& rv, const uint32_t r[4],
                                             S o[8], float& E_out) {
     if constexpr (SPLIT) {
-        float delta[8], hv[8];
-        relax_delta(g, d, rv, delta);
+        float delta[8], e[8], hv[8];
+        relax_delta(g, d, rv, delta, e);
         const float E = ((g[0] + g[2]) + (g[1] + g[3])) + ((g[4] + g[6]) + (g[5] + g[7]));
 #pragma unroll
-        for (int i = 0; i < 8; ++i) hv[i] = (g[i] - omega_e(i, E)) + delta[i];
+        for (int i = 0; i < 8; ++i) hv[i] = (g[i] - e[i]) + delta[i];
         round_pairs<S, SR, 8>(hv, r, o);
         float res = 0.0f;
 #pragma unroll
