@@ -103,21 +103,21 @@ Geometry geometry_of(const lbm_instance& in, int es, int layout, bool split = fa
 // (it streams the same rows and the strips' halo whatever the number of
 // stages; below five FP32 steps it is bound by memory requests, above by
 // VALU issue), so the way a short run is cut into launches matters: 20 FP32
-// steps cost 3558 us as 7 + 7 + 6 and 4364 us as 5 + 5 + 5 + 5.  The check
+// steps cost 3522 us as 7 + 7 + 6 and 4372 us as 5 + 5 + 5 + 5.  The check
 // variants of five, six and seven FP32 steps need 131, 145 and 159 VGPRs
 // (three waves per SIMD instead of four).  lbm_autotune replaces the plain figures
 // by its own timings on the handle's lattices and scales the check figures.
 static void default_costs(int storage, double plain[8], double check[8]) {
-    static const double p_tab[5][8] = {{0, 741, 1214, 1208, 1237, 1092, 1098, 1220},   // F32
+    static const double p_tab[5][8] = {{0, 737, 1214, 1208, 1237, 1093, 1098, 1212},   // F32
                                        {0, 496, 604, 600, 743, 0, 0, 0},               // F16
                                        {0, 484, 607, 598, 738, 0, 0, 0},               // BF16
-                                       {0, 485, 716, 721, 864, 0, 0, 0},               // F16_SPLIT
-                                       {0, 485, 722, 738, 898, 0, 0, 0}};              // BF16_SPLIT
-    static const double c_tab[5][8] = {{0, 0, 1216, 1093, 1095, 1218, 1360, 1560},
+                                       {0, 486, 716, 717, 819, 0, 0, 0},               // F16_SPLIT
+                                       {0, 486, 721, 728, 861, 0, 0, 0}};              // BF16_SPLIT
+    static const double c_tab[5][8] = {{0, 0, 1216, 1095, 1095, 1217, 1360, 1558},
                                        {0, 0, 638, 834, 1014, 0, 0, 0},
                                        {0, 0, 679, 852, 1009, 0, 0, 0},
-                                       {0, 0, 734, 894, 1074, 0, 0, 0},
-                                       {0, 0, 739, 912, 1127, 0, 0, 0}};
+                                       {0, 0, 731, 866, 1032, 0, 0, 0},
+                                       {0, 0, 728, 889, 1084, 0, 0, 0}};
     for (int k = 0; k < 8; ++k) plain[k] = check[k] = 0.0;
     if (storage < 0 || storage > 4) return;
     for (int k = 1; k <= fuse_max(storage); ++k) {
