@@ -163,6 +163,19 @@ typedef struct {
  * added before truncation.  Requires one node per lane (launch shape vec 1). */
 #define LBM_FLAG_STOCHASTIC_ROUNDING 0x2
 
+/* 16-bit storage: round every time step of a fused launch to the storage
+ * type, as a stored step is, so that the populations do not depend on how
+ * the steps are grouped into launches (the same bits as single steps).
+ * Without it a fused launch of k >= 3 steps keeps the results of its first
+ * k - 2 steps in FP32 registers and rounds only the last two (the state it
+ * stores and the one before it, from which readouts rebuild time n): the
+ * stored state carries two roundings to 16 bits per launch instead of k,
+ * which makes the 16-bit kinds faster (six steps per launch instead of four)
+ * and more accurate, and the results depend on the launch plan (the steps
+ * per launch, the check interval and where lbm_step calls end).  No effect
+ * on FP32 storage, whose rounding is its arithmetic. */
+#define LBM_FLAG_ROUND_EVERY_STEP 0x4
+
 /* Version string of the library. */
 const char* lbm_version(void);
 
@@ -212,8 +225,9 @@ int lbm_init_device(lbm_handle h, int32_t inst, const double* T, const double* q
  * j = sum c_i g_i, and relax (Eq. 13 with Eqs. 15-16).  At every K-th step
  * the FP64 residual and totals of lbm_residual are formed (from the moments
  * of that step and the one before it).  Several steps may run in one launch
- * (lbm_set_step_fusion), the last ones of the call included; the results do
- * not depend on how the steps are grouped.
+ * (lbm_set_step_fusion), the last ones of the call included; with FP32
+ * storage, or with LBM_FLAG_ROUND_EVERY_STEP, the results do not depend on
+ * how the steps are grouped (16-bit storage otherwise: see that flag).
  * Errors: EINVAL (nsteps < 0), ESTATE (not initialised), EHIP. */
 int lbm_step(lbm_handle h, int64_t nsteps);
 
@@ -291,27 +305,32 @@ int lbm_coefficients(lbm_handle h, int32_t inst, double out[6]);
 int lbm_set_wall_flux(lbm_handle h, int32_t inst, int32_t wall, double q0);
 
 /* Most time steps per launch where allowed (temporal blocking, Eq. 13 applied
- * k times to a tile before its populations go back to HBM, the intermediate
- * states rounded exactly as stored steps): a run of k >= 2 steps is advanced
- * by one launch; a run ends at the latest on a check step (whose residual and
+ * k times to a tile before its populations go back to HBM; the intermediate
+ * states are rounded as stored steps are, for 16-bit storage only the last
+ * one unless LBM_FLAG_ROUND_EVERY_STEP): a run of k >= 2 steps is advanced by
+ * one launch; a run ends at the latest on a check step (whose residual and
  * totals the launch forms) or on the last step of an lbm_step call; 1 issues
  * every step on its own.  Moments read after a call that ended on such a run
- * are rebuilt by replaying its earlier steps once (same bits).  The populations
- * are identical for every setting; the check-step residual and totals agree to
- * the order of their FP64 summation.  The most steps per launch depends on the storage kind (7 FP32,
- * 4 for the 16-bit kinds: lbm_max_step_fusion).  Default
+ * are rebuilt by replaying its earlier steps once (the same bits as the
+ * launch's own state of its last step but one).  With FP32 storage or that
+ * flag the populations are identical for every setting and the check-step
+ * residual and totals agree to the order of their FP64 summation.  The most
+ * steps per launch depends on the storage kind (7 FP32, 6 for the 16-bit
+ * kinds, 4 for 16-bit handles with LBM_FLAG_ROUND_EVERY_STEP:
+ * lbm_max_step_fusion gives the kind's most).  Default
  * for a new handle: that most when its instances hold at least 1024 strips of
  * the fused kernel in all (64 - 2 k columns by 32 rows each, k the most), so
  * that a fused launch fills the chip, else 1.  The per-instance schedule
  * always issues single steps.  Drops captured graphs.  Errors: EINVAL (steps
- * < 1 or more than the storage kind's most). */
+ * < 1 or more than the handle's most). */
 int lbm_set_step_fusion(lbm_handle h, int32_t steps);
 
 /* The current most time steps per launch; -1 for an invalid handle. */
 int32_t lbm_get_step_fusion(lbm_handle h);
 
 /* The most time steps one fused launch takes for storage kind `storage`
- * (lbm_storage); -1 for an invalid kind.  Needs no device. */
+ * (lbm_storage; 16-bit handles with LBM_FLAG_ROUND_EVERY_STEP take at most
+ * 4); -1 for an invalid kind.  Needs no device. */
 int32_t lbm_max_step_fusion(int32_t storage);
 
 /* Select how multi-instance steps are issued (lbm_schedule).  GRAPH captures

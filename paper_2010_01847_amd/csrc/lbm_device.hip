@@ -958,14 +958,17 @@ __device__ __forceinline__ bool on_wall(const InstDesc& d, int x, int y) {
 // output rows and marches along y.  Iteration `it` loads input row
 // yi = y0 - K + it and runs K stages: stage s advances row yi - s from the
 // rows of level s - 1 (level 0: loaded, level s: advanced s steps), on lanes
-// s..63-s (its pulls stay inside the window), rounded exactly as a stored
-// step; stage K stores its output lanes.  A node pulls direction i from row
-// y - c_iy, so of a level's newest row the c_y = -1 movers are used at once,
-// the c_y = 0 movers one iteration later and the c_y = +1 movers two
-// iterations later (kept in registers), and the x neighbours come from the
-// adjacent lanes by DPP.  Per node and step the arithmetic is the single-step
-// kernels' (same functions, same order, same random bits), so the result
-// equals K single steps bit for bit.
+// s..63-s (its pulls stay inside the window); stage K stores its output
+// lanes.  A node pulls direction i from row y - c_iy, so of a level's newest
+// row the c_y = -1 movers are used at once, the c_y = 0 movers one iteration
+// later and the c_y = +1 movers two iterations later (kept in registers), and
+// the x neighbours come from the adjacent lanes by DPP.  Per node and step the
+// arithmetic is the single-step kernels' (same functions, same order, same
+// random bits).  RM (FusedRounding) says which levels are rounded exactly as a
+// stored step: all of them (kRoundEvery, then the result equals K single steps
+// bit for bit), or for 16-bit storage only the last two or the last, the
+// others keeping the FP32 result of the relaxation: the state a 16-bit
+// launch leaves in HBM then carries two roundings to 16 bits, not K.
 
 // Directions by c_y: -1 {3, 6, 7}, 0 {0, 2}, +1 {1, 4, 5}.
 __device__ __forceinline__ constexpr int ymid(int k) { return 2 * k; }
@@ -1019,10 +1022,12 @@ struct MarchWaves {
     static constexpr int value = (sizeof(S) == 4 && K == 7 && END == kEndPlain) ? 4 : 1;
 };
 
-template <class S, int SR, int SPLIT, int K, int KMAX, int END, int CH>
+template <class S, int SR, int SPLIT, int K, int KMAX, int END, int CH, int RM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MarchWaves<S, K, END>::value)))
 void march_kernel(StepArgs a, int xcd, int nontemporal, int64_t snap_stride) {
     static_assert(K >= 2 && K <= KMAX, "stages per launch");
+    static_assert(RM == kRoundEvery || sizeof(S) == 2, "FP32 storage rounds every step");
+    static_assert(RM != kRoundLast || END == kEndPlain, "the replay variant ends plain");
     // input rows loaded ahead: one iteration's stages must cover a row load's
     // latency, so launches of few plain steps load further ahead (8 VGPRs per
     // FP32 row).  Measured on MI355X (8192^2, us per launch, ahead 1 / more):
@@ -1132,14 +1137,23 @@ void march_kernel(StepArgs a, int xcd, int nontemporal, int64_t snap_stride) {
                             node_moments_f64(g, d, q_ref, E, pm_new[0], pm_new[1], pm_new[2]);
                         }
                     }
-                    uint32_t r[4] = {0u, 0u, 0u, 0u};
-                    if (SR)
-                        sr_words(r, colw,
-                                 sr_row_word((uint32_t)(d.node_off + (int64_t)gy * nx), step + (uint32_t)(s - 1), a.seed));
-                    S o[8];
-                    float E;
-                    relax_round<S, SR, SPLIT>(g, d, rv, r, o, E);
-                    reload<S, SPLIT>(o, E, out);
+                    // 16-bit storage: steps that RM does not round keep their
+                    // result in FP32 (round to nearest), as FP32 storage would
+                    const bool keep = RM == kRoundLast || (RM == kRoundLast2 && s < K - 1);
+                    if (keep) {
+                        relax(g, d, rv);
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) out[i] = g[i];
+                    } else {
+                        uint32_t r[4] = {0u, 0u, 0u, 0u};
+                        if (SR)
+                            sr_words(r, colw, sr_row_word((uint32_t)(d.node_off + (int64_t)gy * nx),
+                                                          step + (uint32_t)(s - 1), a.seed));
+                        S o[8];
+                        float E;
+                        relax_round<S, SR, SPLIT>(g, d, rv, r, o, E);
+                        reload<S, SPLIT>(o, E, out);
+                    }
                 } else {
                     const int ox = x0 + lane - KMAX, oy = yi - s;
                     if (lane >= KMAX && lane < KMAX + W && ox < nx) {
@@ -1210,108 +1224,156 @@ void march_kernel(StepArgs a, int xcd, int nontemporal, int64_t snap_stride) {
     }
 }
 
-template <class S, int SR, int SPLIT, int K, int KMAX, int END>
+template <class S, int SR, int SPLIT, int K, int KMAX, int END, int RM>
 static void launch_march_ch(const Shape& sh, const StepArgs& a, int chunked, int64_t snap_stride, hipStream_t st) {
     dim3 grid((a.ntiles + 3) / 4), block(256);
     if (chunked)
-        hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, END, 1>), grid, block, 0, st, a, sh.xcd, sh.nt,
+        hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, END, 1, RM>), grid, block, 0, st, a, sh.xcd, sh.nt,
                            snap_stride);
     else
-        hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, END, 0>), grid, block, 0, st, a, sh.xcd, sh.nt,
+        hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, END, 0, RM>), grid, block, 0, st, a, sh.xcd, sh.nt,
                            snap_stride);
 }
 
-template <class S, int SR, int SPLIT, int K, int KMAX>
+template <class S, int SR, int SPLIT, int K, int KMAX, int RM>
 static void launch_march_e(const Shape& sh, const StepArgs& a, int end, int chunked, int64_t snap_stride,
                            hipStream_t st) {
-    if (end == kEndSnap) launch_march_ch<S, SR, SPLIT, K, KMAX, kEndSnap>(sh, a, chunked, snap_stride, st);
-    else if (end == kEndCheck) launch_march_ch<S, SR, SPLIT, K, KMAX, kEndCheck>(sh, a, chunked, snap_stride, st);
-    else launch_march_ch<S, SR, SPLIT, K, KMAX, kEndPlain>(sh, a, chunked, snap_stride, st);
+    if constexpr (RM == kRoundLast) {
+        launch_march_ch<S, SR, SPLIT, K, KMAX, kEndPlain, RM>(sh, a, chunked, snap_stride, st);
+    } else {
+        if (end == kEndSnap) launch_march_ch<S, SR, SPLIT, K, KMAX, kEndSnap, RM>(sh, a, chunked, snap_stride, st);
+        else if (end == kEndCheck)
+            launch_march_ch<S, SR, SPLIT, K, KMAX, kEndCheck, RM>(sh, a, chunked, snap_stride, st);
+        else launch_march_ch<S, SR, SPLIT, K, KMAX, kEndPlain, RM>(sh, a, chunked, snap_stride, st);
+    }
 }
 
-template <class S, int SPLIT, int K, int KMAX>
+template <class S, int SPLIT, int K, int KMAX, int RM>
 static hipError_t launch_march_s(const Shape& sh, const StepArgs& a, int end, int chunked, int64_t snap_stride,
                                  hipStream_t st) {
-    if (a.sr) launch_march_e<S, 1, SPLIT, K, KMAX>(sh, a, end, chunked, snap_stride, st);
-    else launch_march_e<S, 0, SPLIT, K, KMAX>(sh, a, end, chunked, snap_stride, st);
+    if (a.sr) launch_march_e<S, 1, SPLIT, K, KMAX, RM>(sh, a, end, chunked, snap_stride, st);
+    else launch_march_e<S, 0, SPLIT, K, KMAX, RM>(sh, a, end, chunked, snap_stride, st);
     return hipGetLastError();
 }
 
+// The variant's rounding for k = K (a 16-bit kRoundLast2 launch of two steps
+// rounds both, which is kRoundEvery's kernel); -1 where none is built.
+template <class S, int K>
+constexpr int march_rounding(int rm, int end) {
+    if (sizeof(S) == 4) return rm == kRoundEvery ? kRoundEvery : -1;
+    if (rm == kRoundLast2) return K == 2 ? kRoundEvery : kRoundLast2;
+    if (rm == kRoundLast) return end == kEndPlain ? kRoundLast : -1;
+    if (rm == kRoundEvery) return K <= kFuseEveryStep ? kRoundEvery : -1;
+    return -1;
+}
+
 template <class S, int SPLIT, int K, int KMAX>
-static hipError_t launch_march_k(const Shape& sh, const StepArgs& a, int k, int end, int chunked,
+static hipError_t launch_march_k(const Shape& sh, const StepArgs& a, int k, int end, int chunked, int rm,
                                  int64_t snap_stride, hipStream_t st) {
     if constexpr (K > KMAX) {
         return hipErrorInvalidValue;
     } else {
-        if (k == K) return launch_march_s<S, SPLIT, K, KMAX>(sh, a, end, chunked, snap_stride, st);
-        return launch_march_k<S, SPLIT, K + 1, KMAX>(sh, a, k, end, chunked, snap_stride, st);
+        if (k != K) return launch_march_k<S, SPLIT, K + 1, KMAX>(sh, a, k, end, chunked, rm, snap_stride, st);
+        const int r = march_rounding<S, K>(rm, end);
+        if (r == kRoundEvery) {
+            if constexpr (sizeof(S) == 4 || K <= kFuseEveryStep)
+                return launch_march_s<S, SPLIT, K, KMAX, kRoundEvery>(sh, a, end, chunked, snap_stride, st);
+        }
+        if constexpr (sizeof(S) == 2) {
+            if (r == kRoundLast2) return launch_march_s<S, SPLIT, K, KMAX, kRoundLast2>(sh, a, end, chunked, snap_stride, st);
+            if (r == kRoundLast) return launch_march_s<S, SPLIT, K, KMAX, kRoundLast>(sh, a, end, chunked, snap_stride, st);
+        }
+        return hipErrorInvalidValue;
     }
 }
 
 // Launch every fused-kernel variant a handle may use (its storage kind,
-// rounding and layout; 2 .. fuse_max steps; plain, snapshot and check ends)
-// once with no tiles: each wavefront returns at its first test, touching no
-// memory.  The runtime does its once-per-kernel work (loading the code; for a
-// kernel that spills, setting up scratch memory) at a kernel's first launch,
-// which would otherwise land in the first real launch of each variant.
+// rounding, layout and step rounding; 2 .. fuse_max steps; plain, snapshot and
+// check ends) once with no tiles: each wavefront returns at its first test,
+// touching no memory.  The runtime does its once-per-kernel work (loading the
+// code; for a kernel that spills, setting up scratch memory) at a kernel's
+// first launch, which would otherwise land in the first real launch of each
+// variant.
+template <class S, int SR, int SPLIT, int K, int KMAX, int END, int RM>
+static hipError_t preload_one(int chunked, hipStream_t st) {
+    StepArgs a{};
+    a.ntiles = 0;
+    const dim3 grid(1), block(256);
+    if (chunked)
+        hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, END, 1, RM>), grid, block, 0, st, a, 0, 0, 0);
+    else
+        hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, END, 0, RM>), grid, block, 0, st, a, 0, 0, 0);
+    return hipGetLastError();
+}
+
 template <class S, int SR, int SPLIT, int K, int KMAX>
-static hipError_t preload_march_k(int chunked, hipStream_t st) {
+static hipError_t preload_march_k(int chunked, int every_step, hipStream_t st) {
     if constexpr (K > KMAX) {
         return hipSuccess;
     } else {
-        StepArgs a{};
-        a.ntiles = 0;
-        const dim3 grid(1), block(256);
-        if (chunked) {
-            hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, kEndPlain, 1>), grid, block, 0, st, a, 0, 0, 0);
-            hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, kEndSnap, 1>), grid, block, 0, st, a, 0, 0, 0);
-            hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, kEndCheck, 1>), grid, block, 0, st, a, 0, 0, 0);
-        } else {
-            hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, kEndPlain, 0>), grid, block, 0, st, a, 0, 0, 0);
-            hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, kEndSnap, 0>), grid, block, 0, st, a, 0, 0, 0);
-            hipLaunchKernelGGL((march_kernel<S, SR, SPLIT, K, KMAX, kEndCheck, 0>), grid, block, 0, st, a, 0, 0, 0);
+        hipError_t e = hipSuccess;
+        for (int end = kEndPlain; end <= kEndCheck && e == hipSuccess; ++end) {
+            const int r = march_rounding<S, K>(every_step || sizeof(S) == 4 ? kRoundEvery : kRoundLast2, end);
+            if constexpr (sizeof(S) == 4 || K <= kFuseEveryStep) {
+                if (r == kRoundEvery) {
+                    e = end == kEndPlain   ? preload_one<S, SR, SPLIT, K, KMAX, kEndPlain, kRoundEvery>(chunked, st)
+                        : end == kEndSnap ? preload_one<S, SR, SPLIT, K, KMAX, kEndSnap, kRoundEvery>(chunked, st)
+                                          : preload_one<S, SR, SPLIT, K, KMAX, kEndCheck, kRoundEvery>(chunked, st);
+                }
+            }
+            if constexpr (sizeof(S) == 2) {
+                if (r == kRoundLast2) {
+                    e = end == kEndPlain   ? preload_one<S, SR, SPLIT, K, KMAX, kEndPlain, kRoundLast2>(chunked, st)
+                        : end == kEndSnap ? preload_one<S, SR, SPLIT, K, KMAX, kEndSnap, kRoundLast2>(chunked, st)
+                                          : preload_one<S, SR, SPLIT, K, KMAX, kEndCheck, kRoundLast2>(chunked, st);
+                }
+            }
         }
-        const hipError_t e = hipGetLastError();
+        // the readout replay of a 16-bit handle (a launch without its last step)
+        if constexpr (sizeof(S) == 2 && K < KMAX) {
+            if (e == hipSuccess && !every_step)
+                e = preload_one<S, SR, SPLIT, K, KMAX, kEndPlain, kRoundLast>(chunked, st);
+        }
         if (e != hipSuccess) return e;
-        return preload_march_k<S, SR, SPLIT, K + 1, KMAX>(chunked, st);
+        return preload_march_k<S, SR, SPLIT, K + 1, KMAX>(chunked, every_step, st);
     }
 }
 
 template <class S, int SPLIT, int STORAGE>
-static hipError_t preload_fused_s(int sr, int chunked, hipStream_t st) {
-    return sr ? preload_march_k<S, 1, SPLIT, 2, fuse_max(STORAGE)>(chunked, st)
-              : preload_march_k<S, 0, SPLIT, 2, fuse_max(STORAGE)>(chunked, st);
+static hipError_t preload_fused_s(int sr, int chunked, int every_step, hipStream_t st) {
+    return sr ? preload_march_k<S, 1, SPLIT, 2, fuse_max(STORAGE)>(chunked, every_step, st)
+              : preload_march_k<S, 0, SPLIT, 2, fuse_max(STORAGE)>(chunked, every_step, st);
 }
 
-hipError_t preload_fused(int storage, int sr, int chunked, hipStream_t st) {
+hipError_t preload_fused(int storage, int sr, int chunked, int every_step, hipStream_t st) {
     switch (storage) {
-        case 0: return preload_fused_s<float, 0, 0>(sr, chunked, st);
-        case 1: return preload_fused_s<_Float16, 0, 1>(sr, chunked, st);
-        case 2: return preload_fused_s<bf16_bits, 0, 2>(sr, chunked, st);
-        case 3: return preload_fused_s<_Float16, 1, 3>(sr, chunked, st);
-        case 4: return preload_fused_s<bf16_bits, 1, 4>(sr, chunked, st);
+        case 0: return preload_fused_s<float, 0, 0>(sr, chunked, 1, st);
+        case 1: return preload_fused_s<_Float16, 0, 1>(sr, chunked, every_step, st);
+        case 2: return preload_fused_s<bf16_bits, 0, 2>(sr, chunked, every_step, st);
+        case 3: return preload_fused_s<_Float16, 1, 3>(sr, chunked, every_step, st);
+        case 4: return preload_fused_s<bf16_bits, 1, 4>(sr, chunked, every_step, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <class S, int SPLIT, int STORAGE>
-static hipError_t launch_fused_s(const Shape& sh, const StepArgs& a, int k, int end, int chunked,
+static hipError_t launch_fused_s(const Shape& sh, const StepArgs& a, int k, int end, int chunked, int rm,
                                  int64_t snap_stride, hipStream_t st) {
-    return launch_march_k<S, SPLIT, 2, fuse_max(STORAGE)>(sh, a, k, end, chunked, snap_stride, st);
+    return launch_march_k<S, SPLIT, 2, fuse_max(STORAGE)>(sh, a, k, end, chunked, rm, snap_stride, st);
 }
 
 hipError_t launch_fused(int storage, const Shape& sh, const StepArgs& a, int k, int end, int chunked,
-                        int64_t snap_stride, hipStream_t st) {
+                        int rounding, int64_t snap_stride, hipStream_t st) {
     if (a.ntiles <= 0) return hipSuccess;
     if (end == kEndSnap && !a.snap) return hipErrorInvalidValue;
     if (end == kEndCheck && !a.partials) return hipErrorInvalidValue;
     if (end < kEndPlain || end > kEndCheck) return hipErrorInvalidValue;
     switch (storage) {
-        case 0: return launch_fused_s<float, 0, 0>(sh, a, k, end, chunked, snap_stride, st);
-        case 1: return launch_fused_s<_Float16, 0, 1>(sh, a, k, end, chunked, snap_stride, st);
-        case 2: return launch_fused_s<bf16_bits, 0, 2>(sh, a, k, end, chunked, snap_stride, st);
-        case 3: return launch_fused_s<_Float16, 1, 3>(sh, a, k, end, chunked, snap_stride, st);
-        case 4: return launch_fused_s<bf16_bits, 1, 4>(sh, a, k, end, chunked, snap_stride, st);
+        case 0: return launch_fused_s<float, 0, 0>(sh, a, k, end, chunked, rounding, snap_stride, st);
+        case 1: return launch_fused_s<_Float16, 0, 1>(sh, a, k, end, chunked, rounding, snap_stride, st);
+        case 2: return launch_fused_s<bf16_bits, 0, 2>(sh, a, k, end, chunked, rounding, snap_stride, st);
+        case 3: return launch_fused_s<_Float16, 1, 3>(sh, a, k, end, chunked, rounding, snap_stride, st);
+        case 4: return launch_fused_s<bf16_bits, 1, 4>(sh, a, k, end, chunked, rounding, snap_stride, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -137,28 +137,32 @@ enum FusedEnd { kEndPlain = 0, kEndSnap = 1, kEndCheck = 2 };
 // steps per launch an FP32 update moves about a fifth of the single-step
 // bytes), so the most steps per launch is a per-kind balance between the HBM
 // bytes saved, the halo nodes recomputed and the registers the delay lines
-// take (FP32: 88 / 102 / 116 / 130 VGPRs at 4 / 5 / 6 / 7 steps).  Measured on
-// MI355X (8192^2 periodic lattice, GLUPS, steps per launch FP32 / FP16-SR /
-// BF16-SR / F16_SPLIT / BF16_SPLIT):
-//   4 / 4 / 2 / 3 / 3    221 / 244 / 212 / 255 / 211
-//   5 / 5 / 3 / 4 / 4    277 / 232 / 232 / 267 / 217
-//   6 / 6 / 4 / 5 / 5    315 / 217 / 235 / 271 / 214
-//   7 / 7 / 5 / 6 / 6    293 / 199 / 217 / 245 / 190
-//   8 / 8 / 6 / 7 / 7    280 / 189 / 187 / 245 / 186
-// (single steps: 90 / 147 / 128 / 137 / 131).  Chunks of 64 or 128 rows
-// instead of 32: FP32 302 / 289 at six steps.  The stochastic-rounding words
-// drawn per column and row (device file) instead of per node moved the 16-bit
-// stochastic kinds: FP16-SR 282 / 326 / 317 and BF16-SR 259 / 252 / 247 at
-// 3 / 4 / 5 steps; after the branch changes of the rounding and the shift,
-// F16_SPLIT 289 / 275 / 263 at 4 / 5 / 6 steps, and with one finiteness test
-// per node in the BF16 stochastic store, BF16-SR 291 / 309 / 304 at 3 / 4 / 5.
+// take (FP32: 88 / 102 / 116 / 130 VGPRs at 4 / 5 / 6 / 7 steps).  For the
+// 16-bit kinds it also depends on how many of a launch's steps are rounded to
+// the storage type (FusedRounding): rounding every step, four steps per
+// launch were the fastest (FP16-SR 743, F16_SPLIT 819 us per launch on
+// 8192^2); rounding the last two, six (1,085 and 1,115 us: per step 181 and
+// 186 us against 186 and 205).  Chunks of 64 or 128 rows instead of 32: FP32
+// 302 / 289 GLUPS at six steps against 315.
 constexpr int kMarchRows = 32;
 // Elements between direction runs in the chunked layout (64-node segments).
 constexpr int kChunkPlane = 64;
 __host__ __device__ constexpr int fuse_max(int storage) {
-    return storage == 0 ? 7 : 4;
+    return storage == 0 ? 7 : 6;
 }
 __host__ __device__ constexpr int fused_width(int storage) { return 64 - 2 * fuse_max(storage); }
+// Most steps per launch of a 16-bit handle that rounds every step
+// (LBM_FLAG_ROUND_EVERY_STEP).
+constexpr int kFuseEveryStep = 4;
+// Which of a fused launch's steps round their results to the storage type
+// (the others keep them in FP32 registers; FP32 storage rounds every step,
+// that being its arithmetic):
+//   kRoundEvery: every step (the same bits as single steps);
+//   kRoundLast2: the last two (16-bit default): the state of the last step but
+//                one is the one a replay of the launch without its last step
+//                stores, so readouts rebuild it bit for bit;
+//   kRoundLast : the last only (that replay, plain end).
+enum FusedRounding { kRoundEvery = 0, kRoundLast2 = 1, kRoundLast = 2 };
 // Fewest fused-kernel strips (wavefronts) over all instances for which fused
 // launches are the default: one per SIMD of the chip.
 constexpr int64_t kFuseMinStrips = 1024;
@@ -191,10 +195,13 @@ hipError_t launch_step(int storage, const Shape& sh, int mode, const StepArgs& a
 // kEndCheck, the last one is the check step (kPartials check sums per fused
 // tile go to a.partials, for launch_finalize with fused != 0); chunked != 0
 // for the chunked layout; a.apply_shift refers to the first of them;
-// a.tile_inst / tile_base / ntiles index the fused tile table.  Same bits as k
-// single steps (the check sums equal theirs up to the order of summation).
+// a.tile_inst / tile_base / ntiles index the fused tile table; `rounding`
+// (FusedRounding) says which steps round to the storage type: kRoundEvery
+// (FP32 always; 16-bit k <= kFuseEveryStep) gives the same bits as k single
+// steps (the check sums equal theirs up to the order of summation);
+// kRoundLast is for plain ends only.
 hipError_t launch_fused(int storage, const Shape& sh, const StepArgs& a, int k, int end, int chunked,
-                        int64_t snap_stride, hipStream_t st);
+                        int rounding, int64_t snap_stride, hipStream_t st);
 
 // Moments of the state at time n of one instance.  With pull != 0 the state is
 // rebuilt from the post-relaxation populations of step n-1 (advection plus
@@ -235,10 +242,12 @@ hipError_t launch_fill(void* buf, size_t bytes, uint32_t seed, hipStream_t st);
 // descriptor fields between steps).
 hipError_t launch_set_float(float* dst, float v, hipStream_t st);
 
-// Launch every fused-kernel variant of a storage kind, rounding (sr) and
-// layout once with no tiles (no memory is touched), so that the runtime's
-// first-launch work is done before the first real launch.
-hipError_t preload_fused(int storage, int sr, int chunked, hipStream_t st);
+// Launch every fused-kernel variant of a storage kind, rounding (sr), layout
+// and step rounding (every_step != 0: kRoundEvery only; else the kinds'
+// defaults and the readout replay's kRoundLast) once with no tiles (no memory
+// is touched), so that the runtime's first-launch work is done before the
+// first real launch.
+hipError_t preload_fused(int storage, int sr, int chunked, int every_step, hipStream_t st);
 
 // Copy n <= 64 32-bit words on the device (a kernel, so that it can sit in a
 // captured graph).

@@ -100,29 +100,44 @@ Geometry geometry_of(const lbm_instance& in, int es, int layout, bool split = fa
 // Launch costs of a k-step launch on the second-sound lattice 8192^2
 // (MI355X, microseconds; k = 1 is the single-step kernel), plain and ending on
 // the check step.  A fused launch costs about the same for every k from 2 up
-// (it streams the same rows and the strips' halo whatever the number of
-// stages; below five FP32 steps it is bound by memory requests, above by
-// VALU issue), so the way a short run is cut into launches matters: 20 FP32
-// steps cost 3522 us as 7 + 7 + 6 and 4372 us as 5 + 5 + 5 + 5.  The check
-// variants of five, six and seven FP32 steps need 131, 145 and 159 VGPRs
-// (three waves per SIMD instead of four).  lbm_autotune replaces the plain figures
-// by its own timings on the handle's lattices and scales the check figures.
-static void default_costs(int storage, double plain[8], double check[8]) {
+// to a kind-dependent point (it streams the same rows and the strips' halo
+// whatever the number of stages; below five FP32 steps it is bound by memory
+// requests, above by VALU issue), so the way a short run is cut into launches
+// matters: 20 FP32 steps cost 3522 us as 7 + 7 + 6 and 4372 us as 5 + 5 + 5 +
+// 5.  The check variants of five, six and seven FP32 steps need 131, 145 and
+// 159 VGPRs (three waves per SIMD instead of four).  16-bit kinds: rounding
+// every step (every_step) or the last two of a launch (FusedRounding).
+// lbm_autotune replaces the plain figures by its own timings on the handle's
+// lattices and scales the check figures.
+static void default_costs(int storage, int every_step, double plain[8], double check[8]) {
     static const double p_tab[5][8] = {{0, 737, 1214, 1208, 1237, 1093, 1098, 1212},   // F32
-                                       {0, 496, 604, 600, 743, 0, 0, 0},               // F16
-                                       {0, 484, 607, 598, 738, 0, 0, 0},               // BF16
-                                       {0, 486, 716, 717, 819, 0, 0, 0},               // F16_SPLIT
-                                       {0, 486, 721, 728, 861, 0, 0, 0}};              // BF16_SPLIT
+                                       {0, 499, 625, 631, 734, 930, 1085, 0},          // F16
+                                       {0, 489, 629, 635, 734, 930, 1075, 0},          // BF16
+                                       {0, 489, 733, 740, 783, 979, 1115, 0},          // F16_SPLIT
+                                       {0, 486, 743, 746, 801, 990, 1130, 0}};         // BF16_SPLIT
     static const double c_tab[5][8] = {{0, 0, 1216, 1095, 1095, 1217, 1360, 1558},
-                                       {0, 0, 638, 834, 1014, 0, 0, 0},
-                                       {0, 0, 679, 852, 1009, 0, 0, 0},
-                                       {0, 0, 731, 866, 1032, 0, 0, 0},
-                                       {0, 0, 728, 889, 1084, 0, 0, 0}};
+                                       {0, 0, 692, 842, 953, 1242, 1407, 0},
+                                       {0, 0, 740, 883, 1010, 1257, 1424, 0},
+                                       {0, 0, 762, 877, 998, 1278, 1447, 0},
+                                       {0, 0, 787, 887, 1012, 1292, 1466, 0}};
+    // 16-bit kinds rounding every step (kFuseEveryStep = 4 at most)
+    static const double pe_tab[5][5] = {{0, 0, 0, 0, 0},
+                                        {0, 496, 604, 600, 743},
+                                        {0, 484, 607, 598, 738},
+                                        {0, 486, 716, 717, 819},
+                                        {0, 486, 721, 728, 861}};
+    static const double ce_tab[5][5] = {{0, 0, 0, 0, 0},
+                                        {0, 0, 638, 834, 1014},
+                                        {0, 0, 679, 852, 1009},
+                                        {0, 0, 731, 866, 1032},
+                                        {0, 0, 728, 889, 1084}};
     for (int k = 0; k < 8; ++k) plain[k] = check[k] = 0.0;
     if (storage < 0 || storage > 4) return;
-    for (int k = 1; k <= fuse_max(storage); ++k) {
-        plain[k] = p_tab[storage][k];
-        check[k] = c_tab[storage][k];
+    const bool every = storage != LBM_F32 && every_step;
+    const int kmax = every ? kFuseEveryStep : fuse_max(storage);
+    for (int k = 1; k <= kmax; ++k) {
+        plain[k] = every ? pe_tab[storage][k] : p_tab[storage][k];
+        check[k] = every ? ce_tab[storage][k] : c_tab[storage][k];
     }
 }
 
@@ -331,7 +346,10 @@ struct lbm_ctx {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipStream_t cap_part_stream = nullptr;   // the same for graph capture
     hipEvent_t cap_fork = nullptr, cap_join = nullptr;
-    int fuse = 1;                      // most time steps per launch where allowed (1 .. fuse_max)
+    int fuse = 1;                      // most time steps per launch where allowed (1 .. fuse_cap())
+    int every_step = 1;                // fused launches round every step (FP32; LBM_FLAG_ROUND_EVERY_STEP)
+    // most steps per launch of this handle's kind and step rounding
+    int fuse_cap() const { return (storage != LBM_F32 && every_step) ? kFuseEveryStep : fuse_max(storage); }
     // relative cost of one launch of k steps (index k = 1 .. fuse_max): plain,
     // and fused ending on the check step (see plan_launch)
     double cost_plain[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -647,7 +665,7 @@ static Status check_config(const lbm_config* cfg, std::vector<lbm_instance>* out
         return {LBM_EUNSUPPORTED, "split storage uses the chunked layout only"};
     if (cfg->check_interval != 0 && cfg->check_interval != -1 && cfg->check_interval < 2)
         return {LBM_EINVAL, "check_interval must be 0 (default 100), -1 (off) or >= 2"};
-    if (cfg->flags & ~(LBM_FLAG_EXTERNAL_MEMORY | LBM_FLAG_STOCHASTIC_ROUNDING))
+    if (cfg->flags & ~(LBM_FLAG_EXTERNAL_MEMORY | LBM_FLAG_STOCHASTIC_ROUNDING | LBM_FLAG_ROUND_EVERY_STEP))
         return {LBM_EINVAL, "unknown flags"};
     if (cfg->layout < 0 || cfg->layout > 2)
         return {LBM_EINVAL, "layout must be LBM_LAYOUT_AUTO, _PLANES or _CHUNKED"};
@@ -703,6 +721,7 @@ int lbm_create(const lbm_config* cfg, lbm_handle* out) {
     h->stream = reinterpret_cast<hipStream_t>(cfg->stream);
     h->external = (cfg->flags & LBM_FLAG_EXTERNAL_MEMORY) != 0;
     h->sr = (cfg->flags & LBM_FLAG_STOCHASTIC_ROUNDING) ? 1 : 0;
+    h->every_step = (cfg->storage == LBM_F32 || (cfg->flags & LBM_FLAG_ROUND_EVERY_STEP)) ? 1 : 0;
     h->seed = cfg->seed;
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) {
@@ -764,8 +783,8 @@ int lbm_create(const lbm_config* cfg, lbm_handle* out) {
     // 1024^2 10.3 / 12.6 (640 strips), 2048 x 1024 17.7 / 14.4 (1280 strips),
     // 8192^2 741 / 213: a fused launch takes about one strip's marching time
     // however few strips there are.
-    h->fuse = (int64_t)h->ptile_inst.size() >= kFuseMinStrips ? fuse_max(cfg->storage) : 1;
-    default_costs(h->storage, h->cost_plain, h->cost_check);
+    h->fuse = (int64_t)h->ptile_inst.size() >= kFuseMinStrips ? h->fuse_cap() : 1;
+    default_costs(h->storage, h->every_step, h->cost_plain, h->cost_check);
     e = hipStreamCreateWithFlags(&h->capture_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         g_create_error = std::string("hipStreamCreate: ") + hipGetErrorString(e);
@@ -1081,7 +1100,7 @@ static int issue_fused(lbm_ctx* h, int64_t m, int nsteps, int end, int src_k, hi
     a.tile_base = sp.pt0;
     a.ntiles = sp.pnt;
     HIPCALL(h, launch_fused(h->storage, h->shape, a, nsteps, end, h->layout == LBM_LAYOUT_CHUNKED,
-                            h->L.nodes, st));
+                            h->every_step ? kRoundEvery : kRoundLast2, h->L.nodes, st));
     if (end == kEndCheck)
         HIPCALL(h, launch_finalize(h->d_desc(), h->d_pgroups(), sp.pg0, sp.png, h->d_ref(), h->d_ref_prev(), sp.i0,
                                    sp.ni, h->d_part(), h->d_gpart(), h->d_res(), 1, st));
@@ -1242,7 +1261,7 @@ int lbm_step(lbm_handle h, int64_t nsteps) {
         h->desc_saved = false;
     }
     if (nsteps > 0 && !h->preloaded) {
-        HIPCALL(h, preload_fused(h->storage, h->sr, h->layout == LBM_LAYOUT_CHUNKED, h->stream));
+        HIPCALL(h, preload_fused(h->storage, h->sr, h->layout == LBM_LAYOUT_CHUNKED, h->every_step, h->stream));
         h->preloaded = true;
     }
     // the batched schedule spreads the instances over the parts' streams
@@ -1284,7 +1303,7 @@ static int replay_tail(lbm_ctx* h) {
         a.tile_inst = h->d_ptiles();
         a.ntiles = (int32_t)h->ptile_inst.size();
         HIPCALL(h, launch_fused(h->storage, h->shape, a, t.k - 1, kEndPlain, h->layout == LBM_LAYOUT_CHUNKED,
-                                h->L.nodes, h->stream));
+                                h->every_step ? kRoundEvery : kRoundLast, h->L.nodes, h->stream));
     } else {
         a.tile_inst = h->d_tiles();
         a.ntiles = (int32_t)h->ntiles;
@@ -1464,8 +1483,8 @@ int lbm_set_wall_flux(lbm_handle h, int32_t k, int32_t wall, double q0) {
 
 int lbm_set_step_fusion(lbm_handle h, int32_t steps) {
     if (!valid(h)) return LBM_EINVAL;
-    if (steps < 1 || steps > fuse_max(h->storage))
-        return h->fail(LBM_EINVAL, "steps per launch must be 1 .. " + std::to_string(fuse_max(h->storage)) +
+    if (steps < 1 || steps > h->fuse_cap())
+        return h->fail(LBM_EINVAL, "steps per launch must be 1 .. " + std::to_string(h->fuse_cap()) +
                                        " for this storage kind");
     h->fuse = steps;
     h->drop_graphs();
@@ -1554,8 +1573,8 @@ static std::string tune_key(lbm_ctx* h) {
         mix(in.bc_x * 4 + in.bc_y);
     }
     char b[160];
-    snprintf(b, sizeof b, "%s|s%d|n%zu|%016llx", dev.c_str(), h->storage, h->inst.size(),
-             (unsigned long long)f);
+    snprintf(b, sizeof b, "%s|s%d%s|n%zu|%016llx", dev.c_str(), h->storage,
+             (h->storage != LBM_F32 && h->every_step) ? "e" : "", h->inst.size(), (unsigned long long)f);
     for (char* c = b; *c; ++c)
         if (*c == ' ' || *c == '"') *c = '_';
     return b;
@@ -1638,7 +1657,8 @@ static int time_fused(lbm_ctx* h, int k, int launches, hipEvent_t e0, hipEvent_t
         a.dst = h->buf(1 - src);
         a.ctr_in = h->d_ctr() + src;
         a.ctr_out = h->d_ctr() + (1 - src);
-        HIPCALL(h, launch_fused(h->storage, h->shape, a, k, 0, h->layout == LBM_LAYOUT_CHUNKED, 0, h->stream));
+        HIPCALL(h, launch_fused(h->storage, h->shape, a, k, 0, h->layout == LBM_LAYOUT_CHUNKED,
+                                h->every_step ? kRoundEvery : kRoundLast2, 0, h->stream));
         src = 1 - src;
     }
     HIPCALL(h, hipEventRecord(e1, h->stream));
@@ -1663,7 +1683,7 @@ int lbm_autotune(lbm_handle h, int32_t steps, char* report, size_t report_len) {
         lbm_launch_shape ls = {cached.vec, cached.bx, cached.by, cached.xcd, cached.nt};
         if (report && report_len) snprintf(report, report_len, "{\"key\": \"%s\", \"cached\": true}", key.c_str());
         const int rc = lbm_set_launch_shape(h, &ls);
-        if (!rc) h->fuse = std::min(std::max(cached_fuse, 1), fuse_max(h->storage));
+        if (!rc) h->fuse = std::min(std::max(cached_fuse, 1), h->fuse_cap());
         return rc;
     }
     // scratch contents: a fixed pattern of moderate finite values with
@@ -1722,14 +1742,14 @@ int lbm_autotune(lbm_handle h, int32_t steps, char* report, size_t report_len) {
     // best single-step shape; small lattices hold few strips and may prefer
     // fewer steps per launch
     float fused_us = 1e30f;
-    int fused_k = fuse_max(h->storage);
+    int fused_k = h->fuse_cap();
     std::string fused_rep;
     double launch_us[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // measured per-launch times, k = 1 .. kmax
     if (!rc) {
         h->shape = best;
         build_tiles(h);
         rc = upload_tables(h);
-        for (int k = 2; k <= fuse_max(h->storage) && !rc; ++k) {
+        for (int k = 2; k <= h->fuse_cap() && !rc; ++k) {
             float us = 0.0f;
             rc = time_fused(h, k, (steps + k - 1) / k, e0, e1, &us);
             launch_us[k] = (double)us * k;
@@ -1750,9 +1770,9 @@ int lbm_autotune(lbm_handle h, int32_t steps, char* report, size_t report_len) {
     // launches scaled from the built-in figures by the same ratio
     {
         double dp[8], dc[8];
-        default_costs(h->storage, dp, dc);
+        default_costs(h->storage, h->every_step, dp, dc);
         launch_us[1] = best_us;
-        for (int k = 1; k <= fuse_max(h->storage); ++k) {
+        for (int k = 1; k <= h->fuse_cap(); ++k) {
             if (!(launch_us[k] > 0.0)) continue;
             h->cost_plain[k] = launch_us[k];
             if (k >= 2 && dp[k] > 0.0) h->cost_check[k] = dc[k] * launch_us[k] / dp[k];

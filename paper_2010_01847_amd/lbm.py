@@ -28,6 +28,7 @@ LBM_BC_PERIODIC, LBM_BC_ISOTHERMAL, LBM_BC_DIFFUSE, LBM_BC_GRADIENT, LBM_BC_HEAT
 LBM_SCHED_BATCHED, LBM_SCHED_PER_INSTANCE, LBM_SCHED_GRAPH = 0, 1, 2
 LBM_FLAG_EXTERNAL_MEMORY = 0x1
 LBM_FLAG_STOCHASTIC_ROUNDING = 0x2
+LBM_FLAG_ROUND_EVERY_STEP = 0x4
 LBM_LAYOUT_AUTO, LBM_LAYOUT_PLANES, LBM_LAYOUT_CHUNKED = 0, 1, 2
 LAYOUT = {"auto": LBM_LAYOUT_AUTO, "planes": LBM_LAYOUT_PLANES, "chunked": LBM_LAYOUT_CHUNKED}
 
@@ -308,7 +309,8 @@ class Lattice:
     """One handle over one or more instances, memory from torch, stream from torch."""
 
     def __init__(self, instances: Iterable[lbm_instance], storage="f32", check_interval: int = 0,
-                 device=None, stream=None, layout="auto", rounding="nearest", seed: int = 0):
+                 device=None, stream=None, layout="auto", rounding="nearest", seed: int = 0,
+                 every_step: bool = False):
         import torch
         self._torch = torch
         self.instances: List[lbm_instance] = list(instances)
@@ -322,7 +324,8 @@ class Lattice:
         cfg.check_interval = int(check_interval)
         if rounding not in ("nearest", "stochastic"):
             raise ValueError("rounding must be 'nearest' or 'stochastic'")
-        cfg.flags = LBM_FLAG_EXTERNAL_MEMORY | (LBM_FLAG_STOCHASTIC_ROUNDING if rounding == "stochastic" else 0)
+        cfg.flags = (LBM_FLAG_EXTERNAL_MEMORY | (LBM_FLAG_STOCHASTIC_ROUNDING if rounding == "stochastic" else 0)
+                     | (LBM_FLAG_ROUND_EVERY_STEP if every_step else 0))
         cfg.seed = int(seed) & 0xffffffff
         cfg.inst = ctypes.cast(arr, ctypes.POINTER(lbm_instance))
         cfg.stream = ctypes.c_void_p(self.stream.cuda_stream)

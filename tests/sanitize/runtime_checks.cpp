@@ -59,15 +59,18 @@ int main() {
     for (int st = LBM_F32; st <= LBM_BF16_SPLIT; ++st)
         for (int layout = 0; layout <= 2; ++layout)
             for (int check : {0, -1, 2, 100}) {
+              for (int32_t flags : {0, (int32_t)LBM_FLAG_ROUND_EVERY_STEP}) {
                 std::vector<lbm_instance> v = {inst(2, 2), inst(65, 3, LBM_BC_ISOTHERMAL), inst(513, 77, LBM_BC_GRADIENT,
                                                                                                LBM_BC_DIFFUSE)};
                 lbm_config c = config(v, st);
                 c.layout = layout;
                 c.check_interval = check;
+                c.flags = flags;
                 const int split = st == LBM_F16_SPLIT || st == LBM_BF16_SPLIT;
                 const int rc = required(c, &bytes);
                 if (split && layout == LBM_LAYOUT_PLANES) expect(rc == LBM_EUNSUPPORTED, "split planes refused");
                 else expect(rc == LBM_OK && bytes > 0, "valid config sized");
+              }
             }
     // near the node-count limit (2^31 nodes): sizes must not overflow
     {
@@ -143,7 +146,7 @@ int main() {
     expect(lbm_get_step_fusion(nullptr) == -1, "get_step_fusion(NULL)");
     expect(lbm_set_streams(nullptr, 2) == LBM_EINVAL, "set_streams(NULL)");
     expect(lbm_get_streams(nullptr) == -1, "get_streams(NULL)");
-    expect(lbm_max_step_fusion(LBM_F32) == 7 && lbm_max_step_fusion(LBM_BF16_SPLIT) == 4, "max step fusion");
+    expect(lbm_max_step_fusion(LBM_F32) == 7 && lbm_max_step_fusion(LBM_BF16_SPLIT) == 6, "max step fusion");
     expect(lbm_max_step_fusion(7) == -1, "max step fusion of a bad kind");
     double out[3];
     expect(lbm_totals(nullptr, 0, out) == LBM_EINVAL, "totals(NULL)");

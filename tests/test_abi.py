@@ -166,8 +166,16 @@ def test_max_step_fusion_per_storage_kind():
     """The most time steps per fused launch, per storage kind (no device)."""
     got = [P.lbm_max_step_fusion(k) for k in (P.LBM_F32, P.LBM_F16, P.LBM_BF16, P.LBM_F16_SPLIT,
                                                P.LBM_BF16_SPLIT)]
-    assert got == [7, 4, 4, 4, 4]
+    assert got == [7, 6, 6, 6, 6]
     assert P.lbm_max_step_fusion(5) == -1 and P.lbm_max_step_fusion(-1) == -1
+
+
+def test_round_every_step_flag_accepted():
+    """LBM_FLAG_ROUND_EVERY_STEP is a known flag for every storage kind."""
+    for st in (P.LBM_F32, P.LBM_F16, P.LBM_BF16_SPLIT):
+        cfg = _cfg([P.make_instance(70, 33, 0.6, 5.0)], storage=st,
+                   flags=P.LBM_FLAG_EXTERNAL_MEMORY | P.LBM_FLAG_ROUND_EVERY_STEP)
+        assert P.lbm_required_bytes(cfg) > 0
 
 
 def test_null_handle_calls_are_rejected():

@@ -408,11 +408,13 @@ FUSION_CASES = [
 ]
 
 
-def _fused_run(case, T0, qx, qy, storage, rounding, fuse, steps, check, schedule=None, n_inst=1):
+def _fused_run(case, T0, qx, qy, storage, rounding, fuse, steps, check, schedule=None, n_inst=1,
+               every_step=False):
     """Run with at most `fuse` steps per launch (1: single steps only; None:
-    the storage kind's most, the default)."""
+    the handle's default); every_step: 16-bit storage rounds every step of a
+    fused launch (LBM_FLAG_ROUND_EVERY_STEP)."""
     lat = Lattice([instance_from_case(case)] * n_inst, storage=storage, check_interval=check,
-                  rounding=rounding, seed=9)
+                  rounding=rounding, seed=9, every_step=every_step)
     if fuse is not None:
         lat.set_step_fusion(fuse)
     if schedule:
@@ -435,27 +437,32 @@ def _fused_run(case, T0, qx, qy, storage, rounding, fuse, steps, check, schedule
     return out
 
 
-def _fuse_max(storage):
-    return P.lbm_max_step_fusion(P.STORAGE[storage])
+def _fuse_max(storage, every_step=False):
+    """The most steps per launch of a handle (16-bit rounding every step: 4)."""
+    k = P.lbm_max_step_fusion(P.STORAGE[storage])
+    return min(k, 4) if (every_step and storage != "f32") else k
 
 
-@pytest.mark.parametrize("storage,kmax", [("f32", 7), ("f16", 4), ("bf16", 4), ("f16_split", 4),
-                                          ("bf16_split", 4)])
-def test_step_fusion_range(storage, kmax):
-    """A new handle fuses up to its storage kind's most steps per launch when
-    its lattices fill the chip (at least 1024 strips of the fused kernel) and
-    runs single steps otherwise; 1 .. the most are accepted, 0 and one more
-    are refused."""
-    assert P.lbm_max_step_fusion(P.STORAGE[storage]) == kmax
-    width = 64 - 2 * kmax
+@pytest.mark.parametrize("storage,every,kmax", [("f32", False, 7), ("f32", True, 7), ("f16", False, 6),
+                                                ("bf16", False, 6), ("f16_split", False, 6),
+                                                ("bf16_split", False, 6), ("f16", True, 4),
+                                                ("bf16_split", True, 4)])
+def test_step_fusion_range(storage, every, kmax):
+    """A new handle fuses up to its most steps per launch (the storage kind's,
+    four for 16-bit storage rounding every step) when its lattices fill the
+    chip (at least 1024 strips of the fused kernel) and runs single steps
+    otherwise; 1 .. the most are accepted, 0 and one more are refused."""
+    assert _fuse_max(storage, every) == kmax
+    width = 64 - 2 * P.lbm_max_step_fusion(P.STORAGE[storage])     # strip width: the kind's most
     big = W.Case("big", width * 32, 32 * 32, 0.6, 5.0)            # exactly 1024 strips
-    lat = Lattice([instance_from_case(big)], storage=storage)
+    lat = Lattice([instance_from_case(big)], storage=storage, every_step=every)
     assert lat.step_fusion() == kmax
     lat.close()
-    lat = Lattice([instance_from_case(W.Case("less", width * 31, 32 * 32, 0.6, 5.0))], storage=storage)
+    lat = Lattice([instance_from_case(W.Case("less", width * 31, 32 * 32, 0.6, 5.0))], storage=storage,
+                  every_step=every)
     assert lat.step_fusion() == 1                                     # 31 x 32 strips
     lat.close()
-    lat = Lattice([instance_from_case(W.Case("probe", 8, 8, 0.6, 5.0))], storage=storage)
+    lat = Lattice([instance_from_case(W.Case("probe", 8, 8, 0.6, 5.0))], storage=storage, every_step=every)
     assert lat.step_fusion() == 1
     for bad in (0, kmax + 1):
         with pytest.raises(LBMError) as e:
@@ -482,24 +489,50 @@ def _same_check(a, b, what):
 FUSION_STEPS = (1, 2, 3, 4, 9, 1, 19, 26)
 
 
+def _residual(m1, m0):
+    """||m1 - m0|| / ||m1|| over (dT, qx, qy), as the check step forms it."""
+    return math.sqrt(sum(float(np.sum((a - b) ** 2)) for a, b in zip(m1, m0)) / sum(float(np.sum(a ** 2)) for a in m1))
+
+
+def _default_rounding_run(case, T0, qx, qy, storage, rounding, steps, name):
+    """16-bit storage with its default step rounding (a fused launch rounds
+    only its last two steps): the oracle within the kind's bound, and the
+    readouts consistent with the launches: the moments read at step 19 (a
+    call ending on a fused launch that ends on the snapshot step, rebuilt by
+    replaying that launch without its last step) and at 20 (after the lone
+    check step) give the residual the check step formed from its snapshot."""
+    kmax = _fuse_max(storage)
+    out = _fused_run(case, T0, qx, qy, storage, rounding, kmax, steps, 10)
+    e = eps(case, out[-1][0][:3], oracle_fields(case, sum(steps), T0, qx, qy))
+    ends = list(np.cumsum(steps))
+    m19, m20 = out[ends.index(19)][0][:3], out[ends.index(20)][0]
+    r = _residual(m20[:3], m19)
+    log(f"fused {name}, rounding the last two steps of {kmax}: eps={e}, residual {m20[3]['residual']:.6e} "
+        f"from readouts {r:.6e}")
+    assert max(e) < TOL_STORAGE[storage]
+    assert m20[3]["step"] == 20 and m20[3]["residual"] == pytest.approx(r, rel=1e-3)
+
+
 @pytest.mark.parametrize("name,kw,storage,rounding", FUSION_CASES, ids=[c[0] for c in FUSION_CASES])
 def test_fused_kernel_bitwise(name, kw, storage, rounding):
     """The fused (temporally blocked) kernel gives the same bits as single
-    steps: storage kinds and roundings, every boundary kind, corners, check
-    steps every 10 (a fused launch may end on the check step, forming its
-    residual and totals in registers, or on the snapshot step before one),
-    calls that end on a fused launch of every length (the moments of the
-    final state then come from a replay of the launch's earlier steps), on a
-    check step and on the snapshot step, every number of steps per launch up
-    to the kind's most, and the per-instance and graph schedules.  The check
-    records agree to the order of summation."""
+    steps (16-bit storage rounding every step): storage kinds and roundings,
+    every boundary kind, corners, check steps every 10 (a fused launch may end
+    on the check step, forming its residual and totals in registers, or on
+    the snapshot step before one), calls that end on a fused launch of every
+    length (the moments of the final state then come from a replay of the
+    launch's earlier steps), on a check step and on the snapshot step, every
+    number of steps per launch up to the most, and the per-instance and graph
+    schedules.  The check records agree to the order of summation.  16-bit
+    storage with its default step rounding: see _default_rounding_run."""
     case, T0, qx, qy = _random_case(131, 37, 0.6, 7.0, 51, **kw)
     steps = FUSION_STEPS
-    ref_out = _fused_run(case, T0, qx, qy, storage, rounding, 1, steps, 10)
-    kmax = _fuse_max(storage)
+    every = storage != "f32"
+    ref_out = _fused_run(case, T0, qx, qy, storage, rounding, 1, steps, 10, every_step=every)
+    kmax = _fuse_max(storage, every)
     runs = [(k, None) for k in range(2, kmax + 1)] + [(kmax, "per_instance"), (kmax, "graph")]
     for fuse, sched in runs:
-        got = _fused_run(case, T0, qx, qy, storage, rounding, fuse, steps, 10, sched)
+        got = _fused_run(case, T0, qx, qy, storage, rounding, fuse, steps, 10, sched, every_step=every)
         for a_list, b_list in zip(got, ref_out):
             for a, b in zip(a_list[0][:3], b_list[0][:3]):
                 assert np.array_equal(a, b), (name, fuse, sched)
@@ -508,6 +541,8 @@ def test_fused_kernel_bitwise(name, kw, storage, rounding):
     e = eps(case, ref_out[-1][0][:3], oracle_fields(case, sum(steps), T0, qx, qy))
     log(f"fused {name}: up to {kmax} steps per launch, eps={e}")
     assert max(e) < TOL_STORAGE[storage]
+    if every:
+        _default_rounding_run(case, T0, qx, qy, storage, rounding, steps, name)
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16_split"])
@@ -515,14 +550,16 @@ def test_readout_keeps_the_last_steps_wall_flux(storage):
     """A heat-flux change applies to the steps issued after it; the moments of
     the current time keep the wall flux its last step ran with, also when the
     last launch was fused (its earlier steps are replayed for the readout):
-    fused and single-step runs agree bit for bit, and with the oracle read
-    before the change."""
+    fused and single-step runs agree bit for bit (16-bit storage rounding
+    every step), and with the oracle read before the change (also 16-bit
+    storage with its default step rounding)."""
     kw = dict(bc_y="heatflux", q_wall=(0, 0, 1e-3, -4e-4))
     case, T0, qx, qy = _random_case(131, 37, 0.6, 7.0, 53, **kw)
     plan = [(7, 2e-3), (11, -1e-3), (5, 5e-4), (6, 0.0)]
     outs = []
-    for fuse in (1, None):
-        lat = Lattice([instance_from_case(case)], storage=storage, check_interval=10)
+    every = storage != "f32"
+    for fuse, ev in ((1, every), (_fuse_max(storage, every), every), (_fuse_max(storage), False)):
+        lat = Lattice([instance_from_case(case)], storage=storage, check_interval=10, every_step=ev)
         if fuse:
             lat.set_step_fusion(fuse)
         lat.init(0, T0, qx, qy)
@@ -535,46 +572,55 @@ def test_readout_keeps_the_last_steps_wall_flux(storage):
             got.append(lat.moments(0))
         lat.close()
         outs.append(got)
-    for a, b in zip(*outs):
+    for a, b in zip(outs[0], outs[1]):
         for u, v in zip(a, b):
             assert np.array_equal(u, v), storage
     o = ref.Oracle(case, T0, qx, qy)
     o.set_wall_flux(2, case.q_wall[2])
     o.set_wall_flux(3, case.q_wall[3])
-    for (n, q), g in zip(plan, outs[1]):
+    for (n, q), g, gd in zip(plan, outs[1], outs[2]):
         o.run(n)
         T, qxo, qyo = o.moments()
         e = eps(case, g, (T - case.t0, qxo, qyo))
+        ed = eps(case, gd, (T - case.t0, qxo, qyo))
         o.set_wall_flux(2, q)
-        log(f"wall flux switched after the step, {storage}: eps={e}")
-        assert max(e) < TOL_STORAGE[storage]
+        log(f"wall flux switched after the step, {storage}: eps={e} (default step rounding {ed})")
+        assert max(e) < TOL_STORAGE[storage] and max(ed) < TOL_STORAGE[storage]
 
 
 @pytest.mark.parametrize("storage", ["f32", "bf16", "f16_split"])
-@pytest.mark.parametrize("nx,ny", [(2, 2), (3, 2), (5, 3), (51, 13), (57, 14), (100, 13), (101, 25),
-                                   (99, 20), (112, 31), (70, 33), (113, 65), (111, 34)])
+@pytest.mark.parametrize("nx,ny", [(2, 2), (3, 2), (5, 3), (51, 13), (53, 14), (100, 13), (101, 25),
+                                   (99, 20), (104, 31), (70, 33), (105, 65), (103, 34)])
 def test_fused_kernel_small_and_ragged(nx, ny, storage):
     """Strips wider than the lattice (the window wraps several times), and
-    lattices on a strip edge (50 output columns for FP32, 56 for the 16-bit
-    kinds: 100 = 2 x 50, 112 = 2 x 56) or one node past one (51, 57, 101,
-    113) or one short (99, 111), and one row past a 32-row marching chunk or
+    lattices on a strip edge (50 output columns for FP32, 52 for the 16-bit
+    kinds: 100 = 2 x 50, 104 = 2 x 52) or one node past one (51, 53, 101,
+    105) or one short (99, 103), and one row past a 32-row marching chunk or
     two (33, 65): same bits as single steps for two and for the most steps per
-    launch, and the oracle."""
+    launch (16-bit storage rounding every step), and the oracle (also 16-bit
+    storage with its default step rounding, up to six steps per launch)."""
     case, T0, qx, qy = _random_case(nx, ny, 0.8, 8.0, nx * 7 + ny)
-    # fused launches of every length up to the most (seven FP32, four 16-bit), and singles
+    every = storage != "f32"
+    # fused launches of every length up to the most, and singles
     steps = (5, 8, 7) if storage == "f32" else (5, 8)
-    a = _fused_run(case, T0, qx, qy, storage, "nearest", 1, steps, 0)
-    for fuse in sorted({2, _fuse_max(storage)}):
-        b = _fused_run(case, T0, qx, qy, storage, "nearest", fuse, steps, 0)
+    a = _fused_run(case, T0, qx, qy, storage, "nearest", 1, steps, 0, every_step=every)
+    for fuse in sorted({2, _fuse_max(storage, every)}):
+        b = _fused_run(case, T0, qx, qy, storage, "nearest", fuse, steps, 0, every_step=every)
         for ra, rb in zip(a, b):
             for u, v in zip(ra[0][:3], rb[0][:3]):
                 assert np.array_equal(u, v), (nx, ny, storage, fuse)
-    e = eps(case, a[-1][0][:3], oracle_fields(case, sum(steps), T0, qx, qy))
+    ora = oracle_fields(case, sum(steps), T0, qx, qy)
+    e = eps(case, a[-1][0][:3], ora)
     # plain BF16 misses the 16-bit bound on these rough states, most on the
     # smallest lattices (measured 1.6e-2 .. 2.6e-2 for 2 x 2 .. 5 x 3): 3e-2
     tol = 3e-2 if storage == "bf16" else TOL_STORAGE[storage]
     log(f"fused small {nx}x{ny} {storage}: eps={e}")
     assert max(e) < tol
+    if every:
+        c = _fused_run(case, T0, qx, qy, storage, "nearest", _fuse_max(storage), steps, 0)
+        ed = eps(case, c[-1][0][:3], ora)
+        log(f"fused small {nx}x{ny} {storage}, default step rounding: eps={ed}")
+        assert max(ed) < tol
 
 
 def test_autotune_choices_cache_and_results(tmp_path, monkeypatch):

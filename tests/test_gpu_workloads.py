@@ -43,13 +43,13 @@ TOL16 = 5e-3
 # plain 16-bit kinds that miss the 16-bit bound on a workload: the measured
 # (eps_T, eps_q) of the fixed-seed run; None where the bound is met
 MISSES = {
-    ("second_sound", "bf16", "stochastic"): (None, 2.835e-2),
-    ("second_sound", "f16", "nearest"): (1.645e-2, 3.106e-2),
-    ("second_sound", "bf16", "nearest"): (1.140e-1, 3.089e-1),
-    ("smooth_modes", "f16", "stochastic"): (None, 1.045e-2),
-    ("smooth_modes", "bf16", "stochastic"): (None, 8.322e-2),
-    ("smooth_modes", "f16", "nearest"): (8.822e-3, 1.749e-2),
-    ("smooth_modes", "bf16", "nearest"): (2.921e-2, 1.264e-1),
+    ("second_sound", "bf16", "stochastic"): (None, 2.056e-2),
+    ("second_sound", "f16", "nearest"): (None, 6.178e-3),
+    ("second_sound", "bf16", "nearest"): (2.255e-2, 7.000e-2),
+    ("smooth_modes", "f16", "stochastic"): (None, 8.356e-3),
+    ("smooth_modes", "bf16", "stochastic"): (None, 6.670e-2),
+    ("smooth_modes", "f16", "nearest"): (None, 6.506e-3),
+    ("smooth_modes", "bf16", "nearest"): (6.006e-3, 5.323e-2),
 }
 BAND = (0.8, 1.25)
 # per-node maximum error over the field's maximum magnitude: FP32 storage
