@@ -166,14 +166,14 @@ typedef struct {
 /* 16-bit storage: round every time step of a fused launch to the storage
  * type, as a stored step is, so that the populations do not depend on how
  * the steps are grouped into launches (the same bits as single steps).
- * Without it a fused launch of k >= 3 steps keeps the results of its first
- * k - 2 steps in FP32 registers and rounds only the last two (the state it
- * stores and the one before it, from which readouts rebuild time n): the
- * stored state carries two roundings to 16 bits per launch instead of k,
- * which makes the 16-bit kinds faster (six steps per launch instead of four)
- * and more accurate, and the results depend on the launch plan (the steps
- * per launch, the check interval and where lbm_step calls end).  No effect
- * on FP32 storage, whose rounding is its arithmetic. */
+ * Without it a fused launch keeps the results of all but its last step in
+ * FP32 registers and rounds only the state it stores: one rounding to 16 bits
+ * per launch instead of k, which makes the 16-bit kinds faster (six steps per
+ * launch instead of four) and more accurate, and the results depend on the
+ * launch plan (the steps per launch, the check interval and where lbm_step
+ * calls end).  Readouts after such a launch replay it in full up to the FP64
+ * moments of its last step, so they match what the launch computed.  No
+ * effect on FP32 storage, whose rounding is its arithmetic. */
 #define LBM_FLAG_ROUND_EVERY_STEP 0x4
 
 /* Version string of the library. */
@@ -185,8 +185,10 @@ const char* lbm_version(void);
 const char* lbm_last_error(lbm_handle h);
 
 /* Device bytes a handle of this configuration needs (the two population
- * buffers and a third one that readouts rebuild the last time step in, the
- * residual snapshot, reduction partials, tables). */
+ * buffers and a third region that readouts rebuild the last time step in: a
+ * population buffer, or for 16-bit storage without LBM_FLAG_ROUND_EVERY_STEP
+ * at least 24 bytes per node of FP64 moments; the residual snapshot,
+ * reduction partials, tables). */
 int lbm_required_bytes(const lbm_config* cfg, size_t* bytes);
 
 /* Validate cfg, compute per-instance coefficients (Eqs. 49, 54, 16) and the
@@ -306,15 +308,15 @@ int lbm_set_wall_flux(lbm_handle h, int32_t inst, int32_t wall, double q0);
 
 /* Most time steps per launch where allowed (temporal blocking, Eq. 13 applied
  * k times to a tile before its populations go back to HBM; the intermediate
- * states are rounded as stored steps are, for 16-bit storage only the last
- * one unless LBM_FLAG_ROUND_EVERY_STEP): a run of k >= 2 steps is advanced by
- * one launch; a run ends at the latest on a check step (whose residual and
+ * states are rounded as stored steps are, with 16-bit storage only under
+ * LBM_FLAG_ROUND_EVERY_STEP): a run of k >= 2 steps is advanced by one
+ * launch; a run ends at the latest on a check step (whose residual and
  * totals the launch forms) or on the last step of an lbm_step call; 1 issues
  * every step on its own.  Moments read after a call that ended on such a run
- * are rebuilt by replaying its earlier steps once (the same bits as the
- * launch's own state of its last step but one).  With FP32 storage or that
- * flag the populations are identical for every setting and the check-step
- * residual and totals agree to the order of their FP64 summation.  The most
+ * are rebuilt by replaying it once (the same bits as the launch itself).
+ * With FP32 storage or that flag the populations are identical for every
+ * setting and the check-step residual and totals agree to the order of their
+ * FP64 summation.  The most
  * steps per launch depends on the storage kind (7 FP32, 6 for the 16-bit
  * kinds, 4 for 16-bit handles with LBM_FLAG_ROUND_EVERY_STEP:
  * lbm_max_step_fusion gives the kind's most).  Default

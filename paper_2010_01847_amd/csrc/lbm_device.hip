@@ -879,6 +879,48 @@ hipError_t launch_moments(int storage, const InstDesc* d_desc, const RefState* d
     return hipGetLastError();
 }
 
+// Moments of one instance from FP64 (dT, qx, qy) planes indexed like the
+// snapshot (node_off + y nx + x, `stride` between the planes), written in the
+// form moments_kernel writes them; the partials carry s E as dT C_V.
+__global__ __launch_bounds__(256) void plane_moments_kernel(const InstDesc* __restrict__ descs, int inst,
+                                                            const double* __restrict__ planes, int64_t stride,
+                                                            int out_kind, void* T, void* qx, void* qy, double t0,
+                                                            double grad, DD* partials) {
+    const InstDesc& d = descs[inst];
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    const int y = blockIdx.y;
+    const int nx = d.nx;
+    DD acc[kPartials] = {dd_zero(), dd_zero(), dd_zero(), dd_zero(), dd_zero()};
+    if (x < nx) {
+        const int64_t n = (int64_t)y * nx + x;
+        const int64_t m = d.node_off + n;
+        const double dT = planes[m], vx = planes[m + stride], vy = planes[m + 2 * stride];
+        if (out_kind == 0) {
+            const double tref = t0 - grad * (double)x;
+            if (T) reinterpret_cast<float*>(T)[n] = (float)(tref + dT);
+            if (qx) reinterpret_cast<float*>(qx)[n] = (float)vx;
+            if (qy) reinterpret_cast<float*>(qy)[n] = (float)vy;
+        } else {
+            if (T) reinterpret_cast<double*>(T)[n] = dT;
+            if (qx) reinterpret_cast<double*>(qx)[n] = vx;
+            if (qy) reinterpret_cast<double*>(qy)[n] = vy;
+        }
+        acc[0].hi = dT * d.cv;
+        acc[1].hi = vx;
+        acc[2].hi = vy;
+    }
+    if (partials) block_partials(acc, partials + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * kPartials);
+}
+
+hipError_t launch_plane_moments(const InstDesc* d_desc, int inst, const InstDesc& h, const double* planes,
+                                int64_t stride, int out_kind, void* T, void* qx, void* qy, double t0, double grad,
+                                DD* partials, hipStream_t st) {
+    dim3 grid((h.nx + 255) / 256, h.ny), block(256);
+    hipLaunchKernelGGL(plane_moments_kernel, grid, block, 0, st, d_desc, inst, planes, stride, out_kind, T, qx,
+                       qy, t0, grad, partials);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ several steps per launch
 //
 // Helpers of the fused kernel below: positions mapped to their periodic
@@ -966,9 +1008,9 @@ __device__ __forceinline__ bool on_wall(const InstDesc& d, int x, int y) {
 // arithmetic is the single-step kernels' (same functions, same order, same
 // random bits).  RM (FusedRounding) says which levels are rounded exactly as a
 // stored step: all of them (kRoundEvery, then the result equals K single steps
-// bit for bit), or for 16-bit storage only the last two or the last, the
-// others keeping the FP32 result of the relaxation: the state a 16-bit
-// launch leaves in HBM then carries two roundings to 16 bits, not K.
+// bit for bit), or for 16-bit storage only the last (kRoundLast), the others
+// keeping the FP32 result of the relaxation: the state a 16-bit launch leaves
+// in HBM then carries one rounding to 16 bits, not K.
 
 // Directions by c_y: -1 {3, 6, 7}, 0 {0, 2}, +1 {1, 4, 5}.
 __device__ __forceinline__ constexpr int ymid(int k) { return 2 * k; }
@@ -1009,7 +1051,10 @@ __device__ __forceinline__ void march_gather(const float dn_row[8], const float 
 //              output node, the check-step sums (energy, heat flux, squared
 //              change and squared size of m = (dT, qx, qy)); each wavefront
 //              writes its five FP64 sums to a.partials at its tile index.  No
-//              snapshot goes through HBM.
+//              snapshot goes through HBM;
+//   kEndMoments: (readouts of 16-bit storage, kRoundLast) stage K writes the
+//              FP64 moments of its pulled nodes as kEndSnap does and stores
+//              no populations.
 // CH: chunked layout, whose direction runs are kChunkPlane elements apart, so
 // that the eight loads or stores of a row share one address and differ by
 // immediate offsets.
@@ -1027,7 +1072,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MarchWaves<
 void march_kernel(StepArgs a, int xcd, int nontemporal, int64_t snap_stride) {
     static_assert(K >= 2 && K <= KMAX, "stages per launch");
     static_assert(RM == kRoundEvery || sizeof(S) == 2, "FP32 storage rounds every step");
-    static_assert(RM != kRoundLast || END == kEndPlain, "the replay variant ends plain");
+    static_assert(END != kEndMoments || RM == kRoundLast, "the readout replay rounds the last step only");
     // input rows loaded ahead: one iteration's stages must cover a row load's
     // latency, so launches of few plain steps load further ahead (8 VGPRs per
     // FP32 row).  Measured on MI355X (8192^2, us per launch, ahead 1 / more):
@@ -1137,10 +1182,9 @@ void march_kernel(StepArgs a, int xcd, int nontemporal, int64_t snap_stride) {
                             node_moments_f64(g, d, q_ref, E, pm_new[0], pm_new[1], pm_new[2]);
                         }
                     }
-                    // 16-bit storage: steps that RM does not round keep their
-                    // result in FP32 (round to nearest), as FP32 storage would
-                    const bool keep = RM == kRoundLast || (RM == kRoundLast2 && s < K - 1);
-                    if (keep) {
+                    // 16-bit storage, kRoundLast: the result stays in FP32
+                    // (round to nearest), as FP32 storage would keep it
+                    if (RM == kRoundLast) {
                         relax(g, d, rv);
 #pragma unroll
                         for (int i = 0; i < 8; ++i) out[i] = g[i];
@@ -1158,7 +1202,7 @@ void march_kernel(StepArgs a, int xcd, int nontemporal, int64_t snap_stride) {
                     const int ox = x0 + lane - KMAX, oy = yi - s;
                     if (lane >= KMAX && lane < KMAX + W && ox < nx) {
                         if (on_wall(d, ox, oy)) boundary(g, d, rv.wall_kd, ox, oy);
-                        if constexpr (END == kEndSnap) {
+                        if constexpr (END == kEndSnap || END == kEndMoments) {
                             double E, dT, qx, qy;
                             node_moments_f64(g, d, q_ref, E, dT, qx, qy);
                             const int64_t n = d.node_off + (int64_t)oy * nx + ox;
@@ -1173,19 +1217,22 @@ void march_kernel(StepArgs a, int xcd, int nontemporal, int64_t snap_stride) {
                             const double p0 = pm_old[0], p1 = pm_old[1], p2 = pm_old[2];
                             check_sums(acc, d.s * E, qx, qy, dT, p0, p1, p2);
                         }
-                        uint32_t r[4] = {0u, 0u, 0u, 0u};
-                        if (SR)
-                            sr_words(r, colw,
-                                     sr_row_word((uint32_t)(d.node_off + (int64_t)oy * nx), step + (uint32_t)(s - 1), a.seed));
-                        S o[8];
-                        float E;
-                        relax_round<S, SR, SPLIT>(g, d, rv, r, o, E);
-                        S* row = dst + (int64_t)oy * d.row;
-                        const int64_t c = col_off(d, ox);
+                        if constexpr (END != kEndMoments) {
+                            uint32_t r[4] = {0u, 0u, 0u, 0u};
+                            if (SR)
+                                sr_words(r, colw, sr_row_word((uint32_t)(d.node_off + (int64_t)oy * nx),
+                                                              step + (uint32_t)(s - 1), a.seed));
+                            S o[8];
+                            float E;
+                            relax_round<S, SR, SPLIT>(g, d, rv, r, o, E);
+                            S* row = dst + (int64_t)oy * d.row;
+                            const int64_t c = col_off(d, ox);
 #pragma unroll
-                        for (int i = 0; i < 8; ++i)
-                            store_raw<S>(reinterpret_cast<char*>(row + c + (int64_t)i * plane), o[i], nontemporal);
-                        if (SPLIT) store_one<float, 0>(reinterpret_cast<char*>(row) + e_off(d, ox), E, 0u, nontemporal);
+                            for (int i = 0; i < 8; ++i)
+                                store_raw<S>(reinterpret_cast<char*>(row + c + (int64_t)i * plane), o[i], nontemporal);
+                            if (SPLIT)
+                                store_one<float, 0>(reinterpret_cast<char*>(row) + e_off(d, ox), E, 0u, nontemporal);
+                        }
                     }
                 }
             }
@@ -1238,14 +1285,11 @@ static void launch_march_ch(const Shape& sh, const StepArgs& a, int chunked, int
 template <class S, int SR, int SPLIT, int K, int KMAX, int RM>
 static void launch_march_e(const Shape& sh, const StepArgs& a, int end, int chunked, int64_t snap_stride,
                            hipStream_t st) {
-    if constexpr (RM == kRoundLast) {
-        launch_march_ch<S, SR, SPLIT, K, KMAX, kEndPlain, RM>(sh, a, chunked, snap_stride, st);
-    } else {
-        if (end == kEndSnap) launch_march_ch<S, SR, SPLIT, K, KMAX, kEndSnap, RM>(sh, a, chunked, snap_stride, st);
-        else if (end == kEndCheck)
-            launch_march_ch<S, SR, SPLIT, K, KMAX, kEndCheck, RM>(sh, a, chunked, snap_stride, st);
-        else launch_march_ch<S, SR, SPLIT, K, KMAX, kEndPlain, RM>(sh, a, chunked, snap_stride, st);
-    }
+    if (end == kEndSnap) launch_march_ch<S, SR, SPLIT, K, KMAX, kEndSnap, RM>(sh, a, chunked, snap_stride, st);
+    else if (end == kEndCheck) launch_march_ch<S, SR, SPLIT, K, KMAX, kEndCheck, RM>(sh, a, chunked, snap_stride, st);
+    else if (end == kEndPlain) launch_march_ch<S, SR, SPLIT, K, KMAX, kEndPlain, RM>(sh, a, chunked, snap_stride, st);
+    else if constexpr (RM == kRoundLast)
+        launch_march_ch<S, SR, SPLIT, K, KMAX, kEndMoments, RM>(sh, a, chunked, snap_stride, st);
 }
 
 template <class S, int SPLIT, int K, int KMAX, int RM>
@@ -1256,15 +1300,12 @@ static hipError_t launch_march_s(const Shape& sh, const StepArgs& a, int end, in
     return hipGetLastError();
 }
 
-// The variant's rounding for k = K (a 16-bit kRoundLast2 launch of two steps
-// rounds both, which is kRoundEvery's kernel); -1 where none is built.
+// Whether a variant of k = K steps, step rounding rm and end is built.
 template <class S, int K>
-constexpr int march_rounding(int rm, int end) {
-    if (sizeof(S) == 4) return rm == kRoundEvery ? kRoundEvery : -1;
-    if (rm == kRoundLast2) return K == 2 ? kRoundEvery : kRoundLast2;
-    if (rm == kRoundLast) return end == kEndPlain ? kRoundLast : -1;
-    if (rm == kRoundEvery) return K <= kFuseEveryStep ? kRoundEvery : -1;
-    return -1;
+constexpr bool march_built(int rm, int end) {
+    if (rm == kRoundLast) return sizeof(S) == 2;
+    if (rm != kRoundEvery || end == kEndMoments) return false;
+    return sizeof(S) == 4 || K <= kFuseEveryStep;
 }
 
 template <class S, int SPLIT, int K, int KMAX>
@@ -1274,26 +1315,23 @@ static hipError_t launch_march_k(const Shape& sh, const StepArgs& a, int k, int 
         return hipErrorInvalidValue;
     } else {
         if (k != K) return launch_march_k<S, SPLIT, K + 1, KMAX>(sh, a, k, end, chunked, rm, snap_stride, st);
-        const int r = march_rounding<S, K>(rm, end);
-        if (r == kRoundEvery) {
-            if constexpr (sizeof(S) == 4 || K <= kFuseEveryStep)
-                return launch_march_s<S, SPLIT, K, KMAX, kRoundEvery>(sh, a, end, chunked, snap_stride, st);
-        }
+        if (!march_built<S, K>(rm, end)) return hipErrorInvalidValue;
         if constexpr (sizeof(S) == 2) {
-            if (r == kRoundLast2) return launch_march_s<S, SPLIT, K, KMAX, kRoundLast2>(sh, a, end, chunked, snap_stride, st);
-            if (r == kRoundLast) return launch_march_s<S, SPLIT, K, KMAX, kRoundLast>(sh, a, end, chunked, snap_stride, st);
+            if (rm == kRoundLast)
+                return launch_march_s<S, SPLIT, K, KMAX, kRoundLast>(sh, a, end, chunked, snap_stride, st);
         }
+        if constexpr (sizeof(S) == 4 || K <= kFuseEveryStep)
+            return launch_march_s<S, SPLIT, K, KMAX, kRoundEvery>(sh, a, end, chunked, snap_stride, st);
         return hipErrorInvalidValue;
     }
 }
 
 // Launch every fused-kernel variant a handle may use (its storage kind,
-// rounding, layout and step rounding; 2 .. fuse_max steps; plain, snapshot and
-// check ends) once with no tiles: each wavefront returns at its first test,
-// touching no memory.  The runtime does its once-per-kernel work (loading the
-// code; for a kernel that spills, setting up scratch memory) at a kernel's
-// first launch, which would otherwise land in the first real launch of each
-// variant.
+// rounding, layout and step rounding; 2 .. fuse_max steps; each end) once with
+// no tiles: each wavefront returns at its first test, touching no memory.
+// The runtime does its once-per-kernel work (loading the code; for a kernel
+// that spills, setting up scratch memory) at a kernel's first launch, which
+// would otherwise land in the first real launch of each variant.
 template <class S, int SR, int SPLIT, int K, int KMAX, int END, int RM>
 static hipError_t preload_one(int chunked, hipStream_t st) {
     StepArgs a{};
@@ -1306,33 +1344,28 @@ static hipError_t preload_one(int chunked, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <class S, int SR, int SPLIT, int K, int KMAX, int RM>
+static hipError_t preload_ends(int chunked, hipStream_t st) {
+    hipError_t e = preload_one<S, SR, SPLIT, K, KMAX, kEndPlain, RM>(chunked, st);
+    if (e == hipSuccess) e = preload_one<S, SR, SPLIT, K, KMAX, kEndSnap, RM>(chunked, st);
+    if (e == hipSuccess) e = preload_one<S, SR, SPLIT, K, KMAX, kEndCheck, RM>(chunked, st);
+    if constexpr (RM == kRoundLast) {
+        if (e == hipSuccess) e = preload_one<S, SR, SPLIT, K, KMAX, kEndMoments, RM>(chunked, st);
+    }
+    return e;
+}
+
 template <class S, int SR, int SPLIT, int K, int KMAX>
 static hipError_t preload_march_k(int chunked, int every_step, hipStream_t st) {
     if constexpr (K > KMAX) {
         return hipSuccess;
     } else {
         hipError_t e = hipSuccess;
-        for (int end = kEndPlain; end <= kEndCheck && e == hipSuccess; ++end) {
-            const int r = march_rounding<S, K>(every_step || sizeof(S) == 4 ? kRoundEvery : kRoundLast2, end);
-            if constexpr (sizeof(S) == 4 || K <= kFuseEveryStep) {
-                if (r == kRoundEvery) {
-                    e = end == kEndPlain   ? preload_one<S, SR, SPLIT, K, KMAX, kEndPlain, kRoundEvery>(chunked, st)
-                        : end == kEndSnap ? preload_one<S, SR, SPLIT, K, KMAX, kEndSnap, kRoundEvery>(chunked, st)
-                                          : preload_one<S, SR, SPLIT, K, KMAX, kEndCheck, kRoundEvery>(chunked, st);
-                }
-            }
-            if constexpr (sizeof(S) == 2) {
-                if (r == kRoundLast2) {
-                    e = end == kEndPlain   ? preload_one<S, SR, SPLIT, K, KMAX, kEndPlain, kRoundLast2>(chunked, st)
-                        : end == kEndSnap ? preload_one<S, SR, SPLIT, K, KMAX, kEndSnap, kRoundLast2>(chunked, st)
-                                          : preload_one<S, SR, SPLIT, K, KMAX, kEndCheck, kRoundLast2>(chunked, st);
-                }
-            }
+        if constexpr (sizeof(S) == 2) {
+            if (!every_step) e = preload_ends<S, SR, SPLIT, K, KMAX, kRoundLast>(chunked, st);
         }
-        // the readout replay of a 16-bit handle (a launch without its last step)
-        if constexpr (sizeof(S) == 2 && K < KMAX) {
-            if (e == hipSuccess && !every_step)
-                e = preload_one<S, SR, SPLIT, K, KMAX, kEndPlain, kRoundLast>(chunked, st);
+        if constexpr (sizeof(S) == 4 || K <= kFuseEveryStep) {
+            if (every_step || sizeof(S) == 4) e = preload_ends<S, SR, SPLIT, K, KMAX, kRoundEvery>(chunked, st);
         }
         if (e != hipSuccess) return e;
         return preload_march_k<S, SR, SPLIT, K + 1, KMAX>(chunked, every_step, st);
@@ -1365,9 +1398,9 @@ static hipError_t launch_fused_s(const Shape& sh, const StepArgs& a, int k, int 
 hipError_t launch_fused(int storage, const Shape& sh, const StepArgs& a, int k, int end, int chunked,
                         int rounding, int64_t snap_stride, hipStream_t st) {
     if (a.ntiles <= 0) return hipSuccess;
-    if (end == kEndSnap && !a.snap) return hipErrorInvalidValue;
+    if ((end == kEndSnap || end == kEndMoments) && !a.snap) return hipErrorInvalidValue;
     if (end == kEndCheck && !a.partials) return hipErrorInvalidValue;
-    if (end < kEndPlain || end > kEndCheck) return hipErrorInvalidValue;
+    if (end < kEndPlain || end > kEndMoments) return hipErrorInvalidValue;
     switch (storage) {
         case 0: return launch_fused_s<float, 0, 0>(sh, a, k, end, chunked, rounding, snap_stride, st);
         case 1: return launch_fused_s<_Float16, 0, 1>(sh, a, k, end, chunked, rounding, snap_stride, st);

@@ -125,9 +125,11 @@ struct Shape {
 
 enum StepMode { kPlain = 0, kSnap = 1, kCheck = 2 };
 // How a fused launch ends (see march_kernel): plain steps only, on the
-// snapshot step (FP64 moments written to the snapshot), or on the check step
-// (the snapshot kept in registers, per-tile check sums written).
-enum FusedEnd { kEndPlain = 0, kEndSnap = 1, kEndCheck = 2 };
+// snapshot step (FP64 moments written to the snapshot), on the check step
+// (the snapshot kept in registers, per-tile check sums written), or, for the
+// readout of 16-bit storage, with the FP64 moments of its last step's pulled
+// nodes written to a.snap and no populations stored.
+enum FusedEnd { kEndPlain = 0, kEndSnap = 1, kEndCheck = 2, kEndMoments = 3 };
 
 // Fused kernel (several time steps per pass over HBM, temporal blocking): a
 // wavefront takes a strip of fused_width output columns (a window of 64
@@ -141,9 +143,8 @@ enum FusedEnd { kEndPlain = 0, kEndSnap = 1, kEndCheck = 2 };
 // 16-bit kinds it also depends on how many of a launch's steps are rounded to
 // the storage type (FusedRounding): rounding every step, four steps per
 // launch were the fastest (FP16-SR 743, F16_SPLIT 819 us per launch on
-// 8192^2); rounding the last two, six (1,085 and 1,115 us: per step 181 and
-// 186 us against 186 and 205).  Chunks of 64 or 128 rows instead of 32: FP32
-// 302 / 289 GLUPS at six steps against 315.
+// 8192^2); rounding the last one, six.  Chunks of 64 or 128 rows instead of
+// 32: FP32 302 / 289 GLUPS at six steps against 315.
 constexpr int kMarchRows = 32;
 // Elements between direction runs in the chunked layout (64-node segments).
 constexpr int kChunkPlane = 64;
@@ -155,14 +156,12 @@ __host__ __device__ constexpr int fused_width(int storage) { return 64 - 2 * fus
 // (LBM_FLAG_ROUND_EVERY_STEP).
 constexpr int kFuseEveryStep = 4;
 // Which of a fused launch's steps round their results to the storage type
-// (the others keep them in FP32 registers; FP32 storage rounds every step,
-// that being its arithmetic):
+// (FP32 storage rounds every step, that being its arithmetic):
 //   kRoundEvery: every step (the same bits as single steps);
-//   kRoundLast2: the last two (16-bit default): the state of the last step but
-//                one is the one a replay of the launch without its last step
-//                stores, so readouts rebuild it bit for bit;
-//   kRoundLast : the last only (that replay, plain end).
-enum FusedRounding { kRoundEvery = 0, kRoundLast2 = 1, kRoundLast = 2 };
+//   kRoundLast : the last one (16-bit default); the others keep the FP32
+//                result of the relaxation in registers, and readouts rebuild
+//                time n by replaying the whole launch with kEndMoments.
+enum FusedRounding { kRoundEvery = 0, kRoundLast = 1 };
 // Fewest fused-kernel strips (wavefronts) over all instances for which fused
 // launches are the default: one per SIMD of the chip.
 constexpr int64_t kFuseMinStrips = 1024;
@@ -199,7 +198,8 @@ hipError_t launch_step(int storage, const Shape& sh, int mode, const StepArgs& a
 // (FusedRounding) says which steps round to the storage type: kRoundEvery
 // (FP32 always; 16-bit k <= kFuseEveryStep) gives the same bits as k single
 // steps (the check sums equal theirs up to the order of summation);
-// kRoundLast is for plain ends only.
+// kRoundLast is 16-bit only, and the only one with kEndMoments (whose FP64
+// moments go to a.snap as kEndSnap's do).
 hipError_t launch_fused(int storage, const Shape& sh, const StepArgs& a, int k, int end, int chunked,
                         int rounding, int64_t snap_stride, hipStream_t st);
 
@@ -242,11 +242,18 @@ hipError_t launch_fill(void* buf, size_t bytes, uint32_t seed, hipStream_t st);
 // descriptor fields between steps).
 hipError_t launch_set_float(float* dst, float v, hipStream_t st);
 
+// Moments of instance `inst` from FP64 (dT, qx, qy) planes laid out as the
+// snapshot (a kEndMoments launch's output), in launch_moments' output forms
+// and partials.
+hipError_t launch_plane_moments(const InstDesc* d_desc, int inst, const InstDesc& h, const double* planes,
+                                int64_t stride, int out_kind, void* T, void* qx, void* qy, double t0, double grad,
+                                DD* partials, hipStream_t st);
+
 // Launch every fused-kernel variant of a storage kind, rounding (sr), layout
-// and step rounding (every_step != 0: kRoundEvery only; else the kinds'
-// defaults and the readout replay's kRoundLast) once with no tiles (no memory
-// is touched), so that the runtime's first-launch work is done before the
-// first real launch.
+// and step rounding (every_step != 0 or FP32: kRoundEvery; else kRoundLast,
+// with the readout's kEndMoments) once with no tiles (no memory is touched),
+// so that the runtime's first-launch work is done before the first real
+// launch.
 hipError_t preload_fused(int storage, int sr, int chunked, int every_step, hipStream_t st);
 
 // Copy n <= 64 32-bit words on the device (a kernel, so that it can sit in a

@@ -106,20 +106,20 @@ Geometry geometry_of(const lbm_instance& in, int es, int layout, bool split = fa
 // matters: 20 FP32 steps cost 3522 us as 7 + 7 + 6 and 4372 us as 5 + 5 + 5 +
 // 5.  The check variants of five, six and seven FP32 steps need 131, 145 and
 // 159 VGPRs (three waves per SIMD instead of four).  16-bit kinds: rounding
-// every step (every_step) or the last two of a launch (FusedRounding).
+// every step (every_step) or only the last of a launch (FusedRounding).
 // lbm_autotune replaces the plain figures by its own timings on the handle's
 // lattices and scales the check figures.
 static void default_costs(int storage, int every_step, double plain[8], double check[8]) {
     static const double p_tab[5][8] = {{0, 737, 1214, 1208, 1237, 1093, 1098, 1212},   // F32
-                                       {0, 499, 625, 631, 734, 930, 1085, 0},          // F16
-                                       {0, 489, 629, 635, 734, 930, 1075, 0},          // BF16
-                                       {0, 489, 733, 740, 783, 979, 1115, 0},          // F16_SPLIT
-                                       {0, 486, 743, 746, 801, 990, 1130, 0}};         // BF16_SPLIT
+                                       {0, 497, 572, 600, 680, 870, 1022, 0},          // F16
+                                       {0, 480, 573, 601, 753, 898, 1026, 0},          // BF16
+                                       {0, 486, 733, 743, 752, 924, 1058, 0},          // F16_SPLIT
+                                       {0, 483, 733, 745, 751, 925, 1062, 0}};         // BF16_SPLIT
     static const double c_tab[5][8] = {{0, 0, 1216, 1095, 1095, 1217, 1360, 1558},
-                                       {0, 0, 692, 842, 953, 1242, 1407, 0},
-                                       {0, 0, 740, 883, 1010, 1257, 1424, 0},
-                                       {0, 0, 762, 877, 998, 1278, 1447, 0},
-                                       {0, 0, 787, 887, 1012, 1292, 1466, 0}};
+                                       {0, 0, 640, 776, 897, 1174, 1329, 0},
+                                       {0, 0, 716, 824, 1029, 1184, 1364, 0},
+                                       {0, 0, 749, 813, 935, 1207, 1377, 0},
+                                       {0, 0, 754, 823, 939, 1215, 1390, 0}};
     // 16-bit kinds rounding every step (kFuseEveryStep = 4 at most)
     static const double pe_tab[5][5] = {{0, 0, 0, 0, 0},
                                         {0, 496, 604, 600, 743},
@@ -255,7 +255,15 @@ struct Layout {
     int64_t nodes = 0, tiles_max = 0, mparts_max = 0, groups_max = 0, ptiles = 0, pgroups = 0;
 };
 
-Layout layout_of(const std::vector<lbm_instance>& v, int storage, int check, int layout) {
+// Fused launches round every step: FP32 storage, or LBM_FLAG_ROUND_EVERY_STEP.
+static int every_step_of(const lbm_config* cfg) {
+    return (cfg->storage == LBM_F32 || (cfg->flags & LBM_FLAG_ROUND_EVERY_STEP)) ? 1 : 0;
+}
+
+// every_step: fused launches round every step (FP32, or 16-bit with
+// LBM_FLAG_ROUND_EVERY_STEP); otherwise the readout buffer holds FP64 moment
+// planes (see replay_tail) and is sized for them as well.
+Layout layout_of(const std::vector<lbm_instance>& v, int storage, int check, int layout, int every_step) {
     Layout L;
     const int es = esize_of(storage);
     size_t elems = 0;
@@ -281,7 +289,7 @@ Layout layout_of(const std::vector<lbm_instance>& v, int storage, int check, int
     size_t o = 0;
     L.off_buf[0] = o; o += L.buf_bytes;
     L.off_buf[1] = o; o += L.buf_bytes;
-    L.off_buf[2] = o; o += L.buf_bytes;
+    L.off_buf[2] = o; o += every_step ? L.buf_bytes : std::max(L.buf_bytes, align_up(3 * (size_t)L.nodes * sizeof(double), kAlign));
     L.off_snap = o; o += check ? align_up(3 * (size_t)L.nodes * sizeof(double), kAlign) : 0;
     L.off_part = o; o += align_up((size_t)records * kPartials * sizeof(DD), kAlign);
     L.off_res = o; o += align_up(v.size() * kPartials * sizeof(double), kAlign);
@@ -694,7 +702,7 @@ int lbm_required_bytes(const lbm_config* cfg, size_t* bytes) {
         g_create_error = "bytes is NULL";
         return LBM_EINVAL;
     }
-    *bytes = layout_of(v, cfg->storage, check_of(cfg), resolve_layout(cfg->layout)).total;
+    *bytes = layout_of(v, cfg->storage, check_of(cfg), resolve_layout(cfg->layout), every_step_of(cfg)).total;
     return LBM_OK;
 }
 
@@ -721,7 +729,7 @@ int lbm_create(const lbm_config* cfg, lbm_handle* out) {
     h->stream = reinterpret_cast<hipStream_t>(cfg->stream);
     h->external = (cfg->flags & LBM_FLAG_EXTERNAL_MEMORY) != 0;
     h->sr = (cfg->flags & LBM_FLAG_STOCHASTIC_ROUNDING) ? 1 : 0;
-    h->every_step = (cfg->storage == LBM_F32 || (cfg->flags & LBM_FLAG_ROUND_EVERY_STEP)) ? 1 : 0;
+    h->every_step = every_step_of(cfg);
     h->seed = cfg->seed;
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) {
@@ -737,7 +745,7 @@ int lbm_create(const lbm_config* cfg, lbm_handle* out) {
     }
     const int es = esize_of(h->storage);
     h->layout = resolve_layout(cfg->layout);
-    h->L = layout_of(v, h->storage, h->K, h->layout);
+    h->L = layout_of(v, h->storage, h->K, h->layout, h->every_step);
     h->desc.resize(v.size());
     h->ref.resize(v.size());
     h->qwall.assign(v.size(), std::array<double, 4>{0.0, 0.0, 0.0, 0.0});
@@ -1100,7 +1108,7 @@ static int issue_fused(lbm_ctx* h, int64_t m, int nsteps, int end, int src_k, hi
     a.tile_base = sp.pt0;
     a.ntiles = sp.pnt;
     HIPCALL(h, launch_fused(h->storage, h->shape, a, nsteps, end, h->layout == LBM_LAYOUT_CHUNKED,
-                            h->every_step ? kRoundEvery : kRoundLast2, h->L.nodes, st));
+                            h->every_step ? kRoundEvery : kRoundLast, h->L.nodes, st));
     if (end == kEndCheck)
         HIPCALL(h, launch_finalize(h->d_desc(), h->d_pgroups(), sp.pg0, sp.png, h->d_ref(), h->d_ref_prev(), sp.i0,
                                    sp.ni, h->d_part(), h->d_gpart(), h->d_res(), 1, st));
@@ -1283,6 +1291,11 @@ int lbm_step(lbm_handle h, int64_t nsteps) {
 // n - 1 again from the launch's source buffer, with the descriptors and the
 // reference state that launch ran with and the stochastic-rounding counter it
 // started from.  Same arithmetic, so the same bits as the original steps.
+// 16-bit storage rounding only the last step of a launch (kRoundLast): that
+// launch's state of step n - 1 never existed in the storage type, so the
+// whole launch is replayed instead, ending with kEndMoments: the FP64 moments
+// of its step-n nodes go to the readout buffer (as planes laid out like the
+// snapshot), from the same registers the launch itself relaxed.
 static int replay_tail(lbm_ctx* h) {
     const lbm_ctx::Tail& t = h->tail;
     StepArgs a;
@@ -1299,11 +1312,17 @@ static int replay_tail(lbm_ctx* h) {
     a.ref = t.checked ? h->d_ref_prev() : h->d_ref();
     a.apply_shift = t.apply_shift;
     a.tile_base = 0;
-    if (t.k - 1 >= 2) {
+    if (!h->every_step) {
+        a.snap = reinterpret_cast<double*>(h->buf(lbm_ctx::kReadout));
+        a.tile_inst = h->d_ptiles();
+        a.ntiles = (int32_t)h->ptile_inst.size();
+        HIPCALL(h, launch_fused(h->storage, h->shape, a, t.k, kEndMoments, h->layout == LBM_LAYOUT_CHUNKED,
+                                kRoundLast, h->L.nodes, h->stream));
+    } else if (t.k - 1 >= 2) {
         a.tile_inst = h->d_ptiles();
         a.ntiles = (int32_t)h->ptile_inst.size();
         HIPCALL(h, launch_fused(h->storage, h->shape, a, t.k - 1, kEndPlain, h->layout == LBM_LAYOUT_CHUNKED,
-                                h->every_step ? kRoundEvery : kRoundLast, h->L.nodes, h->stream));
+                                kRoundEvery, h->L.nodes, h->stream));
     } else {
         a.tile_inst = h->d_tiles();
         a.ntiles = (int32_t)h->ntiles;
@@ -1325,6 +1344,12 @@ static int run_moments(lbm_ctx* h, int32_t k, int out_kind, void* T, void* qx, v
         if (!h->replayed) {
             int rc = replay_tail(h);
             if (rc) return rc;
+        }
+        if (!h->every_step) {
+            HIPCALL(h, launch_plane_moments(h->d_desc_last(), k, h->desc[k],
+                                            reinterpret_cast<const double*>(h->buf(lbm_ctx::kReadout)), h->L.nodes,
+                                            out_kind, T, qx, qy, in.t0, grad, partials, h->stream));
+            return LBM_OK;
         }
         src = lbm_ctx::kReadout;
     }
@@ -1658,7 +1683,7 @@ static int time_fused(lbm_ctx* h, int k, int launches, hipEvent_t e0, hipEvent_t
         a.ctr_in = h->d_ctr() + src;
         a.ctr_out = h->d_ctr() + (1 - src);
         HIPCALL(h, launch_fused(h->storage, h->shape, a, k, 0, h->layout == LBM_LAYOUT_CHUNKED,
-                                h->every_step ? kRoundEvery : kRoundLast2, 0, h->stream));
+                                h->every_step ? kRoundEvery : kRoundLast, 0, h->stream));
         src = 1 - src;
     }
     HIPCALL(h, hipEventRecord(e1, h->stream));

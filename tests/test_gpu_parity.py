@@ -432,7 +432,7 @@ def _fused_run(case, T0, qx, qy, storage, rounding, fuse, steps, check, schedule
         # the moments, and the last check step's residual and totals (whose
         # residual compares with the snapshot the step before it wrote)
         checks = [lat.last_check(k) for k in range(n_inst)] if 0 < check <= done else [None] * n_inst
-        out.append([lat.moments(k) + (checks[k],) for k in range(n_inst)])
+        out.append([lat.moments(k) + (checks[k], lat.totals(k)) for k in range(n_inst)])
     lat.close()
     return out
 
@@ -496,21 +496,28 @@ def _residual(m1, m0):
 
 def _default_rounding_run(case, T0, qx, qy, storage, rounding, steps, name):
     """16-bit storage with its default step rounding (a fused launch rounds
-    only its last two steps): the oracle within the kind's bound, and the
-    readouts consistent with the launches: the moments read at step 19 (a
-    call ending on a fused launch that ends on the snapshot step, rebuilt by
-    replaying that launch without its last step) and at 20 (after the lone
-    check step) give the residual the check step formed from its snapshot."""
+    only its last step to the storage type): the oracle within the kind's
+    bound, and the readouts consistent with the launches: the moments read at
+    step 19 (a call ending on a fused launch that ends on the snapshot step,
+    rebuilt by replaying that launch up to the moments of its last step) and
+    at 20 (after the lone check step) give the residual the check step formed
+    from the snapshot that launch wrote, and at step 10 (a call ending on a
+    fused launch that ends on the check step) the totals read out equal the
+    ones that launch formed."""
     kmax = _fuse_max(storage)
     out = _fused_run(case, T0, qx, qy, storage, rounding, kmax, steps, 10)
     e = eps(case, out[-1][0][:3], oracle_fields(case, sum(steps), T0, qx, qy))
     ends = list(np.cumsum(steps))
     m19, m20 = out[ends.index(19)][0][:3], out[ends.index(20)][0]
     r = _residual(m20[:3], m19)
-    log(f"fused {name}, rounding the last two steps of {kmax}: eps={e}, residual {m20[3]['residual']:.6e} "
+    log(f"fused {name}, rounding the last step of up to {kmax}: eps={e}, residual {m20[3]['residual']:.6e} "
         f"from readouts {r:.6e}")
     assert max(e) < TOL_STORAGE[storage]
     assert m20[3]["step"] == 20 and m20[3]["residual"] == pytest.approx(r, rel=1e-3)
+    m10 = out[ends.index(10)][0]
+    assert m10[3]["step"] == 10
+    for u, v in zip(m10[4], m10[3]["totals"]):
+        assert u == pytest.approx(v, rel=1e-9, abs=1e-12), (name, m10[4], m10[3]["totals"])
 
 
 @pytest.mark.parametrize("name,kw,storage,rounding", FUSION_CASES, ids=[c[0] for c in FUSION_CASES])

@@ -10,15 +10,18 @@ FP64 oracle.
   stepped by the oracle, and the batched / per-instance / graph schedules.
 
 Tolerances (relative L2 of the temperature deviation and of the heat flux):
-FP32 storage 1e-5; 16-bit storage 5e-3.  The split 16-bit kinds (FP32 energy,
-16-bit non-equilibrium shares) meet 5e-3 on every workload, in FP16 and BF16.
-Plain 16-bit population storage (the eight populations in 16 bits) meets it
-where stated below and otherwise misses the 16-bit bound: on these smooth
-fields the heat flux is about a hundredth of the stored populations, so its
-16-bit rounding noise is too (and round to nearest stalls the smooth field).
-Those misses are asserted as a band around the measured value (the runs are
-deterministic: fixed seeds), so that a change in either direction shows, and
-every row is also held to the per-node maximum error bound.
+FP32 storage 1e-5; 16-bit storage 5e-3.  The 16-bit runs use the library's
+default step rounding (a fused launch of six steps rounds the state it stores
+to 16 bits; its other steps stay in FP32 registers).  The split 16-bit kinds
+(FP32 energy, 16-bit non-equilibrium shares) and plain FP16 population
+storage (the eight populations in 16 bits), with either rounding, meet 5e-3
+on every workload.  Plain BF16 storage misses the 16-bit bound on the heat
+flux: on these smooth fields the heat flux is about a hundredth of the stored
+populations, so its 8-bit-mantissa rounding noise is about a hundred times
+larger relative to it.  Those misses are asserted as a band around the
+measured value (the runs are deterministic: fixed seeds), so that a change in
+either direction shows, and every row is also held to the per-node maximum
+error bound.
 
 Sampled rows of the full-size workloads sit off the 32-row marching chunks'
 first rows (offsets 17 and 31 within a chunk), where the fused kernel's
@@ -43,19 +46,16 @@ TOL16 = 5e-3
 # plain 16-bit kinds that miss the 16-bit bound on a workload: the measured
 # (eps_T, eps_q) of the fixed-seed run; None where the bound is met
 MISSES = {
-    ("second_sound", "bf16", "stochastic"): (None, 2.056e-2),
-    ("second_sound", "f16", "nearest"): (None, 6.178e-3),
-    ("second_sound", "bf16", "nearest"): (2.255e-2, 7.000e-2),
-    ("smooth_modes", "f16", "stochastic"): (None, 8.356e-3),
-    ("smooth_modes", "bf16", "stochastic"): (None, 6.670e-2),
-    ("smooth_modes", "f16", "nearest"): (None, 6.506e-3),
-    ("smooth_modes", "bf16", "nearest"): (6.006e-3, 5.323e-2),
+    ("second_sound", "bf16", "stochastic"): (None, 8.584e-3),
+    ("second_sound", "bf16", "nearest"): (None, 1.432e-2),
+    ("smooth_modes", "bf16", "stochastic"): (None, 1.859e-2),
+    ("smooth_modes", "bf16", "nearest"): (None, 1.691e-2),
 }
 BAND = (0.8, 1.25)
 # per-node maximum error over the field's maximum magnitude: FP32 storage
-# 3e-5 (measured up to 1.07e-5), split 16-bit kinds 3e-2 (measured up to
-# 8.9e-3), plain 16-bit kinds 1 (their L2 misses are bounded by BAND)
-MAXREL = {"f32": 3e-5, "f16_split": 3e-2, "bf16_split": 3e-2, "f16": 1.0, "bf16": 1.0}
+# 3e-5 (measured up to 1.07e-5), split 16-bit kinds 1e-2 (measured up to
+# 2.6e-3), FP16 3e-2 (up to 1.03e-2), BF16 0.5 (up to 0.13)
+MAXREL = {"f32": 3e-5, "f16_split": 1e-2, "bf16_split": 1e-2, "f16": 3e-2, "bf16": 0.5}
 
 
 def _rel(a, b, base):
