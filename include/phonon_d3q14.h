@@ -50,7 +50,8 @@ typedef struct lbm3d_ctx* lbm3d_handle;
 typedef struct {
     int32_t nx, ny, nz;     /* nodes per axis, >= 1 each, fewer than 2^32 nodes in all */
     int32_t storage;        /* LBM_F32, LBM_F16 or LBM_BF16 (the split kinds are D2Q8 only) */
-    int32_t flags;          /* LBM_FLAG_EXTERNAL_MEMORY, LBM_FLAG_STOCHASTIC_ROUNDING */
+    int32_t flags;          /* LBM_FLAG_EXTERNAL_MEMORY, LBM_FLAG_STOCHASTIC_ROUNDING,
+                               LBM_FLAG_ROUND_EVERY_STEP */
     int32_t layout;         /* lbm_layout: PLANES = 14 direction planes (rows padded to 64
                                nodes); CHUNKED = 64-node row segments holding their 14
                                direction runs back to back; AUTO = CHUNKED */
@@ -133,10 +134,13 @@ int lbm3d_totals(lbm3d_handle h, double out[4]);
 /* Time steps per launch: 2 advances two steps in one pass over HBM where an
  * lbm3d_step call has at least two steps left (temporal blocking: each block
  * owns 60 x 12 nodes of every plane of a z-range, marches along z, and keeps
- * the intermediate state, rounded exactly as a stored step, in LDS and
- * registers); 1 issues every step on its own.  Results are identical either
- * way.  Default: 2 when the box holds at least 256 such blocks (60 x 12 nodes
- * of 32 planes each: one per CU), else 1.  Errors: EINVAL (steps not 1 or 2). */
+ * the intermediate state in LDS and registers: rounded exactly as a stored
+ * step for FP32 storage and under LBM_FLAG_ROUND_EVERY_STEP, else in FP32);
+ * 1 issues every step on its own.  FP32 and that flag: results identical
+ * either way; 16-bit storage otherwise rounds one state per launch, so its
+ * results depend on the steps per launch (see LBM_FLAG_ROUND_EVERY_STEP).
+ * Default: 2 when the box holds at least 256 such blocks (60 x 12 nodes of 32
+ * planes each: one per CU), else 1.  Errors: EINVAL (steps not 1 or 2). */
 int lbm3d_set_step_fusion(lbm3d_handle h, int32_t steps);
 
 /* The current time steps per launch (1 or 2); -1 for an invalid handle. */

@@ -297,8 +297,11 @@ hipError_t launch_step(int storage, int sr, const StepArgs& a, hipStream_t st) {
 // each thread keeps the later ones in registers, and per iteration a single
 // LDS plane per stage holds, direction by direction, exactly the values that
 // stage pulls.  Per node and step the arithmetic is the single-step kernel's
-// (same functions, same order, same random bits), so the result equals two
-// single steps bit for bit.
+// (same functions, same order, same random bits).  RS = 1: the stage-1 results
+// are rounded exactly as a stored step and read back, so the result equals two
+// single steps bit for bit (FP32 storage always); RS = 0 (16-bit storage by
+// default): they stay in FP32, so the state a launch stores carries one
+// rounding to 16 bits, not two.
 
 // Directions by c_z: -1 (5), 0 (4), +1 (5).
 __host__ __device__ constexpr int dir_dn(int k) { return k == 0 ? 5 : 9 + k; }
@@ -310,16 +313,18 @@ __device__ __forceinline__ int wrap_mod(int v, int n) {
     return r < 0 ? r + n : r;
 }
 
-template <class S, int SR, int L, int YO, int NW>
+template <class S, int SR, int L, int YO, int NW, int RS>
 __global__ __launch_bounds__(64 * NW) void pair_kernel(PairArgs a) {
     constexpr int WR = YO + 4;                // window rows
     constexpr int NJ = (WR + NW - 1) / NW;    // window rows per wavefront (NW wavefronts)
-    // The window holds stored values (input planes, and stage-1 results rounded
-    // exactly as a stored step): in the storage type itself, so a 16-bit
-    // window takes half the LDS and its values need no conversion to be kept.
+    // The window holds stored values (input planes, and with RS stage-1 results
+    // rounded exactly as a stored step): in the storage type itself, so a
+    // 16-bit window takes half the LDS and its values need no conversion to be
+    // kept.  Without RS the stage-1 values are FP32.
     using LT = S;
+    using LB = typename std::conditional<RS || sizeof(S) == 4, S, float>::type;
     __shared__ LT lds_a[kQ][WR][64];          // stage 1 pulls (input values)
-    __shared__ LT lds_b[kQ][YO + 2][64];      // stage 2 pulls (stage-1 values, inner rows)
+    __shared__ LB lds_b[kQ][YO + 2][64];      // stage 2 pulls (stage-1 values, inner rows)
     const Geometry& g = a.g;
     uint32_t tile = blockIdx.x;
     if (a.xcd_remap) {
@@ -349,15 +354,23 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(PairArgs a) {
 
     S nvr[NJ][kQ];                            // the input plane, raw (it goes to LDS as stored)
     LT a_mid[NJ][4], a_up1[NJ][5], a_up2[NJ][5];      // later-needed input values
-    LT b_mid[NJ][4], b_up1[NJ][5], b_up2[NJ][5];      // later-needed stage-1 values
+    LB b_mid[NJ][4], b_up1[NJ][5], b_up2[NJ][5];      // later-needed stage-1 values
     LT zero;
+    LB zerob;
     __builtin_memset(&zero, 0, sizeof zero);
+    __builtin_memset(&zerob, 0, sizeof zerob);
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) a_mid[j][k] = b_mid[j][k] = zero;
+        for (int k = 0; k < 4; ++k) {
+            a_mid[j][k] = zero;
+            b_mid[j][k] = zerob;
+        }
 #pragma unroll
-        for (int k = 0; k < 5; ++k) a_up1[j][k] = a_up2[j][k] = b_up1[j][k] = b_up2[j][k] = zero;
+        for (int k = 0; k < 5; ++k) {
+            a_up1[j][k] = a_up2[j][k] = zero;
+            b_up1[j][k] = b_up2[j][k] = zerob;
+        }
     }
 
     auto load_plane = [&](int zi) {
@@ -395,11 +408,11 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(PairArgs a) {
         }
         __syncthreads();
         // stage 1: plane zi - 1 on the inner window
-        LT s1[NJ][kQ];
+        LB s1[NJ][kQ];
 #pragma unroll
         for (int j = 0; j < NJ; ++j)
 #pragma unroll
-            for (int i = 0; i < kQ; ++i) s1[j][i] = zero;
+            for (int i = 0; i < kQ; ++i) s1[j][i] = zerob;
         if (it >= 2) {
             const int zw = wrap_mod(zi - 1, g.nz);
 #pragma unroll
@@ -412,9 +425,16 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(PairArgs a) {
                 float E, jx, jy, jz;
                 moments(v, E, jx, jy, jz);
                 uint32_t r[7] = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
-                if (SR) sr_words3(r, colw, sr_row_word3((uint32_t)zw * (uint32_t)g.ny + (uint32_t)gy[j], a.step, a.seed));
-                relax_round_all<S, SR>(a.c, v, a.c.omega_axis * E, a.c.omega_corner * E, jx, jy, jz, r, s1[j],
-                                       std::make_integer_sequence<int, kQ>{});
+                if constexpr (__is_same(LB, S)) {
+                    if (SR)
+                        sr_words3(r, colw, sr_row_word3((uint32_t)zw * (uint32_t)g.ny + (uint32_t)gy[j], a.step, a.seed));
+                    relax_round_all<S, SR>(a.c, v, a.c.omega_axis * E, a.c.omega_corner * E, jx, jy, jz, r, s1[j],
+                                           std::make_integer_sequence<int, kQ>{});
+                } else {
+                    // kept in FP32, rounded to nearest as FP32 storage would keep it
+                    relax_round_all<float, 0>(a.c, v, a.c.omega_axis * E, a.c.omega_corner * E, jx, jy, jz, r,
+                                              s1[j], std::make_integer_sequence<int, kQ>{});
+                }
             }
         }
         // the loaded plane's later-needed movers wait in registers
@@ -454,7 +474,7 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(PairArgs a) {
                 if (ly < 2 || ly > YO + 1 || lx < 2 || lx > 61 || ox >= g.nx || oy >= g.ny) continue;
                 float v[kQ];
 #pragma unroll
-                for (int i = 0; i < kQ; ++i) v[i] = Cvt<S>::ld(lds_b[i][ly - 1 - cy(i)][lx - cx(i)]);
+                for (int i = 0; i < kQ; ++i) v[i] = Cvt<LB>::ld(lds_b[i][ly - 1 - cy(i)][lx - cx(i)]);
                 float E, jx, jy, jz;
                 moments(v, E, jx, jy, jz);
                 uint32_t r[7] = {0u, 0u, 0u, 0u, 0u, 0u, 0u};
@@ -479,22 +499,28 @@ __global__ __launch_bounds__(64 * NW) void pair_kernel(PairArgs a) {
     }
 }
 
-template <class S, int L>
-static void launch_pair_l(int sr, const PairArgs& a, hipStream_t st) {
+template <class S, int L, int RS>
+static void launch_pair_r(int sr, const PairArgs& a, hipStream_t st) {
     const dim3 grid(a.xcd_remap ? 8u * ((a.ntiles + 7u) / 8u) : a.ntiles), block(64 * kPairNW);
-    if (sr) hipLaunchKernelGGL((pair_kernel<S, 1, L, kPairYO, kPairNW>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((pair_kernel<S, 0, L, kPairYO, kPairNW>), grid, block, 0, st, a);
+    if (sr) hipLaunchKernelGGL((pair_kernel<S, 1, L, kPairYO, kPairNW, RS>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((pair_kernel<S, 0, L, kPairYO, kPairNW, RS>), grid, block, 0, st, a);
 }
 
-hipError_t launch_pair(int storage, int sr, const PairArgs& a, hipStream_t st) {
+template <class S, int L>
+static void launch_pair_l(int sr, int every_step, const PairArgs& a, hipStream_t st) {
+    if (sizeof(S) == 4 || every_step) launch_pair_r<S, L, 1>(sr, a, st);
+    else if constexpr (sizeof(S) == 2) launch_pair_r<S, L, 0>(sr, a, st);
+}
+
+hipError_t launch_pair(int storage, int sr, int every_step, const PairArgs& a, hipStream_t st) {
     if (a.ntiles == 0) return hipSuccess;
     switch (storage * 2 + (a.g.layout ? 1 : 0)) {
-        case 0: launch_pair_l<float, 0>(sr, a, st); break;
-        case 1: launch_pair_l<float, 1>(sr, a, st); break;
-        case 2: launch_pair_l<_Float16, 0>(sr, a, st); break;
-        case 3: launch_pair_l<_Float16, 1>(sr, a, st); break;
-        case 4: launch_pair_l<bf16_bits, 0>(sr, a, st); break;
-        case 5: launch_pair_l<bf16_bits, 1>(sr, a, st); break;
+        case 0: launch_pair_l<float, 0>(sr, 1, a, st); break;
+        case 1: launch_pair_l<float, 1>(sr, 1, a, st); break;
+        case 2: launch_pair_l<_Float16, 0>(sr, every_step, a, st); break;
+        case 3: launch_pair_l<_Float16, 1>(sr, every_step, a, st); break;
+        case 4: launch_pair_l<bf16_bits, 0>(sr, every_step, a, st); break;
+        case 5: launch_pair_l<bf16_bits, 1>(sr, every_step, a, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

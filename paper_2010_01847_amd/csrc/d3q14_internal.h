@@ -87,7 +87,9 @@ struct PairArgs {
     uint32_t ntiles;            // ptx * pty * ptz
     int32_t zchunk;
 };
-hipError_t launch_pair(int storage, int sr, const PairArgs& a, hipStream_t st);
+// every_step: 16-bit storage rounds the first step's results to the storage
+// type as well (the same bits as two single steps); FP32 always does.
+hipError_t launch_pair(int storage, int sr, int every_step, const PairArgs& a, hipStream_t st);
 
 // Fill `bytes` (a multiple of 4) with the timing scratch pattern of the
 // device file (moderate finite values in every storage type, changing bits).

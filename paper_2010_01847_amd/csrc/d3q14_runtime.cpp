@@ -86,7 +86,7 @@ Status3 check3(const lbm3d_config* c) {
     if (c->nx < 1 || c->ny < 1 || c->nz < 1) return {LBM_EINVAL, "nx, ny, nz must be >= 1"};
     if (c->storage != LBM_F32 && c->storage != LBM_F16 && c->storage != LBM_BF16)
         return {LBM_EINVAL, "storage must be LBM_F32, LBM_F16 or LBM_BF16"};
-    if (c->flags & ~(LBM_FLAG_EXTERNAL_MEMORY | LBM_FLAG_STOCHASTIC_ROUNDING))
+    if (c->flags & ~(LBM_FLAG_EXTERNAL_MEMORY | LBM_FLAG_STOCHASTIC_ROUNDING | LBM_FLAG_ROUND_EVERY_STEP))
         return {LBM_EINVAL, "unknown flag bits"};
     if (!(c->tau_n > 0.0) || !std::isfinite(c->tau_n)) return {LBM_EINVAL, "tau_n must be finite and > 0"};
     if (!(c->tau_r > 0.0)) return {LBM_EINVAL, "tau_r must be > 0 (+inf allowed)"};
@@ -335,7 +335,8 @@ int lbm3d_step(lbm3d_handle h, int64_t nsteps) {
             p.src = h->buf(h->cur);
             p.dst = h->buf(1 - h->cur);
             p.step = (uint32_t)h->steps;
-            HIPCALL3(h, launch_pair(h->cfg.storage, sr, p, h->stream));
+            HIPCALL3(h, launch_pair(h->cfg.storage, sr, (h->cfg.flags & LBM_FLAG_ROUND_EVERY_STEP) ? 1 : 0, p,
+                                    h->stream));
             h->cur = 1 - h->cur;
             h->steps += 2;
             k += 2;

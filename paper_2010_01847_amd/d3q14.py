@@ -14,7 +14,8 @@ from typing import Optional, Sequence, Tuple
 
 import numpy as np
 
-from .lbm import (LAYOUT, LBM_BF16, LBM_F16, LBM_F32, LBM_FLAG_EXTERNAL_MEMORY, LBM_FLAG_STOCHASTIC_ROUNDING,
+from .lbm import (LAYOUT, LBM_BF16, LBM_F16, LBM_F32, LBM_FLAG_EXTERNAL_MEMORY, LBM_FLAG_ROUND_EVERY_STEP,
+                  LBM_FLAG_STOCHASTIC_ROUNDING,
                   LBM_OK, LBMError, library as _library)
 
 
@@ -165,14 +166,15 @@ class Box:
 
     def __init__(self, nx: int, ny: int, nz: int, tau_n: float, tau_r: float, storage: str = "f32",
                  t0: float = 1.0, cv: float = 1.0, scale: float = 0.0, stochastic: bool = False,
-                 seed: int = 0, layout: str = "auto"):
+                 seed: int = 0, layout: str = "auto", every_step: bool = False):
         import torch
         self.torch = torch
         self.shape = (int(nz), int(ny), int(nx))
         cfg = lbm3d_config()
         cfg.nx, cfg.ny, cfg.nz = int(nx), int(ny), int(nz)
         cfg.storage = STORAGE3[storage]
-        cfg.flags = LBM_FLAG_EXTERNAL_MEMORY | (LBM_FLAG_STOCHASTIC_ROUNDING if stochastic else 0)
+        cfg.flags = (LBM_FLAG_EXTERNAL_MEMORY | (LBM_FLAG_STOCHASTIC_ROUNDING if stochastic else 0)
+                     | (LBM_FLAG_ROUND_EVERY_STEP if every_step else 0))
         cfg.layout = LAYOUT[layout]
         cfg.seed = int(seed) & 0xffffffff
         cfg.tau_n, cfg.tau_r, cfg.cv, cfg.t0, cfg.scale = float(tau_n), float(tau_r), float(cv), float(t0), float(scale)

@@ -38,10 +38,10 @@ def _oracle(nx, ny, nz, tau_n, tau_r, T0, q, steps):
 
 
 def _gpu(nx, ny, nz, tau_n, tau_r, T0, q, steps, storage="f32", shape=None, stochastic=False, seed=0,
-         scale=0.0, layout="auto", fuse=1):
+         scale=0.0, layout="auto", fuse=1, every_step=False):
     """Moments after each call of `steps` (an int, or a sequence of call lengths)."""
     box = Box(nx, ny, nz, tau_n, tau_r, storage=storage, stochastic=stochastic, seed=seed, scale=scale,
-              layout=layout)
+              layout=layout, every_step=every_step)
     if shape:
         box.set_launch_shape(**shape)
     box.set_step_fusion(fuse)
@@ -250,37 +250,52 @@ def test_full_size_thermal_waves(storage, layout, fuse):
     e_t, e_q = _eps([s[:, 0], s[:, 1], s[:, 2], s[:, 3]], [T - 1.0, qx, qy, qz])
     log(f"d3q14 full size {storage} {layout} fuse={fuse}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
     if storage == "bf16":
-        # misses the 16-bit bound on the heat flux (measured 7.243e-3 on this
-        # fixed-seed run): held within 0.8x .. 1.25x of it
-        log(f"  d3q14 full size bf16 eps_q misses the 16-bit bound: {e_q:.3e}")
-        assert e_t < 5e-3 and 0.8 * 7.243e-3 <= e_q <= 1.25 * 7.243e-3
+        # misses the 16-bit bound on the heat flux (measured on this fixed-seed
+        # run: 7.243e-3 in single steps, BF16_PAIR_MISS with two steps per
+        # launch, which round one state to BF16 instead of two): held within
+        # 0.8x .. 1.25x of it
+        meas = 7.243e-3 if fuse == 1 else BF16_PAIR_MISS
+        log(f"  d3q14 full size bf16 eps_q misses the 16-bit bound: {e_q:.3e} (measured {meas:.3e})")
+        assert e_t < 5e-3 and 0.8 * meas <= e_q <= 1.25 * meas
     else:
         assert e_t < TOL3[storage] and e_q < TOL3[storage]
 
 
 FUSION3 = [("f32", False, "chunked"), ("f32", False, "planes"), ("f32", True, "chunked"),
            ("bf16", True, "chunked"), ("f16", True, "planes"), ("f16", False, "chunked")]
+# eps_q of the full-size BF16 (stochastic) run with two steps per launch
+BF16_PAIR_MISS = 6.429e-3
 
 
 @pytest.mark.parametrize("storage,stochastic,layout", FUSION3)
 def test_two_step_kernel_bitwise(storage, stochastic, layout):
     """Two steps per launch (the z-marching kernel) give the same bits as single
-    steps: storage kinds and roundings, both layouts, a box ragged against the
-    60 x 4 tiles and the 32-plane z ranges, and call lengths that leave odd
-    remainders (run as single steps)."""
+    steps (16-bit storage rounding every step): storage kinds and roundings,
+    both layouts, a box ragged against the 60 x 4 tiles and the 32-plane z
+    ranges, and call lengths that leave odd remainders (run as single steps).
+    16-bit storage by default (the first step of a launch kept in FP32): the
+    oracle within the kind's bound."""
     nx, ny, nz = 131, 11, 37
     T0, q = _random_start(nx, ny, nz, 81)
     calls = (1, 2, 3, 7, 10)
+    every = storage != "f32"
     ref_out = _gpu(nx, ny, nz, 0.6, 7.0, T0, q, calls, storage=storage, stochastic=stochastic, seed=5,
-                   layout=layout, fuse=1)
+                   layout=layout, fuse=1, every_step=every)
     got = _gpu(nx, ny, nz, 0.6, 7.0, T0, q, calls, storage=storage, stochastic=stochastic, seed=5,
-               layout=layout, fuse=2)
+               layout=layout, fuse=2, every_step=every)
     for a_fields, b_fields in zip(got, ref_out):
         for a, b in zip(a_fields, b_fields):
             assert np.array_equal(a, b), (storage, stochastic, layout)
-    e_t, e_q = _eps(got[-1], _oracle(nx, ny, nz, 0.6, 7.0, T0, q, sum(calls)))
+    ora = _oracle(nx, ny, nz, 0.6, 7.0, T0, q, sum(calls))
+    e_t, e_q = _eps(got[-1], ora)
     log(f"d3q14 two-step {storage} sr={stochastic} {layout}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
     assert e_t < TOL3[storage] and e_q < TOL3[storage]
+    if every:
+        dflt = _gpu(nx, ny, nz, 0.6, 7.0, T0, q, calls, storage=storage, stochastic=stochastic, seed=5,
+                    layout=layout, fuse=2)
+        e_t, e_q = _eps(dflt[-1], ora)
+        log(f"d3q14 two-step {storage} sr={stochastic} {layout}, first step in FP32: eps_T={e_t:.3e} eps_q={e_q:.3e}")
+        assert e_t < TOL3[storage] and e_q < TOL3[storage]
 
 
 @pytest.mark.parametrize("dims", [(1, 1, 1), (2, 3, 1), (5, 2, 4), (61, 5, 3), (64, 4, 33), (59, 9, 2)])
