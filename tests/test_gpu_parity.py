@@ -503,7 +503,8 @@ def _default_rounding_run(case, T0, qx, qy, storage, rounding, steps, name):
     at 20 (after the lone check step) give the residual the check step formed
     from the snapshot that launch wrote, and at step 10 (a call ending on a
     fused launch that ends on the check step) the totals read out equal the
-    ones that launch formed."""
+    ones that launch formed; the same oracle and residual checks under the
+    graph schedule."""
     kmax = _fuse_max(storage)
     out = _fused_run(case, T0, qx, qy, storage, rounding, kmax, steps, 10)
     e = eps(case, out[-1][0][:3], oracle_fields(case, sum(steps), T0, qx, qy))
@@ -518,6 +519,14 @@ def _default_rounding_run(case, T0, qx, qy, storage, rounding, steps, name):
     assert m10[3]["step"] == 10
     for u, v in zip(m10[4], m10[3]["totals"]):
         assert u == pytest.approx(v, rel=1e-9, abs=1e-12), (name, m10[4], m10[3]["totals"])
+    # the graph schedule (its captured chunks plan their own launches, so the
+    # bits differ from the eager run's): the oracle, and its readouts against
+    # its own check steps
+    gr = _fused_run(case, T0, qx, qy, storage, rounding, kmax, steps, 10, "graph")
+    e = eps(case, gr[-1][0][:3], oracle_fields(case, sum(steps), T0, qx, qy))
+    g20 = gr[ends.index(20)][0]
+    assert max(e) < TOL_STORAGE[storage], (name, "graph", e)
+    assert g20[3]["residual"] == pytest.approx(_residual(g20[:3], gr[ends.index(19)][0][:3]), rel=1e-3)
 
 
 @pytest.mark.parametrize("name,kw,storage,rounding", FUSION_CASES, ids=[c[0] for c in FUSION_CASES])
