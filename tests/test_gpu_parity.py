@@ -771,6 +771,32 @@ def test_batched_schedules_bitwise_and_parity():
         assert e_q < 1e-5 and e_t < 1e-5
 
 
+def test_batched_streams_16bit_default_rounding():
+    """16-bit storage with its default step rounding (the stored step rounded
+    only) on uneven instances: the batched schedule on one stream and on two
+    give the same bits (the same launch plan), with readouts after calls that
+    end on fused launches; every instance matches the oracle within 5e-3."""
+    cases = W.knudsen_sweep(n_inst=6, seed=7, side_lo=20, side_hi=140, steps=0)
+    insts = [instance_from_case(c, 2.0 ** -20) for c in cases]
+    outs = []
+    for streams in (1, 2):
+        lat = Lattice(insts, storage="f16", check_interval=10, rounding="stochastic", seed=5)
+        lat.set_streams(streams)
+        lat.set_step_fusion(_fuse_max("f16"))
+        for k in range(len(cases)):
+            lat.init(k)
+        lat.step(45)
+        lat.step(13)
+        outs.append([lat.moments(k) for k in range(len(cases))])
+        lat.close()
+    for k, case in enumerate(cases):
+        for a, b in zip(outs[0][k], outs[1][k]):
+            assert np.array_equal(a, b), k
+        e_t, e_q = eps(case, outs[1][k], oracle_fields(case, 58))
+        log(f"batched f16 SR inst {k}: eps_T={e_t:.3e} eps_q={e_q:.3e}")
+        assert e_t < 5e-3 and e_q < 5e-3, (k, e_t, e_q)
+
+
 def test_graph_every_replay_matches_eager():
     """Each replay of a captured chunk (check steps every 10, so one replay per
     10-step call; the two parts as two branches; fused launches ending on the
