@@ -16,8 +16,9 @@ against the FP64 oracle (relative L2 of the temperature deviation and of the
 heat flux, pass or fail against 1e-5 for FP32 storage and 5e-3 for 16-bit
 storage, computed after the timed region):
 
-* "rows": the same workload in every storage kind (FP16 / BF16 with
-  stochastic rounding, the split FP16 / BF16 forms), each run on to the
+* "rows": the same workload in every storage kind (FP16 with stochastic
+  rounding and to nearest, BF16 with stochastic rounding, the split FP16 /
+  BF16 forms), each run on to the
   workload's 4000 steps and compared on sampled rows with the exact periodic
   solution; "front": the pulse-front speed;
 * "walls" (128 x 64 isothermal walls, 5000 steps) and "channel" (1024 x 256
@@ -104,11 +105,12 @@ def _parse():
     p.add_argument("--warmup", type=int, default=50)
     p.add_argument("--n", type=int, default=8192, help="lattice side")
     p.add_argument("--storage", default="f32", choices=list(BYTES_PER_NODE))
-    p.add_argument("--rows", default="f16:stochastic,bf16:stochastic,f16_split,bf16_split",
+    p.add_argument("--rows", default="f16:stochastic,f16:nearest,bf16:stochastic,f16_split,bf16_split",
                    help="extra rows, storage[:rounding] ('' for none)")
     p.add_argument("--rounding", default=None, choices=["nearest", "stochastic"],
                    help="rounding of the main row's stores (default: stochastic for plain 16-bit "
-                        "storage, which stalls on smooth fields otherwise; nearest for the rest)")
+                        "storage, which stalls on smooth fields when every step is rounded to "
+                        "nearest; nearest for the rest)")
     p.add_argument("--accuracy-steps", type=int, default=4000,
                    help="steps after which each second-sound row is compared with the exact solution")
     p.add_argument("--sweep-steps", type=int, default=300, help="timed steps per sweep schedule (0: skip)")
