@@ -775,7 +775,8 @@ def test_batched_streams_16bit_default_rounding():
     """16-bit storage with its default step rounding (the stored step rounded
     only) on uneven instances: the batched schedule on one stream and on two
     give the same bits (the same launch plan), with readouts after calls that
-    end on fused launches; every instance matches the oracle within 5e-3."""
+    end on fused launches (FP64 and FP32 fields and the totals agree); every
+    instance matches the oracle within 5e-3."""
     cases = W.knudsen_sweep(n_inst=6, seed=7, side_lo=20, side_hi=140, steps=0)
     insts = [instance_from_case(c, 2.0 ** -20) for c in cases]
     outs = []
@@ -788,6 +789,15 @@ def test_batched_streams_16bit_default_rounding():
         lat.step(45)
         lat.step(13)
         outs.append([lat.moments(k) for k in range(len(cases))])
+        # the FP32 readout and the totals come from the same rebuilt moments
+        for k, case in enumerate(cases):
+            dT, qx, qy = outs[-1][k]
+            T32, qx32, qy32 = lat.moments_f32(k)
+            tref = np.tile(case.t_ref(), (case.ny, 1))
+            assert np.allclose(T32, tref + dT, rtol=0, atol=2e-7), k
+            assert np.array_equal(qx32, qx.astype(np.float32)) and np.array_equal(qy32, qy.astype(np.float32)), k
+            tot = lat.totals(k)
+            assert tot[1] == pytest.approx(float(np.sum(qx)), rel=1e-9, abs=1e-12), k
         lat.close()
     for k, case in enumerate(cases):
         for a, b in zip(outs[0][k], outs[1][k]):
