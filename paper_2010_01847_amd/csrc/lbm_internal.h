@@ -60,6 +60,7 @@ struct alignas(64) InstDesc {
     float sigma;            // 1 - rho = 2 / (2 tau_r + 1): decay of the flux share per step
     float wall_g[4];        // C_V (T_wall - T_ref) / s for isothermal walls (times omega_i)
     float wall_q[4];        // q_0 / (beta s) for heat-flux walls (added to the incident sum)
+    float flux_a, flux_d;   // (1 / tau - sigma) x 1/3 and x 1/12: the folded flux coefficients (relax_folded)
     double s_cv;            // s / C_V   (dT = s E / C_V)
     double s_beta;          // s * beta  (q = q_ref + s beta j)
     double s;               // storage scale

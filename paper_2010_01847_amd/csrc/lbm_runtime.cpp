@@ -111,15 +111,15 @@ Geometry geometry_of(const lbm_instance& in, int es, int layout, bool split = fa
 // lattices and scales the check figures.
 static void default_costs(int storage, int every_step, double plain[8], double check[8]) {
     static const double p_tab[5][8] = {{0, 737, 1214, 1208, 1237, 1093, 1098, 1212},   // F32
-                                       {0, 497, 572, 600, 680, 870, 1022, 0},          // F16
-                                       {0, 480, 573, 601, 753, 898, 1026, 0},          // BF16
-                                       {0, 486, 733, 743, 752, 924, 1058, 0},          // F16_SPLIT
-                                       {0, 483, 733, 745, 751, 925, 1062, 0}};         // BF16_SPLIT
+                                       {0, 498, 572, 588, 650, 823, 947, 0},           // F16
+                                       {0, 482, 573, 588, 722, 828, 948, 0},           // BF16
+                                       {0, 483, 730, 742, 744, 869, 985, 0},           // F16_SPLIT
+                                       {0, 482, 733, 745, 744, 873, 994, 0}};          // BF16_SPLIT
     static const double c_tab[5][8] = {{0, 0, 1216, 1095, 1095, 1217, 1360, 1558},
-                                       {0, 0, 640, 776, 897, 1174, 1329, 0},
-                                       {0, 0, 716, 824, 1029, 1184, 1364, 0},
-                                       {0, 0, 749, 813, 935, 1207, 1377, 0},
-                                       {0, 0, 754, 823, 939, 1215, 1390, 0}};
+                                       {0, 0, 631, 757, 857, 1114, 1260, 0},
+                                       {0, 0, 703, 788, 995, 1122, 1269, 0},
+                                       {0, 0, 747, 797, 897, 1155, 1300, 0},
+                                       {0, 0, 753, 814, 909, 1162, 1309, 0}};
     // 16-bit kinds rounding every step (kFuseEveryStep = 4 at most)
     static const double pe_tab[5][5] = {{0, 0, 0, 0, 0},
                                         {0, 496, 604, 600, 743},
@@ -594,6 +594,8 @@ static void fill_desc(lbm_ctx* h, size_t k, double s) {
     InstDesc& d = h->desc[k];
     d.inv_tau = (float)(1.0 / c.tau);
     d.sigma = (float)c.one_minus_rho;
+    d.flux_a = (float)((1.0 / c.tau - c.one_minus_rho) / 3.0);
+    d.flux_d = (float)((1.0 / c.tau - c.one_minus_rho) / 12.0);
     for (int w = 0; w < 4; ++w) d.wall_g[w] = (float)(in.cv * (in.t_wall[w] - in.t0) / s);
     for (int w = 0; w < 4; ++w) d.wall_q[w] = (float)(h->qwall[k][w] / (c.beta * s));
     d.s = s;
