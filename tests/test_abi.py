@@ -178,6 +178,22 @@ def test_round_every_step_flag_accepted():
         assert P.lbm_required_bytes(cfg) > 0
 
 
+def test_readout_region_sized_for_moment_planes():
+    """16-bit storage rounding only the stored step rebuilds readouts as FP64
+    moment planes (24 bytes per node) instead of a population buffer (16 or
+    20 bytes per node on rows of whole 64-node chunks): its handles need more
+    memory than with LBM_FLAG_ROUND_EVERY_STEP, by about 24 - 20 bytes per node
+    or more; FP32 handles need the same either way."""
+    insts = [P.make_instance(1024, 700, 0.6, 5.0), P.make_instance(384, 129, 0.7, 50.0)]
+    nodes = 1024 * 700 + 384 * 129
+    every = P.LBM_FLAG_EXTERNAL_MEMORY | P.LBM_FLAG_ROUND_EVERY_STEP
+    for st in (P.LBM_F16, P.LBM_BF16, P.LBM_F16_SPLIT, P.LBM_BF16_SPLIT):
+        dflt = P.lbm_required_bytes(_cfg(insts, storage=st))
+        flag = P.lbm_required_bytes(_cfg(insts, storage=st, flags=every))
+        assert dflt - flag >= 3.9 * nodes, st
+    assert P.lbm_required_bytes(_cfg(insts)) == P.lbm_required_bytes(_cfg(insts, flags=every))
+
+
 def test_null_handle_calls_are_rejected():
     assert P.library().lbm_step(None, 1) == P.LBM_EINVAL
     assert P.library().lbm_steps_done(None) == -1
