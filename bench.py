@@ -490,7 +490,7 @@ def _eps_fields(case, gpu, ora):
     return (num / den if den > 0 else num), _rel_l2([(qx, qxo), (qy, qyo)])
 
 
-def _verdict(storage, e_t, e_q):
+def _bound_check(storage, e_t, e_q):
     bound = BOUND[storage]
     ok = e_t <= bound and e_q <= bound
     return {"eps_T": float(f"{e_t:.4g}"), "eps_q": float(f"{e_q:.4g}"), "bound": bound, "pass": ok,
@@ -545,7 +545,7 @@ def _oracle_leg(args, W, c3_rows, c3_sample_rows, front, walls, channel, sweep, 
             exact[n] = bloch.SeparableSolution(f, f, a["amp"], n, case.tau_n, case.tau_r).rows(c3_sample_rows)
         To, qxo, qyo = exact[n]
         dT, qx, qy = r.pop("_samples")
-        r["accuracy"] = _verdict(r["storage"], _rel_l2([(dT, To - 1.0)]), _rel_l2([(qx, qxo), (qy, qyo)]))
+        r["accuracy"] = _bound_check(r["storage"], _rel_l2([(dT, To - 1.0)]), _rel_l2([(qx, qxo), (qy, qyo)]))
         r["accuracy"]["compared"] = f"{len(c3_sample_rows)} rows x {case.nx} after {n} steps vs exact solution"
     # pulse front: ring-peak radius along the centre row, least-squares speed
     if front:
@@ -566,7 +566,7 @@ def _oracle_leg(args, W, c3_rows, c3_sample_rows, front, walls, channel, sweep, 
         o = ref.Oracle(wc)
         o.run(wc.steps)
         T, qxo, qyo = o.moments()
-        walls["accuracy"] = _verdict("f32", *_eps_fields(wc, walls.pop("_fields"), (T, qxo, qyo)))
+        walls["accuracy"] = _bound_check("f32", *_eps_fields(wc, walls.pop("_fields"), (T, qxo, qyo)))
     # channel: FP64 steady state (the solution is uniform along x: 4 columns)
     if channel:
         tau_n, ratio = channel.pop("_case")
@@ -581,7 +581,7 @@ def _oracle_leg(args, W, c3_rows, c3_sample_rows, front, walls, channel, sweep, 
             prev = qxo.copy()
         T, qxo, qyo = o.moments()
         dT, qx, qy = channel.pop("_fields")
-        channel["accuracy"] = _verdict("f32", *_eps_fields(cc, (dT[:, :4], qx[:, :4], qy[:, :4]), (T, qxo, qyo)))
+        channel["accuracy"] = _bound_check("f32", *_eps_fields(cc, (dT[:, :4], qx[:, :4], qy[:, :4]), (T, qxo, qyo)))
         channel["accuracy"]["compared"] = "columns 0-3 (the solution is uniform along x), all rows"
         d = cc.ny - 1
         kn_c = cf.knudsen(cf.scheme_constants(tau_n, cc.tau_r)["tau_c"], d)
@@ -598,7 +598,7 @@ def _oracle_leg(args, W, c3_rows, c3_sample_rows, front, walls, channel, sweep, 
             o.run(sweep["fields_at_step"])
             e_t, e_q = _eps_fields(c, fields, o.moments())
             worst_t, worst_q = max(worst_t, e_t), max(worst_q, e_q)
-        sweep["accuracy"] = _verdict("f32", worst_t, worst_q)
+        sweep["accuracy"] = _bound_check("f32", worst_t, worst_q)
         sweep["accuracy"]["compared"] = "worst of instances 0-3, all nodes"
     # large: exact 16-mode solution on the sampled rows; totals against the
     # exact invariants (energy kept, heat flux times rho per step)
@@ -612,7 +612,7 @@ def _oracle_leg(args, W, c3_rows, c3_sample_rows, front, walls, channel, sweep, 
                 sol[n] = bloch.ModeSolution(lc.init_args["modes"], lc.nx, lc.ny, n, lc.tau_n, lc.tau_r).rows(large_rows)
             To, qxo, qyo = sol[n]
             dT, qx, qy = r.pop("_samples")
-            r["accuracy"] = _verdict(r["storage"], _rel_l2([(dT, To - 1.0)]), _rel_l2([(qx, qxo), (qy, qyo)]))
+            r["accuracy"] = _bound_check(r["storage"], _rel_l2([(dT, To - 1.0)]), _rel_l2([(qx, qxo), (qy, qyo)]))
             r["accuracy"]["compared"] = f"{len(large_rows)} rows x {lc.nx} after {n} steps vs exact solution"
             e0, e1 = r["totals_start"][0], r["totals_end"][0]
             amp = 1e-3 * lc.nx * lc.ny     # the field's amplitude times the node count
@@ -626,7 +626,7 @@ def _oracle_leg(args, W, c3_rows, c3_sample_rows, front, walls, channel, sweep, 
             s = r.pop("_samples")
             T, qx, qy, qz = bloch_d3q14.ModeSolution(dc.init_args["modes"], dc.nx, dc.ny, dc.nz, r["accuracy_steps"],
                                                     dc.tau_n, dc.tau_r).at(xs, ys, zs)
-            r["accuracy"] = _verdict(r["storage"], _rel_l2([(s[:, 0], T - 1.0)]),
+            r["accuracy"] = _bound_check(r["storage"], _rel_l2([(s[:, 0], T - 1.0)]),
                                      _rel_l2([(s[:, 1], qx), (s[:, 2], qy), (s[:, 3], qz)]))
     out["cpu_baseline"] = _cpu_baseline(args, W, ref)
     return out
